@@ -1,0 +1,256 @@
+"""FP64 CPU oracle for the GES rasterizer — TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The product path (the HIP library and
+its Python binding) never imports, links or calls it, and it imports nothing
+from the product path.
+
+The arithmetic lives in ``gesr_oracle.cpp`` (double precision, OpenMP); this
+module only builds/loads it and marshals numpy arrays.
+
+Settings values are rounded to float32 before they are promoted to double,
+so both sides compare against exactly the same thresholds.  Splat parameters
+are taken as given (float32 scenes promote exactly; finite-difference checks
+pass perturbed float64 values).
+
+Parity status of each function is listed in the header of the C++ source;
+every function here is pinned by the CPU tests under ``tests/``
+(closed forms, library routines, brute force and finite differences).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass, field
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "gesr_oracle.cpp")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with g++ (-O2, OpenMP, strict IEEE double)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        cmd = ["g++", "-O2", "-std=c++17", "-fopenmp", "-fPIC", "-shared", "-ffp-contract=off",
+               "-fno-fast-math", "-o", tmp, _SRC]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        _lib = ctypes.CDLL(_LIB)
+        _lib.orc_bin_count.restype = ctypes.c_uint64
+        _lib.orc_total_tiles.restype = ctypes.c_long
+    return _lib
+
+
+@dataclass
+class Settings:
+    """Rasterizer constants (values shared with the GPU side, not code)."""
+    kappa: float = 0.5
+    rho: float = 0.1
+    alpha_min: float = 1.0 / 255.0
+    alpha_max: float = 0.99
+    t_min: float = 1e-4
+    blur: float = 0.3
+    znear: float = 0.2
+    clip_fac: float = 1.3
+    bg: Sequence[float] = field(default_factory=lambda: (0.0, 0.0, 0.0))
+    tile_w: int = 16
+    tile_h: int = 16
+    sh_degree: int = 0
+
+    def array(self) -> np.ndarray:
+        f = lambda x: float(np.float32(x))  # noqa: E731
+        return np.array([f(self.kappa), f(self.rho), f(self.alpha_min), f(self.alpha_max), f(self.t_min),
+                         f(self.blur), f(self.znear), f(self.clip_fac), f(self.bg[0]), f(self.bg[1]),
+                         f(self.bg[2]), self.tile_w, self.tile_h, self.sh_degree, 0, 0], dtype=np.float64)
+
+
+def views_array(cameras) -> np.ndarray:
+    out = np.zeros((len(cameras), 24), dtype=np.float64)
+    for k, c in enumerate(cameras):
+        out[k, 0] = c.width
+        out[k, 1] = c.height
+        out[k, 2:6] = [np.float32(c.fx), np.float32(c.fy), np.float32(c.cx), np.float32(c.cy)]
+        vm = np.asarray(c.viewmat, dtype=np.float32).astype(np.float64)
+        out[k, 6:15] = vm[:, :3].reshape(-1)
+        out[k, 15:18] = vm[:, 3]
+        out[k, 18:21] = np.asarray(c.campos, dtype=np.float32).astype(np.float64)
+    return out
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
+
+
+def _f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def tile_grid(cameras, tile_w, tile_h):
+    """(tiles_x, tiles_y, tile_base) per view and the total tile count."""
+    out, base = [], 0
+    for c in cameras:
+        tx = (c.width + tile_w - 1) // tile_w
+        ty = (c.height + tile_h - 1) // tile_h
+        out.append((tx, ty, base))
+        base += tx * ty
+    return out, base
+
+
+def project(scene, st: Settings) -> dict:
+    """FP64 projection of every (view, splat); arrays indexed [view * N + splat]."""
+    N, V = scene.n, scene.n_views
+    VN = N * V
+    r = dict(
+        rec=np.zeros((VN, 11)), depth=np.zeros(VN), z32=np.zeros(VN, np.float32), sigma2d=np.zeros((VN, 3)),
+        edges=np.zeros((VN, 4)), pix_rect=np.zeros((VN, 4), np.int32), tile_rect=np.zeros((VN, 4), np.int32),
+        tiles_touched=np.zeros(VN, np.uint32), cull=np.zeros(VN, np.uint8), clamp=np.zeros(VN, np.uint8))
+    sh = _f64(scene.sh.reshape(N, -1))
+    lib().orc_project(N, V, _p(_f64(scene.means)), _p(_f64(scene.scales)), _p(_f64(scene.quats)),
+                      _p(_f64(scene.opacities)), _p(_f64(scene.betas)), _p(sh), _p(views_array(scene.cameras)),
+                      _p(st.array()), _p(r["rec"]), _p(r["depth"]), _p(r["z32"]), _p(r["sigma2d"]),
+                      _p(r["edges"]), _p(r["pix_rect"]), _p(r["tile_rect"]), _p(r["tiles_touched"]),
+                      _p(r["cull"]), _p(r["clamp"]))
+    r["zbits"] = r["z32"].view(np.uint32)
+    return r
+
+
+def bin_instances(N, cameras, tile_rect, tiles_touched, zbits, st: Settings):
+    """Stable-sorted (keys, vals, ranges[T, 2]) of the (tile | depth) instances."""
+    V = len(cameras)
+    tiles_touched = np.ascontiguousarray(tiles_touched, dtype=np.uint32)
+    M = int(lib().orc_bin_count(ctypes.c_long(V * N), _p(tiles_touched)))
+    _, T = tile_grid(cameras, st.tile_w, st.tile_h)
+    keys = np.zeros(max(M, 1), np.uint64)
+    vals = np.zeros(max(M, 1), np.uint32)
+    ranges = np.zeros((T, 2), np.uint32)
+    lib().orc_bin(N, V, _p(np.ascontiguousarray(tile_rect, np.int32)), _p(tiles_touched),
+                  _p(np.ascontiguousarray(zbits, np.uint32)), _p(views_array(cameras)), st.tile_w, st.tile_h,
+                  _p(keys), _p(vals), _p(ranges))
+    return keys[:M], vals[:M], ranges
+
+
+def render_fwd(N, cameras, rec, vals, ranges, st: Settings) -> dict:
+    P = sum(c.width * c.height for c in cameras)
+    out = dict(image=np.zeros(3 * P), final_T=np.zeros(P), n_contrib=np.zeros(P, np.uint32),
+               n_listed=np.zeros(P, np.uint32), n_hit=np.zeros(P, np.uint32), ambig=np.zeros(P, np.uint8))
+    vals = np.ascontiguousarray(vals, np.uint32)
+    if vals.size == 0:
+        vals = np.zeros(1, np.uint32)
+    lib().orc_render_fwd(N, len(cameras), _p(views_array(cameras)), _p(st.array()), _p(_f64(rec)), _p(vals),
+                         _p(np.ascontiguousarray(ranges, np.uint32)), _p(out["image"]), _p(out["final_T"]),
+                         _p(out["n_contrib"]), _p(out["n_listed"]), _p(out["n_hit"]), _p(out["ambig"]))
+    return out
+
+
+def brute_fwd(N, cameras, rec, zbits, cull, st: Settings, pix_rect=None, window=None) -> dict:
+    P = sum(c.width * c.height for c in cameras)
+    out = dict(image=np.zeros(3 * P), final_T=np.ones(P), n_hit=np.zeros(P, np.uint32), ambig=np.zeros(P, np.uint8))
+    lib().orc_brute_fwd(N, len(cameras), _p(views_array(cameras)), _p(st.array()), _p(_f64(rec)),
+                        _p(np.ascontiguousarray(zbits, np.uint32)), _p(np.ascontiguousarray(cull, np.uint8)),
+                        _p(None if pix_rect is None else np.ascontiguousarray(pix_rect, np.int32)),
+                        _p(None if window is None else np.ascontiguousarray(window, np.int32)),
+                        _p(out["image"]), _p(out["final_T"]), _p(out["n_hit"]), _p(out["ambig"]))
+    return out
+
+
+def render_bwd(N, cameras, rec, vals, ranges, dL_dimage, st: Settings) -> np.ndarray:
+    V = len(cameras)
+    g2 = np.zeros((V * N, 10))
+    vals = np.ascontiguousarray(vals, np.uint32)
+    if vals.size == 0:
+        vals = np.zeros(1, np.uint32)
+    lib().orc_render_bwd(N, V, _p(views_array(cameras)), _p(st.array()), _p(_f64(rec)), _p(vals),
+                         _p(np.ascontiguousarray(ranges, np.uint32)), _p(_f64(dL_dimage)), _p(g2))
+    return g2
+
+
+def window_fwdbwd(N, cameras, rec, zbits, cull, pix_rect, window, dL_dimage, watch, st: Settings):
+    """(sum_window dL.image, grad2d rows of `watch`, decision hash)."""
+    watch = np.ascontiguousarray(watch, dtype=np.int64)
+    loss = ctypes.c_double(0.0)
+    dec = ctypes.c_uint64(0)
+    wg = np.zeros((max(len(watch), 1), 10))
+    lib().orc_window_fwdbwd(N, len(cameras), _p(views_array(cameras)), _p(st.array()), _p(_f64(rec)),
+                            _p(np.ascontiguousarray(zbits, np.uint32)), _p(np.ascontiguousarray(cull, np.uint8)),
+                            _p(np.ascontiguousarray(pix_rect, np.int32)),
+                            _p(np.ascontiguousarray(window, np.int32)), _p(_f64(dL_dimage)), len(watch),
+                            _p(watch), ctypes.byref(loss), _p(wg), ctypes.byref(dec))
+    return loss.value, wg[:len(watch)], dec.value
+
+
+def project_bwd(scene, grad2d, st: Settings) -> dict:
+    N, V = scene.n, scene.n_views
+    K = (st.sh_degree + 1) ** 2
+    g = dict(means=np.zeros((N, 3)), scales=np.zeros((N, 3)), quats=np.zeros((N, 4)), opacities=np.zeros(N),
+             betas=np.zeros(N), sh=np.zeros((N, K, 3)))
+    lib().orc_project_bwd(N, V, _p(_f64(scene.means)), _p(_f64(scene.scales)), _p(_f64(scene.quats)),
+                          _p(_f64(scene.opacities)), _p(_f64(scene.betas)), _p(_f64(scene.sh.reshape(N, -1))),
+                          _p(views_array(scene.cameras)), _p(st.array()), _p(_f64(grad2d)),
+                          _p(g["means"]), _p(g["scales"]), _p(g["quats"]), _p(g["opacities"]), _p(g["betas"]),
+                          _p(g["sh"]))
+    return g
+
+
+def sh_basis(degree: int, dirs) -> np.ndarray:
+    dirs = _f64(dirs)
+    n = dirs.shape[0]
+    out = np.zeros((n, (degree + 1) ** 2))
+    lib().orc_sh_basis(degree, ctypes.c_long(n), _p(dirs), _p(out))
+    return out
+
+
+def set_threads(n: int):
+    lib().orc_set_num_threads(int(n))
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())
+
+
+# ------------------------------------------------------------------ pipeline
+def forward(scene, st: Settings) -> dict:
+    """Full FP64 pipeline: project -> bin -> tiled render."""
+    pr = project(scene, st)
+    keys, vals, ranges = bin_instances(scene.n, scene.cameras, pr["tile_rect"], pr["tiles_touched"], pr["zbits"], st)
+    out = render_fwd(scene.n, scene.cameras, pr["rec"], vals, ranges, st)
+    out.update(proj=pr, keys=keys, vals=vals, ranges=ranges)
+    return out
+
+
+def backward(scene, st: Settings, fwd: dict, dL_dimage) -> dict:
+    g2 = render_bwd(scene.n, scene.cameras, fwd["proj"]["rec"], fwd["vals"], fwd["ranges"], dL_dimage, st)
+    g = project_bwd(scene, g2, st)
+    g["grad2d"] = g2
+    return g
+
+
+def flat_images(images) -> np.ndarray:
+    """Concatenate per-view (3, H, W) arrays in the oracle's view-major CHW layout."""
+    return np.concatenate([np.asarray(im, dtype=np.float64).reshape(-1) for im in images])
+
+
+def split_images(flat, cameras):
+    out, off = [], 0
+    for c in cameras:
+        n = 3 * c.width * c.height
+        out.append(np.asarray(flat[off:off + n]).reshape(3, c.height, c.width))
+        off += n
+    return out

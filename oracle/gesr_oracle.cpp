@@ -1,0 +1,809 @@
+// FP64 CPU oracle for the generalized-exponential-splat (GES) rasterizer.
+//
+// TEST INFRASTRUCTURE ONLY.  Nothing in the product path links, loads or calls
+// this file; only the tests, the smoke check and the CPU-baseline leg of the
+// benchmark do.  It shares no code, header or constant table with the HIP
+// library: it is written from the paper's equations and the readings listed
+// next to each function.
+//
+// Paper passages followed (DyGASR, arXiv 2411.09156):
+//   * GEF / GES falloff: Sec. 3.2, Eq. (1)-(3).  In screen space a splat at
+//     squared Mahalanobis distance q contributes exp(-kappa * q^(beta/2));
+//     kappa = 1/2 reproduces Eq. (3), beta = 2 is the Gaussian of Eq. (2).
+//   * Covariance Sigma = R S S^T R^T: Eq. (4).
+//   * Screen covariance Sigma' = J W Sigma W^T J^T: Sec. 3.2 (after Eq. 4).
+//   * Shape-modulated scale gamma_hat = phi(eps) gamma, Eq. (6)-(7); phi is
+//     read as 2 / (1 + exp(-rho (beta - 2))) so that phi(2) = 1.
+//   * Volume rendering, Eq. (5), evaluated as discrete front-to-back alpha
+//     blending (the "alpha-blending coefficients" of Sec. 3.3).
+//
+// Everything is double precision.  Inputs arrive as float32 and are promoted
+// exactly.  The projection is written once as a template over the scalar
+// type: with `double` it is the forward; with a forward-mode dual number it
+// yields the exact Jacobian of every projected quantity, which is how the
+// projection adjoint is obtained (no hand-derived chain rule).  The render
+// adjoint uses explicit per-pixel fragment lists (no transmittance division).
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <numeric>
+#include <vector>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+namespace {
+
+// ---------------------------------------------------------------- settings
+struct Settings {
+    double kappa, rho, alpha_min, alpha_max, t_min, blur, znear, clip_fac;
+    double bg[3];
+    int tile_w, tile_h, sh_degree;
+};
+
+Settings read_settings(const double* s) {
+    Settings o;
+    o.kappa = s[0]; o.rho = s[1]; o.alpha_min = s[2]; o.alpha_max = s[3]; o.t_min = s[4];
+    o.blur = s[5]; o.znear = s[6]; o.clip_fac = s[7];
+    o.bg[0] = s[8]; o.bg[1] = s[9]; o.bg[2] = s[10];
+    o.tile_w = (int)s[11]; o.tile_h = (int)s[12]; o.sh_degree = (int)s[13];
+    return o;
+}
+
+struct View {
+    int W, H;
+    double fx, fy, cx, cy;
+    double R[9];   // world -> camera rotation, row-major
+    double t[3];
+    double campos[3];
+    int tiles_x, tiles_y;
+    long tile_base;  // first global tile id of this view
+    long pix_base;   // first pixel of this view in the concatenated outputs
+};
+
+std::vector<View> read_views(const double* v, int V, int tile_w, int tile_h) {
+    std::vector<View> out(V);
+    long tb = 0, pb = 0;
+    for (int k = 0; k < V; ++k) {
+        const double* a = v + 24 * k;
+        View& w = out[k];
+        w.W = (int)a[0]; w.H = (int)a[1];
+        w.fx = a[2]; w.fy = a[3]; w.cx = a[4]; w.cy = a[5];
+        for (int j = 0; j < 9; ++j) w.R[j] = a[6 + j];
+        for (int j = 0; j < 3; ++j) w.t[j] = a[15 + j];
+        for (int j = 0; j < 3; ++j) w.campos[j] = a[18 + j];
+        w.tiles_x = (w.W + tile_w - 1) / tile_w;
+        w.tiles_y = (w.H + tile_h - 1) / tile_h;
+        w.tile_base = tb;
+        w.pix_base = pb;
+        tb += (long)w.tiles_x * w.tiles_y;
+        pb += (long)w.W * w.H;
+    }
+    return out;
+}
+
+// ------------------------------------------------------------- dual numbers
+// Forward-mode dual number with D tangent directions.
+template <int D>
+struct Dual {
+    double v;
+    double d[D];
+    Dual() : v(0) { std::fill(d, d + D, 0.0); }
+    Dual(double x) : v(x) { std::fill(d, d + D, 0.0); }  // NOLINT: constants promote
+    static Dual var(double x, int k) { Dual r(x); r.d[k] = 1.0; return r; }
+};
+
+template <int D> Dual<D> operator+(const Dual<D>& a, const Dual<D>& b) {
+    Dual<D> r(a.v + b.v); for (int k = 0; k < D; ++k) r.d[k] = a.d[k] + b.d[k]; return r;
+}
+template <int D> Dual<D> operator-(const Dual<D>& a, const Dual<D>& b) {
+    Dual<D> r(a.v - b.v); for (int k = 0; k < D; ++k) r.d[k] = a.d[k] - b.d[k]; return r;
+}
+template <int D> Dual<D> operator-(const Dual<D>& a) {
+    Dual<D> r(-a.v); for (int k = 0; k < D; ++k) r.d[k] = -a.d[k]; return r;
+}
+template <int D> Dual<D> operator*(const Dual<D>& a, const Dual<D>& b) {
+    Dual<D> r(a.v * b.v); for (int k = 0; k < D; ++k) r.d[k] = a.d[k] * b.v + a.v * b.d[k]; return r;
+}
+template <int D> Dual<D> operator/(const Dual<D>& a, const Dual<D>& b) {
+    Dual<D> r(a.v / b.v);
+    for (int k = 0; k < D; ++k) r.d[k] = (a.d[k] * b.v - a.v * b.d[k]) / (b.v * b.v);
+    return r;
+}
+template <int D> Dual<D> operator+(const Dual<D>& a, double b) { return a + Dual<D>(b); }
+template <int D> Dual<D> operator+(double a, const Dual<D>& b) { return Dual<D>(a) + b; }
+template <int D> Dual<D> operator-(const Dual<D>& a, double b) { return a - Dual<D>(b); }
+template <int D> Dual<D> operator-(double a, const Dual<D>& b) { return Dual<D>(a) - b; }
+template <int D> Dual<D> operator*(const Dual<D>& a, double b) { return a * Dual<D>(b); }
+template <int D> Dual<D> operator*(double a, const Dual<D>& b) { return Dual<D>(a) * b; }
+template <int D> Dual<D> operator/(const Dual<D>& a, double b) { return a / Dual<D>(b); }
+template <int D> Dual<D> operator/(double a, const Dual<D>& b) { return Dual<D>(a) / b; }
+
+template <int D> Dual<D> sqrt(const Dual<D>& a) {
+    double s = std::sqrt(a.v);
+    Dual<D> r(s); for (int k = 0; k < D; ++k) r.d[k] = a.d[k] / (2.0 * s); return r;
+}
+template <int D> Dual<D> exp(const Dual<D>& a) {
+    double e = std::exp(a.v);
+    Dual<D> r(e); for (int k = 0; k < D; ++k) r.d[k] = a.d[k] * e; return r;
+}
+
+inline double val(double x) { return x; }
+template <int D> double val(const Dual<D>& x) { return x.v; }
+using std::exp;
+using std::sqrt;
+
+// ------------------------------------------------- real spherical harmonics
+// Real SH with the Condon-Shortley phase kept, index l*l + l + m, m = -l..l:
+//   m > 0 : sqrt(2) K_l^m P_l^m(cos th) cos(m ph)
+//   m < 0 : sqrt(2) K_l^|m| P_l^|m|(cos th) sin(|m| ph)
+//   m = 0 : K_l^0 P_l(cos th)
+// with K_l^m = sqrt((2l+1)/(4 pi) (l-m)!/(l+m)!) and P_l^m carrying (-1)^m.
+// For a unit direction (x, y, z) = (sin th cos ph, sin th sin ph, cos th):
+//   P_l^m(z) = (-1)^m (1 - z^2)^(m/2) d^m/dz^m P_l(z),
+//   (1 - z^2)^(m/2) cos(m ph) = Re (x + i y)^m,  ... sin(m ph) = Im (x + i y)^m,
+// so every basis function is a polynomial in (x, y, z) and the derivative with
+// respect to the direction follows from the dual arithmetic.
+double factorial(int n) { double f = 1; for (int i = 2; i <= n; ++i) f *= i; return f; }
+double binom(int n, int k) { return factorial(n) / (factorial(k) * factorial(n - k)); }
+
+// m-th derivative of the Legendre polynomial P_l at z, from
+// P_l(z) = 2^-l sum_k (-1)^k C(l,k) C(2l-2k,l) z^(l-2k).
+template <class S> S legendre_deriv(int l, int m, const S& z) {
+    S acc(0.0);
+    for (int k = 0; 2 * k <= l; ++k) {
+        int p = l - 2 * k;
+        if (p < m) continue;
+        double c = std::ldexp(1.0, -l) * ((k & 1) ? -1.0 : 1.0) * binom(l, k) * binom(2 * l - 2 * k, l) *
+                   factorial(p) / factorial(p - m);
+        S term(c);
+        for (int e = 0; e < p - m; ++e) term = term * z;
+        acc = acc + term;
+    }
+    return acc;
+}
+
+template <class S> void sh_basis(int degree, const S& x, const S& y, const S& z, S* out) {
+    const double pi = 3.14159265358979323846;
+    for (int l = 0; l <= degree; ++l) {
+        for (int m = -l; m <= l; ++m) {
+            int am = m < 0 ? -m : m;
+            double K = std::sqrt((2.0 * l + 1.0) / (4.0 * pi) * factorial(l - am) / factorial(l + am));
+            S pd = legendre_deriv<S>(l, am, z);
+            // (x + i y)^am
+            S re(1.0), im(0.0);
+            for (int e = 0; e < am; ++e) {
+                S nr = re * x - im * y;
+                S ni = re * y + im * x;
+                re = nr; im = ni;
+            }
+            double phase = (am & 1) ? -1.0 : 1.0;
+            S Y;
+            if (m == 0) Y = K * pd;
+            else if (m > 0) Y = (std::sqrt(2.0) * K * phase) * pd * re;
+            else Y = (std::sqrt(2.0) * K * phase) * pd * im;
+            out[l * l + l + m] = Y;
+        }
+    }
+}
+
+// ------------------------------------------------------------- projection
+enum Cull : uint8_t { KEEP = 0, CULL_NEAR = 1, CULL_DET = 2, CULL_OPACITY = 3, CULL_EMPTY = 4, CULL_NONFINITE = 5 };
+
+template <class S>
+struct Proj {
+    S u, v, A, B, C, o, beta, rgb[3];
+    double depth = 0, qmax = 0, sig[3] = {0, 0, 0}, edges[4] = {0, 0, 0, 0};
+    int pix[4] = {-1, -1, -2, -2}, tiles[4] = {-1, -1, -2, -2};
+    uint32_t touched = 0;
+    uint8_t cull = KEEP, clamp = 0;
+};
+
+// Projects one splat into one view.  `mean`, `scale`, `quat`, `opac`, `beta`
+// are scalars of type S (double, or duals carrying the Jacobian); `sh` points
+// at K*3 coefficients (colour is linear in them).
+template <class S>
+Proj<S> project_one(const S mean[3], const S scale[3], const S quat[4], const S& opac, const S& beta,
+                    const double* sh, const View& vw, const Settings& st) {
+    Proj<S> r;
+    // camera-space position: p = W mu + t  (W is the view rotation)
+    S p[3];
+    for (int a = 0; a < 3; ++a)
+        p[a] = vw.R[3 * a + 0] * mean[0] + vw.R[3 * a + 1] * mean[1] + vw.R[3 * a + 2] * mean[2] + vw.t[a];
+    r.depth = val(p[2]);
+    if (!(val(p[2]) > st.znear)) { r.cull = std::isfinite(val(p[2])) ? CULL_NEAR : CULL_NONFINITE; return r; }
+
+    // rotation of the normalised quaternion (w, x, y, z), Eq. (4)
+    S qn = sqrt(quat[0] * quat[0] + quat[1] * quat[1] + quat[2] * quat[2] + quat[3] * quat[3]);
+    S w = quat[0] / qn, x = quat[1] / qn, y = quat[2] / qn, z = quat[3] / qn;
+    S Rq[9] = {
+        1.0 - 2.0 * (y * y + z * z), 2.0 * (x * y - w * z),       2.0 * (x * z + w * y),
+        2.0 * (x * y + w * z),       1.0 - 2.0 * (x * x + z * z), 2.0 * (y * z - w * x),
+        2.0 * (x * z - w * y),       2.0 * (y * z + w * x),       1.0 - 2.0 * (x * x + y * y)};
+
+    // shape-modulated scale, Eq. (6)-(7): gamma_hat = phi(beta) gamma
+    S phi = 2.0 / (1.0 + exp(-st.rho * (beta - 2.0)));
+    S M[9];  // M = R diag(phi s)
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) M[3 * a + b] = Rq[3 * a + b] * (phi * scale[b]);
+    S Sig[9];  // Sigma = M M^T
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) Sig[3 * a + b] = M[3 * a] * M[3 * b] + M[3 * a + 1] * M[3 * b + 1] + M[3 * a + 2] * M[3 * b + 2];
+
+    // perspective Jacobian J at the (frustum-clamped) centre
+    double limx = st.clip_fac * vw.W / (2.0 * vw.fx), limy = st.clip_fac * vw.H / (2.0 * vw.fy);
+    S txz = p[0] / p[2], tyz = p[1] / p[2];
+    S xt = (val(txz) > limx) ? S(limx) * p[2] : (val(txz) < -limx) ? S(-limx) * p[2] : p[0];
+    S yt = (val(tyz) > limy) ? S(limy) * p[2] : (val(tyz) < -limy) ? S(-limy) * p[2] : p[1];
+    S J[6] = {vw.fx / p[2], S(0.0), -vw.fx * xt / (p[2] * p[2]),
+              S(0.0), vw.fy / p[2], -vw.fy * yt / (p[2] * p[2])};
+    S T[6];  // T = J W
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 3; ++b)
+            T[3 * a + b] = J[3 * a] * vw.R[b] + J[3 * a + 1] * vw.R[3 + b] + J[3 * a + 2] * vw.R[6 + b];
+    // Sigma' = T Sigma T^T + blur I
+    S TS[6];
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 3; ++b)
+            TS[3 * a + b] = T[3 * a] * Sig[b] + T[3 * a + 1] * Sig[3 + b] + T[3 * a + 2] * Sig[6 + b];
+    S sa = TS[0] * T[0] + TS[1] * T[1] + TS[2] * T[2] + st.blur;
+    S sb = TS[0] * T[3] + TS[1] * T[4] + TS[2] * T[5];
+    S sc = TS[3] * T[3] + TS[4] * T[4] + TS[5] * T[5] + st.blur;
+    r.sig[0] = val(sa); r.sig[1] = val(sb); r.sig[2] = val(sc);
+    S det = sa * sc - sb * sb;
+    if (!(val(det) > 0.0)) { r.cull = std::isfinite(val(det)) ? CULL_DET : CULL_NONFINITE; return r; }
+    r.A = sc / det; r.B = -sb / det; r.C = sa / det;
+
+    // projected centre; pixel (i, j) has its centre at (i + 1/2, j + 1/2)
+    r.u = vw.fx * p[0] / p[2] + vw.cx;
+    r.v = vw.fy * p[1] / p[2] + vw.cy;
+
+    // view-dependent colour from SH: rgb = sum_lm Y_lm(dir) k_lm + 1/2, clamped at 0
+    S dvec[3] = {mean[0] - vw.campos[0], mean[1] - vw.campos[1], mean[2] - vw.campos[2]};
+    S dn = sqrt(dvec[0] * dvec[0] + dvec[1] * dvec[1] + dvec[2] * dvec[2]);
+    S Y[16];
+    sh_basis<S>(st.sh_degree, dvec[0] / dn, dvec[1] / dn, dvec[2] / dn, Y);
+    int K = (st.sh_degree + 1) * (st.sh_degree + 1);
+    for (int c = 0; c < 3; ++c) {
+        S acc(0.5);
+        for (int k = 0; k < K; ++k) acc = acc + Y[k] * sh[3 * k + c];
+        if (val(acc) < 0.0) { r.rgb[c] = S(0.0); r.clamp |= (uint8_t)(1u << c); }
+        else r.rgb[c] = acc;
+    }
+    r.o = opac;
+    r.beta = beta;
+
+    // footprint: alpha >= alpha_min  <=>  q <= (ln(o/alpha_min)/kappa)^(2/beta)
+    double o = val(opac), bt = val(beta);
+    bool finite = std::isfinite(val(r.u)) && std::isfinite(val(r.v)) && std::isfinite(val(r.A)) &&
+                  std::isfinite(val(r.B)) && std::isfinite(val(r.C)) && std::isfinite(o) && std::isfinite(bt) &&
+                  std::isfinite(val(r.rgb[0])) && std::isfinite(val(r.rgb[1])) && std::isfinite(val(r.rgb[2]));
+    if (!finite) { r.cull = CULL_NONFINITE; return r; }
+    if (o < st.alpha_min) { r.cull = CULL_OPACITY; return r; }
+    double L = std::log(o / st.alpha_min) / st.kappa;
+    r.qmax = std::pow(L, 2.0 / bt) * (1.0 + std::ldexp(1.0, -10));
+    double rx = std::sqrt(r.qmax * val(sa)), ry = std::sqrt(r.qmax * val(sc));
+    double uu = val(r.u), vv = val(r.v);
+    r.edges[0] = uu - rx - 0.5; r.edges[1] = uu + rx - 0.5;
+    r.edges[2] = vv - ry - 0.5; r.edges[3] = vv + ry - 0.5;
+    double fx0 = std::ceil(r.edges[0]), fx1 = std::floor(r.edges[1]);
+    double fy0 = std::ceil(r.edges[2]), fy1 = std::floor(r.edges[3]);
+    fx0 = std::max(fx0, 0.0); fy0 = std::max(fy0, 0.0);
+    fx1 = std::min(fx1, (double)(vw.W - 1)); fy1 = std::min(fy1, (double)(vw.H - 1));
+    if (!(fx0 <= fx1 && fy0 <= fy1)) { r.cull = CULL_EMPTY; return r; }
+    r.pix[0] = (int)fx0; r.pix[1] = (int)fy0; r.pix[2] = (int)fx1; r.pix[3] = (int)fy1;
+    r.tiles[0] = r.pix[0] / st.tile_w; r.tiles[1] = r.pix[1] / st.tile_h;
+    r.tiles[2] = r.pix[2] / st.tile_w; r.tiles[3] = r.pix[3] / st.tile_h;
+    r.touched = (uint32_t)((r.tiles[2] - r.tiles[0] + 1) * (r.tiles[3] - r.tiles[1] + 1));
+    return r;
+}
+
+// ---------------------------------------------------------- compositing
+// One fragment of a pixel's list: the splat's screen-space record.
+struct Rec {
+    double u, v, A, B, C, o, beta, qmax, r, g, b;
+};
+
+inline Rec load_rec(const double* rec, long idx) {
+    const double* a = rec + 11 * idx;
+    return Rec{a[0], a[1], a[2], a[3], a[4], a[5], a[6], a[7], a[8], a[9], a[10]};
+}
+
+// Falloff of Eq. (3) at pixel centre (px, py): G = exp(-kappa q^(beta/2)).
+struct Frag { double dx, dy, q, P, G, oG, alpha; };
+
+inline Frag eval_frag(const Rec& s, double px, double py, const Settings& st) {
+    Frag f;
+    f.dx = px - s.u;
+    f.dy = py - s.v;
+    f.q = s.A * f.dx * f.dx + 2.0 * s.B * f.dx * f.dy + s.C * f.dy * f.dy;
+    if (f.q < 0.0) f.q = 0.0;
+    f.P = (f.q > 0.0) ? std::pow(f.q, 0.5 * s.beta) : 0.0;
+    f.G = std::exp(-st.kappa * f.P);
+    f.oG = s.o * f.G;
+    f.alpha = std::min(st.alpha_max, f.oG);
+    return f;
+}
+
+inline bool near_rel(double a, double b, double tol) { return std::fabs(a - b) <= tol * std::fabs(b); }
+
+// Ambiguity flags: a fragment whose decision could flip under FP32 rounding.
+constexpr double AMBIG = 1e-5;
+inline uint8_t frag_ambiguity(const Frag& f, double Tnext, const Settings& st) {
+    uint8_t a = 0;
+    if (near_rel(f.oG, st.alpha_min, AMBIG)) a |= 1;
+    if (near_rel(f.oG, st.alpha_max, AMBIG)) a |= 2;
+    if (near_rel(Tnext, st.t_min, AMBIG)) a |= 4;
+    return a;
+}
+
+struct PixelOut {
+    double C[3];
+    double T;
+    uint32_t n_contrib, n_listed, n_hit;
+    uint8_t ambig;
+};
+
+// One explicit list entry of a composited fragment (used by the adjoint).
+struct Hit { long idx; long row; double alpha, T; Frag f; };
+
+// Front-to-back compositing of one pixel over `list` (indices into rec, in
+// order).  Skips fragments with alpha < alpha_min; stops before compositing a
+// fragment that would take T below t_min.  n_contrib is the 1-based list
+// position of the last composited fragment.
+template <class ListFn>
+PixelOut composite_pixel(long count, ListFn idx_at, const double* rec, double px, double py, const Settings& st,
+                         std::vector<Hit>* hits, const long* rows = nullptr) {
+    PixelOut o{{0, 0, 0}, 1.0, 0, 0, 0, 0};
+    double T = 1.0;
+    for (long k = 0; k < count; ++k) {
+        long idx = idx_at(k);
+        Rec s = load_rec(rec, idx);
+        Frag f = eval_frag(s, px, py, st);
+        o.n_listed++;
+        double Tn = T * (1.0 - f.alpha);
+        o.ambig |= frag_ambiguity(f, Tn, st);
+        if (f.alpha < st.alpha_min) continue;
+        o.n_hit++;
+        if (Tn < st.t_min) break;
+        o.C[0] += s.r * f.alpha * T;
+        o.C[1] += s.g * f.alpha * T;
+        o.C[2] += s.b * f.alpha * T;
+        if (hits) hits->push_back(Hit{idx, rows ? rows[k] : idx, f.alpha, T, f});
+        T = Tn;
+        o.n_contrib = (uint32_t)(k + 1);
+    }
+    for (int c = 0; c < 3; ++c) o.C[c] += T * st.bg[c];
+    o.T = T;
+    return o;
+}
+
+// Adjoint of composite_pixel for one pixel, from its explicit hit list.
+// g = dL/dC (3 values); writes into grad2d rows (10 per splat-view index):
+// du, dv, dA, dB, dC, dopacity, dbeta, dr, dg, db.
+void pixel_adjoint(const std::vector<Hit>& hits, double Tfinal, const double* g, const double* rec,
+                   const Settings& st, double* grad2d) {
+    double Bk[3] = {st.bg[0], st.bg[1], st.bg[2]};  // colour behind fragment k, per unit T_{k+1}
+    (void)Tfinal;
+    for (long k = (long)hits.size() - 1; k >= 0; --k) {
+        const Hit& h = hits[k];
+        Rec s = load_rec(rec, h.idx);
+        double* gr = grad2d + 10 * h.row;
+        double col[3] = {s.r, s.g, s.b};
+        double dL_dalpha = 0.0;
+        for (int c = 0; c < 3; ++c) {
+            gr[7 + c] += h.alpha * h.T * g[c];
+            dL_dalpha += h.T * (col[c] - Bk[c]) * g[c];
+        }
+        for (int c = 0; c < 3; ++c) Bk[c] = h.alpha * col[c] + (1.0 - h.alpha) * Bk[c];
+        const Frag& f = h.f;
+        if (f.oG > st.alpha_max) continue;  // alpha clamped: no dependence on o or G
+        gr[5] += dL_dalpha * f.G;
+        double dL_dG = dL_dalpha * s.o;
+        double dG_dq = 0.0, dG_dbeta = 0.0;
+        if (f.q > 0.0) {
+            dG_dq = -st.kappa * f.G * (0.5 * s.beta) * f.P / f.q;
+            dG_dbeta = -st.kappa * f.G * f.P * 0.5 * std::log(f.q);
+        }
+        double dL_dq = dL_dG * dG_dq;
+        gr[6] += dL_dG * dG_dbeta;
+        gr[0] += dL_dq * (-2.0 * (s.A * f.dx + s.B * f.dy));
+        gr[1] += dL_dq * (-2.0 * (s.B * f.dx + s.C * f.dy));
+        gr[2] += dL_dq * f.dx * f.dx;
+        gr[3] += dL_dq * 2.0 * f.dx * f.dy;
+        gr[4] += dL_dq * f.dy * f.dy;
+    }
+}
+
+int nthreads() {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+int thread_id() {
+#ifdef _OPENMP
+    return omp_get_thread_num();
+#else
+    return 0;
+#endif
+}
+
+}  // namespace
+
+extern "C" {
+
+// Number of threads the oracle's parallel loops use.
+int orc_num_threads(void) { return nthreads(); }
+void orc_set_num_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
+// Projection of N splats into V views (FP64).
+//   views: V x 24 doubles: W, H, fx, fy, cx, cy, R[9] row-major, t[3], campos[3], pad
+//   settings: kappa, rho, alpha_min, alpha_max, t_min, blur, znear, clip_fac, bg[3],
+//             tile_w, tile_h, sh_degree
+// Outputs are [V][N]-indexed (view-major):
+//   rec[11]: u, v, A, B, C, opacity, beta, qmax, r, g, b;  depth; z32 = RN_fp32(depth);
+//   sigma2d[3] = (a, b, c) of Sigma'; edges[4] = u-rx-1/2, u+rx-1/2, v-ry-1/2, v+ry-1/2;
+//   pix_rect[4] / tile_rect[4] inclusive (x0, y0, x1, y1); tiles_touched; cull; clamp.
+int orc_project(int N, int V, const double* means, const double* scales, const double* quats, const double* opac,
+                const double* betas, const double* sh, const double* views, const double* settings, double* rec,
+                double* depth, float* z32, double* sigma2d, double* edges, int32_t* pix_rect, int32_t* tile_rect,
+                uint32_t* tiles_touched, uint8_t* cull, uint8_t* clamp) {
+    Settings st = read_settings(settings);
+    std::vector<View> vw = read_views(views, V, st.tile_w, st.tile_h);
+    int K = (st.sh_degree + 1) * (st.sh_degree + 1);
+#pragma omp parallel for schedule(static)
+    for (long i = 0; i < N; ++i) {
+        double m[3], s[3], q[4];
+        for (int a = 0; a < 3; ++a) { m[a] = means[3 * i + a]; s[a] = scales[3 * i + a]; }
+        for (int a = 0; a < 4; ++a) q[a] = quats[4 * i + a];
+        for (int v = 0; v < V; ++v) {
+            Proj<double> p = project_one<double>(m, s, q, (double)opac[i], (double)betas[i], sh + (long)i * K * 3, vw[v], st);
+            long o = (long)v * N + i;
+            double r11[11] = {p.u, p.v, p.A, p.B, p.C, p.o, p.beta, p.qmax, p.rgb[0], p.rgb[1], p.rgb[2]};
+            if (p.cull != KEEP) std::fill(r11, r11 + 11, 0.0);
+            std::memcpy(rec + 11 * o, r11, sizeof r11);
+            depth[o] = p.depth;
+            z32[o] = (float)p.depth;
+            for (int a = 0; a < 3; ++a) sigma2d[3 * o + a] = p.sig[a];
+            for (int a = 0; a < 4; ++a) {
+                edges[4 * o + a] = p.edges[a];
+                pix_rect[4 * o + a] = p.pix[a];
+                tile_rect[4 * o + a] = p.tiles[a];
+            }
+            tiles_touched[o] = p.cull == KEEP ? p.touched : 0;
+            cull[o] = p.cull;
+            clamp[o] = p.clamp;
+        }
+    }
+    return 0;
+}
+
+uint64_t orc_bin_count(long VN, const uint32_t* tiles_touched) {
+    uint64_t m = 0;
+    for (long k = 0; k < VN; ++k) m += tiles_touched[k];
+    return m;
+}
+
+long orc_total_tiles(int V, const double* views, int tile_w, int tile_h) {
+    std::vector<View> vw = read_views(views, V, tile_w, tile_h);
+    return vw.back().tile_base + (long)vw.back().tiles_x * vw.back().tiles_y;
+}
+
+// Binning: one instance per (splat, view, tile) overlap, emitted in
+// (view, splat, tile-row, tile-column) order with key = tile << 32 | bits(z32)
+// and value = view * N + splat; stable sort by key; ranges[t] = [first, end)
+// of tile t in the sorted list ((0, 0) when empty).
+int orc_bin(int N, int V, const int32_t* tile_rect, const uint32_t* tiles_touched, const uint32_t* zbits,
+            const double* views, int tile_w, int tile_h, uint64_t* keys, uint32_t* vals, uint32_t* ranges) {
+    std::vector<View> vw = read_views(views, V, tile_w, tile_h);
+    long T = vw.back().tile_base + (long)vw.back().tiles_x * vw.back().tiles_y;
+    std::vector<std::pair<uint64_t, uint32_t>> inst;
+    for (int v = 0; v < V; ++v)
+        for (long i = 0; i < N; ++i) {
+            long o = (long)v * N + i;
+            if (tiles_touched[o] == 0) continue;
+            const int32_t* r = tile_rect + 4 * o;
+            for (int ty = r[1]; ty <= r[3]; ++ty)
+                for (int tx = r[0]; tx <= r[2]; ++tx) {
+                    uint64_t tile = (uint64_t)(vw[v].tile_base + (long)ty * vw[v].tiles_x + tx);
+                    inst.emplace_back((tile << 32) | zbits[o], (uint32_t)o);
+                }
+        }
+    std::stable_sort(inst.begin(), inst.end(),
+                     [](const std::pair<uint64_t, uint32_t>& a, const std::pair<uint64_t, uint32_t>& b) {
+                         return a.first < b.first;
+                     });
+    for (long t = 0; t < T; ++t) { ranges[2 * t] = 0; ranges[2 * t + 1] = 0; }
+    for (size_t k = 0; k < inst.size(); ++k) {
+        keys[k] = inst[k].first;
+        vals[k] = inst[k].second;
+        uint64_t t = inst[k].first >> 32;
+        if (k == 0 || (inst[k - 1].first >> 32) != t) ranges[2 * t] = (uint32_t)k;
+        ranges[2 * t + 1] = (uint32_t)(k + 1);
+    }
+    return 0;
+}
+
+// Tiled forward: every pixel composites the sorted list of its tile.
+// Outputs (concatenated over views): image [3][H][W] per view, final_T,
+// n_contrib, n_listed, n_hit, ambig (bit0 alpha ~ alpha_min, bit1 oG ~ alpha_max,
+// bit2 T' ~ t_min).
+int orc_render_fwd(int N, int V, const double* views, const double* settings, const double* rec,
+                   const uint32_t* vals, const uint32_t* ranges, double* image, double* final_T,
+                   uint32_t* n_contrib, uint32_t* n_listed, uint32_t* n_hit, uint8_t* ambig) {
+    (void)N;
+    Settings st = read_settings(settings);
+    std::vector<View> vw = read_views(views, V, st.tile_w, st.tile_h);
+    for (int v = 0; v < V; ++v) {
+        const View& w = vw[v];
+#pragma omp parallel for schedule(dynamic, 4)
+        for (long y = 0; y < w.H; ++y)
+            for (long x = 0; x < w.W; ++x) {
+                long t = w.tile_base + (y / st.tile_h) * w.tiles_x + x / st.tile_w;
+                uint32_t s0 = ranges[2 * t], s1 = ranges[2 * t + 1];
+                PixelOut po = composite_pixel(
+                    (long)s1 - s0, [&](long k) { return (long)vals[s0 + k]; }, rec, x + 0.5, y + 0.5, st, nullptr);
+                long p = w.pix_base + y * w.W + x;
+                long HW = (long)w.W * w.H;
+                for (int c = 0; c < 3; ++c) image[3 * w.pix_base + c * HW + y * w.W + x] = po.C[c];
+                final_T[p] = po.T;
+                n_contrib[p] = po.n_contrib;
+                if (n_listed) n_listed[p] = po.n_listed;
+                if (n_hit) n_hit[p] = po.n_hit;
+                if (ambig) ambig[p] = po.ambig;
+            }
+    }
+    return 0;
+}
+
+// Candidate lists per view for the brute-force renderer: every non-culled
+// splat of the view, ordered by (z32, splat index).
+static std::vector<std::vector<long>> depth_order(int N, int V, const uint32_t* zbits, const uint8_t* cull) {
+    std::vector<std::vector<long>> ord(V);
+    for (int v = 0; v < V; ++v) {
+        for (long i = 0; i < N; ++i)
+            if (cull[(long)v * N + i] == KEEP) ord[v].push_back((long)v * N + i);
+        std::stable_sort(ord[v].begin(), ord[v].end(), [&](long a, long b) { return zbits[a] < zbits[b]; });
+    }
+    return ord;
+}
+
+// Brute force: each pixel composites every non-culled splat of its view in
+// (z32, index) order.  With pix_rect non-null, splats whose pixel rectangle
+// misses the pixel are left out (used for fast window evaluation).  window
+// (V x 4: x0, y0, x1, y1 inclusive; nullable) restricts the pixels evaluated;
+// pixels outside it are left untouched.
+int orc_brute_fwd(int N, int V, const double* views, const double* settings, const double* rec,
+                  const uint32_t* zbits, const uint8_t* cull, const int32_t* pix_rect, const int32_t* window,
+                  double* image, double* final_T, uint32_t* n_hit, uint8_t* ambig) {
+    Settings st = read_settings(settings);
+    std::vector<View> vw = read_views(views, V, st.tile_w, st.tile_h);
+    auto ord = depth_order(N, V, zbits, cull);
+    for (int v = 0; v < V; ++v) {
+        const View& w = vw[v];
+        int x0 = 0, y0 = 0, x1 = w.W - 1, y1 = w.H - 1;
+        if (window) { x0 = std::max(x0, window[4 * v]); y0 = std::max(y0, window[4 * v + 1]);
+                      x1 = std::min(x1, window[4 * v + 2]); y1 = std::min(y1, window[4 * v + 3]); }
+        std::vector<long> cand;
+        for (long o : ord[v]) {
+            if (pix_rect) {
+                const int32_t* r = pix_rect + 4 * o;
+                if (r[2] < x0 || r[0] > x1 || r[3] < y0 || r[1] > y1) continue;
+            }
+            cand.push_back(o);
+        }
+#pragma omp parallel for schedule(dynamic, 1)
+        for (long y = y0; y <= y1; ++y) {
+            std::vector<long> list;
+            for (long x = x0; x <= x1; ++x) {
+                list.clear();
+                for (long o : cand) {
+                    if (pix_rect) {
+                        const int32_t* r = pix_rect + 4 * o;
+                        if (x < r[0] || x > r[2] || y < r[1] || y > r[3]) continue;
+                    }
+                    list.push_back(o);
+                }
+                PixelOut po = composite_pixel((long)list.size(), [&](long k) { return list[k]; }, rec, x + 0.5,
+                                              y + 0.5, st, nullptr);
+                long p = w.pix_base + y * w.W + x;
+                long HW = (long)w.W * w.H;
+                for (int c = 0; c < 3; ++c) image[3 * w.pix_base + c * HW + y * w.W + x] = po.C[c];
+                final_T[p] = po.T;
+                if (n_hit) n_hit[p] = po.n_hit;
+                if (ambig) ambig[p] = po.ambig;
+            }
+        }
+    }
+    return 0;
+}
+
+// Render adjoint over the tiled lists: re-runs the forward per pixel keeping
+// the explicit list of composited fragments (alpha_k, T_k) and back-propagates
+// dL/dimage into grad2d [V*N][10] (du, dv, dA, dB, dC, dopacity, dbeta, dr, dg, db).
+// Accumulation uses one buffer per thread, summed in thread order.
+int orc_render_bwd(int N, int V, const double* views, const double* settings, const double* rec,
+                   const uint32_t* vals, const uint32_t* ranges, const double* dL_dimage, double* grad2d) {
+    Settings st = read_settings(settings);
+    std::vector<View> vw = read_views(views, V, st.tile_w, st.tile_h);
+    long VN = (long)V * N;
+    int nt = nthreads();
+    std::vector<std::vector<double>> acc(nt);
+#pragma omp parallel
+    {
+        std::vector<double>& g2 = acc[thread_id()];
+        g2.assign(10 * VN, 0.0);
+        std::vector<Hit> hits;
+        for (int v = 0; v < V; ++v) {
+            const View& w = vw[v];
+            long HW = (long)w.W * w.H;
+#pragma omp for schedule(dynamic, 4)
+            for (long y = 0; y < w.H; ++y)
+                for (long x = 0; x < w.W; ++x) {
+                    long t = w.tile_base + (y / st.tile_h) * w.tiles_x + x / st.tile_w;
+                    uint32_t s0 = ranges[2 * t], s1 = ranges[2 * t + 1];
+                    hits.clear();
+                    PixelOut po = composite_pixel(
+                        (long)s1 - s0, [&](long k) { return (long)vals[s0 + k]; }, rec, x + 0.5, y + 0.5, st, &hits);
+                    double g[3];
+                    for (int c = 0; c < 3; ++c) g[c] = dL_dimage[3 * w.pix_base + c * HW + y * w.W + x];
+                    pixel_adjoint(hits, po.T, g, rec, st, g2.data());
+                }
+        }
+    }
+    std::fill(grad2d, grad2d + 10 * VN, 0.0);
+    for (int k = 0; k < nt; ++k)
+        if (!acc[k].empty())
+            for (long j = 0; j < 10 * VN; ++j) grad2d[j] += acc[k][j];
+    return 0;
+}
+
+// Window forward + adjoint by brute force with the pixel-rectangle filter:
+// pixels in window (V x 4, inclusive) only.  Returns sum over the window of
+// dL_dimage . image in *loss and, for the `n_watch` splat-view indices in
+// `watch`, their grad2d rows (n_watch x 10).  `decisions` receives a hash of
+// every skip/terminate/clamp decision taken (for finite-difference checks).
+int orc_window_fwdbwd(int N, int V, const double* views, const double* settings, const double* rec,
+                      const uint32_t* zbits, const uint8_t* cull, const int32_t* pix_rect, const int32_t* window,
+                      const double* dL_dimage, int n_watch, const long* watch, double* loss, double* watch_grad,
+                      uint64_t* decisions) {
+    Settings st = read_settings(settings);
+    std::vector<View> vw = read_views(views, V, st.tile_w, st.tile_h);
+    auto ord = depth_order(N, V, zbits, cull);
+    // watched index -> output row
+    std::vector<std::pair<long, int>> wmap;
+    for (int k = 0; k < n_watch; ++k) wmap.emplace_back(watch[k], k);
+    std::sort(wmap.begin(), wmap.end());
+    double total = 0.0;
+    uint64_t dh = 1469598103934665603ull;
+    std::fill(watch_grad, watch_grad + 10 * (long)n_watch, 0.0);
+    for (int v = 0; v < V; ++v) {
+        const View& w = vw[v];
+        int x0 = std::max(0, window[4 * v]), y0 = std::max(0, window[4 * v + 1]);
+        int x1 = std::min(w.W - 1, window[4 * v + 2]), y1 = std::min(w.H - 1, window[4 * v + 3]);
+        if (x0 > x1 || y0 > y1) continue;
+        std::vector<long> cand;
+        for (long o : ord[v]) {
+            const int32_t* r = pix_rect + 4 * o;
+            if (r[2] < x0 || r[0] > x1 || r[3] < y0 || r[1] > y1) continue;
+            cand.push_back(o);
+        }
+        long HW = (long)w.W * w.H;
+        std::vector<long> list, rows;
+        std::vector<Hit> hits;
+        // gradients accumulate in a compact buffer with one row per candidate
+        std::vector<double> g2(10 * cand.size(), 0.0);
+        for (long y = y0; y <= y1; ++y)
+            for (long x = x0; x <= x1; ++x) {
+                list.clear();
+                rows.clear();
+                for (size_t c = 0; c < cand.size(); ++c) {
+                    const int32_t* r = pix_rect + 4 * cand[c];
+                    if (x < r[0] || x > r[2] || y < r[1] || y > r[3]) continue;
+                    list.push_back(cand[c]);
+                    rows.push_back((long)c);
+                }
+                hits.clear();
+                PixelOut po = composite_pixel((long)list.size(), [&](long k) { return list[k]; }, rec, x + 0.5,
+                                              y + 0.5, st, &hits, rows.data());
+                double g[3];
+                for (int c = 0; c < 3; ++c) {
+                    g[c] = dL_dimage[3 * w.pix_base + c * HW + y * w.W + x];
+                    total += g[c] * po.C[c];
+                }
+                pixel_adjoint(hits, po.T, g, rec, st, g2.data());
+                for (const Hit& h : hits) {
+                    uint64_t e = (uint64_t)h.idx * 1315423911ull + (uint64_t)(h.f.oG > st.alpha_max);
+                    dh = (dh ^ e) * 1099511628211ull;
+                }
+                dh = (dh ^ (uint64_t)po.n_contrib) * 1099511628211ull;
+            }
+        for (auto& pr : wmap) {
+            auto it = std::lower_bound(cand.begin(), cand.end(), pr.first);
+            // cand is in depth order, not index order: search linearly on a miss
+            long c = -1;
+            if (it != cand.end() && *it == pr.first) c = it - cand.begin();
+            else for (size_t j = 0; j < cand.size(); ++j) if (cand[j] == pr.first) { c = (long)j; break; }
+            if (c < 0) continue;
+            for (int j = 0; j < 10; ++j) watch_grad[10 * pr.second + j] += g2[10 * c + j];
+        }
+    }
+    *loss = total;
+    if (decisions) *decisions = dh;
+    return 0;
+}
+
+// Projection adjoint: grad2d [V*N][10] -> gradients of the splat inputs,
+// summed over views in ascending order.  The Jacobian of every projected
+// quantity with respect to (mean, scale, quat, opacity, beta) comes from
+// forward-mode dual numbers through project_one; the SH coefficients enter the
+// colour linearly, so their gradient is Y_lm(dir) times the unclamped colour
+// gradient.
+int orc_project_bwd(int N, int V, const double* means, const double* scales, const double* quats, const double* opac,
+                    const double* betas, const double* sh, const double* views, const double* settings,
+                    const double* grad2d, double* g_means, double* g_scales, double* g_quats, double* g_opac,
+                    double* g_betas, double* g_sh) {
+    Settings st = read_settings(settings);
+    std::vector<View> vw = read_views(views, V, st.tile_w, st.tile_h);
+    int K = (st.sh_degree + 1) * (st.sh_degree + 1);
+    typedef Dual<12> D;
+#pragma omp parallel for schedule(static)
+    for (long i = 0; i < N; ++i) {
+        D m[3], s[3], q[4];
+        for (int a = 0; a < 3; ++a) m[a] = D::var(means[3 * i + a], a);
+        for (int a = 0; a < 3; ++a) s[a] = D::var(scales[3 * i + a], 3 + a);
+        for (int a = 0; a < 4; ++a) q[a] = D::var(quats[4 * i + a], 6 + a);
+        D o = D::var(opac[i], 10), b = D::var(betas[i], 11);
+        double gacc[12] = {0};
+        std::vector<double> gsh(3 * K, 0.0);
+        for (int v = 0; v < V; ++v) {
+            long idx = (long)v * N + i;
+            Proj<D> p = project_one<D>(m, s, q, o, b, sh + (long)i * K * 3, vw[v], st);
+            if (p.cull != KEEP) continue;
+            const double* g = grad2d + 10 * idx;
+            const D* outs[10] = {&p.u, &p.v, &p.A, &p.B, &p.C, &p.o, &p.beta, &p.rgb[0], &p.rgb[1], &p.rgb[2]};
+            for (int k = 0; k < 12; ++k) {
+                double acc = 0.0;
+                for (int j = 0; j < 10; ++j) acc += g[j] * outs[j]->d[k];
+                gacc[k] += acc;
+            }
+            // SH coefficients: d rgb_c / d k_lc = Y_lm(dir), zero on a clamped channel
+            double dv[3] = {means[3 * i] - vw[v].campos[0], means[3 * i + 1] - vw[v].campos[1],
+                            means[3 * i + 2] - vw[v].campos[2]};
+            double dn = std::sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
+            double Y[16];
+            sh_basis<double>(st.sh_degree, dv[0] / dn, dv[1] / dn, dv[2] / dn, Y);
+            for (int c = 0; c < 3; ++c) {
+                if (p.clamp & (1u << c)) continue;
+                for (int k = 0; k < K; ++k) gsh[3 * k + c] += Y[k] * g[7 + c];
+            }
+        }
+        for (int a = 0; a < 3; ++a) g_means[3 * i + a] = gacc[a];
+        for (int a = 0; a < 3; ++a) g_scales[3 * i + a] = gacc[3 + a];
+        for (int a = 0; a < 4; ++a) g_quats[4 * i + a] = gacc[6 + a];
+        g_opac[i] = gacc[10];
+        g_betas[i] = gacc[11];
+        for (int k = 0; k < 3 * K; ++k) g_sh[(long)i * 3 * K + k] = gsh[k];
+    }
+    return 0;
+}
+
+// Real SH basis (for tests): n directions (x, y, z) -> n x (deg+1)^2 values.
+int orc_sh_basis(int degree, long n, const double* dirs, double* out) {
+    int K = (degree + 1) * (degree + 1);
+    for (long i = 0; i < n; ++i) sh_basis<double>(degree, dirs[3 * i], dirs[3 * i + 1], dirs[3 * i + 2], out + K * i);
+    return 0;
+}
+
+}  // extern "C"
