@@ -1,0 +1,236 @@
+/* gesr.h — C ABI of the generalized-exponential-splat (GES) rasterizer for
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The library implements the differentiable rasterizer of DyGASR (arXiv
+ * 2411.09156): each 3-D splat with shape parameter beta (epsilon in the paper,
+ * Sec. 3.2, Eq. 1-3) is projected to a screen-space conic (Eq. 4 and the
+ * Sigma' = J W Sigma W^T J^T passage, with the shape-modulated scale of
+ * Eq. 6-7), binned into screen tiles, and alpha-composited front to back
+ * (Eq. 5 evaluated as discrete alpha blending); the backward pass returns
+ * gradients for position, scale, rotation, opacity, beta and SH colour.
+ *
+ * Conventions for every entry point
+ *  - Array pointers marked DEVICE are device memory owned by the caller; the
+ *    library never allocates, frees or retains them past the call.  HOST
+ *    pointers are read during the call only.
+ *  - All device work is enqueued on `stream` (a hipStream_t; NULL = default
+ *    stream).  Calls return after enqueueing, except where a synchronous
+ *    capacity check is requested (gesr_bin with GESR_BIN_SYNC).
+ *  - Arguments are validated on the host before anything is enqueued.  An
+ *    invalid argument returns GESR_ERR_INVALID and enqueues nothing; the
+ *    message is available from gesr_last_error(ctx).
+ *  - A HIP launch or copy failure returns GESR_ERR_HIP.  An asynchronous
+ *    device fault surfaces as GESR_ERR_HIP from a later call.
+ *  - Device pointers must be 16-byte aligned (torch allocations are).
+ *  - A context is not thread-safe; use one per host thread.
+ *  - Per-(view, splat) arrays are indexed vi = view * n + splat.
+ *  - Images are float32, CHW per view, views concatenated in order.
+ */
+#ifndef GESR_H
+#define GESR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GESR_OK = 0,
+    GESR_ERR_INVALID = 1,     /* bad argument; nothing enqueued */
+    GESR_ERR_CAPACITY = 2,    /* instance count exceeds bins->m_cap (see gesr_bin) */
+    GESR_ERR_HIP = 3,         /* HIP runtime error */
+    GESR_ERR_UNSUPPORTED = 4  /* valid but not supported by this build (e.g. tile shape) */
+} gesr_status;
+
+#define GESR_MAX_VIEWS 32
+#define GESR_REC_FLOATS 12    /* floats per projected record */
+#define GESR_PARTIAL_FLOATS 10 /* floats per instance gradient partial */
+
+typedef struct gesr_ctx gesr_ctx;
+
+/* Creates a context bound to HIP device `device`.  Host-only: no device
+ * memory is allocated.  Returns GESR_ERR_INVALID for a NULL `out`. */
+gesr_status gesr_ctx_create(int device, gesr_ctx** out);
+void gesr_ctx_destroy(gesr_ctx* ctx);
+/* Message of the last non-OK status returned on `ctx` ("" if none). */
+const char* gesr_last_error(const gesr_ctx* ctx);
+const char* gesr_status_string(gesr_status s);
+
+/* Pinhole camera, OpenCV axes (x right, y down, z forward).  A pixel (i, j)
+ * has its centre at (i + 1/2, j + 1/2). */
+typedef struct {
+    int32_t width, height;
+    float fx, fy, cx, cy;
+    float viewmat[12]; /* world -> camera [R | t], row-major 3x4 (W of Sec. 3.2) */
+    float campos[3];   /* camera centre in world coordinates (SH view direction) */
+} gesr_camera;
+
+/* Rasterizer constants.  gesr_default_settings() fills the defaults:
+ *  kappa = 0.5   falloff exp(-kappa q^(beta/2)); 1/2 reproduces Eq. 3
+ *  rho = 0.1     shape strength of Eq. 7 (value of Sec. 4.2), read as
+ *                phi = 2 / (1 + exp(-rho (beta - 2)))
+ *  alpha_min = 1/255, alpha_max = 0.99, t_min = 1e-4  blending thresholds
+ *  blur = 0.3 (px^2 added to Sigma'), znear = 0.2, clip_fac = 1.3
+ *  bg = (0, 0, 0)
+ *  tile_w = tile_h = 16; batch = 0 (automatic); radix_bits = 8. */
+typedef struct {
+    int32_t sh_degree; /* 0..3; K = (sh_degree + 1)^2 coefficients per channel */
+    float kappa, rho;
+    float alpha_min, alpha_max, t_min;
+    float blur, znear, clip_fac;
+    float bg[3];
+    int32_t tile_w, tile_h; /* supported: 16x16, 32x16, 32x32, 8x8 */
+    int32_t batch;          /* splats staged per LDS batch in the renderers (0 = auto) */
+    int32_t radix_bits;     /* digit width of the instance sort, 4..8 */
+    int32_t reserved[4];
+} gesr_settings;
+
+void gesr_default_settings(gesr_settings* s);
+
+/* Splat parameters, structure-of-arrays, DEVICE float32:
+ *  mean[3][n], scale[3][n] (linear, > 0), quat[4][n] (w, x, y, z; normalised
+ *  inside), opacity[n] (activated, in (0, 1)), beta[n] (> 0),
+ *  sh[K * 3][n] (coefficient k of channel c at row k * 3 + c; real SH with
+ *  the Condon-Shortley phase, index l*l + l + m). */
+typedef struct {
+    int32_t n;
+    const float* mean;
+    const float* scale;
+    const float* quat;
+    const float* opacity;
+    const float* beta;
+    const float* sh;
+} gesr_splats;
+
+/* Projection outputs, DEVICE, caller-allocated ([V * n] entries each):
+ *  rec[V*n][12]: u, v, L00, L10, L11, opacity, beta, qmax, r, g, b, depth
+ *       (the conic Sigma'^-1 = [[A, B], [B, C]] in Cholesky form:
+ *        A = L00^2, B = L00 L10, C = L10^2 + L11^2, so that
+ *        q = (L00 dx + L10 dy)^2 + (L11 dy)^2; qmax = largest q with
+ *        alpha >= alpha_min, padded by 2^-10; rgb after the clamp at 0)
+ *  tiles_touched[V*n]: tiles covered (0 = culled)
+ *  rect[V*n][2]: inclusive tile rectangle (tx0 | ty0 << 16, tx1 | ty1 << 16)
+ *  depth_key[V*n]: bit pattern of the float32 camera depth. */
+typedef struct {
+    float* rec;
+    uint32_t* tiles_touched;
+    uint32_t* rect;
+    uint32_t* depth_key;
+} gesr_proj;
+
+/* Binning outputs, DEVICE, caller-allocated.  `scratch` must hold at least
+ * gesr_sizes.bin_scratch_bytes for the same (cams, V, n, settings, m_cap).
+ *  tile_sorted[m_cap], val_sorted[m_cap]: instances sorted by the 64-bit key
+ *      (global tile id << 32 | depth_key), stable with respect to emission in
+ *      (view, splat, tile row, tile column) order; val = view * n + splat.
+ *  ranges[T][2]: [first, end) of each global tile in the sorted list, (0, 0)
+ *      when empty.  Global tile ids number the tiles of view 0 row-major,
+ *      then view 1, and so on.
+ *  worklist[T]: global tile ids ordered by decreasing list length (ties by id).
+ *  inst_base[V*n]: pre-sort instance id of the first instance of (view, splat).
+ *  counters[4]: [0] = M (instances wanted), [1] = 1 if M > m_cap,
+ *      [2] = min(M, m_cap).  Written on the device. */
+typedef struct {
+    uint64_t m_cap;
+    uint32_t* tile_sorted;
+    uint32_t* val_sorted;
+    uint32_t* ranges;
+    uint32_t* worklist;
+    uint32_t* inst_base;
+    uint32_t* counters;
+    void* scratch;
+    size_t scratch_bytes;
+} gesr_bins;
+
+/* Gradient outputs, DEVICE, same layouts as gesr_splats; overwritten. */
+typedef struct {
+    float* mean;
+    float* scale;
+    float* quat;
+    float* opacity;
+    float* beta;
+    float* sh;
+} gesr_grads;
+
+typedef struct {
+    uint64_t total_tiles;      /* T: tiles over all views */
+    uint64_t total_pixels;     /* P: pixels over all views */
+    size_t bin_scratch_bytes;  /* gesr_bins.scratch size for the given m_cap */
+    size_t partial_bytes;      /* gesr_render_bwd partial buffer for m_cap */
+    uint64_t max_sort_blocks;  /* informational */
+} gesr_sizes;
+
+/* Sizes of the caller-allocated buffers.  Host-only. */
+gesr_status gesr_query_sizes(gesr_ctx* ctx, const gesr_camera* cams, int V, int n, const gesr_settings* st,
+                             uint64_t m_cap, gesr_sizes* out);
+
+/* Projection (Sec. 3.2: Eq. 4, Sigma' = J W Sigma W^T J^T, Eq. 6-7; SH colour).
+ * For every (view, splat): camera transform, near-plane cull (depth <=
+ * znear), Sigma = M M^T with M = R(q) diag(phi(beta) s), EWA screen
+ * covariance with the Jacobian at the centre clamped to clip_fac times the
+ * half field of view, plus blur; conic factor; SH colour + 0.5 clamped at 0;
+ * alpha_min footprint qmax = (ln(o/alpha_min)/kappa)^(2/beta) (1 + 2^-10) and
+ * its pixel and tile rectangles.  Non-finite results and opacity < alpha_min
+ * cull the pair (tiles_touched = 0).  Reads each splat once for all views. */
+gesr_status gesr_project(gesr_ctx* ctx, const gesr_splats* splats, const gesr_camera* cams, int V,
+                         const gesr_settings* st, const gesr_proj* out, void* stream);
+
+#define GESR_BIN_SYNC 1 /* read M back and fail with GESR_ERR_CAPACITY if M > m_cap */
+
+/* Tile binning: one instance per (view, splat, covered tile), sorted by the
+ * (tile | depth) key (see gesr_bins).  With GESR_BIN_SYNC the call
+ * synchronises `stream` once after counting; if M > m_cap it returns
+ * GESR_ERR_CAPACITY with *m_out = M and leaves the sorted lists undefined.
+ * Without it the call never synchronises (capturable in a HIP graph): lists
+ * are truncated to m_cap and counters[1] is set.  *m_out (nullable) receives
+ * M only with GESR_BIN_SYNC. */
+gesr_status gesr_bin(gesr_ctx* ctx, const gesr_proj* proj, const gesr_camera* cams, int V, int n,
+                     const gesr_settings* st, const gesr_bins* bins, int flags, uint64_t* m_out, void* stream);
+
+/* Optional per-pixel counters of gesr_render_fwd: fragments evaluated up to
+ * termination (listed) and those with alpha >= alpha_min (hit). */
+typedef struct {
+    uint32_t* n_listed;
+    uint32_t* n_hit;
+} gesr_fwd_counts;
+
+/* Forward compositing (Eq. 5 as front-to-back alpha blending).  Per pixel,
+ * over its tile's sorted list: q from the conic at the pixel centre,
+ * alpha = min(alpha_max, o exp(-kappa q^(beta/2))); fragments with
+ * alpha < alpha_min are skipped; compositing stops before a fragment that
+ * would take T below t_min.  Outputs (DEVICE, P = total pixels):
+ * image[3P] (CHW per view), final_T[P], n_contrib[P] (1-based list position
+ * of the last composited fragment, 0 if none).  counts may be NULL. */
+gesr_status gesr_render_fwd(gesr_ctx* ctx, const gesr_proj* proj, const gesr_bins* bins, const gesr_camera* cams,
+                            int V, int n, const gesr_settings* st, float* image, float* final_T,
+                            uint32_t* n_contrib, const gesr_fwd_counts* counts, void* stream);
+
+/* Backward pass: adjoint of gesr_render_fwd and gesr_project for upstream
+ * dL_dimage (same layout as image).  Transmittance is recovered per pixel by
+ * division from final_T and n_contrib (no per-fragment state is stored);
+ * each tile reduces its pixels' contributions per instance without atomics
+ * into `partials` (DEVICE, gesr_sizes.partial_bytes); a fixed-order segmented
+ * sum per (view, splat) then feeds the projection adjoint, summed over views
+ * in ascending order.  grad2d (DEVICE [V*n][10], nullable) receives the
+ * screen-space gradients du, dv, dL00, dL10, dL11, dopacity, dbeta, dr, dg, db
+ * (dbeta here is the falloff term only; the phi(beta) term is added in the
+ * projection adjoint).
+ * `out` arrays are overwritten.  Results are bitwise reproducible. */
+gesr_status gesr_render_bwd(gesr_ctx* ctx, const gesr_splats* splats, const gesr_proj* proj, const gesr_bins* bins,
+                            const gesr_camera* cams, int V, const gesr_settings* st, const float* final_T,
+                            const uint32_t* n_contrib, const float* dL_dimage, float* partials, float* grad2d,
+                            const gesr_grads* out, void* stream);
+
+/* L1 photometric term of Eq. 8 (the (1 - lambda) L1 part):
+ * grad[i] = scale * sign(image[i] - target[i]) (sign(0) = 0), DEVICE, count
+ * elements. */
+gesr_status gesr_l1_grad(gesr_ctx* ctx, const float* image, const float* target, uint64_t count, float scale,
+                         float* grad, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GESR_H */

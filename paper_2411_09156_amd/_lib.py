@@ -1,0 +1,127 @@
+"""ctypes declarations mirroring include/gesr.h (argument marshalling only).
+
+Loading fails loudly if libgesr.so has not been built: there is no fallback
+implementation of any step.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgesr.so")
+
+GESR_OK = 0
+GESR_ERR_INVALID = 1
+GESR_ERR_CAPACITY = 2
+GESR_ERR_HIP = 3
+GESR_ERR_UNSUPPORTED = 4
+GESR_BIN_SYNC = 1
+MAX_VIEWS = 32
+REC_FLOATS = 12
+PARTIAL_FLOATS = 10
+
+EXPORTS = (
+    "gesr_ctx_create", "gesr_ctx_destroy", "gesr_last_error", "gesr_status_string", "gesr_default_settings",
+    "gesr_query_sizes", "gesr_project", "gesr_bin", "gesr_render_fwd", "gesr_render_bwd", "gesr_l1_grad",
+)
+
+c_float_p = ctypes.POINTER(ctypes.c_float)
+c_u32_p = ctypes.POINTER(ctypes.c_uint32)
+
+
+class Camera(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32), ("fx", ctypes.c_float),
+                ("fy", ctypes.c_float), ("cx", ctypes.c_float), ("cy", ctypes.c_float),
+                ("viewmat", ctypes.c_float * 12), ("campos", ctypes.c_float * 3)]
+
+
+class Settings(ctypes.Structure):
+    _fields_ = [("sh_degree", ctypes.c_int32), ("kappa", ctypes.c_float), ("rho", ctypes.c_float),
+                ("alpha_min", ctypes.c_float), ("alpha_max", ctypes.c_float), ("t_min", ctypes.c_float),
+                ("blur", ctypes.c_float), ("znear", ctypes.c_float), ("clip_fac", ctypes.c_float),
+                ("bg", ctypes.c_float * 3), ("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32),
+                ("batch", ctypes.c_int32), ("radix_bits", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+
+
+class Splats(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("mean", ctypes.c_void_p), ("scale", ctypes.c_void_p),
+                ("quat", ctypes.c_void_p), ("opacity", ctypes.c_void_p), ("beta", ctypes.c_void_p),
+                ("sh", ctypes.c_void_p)]
+
+
+class Proj(ctypes.Structure):
+    _fields_ = [("rec", ctypes.c_void_p), ("tiles_touched", ctypes.c_void_p), ("rect", ctypes.c_void_p),
+                ("depth_key", ctypes.c_void_p)]
+
+
+class Bins(ctypes.Structure):
+    _fields_ = [("m_cap", ctypes.c_uint64), ("tile_sorted", ctypes.c_void_p), ("val_sorted", ctypes.c_void_p),
+                ("ranges", ctypes.c_void_p), ("worklist", ctypes.c_void_p), ("inst_base", ctypes.c_void_p),
+                ("counters", ctypes.c_void_p), ("scratch", ctypes.c_void_p), ("scratch_bytes", ctypes.c_size_t)]
+
+
+class Grads(ctypes.Structure):
+    _fields_ = [("mean", ctypes.c_void_p), ("scale", ctypes.c_void_p), ("quat", ctypes.c_void_p),
+                ("opacity", ctypes.c_void_p), ("beta", ctypes.c_void_p), ("sh", ctypes.c_void_p)]
+
+
+class Sizes(ctypes.Structure):
+    _fields_ = [("total_tiles", ctypes.c_uint64), ("total_pixels", ctypes.c_uint64),
+                ("bin_scratch_bytes", ctypes.c_size_t), ("partial_bytes", ctypes.c_size_t),
+                ("max_sort_blocks", ctypes.c_uint64)]
+
+
+class FwdCounts(ctypes.Structure):
+    _fields_ = [("n_listed", ctypes.c_void_p), ("n_hit", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def load():
+    """Loads libgesr.so; raises if it is missing (no fallback path exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing (run __graft_entry__.build() "
+                           "or python paper_2411_09156_amd/build.py)")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    vp = ctypes.c_void_p
+    st = ctypes.c_int
+    lib.gesr_ctx_create.argtypes = [ctypes.c_int, P(vp)]
+    lib.gesr_ctx_create.restype = st
+    lib.gesr_ctx_destroy.argtypes = [vp]
+    lib.gesr_ctx_destroy.restype = None
+    lib.gesr_last_error.argtypes = [vp]
+    lib.gesr_last_error.restype = ctypes.c_char_p
+    lib.gesr_status_string.argtypes = [st]
+    lib.gesr_status_string.restype = ctypes.c_char_p
+    lib.gesr_default_settings.argtypes = [P(Settings)]
+    lib.gesr_default_settings.restype = None
+    lib.gesr_query_sizes.argtypes = [vp, P(Camera), ctypes.c_int, ctypes.c_int, P(Settings), ctypes.c_uint64,
+                                     P(Sizes)]
+    lib.gesr_query_sizes.restype = st
+    lib.gesr_project.argtypes = [vp, P(Splats), P(Camera), ctypes.c_int, P(Settings), P(Proj), vp]
+    lib.gesr_project.restype = st
+    lib.gesr_bin.argtypes = [vp, P(Proj), P(Camera), ctypes.c_int, ctypes.c_int, P(Settings), P(Bins),
+                             ctypes.c_int, P(ctypes.c_uint64), vp]
+    lib.gesr_bin.restype = st
+    lib.gesr_render_fwd.argtypes = [vp, P(Proj), P(Bins), P(Camera), ctypes.c_int, ctypes.c_int, P(Settings),
+                                    vp, vp, vp, P(FwdCounts), vp]
+    lib.gesr_render_fwd.restype = st
+    lib.gesr_render_bwd.argtypes = [vp, P(Splats), P(Proj), P(Bins), P(Camera), ctypes.c_int, P(Settings),
+                                    vp, vp, vp, vp, vp, P(Grads), vp]
+    lib.gesr_render_bwd.restype = st
+    lib.gesr_l1_grad.argtypes = [vp, vp, vp, ctypes.c_uint64, ctypes.c_float, vp, vp]
+    lib.gesr_l1_grad.restype = st
+    _lib = lib
+    return lib
+
+
+class GesrError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"gesr status {status}: {message}")
+        self.status = status

@@ -1,0 +1,531 @@
+// C ABI of the GES rasterizer: argument validation, scratch layout and the
+// launch sequence of each entry point.  Host code; device work is enqueued on
+// the caller's stream and nothing is allocated here.
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+
+#include "gesr.h"
+#include "gesr_device.h"
+#include "gesr_kernels.h"
+
+struct gesr_ctx {
+    int device;
+    std::string err;
+};
+
+namespace {
+
+using namespace gesr;
+
+gesr_status fail(gesr_ctx* ctx, gesr_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (ctx) ctx->err = buf;
+    return s;
+}
+
+gesr_status hip_check(gesr_ctx* ctx, hipError_t e, const char* what) {
+    if (e == hipSuccess) return GESR_OK;
+    return fail(ctx, GESR_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define GESR_TRY(expr)                      \
+    do {                                    \
+        gesr_status _s = (expr);            \
+        if (_s != GESR_OK) return _s;       \
+    } while (0)
+
+bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
+bool tile_supported(int tw, int th) {
+    return (tw == 16 && th == 16) || (tw == 8 && th == 8) || (tw == 32 && th == 16) || (tw == 32 && th == 32);
+}
+
+gesr_status check_settings(gesr_ctx* ctx, const gesr_settings* st) {
+    if (!st) return fail(ctx, GESR_ERR_INVALID, "settings is NULL");
+    if (st->sh_degree < 0 || st->sh_degree > 3)
+        return fail(ctx, GESR_ERR_INVALID, "sh_degree %d outside 0..3", st->sh_degree);
+    if (!(st->kappa > 0.f) || !isfinite(st->kappa)) return fail(ctx, GESR_ERR_INVALID, "kappa must be > 0");
+    if (!isfinite(st->rho)) return fail(ctx, GESR_ERR_INVALID, "rho must be finite");
+    if (!(st->alpha_min > 0.f && st->alpha_min < st->alpha_max && st->alpha_max < 1.f))
+        return fail(ctx, GESR_ERR_INVALID, "need 0 < alpha_min < alpha_max < 1");
+    if (!(st->t_min > 0.f && st->t_min < 1.f)) return fail(ctx, GESR_ERR_INVALID, "need 0 < t_min < 1");
+    if (!(st->blur >= 0.f) || !isfinite(st->blur)) return fail(ctx, GESR_ERR_INVALID, "blur must be >= 0");
+    if (!(st->znear > 0.f) || !isfinite(st->znear)) return fail(ctx, GESR_ERR_INVALID, "znear must be > 0");
+    if (!(st->clip_fac > 0.f) || !isfinite(st->clip_fac)) return fail(ctx, GESR_ERR_INVALID, "clip_fac must be > 0");
+    for (int c = 0; c < 3; ++c)
+        if (!isfinite(st->bg[c])) return fail(ctx, GESR_ERR_INVALID, "bg must be finite");
+    if (st->tile_w <= 0 || st->tile_h <= 0) return fail(ctx, GESR_ERR_INVALID, "tile size must be positive");
+    if (!tile_supported(st->tile_w, st->tile_h))
+        return fail(ctx, GESR_ERR_UNSUPPORTED, "tile shape %dx%d not supported (16x16, 8x8, 32x16, 32x32)",
+                    st->tile_w, st->tile_h);
+    if (st->radix_bits < 4 || st->radix_bits > 8)
+        return fail(ctx, GESR_ERR_INVALID, "radix_bits %d outside 4..8", st->radix_bits);
+    if (st->batch < 0) return fail(ctx, GESR_ERR_INVALID, "batch must be >= 0");
+    return GESR_OK;
+}
+
+struct Geometry {
+    uint64_t total_tiles = 0, total_pixels = 0;
+    uint64_t vn = 0;
+};
+
+gesr_status check_cams(gesr_ctx* ctx, const gesr_camera* cams, int V, int n, const gesr_settings* st, Geometry* g) {
+    if (!cams) return fail(ctx, GESR_ERR_INVALID, "cams is NULL");
+    if (V < 1 || V > GESR_MAX_VIEWS) return fail(ctx, GESR_ERR_INVALID, "V = %d outside 1..%d", V, GESR_MAX_VIEWS);
+    if (n < 0) return fail(ctx, GESR_ERR_INVALID, "n = %d is negative", n);
+    uint64_t tiles = 0, pix = 0;
+    for (int v = 0; v < V; ++v) {
+        const gesr_camera& c = cams[v];
+        if (c.width < 1 || c.height < 1) return fail(ctx, GESR_ERR_INVALID, "view %d: width/height must be >= 1", v);
+        if (!(c.fx > 0.f) || !(c.fy > 0.f) || !isfinite(c.fx) || !isfinite(c.fy) || !isfinite(c.cx) ||
+            !isfinite(c.cy))
+            return fail(ctx, GESR_ERR_INVALID, "view %d: focal lengths must be finite and > 0", v);
+        for (int k = 0; k < 12; ++k)
+            if (!isfinite(c.viewmat[k])) return fail(ctx, GESR_ERR_INVALID, "view %d: viewmat not finite", v);
+        for (int k = 0; k < 3; ++k)
+            if (!isfinite(c.campos[k])) return fail(ctx, GESR_ERR_INVALID, "view %d: campos not finite", v);
+        const uint64_t tx = ((uint64_t)c.width + st->tile_w - 1) / st->tile_w;
+        const uint64_t ty = ((uint64_t)c.height + st->tile_h - 1) / st->tile_h;
+        if (tx > 0xFFFFu || ty > 0xFFFFu) return fail(ctx, GESR_ERR_INVALID, "view %d: too many tiles per axis", v);
+        tiles += tx * ty;
+        pix += (uint64_t)c.width * (uint64_t)c.height;
+    }
+    if (3 * pix >= (1ull << 32)) return fail(ctx, GESR_ERR_INVALID, "3 * total pixels must be < 2^32");
+    if (tiles >= (1ull << 31)) return fail(ctx, GESR_ERR_INVALID, "too many tiles");
+    const uint64_t vn = (uint64_t)V * (uint64_t)n;
+    if (vn >= (1ull << 32)) return fail(ctx, GESR_ERR_INVALID, "V * n must be < 2^32");
+    g->total_tiles = tiles;
+    g->total_pixels = pix;
+    g->vn = vn;
+    return GESR_OK;
+}
+
+DevSettings dev_settings(const gesr_settings* s) {
+    DevSettings d;
+    d.kappa = s->kappa;
+    d.neg_kappa_log2e = -s->kappa * 1.4426950408889634f;
+    d.rho = s->rho;
+    d.alpha_min = s->alpha_min;
+    d.alpha_max = s->alpha_max;
+    d.t_min = s->t_min;
+    d.blur = s->blur;
+    d.znear = s->znear;
+    d.clip_fac = s->clip_fac;
+    for (int c = 0; c < 3; ++c) d.bg[c] = s->bg[c];
+    d.tile_w = s->tile_w;
+    d.tile_h = s->tile_h;
+    d.sh_degree = s->sh_degree;
+    return d;
+}
+
+DevCams dev_cams(const gesr_camera* cams, int V, const gesr_settings* st) {
+    DevCams d;
+    memset(&d, 0, sizeof d);
+    d.V = V;
+    uint32_t tb = 0, pb = 0;
+    for (int v = 0; v < V; ++v) {
+        const gesr_camera& c = cams[v];
+        DevView& w = d.v[v];
+        w.W = c.width;
+        w.H = c.height;
+        w.fx = c.fx;
+        w.fy = c.fy;
+        w.cx = c.cx;
+        w.cy = c.cy;
+        for (int r = 0; r < 3; ++r) {
+            for (int k = 0; k < 3; ++k) w.R[3 * r + k] = c.viewmat[4 * r + k];
+            w.t[r] = c.viewmat[4 * r + 3];
+            w.campos[r] = c.campos[r];
+        }
+        w.tiles_x = (c.width + st->tile_w - 1) / st->tile_w;
+        w.tiles_y = (c.height + st->tile_h - 1) / st->tile_h;
+        w.tile_base = tb;
+        w.pix_base = pb;
+        tb += (uint32_t)(w.tiles_x * w.tiles_y);
+        pb += (uint32_t)(c.width * c.height);
+    }
+    return d;
+}
+
+// Layout of gesr_bins.scratch (256-byte aligned sub-buffers).
+struct BinScratch {
+    uint32_t *d_keys_a, *d_vals_a, *d_keys_b, *d_vals_b;  // depth sort, [V*n]
+    uint32_t *cnt_sorted, *offsets;                       // [V*n]
+    uint32_t *i_keys, *i_vals;                            // instance sort partner, [m_cap]
+    uint32_t *w_keys_a, *w_vals_a, *w_keys_b;             // worklist sort, [T]
+    uint32_t *block_hist, *scan_partials;
+    size_t bytes;
+};
+
+uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
+
+BinScratch carve(void* base, uint64_t vn, uint64_t m_cap, uint64_t T) {
+    BinScratch s;
+    size_t off = 0;
+    char* b = (char*)base;
+    auto take = [&](uint64_t count) -> uint32_t* {
+        uint32_t* p = b ? (uint32_t*)(b + off) : nullptr;
+        off += ((count * 4 + 255) / 256) * 256;
+        return p;
+    };
+    const uint64_t vn1 = vn > 0 ? vn : 1;
+    const uint64_t T1 = T > 0 ? T : 1;
+    s.d_keys_a = take(vn1);
+    s.d_vals_a = take(vn1);
+    s.d_keys_b = take(vn1);
+    s.d_vals_b = take(vn1);
+    s.cnt_sorted = take(vn1);
+    s.offsets = take(vn1);
+    s.i_keys = take(m_cap);
+    s.i_vals = take(m_cap);
+    s.w_keys_a = take(T1);
+    s.w_vals_a = take(T1);
+    s.w_keys_b = take(T1);
+    uint64_t maxcount = vn1 > m_cap ? vn1 : m_cap;
+    if (T1 > maxcount) maxcount = T1;
+    const uint64_t hist = 256ull * ceil_div(maxcount, SORT_TILE);
+    s.block_hist = take(hist);
+    const uint64_t scan_items = hist > vn1 ? hist : vn1;
+    s.scan_partials = take(ceil_div(scan_items, SCAN_TILE) + 64);
+    s.bytes = off;
+    return s;
+}
+
+int bits_for(uint64_t count) {
+    int b = 0;
+    while (b < 32 && (1ull << b) < count) ++b;
+    return b;
+}
+
+gesr_status check_splats(gesr_ctx* ctx, const gesr_splats* sp, int sh_degree, bool need_all) {
+    if (!sp) return fail(ctx, GESR_ERR_INVALID, "splats is NULL");
+    if (sp->n < 0) return fail(ctx, GESR_ERR_INVALID, "splats->n is negative");
+    if (sp->n == 0 && !need_all) return GESR_OK;
+    const void* ptrs[6] = {sp->mean, sp->scale, sp->quat, sp->opacity, sp->beta, sp->sh};
+    const char* names[6] = {"mean", "scale", "quat", "opacity", "beta", "sh"};
+    for (int k = 0; k < 6; ++k) {
+        if (!ptrs[k]) return fail(ctx, GESR_ERR_INVALID, "splats->%s is NULL", names[k]);
+        if (!aligned16(ptrs[k])) return fail(ctx, GESR_ERR_INVALID, "splats->%s is not 16-byte aligned", names[k]);
+    }
+    (void)sh_degree;
+    return GESR_OK;
+}
+
+gesr_status check_proj(gesr_ctx* ctx, const gesr_proj* p) {
+    if (!p) return fail(ctx, GESR_ERR_INVALID, "proj is NULL");
+    const void* ptrs[4] = {p->rec, p->tiles_touched, p->rect, p->depth_key};
+    const char* names[4] = {"rec", "tiles_touched", "rect", "depth_key"};
+    for (int k = 0; k < 4; ++k) {
+        if (!ptrs[k]) return fail(ctx, GESR_ERR_INVALID, "proj->%s is NULL", names[k]);
+        if (!aligned16(ptrs[k])) return fail(ctx, GESR_ERR_INVALID, "proj->%s is not 16-byte aligned", names[k]);
+    }
+    return GESR_OK;
+}
+
+gesr_status check_bins(gesr_ctx* ctx, const gesr_bins* b, bool need_scratch) {
+    if (!b) return fail(ctx, GESR_ERR_INVALID, "bins is NULL");
+    if (b->m_cap < 1 || b->m_cap >= (1ull << 32))
+        return fail(ctx, GESR_ERR_INVALID, "m_cap must be in [1, 2^32)");
+    const void* ptrs[6] = {b->tile_sorted, b->val_sorted, b->ranges, b->worklist, b->inst_base, b->counters};
+    const char* names[6] = {"tile_sorted", "val_sorted", "ranges", "worklist", "inst_base", "counters"};
+    for (int k = 0; k < 6; ++k) {
+        if (!ptrs[k]) return fail(ctx, GESR_ERR_INVALID, "bins->%s is NULL", names[k]);
+        if (!aligned16(ptrs[k])) return fail(ctx, GESR_ERR_INVALID, "bins->%s is not 16-byte aligned", names[k]);
+    }
+    if (need_scratch && (!b->scratch || !aligned16(b->scratch)))
+        return fail(ctx, GESR_ERR_INVALID, "bins->scratch is NULL or not 16-byte aligned");
+    return GESR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* gesr_status_string(gesr_status s) {
+    switch (s) {
+        case GESR_OK: return "ok";
+        case GESR_ERR_INVALID: return "invalid argument";
+        case GESR_ERR_CAPACITY: return "instance capacity exceeded";
+        case GESR_ERR_HIP: return "HIP error";
+        case GESR_ERR_UNSUPPORTED: return "unsupported";
+    }
+    return "unknown status";
+}
+
+gesr_status gesr_ctx_create(int device, gesr_ctx** out) {
+    if (!out) return GESR_ERR_INVALID;
+    if (device < 0) return GESR_ERR_INVALID;
+    gesr_ctx* c = new gesr_ctx;
+    c->device = device;
+    *out = c;
+    return GESR_OK;
+}
+
+void gesr_ctx_destroy(gesr_ctx* ctx) { delete ctx; }
+
+const char* gesr_last_error(const gesr_ctx* ctx) { return ctx ? ctx->err.c_str() : "context is NULL"; }
+
+void gesr_default_settings(gesr_settings* s) {
+    if (!s) return;
+    memset(s, 0, sizeof *s);
+    s->sh_degree = 0;
+    s->kappa = 0.5f;
+    s->rho = 0.1f;
+    s->alpha_min = 1.0f / 255.0f;
+    s->alpha_max = 0.99f;
+    s->t_min = 1e-4f;
+    s->blur = 0.3f;
+    s->znear = 0.2f;
+    s->clip_fac = 1.3f;
+    s->tile_w = 16;
+    s->tile_h = 16;
+    s->batch = 0;
+    s->radix_bits = 8;
+}
+
+gesr_status gesr_query_sizes(gesr_ctx* ctx, const gesr_camera* cams, int V, int n, const gesr_settings* st,
+                             uint64_t m_cap, gesr_sizes* out) {
+    if (!ctx) return GESR_ERR_INVALID;
+    if (!out) return fail(ctx, GESR_ERR_INVALID, "out is NULL");
+    GESR_TRY(check_settings(ctx, st));
+    Geometry g;
+    GESR_TRY(check_cams(ctx, cams, V, n, st, &g));
+    if (m_cap < 1 || m_cap >= (1ull << 32)) return fail(ctx, GESR_ERR_INVALID, "m_cap must be in [1, 2^32)");
+    BinScratch s = carve(nullptr, g.vn, m_cap, g.total_tiles);
+    out->total_tiles = g.total_tiles;
+    out->total_pixels = g.total_pixels;
+    out->bin_scratch_bytes = s.bytes;
+    out->partial_bytes = (size_t)m_cap * GESR_PARTIAL_FLOATS * sizeof(float);
+    out->max_sort_blocks = ceil_div(m_cap, SORT_TILE);
+    ctx->err.clear();
+    return GESR_OK;
+}
+
+gesr_status gesr_project(gesr_ctx* ctx, const gesr_splats* splats, const gesr_camera* cams, int V,
+                         const gesr_settings* st, const gesr_proj* out, void* stream) {
+    if (!ctx) return GESR_ERR_INVALID;
+    GESR_TRY(check_settings(ctx, st));
+    GESR_TRY(check_splats(ctx, splats, st->sh_degree, false));
+    Geometry g;
+    GESR_TRY(check_cams(ctx, cams, V, splats->n, st, &g));
+    GESR_TRY(check_proj(ctx, out));
+    ProjectArgs a;
+    a.n = splats->n;
+    a.mean = splats->mean;
+    a.scale = splats->scale;
+    a.quat = splats->quat;
+    a.opacity = splats->opacity;
+    a.beta = splats->beta;
+    a.sh = splats->sh;
+    a.rec = out->rec;
+    a.tiles_touched = out->tiles_touched;
+    a.rect = out->rect;
+    a.depth_key = out->depth_key;
+    a.st = dev_settings(st);
+    a.cams = dev_cams(cams, V, st);
+    GESR_TRY(hip_check(ctx, hipSetDevice(ctx->device), "hipSetDevice"));
+    GESR_TRY(hip_check(ctx, launch_project(a, st->sh_degree, (hipStream_t)stream), "project launch"));
+    ctx->err.clear();
+    return GESR_OK;
+}
+
+gesr_status gesr_bin(gesr_ctx* ctx, const gesr_proj* proj, const gesr_camera* cams, int V, int n,
+                     const gesr_settings* st, const gesr_bins* bins, int flags, uint64_t* m_out, void* stream) {
+    if (!ctx) return GESR_ERR_INVALID;
+    GESR_TRY(check_settings(ctx, st));
+    Geometry g;
+    GESR_TRY(check_cams(ctx, cams, V, n, st, &g));
+    GESR_TRY(check_proj(ctx, proj));
+    GESR_TRY(check_bins(ctx, bins, true));
+    BinScratch s = carve(bins->scratch, g.vn, bins->m_cap, g.total_tiles);
+    if (bins->scratch_bytes < s.bytes)
+        return fail(ctx, GESR_ERR_INVALID, "bins->scratch_bytes %zu < required %zu", bins->scratch_bytes, s.bytes);
+    hipStream_t strm = (hipStream_t)stream;
+    GESR_TRY(hip_check(ctx, hipSetDevice(ctx->device), "hipSetDevice"));
+    const DevCams dc = dev_cams(cams, V, st);
+    const uint64_t T = g.total_tiles;
+
+    // 1. depth order of the (view, splat) pairs: LSD passes over the 32 depth bits
+    SortBuffers db{s.d_keys_a, s.d_vals_a, s.d_keys_b, s.d_vals_b, s.block_hist, s.scan_partials};
+    bool in_b = false;
+    GESR_TRY(hip_check(ctx, radix_sort(proj->depth_key, nullptr, g.vn, nullptr, 32, 8, db, &in_b, strm),
+                       "depth sort"));
+    const uint32_t* order = in_b ? s.d_vals_b : s.d_vals_a;
+    // 2. instance offsets in depth order; M -> counters[0]
+    GESR_TRY(hip_check(ctx, launch_gather_counts(order, proj->tiles_touched, s.cnt_sorted, g.vn, strm), "gather"));
+    GESR_TRY(hip_check(ctx, scan_exclusive(s.cnt_sorted, s.offsets, g.vn, s.scan_partials, bins->counters, strm),
+                       "offset scan"));
+    GESR_TRY(hip_check(ctx, launch_set_counters(bins->counters, bins->m_cap, strm), "counters"));
+    if (flags & GESR_BIN_SYNC) {
+        uint32_t m = 0;
+        GESR_TRY(hip_check(ctx, hipMemcpyAsync(&m, bins->counters, sizeof m, hipMemcpyDeviceToHost, strm), "M copy"));
+        GESR_TRY(hip_check(ctx, hipStreamSynchronize(strm), "M sync"));
+        if (m_out) *m_out = m;
+        if ((uint64_t)m > bins->m_cap)
+            return fail(ctx, GESR_ERR_CAPACITY, "M = %u instances exceed m_cap = %llu", m,
+                        (unsigned long long)bins->m_cap);
+    }
+    // 3. duplicate in depth order, then stable sort by tile id
+    const int tile_bits = bits_for(T);
+    const int passes = radix_passes(tile_bits, st->radix_bits);
+    SortBuffers ib;
+    uint32_t *dup_keys, *dup_vals;
+    if (passes % 2 == 1) {  // dup -> scratch (b), final pass lands in the outputs (a)
+        ib = SortBuffers{bins->tile_sorted, bins->val_sorted, s.i_keys, s.i_vals, s.block_hist, s.scan_partials};
+        dup_keys = s.i_keys;
+        dup_vals = s.i_vals;
+    } else {  // dup -> outputs (b); even number of passes returns there
+        ib = SortBuffers{s.i_keys, s.i_vals, bins->tile_sorted, bins->val_sorted, s.block_hist, s.scan_partials};
+        dup_keys = bins->tile_sorted;
+        dup_vals = bins->val_sorted;
+    }
+    GESR_TRY(hip_check(ctx,
+                       launch_duplicate(order, s.offsets, g.vn, n, proj->tiles_touched, proj->rect, dc, bins->m_cap,
+                                        dup_keys, dup_vals, bins->inst_base, strm),
+                       "duplicate"));
+    if (passes > 0) {
+        GESR_TRY(hip_check(ctx,
+                           radix_sort(dup_keys, dup_vals, bins->m_cap, bins->counters + 2, tile_bits,
+                                      st->radix_bits, ib, &in_b, strm),
+                           "tile sort"));
+    }
+    // 4. per-tile ranges
+    GESR_TRY(hip_check(ctx, launch_fill_u32(bins->ranges, 0u, 2 * T, strm), "range fill"));
+    GESR_TRY(hip_check(ctx, launch_ranges(bins->tile_sorted, bins->counters + 2, bins->m_cap, bins->ranges, strm),
+                       "ranges"));
+    // 5. worklist: tiles by decreasing list length
+    GESR_TRY(hip_check(ctx, launch_worklist_keys(bins->ranges, T, s.w_keys_b, strm), "worklist keys"));
+    SortBuffers wb{s.w_keys_a, s.w_vals_a, s.w_keys_b, bins->worklist, s.block_hist, s.scan_partials};
+    GESR_TRY(hip_check(ctx, radix_sort(s.w_keys_b, nullptr, T, nullptr, 16, 8, wb, &in_b, strm), "worklist sort"));
+    ctx->err.clear();
+    return GESR_OK;
+}
+
+gesr_status gesr_render_fwd(gesr_ctx* ctx, const gesr_proj* proj, const gesr_bins* bins, const gesr_camera* cams,
+                            int V, int n, const gesr_settings* st, float* image, float* final_T, uint32_t* n_contrib,
+                            const gesr_fwd_counts* counts, void* stream) {
+    if (!ctx) return GESR_ERR_INVALID;
+    GESR_TRY(check_settings(ctx, st));
+    Geometry g;
+    GESR_TRY(check_cams(ctx, cams, V, n, st, &g));
+    GESR_TRY(check_proj(ctx, proj));
+    GESR_TRY(check_bins(ctx, bins, false));
+    if (!image || !final_T || !n_contrib) return fail(ctx, GESR_ERR_INVALID, "image/final_T/n_contrib is NULL");
+    if (counts && (!counts->n_listed || !counts->n_hit))
+        return fail(ctx, GESR_ERR_INVALID, "counts given with a NULL array");
+    RenderArgs a;
+    memset(&a, 0, sizeof a);
+    a.n = n;
+    a.rec = proj->rec;
+    a.val_sorted = bins->val_sorted;
+    a.ranges = bins->ranges;
+    a.worklist = bins->worklist;
+    a.rect = proj->rect;
+    a.inst_base = bins->inst_base;
+    a.n_items = (uint32_t)g.total_tiles;
+    a.image = image;
+    a.final_T = final_T;
+    a.n_contrib = n_contrib;
+    a.n_listed = counts ? counts->n_listed : nullptr;
+    a.n_hit = counts ? counts->n_hit : nullptr;
+    a.st = dev_settings(st);
+    a.cams = dev_cams(cams, V, st);
+    GESR_TRY(hip_check(ctx, hipSetDevice(ctx->device), "hipSetDevice"));
+    GESR_TRY(hip_check(ctx, launch_render_fwd(a, st->tile_w, st->tile_h, counts != nullptr, (hipStream_t)stream),
+                       "render_fwd launch"));
+    ctx->err.clear();
+    return GESR_OK;
+}
+
+gesr_status gesr_render_bwd(gesr_ctx* ctx, const gesr_splats* splats, const gesr_proj* proj, const gesr_bins* bins,
+                            const gesr_camera* cams, int V, const gesr_settings* st, const float* final_T,
+                            const uint32_t* n_contrib, const float* dL_dimage, float* partials, float* grad2d,
+                            const gesr_grads* out, void* stream) {
+    if (!ctx) return GESR_ERR_INVALID;
+    GESR_TRY(check_settings(ctx, st));
+    GESR_TRY(check_splats(ctx, splats, st->sh_degree, false));
+    Geometry g;
+    GESR_TRY(check_cams(ctx, cams, V, splats->n, st, &g));
+    GESR_TRY(check_proj(ctx, proj));
+    GESR_TRY(check_bins(ctx, bins, false));
+    if (!final_T || !n_contrib || !dL_dimage) return fail(ctx, GESR_ERR_INVALID, "final_T/n_contrib/dL_dimage is NULL");
+    if (!partials || !aligned16(partials)) return fail(ctx, GESR_ERR_INVALID, "partials is NULL or misaligned");
+    if (!out) return fail(ctx, GESR_ERR_INVALID, "out is NULL");
+    if (splats->n > 0) {
+        const void* ptrs[6] = {out->mean, out->scale, out->quat, out->opacity, out->beta, out->sh};
+        for (int k = 0; k < 6; ++k)
+            if (!ptrs[k] || !aligned16(ptrs[k])) return fail(ctx, GESR_ERR_INVALID, "gradient output %d invalid", k);
+    }
+    hipStream_t strm = (hipStream_t)stream;
+    GESR_TRY(hip_check(ctx, hipSetDevice(ctx->device), "hipSetDevice"));
+    const DevSettings ds = dev_settings(st);
+    const DevCams dc = dev_cams(cams, V, st);
+    RenderArgs a;
+    memset(&a, 0, sizeof a);
+    a.n = splats->n;
+    a.rec = proj->rec;
+    a.val_sorted = bins->val_sorted;
+    a.ranges = bins->ranges;
+    a.worklist = bins->worklist;
+    a.rect = proj->rect;
+    a.inst_base = bins->inst_base;
+    a.n_items = (uint32_t)g.total_tiles;
+    a.final_T = const_cast<float*>(final_T);
+    a.n_contrib = const_cast<uint32_t*>(n_contrib);
+    a.dL_dimage = dL_dimage;
+    a.partials = partials;
+    a.st = ds;
+    a.cams = dc;
+    const int batch = st->batch > 0 ? st->batch : 64;
+    GESR_TRY(hip_check(ctx, launch_render_bwd(a, st->tile_w, st->tile_h, batch, strm), "render_bwd launch"));
+    ProjectBwdArgs b;
+    b.n = splats->n;
+    b.mean = splats->mean;
+    b.scale = splats->scale;
+    b.quat = splats->quat;
+    b.opacity = splats->opacity;
+    b.beta = splats->beta;
+    b.sh = splats->sh;
+    b.tiles_touched = proj->tiles_touched;
+    b.inst_base = bins->inst_base;
+    b.partials = partials;
+    b.m_cap = bins->m_cap;
+    b.grad2d = grad2d;
+    b.g_mean = out->mean;
+    b.g_scale = out->scale;
+    b.g_quat = out->quat;
+    b.g_opacity = out->opacity;
+    b.g_beta = out->beta;
+    b.g_sh = out->sh;
+    b.st = ds;
+    b.cams = dc;
+    GESR_TRY(hip_check(ctx, launch_project_bwd(b, st->sh_degree, strm), "project_bwd launch"));
+    ctx->err.clear();
+    return GESR_OK;
+}
+
+gesr_status gesr_l1_grad(gesr_ctx* ctx, const float* image, const float* target, uint64_t count, float scale,
+                         float* grad, void* stream) {
+    if (!ctx) return GESR_ERR_INVALID;
+    if (count > 0 && (!image || !target || !grad)) return fail(ctx, GESR_ERR_INVALID, "NULL array");
+    if (!isfinite(scale)) return fail(ctx, GESR_ERR_INVALID, "scale must be finite");
+    GESR_TRY(hip_check(ctx, hipSetDevice(ctx->device), "hipSetDevice"));
+    GESR_TRY(hip_check(ctx, launch_l1_grad(image, target, count, scale, grad, (hipStream_t)stream), "l1 launch"));
+    ctx->err.clear();
+    return GESR_OK;
+}
+
+}  // extern "C"
+
+static_assert(sizeof(gesr::RenderArgs) < 4000, "kernel arguments too large");
+static_assert(sizeof(gesr::ProjectArgs) < 4000, "kernel arguments too large");
+static_assert(sizeof(gesr::ProjectBwdArgs) < 4000, "kernel arguments too large");

@@ -1,0 +1,103 @@
+// Device-side definitions shared by the GES rasterizer kernels (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gesr.h"
+
+namespace gesr {
+
+// Per-view constants, passed by value in kernel arguments.
+struct DevView {
+    int W, H;
+    float fx, fy, cx, cy;
+    float R[9];  // world -> camera rotation (row-major)
+    float t[3];
+    float campos[3];
+    int tiles_x, tiles_y;
+    uint32_t tile_base;  // first global tile id of the view
+    uint32_t pix_base;   // first pixel of the view in the concatenated outputs
+};
+
+struct DevCams {
+    int V;
+    int pad[3];
+    DevView v[GESR_MAX_VIEWS];
+};
+
+struct DevSettings {
+    float kappa;
+    float neg_kappa_log2e;  // -kappa * log2(e): G = exp2(neg_kappa_log2e * P)
+    float rho;
+    float alpha_min, alpha_max, t_min;
+    float blur, znear, clip_fac;
+    float bg[3];
+    int tile_w, tile_h;
+    int sh_degree;
+};
+
+constexpr float kLn2 = 0.693147180559945309f;
+
+__device__ __forceinline__ float hw_log2(float x) { return __builtin_amdgcn_logf(x); }
+__device__ __forceinline__ float hw_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
+__device__ __forceinline__ float hw_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// Index of the view that owns global tile `t` (views are few; linear scan).
+__device__ __forceinline__ int view_of_tile(const DevCams& c, uint32_t t) {
+    int v = 0;
+    while (v + 1 < c.V && t >= c.v[v + 1].tile_base) ++v;
+    return v;
+}
+
+// Screen-space record of one projected splat as staged by the renderers.
+//   a = (u, v, L00, L10), b = (L11, opacity, beta / 2, qmax), c = (r, g, b, -)
+// with the conic factored as q = (L00 dx + L10 dy)^2 + (L11 dy)^2.  The
+// generalized-exponential falloff G = exp(-kappa q^(beta/2)) is evaluated by
+// `ges_alpha`; the forward and the backward call the same functions so alpha
+// is bit-identical in both.
+struct Fragment {
+    float dx, dy, t, w, q, l2q, P, G, oG, alpha;
+};
+
+__device__ __forceinline__ float ges_q(const float4& a, float L11, float px, float py, Fragment& f) {
+    f.dx = px - a.x;
+    f.dy = py - a.y;
+    f.t = fmaf(a.w, f.dy, a.z * f.dx);
+    f.w = L11 * f.dy;
+    return fmaf(f.t, f.t, f.w * f.w);
+}
+
+__device__ __forceinline__ void ges_alpha(float q, float half_beta, float opacity, const DevSettings& st, Fragment& f) {
+    f.q = q;
+    f.l2q = hw_log2(q);                    // -inf at q = 0
+    f.P = hw_exp2(half_beta * f.l2q);      // q^(beta/2); 0 at q = 0
+    f.G = hw_exp2(st.neg_kappa_log2e * f.P);
+    f.oG = opacity * f.G;
+    f.alpha = fminf(st.alpha_max, f.oG);
+}
+
+// Wave-wide sum (64 lanes) by butterfly; every lane receives the total.
+__device__ __forceinline__ float wave_sum(float x) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) x += __shfl_xor(x, m, 64);
+    return x;
+}
+
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t x) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        uint32_t y = __shfl_xor(x, m, 64);
+        x = x > y ? x : y;
+    }
+    return x;
+}
+
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+    uint32_t l = __lane_id();
+    return l == 0 ? 0ull : ((~0ull) >> (64 - l));
+}
+
+}  // namespace gesr

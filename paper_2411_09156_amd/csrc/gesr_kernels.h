@@ -1,0 +1,104 @@
+// Kernel argument blocks and launchers of the GES rasterizer (host + device).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gesr_device.h"
+
+namespace gesr {
+
+struct ProjectArgs {
+    int n;
+    const float *mean, *scale, *quat, *opacity, *beta, *sh;
+    float* rec;
+    uint32_t* tiles_touched;
+    uint32_t* rect;
+    uint32_t* depth_key;
+    DevSettings st;
+    DevCams cams;
+};
+
+struct ProjectBwdArgs {
+    int n;
+    const float *mean, *scale, *quat, *opacity, *beta, *sh;
+    const uint32_t* tiles_touched;
+    const uint32_t* inst_base;
+    const float* partials;
+    uint64_t m_cap;  // partials hold instances [0, m_cap)
+    float* grad2d;  // nullable
+    float *g_mean, *g_scale, *g_quat, *g_opacity, *g_beta, *g_sh;
+    DevSettings st;
+    DevCams cams;
+};
+
+struct RenderArgs {
+    int n;
+    const float* rec;
+    const uint32_t* val_sorted;
+    const uint32_t* ranges;
+    const uint32_t* worklist;
+    const uint32_t* rect;
+    const uint32_t* inst_base;
+    uint32_t n_items;  // number of work items (tiles) in the worklist
+    // forward outputs / backward inputs
+    float* image;
+    float* final_T;
+    uint32_t* n_contrib;
+    uint32_t* n_listed;  // nullable
+    uint32_t* n_hit;     // nullable
+    // backward
+    const float* dL_dimage;
+    float* partials;
+    DevSettings st;
+    DevCams cams;
+};
+
+hipError_t launch_project(const ProjectArgs& a, int sh_degree, hipStream_t stream);
+hipError_t launch_project_bwd(const ProjectBwdArgs& a, int sh_degree, hipStream_t stream);
+hipError_t launch_render_fwd(const RenderArgs& a, int tile_w, int tile_h, bool counts, hipStream_t stream);
+hipError_t launch_render_bwd(const RenderArgs& a, int tile_w, int tile_h, int batch, hipStream_t stream);
+
+// ---------------------------------------------------------------- sorting
+constexpr int SORT_THREADS = 256;
+constexpr int SORT_ITEMS = 16;
+constexpr int SORT_TILE = SORT_THREADS * SORT_ITEMS;  // keys per sort block
+constexpr int SCAN_TILE = 4096;                       // items per scan block
+constexpr int SCAN_TOP_MAX = 32768;                   // max blocks of a two-level scan
+
+// Exclusive scan of `count` uint32 values; the grand total goes to *total
+// (device, nullable).  `partials` needs ceil(count / SCAN_TILE) entries.
+hipError_t scan_exclusive(const uint32_t* in, uint32_t* out, uint64_t count, uint32_t* partials, uint32_t* total,
+                          hipStream_t stream);
+
+// Stable LSD radix sort of `count_static` (or *count_dev when non-null, which
+// must not exceed count_static) 32-bit keys over bits [0, key_bits) carrying
+// 32-bit values.  vals_in == nullptr means values are the positions 0..n-1.
+// Ping-pongs between (keys_a, vals_a) and (keys_b, vals_b); the first pass
+// reads keys_in / vals_in.  Returns (via *result_in_b) whether the result
+// ends in the b buffers.
+struct SortBuffers {
+    uint32_t *keys_a, *vals_a, *keys_b, *vals_b;
+    uint32_t* block_hist;  // 2^radix_bits * ceil(count_static / SORT_TILE)
+    uint32_t* scan_partials;
+};
+hipError_t radix_sort(const uint32_t* keys_in, const uint32_t* vals_in, uint64_t count_static,
+                      const uint32_t* count_dev, int key_bits, int radix_bits, const SortBuffers& b,
+                      bool* result_in_b, hipStream_t stream);
+int radix_passes(int key_bits, int radix_bits);
+
+// Binning helper kernels.
+hipError_t launch_gather_counts(const uint32_t* order, const uint32_t* tiles_touched, uint32_t* out, uint64_t count,
+                                hipStream_t stream);
+hipError_t launch_duplicate(const uint32_t* order, const uint32_t* offsets, uint64_t count, int n,
+                            const uint32_t* tiles_touched, const uint32_t* rect, const DevCams& cams,
+                            uint64_t m_cap, uint32_t* keys, uint32_t* vals, uint32_t* inst_base, hipStream_t stream);
+hipError_t launch_set_counters(uint32_t* counters, uint64_t m_cap, hipStream_t stream);
+hipError_t launch_fill_u32(uint32_t* p, uint32_t value, uint64_t count, hipStream_t stream);
+hipError_t launch_ranges(const uint32_t* tiles, const uint32_t* count_dev, uint64_t m_cap, uint32_t* ranges,
+                         hipStream_t stream);
+hipError_t launch_worklist_keys(const uint32_t* ranges, uint64_t total_tiles, uint32_t* keys, hipStream_t stream);
+hipError_t launch_l1_grad(const float* image, const float* target, uint64_t count, float scale, float* grad,
+                          hipStream_t stream);
+
+}  // namespace gesr

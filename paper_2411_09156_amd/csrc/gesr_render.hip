@@ -1,0 +1,304 @@
+// Tile renderers of the GES rasterizer (gfx950).
+//
+// Forward: front-to-back alpha blending (Eq. 5 evaluated discretely) of the
+// generalized-exponential falloff exp(-kappa q^(beta/2)) (Eq. 3 in screen
+// space).  One workgroup per (view, tile) work item, taken in worklist order
+// (longest lists first, so the hardware dispatcher schedules greedily by
+// load); each wave covers an 8x8 pixel block so lanes of a wave see similar
+// footprints.  Splat records are staged through LDS in batches and every lane
+// reads them by broadcast.
+//
+// Backward: the same tile mapping, traversing each pixel's list in reverse
+// from its n_contrib and recovering transmittance by division from final_T
+// (no per-fragment state is stored in the forward).  Per splat, each wave
+// sums its pixels' 10 gradient terms with cross-lane reductions, the waves'
+// sums are added in fixed order, and the tile writes one partial per
+// instance: no atomics, bitwise reproducible.
+
+#include "gesr_device.h"
+#include "gesr_kernels.h"
+
+namespace gesr {
+
+namespace {
+
+template <int TW, int TH>
+struct TileMap {
+    static constexpr int NT = TW * TH;
+    static constexpr int NW = NT / 64;
+    static constexpr int WX = TW / 8;
+    // pixel offset inside the tile of thread `tid`
+    __device__ static __forceinline__ void pixel(int tid, int& lx, int& ly) {
+        const int w = tid >> 6, l = tid & 63;
+        lx = (w % WX) * 8 + (l & 7);
+        ly = (w / WX) * 8 + (l >> 3);
+    }
+};
+
+struct TileInfo {
+    int v;
+    int x, y;       // pixel of this thread
+    bool inside;
+    uint32_t pix;   // index into per-pixel arrays
+    uint32_t ch;    // channel stride of the view (H * W)
+    uint32_t img;   // index of channel 0 in the image arrays
+    uint32_t tx, ty;
+    uint32_t r0, r1;  // list range
+};
+
+template <int TW, int TH>
+__device__ __forceinline__ TileInfo tile_info(const RenderArgs& a, uint32_t t) {
+    TileInfo ti;
+    ti.v = view_of_tile(a.cams, t);
+    const DevView& w = a.cams.v[ti.v];
+    const uint32_t lt = t - w.tile_base;
+    ti.tx = lt % (uint32_t)w.tiles_x;
+    ti.ty = lt / (uint32_t)w.tiles_x;
+    int lx, ly;
+    TileMap<TW, TH>::pixel(threadIdx.x, lx, ly);
+    ti.x = (int)ti.tx * TW + lx;
+    ti.y = (int)ti.ty * TH + ly;
+    ti.inside = ti.x < w.W && ti.y < w.H;
+    const uint32_t local = (uint32_t)ti.y * (uint32_t)w.W + (uint32_t)ti.x;
+    ti.pix = w.pix_base + local;
+    ti.ch = (uint32_t)w.W * (uint32_t)w.H;
+    ti.img = 3u * w.pix_base + local;
+    const uint2 r = reinterpret_cast<const uint2*>(a.ranges)[t];
+    ti.r0 = r.x;
+    ti.r1 = r.y;
+    return ti;
+}
+
+// Stage record `vi` into LDS as (u, v, L00, L10), (L11, o, beta/2, qmax), (r, g, b, -).
+__device__ __forceinline__ void stage_record(const float* rec, uint32_t vi, float4& sa, float4& sb, float4& sc) {
+    const float4* r = reinterpret_cast<const float4*>(rec + (size_t)vi * GESR_REC_FLOATS);
+    float4 b = r[1];
+    sa = r[0];
+    sb = make_float4(b.x, b.y, 0.5f * b.z, b.w);
+    sc = r[2];
+}
+
+template <int TW, int TH, bool COUNT>
+__global__ __launch_bounds__(TW * TH) void k_render_fwd(RenderArgs a) {
+    constexpr int NT = TW * TH;
+    __shared__ float4 sA[NT], sB[NT], sC[NT];
+    const uint32_t t = a.worklist[blockIdx.x];
+    const TileInfo ti = tile_info<TW, TH>(a, t);
+    const DevSettings& st = a.st;
+    const float px = (float)ti.x + 0.5f, py = (float)ti.y + 0.5f;
+
+    float T = 1.0f, cr = 0.f, cg = 0.f, cb = 0.f;
+    uint32_t contrib = 0, listed = 0, hit = 0;
+    bool done = !ti.inside;
+    for (uint32_t base = ti.r0; base < ti.r1; base += NT) {
+        if (__syncthreads_count(done) == NT) break;
+        const uint32_t pos = base + threadIdx.x;
+        if (pos < ti.r1) stage_record(a.rec, a.val_sorted[pos], sA[threadIdx.x], sB[threadIdx.x], sC[threadIdx.x]);
+        __syncthreads();
+        const int cnt = (int)min<uint32_t>(NT, ti.r1 - base);
+        if (!done) {
+            for (int j = 0; j < cnt; ++j) {
+                const float4 ra = sA[j];
+                const float4 rb = sB[j];
+                Fragment f;
+                const float q = ges_q(ra, rb.x, px, py, f);
+                if (COUNT) ++listed;
+                if (q > rb.w) continue;  // beyond the alpha_min footprint
+                ges_alpha(q, rb.z, rb.y, st, f);
+                if (f.alpha < st.alpha_min) continue;
+                if (COUNT) ++hit;
+                const float Tn = T * (1.0f - f.alpha);
+                if (Tn < st.t_min) {
+                    done = true;
+                    break;
+                }
+                const float4 rc = sC[j];
+                const float w = f.alpha * T;
+                cr = fmaf(rc.x, w, cr);
+                cg = fmaf(rc.y, w, cg);
+                cb = fmaf(rc.z, w, cb);
+                T = Tn;
+                contrib = base + (uint32_t)j + 1u - ti.r0;
+            }
+        }
+    }
+    if (ti.inside) {
+        a.image[ti.img] = fmaf(T, st.bg[0], cr);
+        a.image[ti.img + ti.ch] = fmaf(T, st.bg[1], cg);
+        a.image[ti.img + 2 * ti.ch] = fmaf(T, st.bg[2], cb);
+        a.final_T[ti.pix] = T;
+        a.n_contrib[ti.pix] = contrib;
+        if (COUNT) {
+            a.n_listed[ti.pix] = listed;
+            a.n_hit[ti.pix] = hit;
+        }
+    }
+}
+
+template <int TW, int TH, int BATCH>
+__global__ __launch_bounds__(TW * TH) void k_render_bwd(RenderArgs a) {
+    constexpr int NT = TW * TH;
+    constexpr int NW = NT / 64;
+    constexpr int NP = GESR_PARTIAL_FLOATS;
+    static_assert(BATCH <= NT, "batch larger than the workgroup");
+    __shared__ float4 sA[BATCH], sB[BATCH], sC[BATCH];
+    __shared__ uint32_t sInst[BATCH];
+    __shared__ float sRed[NW][BATCH][NP];
+    __shared__ uint32_t sMax[NW];
+
+    const uint32_t t = a.worklist[blockIdx.x];
+    const TileInfo ti = tile_info<TW, TH>(a, t);
+    const DevSettings& st = a.st;
+    const float px = (float)ti.x + 0.5f, py = (float)ti.y + 0.5f;
+    const uint32_t lane = __lane_id(), wave = threadIdx.x >> 6;
+
+    float T = 0.f, g0 = 0.f, g1 = 0.f, g2 = 0.f;
+    uint32_t nc = 0;
+    if (ti.inside) {
+        T = a.final_T[ti.pix];
+        nc = a.n_contrib[ti.pix];
+        g0 = a.dL_dimage[ti.img];
+        g1 = a.dL_dimage[ti.img + ti.ch];
+        g2 = a.dL_dimage[ti.img + 2 * ti.ch];
+    }
+    float Br = st.bg[0], Bg = st.bg[1], Bb = st.bg[2];  // colour behind, per unit transmittance
+
+    // deepest list position any pixel of the tile composited
+    const uint32_t wmax = wave_max_u32(nc);
+    if (lane == 0) sMax[wave] = wmax;
+    __syncthreads();
+    uint32_t maxnc = 0;
+    for (int w = 0; w < NW; ++w) maxnc = max(maxnc, sMax[w]);
+    const uint32_t end = ti.r0 + maxnc;
+
+    for (uint32_t hi = end; hi > ti.r0;) {
+        const uint32_t lo = (hi - ti.r0 > (uint32_t)BATCH) ? hi - BATCH : ti.r0;
+        const int cnt = (int)(hi - lo);
+        if ((int)threadIdx.x < cnt) {
+            const uint32_t pos = hi - 1u - threadIdx.x;
+            const uint32_t vi = a.val_sorted[pos];
+            stage_record(a.rec, vi, sA[threadIdx.x], sB[threadIdx.x], sC[threadIdx.x]);
+            const uint2 r = reinterpret_cast<const uint2*>(a.rect)[vi];
+            const uint32_t tx0 = r.x & 0xFFFFu, ty0 = r.x >> 16, tx1 = r.y & 0xFFFFu;
+            sInst[threadIdx.x] = a.inst_base[vi] + (ti.ty - ty0) * (tx1 - tx0 + 1u) + (ti.tx - tx0);
+        }
+        __syncthreads();
+        for (int j = 0; j < cnt; ++j) {
+            const uint32_t prel = hi - 1u - (uint32_t)j - ti.r0;  // 0-based list position
+            float gr[NP];
+#pragma unroll
+            for (int k = 0; k < NP; ++k) gr[k] = 0.f;
+            bool act = false;
+            if (prel < nc) {
+                const float4 ra = sA[j];
+                const float4 rb = sB[j];
+                Fragment f;
+                const float q = ges_q(ra, rb.x, px, py, f);
+                if (q <= rb.w) {
+                    ges_alpha(q, rb.z, rb.y, st, f);
+                    if (f.alpha >= st.alpha_min) {
+                        act = true;
+                        const float4 rc = sC[j];
+                        const float Tk = T * hw_rcp(1.0f - f.alpha);
+                        const float aT = f.alpha * Tk;
+                        gr[7] = aT * g0;
+                        gr[8] = aT * g1;
+                        gr[9] = aT * g2;
+                        const float dLda = Tk * ((rc.x - Br) * g0 + (rc.y - Bg) * g1 + (rc.z - Bb) * g2);
+                        Br = fmaf(f.alpha, rc.x - Br, Br);
+                        Bg = fmaf(f.alpha, rc.y - Bg, Bg);
+                        Bb = fmaf(f.alpha, rc.z - Bb, Bb);
+                        T = Tk;
+                        if (f.oG <= st.alpha_max) {
+                            gr[5] = dLda * f.G;
+                            const float dLdG = dLda * rb.y;
+                            if (f.q > 1e-30f) {
+                                const float kGP = -st.kappa * f.G * f.P;  // dG/dP * P
+                                const float dLdq = dLdG * kGP * rb.z * hw_rcp(f.q);
+                                gr[6] = dLdG * kGP * 0.5f * (f.l2q * kLn2);
+                                // q = t^2 + w^2, t = L00 dx + L10 dy, w = L11 dy, dx = px - u
+                                const float tq = 2.0f * dLdq * f.t, wq = 2.0f * dLdq * f.w;
+                                gr[0] = -tq * ra.z;
+                                gr[1] = -(tq * ra.w + wq * rb.x);
+                                gr[2] = tq * f.dx;
+                                gr[3] = tq * f.dy;
+                                gr[4] = wq * f.dy;
+                            }
+                        }
+                    }
+                }
+            }
+            if (__ballot(act) != 0ull) {
+#pragma unroll
+                for (int k = 0; k < NP; ++k) gr[k] = wave_sum(gr[k]);
+                if (lane == 0)
+#pragma unroll
+                    for (int k = 0; k < NP; ++k) sRed[wave][j][k] = gr[k];
+            } else if (lane == 0) {
+#pragma unroll
+                for (int k = 0; k < NP; ++k) sRed[wave][j][k] = 0.f;
+            }
+        }
+        __syncthreads();
+        for (int jj = threadIdx.x; jj < cnt; jj += NT) {
+            float s[NP];
+#pragma unroll
+            for (int k = 0; k < NP; ++k) s[k] = sRed[0][jj][k];
+            for (int w = 1; w < NW; ++w)
+#pragma unroll
+                for (int k = 0; k < NP; ++k) s[k] += sRed[w][jj][k];
+            float2* dst = reinterpret_cast<float2*>(a.partials + (size_t)sInst[jj] * NP);
+#pragma unroll
+            for (int k = 0; k < NP / 2; ++k) dst[k] = make_float2(s[2 * k], s[2 * k + 1]);
+        }
+        __syncthreads();
+        hi = lo;
+    }
+    // instances after the deepest composited position contribute nothing
+    for (uint32_t pos = end + threadIdx.x; pos < ti.r1; pos += NT) {
+        const uint32_t vi = a.val_sorted[pos];
+        const uint2 r = reinterpret_cast<const uint2*>(a.rect)[vi];
+        const uint32_t tx0 = r.x & 0xFFFFu, ty0 = r.x >> 16, tx1 = r.y & 0xFFFFu;
+        const uint32_t inst = a.inst_base[vi] + (ti.ty - ty0) * (tx1 - tx0 + 1u) + (ti.tx - tx0);
+        float2* dst = reinterpret_cast<float2*>(a.partials + (size_t)inst * NP);
+#pragma unroll
+        for (int k = 0; k < NP / 2; ++k) dst[k] = make_float2(0.f, 0.f);
+    }
+}
+
+template <int TW, int TH>
+hipError_t fwd_shape(const RenderArgs& a, bool counts, hipStream_t s) {
+    if (counts)
+        hipLaunchKernelGGL((k_render_fwd<TW, TH, true>), dim3(a.n_items), dim3(TW * TH), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_render_fwd<TW, TH, false>), dim3(a.n_items), dim3(TW * TH), 0, s, a);
+    return hipGetLastError();
+}
+
+template <int TW, int TH, int BATCH>
+hipError_t bwd_shape(const RenderArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL((k_render_bwd<TW, TH, BATCH>), dim3(a.n_items), dim3(TW * TH), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_render_fwd(const RenderArgs& a, int tw, int th, bool counts, hipStream_t s) {
+    if (a.n_items == 0) return hipSuccess;
+    if (tw == 16 && th == 16) return fwd_shape<16, 16>(a, counts, s);
+    if (tw == 8 && th == 8) return fwd_shape<8, 8>(a, counts, s);
+    if (tw == 32 && th == 16) return fwd_shape<32, 16>(a, counts, s);
+    if (tw == 32 && th == 32) return fwd_shape<32, 32>(a, counts, s);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_render_bwd(const RenderArgs& a, int tw, int th, int batch, hipStream_t s) {
+    if (a.n_items == 0) return hipSuccess;
+    if (tw == 16 && th == 16) return batch >= 128 ? bwd_shape<16, 16, 128>(a, s) : bwd_shape<16, 16, 64>(a, s);
+    if (tw == 8 && th == 8) return bwd_shape<8, 8, 64>(a, s);
+    if (tw == 32 && th == 16) return batch >= 128 ? bwd_shape<32, 16, 128>(a, s) : bwd_shape<32, 16, 64>(a, s);
+    if (tw == 32 && th == 32) return bwd_shape<32, 32, 64>(a, s);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace gesr

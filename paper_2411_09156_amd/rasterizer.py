@@ -1,0 +1,282 @@
+"""Python binding of libgesr: buffer allocation (torch) and argument marshalling.
+
+Every step of the rasterizer runs in the HIP library; this module only
+allocates device tensors with torch's caching allocator, fills the C structs
+of include/gesr.h with their addresses and passes torch's current stream.
+
+Layouts (device, float32 unless noted):
+  splats  mean [3, N], scale [3, N], quat [4, N] (w, x, y, z), opacity [N],
+          beta [N], sh [K * 3, N] (coefficient k of channel c at row 3k + c)
+  image   concatenation over views of [3, H, W] (CHW), flat [3 * P]
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+from typing import List, Optional, Sequence
+
+import torch
+
+from . import _lib
+
+
+@dataclasses.dataclass
+class RasterSettings:
+    """Mirror of gesr_settings (see include/gesr.h for the meaning of each field)."""
+    sh_degree: int = 0
+    kappa: float = 0.5
+    rho: float = 0.1
+    alpha_min: float = 1.0 / 255.0
+    alpha_max: float = 0.99
+    t_min: float = 1e-4
+    blur: float = 0.3
+    znear: float = 0.2
+    clip_fac: float = 1.3
+    bg: Sequence[float] = (0.0, 0.0, 0.0)
+    tile_w: int = 16
+    tile_h: int = 16
+    batch: int = 0
+    radix_bits: int = 8
+
+    def to_c(self) -> _lib.Settings:
+        s = _lib.Settings()
+        s.sh_degree = self.sh_degree
+        s.kappa, s.rho = self.kappa, self.rho
+        s.alpha_min, s.alpha_max, s.t_min = self.alpha_min, self.alpha_max, self.t_min
+        s.blur, s.znear, s.clip_fac = self.blur, self.znear, self.clip_fac
+        for c in range(3):
+            s.bg[c] = float(self.bg[c])
+        s.tile_w, s.tile_h, s.batch, s.radix_bits = self.tile_w, self.tile_h, self.batch, self.radix_bits
+        return s
+
+
+def cameras_to_c(cameras) -> ctypes.Array:
+    """Any objects with width, height, fx, fy, cx, cy, viewmat (3x4), campos (3)."""
+    arr = (_lib.Camera * len(cameras))()
+    for k, c in enumerate(cameras):
+        arr[k].width, arr[k].height = int(c.width), int(c.height)
+        arr[k].fx, arr[k].fy, arr[k].cx, arr[k].cy = float(c.fx), float(c.fy), float(c.cx), float(c.cy)
+        vm = [float(x) for row in c.viewmat for x in row]
+        for j in range(12):
+            arr[k].viewmat[j] = vm[j]
+        for j in range(3):
+            arr[k].campos[j] = float(c.campos[j])
+    return arr
+
+
+@dataclasses.dataclass
+class Splats:
+    """SoA device tensors of the rasterizer inputs."""
+    mean: torch.Tensor
+    scale: torch.Tensor
+    quat: torch.Tensor
+    opacity: torch.Tensor
+    beta: torch.Tensor
+    sh: torch.Tensor
+
+    @property
+    def n(self) -> int:
+        return int(self.opacity.shape[0])
+
+    def tensors(self):
+        return (self.mean, self.scale, self.quat, self.opacity, self.beta, self.sh)
+
+    @staticmethod
+    def from_aos(means, scales, quats, opacities, betas, sh, device="cuda") -> "Splats":
+        """From row-per-splat arrays ([N,3], [N,3], [N,4], [N], [N], [N,K,3])."""
+        def t(x):
+            return torch.as_tensor(x, dtype=torch.float32).to(device)
+        n = t(opacities).shape[0]
+        return Splats(t(means).t().contiguous(), t(scales).t().contiguous(), t(quats).t().contiguous(),
+                      t(opacities).contiguous(), t(betas).contiguous(), t(sh).reshape(n, -1).t().contiguous())
+
+    def to_c(self) -> _lib.Splats:
+        s = _lib.Splats()
+        s.n = self.n
+        s.mean, s.scale, s.quat = self.mean.data_ptr(), self.scale.data_ptr(), self.quat.data_ptr()
+        s.opacity, s.beta, s.sh = self.opacity.data_ptr(), self.beta.data_ptr(), self.sh.data_ptr()
+        return s
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Rasterizer:
+    """One rasterizer per (camera set, settings).  Calls enqueue on torch's
+    current stream; outputs are freshly allocated device tensors."""
+
+    def __init__(self, cameras, settings: RasterSettings, device: int = 0):
+        self.lib = _lib.load()
+        self.cameras = list(cameras)
+        self.V = len(self.cameras)
+        self.settings = settings
+        self.st_c = settings.to_c()
+        self.cams_c = cameras_to_c(self.cameras)
+        self.device = torch.device("cuda", device)
+        ctx = ctypes.c_void_p()
+        self._check(self.lib.gesr_ctx_create(device, ctypes.byref(ctx)), None)
+        self.ctx = ctx
+        self.m_cap_hint = 0
+        self.views = [(int(c.width), int(c.height)) for c in self.cameras]
+        self.n_pixels = sum(w * h for w, h in self.views)
+
+    def __del__(self):
+        lib = getattr(self, "lib", None)
+        if lib is not None and getattr(self, "ctx", None):
+            lib.gesr_ctx_destroy(self.ctx)
+            self.ctx = None
+
+    # ------------------------------------------------------------ helpers
+    def _check(self, status: int, ctx) -> None:
+        if status != _lib.GESR_OK:
+            msg = self.lib.gesr_last_error(ctx).decode() if ctx else self.lib.gesr_status_string(status).decode()
+            raise _lib.GesrError(status, msg)
+
+    def sizes(self, n: int, m_cap: int) -> _lib.Sizes:
+        out = _lib.Sizes()
+        self._check(self.lib.gesr_query_sizes(self.ctx, self.cams_c, self.V, n, ctypes.byref(self.st_c),
+                                              max(int(m_cap), 1), ctypes.byref(out)), self.ctx)
+        return out
+
+    def _empty(self, n, dtype=torch.float32):
+        return torch.empty(max(int(n), 1), dtype=dtype, device=self.device)
+
+    # ---------------------------------------------------------- pipeline
+    def project(self, sp: Splats) -> dict:
+        vn = self.V * sp.n
+        p = dict(rec=self._empty(vn * _lib.REC_FLOATS), tiles_touched=self._empty(vn, torch.int32),
+                 rect=self._empty(2 * vn, torch.int32), depth_key=self._empty(vn, torch.int32))
+        self._check(self.lib.gesr_project(self.ctx, ctypes.byref(sp.to_c()), self.cams_c, self.V,
+                                          ctypes.byref(self.st_c), ctypes.byref(self._proj_c(p)), _stream()),
+                    self.ctx)
+        return p
+
+    @staticmethod
+    def _proj_c(p) -> _lib.Proj:
+        c = _lib.Proj()
+        c.rec, c.tiles_touched = p["rec"].data_ptr(), p["tiles_touched"].data_ptr()
+        c.rect, c.depth_key = p["rect"].data_ptr(), p["depth_key"].data_ptr()
+        return c
+
+    def alloc_bins(self, n: int, m_cap: int) -> dict:
+        sz = self.sizes(n, m_cap)
+        T = int(sz.total_tiles)
+        return dict(m_cap=int(m_cap), tile_sorted=self._empty(m_cap, torch.int32),
+                    val_sorted=self._empty(m_cap, torch.int32), ranges=self._empty(2 * T, torch.int32),
+                    worklist=self._empty(T, torch.int32), inst_base=self._empty(self.V * n, torch.int32),
+                    counters=self._empty(4, torch.int32),
+                    scratch=torch.empty(int(sz.bin_scratch_bytes), dtype=torch.uint8, device=self.device),
+                    total_tiles=T)
+
+    @staticmethod
+    def _bins_c(b) -> _lib.Bins:
+        c = _lib.Bins()
+        c.m_cap = b["m_cap"]
+        for k in ("tile_sorted", "val_sorted", "ranges", "worklist", "inst_base", "counters", "scratch"):
+            setattr(c, k, b[k].data_ptr())
+        c.scratch_bytes = b["scratch"].numel()
+        return c
+
+    def bin(self, proj: dict, n: int, m_cap: Optional[int] = None, sync: bool = True) -> dict:
+        """Bins the projected splats.  With sync (eager) the instance count is read
+        back and the buffers regrown if needed; without it the call never
+        synchronises and lists beyond m_cap are truncated (counters[1] set)."""
+        if m_cap is None:
+            m_cap = self.m_cap_hint or max(4 * self.V * n, 1024)
+        while True:
+            b = self.alloc_bins(n, m_cap)
+            m = ctypes.c_uint64(0)
+            st = self.lib.gesr_bin(self.ctx, ctypes.byref(self._proj_c(proj)), self.cams_c, self.V, n,
+                                   ctypes.byref(self.st_c), ctypes.byref(self._bins_c(b)),
+                                   _lib.GESR_BIN_SYNC if sync else 0, ctypes.byref(m), _stream())
+            if st == _lib.GESR_ERR_CAPACITY and sync:
+                m_cap = int(m.value * 1.05) + 1024
+                continue
+            self._check(st, self.ctx)
+            if sync:
+                b["M"] = int(m.value)
+                self.m_cap_hint = max(self.m_cap_hint, int(m.value * 1.05) + 1024)
+            return b
+
+    def render_fwd(self, proj: dict, bins: dict, n: int, counts: bool = False) -> dict:
+        P = self.n_pixels
+        out = dict(image=self._empty(3 * P), final_T=self._empty(P), n_contrib=self._empty(P, torch.int32))
+        cnt = None
+        if counts:
+            out["n_listed"] = self._empty(P, torch.int32)
+            out["n_hit"] = self._empty(P, torch.int32)
+            cnt = _lib.FwdCounts(out["n_listed"].data_ptr(), out["n_hit"].data_ptr())
+        self._check(self.lib.gesr_render_fwd(self.ctx, ctypes.byref(self._proj_c(proj)),
+                                             ctypes.byref(self._bins_c(bins)), self.cams_c, self.V, n,
+                                             ctypes.byref(self.st_c), out["image"].data_ptr(),
+                                             out["final_T"].data_ptr(), out["n_contrib"].data_ptr(),
+                                             ctypes.byref(cnt) if cnt is not None else None, _stream()), self.ctx)
+        return out
+
+    def render_bwd(self, sp: Splats, proj: dict, bins: dict, final_T, n_contrib, dL_dimage,
+                   want_grad2d: bool = False) -> dict:
+        n = sp.n
+        g = dict(mean=torch.empty_like(sp.mean), scale=torch.empty_like(sp.scale), quat=torch.empty_like(sp.quat),
+                 opacity=torch.empty_like(sp.opacity), beta=torch.empty_like(sp.beta), sh=torch.empty_like(sp.sh))
+        gc = _lib.Grads(*(g[k].data_ptr() for k in ("mean", "scale", "quat", "opacity", "beta", "sh")))
+        partials = self._empty(bins["m_cap"] * _lib.PARTIAL_FLOATS)
+        grad2d = self._empty(self.V * n * _lib.PARTIAL_FLOATS) if want_grad2d else None
+        dL = dL_dimage.contiguous()
+        self._check(self.lib.gesr_render_bwd(self.ctx, ctypes.byref(sp.to_c()), ctypes.byref(self._proj_c(proj)),
+                                             ctypes.byref(self._bins_c(bins)), self.cams_c, self.V,
+                                             ctypes.byref(self.st_c), final_T.data_ptr(), n_contrib.data_ptr(),
+                                             dL.data_ptr(), partials.data_ptr(),
+                                             grad2d.data_ptr() if grad2d is not None else None,
+                                             ctypes.byref(gc), _stream()), self.ctx)
+        if grad2d is not None:
+            g["grad2d"] = grad2d
+        return g
+
+    def l1_grad(self, image, target, scale: float):
+        grad = torch.empty_like(image)
+        self._check(self.lib.gesr_l1_grad(self.ctx, image.data_ptr(), target.data_ptr(), image.numel(),
+                                          float(scale), grad.data_ptr(), _stream()), self.ctx)
+        return grad
+
+    def forward(self, sp: Splats, sync: bool = True, m_cap: Optional[int] = None, counts: bool = False):
+        proj = self.project(sp)
+        bins = self.bin(proj, sp.n, m_cap=m_cap, sync=sync)
+        out = self.render_fwd(proj, bins, sp.n, counts=counts)
+        out.update(proj=proj, bins=bins)
+        return out
+
+    def split_images(self, flat: torch.Tensor) -> List[torch.Tensor]:
+        out, off = [], 0
+        for w, h in self.views:
+            out.append(flat[off:off + 3 * w * h].view(3, h, w))
+            off += 3 * w * h
+        return out
+
+
+class GESRender(torch.autograd.Function):
+    """Differentiable GES rendering of all views of `rast` in one batch.
+
+    forward(rast, mean, scale, quat, opacity, beta, sh) -> flat image [3P].
+    Saves the projection, the bins, final_T and n_contrib; the backward
+    recomputes per-fragment state from them (no per-fragment storage)."""
+
+    @staticmethod
+    def forward(ctx, rast: Rasterizer, mean, scale, quat, opacity, beta, sh):
+        sp = Splats(mean.detach().contiguous(), scale.detach().contiguous(), quat.detach().contiguous(),
+                    opacity.detach().contiguous(), beta.detach().contiguous(), sh.detach().contiguous())
+        out = rast.forward(sp)
+        ctx.rast = rast
+        ctx.sp = sp
+        ctx.state = (out["proj"], out["bins"], out["final_T"], out["n_contrib"])
+        return out["image"]
+
+    @staticmethod
+    def backward(ctx, dL_dimage):
+        proj, bins, final_T, n_contrib = ctx.state
+        g = ctx.rast.render_bwd(ctx.sp, proj, bins, final_T, n_contrib, dL_dimage)
+        return None, g["mean"], g["scale"], g["quat"], g["opacity"], g["beta"], g["sh"]
+
+
+def render(rast: Rasterizer, mean, scale, quat, opacity, beta, sh) -> torch.Tensor:
+    return GESRender.apply(rast, mean, scale, quat, opacity, beta, sh)

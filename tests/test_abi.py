@@ -1,0 +1,157 @@
+"""C ABI contract checks that need no GPU: the library loads, exports every
+function declared in include/gesr.h, its struct layouts match the header
+(compiled independently with gcc), and invalid arguments are rejected on the
+host with GESR_ERR_INVALID / GESR_ERR_UNSUPPORTED before any device work."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2411_09156_amd import _lib
+from paper_2411_09156_amd.rasterizer import RasterSettings, cameras_to_c
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gesr.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return _lib.load()
+
+
+def test_exports_every_declared_function(lib):
+    text = open(HEADER).read()
+    declared = set(re.findall(r"\b(gesr_[a-z0-9_]+)\s*\(", text))
+    assert declared == set(_lib.EXPORTS)
+    nm = subprocess.run(["nm", "-D", "--defined-only", _lib.LIB_PATH], capture_output=True, text=True, check=True)
+    exported = set(re.findall(r"\b(gesr_[a-z0-9_]+)\b", nm.stdout))
+    assert declared <= exported, declared - exported
+
+
+def test_struct_layouts_match_header(tmp_path):
+    src = tmp_path / "sizes.c"
+    src.write_text("""
+#include <stdio.h>
+#include <stddef.h>
+#include "gesr.h"
+int main(void) {
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(gesr_camera), sizeof(gesr_settings), sizeof(gesr_splats),
+         sizeof(gesr_proj), sizeof(gesr_bins), sizeof(gesr_grads), sizeof(gesr_sizes), sizeof(gesr_fwd_counts));
+  printf("%zu %zu %zu\\n", offsetof(gesr_settings, bg), offsetof(gesr_bins, scratch_bytes),
+         offsetof(gesr_camera, campos));
+  return 0;
+}
+""")
+    exe = tmp_path / "sizes"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    sizes = [int(x) for x in out[0].split()]
+    offs = [int(x) for x in out[1].split()]
+    mine = [ctypes.sizeof(t) for t in (_lib.Camera, _lib.Settings, _lib.Splats, _lib.Proj, _lib.Bins, _lib.Grads,
+                                       _lib.Sizes, _lib.FwdCounts)]
+    assert sizes == mine
+    assert offs == [_lib.Settings.bg.offset, _lib.Bins.scratch_bytes.offset, _lib.Camera.campos.offset]
+
+
+def _ctx(lib):
+    ctx = ctypes.c_void_p()
+    assert lib.gesr_ctx_create(0, ctypes.byref(ctx)) == _lib.GESR_OK
+    return ctx
+
+
+class _Cam:
+    def __init__(self, w=64, h=48):
+        self.width, self.height, self.fx, self.fy, self.cx, self.cy = w, h, 50.0, 50.0, w / 2, h / 2
+        self.viewmat = [[1, 0, 0, 0], [0, 1, 0, 0], [0, 0, 1, 4]]
+        self.campos = [0, 0, -4]
+
+
+def test_defaults_match_binding(lib):
+    s = _lib.Settings()
+    lib.gesr_default_settings(ctypes.byref(s))
+    d = RasterSettings()
+    assert (s.sh_degree, s.tile_w, s.tile_h, s.batch, s.radix_bits) == (d.sh_degree, d.tile_w, d.tile_h, d.batch,
+                                                                         d.radix_bits)
+    for k in ("kappa", "rho", "alpha_min", "alpha_max", "t_min", "blur", "znear", "clip_fac"):
+        assert getattr(s, k) == pytest.approx(getattr(d, k), rel=1e-7)
+
+
+def test_query_sizes_host_only(lib):
+    ctx = _ctx(lib)
+    cams = cameras_to_c([_Cam(64, 48), _Cam(33, 17)])
+    st = RasterSettings().to_c()
+    out = _lib.Sizes()
+    assert lib.gesr_query_sizes(ctx, cams, 2, 100, ctypes.byref(st), 5000, ctypes.byref(out)) == _lib.GESR_OK
+    assert out.total_tiles == 4 * 3 + 3 * 2
+    assert out.total_pixels == 64 * 48 + 33 * 17
+    assert out.partial_bytes == 5000 * 10 * 4
+    assert out.bin_scratch_bytes > 0
+    lib.gesr_ctx_destroy(ctx)
+
+
+@pytest.mark.parametrize("field,value,status", [
+    ("sh_degree", 4, _lib.GESR_ERR_INVALID),
+    ("sh_degree", -1, _lib.GESR_ERR_INVALID),
+    ("kappa", 0.0, _lib.GESR_ERR_INVALID),
+    ("alpha_min", 0.995, _lib.GESR_ERR_INVALID),
+    ("t_min", 0.0, _lib.GESR_ERR_INVALID),
+    ("znear", -1.0, _lib.GESR_ERR_INVALID),
+    ("radix_bits", 9, _lib.GESR_ERR_INVALID),
+    ("tile_w", 24, _lib.GESR_ERR_UNSUPPORTED),
+])
+def test_invalid_settings_rejected(lib, field, value, status):
+    ctx = _ctx(lib)
+    cams = cameras_to_c([_Cam()])
+    st = RasterSettings().to_c()
+    setattr(st, field, value)
+    out = _lib.Sizes()
+    assert lib.gesr_query_sizes(ctx, cams, 1, 10, ctypes.byref(st), 100, ctypes.byref(out)) == status
+    assert len(lib.gesr_last_error(ctx)) > 0
+    lib.gesr_ctx_destroy(ctx)
+
+
+def test_invalid_views_and_sizes_rejected(lib):
+    ctx = _ctx(lib)
+    st = RasterSettings().to_c()
+    out = _lib.Sizes()
+    cams = cameras_to_c([_Cam()])
+    assert lib.gesr_query_sizes(ctx, cams, 0, 10, ctypes.byref(st), 100, ctypes.byref(out)) == _lib.GESR_ERR_INVALID
+    assert lib.gesr_query_sizes(ctx, cams, 1, -5, ctypes.byref(st), 100, ctypes.byref(out)) == _lib.GESR_ERR_INVALID
+    assert lib.gesr_query_sizes(ctx, cams, 1, 10, ctypes.byref(st), 0, ctypes.byref(out)) == _lib.GESR_ERR_INVALID
+    bad = cameras_to_c([_Cam(0, 10)])
+    assert lib.gesr_query_sizes(ctx, bad, 1, 10, ctypes.byref(st), 100, ctypes.byref(out)) == _lib.GESR_ERR_INVALID
+    many = cameras_to_c([_Cam()] * (_lib.MAX_VIEWS + 1))
+    assert lib.gesr_query_sizes(ctx, many, _lib.MAX_VIEWS + 1, 10, ctypes.byref(st), 100,
+                                ctypes.byref(out)) == _lib.GESR_ERR_INVALID
+    lib.gesr_ctx_destroy(ctx)
+
+
+def test_null_and_misaligned_pointers_rejected_before_launch(lib):
+    ctx = _ctx(lib)
+    st = RasterSettings().to_c()
+    cams = cameras_to_c([_Cam()])
+    sp = _lib.Splats(10, 0, 0, 0, 0, 0, 0)
+    proj = _lib.Proj(0, 0, 0, 0)
+    assert lib.gesr_project(ctx, ctypes.byref(sp), cams, 1, ctypes.byref(st), ctypes.byref(proj),
+                            None) == _lib.GESR_ERR_INVALID
+    assert "NULL" in lib.gesr_last_error(ctx).decode()
+    sp = _lib.Splats(10, 16, 32, 48, 64, 80, 8)  # sh misaligned
+    assert lib.gesr_project(ctx, ctypes.byref(sp), cams, 1, ctypes.byref(st), ctypes.byref(proj),
+                            None) == _lib.GESR_ERR_INVALID
+    assert "aligned" in lib.gesr_last_error(ctx).decode()
+    # NULL context
+    assert lib.gesr_project(None, ctypes.byref(sp), cams, 1, ctypes.byref(st), ctypes.byref(proj),
+                            None) == _lib.GESR_ERR_INVALID
+    bins = _lib.Bins()
+    bins.m_cap = 0
+    proj = _lib.Proj(16, 16, 16, 16)
+    assert lib.gesr_bin(ctx, ctypes.byref(proj), cams, 1, 10, ctypes.byref(st), ctypes.byref(bins), 0, None,
+                        None) == _lib.GESR_ERR_INVALID
+    lib.gesr_ctx_destroy(ctx)
+
+
+def test_status_strings(lib):
+    for s in range(5):
+        assert len(lib.gesr_status_string(s)) > 0

@@ -1,0 +1,204 @@
+"""GPU parity of every hot-path stage against the FP64 oracle.
+
+Stage tests feed the oracle the GPU's own inputs for that stage (so a
+disagreement is the stage's own), then an end-to-end test compares the whole
+GPU pipeline with the oracle run from the splat parameters.
+
+Bars (derived in the design notes):
+  * binning: bit-exact keys, values, ranges, instance count and instance bases;
+  * images / final_T: max error <= 1e-4 * max(max|C|, 1) on pixels that are not
+    ambiguous (a fragment within 1e-5 of alpha_min / alpha_max / t_min, or a
+    tile list that differs), and relative L2 <= 1e-4 over all pixels;
+    n_contrib and the fragment counts exact on non-ambiguous pixels;
+  * gradients: per tensor, inf-norm and 2-norm of the error <= 1e-3 of the
+    reference's norms, with identical upstream dL/dimage on both sides.
+"""
+import functools
+
+import numpy as np
+import pytest
+
+import gesr_inputs as gi
+import oracle
+from tests.gpu_util import (ambiguous_from_lists, conic_grads_to_factor, factor_grads_to_conic, image_errors, log,
+                            norm_errors, oracle_rec, run_gpu, tile_lists)
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(name):
+    """(scene, oracle settings) of a named parity case."""
+    if name == "tiny-d1":
+        return gi.tiny_scene(0, n=12, deg=1), oracle.Settings(sh_degree=1)
+    if name == "tiny-d3-2v-bg":
+        return gi.tiny_scene(2, n=30, deg=3, n_views=2), oracle.Settings(sh_degree=3, bg=(0.2, 0.5, 0.1))
+    if name == "tiny-kappa1":
+        return gi.tiny_scene(3, n=20, deg=2, beta=(0.7, 4.5)), oracle.Settings(sh_degree=2, kappa=1.0)
+    if name == "plain-2k":
+        return gi.make_workload(1), oracle.Settings()
+    if name == "plain-2k-t8":
+        return gi.make_workload(1), oracle.Settings(tile_w=8, tile_h=8)
+    if name == "plain-2k-t32x16":
+        return gi.make_workload(1), oracle.Settings(tile_w=32, tile_h=16)
+    if name == "plain-2k-t32":
+        return gi.make_workload(1), oracle.Settings(tile_w=32, tile_h=32)
+    if name == "spheres-100k":
+        return gi.make_workload(2), oracle.Settings(sh_degree=3)
+    if name == "drt-50k-8v":
+        return gi.make_workload(3, n_override=50_000), oracle.Settings()
+    if name == "surfels-40k-2v":
+        return gi.make_workload(4, n_override=40_000, views_override=2), oracle.Settings(sh_degree=3)
+    if name == "blobs-100k-2v":
+        return gi.make_workload(5, n_override=100_000, views_override=2), oracle.Settings(sh_degree=3)
+    raise KeyError(name)
+
+
+CASES = ["tiny-d1", "tiny-d3-2v-bg", "tiny-kappa1", "plain-2k", "plain-2k-t8", "plain-2k-t32x16", "plain-2k-t32",
+         "spheres-100k", "drt-50k-8v", "surfels-40k-2v", "blobs-100k-2v"]
+
+
+@functools.lru_cache(maxsize=2)
+def _run(name):
+    scene, st = _case(name)
+    dL = oracle.flat_images(gi.upstream_grads(scene, 7))
+    log(f"[gpu] case {name}: n={scene.n} views={scene.n_views} px={scene.n_pixels}")
+    g = run_gpu(scene, st, dL=dL)
+    log(f"[gpu] case {name}: done, M={g['M']}")
+    return scene, st, dL, g
+
+
+@functools.lru_cache(maxsize=2)
+def _oracle_same_inputs(name):
+    scene, st, dL, g = _run(name)
+    rec = oracle_rec(g["rec"])
+    fwd = oracle.render_fwd(scene.n, scene.cameras, rec, g["val_sorted"], g["ranges"], st)
+    g2 = oracle.render_bwd(scene.n, scene.cameras, rec, g["val_sorted"], g["ranges"], dL, st)
+    return rec, fwd, g2
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_project(name):
+    scene, st, dL, g = _run(name)
+    pr = oracle.project(scene, st)
+    keep_g = g["tiles_touched"] > 0
+    keep_o = pr["tiles_touched"] > 0
+    both = keep_g & keep_o
+    VN = len(keep_g)
+    assert (keep_g != keep_o).sum() <= max(2, VN // 10000), (keep_g != keep_o).sum()
+    r, o = g["rec"][both].astype(np.float64), pr["rec"][both]
+    cams = scene.cameras
+    cx = np.concatenate([np.full(scene.n, c.cx) for c in cams])[both]
+    cy = np.concatenate([np.full(scene.n, c.cy) for c in cams])[both]
+    np.testing.assert_array_less(np.abs(r[:, 0] - o[:, 0]), 1e-6 * (np.abs(o[:, 0] - cx) + np.abs(o[:, 0])) + 1e-5)
+    np.testing.assert_array_less(np.abs(r[:, 1] - o[:, 1]), 1e-6 * (np.abs(o[:, 1] - cy) + np.abs(o[:, 1])) + 1e-5)
+    A, B, C = r[:, 2] ** 2, r[:, 2] * r[:, 3], r[:, 3] ** 2 + r[:, 4] ** 2
+    np.testing.assert_array_less(np.abs(A - o[:, 2]), 2e-5 * o[:, 2] + 1e-30)
+    np.testing.assert_array_less(np.abs(C - o[:, 4]), 2e-5 * o[:, 4] + 1e-30)
+    np.testing.assert_array_less(np.abs(B - o[:, 3]), 2e-5 * np.sqrt(o[:, 2] * o[:, 4]) + 1e-30)
+    np.testing.assert_array_equal(r[:, 5], o[:, 5])
+    np.testing.assert_array_equal(r[:, 6], o[:, 6])
+    np.testing.assert_array_less(np.abs(r[:, 7] - o[:, 7]), 1e-5 * o[:, 7] + 1e-30)
+    np.testing.assert_array_less(np.abs(r[:, 8:11] - o[:, 8:11]), 1e-5)
+    # depth key: float32 rounding of the exact depth (near-ties may differ by one ulp)
+    dk_o = pr["zbits"][both].astype(np.int64)
+    dk_g = g["depth_key"][both].astype(np.int64)
+    assert np.abs(dk_g - dk_o).max() <= 1
+    assert (dk_g != dk_o).sum() <= max(1, both.sum() // 100000)
+    # tile rectangles agree away from pixel-boundary ties of the FP64 edges
+    diff = (g["tile_rect"][both] != pr["tile_rect"][both]).any(1)
+    e = pr["edges"][both]
+    near = (np.abs(e - np.round(e)) < 1e-3).any(1)
+    assert (diff & ~near).sum() == 0
+    log(f"[gpu] {name}: project ok; culls differ {int((keep_g != keep_o).sum())}, rects in guard band "
+        f"{int(diff.sum())}, depth ulps {int((dk_g != dk_o).sum())}")
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_bin_bit_exact(name):
+    """Oracle binning of the GPU's own per-splat results (rect, depth key) equals
+    the GPU's sorted instance list, ranges, count and instance bases exactly."""
+    scene, st, dL, g = _run(name)
+    keys, vals, ranges = oracle.bin_instances(scene.n, scene.cameras, g["tile_rect"], g["tiles_touched"],
+                                              g["depth_key"], st)
+    assert g["overflow"] == 0
+    assert g["M"] == len(vals)
+    np.testing.assert_array_equal(g["val_sorted"], vals)
+    np.testing.assert_array_equal(g["tile_sorted"].astype(np.uint64), keys >> np.uint64(32))
+    np.testing.assert_array_equal(g["depth_key"][g["val_sorted"]].astype(np.uint64), keys & np.uint64(0xFFFFFFFF))
+    np.testing.assert_array_equal(g["ranges"], ranges)
+    # worklist: every tile once, by decreasing list length, ties by tile id
+    lens = ranges[:, 1].astype(np.int64) - ranges[:, 0]
+    expect = np.lexsort((np.arange(len(lens)), -np.minimum(lens, 0xFFFF)))
+    np.testing.assert_array_equal(g["worklist"], expect)
+    # instance bases: exclusive scan of tiles_touched in stable depth order
+    order = np.argsort(g["depth_key"], kind="stable")
+    base = np.zeros_like(order)
+    base[order] = np.concatenate([[0], np.cumsum(g["tiles_touched"][order].astype(np.int64))[:-1]])
+    np.testing.assert_array_equal(g["inst_base"], base)
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_render_fwd_same_inputs(name):
+    scene, st, dL, g = _run(name)
+    rec, fwd, _ = _oracle_same_inputs(name)
+    amb = fwd["ambig"] > 0
+    errs = image_errors(g["image"], fwd["image"], amb, scene.cameras)
+    for bad, mx, bound, l2 in errs:
+        assert bad == 0 and l2 <= 1e-4, errs
+    ok = ~amb
+    assert np.abs(g["final_T"][ok] - fwd["final_T"][ok]).max() <= 1e-4
+    np.testing.assert_array_equal(g["n_contrib"][ok], fwd["n_contrib"][ok])
+    np.testing.assert_array_equal(g["n_listed"][ok], fwd["n_listed"][ok])
+    np.testing.assert_array_equal(g["n_hit"][ok], fwd["n_hit"][ok])
+    log(f"[gpu] {name}: fwd ok; ambiguous px {int(amb.sum())}/{amb.size}; max err "
+        f"{max(e[1] for e in errs):.2e}; listed/px {fwd['n_listed'].mean():.1f} hit/px {fwd['n_hit'].mean():.1f}")
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_render_bwd_same_inputs(name):
+    """Screen-space gradients per (view, splat) after the tile partials and the
+    segmented sum, against the oracle's explicit-list adjoint."""
+    scene, st, dL, g = _run(name)
+    rec, fwd, g2 = _oracle_same_inputs(name)
+    ref = conic_grads_to_factor(g2, g["rec"])
+    labels = ["du", "dv", "dL00", "dL10", "dL11", "dop", "dbeta", "dr", "dg", "db"]
+    res = {}
+    for k, lab in enumerate(labels):
+        einf, e2 = norm_errors(g["grad2d"][:, k], ref[:, k])
+        res[lab] = (einf, e2)
+        assert einf <= 1e-3 and e2 <= 1e-3, (lab, einf, e2)
+    log(f"[gpu] {name}: bwd ok; worst {max(max(v) for v in res.values()):.2e}")
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_project_bwd_same_inputs(name):
+    """Projection adjoint fed the GPU's own screen-space gradients: the oracle's
+    dual-number Jacobian gives the reference parameter gradients."""
+    scene, st, dL, g = _run(name)
+    g2 = factor_grads_to_conic(g["grad2d"], g["rec"])
+    ref = oracle.project_bwd(scene, g2, st)
+    for k in ("means", "scales", "quats", "opacities", "betas", "sh"):
+        einf, e2 = norm_errors(g["g_" + k], ref[k])
+        assert einf <= 1e-3 and e2 <= 1e-3, (k, einf, e2)
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_end_to_end(name):
+    """Whole GPU pipeline vs the oracle run from the splat parameters."""
+    scene, st, dL, g = _run(name)
+    fo = oracle.forward(scene, st)
+    amb = (fo["ambig"] > 0) | ambiguous_from_lists(scene.cameras, st, tile_lists(g["val_sorted"], g["ranges"]),
+                                                   tile_lists(fo["vals"], fo["ranges"]))
+    errs = image_errors(g["image"], fo["image"], amb, scene.cameras)
+    for bad, mx, bound, l2 in errs:
+        assert bad == 0 and l2 <= 1e-4, errs
+    ok = ~amb
+    assert np.abs(g["final_T"][ok] - fo["final_T"][ok]).max() <= 1e-4
+    go = oracle.backward(scene, st, fo, dL)
+    worst = 0.0
+    for k in ("means", "scales", "quats", "opacities", "betas", "sh"):
+        einf, e2 = norm_errors(g["g_" + k], go[k])
+        worst = max(worst, einf, e2)
+        assert einf <= 1e-3 and e2 <= 1e-3, (k, einf, e2)
+    log(f"[gpu] {name}: end-to-end ok; ambiguous px {int(amb.sum())}; image max err "
+        f"{max(e[1] for e in errs):.2e}; grad worst {worst:.2e}")
