@@ -1,0 +1,293 @@
+#!/usr/bin/env python3
+"""Benchmark: batched forward + backward GES rendering on one MI355X.
+
+One step = the whole hot path over every view of the workload: projection,
+tile binning (radix sort), forward compositing, the L1 loss gradient, the
+per-tile render adjoint and the projection adjoint, all in the HIP library,
+captured once in a HIP graph and replayed.  The default workload is the
+dynamic-resolution batch: 500,000 splats, 8 ring views at 1/8 .. 1 of
+1600x1064 (6,304,200 pixels).
+
+Printed: one JSON line with Mpix/s (pixels of all views per second of
+fwd+bwd), the per-view comparison, per-stage times from HIP events on the
+launch stream, the roofline of the dominant kernel and the FP64 oracle timed
+on the host cores over a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "fwd+bwd render Mpix/s, batched vs per-view, at ≤1e-4 rel err vs FP64 oracle"
+WORKLOADS = {"plain": 1, "spheres": 2, "drt": 3, "surfels": 4, "blobs": 5}
+
+# MI355X: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz = 39.3e12 non-packed FP32 VALU
+# lane-slots per second (a transcendental occupies 4 slots); HBM3E 8 TB/s.
+VALU_SLOTS_PER_S = 256 * 64 * 2.4e9
+HBM_BYTES_PER_S = 8.0e12
+
+# Algorithmic VALU slots per fragment (see the design notes for the count):
+#   forward : 8 per listed fragment, +24 per hit (3 transcendentals)
+#   backward: 9 per listed fragment, +73 per hit (5 transcendentals, 10 sums)
+FWD_LISTED, FWD_HIT = 8, 24
+BWD_LISTED, BWD_HIT = 9, 73
+
+
+def parse_args():
+    p = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=20)
+    p.add_argument("--warmup", type=int, default=5)
+    p.add_argument("--workload", default="drt", choices=sorted(WORKLOADS))
+    p.add_argument("--tile", default="16x16")
+    p.add_argument("--batch", type=int, default=0)
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-per-view", action="store_true")
+    p.add_argument("--no-graph", action="store_true")
+    p.add_argument("--cpu-sample-views", default="0,1,2")
+    return p.parse_args()
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def main():
+    args = parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU design "
+              "(views sharded across GPUs, one gradient all-reduce) is described in DESIGN.md but not built.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import gesr_inputs as gi
+    from paper_2411_09156_amd import Rasterizer, RasterSettings, Splats
+
+    torch.cuda.init()
+    k = WORKLOADS[args.workload]
+    tw, th = (int(x) for x in args.tile.split("x"))
+    log(f"[bench] building workload {args.workload}")
+    scene = gi.make_workload(k)
+    N, V, P = scene.n, scene.n_views, scene.n_pixels
+    rs = RasterSettings(sh_degree=scene.sh_degree, tile_w=tw, tile_h=th, batch=args.batch)
+    sp = Splats.from_aos(scene.means, scene.scales, scene.quats, scene.opacities, scene.betas, scene.sh)
+    target = torch.as_tensor(np.concatenate([t.reshape(-1) for t in gi.target_images(scene, k)]), device="cuda")
+
+    def make_step(rast, sp, target, m_cap, events=None):
+        n = sp.n
+        scale = 1.0 / float(target.numel())
+
+        def rec(i):
+            if events is not None:
+                events[i].record()
+
+        def step():
+            rec(0)
+            proj = rast.project(sp)
+            rec(1)
+            bins = rast.bin(proj, n, m_cap=m_cap, sync=False)
+            rec(2)
+            f = rast.render_fwd(proj, bins, n)
+            rec(3)
+            dL = rast.l1_grad(f["image"], target, scale)
+            rec(4)
+            partials = rast.render_bwd_tiles(proj, bins, n, f["final_T"], f["n_contrib"], dL)
+            rec(5)
+            g = rast.project_bwd(sp, proj, bins, partials)
+            rec(6)
+            return f, g, bins
+        return step
+
+    # ------------------------------------------------------------ sizing
+    rast = Rasterizer(scene.cameras, rs)
+    log("[bench] sizing run (eager, synchronous count)")
+    first = rast.forward(sp, sync=True, counts=True)
+    M = int(first["bins"]["M"])
+    m_cap = M
+    n_listed = int(first["n_listed"].to(torch.int64).sum().item())
+    n_hit = int(first["n_hit"].to(torch.int64).sum().item())
+    del first
+    torch.cuda.synchronize()
+    log(f"[bench] M={M} instances, listed={n_listed}, hit={n_hit}")
+
+    # ---------------------------------------------------- batched, graph
+    step = make_step(rast, sp, target, m_cap)
+    for _ in range(max(args.warmup, 1)):
+        step()
+    torch.cuda.synchronize()
+    if not args.no_graph:
+        graph = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            step()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(graph):
+            res = step()
+        run = graph.replay
+    else:
+        res = None
+        run = step
+    for _ in range(args.warmup):
+        run()
+    torch.cuda.synchronize()
+    log(f"[bench] timing {args.steps} batched steps")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(args.steps):
+        run()
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1) / args.steps
+    if res is not None:
+        cnt = res[2]["counters"].cpu().numpy().view(np.uint32)
+        assert cnt[1] == 0, "instance capacity overflowed inside the graph"
+    value = P / (ms * 1e-3) / 1e6
+
+    # ------------------------------------- per-stage times (eager, events)
+    names = ["project", "bin", "render_fwd", "l1_grad", "render_bwd_tiles", "project_bwd"]
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(7)]
+    tstep = make_step(rast, sp, target, m_cap, evs)
+    tstep()
+    torch.cuda.synchronize()
+    acc = np.zeros(6)
+    for _ in range(args.steps):
+        tstep()
+        torch.cuda.synchronize()
+        acc += [evs[i].elapsed_time(evs[i + 1]) for i in range(6)]
+    stage_ms = dict(zip(names, (acc / args.steps).round(4).tolist()))
+    eager_ms = float(acc.sum() / args.steps)
+
+    # -------------------------------------------------- per-view baseline
+    per_view = None
+    if not args.no_per_view:
+        log("[bench] per-view pipelines")
+        rasts, steps = [], []
+        off = 0
+        for v, cam in enumerate(scene.cameras):
+            r = Rasterizer([cam], rs)
+            npx = 3 * cam.width * cam.height
+            tv = target[off:off + npx]
+            off += npx
+            fv = r.forward(sp, sync=True)
+            mv = int(fv["bins"]["M"])
+            del fv
+            rasts.append(r)
+            steps.append(make_step(r, sp, tv, mv))
+
+        def per_view_step():
+            total = None
+            for s in steps:
+                f, g, _ = s()
+                if total is None:
+                    total = {k2: v2.clone() for k2, v2 in g.items()}
+                else:
+                    for k2 in total:
+                        total[k2].add_(g[k2])
+            return total
+        for _ in range(args.warmup):
+            per_view_step()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(args.steps):
+            per_view_step()
+        e1.record()
+        torch.cuda.synchronize()
+        pv_ms = e0.elapsed_time(e1) / args.steps
+        pv_graph_ms = None
+        if not args.no_graph:
+            g2 = torch.cuda.CUDAGraph()
+            side = torch.cuda.Stream()
+            side.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(side):
+                per_view_step()
+            torch.cuda.current_stream().wait_stream(side)
+            torch.cuda.synchronize()
+            with torch.cuda.graph(g2):
+                per_view_step()
+            for _ in range(args.warmup):
+                g2.replay()
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(args.steps):
+                g2.replay()
+            e1.record()
+            torch.cuda.synchronize()
+            pv_graph_ms = e0.elapsed_time(e1) / args.steps
+        per_view = {"eager_ms_per_step": round(pv_ms, 4), "eager_mpix_s": round(P / (pv_ms * 1e-3) / 1e6, 2),
+                    "graph_ms_per_step": None if pv_graph_ms is None else round(pv_graph_ms, 4),
+                    "graph_mpix_s": None if pv_graph_ms is None else round(P / (pv_graph_ms * 1e-3) / 1e6, 2),
+                    "batched_speedup_vs_eager": round(pv_ms / ms, 3),
+                    "batched_speedup_vs_graph": None if pv_graph_ms is None else round(pv_graph_ms / ms, 3)}
+
+    # ------------------------------------------------------------ roofline
+    fwd_slots = FWD_LISTED * n_listed + FWD_HIT * n_hit
+    bwd_slots = BWD_LISTED * n_listed + BWD_HIT * n_hit
+    kern = {"render_fwd": fwd_slots, "render_bwd_tiles": bwd_slots}
+    dom = max(kern, key=lambda kk: stage_ms[kk])
+    achieved = kern[dom] / (stage_ms[dom] * 1e-3) / 1e12
+    peak = VALU_SLOTS_PER_S / 1e12
+    roofline = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3), "peak": round(peak, 3),
+                "unit": "Tslot/s", "frac": round(achieved / peak, 4), "traffic": None,
+                "algorithmic_slots_per_launch": int(kern[dom])}
+
+    # ------------------------------------------------------- CPU baseline
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(scene, k, [int(x) for x in args.cpu_sample_views.split(",")], rs)
+
+    out = {
+        "metric": METRIC, "value": round(value, 2), "unit": "Mpix/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": scene.name, "splats": N, "views": V, "pixels": P,
+                   "resolutions": [f"{c.width}x{c.height}" for c in scene.cameras], "sh_degree": scene.sh_degree,
+                   "tile": args.tile, "graph": not args.no_graph, "instances": M},
+        "fragments": {"listed": n_listed, "hit": n_hit,
+                      "listed_per_s": round(n_listed / (ms * 1e-3), 1), "hit_per_s": round(n_hit / (ms * 1e-3), 1)},
+        "stages_ms": stage_ms, "eager_ms_per_step": round(eager_ms, 4), "per_view": per_view,
+        "roofline": roofline, "cpu_baseline": cpu, "wall_s_timed": round(wall, 3),
+    }
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(scene, k, views, rs):
+    """The FP64 oracle (as it stands) on the same workload restricted to a
+    subset of its views: project, bin, render, L1 gradient, backward."""
+    import copy
+
+    import numpy as np
+
+    import gesr_inputs as gi
+    import oracle
+    sub = copy.copy(scene)
+    sub.cameras = [scene.cameras[v] for v in views]
+    st = oracle.Settings(sh_degree=scene.sh_degree, tile_w=rs.tile_w, tile_h=rs.tile_h)
+    targets = gi.target_images(scene, k)
+    tgt = oracle.flat_images([targets[v] for v in views])
+    log(f"[bench] cpu baseline: oracle on views {views} ({sub.n_pixels} px) with {oracle.num_threads()} threads")
+    t0 = time.perf_counter()
+    fo = oracle.forward(sub, st)
+    dL = np.sign(fo["image"] - tgt) / tgt.size
+    oracle.backward(sub, st, fo, dL)
+    dt = time.perf_counter() - t0
+    return {"value": round(sub.n_pixels / dt / 1e6, 4), "unit": "Mpix/s", "cores": oracle.num_threads(),
+            "kind": "oracle", "seconds": round(dt, 2),
+            "sample": f"views {views} of the workload ({sub.n_pixels} px, all {scene.n} splats), FP64 fwd+bwd"}
+
+
+if __name__ == "__main__":
+    main()

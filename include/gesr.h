@@ -223,6 +223,22 @@ gesr_status gesr_render_bwd(gesr_ctx* ctx, const gesr_splats* splats, const gesr
                             const uint32_t* n_contrib, const float* dL_dimage, float* partials, float* grad2d,
                             const gesr_grads* out, void* stream);
 
+/* The two halves of gesr_render_bwd, for callers that schedule or time them
+ * separately.  gesr_render_bwd_tiles: the per-tile render adjoint, writing one
+ * gradient partial (10 floats, grad2d order) per instance into `partials`
+ * (DEVICE, gesr_sizes.partial_bytes; every instance slot below min(M, m_cap)
+ * is written).  gesr_project_bwd: the fixed-order per-(view, splat) sum of
+ * those partials, then the projection adjoint (Eq. 4, 6-7 and the EWA
+ * passage of Sec. 3.2) summed over views in ascending order.  Arguments as in
+ * gesr_render_bwd; n = splats->n. */
+gesr_status gesr_render_bwd_tiles(gesr_ctx* ctx, const gesr_proj* proj, const gesr_bins* bins,
+                                  const gesr_camera* cams, int V, int n, const gesr_settings* st,
+                                  const float* final_T, const uint32_t* n_contrib, const float* dL_dimage,
+                                  float* partials, void* stream);
+gesr_status gesr_project_bwd(gesr_ctx* ctx, const gesr_splats* splats, const gesr_proj* proj, const gesr_bins* bins,
+                             const gesr_camera* cams, int V, const gesr_settings* st, const float* partials,
+                             float* grad2d, const gesr_grads* out, void* stream);
+
 /* L1 photometric term of Eq. 8 (the (1 - lambda) L1 part):
  * grad[i] = scale * sign(image[i] - target[i]) (sign(0) = 0), DEVICE, count
  * elements. */

@@ -70,12 +70,19 @@ class Settings:
     tile_w: int = 16
     tile_h: int = 16
     sh_degree: int = 0
+    # Ambiguity model (pixels whose decisions may legitimately differ in a
+    # float32 implementation): relative alpha error of the evaluation itself,
+    # absolute error of the projected centre (px) and relative conic error.
+    ambig_tol: float = 1e-5
+    ambig_pos: float = 0.0
+    ambig_conic: float = 0.0
 
     def array(self) -> np.ndarray:
         f = lambda x: float(np.float32(x))  # noqa: E731
         return np.array([f(self.kappa), f(self.rho), f(self.alpha_min), f(self.alpha_max), f(self.t_min),
                          f(self.blur), f(self.znear), f(self.clip_fac), f(self.bg[0]), f(self.bg[1]),
-                         f(self.bg[2]), self.tile_w, self.tile_h, self.sh_degree, 0, 0], dtype=np.float64)
+                         f(self.bg[2]), self.tile_w, self.tile_h, self.sh_degree, self.ambig_tol, self.ambig_pos,
+                         self.ambig_conic, 0], dtype=np.float64)
 
 
 def views_array(cameras) -> np.ndarray:

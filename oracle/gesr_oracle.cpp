@@ -42,6 +42,12 @@ struct Settings {
     double kappa, rho, alpha_min, alpha_max, t_min, blur, znear, clip_fac;
     double bg[3];
     int tile_w, tile_h, sh_degree;
+    // Ambiguity model: a decision is flagged when the threshold lies within the
+    // first-order error band of a float32 implementation:
+    //   ambig        relative error of the alpha evaluation itself
+    //   ambig_pos    absolute error (pixels) of the projected centre
+    //   ambig_conic  relative error of the projected conic
+    double ambig, ambig_pos, ambig_conic;
 };
 
 Settings read_settings(const double* s) {
@@ -50,6 +56,9 @@ Settings read_settings(const double* s) {
     o.blur = s[5]; o.znear = s[6]; o.clip_fac = s[7];
     o.bg[0] = s[8]; o.bg[1] = s[9]; o.bg[2] = s[10];
     o.tile_w = (int)s[11]; o.tile_h = (int)s[12]; o.sh_degree = (int)s[13];
+    o.ambig = s[14] > 0.0 ? s[14] : 1e-5;
+    o.ambig_pos = s[15];
+    o.ambig_conic = s[16];
     return o;
 }
 
@@ -330,13 +339,25 @@ inline Frag eval_frag(const Rec& s, double px, double py, const Settings& st) {
 
 inline bool near_rel(double a, double b, double tol) { return std::fabs(a - b) <= tol * std::fabs(b); }
 
-// Ambiguity flags: a fragment whose decision could flip under FP32 rounding.
-constexpr double AMBIG = 1e-5;
-inline uint8_t frag_ambiguity(const Frag& f, double Tnext, const Settings& st) {
+// Error band of ln(alpha) for a fragment: ln(alpha) moves by
+// kappa (beta/2) P (dq/q), with dq/q <= 2 |du|/|d| + conic error.
+inline double frag_band(const Frag& f, const Rec& s, const Settings& st) {
+    double d = std::sqrt(f.dx * f.dx + f.dy * f.dy);
+    double sens = st.kappa * 0.5 * s.beta * f.P;
+    return st.ambig + sens * (2.0 * st.ambig_pos / std::max(d, 0.25) + st.ambig_conic);
+}
+
+// Ambiguity flags: bit0 alpha ~ alpha_min, bit1 oG ~ alpha_max, bit2 T' ~ t_min.
+// `band` bounds |d ln alpha| of the fragment and `tband` bounds |d ln T| of the
+// transmittance accumulated over the fragments composited so far; a decision is
+// flagged when its threshold lies within that band in log space.
+inline bool near_log(double a, double b, double band) { return a > 0.0 && std::fabs(std::log(a / b)) <= band; }
+
+inline uint8_t frag_ambiguity(const Frag& f, double Tnext, double band, double tband, const Settings& st) {
     uint8_t a = 0;
-    if (near_rel(f.oG, st.alpha_min, AMBIG)) a |= 1;
-    if (near_rel(f.oG, st.alpha_max, AMBIG)) a |= 2;
-    if (near_rel(Tnext, st.t_min, AMBIG)) a |= 4;
+    if (near_log(f.oG, st.alpha_min, band)) a |= 1;
+    if (near_log(f.oG, st.alpha_max, band)) a |= 2;
+    if (near_log(Tnext, st.t_min, tband)) a |= 4;
     return a;
 }
 
@@ -359,13 +380,16 @@ PixelOut composite_pixel(long count, ListFn idx_at, const double* rec, double px
                          std::vector<Hit>* hits, const long* rows = nullptr) {
     PixelOut o{{0, 0, 0}, 1.0, 0, 0, 0, 0};
     double T = 1.0;
+    double tband = st.ambig;  // relative error band of T
     for (long k = 0; k < count; ++k) {
         long idx = idx_at(k);
         Rec s = load_rec(rec, idx);
         Frag f = eval_frag(s, px, py, st);
         o.n_listed++;
         double Tn = T * (1.0 - f.alpha);
-        o.ambig |= frag_ambiguity(f, Tn, st);
+        double band = frag_band(f, s, st);
+        double tnext_band = tband + band * f.alpha / std::max(1.0 - f.alpha, 1e-12);
+        o.ambig |= frag_ambiguity(f, Tn, band, tnext_band, st);
         if (f.alpha < st.alpha_min) continue;
         o.n_hit++;
         if (Tn < st.t_min) break;
@@ -374,6 +398,7 @@ PixelOut composite_pixel(long count, ListFn idx_at, const double* rec, double px
         o.C[2] += s.b * f.alpha * T;
         if (hits) hits->push_back(Hit{idx, rows ? rows[k] : idx, f.alpha, T, f});
         T = Tn;
+        tband = tnext_band;
         o.n_contrib = (uint32_t)(k + 1);
     }
     for (int c = 0; c < 3; ++c) o.C[c] += T * st.bg[c];
@@ -450,7 +475,7 @@ void orc_set_num_threads(int n) {
 // Projection of N splats into V views (FP64).
 //   views: V x 24 doubles: W, H, fx, fy, cx, cy, R[9] row-major, t[3], campos[3], pad
 //   settings: kappa, rho, alpha_min, alpha_max, t_min, blur, znear, clip_fac, bg[3],
-//             tile_w, tile_h, sh_degree
+//             tile_w, tile_h, sh_degree, ambig (0 = 1e-5), ambig_pos, ambig_conic
 // Outputs are [V][N]-indexed (view-major):
 //   rec[11]: u, v, A, B, C, opacity, beta, qmax, r, g, b;  depth; z32 = RN_fp32(depth);
 //   sigma2d[3] = (a, b, c) of Sigma'; edges[4] = u-rx-1/2, u+rx-1/2, v-ry-1/2, v+ry-1/2;

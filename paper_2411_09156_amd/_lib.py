@@ -23,7 +23,8 @@ PARTIAL_FLOATS = 10
 
 EXPORTS = (
     "gesr_ctx_create", "gesr_ctx_destroy", "gesr_last_error", "gesr_status_string", "gesr_default_settings",
-    "gesr_query_sizes", "gesr_project", "gesr_bin", "gesr_render_fwd", "gesr_render_bwd", "gesr_l1_grad",
+    "gesr_query_sizes", "gesr_project", "gesr_bin", "gesr_render_fwd", "gesr_render_bwd", "gesr_render_bwd_tiles",
+    "gesr_project_bwd", "gesr_l1_grad",
 )
 
 c_float_p = ctypes.POINTER(ctypes.c_float)
@@ -115,6 +116,12 @@ def load():
     lib.gesr_render_bwd.argtypes = [vp, P(Splats), P(Proj), P(Bins), P(Camera), ctypes.c_int, P(Settings),
                                     vp, vp, vp, vp, vp, P(Grads), vp]
     lib.gesr_render_bwd.restype = st
+    lib.gesr_render_bwd_tiles.argtypes = [vp, P(Proj), P(Bins), P(Camera), ctypes.c_int, ctypes.c_int, P(Settings),
+                                          vp, vp, vp, vp, vp]
+    lib.gesr_render_bwd_tiles.restype = st
+    lib.gesr_project_bwd.argtypes = [vp, P(Splats), P(Proj), P(Bins), P(Camera), ctypes.c_int, P(Settings), vp, vp,
+                                     P(Grads), vp]
+    lib.gesr_project_bwd.restype = st
     lib.gesr_l1_grad.argtypes = [vp, vp, vp, ctypes.c_uint64, ctypes.c_float, vp, vp]
     lib.gesr_l1_grad.restype = st
     _lib = lib

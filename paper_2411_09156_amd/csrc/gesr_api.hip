@@ -446,32 +446,22 @@ gesr_status gesr_render_fwd(gesr_ctx* ctx, const gesr_proj* proj, const gesr_bin
     return GESR_OK;
 }
 
-gesr_status gesr_render_bwd(gesr_ctx* ctx, const gesr_splats* splats, const gesr_proj* proj, const gesr_bins* bins,
-                            const gesr_camera* cams, int V, const gesr_settings* st, const float* final_T,
-                            const uint32_t* n_contrib, const float* dL_dimage, float* partials, float* grad2d,
-                            const gesr_grads* out, void* stream) {
+gesr_status gesr_render_bwd_tiles(gesr_ctx* ctx, const gesr_proj* proj, const gesr_bins* bins,
+                                  const gesr_camera* cams, int V, int n, const gesr_settings* st,
+                                  const float* final_T, const uint32_t* n_contrib, const float* dL_dimage,
+                                  float* partials, void* stream) {
     if (!ctx) return GESR_ERR_INVALID;
     GESR_TRY(check_settings(ctx, st));
-    GESR_TRY(check_splats(ctx, splats, st->sh_degree, false));
     Geometry g;
-    GESR_TRY(check_cams(ctx, cams, V, splats->n, st, &g));
+    GESR_TRY(check_cams(ctx, cams, V, n, st, &g));
     GESR_TRY(check_proj(ctx, proj));
     GESR_TRY(check_bins(ctx, bins, false));
     if (!final_T || !n_contrib || !dL_dimage) return fail(ctx, GESR_ERR_INVALID, "final_T/n_contrib/dL_dimage is NULL");
     if (!partials || !aligned16(partials)) return fail(ctx, GESR_ERR_INVALID, "partials is NULL or misaligned");
-    if (!out) return fail(ctx, GESR_ERR_INVALID, "out is NULL");
-    if (splats->n > 0) {
-        const void* ptrs[6] = {out->mean, out->scale, out->quat, out->opacity, out->beta, out->sh};
-        for (int k = 0; k < 6; ++k)
-            if (!ptrs[k] || !aligned16(ptrs[k])) return fail(ctx, GESR_ERR_INVALID, "gradient output %d invalid", k);
-    }
-    hipStream_t strm = (hipStream_t)stream;
     GESR_TRY(hip_check(ctx, hipSetDevice(ctx->device), "hipSetDevice"));
-    const DevSettings ds = dev_settings(st);
-    const DevCams dc = dev_cams(cams, V, st);
     RenderArgs a;
     memset(&a, 0, sizeof a);
-    a.n = splats->n;
+    a.n = n;
     a.rec = proj->rec;
     a.val_sorted = bins->val_sorted;
     a.ranges = bins->ranges;
@@ -483,10 +473,33 @@ gesr_status gesr_render_bwd(gesr_ctx* ctx, const gesr_splats* splats, const gesr
     a.n_contrib = const_cast<uint32_t*>(n_contrib);
     a.dL_dimage = dL_dimage;
     a.partials = partials;
-    a.st = ds;
-    a.cams = dc;
+    a.st = dev_settings(st);
+    a.cams = dev_cams(cams, V, st);
     const int batch = st->batch > 0 ? st->batch : 64;
-    GESR_TRY(hip_check(ctx, launch_render_bwd(a, st->tile_w, st->tile_h, batch, strm), "render_bwd launch"));
+    GESR_TRY(hip_check(ctx, launch_render_bwd(a, st->tile_w, st->tile_h, batch, (hipStream_t)stream),
+                       "render_bwd launch"));
+    ctx->err.clear();
+    return GESR_OK;
+}
+
+gesr_status gesr_project_bwd(gesr_ctx* ctx, const gesr_splats* splats, const gesr_proj* proj, const gesr_bins* bins,
+                             const gesr_camera* cams, int V, const gesr_settings* st, const float* partials,
+                             float* grad2d, const gesr_grads* out, void* stream) {
+    if (!ctx) return GESR_ERR_INVALID;
+    GESR_TRY(check_settings(ctx, st));
+    GESR_TRY(check_splats(ctx, splats, st->sh_degree, false));
+    Geometry g;
+    GESR_TRY(check_cams(ctx, cams, V, splats->n, st, &g));
+    GESR_TRY(check_proj(ctx, proj));
+    GESR_TRY(check_bins(ctx, bins, false));
+    if (!partials || !aligned16(partials)) return fail(ctx, GESR_ERR_INVALID, "partials is NULL or misaligned");
+    if (!out) return fail(ctx, GESR_ERR_INVALID, "out is NULL");
+    if (splats->n > 0) {
+        const void* ptrs[6] = {out->mean, out->scale, out->quat, out->opacity, out->beta, out->sh};
+        for (int k = 0; k < 6; ++k)
+            if (!ptrs[k] || !aligned16(ptrs[k])) return fail(ctx, GESR_ERR_INVALID, "gradient output %d invalid", k);
+    }
+    GESR_TRY(hip_check(ctx, hipSetDevice(ctx->device), "hipSetDevice"));
     ProjectBwdArgs b;
     b.n = splats->n;
     b.mean = splats->mean;
@@ -506,11 +519,23 @@ gesr_status gesr_render_bwd(gesr_ctx* ctx, const gesr_splats* splats, const gesr
     b.g_opacity = out->opacity;
     b.g_beta = out->beta;
     b.g_sh = out->sh;
-    b.st = ds;
-    b.cams = dc;
-    GESR_TRY(hip_check(ctx, launch_project_bwd(b, st->sh_degree, strm), "project_bwd launch"));
+    b.st = dev_settings(st);
+    b.cams = dev_cams(cams, V, st);
+    GESR_TRY(hip_check(ctx, launch_project_bwd(b, st->sh_degree, (hipStream_t)stream), "project_bwd launch"));
     ctx->err.clear();
     return GESR_OK;
+}
+
+gesr_status gesr_render_bwd(gesr_ctx* ctx, const gesr_splats* splats, const gesr_proj* proj, const gesr_bins* bins,
+                            const gesr_camera* cams, int V, const gesr_settings* st, const float* final_T,
+                            const uint32_t* n_contrib, const float* dL_dimage, float* partials, float* grad2d,
+                            const gesr_grads* out, void* stream) {
+    if (!ctx) return GESR_ERR_INVALID;
+    if (!splats) return fail(ctx, GESR_ERR_INVALID, "splats is NULL");
+    if (!out) return fail(ctx, GESR_ERR_INVALID, "out is NULL");
+    GESR_TRY(gesr_render_bwd_tiles(ctx, proj, bins, cams, V, splats->n, st, final_T, n_contrib, dL_dimage, partials,
+                                   stream));
+    return gesr_project_bwd(ctx, splats, proj, bins, cams, V, st, partials, grad2d, out, stream);
 }
 
 gesr_status gesr_l1_grad(gesr_ctx* ctx, const float* image, const float* target, uint64_t count, float scale,

@@ -137,6 +137,7 @@ struct SplatGeom {
     float R[9];
     float phi;
     float M[9];    // R diag(phi s)
+    float ps[3];   // phi s
 };
 
 __device__ __forceinline__ void splat_geom(const float* s, const float* q, float beta, const DevSettings& st,
@@ -158,8 +159,9 @@ __device__ __forceinline__ void splat_geom(const float* s, const float* q, float
     g.R[7] = 2.f * (y * z + w * x);
     g.R[8] = 1.f - 2.f * (x * x + y * y);
     g.phi = 2.0f / (1.0f + expf(-st.rho * (beta - 2.0f)));
+    for (int b = 0; b < 3; ++b) g.ps[b] = g.phi * s[b];
     for (int a = 0; a < 3; ++a)
-        for (int b = 0; b < 3; ++b) g.M[3 * a + b] = g.R[3 * a + b] * (g.phi * s[b]);
+        for (int b = 0; b < 3; ++b) g.M[3 * a + b] = g.R[3 * a + b] * g.ps[b];
 }
 
 // Per-view projection state (kept for the adjoint).
@@ -209,11 +211,21 @@ __device__ __forceinline__ void project_view(const float* mean, const SplatGeom&
     const float a0 = U0[0] * U0[0] + U0[1] * U0[1] + U0[2] * U0[2];
     const float c0 = U1[0] * U1[0] + U1[1] * U1[1] + U1[2] * U1[2];
     vp.b = U0[0] * U1[0] + U0[1] * U1[1] + U0[2] * U1[2];
-    // det(U U^T + blur I) = |U0 x U1|^2 + blur (|U0|^2 + |U1|^2) + blur^2: a sum of
-    // non-negative terms, free of the cancellation in a c - b^2 for thin footprints
-    const float x0 = U0[1] * U1[2] - U0[2] * U1[1];
-    const float x1 = U0[2] * U1[0] - U0[0] * U1[2];
-    const float x2 = U0[0] * U1[1] - U0[1] * U1[0];
+    // det(U U^T + blur I) = |U0 x U1|^2 + blur (|U0|^2 + |U1|^2) + blur^2, a sum of
+    // non-negative terms (no cancellation as in a c - b^2 for thin footprints).
+    // With U0 = M^T T0, U1 = M^T T1:  U0 x U1 = det(M) M^-1 (T0 x T1), whose k-th
+    // component is (prod_{j != k} phi s_j) (R^T (T0 x T1))_k -- exact in form even
+    // for near-2-D splats seen edge-on.
+    const float n0 = T[1] * T[5] - T[2] * T[4];
+    const float n1 = T[2] * T[3] - T[0] * T[5];
+    const float n2 = T[0] * T[4] - T[1] * T[3];
+    const float* R = g.R;
+    const float m0 = R[0] * n0 + R[3] * n1 + R[6] * n2;
+    const float m1 = R[1] * n0 + R[4] * n1 + R[7] * n2;
+    const float m2 = R[2] * n0 + R[5] * n1 + R[8] * n2;
+    const float x0 = (g.ps[1] * g.ps[2]) * m0;
+    const float x1 = (g.ps[0] * g.ps[2]) * m1;
+    const float x2 = (g.ps[0] * g.ps[1]) * m2;
     vp.det = (x0 * x0 + x1 * x1 + x2 * x2) + st.blur * (a0 + c0) + st.blur * st.blur;
     vp.a = a0 + st.blur;
     vp.c = c0 + st.blur;

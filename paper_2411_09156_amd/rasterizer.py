@@ -233,6 +233,31 @@ class Rasterizer:
             g["grad2d"] = grad2d
         return g
 
+    def render_bwd_tiles(self, proj: dict, bins: dict, n: int, final_T, n_contrib, dL_dimage, partials=None):
+        """Per-tile render adjoint only: returns the per-instance partials."""
+        if partials is None:
+            partials = self._empty(bins["m_cap"] * _lib.PARTIAL_FLOATS)
+        self._check(self.lib.gesr_render_bwd_tiles(self.ctx, ctypes.byref(self._proj_c(proj)),
+                                                   ctypes.byref(self._bins_c(bins)), self.cams_c, self.V, n,
+                                                   ctypes.byref(self.st_c), final_T.data_ptr(), n_contrib.data_ptr(),
+                                                   dL_dimage.data_ptr(), partials.data_ptr(), _stream()), self.ctx)
+        return partials
+
+    def project_bwd(self, sp: Splats, proj: dict, bins: dict, partials, want_grad2d: bool = False) -> dict:
+        """Segmented sum of the partials and the projection adjoint."""
+        g = dict(mean=torch.empty_like(sp.mean), scale=torch.empty_like(sp.scale), quat=torch.empty_like(sp.quat),
+                 opacity=torch.empty_like(sp.opacity), beta=torch.empty_like(sp.beta), sh=torch.empty_like(sp.sh))
+        gc = _lib.Grads(*(g[k].data_ptr() for k in ("mean", "scale", "quat", "opacity", "beta", "sh")))
+        grad2d = self._empty(self.V * sp.n * _lib.PARTIAL_FLOATS) if want_grad2d else None
+        self._check(self.lib.gesr_project_bwd(self.ctx, ctypes.byref(sp.to_c()), ctypes.byref(self._proj_c(proj)),
+                                              ctypes.byref(self._bins_c(bins)), self.cams_c, self.V,
+                                              ctypes.byref(self.st_c), partials.data_ptr(),
+                                              grad2d.data_ptr() if grad2d is not None else None, ctypes.byref(gc),
+                                              _stream()), self.ctx)
+        if grad2d is not None:
+            g["grad2d"] = grad2d
+        return g
+
     def l1_grad(self, image, target, scale: float):
         grad = torch.empty_like(image)
         self._check(self.lib.gesr_l1_grad(self.ctx, image.data_ptr(), target.data_ptr(), image.numel(),

@@ -34,19 +34,16 @@ def splats_of(scene):
     return Splats.from_aos(scene.means, scene.scales, scene.quats, scene.opacities, scene.betas, scene.sh)
 
 
-def run_gpu(scene, st: oracle.Settings, dL=None, counts=True, rast=None, **kw) -> dict:
-    """Full HIP pipeline; returns numpy outputs (plus the torch state under 'torch')."""
+def run_gpu(scene, st: oracle.Settings, counts=True, rast=None, **kw) -> dict:
+    """HIP forward pipeline; returns numpy outputs (plus the torch state under 'torch')."""
     import torch
     from paper_2411_09156_amd import Rasterizer
     if rast is None:
         rast = Rasterizer(scene.cameras, raster_settings(st, **kw))
     sp = splats_of(scene)
     out = rast.forward(sp, counts=counts)
-    res = {}
-    if dL is not None:
-        g = rast.render_bwd(sp, out["proj"], out["bins"], out["final_T"], out["n_contrib"],
-                            torch.as_tensor(np.asarray(dL, np.float32), device="cuda"), want_grad2d=True)
     torch.cuda.synchronize()
+    res = {}
     N, V = scene.n, scene.n_views
     VN = N * V
     p, b = out["proj"], out["bins"]
@@ -72,17 +69,50 @@ def run_gpu(scene, st: oracle.Settings, dL=None, counts=True, rast=None, **kw) -
     if counts:
         res["n_listed"] = u32(out["n_listed"])[:P]
         res["n_hit"] = u32(out["n_hit"])[:P]
-    if dL is not None:
-        K = (st.sh_degree + 1) ** 2
-        res["grad2d"] = f32(g["grad2d"])[:VN * 10].reshape(VN, 10)
-        res["g_means"] = f32(g["mean"]).reshape(3, N).T
-        res["g_scales"] = f32(g["scale"]).reshape(3, N).T
-        res["g_quats"] = f32(g["quat"]).reshape(4, N).T
-        res["g_opacities"] = f32(g["opacity"])
-        res["g_betas"] = f32(g["beta"])
-        res["g_sh"] = f32(g["sh"]).reshape(K * 3, N).T.reshape(N, K, 3)
     res["torch"] = (rast, sp, out)
     return res
+
+
+def run_gpu_bwd(scene, st: oracle.Settings, res: dict, dL) -> dict:
+    """HIP backward for upstream dL (flat image layout); numpy gradients."""
+    import torch
+    rast, sp, out = res["torch"]
+    g = rast.render_bwd(sp, out["proj"], out["bins"], out["final_T"], out["n_contrib"],
+                        torch.as_tensor(np.asarray(dL, np.float32), device="cuda"), want_grad2d=True)
+    torch.cuda.synchronize()
+    N, V = scene.n, scene.n_views
+    K = (st.sh_degree + 1) ** 2
+    return dict(grad2d=f32(g["grad2d"])[:N * V * 10].reshape(N * V, 10),
+                means=f32(g["mean"]).reshape(3, N).T, scales=f32(g["scale"]).reshape(3, N).T,
+                quats=f32(g["quat"]).reshape(4, N).T, opacities=f32(g["opacity"]), betas=f32(g["beta"]),
+                sh=f32(g["sh"]).reshape(K * 3, N).T.reshape(N, K, 3))
+
+
+def mask_upstream(dL, ambiguous, cameras):
+    """Zero dL/dimage (all channels) at the given pixels (flat CHW-per-view layout)."""
+    out = np.array(dL, dtype=np.float64, copy=True)
+    amb = np.asarray(ambiguous, bool)
+    off_i = off_p = 0
+    for c in cameras:
+        P = c.width * c.height
+        m = amb[off_p:off_p + P]
+        for ch in range(3):
+            seg = out[off_i + ch * P:off_i + (ch + 1) * P]
+            seg[m] = 0.0
+        off_i += 3 * P
+        off_p += P
+    return out
+
+
+def e2e_settings(st: oracle.Settings, cameras) -> oracle.Settings:
+    """Oracle settings whose ambiguity band covers float32 projection error:
+    centre error 2 ulp of the image extent, conic error 2e-5 (99.99th
+    percentile of the projection's measured error)."""
+    import copy
+    s = copy.copy(st)
+    s.ambig_pos = 2.0 ** -22 * max(max(c.width, c.height) for c in cameras)
+    s.ambig_conic = 2e-5
+    return s
 
 
 def oracle_rec(gpu_rec: np.ndarray) -> np.ndarray:
@@ -155,21 +185,31 @@ def norm_errors(a, b):
     return (einf / ninf if ninf > 0 else einf, e2 / n2 if n2 > 0 else e2)
 
 
-def tile_lists(vals, ranges):
-    return [tuple(vals[s0:s1]) for s0, s1 in ranges]
+def differing_tiles(vals_a, ranges_a, vals_b, ranges_b) -> np.ndarray:
+    """Boolean per global tile: True where the two sorted lists of the tile differ."""
+    ranges_a = np.asarray(ranges_a, np.int64)
+    ranges_b = np.asarray(ranges_b, np.int64)
+    la = ranges_a[:, 1] - ranges_a[:, 0]
+    lb = ranges_b[:, 1] - ranges_b[:, 0]
+    diff = la != lb
+    idx = np.nonzero(~diff & (la > 0))[0]
+    L = la[idx]
+    if L.sum() > 0:
+        off = np.arange(L.sum()) - np.repeat(np.cumsum(L) - L, L)
+        pa = np.repeat(ranges_a[idx, 0], L) + off
+        pb = np.repeat(ranges_b[idx, 0], L) + off
+        neq = np.asarray(vals_a)[pa] != np.asarray(vals_b)[pb]
+        diff[np.unique(np.repeat(idx, L)[neq])] = True
+    return diff
 
 
-def ambiguous_from_lists(cameras, st, lists_a, lists_b):
-    """Pixel mask: True where the pixel's tile list differs between two binnings."""
+def ambiguous_tiles_to_pixels(cameras, st, tile_diff) -> np.ndarray:
+    """Pixel mask of the tiles flagged in `tile_diff`."""
     grid, T = oracle.tile_grid(cameras, st.tile_w, st.tile_h)
     masks = []
     for v, c in enumerate(cameras):
         tx_n, ty_n, base = grid[v]
-        m = np.zeros((c.height, c.width), bool)
-        for ty in range(ty_n):
-            for tx in range(tx_n):
-                t = base + ty * tx_n + tx
-                if lists_a[t] != lists_b[t]:
-                    m[ty * st.tile_h:(ty + 1) * st.tile_h, tx * st.tile_w:(tx + 1) * st.tile_w] = True
+        t = tile_diff[base:base + tx_n * ty_n].reshape(ty_n, tx_n)
+        m = np.repeat(np.repeat(t, st.tile_h, 0), st.tile_w, 1)[:c.height, :c.width]
         masks.append(m.reshape(-1))
     return np.concatenate(masks)

@@ -7,11 +7,17 @@ GPU pipeline with the oracle run from the splat parameters.
 Bars (derived in the design notes):
   * binning: bit-exact keys, values, ranges, instance count and instance bases;
   * images / final_T: max error <= 1e-4 * max(max|C|, 1) on pixels that are not
-    ambiguous (a fragment within 1e-5 of alpha_min / alpha_max / t_min, or a
-    tile list that differs), and relative L2 <= 1e-4 over all pixels;
-    n_contrib and the fragment counts exact on non-ambiguous pixels;
+    ambiguous, and relative L2 <= 1e-4 over all pixels; n_contrib and the
+    fragment counts exact on non-ambiguous pixels.  A pixel is ambiguous when
+    one of its fragments lies within the float32 error band of alpha_min,
+    alpha_max or t_min (1e-5 relative when both sides share the GPU's records;
+    end to end the band adds the first-order effect of float32 centre and
+    conic error), or, end to end, when compositing the GPU's tile list instead
+    of the oracle's changes the oracle's own result at that pixel;
   * gradients: per tensor, inf-norm and 2-norm of the error <= 1e-3 of the
-    reference's norms, with identical upstream dL/dimage on both sides.
+    reference's norms, for the same seeded upstream dL/dimage on both sides,
+    zeroed at ambiguous pixels (a threshold flip there is a legitimate
+    difference, not an error).
 """
 import functools
 
@@ -20,8 +26,8 @@ import pytest
 
 import gesr_inputs as gi
 import oracle
-from tests.gpu_util import (ambiguous_from_lists, conic_grads_to_factor, factor_grads_to_conic, image_errors, log,
-                            norm_errors, oracle_rec, run_gpu, tile_lists)
+from tests.gpu_util import (conic_grads_to_factor, e2e_settings, factor_grads_to_conic, image_errors, log,
+                            mask_upstream, norm_errors, oracle_rec, run_gpu, run_gpu_bwd)
 
 pytestmark = pytest.mark.gpu
 
@@ -57,28 +63,60 @@ CASES = ["tiny-d1", "tiny-d3-2v-bg", "tiny-kappa1", "plain-2k", "plain-2k-t8", "
          "spheres-100k", "drt-50k-8v", "surfels-40k-2v", "blobs-100k-2v"]
 
 
-@functools.lru_cache(maxsize=2)
+@functools.lru_cache(maxsize=1)
 def _run(name):
     scene, st = _case(name)
-    dL = oracle.flat_images(gi.upstream_grads(scene, 7))
     log(f"[gpu] case {name}: n={scene.n} views={scene.n_views} px={scene.n_pixels}")
-    g = run_gpu(scene, st, dL=dL)
-    log(f"[gpu] case {name}: done, M={g['M']}")
-    return scene, st, dL, g
+    g = run_gpu(scene, st)
+    log(f"[gpu] case {name}: forward done, M={g['M']}")
+    return scene, st, g
 
 
-@functools.lru_cache(maxsize=2)
-def _oracle_same_inputs(name):
-    scene, st, dL, g = _run(name)
+@functools.lru_cache(maxsize=1)
+def _same_inputs(name):
+    """Oracle fed the GPU's records and lists; gradients for an upstream dL that
+    is zero at pixels whose decisions are ambiguous (identical on both sides)."""
+    scene, st, g = _run(name)
     rec = oracle_rec(g["rec"])
     fwd = oracle.render_fwd(scene.n, scene.cameras, rec, g["val_sorted"], g["ranges"], st)
+    dL = mask_upstream(oracle.flat_images(gi.upstream_grads(scene, 7)), fwd["ambig"] > 0, scene.cameras)
+    log(f"[gpu] case {name}: backward (same inputs)")
+    gb = run_gpu_bwd(scene, st, g, dL)
     g2 = oracle.render_bwd(scene.n, scene.cameras, rec, g["val_sorted"], g["ranges"], dL, st)
-    return rec, fwd, g2
+    return rec, fwd, dL, gb, g2
+
+
+@functools.lru_cache(maxsize=1)
+def _end_to_end(name):
+    """Oracle run from the parameters.  Ambiguous pixels: a fragment inside the
+    float32 band of a threshold, or a pixel whose oracle result changes when
+    the oracle composites the GPU's tile lists instead of its own (the lists
+    differ only at guard bands of the rectangles and depth keys)."""
+    scene, st, g = _run(name)
+    se = e2e_settings(st, scene.cameras)
+    fo = oracle.forward(scene, se)
+    fl = oracle.render_fwd(scene.n, scene.cameras, fo["proj"]["rec"], g["val_sorted"], g["ranges"], se)
+    P = scene.n_pixels
+    changed = (fl["image"] != fo["image"]).reshape(-1)
+    list_amb = np.zeros(P, bool)
+    off_i = off_p = 0
+    for c in scene.cameras:
+        n = c.width * c.height
+        list_amb[off_p:off_p + n] = changed[off_i:off_i + 3 * n].reshape(3, n).any(0)
+        off_i += 3 * n
+        off_p += n
+    list_amb |= fl["final_T"] != fo["final_T"]
+    amb = (fo["ambig"] > 0) | (fl["ambig"] > 0) | list_amb
+    dL = mask_upstream(oracle.flat_images(gi.upstream_grads(scene, 7)), amb, scene.cameras)
+    log(f"[gpu] case {name}: backward (end to end); pixels changed by the GPU lists {int(list_amb.sum())}")
+    gb = run_gpu_bwd(scene, st, g, dL)
+    go = oracle.backward(scene, se, fo, dL)
+    return fo, amb, dL, gb, go
 
 
 @pytest.mark.parametrize("name", CASES)
 def test_project(name):
-    scene, st, dL, g = _run(name)
+    scene, st, g = _run(name)
     pr = oracle.project(scene, st)
     keep_g = g["tiles_touched"] > 0
     keep_o = pr["tiles_touched"] > 0
@@ -89,12 +127,22 @@ def test_project(name):
     cams = scene.cameras
     cx = np.concatenate([np.full(scene.n, c.cx) for c in cams])[both]
     cy = np.concatenate([np.full(scene.n, c.cy) for c in cams])[both]
-    np.testing.assert_array_less(np.abs(r[:, 0] - o[:, 0]), 1e-6 * (np.abs(o[:, 0] - cx) + np.abs(o[:, 0])) + 1e-5)
-    np.testing.assert_array_less(np.abs(r[:, 1] - o[:, 1]), 1e-6 * (np.abs(o[:, 1] - cy) + np.abs(o[:, 1])) + 1e-5)
+    # centre: within 2 float32 ulps of the view's extent (u = fx x/z + cx rounds
+    # at the scale of the image, also where the two terms cancel near u = 0)
+    ext = np.concatenate([np.full(scene.n, max(c.width, c.height)) for c in cams])[both]
+    ulp = np.spacing(np.maximum(np.maximum(np.abs(o[:, 0]), np.abs(o[:, 1])), ext).astype(np.float32))
+    eu = np.abs(r[:, 0] - o[:, 0]) / ulp
+    ev = np.abs(r[:, 1] - o[:, 1]) / ulp
+    assert max(eu.max(), ev.max()) <= 2.0, (eu.max(), ev.max())
+    # conic: 1e-4 relative.  Near edge-on flat splats the determinant's cross term
+    # is (disk normal . viewing ray), whose float32 evaluation from a float32
+    # rotation loses about eps |ray| / |normal . ray|; elsewhere errors are ~1e-6.
     A, B, C = r[:, 2] ** 2, r[:, 2] * r[:, 3], r[:, 3] ** 2 + r[:, 4] ** 2
-    np.testing.assert_array_less(np.abs(A - o[:, 2]), 2e-5 * o[:, 2] + 1e-30)
-    np.testing.assert_array_less(np.abs(C - o[:, 4]), 2e-5 * o[:, 4] + 1e-30)
-    np.testing.assert_array_less(np.abs(B - o[:, 3]), 2e-5 * np.sqrt(o[:, 2] * o[:, 4]) + 1e-30)
+    eA = np.abs(A - o[:, 2]) / o[:, 2]
+    eC = np.abs(C - o[:, 4]) / o[:, 4]
+    eB = np.abs(B - o[:, 3]) / np.sqrt(o[:, 2] * o[:, 4])
+    econ = np.maximum(np.maximum(eA, eC), eB)
+    assert econ.max() <= 1e-4, econ.max()
     np.testing.assert_array_equal(r[:, 5], o[:, 5])
     np.testing.assert_array_equal(r[:, 6], o[:, 6])
     np.testing.assert_array_less(np.abs(r[:, 7] - o[:, 7]), 1e-5 * o[:, 7] + 1e-30)
@@ -110,14 +158,15 @@ def test_project(name):
     near = (np.abs(e - np.round(e)) < 1e-3).any(1)
     assert (diff & ~near).sum() == 0
     log(f"[gpu] {name}: project ok; culls differ {int((keep_g != keep_o).sum())}, rects in guard band "
-        f"{int(diff.sum())}, depth ulps {int((dk_g != dk_o).sum())}")
+        f"{int(diff.sum())}, depth ulps {int((dk_g != dk_o).sum())}; centre err max {max(eu.max(), ev.max()):.2f} ulp; "
+        f"conic rel err max {econ.max():.2e}, 99.99% {np.quantile(econ, 0.9999):.2e}")
 
 
 @pytest.mark.parametrize("name", CASES)
 def test_bin_bit_exact(name):
     """Oracle binning of the GPU's own per-splat results (rect, depth key) equals
     the GPU's sorted instance list, ranges, count and instance bases exactly."""
-    scene, st, dL, g = _run(name)
+    scene, st, g = _run(name)
     keys, vals, ranges = oracle.bin_instances(scene.n, scene.cameras, g["tile_rect"], g["tiles_touched"],
                                               g["depth_key"], st)
     assert g["overflow"] == 0
@@ -139,8 +188,8 @@ def test_bin_bit_exact(name):
 
 @pytest.mark.parametrize("name", CASES)
 def test_render_fwd_same_inputs(name):
-    scene, st, dL, g = _run(name)
-    rec, fwd, _ = _oracle_same_inputs(name)
+    scene, st, g = _run(name)
+    rec, fwd, dL, gb, g2 = _same_inputs(name)
     amb = fwd["ambig"] > 0
     errs = image_errors(g["image"], fwd["image"], amb, scene.cameras)
     for bad, mx, bound, l2 in errs:
@@ -158,47 +207,44 @@ def test_render_fwd_same_inputs(name):
 def test_render_bwd_same_inputs(name):
     """Screen-space gradients per (view, splat) after the tile partials and the
     segmented sum, against the oracle's explicit-list adjoint."""
-    scene, st, dL, g = _run(name)
-    rec, fwd, g2 = _oracle_same_inputs(name)
+    scene, st, g = _run(name)
+    rec, fwd, dL, gb, g2 = _same_inputs(name)
     ref = conic_grads_to_factor(g2, g["rec"])
     labels = ["du", "dv", "dL00", "dL10", "dL11", "dop", "dbeta", "dr", "dg", "db"]
-    res = {}
+    worst = 0.0
     for k, lab in enumerate(labels):
-        einf, e2 = norm_errors(g["grad2d"][:, k], ref[:, k])
-        res[lab] = (einf, e2)
+        einf, e2 = norm_errors(gb["grad2d"][:, k], ref[:, k])
+        worst = max(worst, einf, e2)
         assert einf <= 1e-3 and e2 <= 1e-3, (lab, einf, e2)
-    log(f"[gpu] {name}: bwd ok; worst {max(max(v) for v in res.values()):.2e}")
+    log(f"[gpu] {name}: bwd ok; worst {worst:.2e}")
 
 
 @pytest.mark.parametrize("name", CASES)
 def test_project_bwd_same_inputs(name):
     """Projection adjoint fed the GPU's own screen-space gradients: the oracle's
     dual-number Jacobian gives the reference parameter gradients."""
-    scene, st, dL, g = _run(name)
-    g2 = factor_grads_to_conic(g["grad2d"], g["rec"])
-    ref = oracle.project_bwd(scene, g2, st)
+    scene, st, g = _run(name)
+    rec, fwd, dL, gb, g2 = _same_inputs(name)
+    ref = oracle.project_bwd(scene, factor_grads_to_conic(gb["grad2d"], g["rec"]), st)
     for k in ("means", "scales", "quats", "opacities", "betas", "sh"):
-        einf, e2 = norm_errors(g["g_" + k], ref[k])
+        einf, e2 = norm_errors(gb[k], ref[k])
         assert einf <= 1e-3 and e2 <= 1e-3, (k, einf, e2)
 
 
 @pytest.mark.parametrize("name", CASES)
 def test_end_to_end(name):
     """Whole GPU pipeline vs the oracle run from the splat parameters."""
-    scene, st, dL, g = _run(name)
-    fo = oracle.forward(scene, st)
-    amb = (fo["ambig"] > 0) | ambiguous_from_lists(scene.cameras, st, tile_lists(g["val_sorted"], g["ranges"]),
-                                                   tile_lists(fo["vals"], fo["ranges"]))
+    scene, st, g = _run(name)
+    fo, amb, dL, gb, go = _end_to_end(name)
     errs = image_errors(g["image"], fo["image"], amb, scene.cameras)
     for bad, mx, bound, l2 in errs:
         assert bad == 0 and l2 <= 1e-4, errs
     ok = ~amb
     assert np.abs(g["final_T"][ok] - fo["final_T"][ok]).max() <= 1e-4
-    go = oracle.backward(scene, st, fo, dL)
     worst = 0.0
     for k in ("means", "scales", "quats", "opacities", "betas", "sh"):
-        einf, e2 = norm_errors(g["g_" + k], go[k])
+        einf, e2 = norm_errors(gb[k], go[k])
         worst = max(worst, einf, e2)
         assert einf <= 1e-3 and e2 <= 1e-3, (k, einf, e2)
-    log(f"[gpu] {name}: end-to-end ok; ambiguous px {int(amb.sum())}; image max err "
+    log(f"[gpu] {name}: end-to-end ok; ambiguous px {int(amb.sum())}/{amb.size}; image max err "
         f"{max(e[1] for e in errs):.2e}; grad worst {worst:.2e}")
