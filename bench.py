@@ -101,9 +101,9 @@ def main():
             rec(3)
             dL = rast.l1_grad(f["image"], target, scale)
             rec(4)
-            partials = rast.render_bwd_tiles(proj, bins, n, f["final_T"], f["n_contrib"], dL)
+            ws = rast.render_bwd_tiles(proj, bins, n, f["final_T"], f["n_contrib"], dL)
             rec(5)
-            g = rast.project_bwd(sp, proj, bins, partials)
+            g = rast.project_bwd(sp, proj, bins, ws)
             rec(6)
             return f, g, bins
         return step
@@ -158,7 +158,7 @@ def main():
     value = P / (ms * 1e-3) / 1e6
 
     # ------------------------------------- per-stage times (eager, events)
-    names = ["project", "bin", "render_fwd", "l1_grad", "render_bwd_tiles", "project_bwd"]
+    names = ["project", "bin", "render_fwd", "l1_grad", "render_bwd_tiles", "seg_reduce+project_bwd"]
     evs = [torch.cuda.Event(enable_timing=True) for _ in range(7)]
     tstep = make_step(rast, sp, target, m_cap, evs)
     tstep()

@@ -158,7 +158,7 @@ typedef struct {
     uint64_t total_tiles;      /* T: tiles over all views */
     uint64_t total_pixels;     /* P: pixels over all views */
     size_t bin_scratch_bytes;  /* gesr_bins.scratch size for the given m_cap */
-    size_t partial_bytes;      /* gesr_render_bwd partial buffer for m_cap */
+    size_t bwd_workspace_bytes; /* backward workspace (tile cuts, partials) for m_cap */
     uint64_t max_sort_blocks;  /* informational */
 } gesr_sizes;
 
@@ -209,34 +209,40 @@ gesr_status gesr_render_fwd(gesr_ctx* ctx, const gesr_proj* proj, const gesr_bin
 
 /* Backward pass: adjoint of gesr_render_fwd and gesr_project for upstream
  * dL_dimage (same layout as image).  Transmittance is recovered per pixel by
- * division from final_T and n_contrib (no per-fragment state is stored);
- * each tile reduces its pixels' contributions per instance without atomics
- * into `partials` (DEVICE, gesr_sizes.partial_bytes); a fixed-order segmented
- * sum per (view, splat) then feeds the projection adjoint, summed over views
- * in ascending order.  grad2d (DEVICE [V*n][10], nullable) receives the
+ * division from final_T and n_contrib (no per-fragment state is stored in the
+ * forward); each tile reduces its pixels' contributions per instance without
+ * atomics; a fixed-order segmented sum per (view, splat) then feeds the
+ * projection adjoint, summed over views in ascending order.
+ * `workspace` (DEVICE, gesr_sizes.bwd_workspace_bytes) holds, in order and
+ * 256-byte aligned: the per-tile cut keys (uint64 [T]), the screen-space
+ * gradients (float [V*n][10]) and the per-instance partials (float
+ * [m_cap][10]).  grad2d (DEVICE [V*n][10], nullable) receives the
  * screen-space gradients du, dv, dL00, dL10, dL11, dopacity, dbeta, dr, dg, db
  * (dbeta here is the falloff term only; the phi(beta) term is added in the
- * projection adjoint).
- * `out` arrays are overwritten.  Results are bitwise reproducible. */
+ * projection adjoint).  `out` arrays are overwritten.  Results are bitwise
+ * reproducible, and identical whether views are batched or rendered alone. */
 gesr_status gesr_render_bwd(gesr_ctx* ctx, const gesr_splats* splats, const gesr_proj* proj, const gesr_bins* bins,
                             const gesr_camera* cams, int V, const gesr_settings* st, const float* final_T,
-                            const uint32_t* n_contrib, const float* dL_dimage, float* partials, float* grad2d,
+                            const uint32_t* n_contrib, const float* dL_dimage, void* workspace, float* grad2d,
                             const gesr_grads* out, void* stream);
 
 /* The two halves of gesr_render_bwd, for callers that schedule or time them
- * separately.  gesr_render_bwd_tiles: the per-tile render adjoint, writing one
- * gradient partial (10 floats, grad2d order) per instance into `partials`
- * (DEVICE, gesr_sizes.partial_bytes; every instance slot below min(M, m_cap)
- * is written).  gesr_project_bwd: the fixed-order per-(view, splat) sum of
- * those partials, then the projection adjoint (Eq. 4, 6-7 and the EWA
+ * separately.  gesr_render_bwd_tiles: the per-tile render adjoint.  Each tile
+ * visits its list up to the deepest position any of its pixels composited,
+ * writes one gradient partial (10 floats, grad2d order) per visited instance
+ * into the workspace and records the (depth key << 32 | view * n + splat) of
+ * its first unvisited position (all ones when none): lists are strictly
+ * increasing in that key, so an instance was visited iff its key is below its
+ * tile's cut.  gesr_project_bwd: per (view, splat), the fixed-order sum of its
+ * visited partials, then the projection adjoint (Eq. 4, 6-7 and the EWA
  * passage of Sec. 3.2) summed over views in ascending order.  Arguments as in
  * gesr_render_bwd; n = splats->n. */
 gesr_status gesr_render_bwd_tiles(gesr_ctx* ctx, const gesr_proj* proj, const gesr_bins* bins,
                                   const gesr_camera* cams, int V, int n, const gesr_settings* st,
                                   const float* final_T, const uint32_t* n_contrib, const float* dL_dimage,
-                                  float* partials, void* stream);
+                                  void* workspace, void* stream);
 gesr_status gesr_project_bwd(gesr_ctx* ctx, const gesr_splats* splats, const gesr_proj* proj, const gesr_bins* bins,
-                             const gesr_camera* cams, int V, const gesr_settings* st, const float* partials,
+                             const gesr_camera* cams, int V, const gesr_settings* st, void* workspace,
                              float* grad2d, const gesr_grads* out, void* stream);
 
 /* L1 photometric term of Eq. 8 (the (1 - lambda) L1 part):

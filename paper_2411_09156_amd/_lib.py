@@ -69,7 +69,7 @@ class Grads(ctypes.Structure):
 
 class Sizes(ctypes.Structure):
     _fields_ = [("total_tiles", ctypes.c_uint64), ("total_pixels", ctypes.c_uint64),
-                ("bin_scratch_bytes", ctypes.c_size_t), ("partial_bytes", ctypes.c_size_t),
+                ("bin_scratch_bytes", ctypes.c_size_t), ("bwd_workspace_bytes", ctypes.c_size_t),
                 ("max_sort_blocks", ctypes.c_uint64)]
 
 

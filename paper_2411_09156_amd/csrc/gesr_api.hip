@@ -200,6 +200,30 @@ BinScratch carve(void* base, uint64_t vn, uint64_t m_cap, uint64_t T) {
     return s;
 }
 
+// Layout of the backward workspace (256-byte aligned sub-buffers).
+struct BwdWorkspace {
+    uint64_t* tile_cut;  // [T]
+    float* grad2d;       // [V*n][10]
+    float* partials;     // [m_cap][10]
+    size_t bytes;
+};
+
+BwdWorkspace carve_bwd(void* base, uint64_t vn, uint64_t m_cap, uint64_t T) {
+    BwdWorkspace w;
+    size_t off = 0;
+    char* b = (char*)base;
+    auto take = [&](uint64_t bytes) -> char* {
+        char* p = b ? b + off : nullptr;
+        off += ((bytes + 255) / 256) * 256;
+        return p;
+    };
+    w.tile_cut = (uint64_t*)take((T > 0 ? T : 1) * 8);
+    w.grad2d = (float*)take((vn > 0 ? vn : 1) * GESR_PARTIAL_FLOATS * 4);
+    w.partials = (float*)take(m_cap * GESR_PARTIAL_FLOATS * 4);
+    w.bytes = off;
+    return w;
+}
+
 int bits_for(uint64_t count) {
     int b = 0;
     while (b < 32 && (1ull << b) < count) ++b;
@@ -304,7 +328,7 @@ gesr_status gesr_query_sizes(gesr_ctx* ctx, const gesr_camera* cams, int V, int 
     out->total_tiles = g.total_tiles;
     out->total_pixels = g.total_pixels;
     out->bin_scratch_bytes = s.bytes;
-    out->partial_bytes = (size_t)m_cap * GESR_PARTIAL_FLOATS * sizeof(float);
+    out->bwd_workspace_bytes = carve_bwd(nullptr, g.vn, m_cap, g.total_tiles).bytes;
     out->max_sort_blocks = ceil_div(m_cap, SORT_TILE);
     ctx->err.clear();
     return GESR_OK;
@@ -449,7 +473,7 @@ gesr_status gesr_render_fwd(gesr_ctx* ctx, const gesr_proj* proj, const gesr_bin
 gesr_status gesr_render_bwd_tiles(gesr_ctx* ctx, const gesr_proj* proj, const gesr_bins* bins,
                                   const gesr_camera* cams, int V, int n, const gesr_settings* st,
                                   const float* final_T, const uint32_t* n_contrib, const float* dL_dimage,
-                                  float* partials, void* stream) {
+                                  void* workspace, void* stream) {
     if (!ctx) return GESR_ERR_INVALID;
     GESR_TRY(check_settings(ctx, st));
     Geometry g;
@@ -457,8 +481,9 @@ gesr_status gesr_render_bwd_tiles(gesr_ctx* ctx, const gesr_proj* proj, const ge
     GESR_TRY(check_proj(ctx, proj));
     GESR_TRY(check_bins(ctx, bins, false));
     if (!final_T || !n_contrib || !dL_dimage) return fail(ctx, GESR_ERR_INVALID, "final_T/n_contrib/dL_dimage is NULL");
-    if (!partials || !aligned16(partials)) return fail(ctx, GESR_ERR_INVALID, "partials is NULL or misaligned");
+    if (!workspace || !aligned16(workspace)) return fail(ctx, GESR_ERR_INVALID, "workspace is NULL or misaligned");
     GESR_TRY(hip_check(ctx, hipSetDevice(ctx->device), "hipSetDevice"));
+    const BwdWorkspace ws = carve_bwd(workspace, g.vn, bins->m_cap, g.total_tiles);
     RenderArgs a;
     memset(&a, 0, sizeof a);
     a.n = n;
@@ -472,7 +497,9 @@ gesr_status gesr_render_bwd_tiles(gesr_ctx* ctx, const gesr_proj* proj, const ge
     a.final_T = const_cast<float*>(final_T);
     a.n_contrib = const_cast<uint32_t*>(n_contrib);
     a.dL_dimage = dL_dimage;
-    a.partials = partials;
+    a.partials = ws.partials;
+    a.depth_key = proj->depth_key;
+    a.tile_cut = ws.tile_cut;
     a.st = dev_settings(st);
     a.cams = dev_cams(cams, V, st);
     const int batch = st->batch > 0 ? st->batch : 64;
@@ -483,7 +510,7 @@ gesr_status gesr_render_bwd_tiles(gesr_ctx* ctx, const gesr_proj* proj, const ge
 }
 
 gesr_status gesr_project_bwd(gesr_ctx* ctx, const gesr_splats* splats, const gesr_proj* proj, const gesr_bins* bins,
-                             const gesr_camera* cams, int V, const gesr_settings* st, const float* partials,
+                             const gesr_camera* cams, int V, const gesr_settings* st, void* workspace,
                              float* grad2d, const gesr_grads* out, void* stream) {
     if (!ctx) return GESR_ERR_INVALID;
     GESR_TRY(check_settings(ctx, st));
@@ -492,7 +519,8 @@ gesr_status gesr_project_bwd(gesr_ctx* ctx, const gesr_splats* splats, const ges
     GESR_TRY(check_cams(ctx, cams, V, splats->n, st, &g));
     GESR_TRY(check_proj(ctx, proj));
     GESR_TRY(check_bins(ctx, bins, false));
-    if (!partials || !aligned16(partials)) return fail(ctx, GESR_ERR_INVALID, "partials is NULL or misaligned");
+    if (!workspace || !aligned16(workspace)) return fail(ctx, GESR_ERR_INVALID, "workspace is NULL or misaligned");
+    if (grad2d && !aligned16(grad2d)) return fail(ctx, GESR_ERR_INVALID, "grad2d is misaligned");
     if (!out) return fail(ctx, GESR_ERR_INVALID, "out is NULL");
     if (splats->n > 0) {
         const void* ptrs[6] = {out->mean, out->scale, out->quat, out->opacity, out->beta, out->sh};
@@ -500,6 +528,22 @@ gesr_status gesr_project_bwd(gesr_ctx* ctx, const gesr_splats* splats, const ges
             if (!ptrs[k] || !aligned16(ptrs[k])) return fail(ctx, GESR_ERR_INVALID, "gradient output %d invalid", k);
     }
     GESR_TRY(hip_check(ctx, hipSetDevice(ctx->device), "hipSetDevice"));
+    const BwdWorkspace ws = carve_bwd(workspace, g.vn, bins->m_cap, g.total_tiles);
+    const DevCams dc = dev_cams(cams, V, st);
+    float* g2 = grad2d ? grad2d : ws.grad2d;
+    SegReduceArgs r;
+    r.n = splats->n;
+    r.vn = (uint32_t)g.vn;
+    r.tiles_touched = proj->tiles_touched;
+    r.rect = proj->rect;
+    r.inst_base = bins->inst_base;
+    r.depth_key = proj->depth_key;
+    r.tile_cut = ws.tile_cut;
+    r.partials = ws.partials;
+    r.m_cap = bins->m_cap;
+    r.grad2d = g2;
+    r.cams = dc;
+    GESR_TRY(hip_check(ctx, launch_seg_reduce(r, (hipStream_t)stream), "seg_reduce launch"));
     ProjectBwdArgs b;
     b.n = splats->n;
     b.mean = splats->mean;
@@ -509,10 +553,7 @@ gesr_status gesr_project_bwd(gesr_ctx* ctx, const gesr_splats* splats, const ges
     b.beta = splats->beta;
     b.sh = splats->sh;
     b.tiles_touched = proj->tiles_touched;
-    b.inst_base = bins->inst_base;
-    b.partials = partials;
-    b.m_cap = bins->m_cap;
-    b.grad2d = grad2d;
+    b.grad2d = g2;
     b.g_mean = out->mean;
     b.g_scale = out->scale;
     b.g_quat = out->quat;
@@ -520,7 +561,7 @@ gesr_status gesr_project_bwd(gesr_ctx* ctx, const gesr_splats* splats, const ges
     b.g_beta = out->beta;
     b.g_sh = out->sh;
     b.st = dev_settings(st);
-    b.cams = dev_cams(cams, V, st);
+    b.cams = dc;
     GESR_TRY(hip_check(ctx, launch_project_bwd(b, st->sh_degree, (hipStream_t)stream), "project_bwd launch"));
     ctx->err.clear();
     return GESR_OK;
@@ -528,14 +569,14 @@ gesr_status gesr_project_bwd(gesr_ctx* ctx, const gesr_splats* splats, const ges
 
 gesr_status gesr_render_bwd(gesr_ctx* ctx, const gesr_splats* splats, const gesr_proj* proj, const gesr_bins* bins,
                             const gesr_camera* cams, int V, const gesr_settings* st, const float* final_T,
-                            const uint32_t* n_contrib, const float* dL_dimage, float* partials, float* grad2d,
+                            const uint32_t* n_contrib, const float* dL_dimage, void* workspace, float* grad2d,
                             const gesr_grads* out, void* stream) {
     if (!ctx) return GESR_ERR_INVALID;
     if (!splats) return fail(ctx, GESR_ERR_INVALID, "splats is NULL");
     if (!out) return fail(ctx, GESR_ERR_INVALID, "out is NULL");
-    GESR_TRY(gesr_render_bwd_tiles(ctx, proj, bins, cams, V, splats->n, st, final_T, n_contrib, dL_dimage, partials,
+    GESR_TRY(gesr_render_bwd_tiles(ctx, proj, bins, cams, V, splats->n, st, final_T, n_contrib, dL_dimage, workspace,
                                    stream));
-    return gesr_project_bwd(ctx, splats, proj, bins, cams, V, st, partials, grad2d, out, stream);
+    return gesr_project_bwd(ctx, splats, proj, bins, cams, V, st, workspace, grad2d, out, stream);
 }
 
 gesr_status gesr_l1_grad(gesr_ctx* ctx, const float* image, const float* target, uint64_t count, float scale,
@@ -554,3 +595,4 @@ gesr_status gesr_l1_grad(gesr_ctx* ctx, const float* image, const float* target,
 static_assert(sizeof(gesr::RenderArgs) < 4000, "kernel arguments too large");
 static_assert(sizeof(gesr::ProjectArgs) < 4000, "kernel arguments too large");
 static_assert(sizeof(gesr::ProjectBwdArgs) < 4000, "kernel arguments too large");
+static_assert(sizeof(gesr::SegReduceArgs) < 4000, "kernel arguments too large");

@@ -84,6 +84,24 @@ __device__ __forceinline__ float wave_sum(float x) {
     return x;
 }
 
+// Wave-wide sum with DPP row operations (no LDS traffic); the total is valid
+// in lane 63 only.  Fixed order: inclusive row sums by row_shr 1..8, then the
+// row totals are chained with row_bcast 15 and row_bcast 31.
+template <int CTRL, int ROW_MASK, int BANK_MASK>
+__device__ __forceinline__ float dpp(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, BANK_MASK, true));
+}
+__device__ __forceinline__ float wave_sum_lane63(float x) {
+    float s = x + dpp<0x111, 0xf, 0xf>(x);   // row_shr:1
+    s = s + dpp<0x112, 0xf, 0xf>(x);         // row_shr:2
+    s = s + dpp<0x113, 0xf, 0xf>(x);         // row_shr:3
+    s = s + dpp<0x114, 0xf, 0xe>(s);         // row_shr:4, banks 1..3
+    s = s + dpp<0x118, 0xf, 0xc>(s);         // row_shr:8, banks 2..3
+    s = s + dpp<0x142, 0xa, 0xf>(s);         // row_bcast:15 into rows 1, 3
+    s = s + dpp<0x143, 0xc, 0xf>(s);         // row_bcast:31 into rows 2, 3
+    return s;
+}
+
 __device__ __forceinline__ uint32_t wave_max_u32(uint32_t x) {
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) {

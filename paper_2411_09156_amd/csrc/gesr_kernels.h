@@ -23,12 +23,25 @@ struct ProjectBwdArgs {
     int n;
     const float *mean, *scale, *quat, *opacity, *beta, *sh;
     const uint32_t* tiles_touched;
-    const uint32_t* inst_base;
-    const float* partials;
-    uint64_t m_cap;  // partials hold instances [0, m_cap)
-    float* grad2d;  // nullable
+    const float* grad2d;  // [V*n][10] screen-space gradients
     float *g_mean, *g_scale, *g_quat, *g_opacity, *g_beta, *g_sh;
     DevSettings st;
+    DevCams cams;
+};
+
+// Segmented sum of the per-instance partials of each (view, splat), skipping
+// instances the render adjoint never visited (key >= its tile's cut).
+struct SegReduceArgs {
+    int n;
+    uint32_t vn;
+    const uint32_t* tiles_touched;
+    const uint32_t* rect;
+    const uint32_t* inst_base;
+    const uint32_t* depth_key;
+    const uint64_t* tile_cut;
+    const float* partials;
+    uint64_t m_cap;
+    float* grad2d;
     DevCams cams;
 };
 
@@ -50,12 +63,15 @@ struct RenderArgs {
     // backward
     const float* dL_dimage;
     float* partials;
+    const uint32_t* depth_key;
+    uint64_t* tile_cut;  // per tile: (depth_key, vi) of the first unvisited position
     DevSettings st;
     DevCams cams;
 };
 
 hipError_t launch_project(const ProjectArgs& a, int sh_degree, hipStream_t stream);
 hipError_t launch_project_bwd(const ProjectBwdArgs& a, int sh_degree, hipStream_t stream);
+hipError_t launch_seg_reduce(const SegReduceArgs& a, hipStream_t stream);
 hipError_t launch_render_fwd(const RenderArgs& a, int tile_w, int tile_h, bool counts, hipStream_t stream);
 hipError_t launch_render_bwd(const RenderArgs& a, int tile_w, int tile_h, int batch, hipStream_t stream);
 

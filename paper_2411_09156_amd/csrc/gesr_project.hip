@@ -12,8 +12,8 @@
 // loads) and every view is projected from registers.
 //
 // Adjoint: per (view, splat), a fixed-order sum of the per-instance partials
-// written by the backward renderer (atomic-free), then the chain rule through
-// the projection, accumulated over views in ascending order.
+// written by the backward renderer (atomic-free, k_seg_reduce), then the chain
+// rule through the projection, accumulated over views in ascending order.
 
 #include "gesr_device.h"
 #include "gesr_kernels.h"
@@ -355,29 +355,15 @@ __global__ __launch_bounds__(256) void k_project_bwd(ProjectBwdArgs a) {
     for (int v = 0; v < a.cams.V; ++v) {
         const size_t vi = (size_t)v * n + i;
         const uint32_t cnt = a.tiles_touched[vi];
-        if (cnt == 0) {
-            if (a.grad2d)
-                for (int k = 0; k < GESR_PARTIAL_FLOATS; ++k) a.grad2d[vi * GESR_PARTIAL_FLOATS + k] = 0.f;
-            continue;
-        }
-        // fixed-order sum of this pair's instance partials (contiguous in emission order)
+        if (cnt == 0) continue;
         float g2[GESR_PARTIAL_FLOATS];
-        for (int k = 0; k < GESR_PARTIAL_FLOATS; ++k) g2[k] = 0.f;
-        // instances past the capacity were truncated from the lists (overflow): skip them
-        const uint64_t base_i = a.inst_base[vi];
-        const uint32_t cnt_in = base_i >= a.m_cap ? 0u : (uint32_t)min<uint64_t>(cnt, a.m_cap - base_i);
-        const float* pp = a.partials + (size_t)base_i * GESR_PARTIAL_FLOATS;
-        for (uint32_t j = 0; j < cnt_in; ++j) {
-            const float2* r2 = reinterpret_cast<const float2*>(pp + (size_t)j * GESR_PARTIAL_FLOATS);
+        const float2* src = reinterpret_cast<const float2*>(a.grad2d + vi * GESR_PARTIAL_FLOATS);
 #pragma unroll
-            for (int k = 0; k < GESR_PARTIAL_FLOATS / 2; ++k) {
-                float2 t = r2[k];
-                g2[2 * k] += t.x;
-                g2[2 * k + 1] += t.y;
-            }
+        for (int k = 0; k < GESR_PARTIAL_FLOATS / 2; ++k) {
+            const float2 t2 = src[k];
+            g2[2 * k] = t2.x;
+            g2[2 * k + 1] = t2.y;
         }
-        if (a.grad2d)
-            for (int k = 0; k < GESR_PARTIAL_FLOATS; ++k) a.grad2d[vi * GESR_PARTIAL_FLOATS + k] = g2[k];
         const float du = g2[0], dv = g2[1];
 
         const DevView& w = a.cams.v[v];
@@ -512,6 +498,53 @@ __global__ __launch_bounds__(256) void k_project_bwd(ProjectBwdArgs a) {
     for (int k = 0; k < K * 3; ++k) a.g_sh[(size_t)k * n + i] = gsh[k];
 }
 
+// One wave per (view, splat): lane l sums the partials of instances
+// l, l + 64, ... that the render adjoint visited, then a fixed DPP tree adds
+// the lanes.  The order depends only on the pair's own instances, so a batch
+// of views and views rendered one at a time give identical sums.
+__global__ __launch_bounds__(256) void k_seg_reduce(SegReduceArgs a) {
+    constexpr int NP = GESR_PARTIAL_FLOATS;
+    const uint64_t vi = ((uint64_t)blockIdx.x * 256u + threadIdx.x) >> 6;
+    const uint32_t lane = __lane_id();
+    if (vi >= a.vn) return;  // uniform over the wave
+    float* out = a.grad2d + (size_t)vi * NP;
+    const uint32_t cnt = a.tiles_touched[vi];
+    float acc[NP];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) acc[k] = 0.f;
+    bool any = false;
+    if (cnt > 0) {
+        const DevView& w = a.cams.v[(uint32_t)vi / (uint32_t)a.n];
+        const uint2 r = reinterpret_cast<const uint2*>(a.rect)[vi];
+        const uint32_t tx0 = r.x & 0xFFFFu, ty0 = r.x >> 16, width = (r.y & 0xFFFFu) - tx0 + 1u;
+        const uint64_t key = ((uint64_t)a.depth_key[vi] << 32) | (uint32_t)vi;
+        const uint64_t base = a.inst_base[vi];
+        for (uint32_t j = lane; j < cnt; j += 64) {
+            const uint32_t ty = ty0 + j / width, tx = tx0 + j % width;
+            const uint32_t t = w.tile_base + ty * (uint32_t)w.tiles_x + tx;
+            if (key < a.tile_cut[t] && base + j < a.m_cap) {
+                const float2* src = reinterpret_cast<const float2*>(a.partials + (base + j) * NP);
+#pragma unroll
+                for (int k = 0; k < NP / 2; ++k) {
+                    const float2 p2 = src[k];
+                    acc[2 * k] += p2.x;
+                    acc[2 * k + 1] += p2.y;
+                }
+                any = true;
+            }
+        }
+    }
+    if (__ballot(any) == 0ull) {
+        if (lane < NP) out[lane] = 0.f;
+        return;
+    }
+#pragma unroll
+    for (int k = 0; k < NP; ++k) acc[k] = wave_sum_lane63(acc[k]);
+    if (lane == 63)
+#pragma unroll
+        for (int k = 0; k < NP; ++k) out[k] = acc[k];
+}
+
 }  // namespace
 
 hipError_t launch_project(const ProjectArgs& a, int sh_degree, hipStream_t stream) {
@@ -523,6 +556,13 @@ hipError_t launch_project(const ProjectArgs& a, int sh_degree, hipStream_t strea
         case 2: hipLaunchKernelGGL(k_project<2>, grid, block, 0, stream, a); break;
         default: hipLaunchKernelGGL(k_project<3>, grid, block, 0, stream, a); break;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_seg_reduce(const SegReduceArgs& a, hipStream_t stream) {
+    if (a.vn == 0) return hipSuccess;
+    const uint64_t threads = (uint64_t)a.vn * 64;
+    hipLaunchKernelGGL(k_seg_reduce, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, stream, a);
     return hipGetLastError();
 }
 

@@ -170,6 +170,17 @@ __global__ __launch_bounds__(TW * TH) void k_render_bwd(RenderArgs a) {
     uint32_t maxnc = 0;
     for (int w = 0; w < NW; ++w) maxnc = max(maxnc, sMax[w]);
     const uint32_t end = ti.r0 + maxnc;
+    // Positions >= end are never visited; record the (depth, index) key of the
+    // first of them so the segmented sum can tell visited instances apart
+    // (a tile list is strictly increasing in that key).
+    if (threadIdx.x == 0) {
+        uint64_t cut = ~0ull;
+        if (end < ti.r1) {
+            const uint32_t vc = a.val_sorted[end];
+            cut = ((uint64_t)a.depth_key[vc] << 32) | vc;
+        }
+        a.tile_cut[t] = cut;
+    }
 
     for (uint32_t hi = end; hi > ti.r0;) {
         const uint32_t lo = (hi - ti.r0 > (uint32_t)BATCH) ? hi - BATCH : ti.r0;
@@ -230,11 +241,11 @@ __global__ __launch_bounds__(TW * TH) void k_render_bwd(RenderArgs a) {
             }
             if (__ballot(act) != 0ull) {
 #pragma unroll
-                for (int k = 0; k < NP; ++k) gr[k] = wave_sum(gr[k]);
-                if (lane == 0)
+                for (int k = 0; k < NP; ++k) gr[k] = wave_sum_lane63(gr[k]);
+                if (lane == 63)
 #pragma unroll
                     for (int k = 0; k < NP; ++k) sRed[wave][j][k] = gr[k];
-            } else if (lane == 0) {
+            } else if (lane == 63) {
 #pragma unroll
                 for (int k = 0; k < NP; ++k) sRed[wave][j][k] = 0.f;
             }
@@ -253,16 +264,6 @@ __global__ __launch_bounds__(TW * TH) void k_render_bwd(RenderArgs a) {
         }
         __syncthreads();
         hi = lo;
-    }
-    // instances after the deepest composited position contribute nothing
-    for (uint32_t pos = end + threadIdx.x; pos < ti.r1; pos += NT) {
-        const uint32_t vi = a.val_sorted[pos];
-        const uint2 r = reinterpret_cast<const uint2*>(a.rect)[vi];
-        const uint32_t tx0 = r.x & 0xFFFFu, ty0 = r.x >> 16, tx1 = r.y & 0xFFFFu;
-        const uint32_t inst = a.inst_base[vi] + (ti.ty - ty0) * (tx1 - tx0 + 1u) + (ti.tx - tx0);
-        float2* dst = reinterpret_cast<float2*>(a.partials + (size_t)inst * NP);
-#pragma unroll
-        for (int k = 0; k < NP / 2; ++k) dst[k] = make_float2(0.f, 0.f);
     }
 }
 

@@ -214,44 +214,35 @@ class Rasterizer:
                                              ctypes.byref(cnt) if cnt is not None else None, _stream()), self.ctx)
         return out
 
+    def alloc_workspace(self, n: int, m_cap: int) -> torch.Tensor:
+        """Backward workspace (tile cuts, screen-space gradients, partials)."""
+        return torch.empty(int(self.sizes(n, m_cap).bwd_workspace_bytes), dtype=torch.uint8, device=self.device)
+
     def render_bwd(self, sp: Splats, proj: dict, bins: dict, final_T, n_contrib, dL_dimage,
                    want_grad2d: bool = False) -> dict:
-        n = sp.n
-        g = dict(mean=torch.empty_like(sp.mean), scale=torch.empty_like(sp.scale), quat=torch.empty_like(sp.quat),
-                 opacity=torch.empty_like(sp.opacity), beta=torch.empty_like(sp.beta), sh=torch.empty_like(sp.sh))
-        gc = _lib.Grads(*(g[k].data_ptr() for k in ("mean", "scale", "quat", "opacity", "beta", "sh")))
-        partials = self._empty(bins["m_cap"] * _lib.PARTIAL_FLOATS)
-        grad2d = self._empty(self.V * n * _lib.PARTIAL_FLOATS) if want_grad2d else None
-        dL = dL_dimage.contiguous()
-        self._check(self.lib.gesr_render_bwd(self.ctx, ctypes.byref(sp.to_c()), ctypes.byref(self._proj_c(proj)),
-                                             ctypes.byref(self._bins_c(bins)), self.cams_c, self.V,
-                                             ctypes.byref(self.st_c), final_T.data_ptr(), n_contrib.data_ptr(),
-                                             dL.data_ptr(), partials.data_ptr(),
-                                             grad2d.data_ptr() if grad2d is not None else None,
-                                             ctypes.byref(gc), _stream()), self.ctx)
-        if grad2d is not None:
-            g["grad2d"] = grad2d
-        return g
+        ws = self.render_bwd_tiles(proj, bins, sp.n, final_T, n_contrib, dL_dimage)
+        return self.project_bwd(sp, proj, bins, ws, want_grad2d=want_grad2d)
 
-    def render_bwd_tiles(self, proj: dict, bins: dict, n: int, final_T, n_contrib, dL_dimage, partials=None):
-        """Per-tile render adjoint only: returns the per-instance partials."""
-        if partials is None:
-            partials = self._empty(bins["m_cap"] * _lib.PARTIAL_FLOATS)
+    def render_bwd_tiles(self, proj: dict, bins: dict, n: int, final_T, n_contrib, dL_dimage, workspace=None):
+        """Per-tile render adjoint only: returns the backward workspace."""
+        if workspace is None:
+            workspace = self.alloc_workspace(n, bins["m_cap"])
+        dL = dL_dimage.contiguous()
         self._check(self.lib.gesr_render_bwd_tiles(self.ctx, ctypes.byref(self._proj_c(proj)),
                                                    ctypes.byref(self._bins_c(bins)), self.cams_c, self.V, n,
                                                    ctypes.byref(self.st_c), final_T.data_ptr(), n_contrib.data_ptr(),
-                                                   dL_dimage.data_ptr(), partials.data_ptr(), _stream()), self.ctx)
-        return partials
+                                                   dL.data_ptr(), workspace.data_ptr(), _stream()), self.ctx)
+        return workspace
 
-    def project_bwd(self, sp: Splats, proj: dict, bins: dict, partials, want_grad2d: bool = False) -> dict:
-        """Segmented sum of the partials and the projection adjoint."""
+    def project_bwd(self, sp: Splats, proj: dict, bins: dict, workspace, want_grad2d: bool = False) -> dict:
+        """Segmented sum of the visited partials and the projection adjoint."""
         g = dict(mean=torch.empty_like(sp.mean), scale=torch.empty_like(sp.scale), quat=torch.empty_like(sp.quat),
                  opacity=torch.empty_like(sp.opacity), beta=torch.empty_like(sp.beta), sh=torch.empty_like(sp.sh))
         gc = _lib.Grads(*(g[k].data_ptr() for k in ("mean", "scale", "quat", "opacity", "beta", "sh")))
         grad2d = self._empty(self.V * sp.n * _lib.PARTIAL_FLOATS) if want_grad2d else None
         self._check(self.lib.gesr_project_bwd(self.ctx, ctypes.byref(sp.to_c()), ctypes.byref(self._proj_c(proj)),
                                               ctypes.byref(self._bins_c(bins)), self.cams_c, self.V,
-                                              ctypes.byref(self.st_c), partials.data_ptr(),
+                                              ctypes.byref(self.st_c), workspace.data_ptr(),
                                               grad2d.data_ptr() if grad2d is not None else None, ctypes.byref(gc),
                                               _stream()), self.ctx)
         if grad2d is not None:
