@@ -84,7 +84,9 @@ typedef struct {
     int32_t tile_w, tile_h; /* supported: 16x16, 32x16, 32x32, 8x8 */
     int32_t batch;          /* splats staged per LDS batch in the renderers (0 = auto) */
     int32_t radix_bits;     /* digit width of the instance sort, 4..8 */
-    int32_t reserved[4];
+    int32_t variant;        /* 16x16 renderers: 0 = one wave per tile (4 px per lane),
+                               1 = one workgroup of four waves per tile */
+    int32_t reserved[3];
 } gesr_settings;
 
 void gesr_default_settings(gesr_settings* s);

@@ -42,7 +42,8 @@ class Settings(ctypes.Structure):
                 ("alpha_min", ctypes.c_float), ("alpha_max", ctypes.c_float), ("t_min", ctypes.c_float),
                 ("blur", ctypes.c_float), ("znear", ctypes.c_float), ("clip_fac", ctypes.c_float),
                 ("bg", ctypes.c_float * 3), ("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32),
-                ("batch", ctypes.c_int32), ("radix_bits", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+                ("batch", ctypes.c_int32), ("radix_bits", ctypes.c_int32), ("variant", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 3)]
 
 
 class Splats(ctypes.Structure):

@@ -70,12 +70,14 @@ gesr_status check_settings(gesr_ctx* ctx, const gesr_settings* st) {
     if (st->radix_bits < 4 || st->radix_bits > 8)
         return fail(ctx, GESR_ERR_INVALID, "radix_bits %d outside 4..8", st->radix_bits);
     if (st->batch < 0) return fail(ctx, GESR_ERR_INVALID, "batch must be >= 0");
+    if (st->variant < 0 || st->variant > 1) return fail(ctx, GESR_ERR_INVALID, "variant must be 0 or 1");
     return GESR_OK;
 }
 
 struct Geometry {
     uint64_t total_tiles = 0, total_pixels = 0;
     uint64_t vn = 0;
+    uint64_t grid_len = 0;  // cells of the per-view tile counting grids
 };
 
 gesr_status check_cams(gesr_ctx* ctx, const gesr_camera* cams, int V, int n, const gesr_settings* st, Geometry* g) {
@@ -83,6 +85,7 @@ gesr_status check_cams(gesr_ctx* ctx, const gesr_camera* cams, int V, int n, con
     if (V < 1 || V > GESR_MAX_VIEWS) return fail(ctx, GESR_ERR_INVALID, "V = %d outside 1..%d", V, GESR_MAX_VIEWS);
     if (n < 0) return fail(ctx, GESR_ERR_INVALID, "n = %d is negative", n);
     uint64_t tiles = 0, pix = 0;
+    g->grid_len = 0;
     for (int v = 0; v < V; ++v) {
         const gesr_camera& c = cams[v];
         if (c.width < 1 || c.height < 1) return fail(ctx, GESR_ERR_INVALID, "view %d: width/height must be >= 1", v);
@@ -98,6 +101,7 @@ gesr_status check_cams(gesr_ctx* ctx, const gesr_camera* cams, int V, int n, con
         if (tx > 0xFFFFu || ty > 0xFFFFu) return fail(ctx, GESR_ERR_INVALID, "view %d: too many tiles per axis", v);
         tiles += tx * ty;
         pix += (uint64_t)c.width * (uint64_t)c.height;
+        g->grid_len += (tx + 1) * (ty + 1);
     }
     if (3 * pix >= (1ull << 32)) return fail(ctx, GESR_ERR_INVALID, "3 * total pixels must be < 2^32");
     if (tiles >= (1ull << 31)) return fail(ctx, GESR_ERR_INVALID, "too many tiles");
@@ -124,6 +128,7 @@ DevSettings dev_settings(const gesr_settings* s) {
     d.tile_w = s->tile_w;
     d.tile_h = s->tile_h;
     d.sh_degree = s->sh_degree;
+    d.variant = s->variant;
     return d;
 }
 
@@ -131,7 +136,7 @@ DevCams dev_cams(const gesr_camera* cams, int V, const gesr_settings* st) {
     DevCams d;
     memset(&d, 0, sizeof d);
     d.V = V;
-    uint32_t tb = 0, pb = 0;
+    uint32_t tb = 0, pb = 0, gb = 0;
     for (int v = 0; v < V; ++v) {
         const gesr_camera& c = cams[v];
         DevView& w = d.v[v];
@@ -150,8 +155,10 @@ DevCams dev_cams(const gesr_camera* cams, int V, const gesr_settings* st) {
         w.tiles_y = (c.height + st->tile_h - 1) / st->tile_h;
         w.tile_base = tb;
         w.pix_base = pb;
+        w.grid_base = gb;
         tb += (uint32_t)(w.tiles_x * w.tiles_y);
         pb += (uint32_t)(c.width * c.height);
+        gb += (uint32_t)((w.tiles_x + 1) * (w.tiles_y + 1));
     }
     return d;
 }
@@ -162,13 +169,16 @@ struct BinScratch {
     uint32_t *cnt_sorted, *offsets;                       // [V*n]
     uint32_t *i_keys, *i_vals;                            // instance sort partner, [m_cap]
     uint32_t *w_keys_a, *w_vals_a, *w_keys_b;             // worklist sort, [T]
+    uint32_t *tile_count, *tile_start;                    // [T]
+    int* diff;                                            // counting grids
+    uint64_t diff_len;
     uint32_t *block_hist, *scan_partials;
     size_t bytes;
 };
 
 uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
 
-BinScratch carve(void* base, uint64_t vn, uint64_t m_cap, uint64_t T) {
+BinScratch carve(void* base, uint64_t vn, uint64_t m_cap, uint64_t T, uint64_t grid_len) {
     BinScratch s;
     size_t off = 0;
     char* b = (char*)base;
@@ -190,6 +200,10 @@ BinScratch carve(void* base, uint64_t vn, uint64_t m_cap, uint64_t T) {
     s.w_keys_a = take(T1);
     s.w_vals_a = take(T1);
     s.w_keys_b = take(T1);
+    s.tile_count = take(T1);
+    s.tile_start = take(T1);
+    s.diff_len = grid_len > 0 ? grid_len : 1;
+    s.diff = (int*)take(s.diff_len);
     uint64_t maxcount = vn1 > m_cap ? vn1 : m_cap;
     if (T1 > maxcount) maxcount = T1;
     const uint64_t hist = 256ull * ceil_div(maxcount, SORT_TILE);
@@ -324,7 +338,7 @@ gesr_status gesr_query_sizes(gesr_ctx* ctx, const gesr_camera* cams, int V, int 
     Geometry g;
     GESR_TRY(check_cams(ctx, cams, V, n, st, &g));
     if (m_cap < 1 || m_cap >= (1ull << 32)) return fail(ctx, GESR_ERR_INVALID, "m_cap must be in [1, 2^32)");
-    BinScratch s = carve(nullptr, g.vn, m_cap, g.total_tiles);
+    BinScratch s = carve(nullptr, g.vn, m_cap, g.total_tiles, g.grid_len);
     out->total_tiles = g.total_tiles;
     out->total_pixels = g.total_pixels;
     out->bin_scratch_bytes = s.bytes;
@@ -370,7 +384,7 @@ gesr_status gesr_bin(gesr_ctx* ctx, const gesr_proj* proj, const gesr_camera* ca
     GESR_TRY(check_cams(ctx, cams, V, n, st, &g));
     GESR_TRY(check_proj(ctx, proj));
     GESR_TRY(check_bins(ctx, bins, true));
-    BinScratch s = carve(bins->scratch, g.vn, bins->m_cap, g.total_tiles);
+    BinScratch s = carve(bins->scratch, g.vn, bins->m_cap, g.total_tiles, g.grid_len);
     if (bins->scratch_bytes < s.bytes)
         return fail(ctx, GESR_ERR_INVALID, "bins->scratch_bytes %zu < required %zu", bins->scratch_bytes, s.bytes);
     hipStream_t strm = (hipStream_t)stream;
@@ -414,7 +428,7 @@ gesr_status gesr_bin(gesr_ctx* ctx, const gesr_proj* proj, const gesr_camera* ca
     }
     GESR_TRY(hip_check(ctx,
                        launch_duplicate(order, s.offsets, g.vn, n, proj->tiles_touched, proj->rect, dc, bins->m_cap,
-                                        dup_keys, dup_vals, bins->inst_base, strm),
+                                        bins->counters, dup_keys, dup_vals, bins->inst_base, strm),
                        "duplicate"));
     if (passes > 0) {
         GESR_TRY(hip_check(ctx,
@@ -422,9 +436,15 @@ gesr_status gesr_bin(gesr_ctx* ctx, const gesr_proj* proj, const gesr_camera* ca
                                       st->radix_bits, ib, &in_b, strm),
                            "tile sort"));
     }
-    // 4. per-tile ranges
-    GESR_TRY(hip_check(ctx, launch_fill_u32(bins->ranges, 0u, 2 * T, strm), "range fill"));
-    GESR_TRY(hip_check(ctx, launch_ranges(bins->tile_sorted, bins->counters + 2, bins->m_cap, bins->ranges, strm),
+    // 4. per-tile ranges from per-tile counts (counting grids of the rectangles)
+    GESR_TRY(hip_check(ctx,
+                       launch_tile_counts(proj->tiles_touched, proj->rect, g.vn, n, dc, s.diff, s.diff_len,
+                                          s.tile_count, strm),
+                       "tile counts"));
+    GESR_TRY(hip_check(ctx, scan_exclusive(s.tile_count, s.tile_start, T, s.scan_partials, nullptr, strm),
+                       "tile count scan"));
+    GESR_TRY(hip_check(ctx, launch_ranges_from_counts(s.tile_count, s.tile_start, T, bins->counters + 2,
+                                                      bins->ranges, strm),
                        "ranges"));
     // 5. worklist: tiles by decreasing list length
     GESR_TRY(hip_check(ctx, launch_worklist_keys(bins->ranges, T, s.w_keys_b, strm), "worklist keys"));

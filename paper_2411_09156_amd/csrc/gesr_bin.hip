@@ -156,13 +156,19 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_hist(const uint32_t* key
     const uint32_t lane = __lane_id(), wave = threadIdx.x / 64;
     const uint64_t base = (uint64_t)blockIdx.x * SORT_TILE + wave * (64 * SORT_ITEMS);
     if ((uint64_t)blockIdx.x * SORT_TILE < n) {
+        // issue every load of the wave's chunk before any ranking work
+        uint32_t k[SORT_ITEMS];
+#pragma unroll
+        for (int r = 0; r < SORT_ITEMS; ++r) {
+            const uint64_t idx = base + r * 64 + lane;
+            k[r] = idx < n ? keys[idx] : 0u;
+        }
+#pragma unroll
         for (int r = 0; r < SORT_ITEMS; ++r) {
             const uint64_t idx = base + r * 64 + lane;
             const bool valid = idx < n;
-            const uint32_t key = valid ? keys[idx] : 0u;
-            const uint32_t digit = (key >> shift) & (RADIX - 1);
+            const uint32_t digit = (k[r] >> shift) & (RADIX - 1);
             const uint64_t vmask = __ballot(valid);
-            if (vmask == 0) break;
             const uint64_t peers = match_digit<BITS>(digit, vmask);
             if (valid && lane == (uint32_t)__ffsll((unsigned long long)peers) - 1)
                 hist[wave][digit] += (uint32_t)__popcll(peers);
@@ -203,12 +209,18 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(const uint32_t* 
     const uint64_t base = block_start + wave * (64 * SORT_ITEMS);
     const uint64_t lt = lanemask_lt();
     uint32_t k[SORT_ITEMS], v[SORT_ITEMS], rank[SORT_ITEMS];
+    // issue every load of the wave's chunk before any ranking work
 #pragma unroll
     for (int r = 0; r < SORT_ITEMS; ++r) {
         const uint64_t idx = base + r * 64 + lane;
         const bool valid = idx < n;
         k[r] = valid ? keys_in[idx] : 0xFFFFFFFFu;
         v[r] = valid ? (vals_in ? vals_in[idx] : (uint32_t)idx) : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < SORT_ITEMS; ++r) {
+        const uint64_t idx = base + r * 64 + lane;
+        const bool valid = idx < n;
         const uint32_t digit = (k[r] >> shift) & (RADIX - 1);
         const uint64_t vmask = __ballot(valid);
         const uint64_t peers = match_digit<BITS>(digit, vmask);
@@ -276,33 +288,118 @@ __global__ __launch_bounds__(256) void k_gather_counts(const uint32_t* order, co
     if (k < count) out[k] = tiles_touched[order[k]];
 }
 
-// One thread per (view, splat) in depth order: writes the pair's instances
-// (tile-row-major over its rectangle) at its scanned offset.
+// Instance expansion, load-balanced: a block owns DUP_SPLATS consecutive
+// (view, splat) pairs in depth order and writes their instances cooperatively
+// (instance j finds its pair by binary search over the block's offsets in
+// LDS), so every store is coalesced however large the rectangles are.
+constexpr int DUP_SPLATS = 256;
+
 __global__ __launch_bounds__(256) void k_duplicate(const uint32_t* order, const uint32_t* offsets, uint64_t count,
                                                    int n, const uint32_t* tiles_touched, const uint32_t* rect,
-                                                   DevCams cams, uint64_t m_cap, uint32_t* keys, uint32_t* vals,
-                                                   uint32_t* inst_base) {
-    const uint64_t k = (uint64_t)blockIdx.x * 256 + threadIdx.x;
-    if (k >= count) return;
-    const uint32_t vi = order[k];
-    const uint32_t off = offsets[k];
-    inst_base[vi] = off;
-    const uint32_t cnt = tiles_touched[vi];
-    if (cnt == 0) return;
-    const int v = (int)(vi / (uint32_t)n);
-    const DevView& w = cams.v[v];
+                                                   DevCams cams, uint64_t m_cap, const uint32_t* total,
+                                                   uint32_t* keys, uint32_t* vals, uint32_t* inst_base) {
+    __shared__ uint32_t s_off[DUP_SPLATS + 1];
+    __shared__ uint32_t s_vi[DUP_SPLATS];
+    __shared__ uint32_t s_r0[DUP_SPLATS];   // tx0 | ty0 << 16
+    __shared__ uint32_t s_w[DUP_SPLATS];    // rectangle width in tiles
+    __shared__ uint32_t s_row[DUP_SPLATS];  // tile_base of the view
+    __shared__ uint32_t s_tx[DUP_SPLATS];   // tiles_x of the view
+    const uint64_t k0 = (uint64_t)blockIdx.x * DUP_SPLATS;
+    const uint64_t k = k0 + threadIdx.x;
+    const uint32_t m_total = *total;
+    if (k < count) {
+        const uint32_t vi = order[k];
+        const uint32_t off = offsets[k];
+        inst_base[vi] = off;
+        s_off[threadIdx.x] = off;
+        s_vi[threadIdx.x] = vi;
+        const uint2 r = reinterpret_cast<const uint2*>(rect)[vi];
+        s_r0[threadIdx.x] = r.x;
+        s_w[threadIdx.x] = (r.y & 0xFFFFu) - (r.x & 0xFFFFu) + 1u;
+        const DevView& w = cams.v[vi / (uint32_t)n];
+        s_row[threadIdx.x] = w.tile_base;
+        s_tx[threadIdx.x] = (uint32_t)w.tiles_x;
+    } else {
+        s_off[threadIdx.x] = m_total;
+    }
+    if (threadIdx.x == 0) s_off[DUP_SPLATS] = (k0 + DUP_SPLATS < count) ? offsets[k0 + DUP_SPLATS] : m_total;
+    __syncthreads();
+    const uint64_t begin = s_off[0];
+    const uint64_t end = min<uint64_t>(s_off[DUP_SPLATS], m_cap);
+    for (uint64_t j = begin + threadIdx.x; j < end; j += 256) {
+        // largest l with s_off[l] <= j (pairs with no instances are skipped over)
+        int lo = 0, hi = DUP_SPLATS;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if ((uint64_t)s_off[mid] <= j) lo = mid;
+            else hi = mid;
+        }
+        const uint32_t q = (uint32_t)(j - s_off[lo]);
+        const uint32_t w = s_w[lo];
+        const uint32_t r0 = s_r0[lo];
+        const uint32_t ty = (r0 >> 16) + q / w, tx = (r0 & 0xFFFFu) + q % w;
+        keys[j] = s_row[lo] + ty * s_tx[lo] + tx;
+        vals[j] = s_vi[lo];
+    }
+}
+
+// Per-tile instance counts from the rectangles: +1/-1 at the four corners of
+// each rectangle in a per-view (tiles_y + 1) x (tiles_x + 1) difference grid,
+// then a 2-D prefix sum (k_tile_counts).  Integer atomics: exact and
+// order-independent.
+__global__ __launch_bounds__(256) void k_rect_corners(const uint32_t* tiles_touched, const uint32_t* rect,
+                                                      uint64_t count, int n, DevCams cams, int* diff) {
+    const uint64_t vi = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    if (vi >= count || tiles_touched[vi] == 0) return;
+    const uint32_t v = (uint32_t)vi / (uint32_t)n;
+    const uint32_t gx = (uint32_t)cams.v[v].tiles_x + 1u;
+    int* g = diff + cams.v[v].grid_base;
     const uint2 r = reinterpret_cast<const uint2*>(rect)[vi];
-    const uint32_t tx0 = r.x & 0xFFFFu, ty0 = r.x >> 16, tx1 = r.y & 0xFFFFu, ty1 = r.y >> 16;
-    uint64_t j = off;
-    for (uint32_t ty = ty0; ty <= ty1; ++ty) {
-        const uint32_t row = w.tile_base + ty * (uint32_t)w.tiles_x;
-        for (uint32_t tx = tx0; tx <= tx1; ++tx, ++j) {
-            if (j < m_cap) {
-                keys[j] = row + tx;
-                vals[j] = vi;
-            }
+    const uint32_t tx0 = r.x & 0xFFFFu, ty0 = r.x >> 16, tx1 = (r.y & 0xFFFFu) + 1u, ty1 = (r.y >> 16) + 1u;
+    atomicAdd(&g[ty0 * gx + tx0], 1);
+    atomicAdd(&g[ty0 * gx + tx1], -1);
+    atomicAdd(&g[ty1 * gx + tx0], -1);
+    atomicAdd(&g[ty1 * gx + tx1], 1);
+}
+
+// One block per view: row prefix sums, then column prefix sums, of the view's
+// difference grid give each tile's instance count.
+__global__ __launch_bounds__(256) void k_tile_counts(DevCams cams, int* diff, uint32_t* counts) {
+    const int v = blockIdx.x;
+    const DevView& w = cams.v[v];
+    const int gx = w.tiles_x + 1;
+    int* g = diff + w.grid_base;
+    for (int y = threadIdx.x; y < w.tiles_y; y += 256) {
+        int run = 0;
+        for (int x = 0; x < w.tiles_x; ++x) {
+            run += g[y * gx + x];
+            g[y * gx + x] = run;
         }
     }
+    __syncthreads();
+    for (int x = threadIdx.x; x < w.tiles_x; x += 256) {
+        int run = 0;
+        for (int y = 0; y < w.tiles_y; ++y) {
+            run += g[y * gx + x];
+            counts[w.tile_base + (uint32_t)(y * w.tiles_x + x)] = (uint32_t)run;
+        }
+    }
+}
+
+// ranges[t] = [start, start + count), clamped to the instances actually listed
+// (min(M, m_cap)); when the capacity overflowed the lists are incomplete and
+// only memory safety is kept.
+__global__ __launch_bounds__(256) void k_ranges_from_counts(const uint32_t* counts, const uint32_t* starts,
+                                                            uint64_t total_tiles, const uint32_t* listed,
+                                                            uint32_t* ranges) {
+    const uint64_t t = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= total_tiles) return;
+    const uint32_t m = *listed;
+    const uint32_t c = counts[t];
+    const uint32_t s0 = starts[t];
+    const uint32_t s1 = s0 + c;
+    // empty tiles get (0, 0)
+    reinterpret_cast<uint2*>(ranges)[t] = c == 0 ? make_uint2(0u, 0u) : make_uint2(s0 < m ? s0 : m, s1 < m ? s1 : m);
 }
 
 __global__ void k_set_counters(uint32_t* c, uint64_t m_cap) {
@@ -318,20 +415,11 @@ __global__ __launch_bounds__(256) void k_fill_u32(uint32_t* p, uint32_t value, u
     if (k < count) p[k] = value;
 }
 
-__global__ __launch_bounds__(256) void k_ranges(const uint32_t* tiles, const uint32_t* count_dev, uint32_t* ranges) {
-    const uint32_t m = *count_dev;
-    const uint32_t k = blockIdx.x * 256 + threadIdx.x;
-    if (k >= m) return;
-    const uint32_t t = tiles[k];
-    if (k == 0 || tiles[k - 1] != t) ranges[2 * t] = k;
-    if (k + 1 == m || tiles[k + 1] != t) ranges[2 * t + 1] = k + 1;
-}
-
 // Worklist key: longer lists first (descending length, ties by tile id).
 __global__ __launch_bounds__(256) void k_worklist_keys(const uint32_t* ranges, uint64_t total_tiles, uint32_t* keys) {
     const uint64_t t = (uint64_t)blockIdx.x * 256 + threadIdx.x;
     if (t >= total_tiles) return;
-    const uint32_t len = ranges[2 * t + 1] - ranges[2 * t];
+    const uint32_t len = ranges[2 * t + 1] - ranges[2 * t];  // list length as listed
     keys[t] = 0xFFFFu - (len < 0xFFFFu ? len : 0xFFFFu);
 }
 
@@ -404,10 +492,31 @@ hipError_t launch_gather_counts(const uint32_t* order, const uint32_t* tiles_tou
 
 hipError_t launch_duplicate(const uint32_t* order, const uint32_t* offsets, uint64_t count, int n,
                             const uint32_t* tiles_touched, const uint32_t* rect, const DevCams& cams,
-                            uint64_t m_cap, uint32_t* keys, uint32_t* vals, uint32_t* inst_base, hipStream_t stream) {
+                            uint64_t m_cap, const uint32_t* total, uint32_t* keys, uint32_t* vals,
+                            uint32_t* inst_base, hipStream_t stream) {
     if (count == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_duplicate, grid_for(count), dim3(256), 0, stream, order, offsets, count, n, tiles_touched,
-                       rect, cams, m_cap, keys, vals, inst_base);
+    hipLaunchKernelGGL(k_duplicate, dim3((unsigned)((count + DUP_SPLATS - 1) / DUP_SPLATS)), dim3(256), 0, stream,
+                       order, offsets, count, n, tiles_touched, rect, cams, m_cap, total, keys, vals, inst_base);
+    return hipGetLastError();
+}
+
+hipError_t launch_tile_counts(const uint32_t* tiles_touched, const uint32_t* rect, uint64_t count, int n,
+                              const DevCams& cams, int* diff, uint64_t diff_len, uint32_t* counts,
+                              hipStream_t stream) {
+    hipLaunchKernelGGL(k_fill_u32, grid_for(diff_len), dim3(256), 0, stream, reinterpret_cast<uint32_t*>(diff), 0u,
+                       diff_len);
+    if (count > 0)
+        hipLaunchKernelGGL(k_rect_corners, grid_for(count), dim3(256), 0, stream, tiles_touched, rect, count, n,
+                           cams, diff);
+    hipLaunchKernelGGL(k_tile_counts, dim3((unsigned)cams.V), dim3(256), 0, stream, cams, diff, counts);
+    return hipGetLastError();
+}
+
+hipError_t launch_ranges_from_counts(const uint32_t* counts, const uint32_t* starts, uint64_t total_tiles,
+                                     const uint32_t* listed, uint32_t* ranges, hipStream_t stream) {
+    if (total_tiles == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ranges_from_counts, grid_for(total_tiles), dim3(256), 0, stream, counts, starts, total_tiles,
+                       listed, ranges);
     return hipGetLastError();
 }
 
@@ -419,13 +528,6 @@ hipError_t launch_set_counters(uint32_t* counters, uint64_t m_cap, hipStream_t s
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, uint64_t count, hipStream_t stream) {
     if (count == 0) return hipSuccess;
     hipLaunchKernelGGL(k_fill_u32, grid_for(count), dim3(256), 0, stream, p, value, count);
-    return hipGetLastError();
-}
-
-hipError_t launch_ranges(const uint32_t* tiles, const uint32_t* count_dev, uint64_t m_cap, uint32_t* ranges,
-                         hipStream_t stream) {
-    if (m_cap == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_ranges, grid_for(m_cap), dim3(256), 0, stream, tiles, count_dev, ranges);
     return hipGetLastError();
 }
 

@@ -18,6 +18,7 @@ struct DevView {
     int tiles_x, tiles_y;
     uint32_t tile_base;  // first global tile id of the view
     uint32_t pix_base;   // first pixel of the view in the concatenated outputs
+    uint32_t grid_base;  // offset of the view's (tiles_y + 1) x (tiles_x + 1) counting grid
 };
 
 struct DevCams {
@@ -35,6 +36,7 @@ struct DevSettings {
     float bg[3];
     int tile_w, tile_h;
     int sh_degree;
+    int variant;  // renderer variant for 16x16 tiles: 0 = one wave per tile, 1 = four waves per tile
 };
 
 constexpr float kLn2 = 0.693147180559945309f;

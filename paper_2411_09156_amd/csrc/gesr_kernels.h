@@ -108,11 +108,17 @@ hipError_t launch_gather_counts(const uint32_t* order, const uint32_t* tiles_tou
                                 hipStream_t stream);
 hipError_t launch_duplicate(const uint32_t* order, const uint32_t* offsets, uint64_t count, int n,
                             const uint32_t* tiles_touched, const uint32_t* rect, const DevCams& cams,
-                            uint64_t m_cap, uint32_t* keys, uint32_t* vals, uint32_t* inst_base, hipStream_t stream);
+                            uint64_t m_cap, const uint32_t* total, uint32_t* keys, uint32_t* vals,
+                            uint32_t* inst_base, hipStream_t stream);
+// Per-tile instance counts (difference grid of rectangle corners, 2-D prefix);
+// view v's (tiles_y + 1) x (tiles_x + 1) grid starts at cams.v[v].grid_base.
+hipError_t launch_tile_counts(const uint32_t* tiles_touched, const uint32_t* rect, uint64_t count, int n,
+                              const DevCams& cams, int* diff, uint64_t diff_len, uint32_t* counts,
+                              hipStream_t stream);
+hipError_t launch_ranges_from_counts(const uint32_t* counts, const uint32_t* starts, uint64_t total_tiles,
+                                     const uint32_t* listed, uint32_t* ranges, hipStream_t stream);
 hipError_t launch_set_counters(uint32_t* counters, uint64_t m_cap, hipStream_t stream);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, uint64_t count, hipStream_t stream);
-hipError_t launch_ranges(const uint32_t* tiles, const uint32_t* count_dev, uint64_t m_cap, uint32_t* ranges,
-                         hipStream_t stream);
 hipError_t launch_worklist_keys(const uint32_t* ranges, uint64_t total_tiles, uint32_t* keys, hipStream_t stream);
 hipError_t launch_l1_grad(const float* image, const float* target, uint64_t count, float scale, float* grad,
                           hipStream_t stream);

@@ -267,6 +267,231 @@ __global__ __launch_bounds__(TW * TH) void k_render_bwd(RenderArgs a) {
     }
 }
 
+// Forward, one wave per 16x16 tile with 4 pixels per lane (one per 8x8
+// quadrant): a staged splat's LDS reads serve 256 pixels; the wave leaves the
+// tile once all its pixels have terminated.
+template <bool COUNT>
+__global__ __launch_bounds__(64) void k_render_fwd_wave16(RenderArgs a) {
+    constexpr int B = 64;
+    __shared__ float4 sA[B], sB[B], sC[B];
+    const uint32_t t = a.worklist[blockIdx.x];
+    const DevSettings& st = a.st;
+    const uint32_t lane = __lane_id();
+    const int v = view_of_tile(a.cams, t);
+    const DevView& w = a.cams.v[v];
+    const uint32_t lt = t - w.tile_base;
+    const uint32_t tx = lt % (uint32_t)w.tiles_x, ty = lt / (uint32_t)w.tiles_x;
+    const uint2 rg = reinterpret_cast<const uint2*>(a.ranges)[t];
+    const uint32_t r0 = rg.x, r1 = rg.y;
+
+    float px[4], py[4], T[4], cr[4], cg[4], cb[4];
+    uint32_t contrib[4], listed[4], hit[4];
+    bool done[4], inside[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int x = (int)tx * 16 + (q & 1) * 8 + (int)(lane & 7);
+        const int y = (int)ty * 16 + (q >> 1) * 8 + (int)(lane >> 3);
+        px[q] = (float)x + 0.5f;
+        py[q] = (float)y + 0.5f;
+        T[q] = 1.0f;
+        cr[q] = cg[q] = cb[q] = 0.f;
+        contrib[q] = listed[q] = hit[q] = 0;
+        inside[q] = x < w.W && y < w.H;
+        done[q] = !inside[q];
+    }
+    for (uint32_t base = r0; base < r1; base += B) {
+        const bool all_done = done[0] && done[1] && done[2] && done[3];
+        if (__ballot(!all_done) == 0ull) break;
+        const uint32_t pos = base + lane;
+        if (pos < r1) stage_record(a.rec, a.val_sorted[pos], sA[lane], sB[lane], sC[lane]);
+        __syncthreads();
+        const int cnt = (int)min<uint32_t>(B, r1 - base);
+        for (int j = 0; j < cnt; ++j) {
+            const float4 ra = sA[j];
+            const float4 rb = sB[j];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (done[q]) continue;
+                Fragment f;
+                const float qq = ges_q(ra, rb.x, px[q], py[q], f);
+                if (COUNT) ++listed[q];
+                if (qq > rb.w) continue;  // beyond the alpha_min footprint
+                ges_alpha(qq, rb.z, rb.y, st, f);
+                if (f.alpha < st.alpha_min) continue;
+                if (COUNT) ++hit[q];
+                const float Tn = T[q] * (1.0f - f.alpha);
+                if (Tn < st.t_min) {
+                    done[q] = true;
+                    continue;
+                }
+                const float4 rc = sC[j];
+                const float wgt = f.alpha * T[q];
+                cr[q] = fmaf(rc.x, wgt, cr[q]);
+                cg[q] = fmaf(rc.y, wgt, cg[q]);
+                cb[q] = fmaf(rc.z, wgt, cb[q]);
+                T[q] = Tn;
+                contrib[q] = base + (uint32_t)j + 1u - r0;
+            }
+        }
+        __syncthreads();
+    }
+    const uint32_t ch = (uint32_t)w.W * (uint32_t)w.H;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        if (!inside[q]) continue;
+        const int x = (int)tx * 16 + (q & 1) * 8 + (int)(lane & 7);
+        const int y = (int)ty * 16 + (q >> 1) * 8 + (int)(lane >> 3);
+        const uint32_t local = (uint32_t)y * (uint32_t)w.W + (uint32_t)x;
+        const uint32_t pix = w.pix_base + local, img = 3u * w.pix_base + local;
+        a.image[img] = fmaf(T[q], st.bg[0], cr[q]);
+        a.image[img + ch] = fmaf(T[q], st.bg[1], cg[q]);
+        a.image[img + 2 * ch] = fmaf(T[q], st.bg[2], cb[q]);
+        a.final_T[pix] = T[q];
+        a.n_contrib[pix] = contrib[q];
+        if (COUNT) {
+            a.n_listed[pix] = listed[q];
+            a.n_hit[pix] = hit[q];
+        }
+    }
+}
+
+// Backward, one wave per 16x16 tile: lane l owns pixel (l & 7, l >> 3) of each
+// 8x8 quadrant (4 pixels per lane), so a staged splat's LDS reads and its
+// 10-value wave reduction serve 256 pixels, and no cross-wave reduction or
+// workgroup barrier beyond the wave itself is needed.
+__global__ __launch_bounds__(64) void k_render_bwd_wave16(RenderArgs a) {
+    constexpr int NP = GESR_PARTIAL_FLOATS;
+    constexpr int B = 64;
+    __shared__ float4 sA[B], sB[B], sC[B];
+    __shared__ uint32_t sInst[B];
+    __shared__ float sRed[B][NP + 1];
+
+    const uint32_t t = a.worklist[blockIdx.x];
+    const DevSettings& st = a.st;
+    const uint32_t lane = __lane_id();
+    const int v = view_of_tile(a.cams, t);
+    const DevView& w = a.cams.v[v];
+    const uint32_t lt = t - w.tile_base;
+    const uint32_t tx = lt % (uint32_t)w.tiles_x, ty = lt / (uint32_t)w.tiles_x;
+    const uint2 rg = reinterpret_cast<const uint2*>(a.ranges)[t];
+    const uint32_t r0 = rg.x, r1 = rg.y;
+    const uint32_t ch = (uint32_t)w.W * (uint32_t)w.H;
+
+    float px[4], py[4], T[4], g0[4], g1[4], g2[4], Br[4], Bg[4], Bb[4];
+    uint32_t nc[4];
+    uint32_t mymax = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int x = (int)tx * 16 + (q & 1) * 8 + (int)(lane & 7);
+        const int y = (int)ty * 16 + (q >> 1) * 8 + (int)(lane >> 3);
+        px[q] = (float)x + 0.5f;
+        py[q] = (float)y + 0.5f;
+        Br[q] = st.bg[0];
+        Bg[q] = st.bg[1];
+        Bb[q] = st.bg[2];
+        T[q] = 0.f;
+        g0[q] = g1[q] = g2[q] = 0.f;
+        nc[q] = 0;
+        if (x < w.W && y < w.H) {
+            const uint32_t local = (uint32_t)y * (uint32_t)w.W + (uint32_t)x;
+            const uint32_t pix = w.pix_base + local, img = 3u * w.pix_base + local;
+            T[q] = a.final_T[pix];
+            nc[q] = a.n_contrib[pix];
+            g0[q] = a.dL_dimage[img];
+            g1[q] = a.dL_dimage[img + ch];
+            g2[q] = a.dL_dimage[img + 2 * ch];
+        }
+        mymax = max(mymax, nc[q]);
+    }
+    const uint32_t maxnc = wave_max_u32(mymax);
+    const uint32_t end = r0 + maxnc;
+    if (lane == 0) {
+        uint64_t cut = ~0ull;
+        if (end < r1) {
+            const uint32_t vc = a.val_sorted[end];
+            cut = ((uint64_t)a.depth_key[vc] << 32) | vc;
+        }
+        a.tile_cut[t] = cut;
+    }
+
+    for (uint32_t hi = end; hi > r0;) {
+        const uint32_t lo = (hi - r0 > (uint32_t)B) ? hi - B : r0;
+        const int cnt = (int)(hi - lo);
+        if ((int)lane < cnt) {
+            const uint32_t pos = hi - 1u - lane;
+            const uint32_t vi = a.val_sorted[pos];
+            stage_record(a.rec, vi, sA[lane], sB[lane], sC[lane]);
+            const uint2 r = reinterpret_cast<const uint2*>(a.rect)[vi];
+            const uint32_t tx0 = r.x & 0xFFFFu, ty0 = r.x >> 16, tx1 = r.y & 0xFFFFu;
+            sInst[lane] = a.inst_base[vi] + (ty - ty0) * (tx1 - tx0 + 1u) + (tx - tx0);
+        }
+        __syncthreads();
+        for (int j = 0; j < cnt; ++j) {
+            const uint32_t prel = hi - 1u - (uint32_t)j - r0;  // 0-based list position
+            const float4 ra = sA[j];
+            const float4 rb = sB[j];
+            float gr[NP];
+#pragma unroll
+            for (int k = 0; k < NP; ++k) gr[k] = 0.f;
+            bool act = false;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (prel >= nc[q]) continue;
+                Fragment f;
+                const float qq = ges_q(ra, rb.x, px[q], py[q], f);
+                if (qq > rb.w) continue;
+                ges_alpha(qq, rb.z, rb.y, st, f);
+                if (f.alpha < st.alpha_min) continue;
+                act = true;
+                const float4 rc = sC[j];
+                const float Tk = T[q] * hw_rcp(1.0f - f.alpha);
+                const float aT = f.alpha * Tk;
+                gr[7] += aT * g0[q];
+                gr[8] += aT * g1[q];
+                gr[9] += aT * g2[q];
+                const float dLda = Tk * ((rc.x - Br[q]) * g0[q] + (rc.y - Bg[q]) * g1[q] + (rc.z - Bb[q]) * g2[q]);
+                Br[q] = fmaf(f.alpha, rc.x - Br[q], Br[q]);
+                Bg[q] = fmaf(f.alpha, rc.y - Bg[q], Bg[q]);
+                Bb[q] = fmaf(f.alpha, rc.z - Bb[q], Bb[q]);
+                T[q] = Tk;
+                if (f.oG <= st.alpha_max) {
+                    gr[5] += dLda * f.G;
+                    const float dLdG = dLda * rb.y;
+                    if (f.q > 1e-30f) {
+                        const float kGP = -st.kappa * f.G * f.P;
+                        const float dLdq = dLdG * kGP * rb.z * hw_rcp(f.q);
+                        gr[6] += dLdG * kGP * 0.5f * (f.l2q * kLn2);
+                        const float tq = 2.0f * dLdq * f.t, wq = 2.0f * dLdq * f.w;
+                        gr[0] += -tq * ra.z;
+                        gr[1] += -(tq * ra.w + wq * rb.x);
+                        gr[2] += tq * f.dx;
+                        gr[3] += tq * f.dy;
+                        gr[4] += wq * f.dy;
+                    }
+                }
+            }
+            if (__ballot(act) != 0ull) {
+#pragma unroll
+                for (int k = 0; k < NP; ++k) gr[k] = wave_sum_lane63(gr[k]);
+                if (lane == 63)
+#pragma unroll
+                    for (int k = 0; k < NP; ++k) sRed[j][k] = gr[k];
+            } else if (lane == 63) {
+#pragma unroll
+                for (int k = 0; k < NP; ++k) sRed[j][k] = 0.f;
+            }
+        }
+        __syncthreads();
+        if ((int)lane < cnt) {
+            float2* dst = reinterpret_cast<float2*>(a.partials + (size_t)sInst[lane] * NP);
+#pragma unroll
+            for (int k = 0; k < NP / 2; ++k) dst[k] = make_float2(sRed[lane][2 * k], sRed[lane][2 * k + 1]);
+        }
+        __syncthreads();
+        hi = lo;
+    }
+}
+
 template <int TW, int TH>
 hipError_t fwd_shape(const RenderArgs& a, bool counts, hipStream_t s) {
     if (counts)
@@ -286,7 +511,14 @@ hipError_t bwd_shape(const RenderArgs& a, hipStream_t s) {
 
 hipError_t launch_render_fwd(const RenderArgs& a, int tw, int th, bool counts, hipStream_t s) {
     if (a.n_items == 0) return hipSuccess;
-    if (tw == 16 && th == 16) return fwd_shape<16, 16>(a, counts, s);
+    if (tw == 16 && th == 16) {
+        if (a.st.variant == 1) return fwd_shape<16, 16>(a, counts, s);
+        if (counts)
+            hipLaunchKernelGGL(k_render_fwd_wave16<true>, dim3(a.n_items), dim3(64), 0, s, a);
+        else
+            hipLaunchKernelGGL(k_render_fwd_wave16<false>, dim3(a.n_items), dim3(64), 0, s, a);
+        return hipGetLastError();
+    }
     if (tw == 8 && th == 8) return fwd_shape<8, 8>(a, counts, s);
     if (tw == 32 && th == 16) return fwd_shape<32, 16>(a, counts, s);
     if (tw == 32 && th == 32) return fwd_shape<32, 32>(a, counts, s);
@@ -295,7 +527,11 @@ hipError_t launch_render_fwd(const RenderArgs& a, int tw, int th, bool counts, h
 
 hipError_t launch_render_bwd(const RenderArgs& a, int tw, int th, int batch, hipStream_t s) {
     if (a.n_items == 0) return hipSuccess;
-    if (tw == 16 && th == 16) return batch >= 128 ? bwd_shape<16, 16, 128>(a, s) : bwd_shape<16, 16, 64>(a, s);
+    if (tw == 16 && th == 16) {
+        if (a.st.variant == 1) return bwd_shape<16, 16, 64>(a, s);  // one workgroup of 4 waves per tile
+        hipLaunchKernelGGL(k_render_bwd_wave16, dim3(a.n_items), dim3(64), 0, s, a);
+        return hipGetLastError();
+    }
     if (tw == 8 && th == 8) return bwd_shape<8, 8, 64>(a, s);
     if (tw == 32 && th == 16) return batch >= 128 ? bwd_shape<32, 16, 128>(a, s) : bwd_shape<32, 16, 64>(a, s);
     if (tw == 32 && th == 32) return bwd_shape<32, 32, 64>(a, s);

@@ -37,6 +37,7 @@ class RasterSettings:
     tile_h: int = 16
     batch: int = 0
     radix_bits: int = 8
+    variant: int = 0
 
     def to_c(self) -> _lib.Settings:
         s = _lib.Settings()
@@ -47,6 +48,7 @@ class RasterSettings:
         for c in range(3):
             s.bg[c] = float(self.bg[c])
         s.tile_w, s.tile_h, s.batch, s.radix_bits = self.tile_w, self.tile_h, self.batch, self.radix_bits
+        s.variant = self.variant
         return s
 
 

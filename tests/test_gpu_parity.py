@@ -33,7 +33,10 @@ pytestmark = pytest.mark.gpu
 
 
 def _case(name):
-    """(scene, oracle settings) of a named parity case."""
+    """(scene, oracle settings) of a named parity case; the suffix "-v1" selects the
+    four-waves-per-tile renderers instead of the one-wave-per-tile ones."""
+    if name.endswith("-v1"):
+        return _case(name[:-3])
     if name == "tiny-d1":
         return gi.tiny_scene(0, n=12, deg=1), oracle.Settings(sh_degree=1)
     if name == "tiny-d3-2v-bg":
@@ -59,15 +62,15 @@ def _case(name):
     raise KeyError(name)
 
 
-CASES = ["tiny-d1", "tiny-d3-2v-bg", "tiny-kappa1", "plain-2k", "plain-2k-t8", "plain-2k-t32x16", "plain-2k-t32",
-         "spheres-100k", "drt-50k-8v", "surfels-40k-2v", "blobs-100k-2v"]
+CASES = ["tiny-d1", "tiny-d3-2v-bg", "tiny-kappa1", "plain-2k", "plain-2k-v1", "plain-2k-t8", "plain-2k-t32x16",
+         "plain-2k-t32", "spheres-100k", "drt-50k-8v", "drt-50k-8v-v1", "surfels-40k-2v", "blobs-100k-2v"]
 
 
 @functools.lru_cache(maxsize=1)
 def _run(name):
     scene, st = _case(name)
     log(f"[gpu] case {name}: n={scene.n} views={scene.n_views} px={scene.n_pixels}")
-    g = run_gpu(scene, st)
+    g = run_gpu(scene, st, variant=1 if name.endswith("-v1") else 0)
     log(f"[gpu] case {name}: forward done, M={g['M']}")
     return scene, st, g
 
