@@ -78,6 +78,7 @@ struct Geometry {
     uint64_t total_tiles = 0, total_pixels = 0;
     uint64_t vn = 0;
     uint64_t grid_len = 0;  // cells of the per-view tile counting grids
+    uint64_t max_cells = 0; // cells of the largest view's grid
 };
 
 gesr_status check_cams(gesr_ctx* ctx, const gesr_camera* cams, int V, int n, const gesr_settings* st, Geometry* g) {
@@ -86,6 +87,7 @@ gesr_status check_cams(gesr_ctx* ctx, const gesr_camera* cams, int V, int n, con
     if (n < 0) return fail(ctx, GESR_ERR_INVALID, "n = %d is negative", n);
     uint64_t tiles = 0, pix = 0;
     g->grid_len = 0;
+    g->max_cells = 0;
     for (int v = 0; v < V; ++v) {
         const gesr_camera& c = cams[v];
         if (c.width < 1 || c.height < 1) return fail(ctx, GESR_ERR_INVALID, "view %d: width/height must be >= 1", v);
@@ -102,7 +104,9 @@ gesr_status check_cams(gesr_ctx* ctx, const gesr_camera* cams, int V, int n, con
         tiles += tx * ty;
         pix += (uint64_t)c.width * (uint64_t)c.height;
         g->grid_len += (tx + 1) * (ty + 1);
+        if ((tx + 1) * (ty + 1) > g->max_cells) g->max_cells = (tx + 1) * (ty + 1);
     }
+
     if (3 * pix >= (1ull << 32)) return fail(ctx, GESR_ERR_INVALID, "3 * total pixels must be < 2^32");
     if (tiles >= (1ull << 31)) return fail(ctx, GESR_ERR_INVALID, "too many tiles");
     const uint64_t vn = (uint64_t)V * (uint64_t)n;
@@ -172,13 +176,14 @@ struct BinScratch {
     uint32_t *tile_count, *tile_start;                    // [T]
     int* diff;                                            // counting grids
     uint64_t diff_len;
+    int* partial_grids;                                   // per-chunk copies of the grids
     uint32_t *block_hist, *scan_partials;
     size_t bytes;
 };
 
 uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
 
-BinScratch carve(void* base, uint64_t vn, uint64_t m_cap, uint64_t T, uint64_t grid_len) {
+BinScratch carve(void* base, uint64_t vn, uint64_t m_cap, uint64_t T, uint64_t grid_len, uint64_t chunks) {
     BinScratch s;
     size_t off = 0;
     char* b = (char*)base;
@@ -204,6 +209,7 @@ BinScratch carve(void* base, uint64_t vn, uint64_t m_cap, uint64_t T, uint64_t g
     s.tile_start = take(T1);
     s.diff_len = grid_len > 0 ? grid_len : 1;
     s.diff = (int*)take(s.diff_len);
+    s.partial_grids = (int*)take(s.diff_len * (chunks > 0 ? chunks : 1));
     uint64_t maxcount = vn1 > m_cap ? vn1 : m_cap;
     if (T1 > maxcount) maxcount = T1;
     const uint64_t hist = 256ull * ceil_div(maxcount, SORT_TILE);
@@ -338,7 +344,7 @@ gesr_status gesr_query_sizes(gesr_ctx* ctx, const gesr_camera* cams, int V, int 
     Geometry g;
     GESR_TRY(check_cams(ctx, cams, V, n, st, &g));
     if (m_cap < 1 || m_cap >= (1ull << 32)) return fail(ctx, GESR_ERR_INVALID, "m_cap must be in [1, 2^32)");
-    BinScratch s = carve(nullptr, g.vn, m_cap, g.total_tiles, g.grid_len);
+    BinScratch s = carve(nullptr, g.vn, m_cap, g.total_tiles, g.grid_len, corner_chunks(n));
     out->total_tiles = g.total_tiles;
     out->total_pixels = g.total_pixels;
     out->bin_scratch_bytes = s.bytes;
@@ -384,7 +390,7 @@ gesr_status gesr_bin(gesr_ctx* ctx, const gesr_proj* proj, const gesr_camera* ca
     GESR_TRY(check_cams(ctx, cams, V, n, st, &g));
     GESR_TRY(check_proj(ctx, proj));
     GESR_TRY(check_bins(ctx, bins, true));
-    BinScratch s = carve(bins->scratch, g.vn, bins->m_cap, g.total_tiles, g.grid_len);
+    BinScratch s = carve(bins->scratch, g.vn, bins->m_cap, g.total_tiles, g.grid_len, corner_chunks(n));
     if (bins->scratch_bytes < s.bytes)
         return fail(ctx, GESR_ERR_INVALID, "bins->scratch_bytes %zu < required %zu", bins->scratch_bytes, s.bytes);
     hipStream_t strm = (hipStream_t)stream;
@@ -438,8 +444,8 @@ gesr_status gesr_bin(gesr_ctx* ctx, const gesr_proj* proj, const gesr_camera* ca
     }
     // 4. per-tile ranges from per-tile counts (counting grids of the rectangles)
     GESR_TRY(hip_check(ctx,
-                       launch_tile_counts(proj->tiles_touched, proj->rect, g.vn, n, dc, s.diff, s.diff_len,
-                                          s.tile_count, strm),
+                       launch_tile_counts(proj->tiles_touched, proj->rect, n, dc, (int)g.max_cells, s.partial_grids,
+                                          s.diff, s.tile_count, strm),
                        "tile counts"));
     GESR_TRY(hip_check(ctx, scan_exclusive(s.tile_count, s.tile_start, T, s.scan_partials, nullptr, strm),
                        "tile count scan"));

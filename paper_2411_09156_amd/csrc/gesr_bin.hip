@@ -143,43 +143,33 @@ __device__ __forceinline__ uint32_t count_of(const uint32_t* count_dev, uint64_t
 }
 
 // Digit histogram of one block of SORT_TILE keys, stored digit-major:
-// block_hist[digit * nblocks + block].
+// block_hist[digit * nblocks + block].  Counting needs no ranking, so LDS
+// atomics (exact, order-independent) replace the ballot matching.
 template <int BITS>
 __global__ __launch_bounds__(SORT_THREADS) void k_radix_hist(const uint32_t* keys, uint64_t count_static,
                                                              const uint32_t* count_dev, int shift,
                                                              uint32_t* block_hist, uint32_t nblocks) {
     constexpr int RADIX = 1 << BITS;
-    __shared__ uint32_t hist[WAVES][RADIX];
-    for (int j = threadIdx.x; j < WAVES * RADIX; j += SORT_THREADS) (&hist[0][0])[j] = 0u;
+    __shared__ uint32_t hist[RADIX];
+    for (int j = threadIdx.x; j < RADIX; j += SORT_THREADS) hist[j] = 0u;
     __syncthreads();
     const uint32_t n = count_of(count_dev, count_static);
-    const uint32_t lane = __lane_id(), wave = threadIdx.x / 64;
-    const uint64_t base = (uint64_t)blockIdx.x * SORT_TILE + wave * (64 * SORT_ITEMS);
-    if ((uint64_t)blockIdx.x * SORT_TILE < n) {
-        // issue every load of the wave's chunk before any ranking work
+    const uint64_t base = (uint64_t)blockIdx.x * SORT_TILE;
+    if (base < n) {
         uint32_t k[SORT_ITEMS];
 #pragma unroll
         for (int r = 0; r < SORT_ITEMS; ++r) {
-            const uint64_t idx = base + r * 64 + lane;
+            const uint64_t idx = base + (uint64_t)r * SORT_THREADS + threadIdx.x;
             k[r] = idx < n ? keys[idx] : 0u;
         }
 #pragma unroll
         for (int r = 0; r < SORT_ITEMS; ++r) {
-            const uint64_t idx = base + r * 64 + lane;
-            const bool valid = idx < n;
-            const uint32_t digit = (k[r] >> shift) & (RADIX - 1);
-            const uint64_t vmask = __ballot(valid);
-            const uint64_t peers = match_digit<BITS>(digit, vmask);
-            if (valid && lane == (uint32_t)__ffsll((unsigned long long)peers) - 1)
-                hist[wave][digit] += (uint32_t)__popcll(peers);
+            const uint64_t idx = base + (uint64_t)r * SORT_THREADS + threadIdx.x;
+            if (idx < n) atomicAdd(&hist[(k[r] >> shift) & (RADIX - 1)], 1u);
         }
     }
     __syncthreads();
-    for (int d = threadIdx.x; d < RADIX; d += SORT_THREADS) {
-        uint32_t tot = 0;
-        for (int w = 0; w < WAVES; ++w) tot += hist[w][d];
-        block_hist[(uint64_t)d * nblocks + blockIdx.x] = tot;
-    }
+    for (int d = threadIdx.x; d < RADIX; d += SORT_THREADS) block_hist[(uint64_t)d * nblocks + blockIdx.x] = hist[d];
 }
 
 // Stable scatter of one block: ranks keys per digit in position order (wave
@@ -345,15 +335,49 @@ __global__ __launch_bounds__(256) void k_duplicate(const uint32_t* order, const 
 
 // Per-tile instance counts from the rectangles: +1/-1 at the four corners of
 // each rectangle in a per-view (tiles_y + 1) x (tiles_x + 1) difference grid,
-// then a 2-D prefix sum (k_tile_counts).  Integer atomics: exact and
-// order-independent.
-__global__ __launch_bounds__(256) void k_rect_corners(const uint32_t* tiles_touched, const uint32_t* rect,
-                                                      uint64_t count, int n, DevCams cams, int* diff) {
+// then a 2-D prefix sum.  Each block accumulates the corners of one chunk of
+// CORNER_CHUNK splats of one view in an LDS copy of the grid (LDS atomics;
+// integer sums, exact) and writes it out whole; k_tile_counts adds the
+// chunks' grids in fixed order and takes the prefix sums.
+constexpr int CORNER_CHUNK = 16384;
+constexpr size_t MAX_CORNER_LDS = 64 * 1024;
+
+__global__ __launch_bounds__(256) void k_rect_corners(const uint32_t* tiles_touched, const uint32_t* rect, int n,
+                                                      DevCams cams, uint32_t chunks, int* partial_grids) {
+    extern __shared__ int s_grid[];
+    const int v = blockIdx.y;
+    const uint32_t c = blockIdx.x;
+    const DevView& w = cams.v[v];
+    const uint32_t gx = (uint32_t)w.tiles_x + 1u;
+    const uint32_t cells = gx * ((uint32_t)w.tiles_y + 1u);
+    for (uint32_t k = threadIdx.x; k < cells; k += 256) s_grid[k] = 0;
+    __syncthreads();
+    const uint64_t i0 = (uint64_t)c * CORNER_CHUNK;
+    const uint64_t i1 = min<uint64_t>(i0 + CORNER_CHUNK, (uint64_t)n);
+    for (uint64_t i = i0 + threadIdx.x; i < i1; i += 256) {
+        const uint64_t vi = (uint64_t)v * (uint64_t)n + i;
+        if (tiles_touched[vi] == 0) continue;
+        const uint2 r = reinterpret_cast<const uint2*>(rect)[vi];
+        const uint32_t tx0 = r.x & 0xFFFFu, ty0 = r.x >> 16, tx1 = (r.y & 0xFFFFu) + 1u, ty1 = (r.y >> 16) + 1u;
+        atomicAdd(&s_grid[ty0 * gx + tx0], 1);
+        atomicAdd(&s_grid[ty0 * gx + tx1], -1);
+        atomicAdd(&s_grid[ty1 * gx + tx0], -1);
+        atomicAdd(&s_grid[ty1 * gx + tx1], 1);
+    }
+    __syncthreads();
+    int* dst = partial_grids + (uint64_t)w.grid_base * chunks + (uint64_t)c * cells;
+    for (uint32_t k = threadIdx.x; k < cells; k += 256) dst[k] = s_grid[k];
+}
+
+// Views whose grid does not fit in LDS: corners go straight to the global grid
+// with global atomics (exact; slower under contention).
+__global__ __launch_bounds__(256) void k_rect_corners_global(const uint32_t* tiles_touched, const uint32_t* rect,
+                                                             uint64_t count, int n, DevCams cams, int* grid) {
     const uint64_t vi = (uint64_t)blockIdx.x * 256 + threadIdx.x;
     if (vi >= count || tiles_touched[vi] == 0) return;
-    const uint32_t v = (uint32_t)vi / (uint32_t)n;
-    const uint32_t gx = (uint32_t)cams.v[v].tiles_x + 1u;
-    int* g = diff + cams.v[v].grid_base;
+    const DevView& w = cams.v[(uint32_t)vi / (uint32_t)n];
+    const uint32_t gx = (uint32_t)w.tiles_x + 1u;
+    int* g = grid + w.grid_base;
     const uint2 r = reinterpret_cast<const uint2*>(rect)[vi];
     const uint32_t tx0 = r.x & 0xFFFFu, ty0 = r.x >> 16, tx1 = (r.y & 0xFFFFu) + 1u, ty1 = (r.y >> 16) + 1u;
     atomicAdd(&g[ty0 * gx + tx0], 1);
@@ -362,13 +386,24 @@ __global__ __launch_bounds__(256) void k_rect_corners(const uint32_t* tiles_touc
     atomicAdd(&g[ty1 * gx + tx1], 1);
 }
 
-// One block per view: row prefix sums, then column prefix sums, of the view's
-// difference grid give each tile's instance count.
-__global__ __launch_bounds__(256) void k_tile_counts(DevCams cams, int* diff, uint32_t* counts) {
+// One block per view: sum the chunks' grids per cell (ascending chunk order;
+// chunks == 0: the grid already holds the sums), then row and column prefix
+// sums give each tile's instance count.
+__global__ __launch_bounds__(256) void k_tile_counts(DevCams cams, uint32_t chunks, const int* partial_grids,
+                                                     int* grid, uint32_t* counts) {
     const int v = blockIdx.x;
     const DevView& w = cams.v[v];
     const int gx = w.tiles_x + 1;
-    int* g = diff + w.grid_base;
+    const uint32_t cells = (uint32_t)gx * (uint32_t)(w.tiles_y + 1);
+    int* g = grid + w.grid_base;
+    const int* src = partial_grids + (uint64_t)w.grid_base * chunks;
+    if (chunks > 0)
+        for (uint32_t k = threadIdx.x; k < cells; k += 256) {
+            int acc = 0;
+            for (uint32_t c = 0; c < chunks; ++c) acc += src[(uint64_t)c * cells + k];
+            g[k] = acc;
+        }
+    __syncthreads();
     for (int y = threadIdx.x; y < w.tiles_y; y += 256) {
         int run = 0;
         for (int x = 0; x < w.tiles_x; ++x) {
@@ -500,15 +535,32 @@ hipError_t launch_duplicate(const uint32_t* order, const uint32_t* offsets, uint
     return hipGetLastError();
 }
 
-hipError_t launch_tile_counts(const uint32_t* tiles_touched, const uint32_t* rect, uint64_t count, int n,
-                              const DevCams& cams, int* diff, uint64_t diff_len, uint32_t* counts,
-                              hipStream_t stream) {
-    hipLaunchKernelGGL(k_fill_u32, grid_for(diff_len), dim3(256), 0, stream, reinterpret_cast<uint32_t*>(diff), 0u,
-                       diff_len);
-    if (count > 0)
-        hipLaunchKernelGGL(k_rect_corners, grid_for(count), dim3(256), 0, stream, tiles_touched, rect, count, n,
-                           cams, diff);
-    hipLaunchKernelGGL(k_tile_counts, dim3((unsigned)cams.V), dim3(256), 0, stream, cams, diff, counts);
+uint32_t corner_chunks(int n) { return (uint32_t)((n + CORNER_CHUNK - 1) / CORNER_CHUNK); }
+
+hipError_t launch_tile_counts(const uint32_t* tiles_touched, const uint32_t* rect, int n, const DevCams& cams,
+                              int max_cells, int* partial_grids, int* grid, uint32_t* counts, hipStream_t stream) {
+    if (n == 0) {  // no splats: every count is zero
+        uint64_t total = 0;
+        for (int v = 0; v < cams.V; ++v) total += (uint64_t)cams.v[v].tiles_x * cams.v[v].tiles_y;
+        hipLaunchKernelGGL(k_fill_u32, grid_for(total), dim3(256), 0, stream, counts, 0u, total);
+        return hipGetLastError();
+    }
+    uint32_t chunks = corner_chunks(n);
+    const size_t lds = (size_t)max_cells * sizeof(int);
+    if (lds <= MAX_CORNER_LDS) {
+        hipLaunchKernelGGL(k_rect_corners, dim3(chunks, (unsigned)cams.V), dim3(256), lds, stream, tiles_touched, rect,
+                           n, cams, chunks, partial_grids);
+    } else {
+        uint64_t cells = 0, vn = (uint64_t)cams.V * (uint64_t)n;
+        for (int v = 0; v < cams.V; ++v) cells += (uint64_t)(cams.v[v].tiles_x + 1) * (cams.v[v].tiles_y + 1);
+        hipLaunchKernelGGL(k_fill_u32, grid_for(cells), dim3(256), 0, stream, reinterpret_cast<uint32_t*>(grid), 0u,
+                           cells);
+        hipLaunchKernelGGL(k_rect_corners_global, grid_for(vn), dim3(256), 0, stream, tiles_touched, rect, vn, n, cams,
+                           grid);
+        chunks = 0;
+    }
+    hipLaunchKernelGGL(k_tile_counts, dim3((unsigned)cams.V), dim3(256), 0, stream, cams, chunks, partial_grids, grid,
+                       counts);
     return hipGetLastError();
 }
 

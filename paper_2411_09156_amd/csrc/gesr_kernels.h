@@ -110,11 +110,13 @@ hipError_t launch_duplicate(const uint32_t* order, const uint32_t* offsets, uint
                             const uint32_t* tiles_touched, const uint32_t* rect, const DevCams& cams,
                             uint64_t m_cap, const uint32_t* total, uint32_t* keys, uint32_t* vals,
                             uint32_t* inst_base, hipStream_t stream);
-// Per-tile instance counts (difference grid of rectangle corners, 2-D prefix);
-// view v's (tiles_y + 1) x (tiles_x + 1) grid starts at cams.v[v].grid_base.
-hipError_t launch_tile_counts(const uint32_t* tiles_touched, const uint32_t* rect, uint64_t count, int n,
-                              const DevCams& cams, int* diff, uint64_t diff_len, uint32_t* counts,
-                              hipStream_t stream);
+// Per-tile instance counts (difference grid of rectangle corners, 2-D prefix).
+// View v's (tiles_y + 1) x (tiles_x + 1) grid starts at cams.v[v].grid_base in
+// `grid`; `partial_grids` holds corner_chunks(n) copies of every grid.
+// max_cells: the largest view grid (its LDS copy must fit one workgroup).
+uint32_t corner_chunks(int n);
+hipError_t launch_tile_counts(const uint32_t* tiles_touched, const uint32_t* rect, int n, const DevCams& cams,
+                              int max_cells, int* partial_grids, int* grid, uint32_t* counts, hipStream_t stream);
 hipError_t launch_ranges_from_counts(const uint32_t* counts, const uint32_t* starts, uint64_t total_tiles,
                                      const uint32_t* listed, uint32_t* ranges, hipStream_t stream);
 hipError_t launch_set_counters(uint32_t* counters, uint64_t m_cap, hipStream_t stream);

@@ -519,8 +519,20 @@ __global__ __launch_bounds__(256) void k_seg_reduce(SegReduceArgs a) {
         const uint32_t tx0 = r.x & 0xFFFFu, ty0 = r.x >> 16, width = (r.y & 0xFFFFu) - tx0 + 1u;
         const uint64_t key = ((uint64_t)a.depth_key[vi] << 32) | (uint32_t)vi;
         const uint64_t base = a.inst_base[vi];
+        const float rw = 1.0f / (float)width;
         for (uint32_t j = lane; j < cnt; j += 64) {
-            const uint32_t ty = ty0 + j / width, tx = tx0 + j % width;
+            // (row, column) of instance j in the rectangle: j / width by a float
+            // reciprocal (exact for j < 2^24 after one correction step)
+            int32_t qy = (int32_t)((float)j * rw);
+            int32_t rx = (int32_t)j - qy * (int32_t)width;
+            if (rx < 0) {
+                --qy;
+                rx += (int32_t)width;
+            } else if (rx >= (int32_t)width) {
+                ++qy;
+                rx -= (int32_t)width;
+            }
+            const uint32_t ty = ty0 + (uint32_t)qy, tx = tx0 + (uint32_t)rx;
             const uint32_t t = w.tile_base + ty * (uint32_t)w.tiles_x + tx;
             if (key < a.tile_cut[t] && base + j < a.m_cap) {
                 const float2* src = reinterpret_cast<const float2*>(a.partials + (base + j) * NP);

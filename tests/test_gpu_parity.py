@@ -57,13 +57,16 @@ def _case(name):
         return gi.make_workload(3, n_override=50_000), oracle.Settings()
     if name == "surfels-40k-2v":
         return gi.make_workload(4, n_override=40_000, views_override=2), oracle.Settings(sh_degree=3)
+    if name == "wide-2200x2100":  # > 16k tiles in one view: global counting-grid path
+        return gi.tiny_scene(8, n=300, deg=1, width=2200, height=2100, log_scale=(-3.5, -2.5)), \
+            oracle.Settings(sh_degree=1)
     if name == "blobs-100k-2v":
         return gi.make_workload(5, n_override=100_000, views_override=2), oracle.Settings(sh_degree=3)
     raise KeyError(name)
 
 
 CASES = ["tiny-d1", "tiny-d3-2v-bg", "tiny-kappa1", "plain-2k", "plain-2k-v1", "plain-2k-t8", "plain-2k-t32x16",
-         "plain-2k-t32", "spheres-100k", "drt-50k-8v", "drt-50k-8v-v1", "surfels-40k-2v", "blobs-100k-2v"]
+         "plain-2k-t32", "spheres-100k", "drt-50k-8v", "drt-50k-8v-v1", "surfels-40k-2v", "blobs-100k-2v", "wide-2200x2100"]
 
 
 @functools.lru_cache(maxsize=1)
