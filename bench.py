@@ -39,6 +39,22 @@ HBM_BYTES_PER_S = 8.0e12
 FWD_LISTED, FWD_HIT = 8, 24
 BWD_LISTED, BWD_HIT = 9, 73
 
+# HBM bytes per launch of the tile adjoint on the default workload, from two
+# rocprofv3 counter passes (FETCH_SIZE x2.0, WRITE_SIZE x1.0 after calibration
+# against a 1 GiB copy; profiles/drt-500k-8views_hbm_counters.md).  Valid only
+# for the kernel source it was measured on (fingerprint below); otherwise null.
+MEASURED_TRAFFIC = {"kernel": "render_bwd_tiles", "workload": "drt-batch-500k-8views",
+                    "fingerprint": "6b8a654d73a83d2c", "bytes": 4436646100}
+
+
+def kernel_fingerprint():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("gesr_render.hip", "gesr_device.h"):
+        with open(os.path.join(ROOT, "paper_2411_09156_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
 
 def parse_args():
     p = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
@@ -51,7 +67,9 @@ def parse_args():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-per-view", action="store_true")
     p.add_argument("--no-graph", action="store_true")
-    p.add_argument("--cpu-sample-views", default="0,1,2")
+    p.add_argument("--cpu-sample-views", default="0,1,2,3,4,5")
+    p.add_argument("--calibrate-copy", type=int, default=0,
+                   help="also run a plain device copy of this many MiB (hardware counter calibration)")
     return p.parse_args()
 
 
@@ -107,6 +125,16 @@ def main():
             rec(6)
             return f, g, bins
         return step
+
+    if args.calibrate_copy > 0:
+        # plain device-to-device copy of known size, for scaling HBM byte counters
+        src = torch.empty(args.calibrate_copy * (1 << 20) // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy: {args.calibrate_copy} MiB read + {args.calibrate_copy} MiB written")
+        del src, dst
 
     # ------------------------------------------------------------ sizing
     rast = Rasterizer(scene.cameras, rs)
@@ -240,8 +268,12 @@ def main():
     dom = max(kern, key=lambda kk: stage_ms[kk])
     achieved = kern[dom] / (stage_ms[dom] * 1e-3) / 1e12
     peak = VALU_SLOTS_PER_S / 1e12
+    traffic = None
+    if (dom == MEASURED_TRAFFIC["kernel"] and scene.name == MEASURED_TRAFFIC["workload"]
+            and kernel_fingerprint() == MEASURED_TRAFFIC["fingerprint"] and args.tile == "16x16"):
+        traffic = MEASURED_TRAFFIC["bytes"]
     roofline = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3), "peak": round(peak, 3),
-                "unit": "Tslot/s", "frac": round(achieved / peak, 4), "traffic": None,
+                "unit": "Tslot/s", "frac": round(achieved / peak, 4), "traffic": traffic,
                 "algorithmic_slots_per_launch": int(kern[dom])}
 
     # ------------------------------------------------------- CPU baseline

@@ -93,6 +93,16 @@ template <int CTRL, int ROW_MASK, int BANK_MASK>
 __device__ __forceinline__ float dpp(float v) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, BANK_MASK, true));
 }
+// Sum over each 16-lane row; the row total is valid in the row's lane 15.
+__device__ __forceinline__ float row_sum_lane15(float x) {
+    float s = x + dpp<0x111, 0xf, 0xf>(x);   // row_shr:1
+    s = s + dpp<0x112, 0xf, 0xf>(x);         // row_shr:2
+    s = s + dpp<0x113, 0xf, 0xf>(x);         // row_shr:3
+    s = s + dpp<0x114, 0xf, 0xe>(s);         // row_shr:4, banks 1..3
+    s = s + dpp<0x118, 0xf, 0xc>(s);         // row_shr:8, banks 2..3
+    return s;
+}
+
 __device__ __forceinline__ float wave_sum_lane63(float x) {
     float s = x + dpp<0x111, 0xf, 0xf>(x);   // row_shr:1
     s = s + dpp<0x112, 0xf, 0xf>(x);         // row_shr:2

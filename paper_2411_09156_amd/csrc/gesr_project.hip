@@ -498,21 +498,22 @@ __global__ __launch_bounds__(256) void k_project_bwd(ProjectBwdArgs a) {
     for (int k = 0; k < K * 3; ++k) a.g_sh[(size_t)k * n + i] = gsh[k];
 }
 
-// One wave per (view, splat): lane l sums the partials of instances
-// l, l + 64, ... that the render adjoint visited, then a fixed DPP tree adds
-// the lanes.  The order depends only on the pair's own instances, so a batch
-// of views and views rendered one at a time give identical sums.
+// Sixteen lanes (one DPP row) per (view, splat): lane l of the row sums the
+// partials of instances l, l + 16, ... that the render adjoint visited, then
+// a fixed DPP tree adds the row.  The order depends only on the pair's own
+// instances, so a batch of views and views rendered one at a time give
+// identical sums.
 __global__ __launch_bounds__(256) void k_seg_reduce(SegReduceArgs a) {
     constexpr int NP = GESR_PARTIAL_FLOATS;
-    const uint64_t vi = ((uint64_t)blockIdx.x * 256u + threadIdx.x) >> 6;
-    const uint32_t lane = __lane_id();
-    if (vi >= a.vn) return;  // uniform over the wave
-    float* out = a.grad2d + (size_t)vi * NP;
-    const uint32_t cnt = a.tiles_touched[vi];
+    constexpr uint32_t L = 16;
+    const uint64_t vi = ((uint64_t)blockIdx.x * 256u + threadIdx.x) / L;
+    const uint32_t lane = __lane_id() & (L - 1);
+    const bool valid = vi < a.vn;
     float acc[NP];
 #pragma unroll
     for (int k = 0; k < NP; ++k) acc[k] = 0.f;
     bool any = false;
+    const uint32_t cnt = valid ? a.tiles_touched[vi] : 0u;
     if (cnt > 0) {
         const DevView& w = a.cams.v[(uint32_t)vi / (uint32_t)a.n];
         const uint2 r = reinterpret_cast<const uint2*>(a.rect)[vi];
@@ -520,7 +521,7 @@ __global__ __launch_bounds__(256) void k_seg_reduce(SegReduceArgs a) {
         const uint64_t key = ((uint64_t)a.depth_key[vi] << 32) | (uint32_t)vi;
         const uint64_t base = a.inst_base[vi];
         const float rw = 1.0f / (float)width;
-        for (uint32_t j = lane; j < cnt; j += 64) {
+        for (uint32_t j = lane; j < cnt; j += L) {
             // (row, column) of instance j in the rectangle: j / width by a float
             // reciprocal (exact for j < 2^24 after one correction step)
             int32_t qy = (int32_t)((float)j * rw);
@@ -546,15 +547,16 @@ __global__ __launch_bounds__(256) void k_seg_reduce(SegReduceArgs a) {
             }
         }
     }
-    if (__ballot(any) == 0ull) {
-        if (lane < NP) out[lane] = 0.f;
-        return;
+    if (__ballot(any) != 0ull) {
+#pragma unroll
+        for (int k = 0; k < NP; ++k) acc[k] = row_sum_lane15(acc[k]);
     }
+    // rows without visited instances hold zeros; lane 15 of each row writes
+    if (valid && lane == L - 1) {
+        float2* out = reinterpret_cast<float2*>(a.grad2d + (size_t)vi * NP);
 #pragma unroll
-    for (int k = 0; k < NP; ++k) acc[k] = wave_sum_lane63(acc[k]);
-    if (lane == 63)
-#pragma unroll
-        for (int k = 0; k < NP; ++k) out[k] = acc[k];
+        for (int k = 0; k < NP / 2; ++k) out[k] = make_float2(acc[2 * k], acc[2 * k + 1]);
+    }
 }
 
 }  // namespace
@@ -573,7 +575,7 @@ hipError_t launch_project(const ProjectArgs& a, int sh_degree, hipStream_t strea
 
 hipError_t launch_seg_reduce(const SegReduceArgs& a, hipStream_t stream) {
     if (a.vn == 0) return hipSuccess;
-    const uint64_t threads = (uint64_t)a.vn * 64;
+    const uint64_t threads = (uint64_t)a.vn * 16;
     hipLaunchKernelGGL(k_seg_reduce, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, stream, a);
     return hipGetLastError();
 }
