@@ -319,3 +319,28 @@ def tiny_scene(seed: int, n: int = 12, width: int = 40, height: int = 32, deg: i
     cams = ring_cameras(n_views, [(width, height)] * n_views) if n_views > 1 else \
         [look_at((0.0, 0.0, -4.0), width=width, height=height)]
     return _finish(f"tiny-{seed}", rng, means, log_scales, quats, betas, sh, deg, cams)
+
+
+RAGGED_SIZES = ((1, 1), (1, 37), (23, 1), (17, 33), (129, 65))
+
+
+def ragged_scene(seed: int, n: int = 200, deg: int = 2) -> Scene:
+    """Views of degenerate and ragged sizes (one pixel, one row, one column,
+    sizes that are not multiples of any tile) on a ring around a small scene."""
+    rng = np.random.default_rng([200 + seed, 0])
+    means = rng.uniform(-0.6, 0.6, (n, 3))
+    log_scales = rng.uniform(-2.6, -1.6, (n, 3))
+    quats = _random_quats(rng, n)
+    betas = rng.uniform(1.0, 4.0, n)
+    sh = _sh_coeffs(rng, n, deg, rest_std=0.3)
+    cams = ring_cameras(len(RAGGED_SIZES), list(RAGGED_SIZES))
+    return _finish(f"ragged-{seed}", rng, means, log_scales, quats, betas, sh, deg, cams)
+
+
+def empty_scene(deg: int = 0, sizes=((1, 1), (37, 19))) -> Scene:
+    """No splats at all."""
+    rng = np.random.default_rng([300, 0])
+    z = np.zeros((0, 3))
+    return _finish("empty", rng, z, z, np.zeros((0, 4)), np.zeros(0), np.zeros((0, (deg + 1) ** 2, 3)), deg,
+                   ring_cameras(len(sizes), list(sizes)))
+

@@ -133,7 +133,7 @@ typedef struct {
  *  worklist[T]: global tile ids ordered by decreasing list length (ties by id).
  *  inst_base[V*n]: pre-sort instance id of the first instance of (view, splat).
  *  counters[4]: [0] = M (instances wanted), [1] = 1 if M > m_cap,
- *      [2] = min(M, m_cap).  Written on the device. */
+ *      [2] = min(M, m_cap); [3] is reserved.  Written on the device. */
 typedef struct {
     uint64_t m_cap;
     uint32_t* tile_sorted;

@@ -129,7 +129,7 @@ def project(scene, st: Settings) -> dict:
         rec=np.zeros((VN, 11)), depth=np.zeros(VN), z32=np.zeros(VN, np.float32), sigma2d=np.zeros((VN, 3)),
         edges=np.zeros((VN, 4)), pix_rect=np.zeros((VN, 4), np.int32), tile_rect=np.zeros((VN, 4), np.int32),
         tiles_touched=np.zeros(VN, np.uint32), cull=np.zeros(VN, np.uint8), clamp=np.zeros(VN, np.uint8))
-    sh = _f64(scene.sh.reshape(N, -1))
+    sh = _f64(scene.sh.reshape(N, int(np.prod(scene.sh.shape[1:]))))
     lib().orc_project(N, V, _p(_f64(scene.means)), _p(_f64(scene.scales)), _p(_f64(scene.quats)),
                       _p(_f64(scene.opacities)), _p(_f64(scene.betas)), _p(sh), _p(views_array(scene.cameras)),
                       _p(st.array()), _p(r["rec"]), _p(r["depth"]), _p(r["z32"]), _p(r["sigma2d"]),
@@ -209,7 +209,7 @@ def project_bwd(scene, grad2d, st: Settings) -> dict:
     g = dict(means=np.zeros((N, 3)), scales=np.zeros((N, 3)), quats=np.zeros((N, 4)), opacities=np.zeros(N),
              betas=np.zeros(N), sh=np.zeros((N, K, 3)))
     lib().orc_project_bwd(N, V, _p(_f64(scene.means)), _p(_f64(scene.scales)), _p(_f64(scene.quats)),
-                          _p(_f64(scene.opacities)), _p(_f64(scene.betas)), _p(_f64(scene.sh.reshape(N, -1))),
+                          _p(_f64(scene.opacities)), _p(_f64(scene.betas)), _p(_f64(scene.sh.reshape(N, int(np.prod(scene.sh.shape[1:]))))),
                           _p(views_array(scene.cameras)), _p(st.array()), _p(_f64(grad2d)),
                           _p(g["means"]), _p(g["scales"]), _p(g["quats"]), _p(g["opacities"]), _p(g["betas"]),
                           _p(g["sh"]))

@@ -524,6 +524,7 @@ gesr_status gesr_render_bwd_tiles(gesr_ctx* ctx, const gesr_proj* proj, const ge
     a.n_contrib = const_cast<uint32_t*>(n_contrib);
     a.dL_dimage = dL_dimage;
     a.partials = ws.partials;
+    a.m_cap = (uint32_t)bins->m_cap;
     a.depth_key = proj->depth_key;
     a.tile_cut = ws.tile_cut;
     a.st = dev_settings(st);

@@ -63,6 +63,7 @@ struct RenderArgs {
     // backward
     const float* dL_dimage;
     float* partials;
+    uint32_t m_cap;  // capacity of partials (instances); only reached when the lists overflowed
     const uint32_t* depth_key;
     uint64_t* tile_cut;  // per tile: (depth_key, vi) of the first unvisited position
     DevSettings st;

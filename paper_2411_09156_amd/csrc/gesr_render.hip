@@ -78,6 +78,21 @@ __device__ __forceinline__ void stage_record(const float* rec, uint32_t vi, floa
     sc = r[2];
 }
 
+constexpr uint32_t kNoInstance = 0xFFFFFFFFu;
+
+// Slot of the instance (splat vi, tile (tx, ty)) in the duplicate order: the
+// splat's instance base plus the tile's row-major position in its rectangle.
+// When the lists overflowed their capacity the ranges no longer match the
+// truncated lists, so a listed splat may not cover the tile or its slot may lie
+// beyond the capacity; kNoInstance then suppresses the partial write.
+__device__ __forceinline__ uint32_t instance_index(const RenderArgs& a, uint2 r, uint32_t vi, uint32_t tx,
+                                                   uint32_t ty) {
+    const uint32_t tx0 = r.x & 0xFFFFu, ty0 = r.x >> 16, tx1 = r.y & 0xFFFFu, ty1 = r.y >> 16;
+    const uint32_t inst = a.inst_base[vi] + (ty - ty0) * (tx1 - tx0 + 1u) + (tx - tx0);
+    const bool inside = tx >= tx0 && tx <= tx1 && ty >= ty0 && ty <= ty1;
+    return inside && inst < a.m_cap ? inst : kNoInstance;
+}
+
 template <int TW, int TH, bool COUNT>
 __global__ __launch_bounds__(TW * TH) void k_render_fwd(RenderArgs a) {
     constexpr int NT = TW * TH;
@@ -190,8 +205,7 @@ __global__ __launch_bounds__(TW * TH) void k_render_bwd(RenderArgs a) {
             const uint32_t vi = a.val_sorted[pos];
             stage_record(a.rec, vi, sA[threadIdx.x], sB[threadIdx.x], sC[threadIdx.x]);
             const uint2 r = reinterpret_cast<const uint2*>(a.rect)[vi];
-            const uint32_t tx0 = r.x & 0xFFFFu, ty0 = r.x >> 16, tx1 = r.y & 0xFFFFu;
-            sInst[threadIdx.x] = a.inst_base[vi] + (ti.ty - ty0) * (tx1 - tx0 + 1u) + (ti.tx - tx0);
+            sInst[threadIdx.x] = instance_index(a, r, vi, ti.tx, ti.ty);
         }
         __syncthreads();
         for (int j = 0; j < cnt; ++j) {
@@ -252,6 +266,7 @@ __global__ __launch_bounds__(TW * TH) void k_render_bwd(RenderArgs a) {
         }
         __syncthreads();
         for (int jj = threadIdx.x; jj < cnt; jj += NT) {
+            if (sInst[jj] == kNoInstance) continue;
             float s[NP];
 #pragma unroll
             for (int k = 0; k < NP; ++k) s[k] = sRed[0][jj][k];
@@ -422,8 +437,7 @@ __global__ __launch_bounds__(64) void k_render_bwd_wave16(RenderArgs a) {
             const uint32_t vi = a.val_sorted[pos];
             stage_record(a.rec, vi, sA[lane], sB[lane], sC[lane]);
             const uint2 r = reinterpret_cast<const uint2*>(a.rect)[vi];
-            const uint32_t tx0 = r.x & 0xFFFFu, ty0 = r.x >> 16, tx1 = r.y & 0xFFFFu;
-            sInst[lane] = a.inst_base[vi] + (ty - ty0) * (tx1 - tx0 + 1u) + (tx - tx0);
+            sInst[lane] = instance_index(a, r, vi, tx, ty);
         }
         __syncthreads();
         for (int j = 0; j < cnt; ++j) {
@@ -482,7 +496,7 @@ __global__ __launch_bounds__(64) void k_render_bwd_wave16(RenderArgs a) {
             }
         }
         __syncthreads();
-        if ((int)lane < cnt) {
+        if ((int)lane < cnt && sInst[lane] != kNoInstance) {
             float2* dst = reinterpret_cast<float2*>(a.partials + (size_t)sInst[lane] * NP);
 #pragma unroll
             for (int k = 0; k < NP / 2; ++k) dst[k] = make_float2(sRed[lane][2 * k], sRed[lane][2 * k + 1]);

@@ -89,8 +89,13 @@ class Splats:
         def t(x):
             return torch.as_tensor(x, dtype=torch.float32).to(device)
         n = t(opacities).shape[0]
-        return Splats(t(means).t().contiguous(), t(scales).t().contiguous(), t(quats).t().contiguous(),
-                      t(opacities).contiguous(), t(betas).contiguous(), t(sh).reshape(n, -1).t().contiguous())
+        shc = t(sh)
+        width = 1
+        for d in shc.shape[1:]:
+            width *= int(d)
+        return Splats(t(means).reshape(n, 3).t().contiguous(), t(scales).reshape(n, 3).t().contiguous(),
+                      t(quats).reshape(n, 4).t().contiguous(), t(opacities).contiguous(), t(betas).contiguous(),
+                      shc.reshape(n, width).t().contiguous())
 
     def to_c(self) -> _lib.Splats:
         s = _lib.Splats()

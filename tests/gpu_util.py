@@ -16,9 +16,11 @@ def log(msg: str) -> None:
 
 def raster_settings(st: oracle.Settings, **kw):
     from paper_2411_09156_amd import RasterSettings
-    return RasterSettings(sh_degree=st.sh_degree, kappa=st.kappa, rho=st.rho, alpha_min=st.alpha_min,
-                          alpha_max=st.alpha_max, t_min=st.t_min, blur=st.blur, znear=st.znear,
-                          clip_fac=st.clip_fac, bg=tuple(st.bg), tile_w=st.tile_w, tile_h=st.tile_h, **kw)
+    args = dict(sh_degree=st.sh_degree, kappa=st.kappa, rho=st.rho, alpha_min=st.alpha_min, alpha_max=st.alpha_max,
+                t_min=st.t_min, blur=st.blur, znear=st.znear, clip_fac=st.clip_fac, bg=tuple(st.bg), tile_w=st.tile_w,
+                tile_h=st.tile_h)
+    args.update(kw)
+    return RasterSettings(**args)
 
 
 def u32(t) -> np.ndarray:
@@ -213,3 +215,53 @@ def ambiguous_tiles_to_pixels(cameras, st, tile_diff) -> np.ndarray:
         m = np.repeat(np.repeat(t, st.tile_h, 0), st.tile_w, 1)[:c.height, :c.width]
         masks.append(m.reshape(-1))
     return np.concatenate(masks)
+
+
+def check_projection(scene, g: dict, pr: dict) -> str:
+    """Projection bars: culls agree except at a handful of threshold ties; centre
+    within 2 float32 ulps of the view extent; conic within 1e-4 relative;
+    opacity and beta exact; qmax 1e-5 relative; colour 1e-5; depth key equal up
+    to one ulp at near-ties; tile rectangles equal away from 1e-3 px of a pixel
+    boundary of the FP64 edges.  Returns a one-line summary."""
+    keep_g = g["tiles_touched"] > 0
+    keep_o = pr["tiles_touched"] > 0
+    both = keep_g & keep_o
+    VN = len(keep_g)
+    assert (keep_g != keep_o).sum() <= max(2, VN // 10000), (keep_g != keep_o).sum()
+    r, o = g["rec"][both].astype(np.float64), pr["rec"][both]
+    cams = scene.cameras
+    # centre: u = fx x/z + cx rounds at the scale of the image, also where the
+    # two terms cancel near u = 0
+    ext = np.concatenate([np.full(scene.n, max(c.width, c.height)) for c in cams])[both]
+    ulp = np.spacing(np.maximum(np.maximum(np.abs(o[:, 0]), np.abs(o[:, 1])), ext).astype(np.float32))
+    eu = np.abs(r[:, 0] - o[:, 0]) / ulp
+    ev = np.abs(r[:, 1] - o[:, 1]) / ulp
+    ecen = max(eu.max(), ev.max()) if eu.size else 0.0
+    assert ecen <= 2.0, (eu.max(), ev.max())
+    # conic: near edge-on flat splats the determinant's cross term is
+    # (disk normal . viewing ray), whose float32 evaluation from a float32
+    # rotation loses about eps |ray| / |normal . ray|; elsewhere errors are ~1e-6
+    A, B, C = r[:, 2] ** 2, r[:, 2] * r[:, 3], r[:, 3] ** 2 + r[:, 4] ** 2
+    eA = np.abs(A - o[:, 2]) / o[:, 2]
+    eC = np.abs(C - o[:, 4]) / o[:, 4]
+    eB = np.abs(B - o[:, 3]) / np.sqrt(o[:, 2] * o[:, 4])
+    econ = np.maximum(np.maximum(eA, eC), eB)
+    emax = float(econ.max()) if econ.size else 0.0
+    assert emax <= 1e-4, emax
+    np.testing.assert_array_equal(r[:, 5], o[:, 5])
+    np.testing.assert_array_equal(r[:, 6], o[:, 6])
+    np.testing.assert_array_less(np.abs(r[:, 7] - o[:, 7]), 1e-5 * o[:, 7] + 1e-30)
+    np.testing.assert_array_less(np.abs(r[:, 8:11] - o[:, 8:11]), 1e-5)
+    dk_o = pr["zbits"][both].astype(np.int64)
+    dk_g = g["depth_key"][both].astype(np.int64)
+    if dk_o.size:
+        assert np.abs(dk_g - dk_o).max() <= 1
+    assert (dk_g != dk_o).sum() <= max(1, both.sum() // 100000)
+    diff = (g["tile_rect"][both] != pr["tile_rect"][both]).any(1)
+    e = pr["edges"][both]
+    near = (np.abs(e - np.round(e)) < 1e-3).any(1)
+    assert (diff & ~near).sum() == 0
+    q9999 = float(np.quantile(econ, 0.9999)) if econ.size else 0.0
+    return (f"culls differ {int((keep_g != keep_o).sum())}, rects in guard band {int(diff.sum())}, depth ulps "
+            f"{int((dk_g != dk_o).sum())}; centre err max {ecen:.2f} ulp; conic rel err max {emax:.2e}, "
+            f"99.99% {q9999:.2e}")

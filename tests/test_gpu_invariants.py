@@ -1,0 +1,478 @@
+"""GPU properties that hold at any size, the method's degenerate cases, the
+library's capacity and graph-capture contracts, and the full benchmark
+workload checked on sampled outputs.
+
+* empty and fully culled scenes render the background and give zero gradients;
+* an instance capacity below M without synchronisation is flagged in
+  counters[1] and stays memory safe; with synchronisation the lists regrow and
+  equal a run with ample capacity;
+* runs are bitwise deterministic; a batch of views equals the views rendered
+  one at a time bit for bit (images, per-view screen-space gradients, and
+  parameter gradients summed over views in view order); images do not depend
+  on the tile size;
+* a captured HIP graph replays to the eager results, also after its inputs
+  change in place;
+* the autograd wrapper returns what the backward entry points return;
+* GPU gradients equal central differences of the FP64 forward;
+* the benchmark workload (500,000 splats, 8 views at the dynamic-resolution
+  sizes, 16x16 tiles, capacity exactly M, no synchronisation inside the step)
+  against the oracle: every projected record, the complete binning through
+  properties that determine it uniquely, and images and gradients on sampled
+  tiles.
+"""
+import copy
+
+import numpy as np
+import pytest
+
+import gesr_inputs as gi
+import oracle
+from tests.gpu_util import (ambiguous_tiles_to_pixels, check_projection, conic_grads_to_factor, e2e_settings,
+                            f32, factor_grads_to_conic, log, mask_upstream, norm_errors, oracle_rec,
+                            raster_settings, run_gpu, run_gpu_bwd, splats_of, u32)
+
+pytestmark = pytest.mark.gpu
+
+PARAMS = ("means", "scales", "quats", "opacities", "betas", "sh")
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _rast(scene, st, **kw):
+    from paper_2411_09156_amd import Rasterizer
+    return Rasterizer(scene.cameras, raster_settings(st, **kw))
+
+
+def _bg_image(scene, bg):
+    return np.concatenate([np.repeat(np.asarray(bg, np.float32), c.width * c.height) for c in scene.cameras])
+
+
+def _fwd_bwd(rast, sp, dL, m_cap=None, sync=True):
+    """(numpy forward outputs, numpy gradients incl. grad2d, counters)."""
+    torch = _torch()
+    f = rast.forward(sp, sync=sync, m_cap=m_cap)
+    g = rast.render_bwd(sp, f["proj"], f["bins"], f["final_T"], f["n_contrib"],
+                        torch.as_tensor(np.asarray(dL, np.float32), device="cuda"), want_grad2d=True)
+    torch.cuda.synchronize()
+    fo = {k: f[k].cpu().numpy().copy() for k in ("image", "final_T", "n_contrib")}
+    go = {k: v.cpu().numpy().copy() for k, v in g.items()}
+    return fo, go, u32(f["bins"]["counters"]).copy()
+
+
+# ------------------------------------------------------------------ degenerate scenes
+def test_empty_scene():
+    scene = gi.empty_scene(deg=1)
+    st = oracle.Settings(sh_degree=1, bg=(0.2, 0.5, 0.1))
+    log("[gpu] empty scene: n=0, views 1x1 and 37x19")
+    g = run_gpu(scene, st)
+    assert g["M"] == 0 and g["overflow"] == 0
+    np.testing.assert_array_equal(g["image"], _bg_image(scene, np.float32(st.bg)))
+    np.testing.assert_array_equal(g["final_T"], 1.0)
+    np.testing.assert_array_equal(g["n_contrib"], 0)
+    np.testing.assert_array_equal(g["ranges"], 0)
+    gb = run_gpu_bwd(scene, st, g, np.ones(3 * scene.n_pixels))
+    assert all(gb[k].size == 0 for k in PARAMS)
+
+
+def test_fully_culled_scene():
+    """Splats behind the camera, inside the near plane, or with opacity below
+    alpha_min produce no instance; the image is the background and every
+    gradient is exactly zero."""
+    scene = gi.tiny_scene(4, n=30, deg=2)
+    m = np.array(scene.means, np.float32)
+    m[:10, 2] = -6.0      # behind the camera at z = -4
+    m[10:20, 2] = -3.9    # depth 0.1 < znear
+    op = np.array(scene.opacities, np.float32)
+    op[20:] = 0.5 / 255.0  # below alpha_min: no footprint
+    scene = copy.copy(scene)
+    scene.means, scene.opacities = m, op
+    st = oracle.Settings(sh_degree=2, bg=(0.3, 0.1, 0.7))
+    pr = oracle.project(scene, st)
+    assert (pr["tiles_touched"] == 0).all()
+    log("[gpu] fully culled scene")
+    g = run_gpu(scene, st)
+    assert g["M"] == 0
+    np.testing.assert_array_equal(g["tiles_touched"], 0)
+    np.testing.assert_array_equal(g["image"], _bg_image(scene, np.float32(st.bg)))
+    np.testing.assert_array_equal(g["final_T"], 1.0)
+    gb = run_gpu_bwd(scene, st, g, gi.sample_rng(5).standard_normal(3 * scene.n_pixels))
+    for k in PARAMS:
+        np.testing.assert_array_equal(gb[k], 0.0)
+
+
+# ------------------------------------------------------------------ capacity
+def test_overflow_without_sync_is_flagged_and_memory_safe():
+    torch = _torch()
+    scene, st = gi.make_workload(1), oracle.Settings()
+    rast = _rast(scene, st)
+    sp = splats_of(scene)
+    M = int(rast.forward(sp, sync=True)["bins"]["M"])
+    cap = M // 3
+    log(f"[gpu] overflow: M={M}, capacity {cap}, no sync")
+    f = rast.forward(sp, sync=False, m_cap=cap)
+    dL = torch.ones(3 * scene.n_pixels, device="cuda")
+    rast.render_bwd(sp, f["proj"], f["bins"], f["final_T"], f["n_contrib"], dL)
+    torch.cuda.synchronize()
+    cnt = u32(f["bins"]["counters"])
+    assert (int(cnt[0]), int(cnt[1]), int(cnt[2])) == (M, 1, cap)
+    assert u32(f["bins"]["ranges"]).max() <= cap
+    assert np.isfinite(f32(f["image"])).all()
+
+
+def test_sync_regrows_capacity_to_the_exact_lists():
+    scene, st = gi.make_workload(1), oracle.Settings()
+    rast = _rast(scene, st)
+    sp = splats_of(scene)
+    ref = rast.forward(sp, sync=True, m_cap=50_000_000)
+    small = _rast(scene, st).forward(sp, sync=True, m_cap=1000)
+    M = int(ref["bins"]["M"])
+    assert int(small["bins"]["M"]) == M and small["bins"]["m_cap"] >= M
+    for k in ("val_sorted", "tile_sorted"):
+        np.testing.assert_array_equal(u32(small["bins"][k])[:M], u32(ref["bins"][k])[:M])
+    np.testing.assert_array_equal(u32(small["bins"]["ranges"]), u32(ref["bins"]["ranges"]))
+    np.testing.assert_array_equal(f32(small["image"]), f32(ref["image"]))
+
+
+# ------------------------------------------------------------------ bitwise invariants
+def test_deterministic_bitwise():
+    scene, st = gi.make_workload(3, n_override=50_000), oracle.Settings()
+    dL = oracle.flat_images(gi.upstream_grads(scene, 7))
+    rast = _rast(scene, st)
+    sp = splats_of(scene)
+    log("[gpu] determinism: two fwd+bwd runs")
+    fa, ga, _ = _fwd_bwd(rast, sp, dL)
+    fb, gb, _ = _fwd_bwd(rast, sp, dL)
+    for k in fa:
+        np.testing.assert_array_equal(fa[k], fb[k])
+    for k in ga:
+        np.testing.assert_array_equal(ga[k], gb[k])
+
+
+def test_batched_equals_per_view_bitwise():
+    """Tile lists, visit order and the per-pair reduction order of a view do not
+    depend on the other views in the batch."""
+    scene, st = gi.make_workload(3, n_override=50_000), oracle.Settings()
+    dL = oracle.flat_images(gi.upstream_grads(scene, 7))
+    N, V = scene.n, scene.n_views
+    sp = splats_of(scene)
+    fb, gb, _ = _fwd_bwd(_rast(scene, st), sp, dL)
+    acc = None
+    off_i = off_p = 0
+    for v in range(V):
+        sv = copy.copy(scene)
+        sv.cameras = [scene.cameras[v]]
+        P = sv.n_pixels
+        log(f"[gpu] per-view run {v} ({sv.cameras[0].width}x{sv.cameras[0].height})")
+        fv, gv, _ = _fwd_bwd(_rast(sv, st), sp, dL[off_i:off_i + 3 * P])
+        np.testing.assert_array_equal(fv["image"][:3 * P], fb["image"][off_i:off_i + 3 * P])
+        np.testing.assert_array_equal(fv["final_T"][:P], fb["final_T"][off_p:off_p + P])
+        np.testing.assert_array_equal(fv["n_contrib"][:P], fb["n_contrib"][off_p:off_p + P])
+        np.testing.assert_array_equal(gv["grad2d"][:N * 10], gb["grad2d"][v * N * 10:(v + 1) * N * 10])
+        # views accumulate in ascending order in float32, starting from zero
+        acc = {k: gv[k].copy() for k in gv if k != "grad2d"} if acc is None else \
+            {k: (acc[k] + gv[k]).astype(np.float32) for k in acc}
+        off_i += 3 * P
+        off_p += P
+    for k in acc:
+        np.testing.assert_array_equal(acc[k], gb[k])
+
+
+def test_images_do_not_depend_on_tile_size():
+    scene, st = gi.make_workload(1), oracle.Settings()
+    sp = splats_of(scene)
+    ref = None
+    for tw, th, var in ((16, 16, 0), (16, 16, 1), (8, 8, 0), (32, 16, 0), (32, 32, 0)):
+        out = _rast(scene, st, tile_w=tw, tile_h=th, variant=var).forward(sp)
+        img = f32(out["image"])
+        T = f32(out["final_T"])
+        log(f"[gpu] tiles {tw}x{th} variant {var}")
+        if ref is None:
+            ref = (img, T)
+            continue
+        # n_contrib is a position in the tile's list, so it depends on the tile
+        np.testing.assert_array_equal(img, ref[0])
+        np.testing.assert_array_equal(T, ref[1])
+
+
+# ------------------------------------------------------------------ graph capture
+def test_graph_replay_matches_eager():
+    torch = _torch()
+    scene, st = gi.make_workload(1), oracle.Settings()
+    rast = _rast(scene, st)
+    sp = splats_of(scene)
+    n = sp.n
+    M = int(rast.forward(sp, sync=True)["bins"]["M"])
+    m_cap = 2 * M
+    dL = torch.as_tensor(oracle.flat_images(gi.upstream_grads(scene, 7)).astype(np.float32), device="cuda")
+
+    def step():
+        proj = rast.project(sp)
+        bins = rast.bin(proj, n, m_cap=m_cap, sync=False)
+        f = rast.render_fwd(proj, bins, n)
+        g = rast.render_bwd(sp, proj, bins, f["final_T"], f["n_contrib"], dL)
+        return f, g, bins
+
+    def snap(res):
+        f, g, bins = res
+        out = {k: f[k].cpu().numpy().copy() for k in ("image", "final_T", "n_contrib")}
+        out.update({"g_" + k: v.cpu().numpy().copy() for k, v in g.items()})
+        out["counters"] = u32(bins["counters"])[:3].copy()  # [3] is unused
+        return out
+
+    def same(a, b):
+        for k in a:
+            np.testing.assert_array_equal(a[k], b[k], err_msg=k)
+
+    eager_a = snap(step())
+    mean0 = sp.mean.clone()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        step()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        res = step()
+    log("[gpu] graph captured; replaying")
+    for rep in range(3):
+        graph.replay()
+        torch.cuda.synchronize()
+        same(eager_a, snap(res))
+        snap(step())  # eager work between replays
+    # new inputs written in place
+    sp.mean.add_(0.01 * torch.sin(torch.arange(sp.mean.numel(), device="cuda", dtype=torch.float32)).view_as(sp.mean))
+    eager_b = snap(step())
+    graph.replay()
+    torch.cuda.synchronize()
+    got_b = snap(res)
+    same(eager_b, got_b)
+    assert not np.array_equal(eager_b["image"], eager_a["image"])
+    sp.mean.copy_(mean0)
+    graph.replay()
+    torch.cuda.synchronize()
+    same(eager_a, snap(res))
+    assert eager_a["counters"][1] == 0 and got_b["counters"][1] == 0
+
+
+# ------------------------------------------------------------------ autograd and loss
+def test_autograd_function_matches_entry_points():
+    torch = _torch()
+    from paper_2411_09156_amd import render
+    scene, st = gi.tiny_scene(2, n=30, deg=3, n_views=2), oracle.Settings(sh_degree=3)
+    rast = _rast(scene, st)
+    sp = splats_of(scene)
+    leaves = [t.clone().requires_grad_(True) for t in sp.tensors()]
+    img = render(rast, *leaves)
+    dL = torch.as_tensor(oracle.flat_images(gi.upstream_grads(scene, 3)).astype(np.float32), device="cuda")
+    (img * dL).sum().backward()
+    f = rast.forward(sp)
+    g = rast.render_bwd(sp, f["proj"], f["bins"], f["final_T"], f["n_contrib"], dL)
+    np.testing.assert_array_equal(f32(img), f32(f["image"]))
+    for leaf, k in zip(leaves, ("mean", "scale", "quat", "opacity", "beta", "sh")):
+        np.testing.assert_array_equal(f32(leaf.grad), f32(g[k]), err_msg=k)
+
+
+def test_l1_gradient():
+    torch = _torch()
+    from paper_2411_09156_amd import Rasterizer
+    rng = gi.sample_rng(9)
+    n = 3 * 1000 + 17
+    img = rng.uniform(0, 1, n).astype(np.float32)
+    tgt = rng.uniform(0, 1, n).astype(np.float32)
+    tgt[::7] = img[::7]  # ties give zero
+    scene = gi.tiny_scene(0)
+    rast = Rasterizer(scene.cameras, raster_settings(oracle.Settings()))
+    scale = 1.0 / n
+    g = f32(rast.l1_grad(torch.as_tensor(img, device="cuda"), torch.as_tensor(tgt, device="cuda"), scale))
+    np.testing.assert_array_equal(g, (np.sign(img.astype(np.float64) - tgt) * np.float32(scale)).astype(np.float32))
+
+
+# ------------------------------------------------------------------ finite differences
+def _fd_loss(scene, st, g_img):
+    pr = oracle.project(scene, st)
+    win = np.array([[0, 0, c.width - 1, c.height - 1] for c in scene.cameras], np.int32)
+    loss, _, dec = oracle.window_fwdbwd(scene.n, scene.cameras, pr["rec"], pr["zbits"], pr["cull"], pr["pix_rect"],
+                                        win, g_img, [], st)
+    return loss, dec
+
+
+@pytest.mark.parametrize("seed,deg,views", [(0, 1, 1), (2, 3, 2)])
+def test_gpu_gradients_match_finite_differences(seed, deg, views):
+    """dL/dtheta of the GPU backward against central differences of the FP64
+    forward, for every parameter of a tiny scene (steps that change a discrete
+    decision are halved, then skipped)."""
+    scene = gi.tiny_scene(seed, n=10, deg=deg, n_views=views)
+    st = oracle.Settings(sh_degree=deg)
+    se = e2e_settings(st, scene.cameras)
+    fo = oracle.forward(scene, se)
+    g_img = mask_upstream(oracle.flat_images(gi.upstream_grads(scene, 11)), fo["ambig"] > 0, scene.cameras)
+    g = run_gpu(scene, st, counts=False)
+    gb = run_gpu_bwd(scene, st, g, g_img)
+    base_loss, base_dec = _fd_loss(scene, st, g_img)
+    gmax = max(np.abs(gb[p]).max() for p in PARAMS)
+    checked = skipped = 0
+    for name in PARAMS:
+        base = np.asarray(getattr(scene, name), np.float64).reshape(-1)
+        an = gb[name].reshape(-1)
+        for k in range(base.size):
+            h = 1e-6 * max(abs(base[k]), 1e-2)
+            ok = False
+            for _ in range(4):
+                vals = []
+                for sgn in (1, -1):
+                    s = copy.copy(scene)
+                    arr = base.copy()
+                    arr[k] += sgn * h
+                    setattr(s, name, arr.reshape(np.asarray(getattr(scene, name)).shape))
+                    vals.append(_fd_loss(s, st, g_img))
+                if vals[0][1] == base_dec and vals[1][1] == base_dec:
+                    ok = True
+                    break
+                h *= 0.5
+            if not ok:
+                skipped += 1
+                continue
+            fd = (vals[0][0] - vals[1][0]) / (2 * h)
+            assert abs(an[k] - fd) <= 2e-3 * max(abs(fd), 1e-2 * gmax), (name, k, an[k], fd)
+            checked += 1
+    assert checked > 0 and skipped <= max(2, checked // 50)
+    log(f"[gpu] FD seed {seed}: {checked} parameters checked, {skipped} skipped")
+
+
+# ------------------------------------------------------------------ full benchmark workload
+def _sample_tiles(ranges, worklist, grid, rng):
+    """The 12 longest lists, 24 random non-empty tiles and the bottom-right
+    (ragged) tile of every view."""
+    lens = ranges[:, 1].astype(np.int64) - ranges[:, 0]
+    heavy = worklist[:12].astype(np.int64)
+    nonempty = np.nonzero(lens > 0)[0]
+    rand = rng.choice(nonempty, 24, replace=False)
+    corners = np.array([base + tx * ty - 1 for tx, ty, base in grid], np.int64)
+    sel = np.zeros(len(lens), bool)
+    sel[np.concatenate([heavy, rand, corners])] = True
+    return sel
+
+
+def test_full_benchmark_workload():
+    torch = _torch()
+    scene = gi.make_workload(3)
+    st = oracle.Settings()
+    N, V = scene.n, scene.n_views
+    VN = N * V
+    rast = _rast(scene, st)
+    sp = splats_of(scene)
+    M = int(rast.forward(sp, sync=True)["bins"]["M"])
+    log(f"[gpu] full workload: n={N} views={V} px={scene.n_pixels} M={M}")
+    torch.cuda.synchronize()
+    # the benchmark's launch configuration: capacity exactly M, no synchronisation
+    proj = rast.project(sp)
+    bins = rast.bin(proj, N, m_cap=M, sync=False)
+    f = rast.render_fwd(proj, bins, N, counts=True)
+    torch.cuda.synchronize()
+    cnt = u32(bins["counters"])
+    assert (int(cnt[0]), int(cnt[1])) == (M, 0)
+
+    # ---- projection: every record
+    rec = f32(proj["rec"])[:VN * 12].reshape(VN, 12)
+    tt = u32(proj["tiles_touched"])[:VN]
+    r = u32(proj["rect"])[:2 * VN].reshape(VN, 2)
+    rect = np.stack([r[:, 0] & 0xFFFF, r[:, 0] >> 16, r[:, 1] & 0xFFFF, r[:, 1] >> 16], 1).astype(np.int64)
+    dk = u32(proj["depth_key"])[:VN]
+    g = dict(rec=rec, tiles_touched=tt, tile_rect=rect.astype(np.int32), depth_key=dk)
+    log("[gpu] full workload: projection " + check_projection(scene, g, oracle.project(scene, st)))
+
+    # ---- binning: properties that determine the lists uniquely
+    grid, T = oracle.tile_grid(scene.cameras, st.tile_w, st.tile_h)
+    tile = u32(bins["tile_sorted"])[:M]
+    val = u32(bins["val_sorted"])[:M]
+    ranges = u32(bins["ranges"])[:2 * T].reshape(T, 2)
+    worklist = u32(bins["worklist"])[:T]
+    assert int(tt.astype(np.int64).sum()) == M
+    np.testing.assert_array_equal(np.bincount(val, minlength=VN), tt)  # each pair once per tile it touches
+    counts = np.bincount(tile, minlength=T)
+    assert counts.size == T
+    starts = np.concatenate([[0], np.cumsum(counts)[:-1]])
+    np.testing.assert_array_equal(ranges[:, 0], np.where(counts > 0, starts, 0))
+    np.testing.assert_array_equal(ranges[:, 1], np.where(counts > 0, starts + counts, 0))
+    tiles_x = np.array([gx for gx, gy, b in grid], np.int64)
+    bases = np.array([b for gx, gy, b in grid], np.int64)
+    CH = 1 << 24
+    for c0 in range(0, M, CH):
+        c1 = min(M, c0 + CH + 1)
+        t_ = tile[c0:c1].astype(np.int64)
+        v_ = val[c0:c1].astype(np.int64)
+        k_ = dk[v_].astype(np.int64)
+        # strictly increasing (tile, depth key, pair index): sorted, no pair twice in a tile
+        same_t = t_[1:] == t_[:-1]
+        assert (t_[1:] >= t_[:-1]).all()
+        inc = (k_[1:] > k_[:-1]) | ((k_[1:] == k_[:-1]) & (v_[1:] > v_[:-1]))
+        assert (inc | ~same_t).all()
+        # every listed tile lies in the pair's rectangle, in the pair's view
+        view = v_ // N
+        lt = t_ - bases[view]
+        tx, ty = lt % tiles_x[view], lt // tiles_x[view]
+        rr = rect[v_]
+        assert ((lt >= 0) & (lt < tiles_x[view] * np.array([gy for gx, gy, b in grid])[view])).all()
+        assert ((tx >= rr[:, 0]) & (tx <= rr[:, 2]) & (ty >= rr[:, 1]) & (ty <= rr[:, 3])).all()
+    lens = ranges[:, 1].astype(np.int64) - ranges[:, 0]
+    np.testing.assert_array_equal(worklist, np.lexsort((np.arange(T), -np.minimum(lens, 0xFFFF))))
+    order = np.argsort(dk, kind="stable")
+    base = np.zeros(VN, np.int64)
+    base[order] = np.concatenate([[0], np.cumsum(tt[order].astype(np.int64))[:-1]])
+    np.testing.assert_array_equal(u32(bins["inst_base"])[:VN], base)
+    log("[gpu] full workload: binning properties hold")
+
+    # ---- render forward and backward on sampled tiles
+    sel = _sample_tiles(ranges, worklist, grid, gi.sample_rng(13))
+    masked = np.where(sel[:, None], ranges, 0).astype(np.uint32)
+    orec = oracle_rec(rec)
+    fo = oracle.render_fwd(N, scene.cameras, orec, val, masked, st)
+    pix = ambiguous_tiles_to_pixels(scene.cameras, st, sel)
+    amb = fo["ambig"] > 0
+    ok = pix & ~amb
+    img = f32(f["image"]).reshape(-1)
+    P = scene.n_pixels
+    pix3 = np.zeros(3 * P, bool)
+    ok3 = np.zeros(3 * P, bool)
+    off_i = off_p = 0
+    for c in scene.cameras:
+        n = c.width * c.height
+        pix3[off_i:off_i + 3 * n] = np.tile(pix[off_p:off_p + n], 3)
+        ok3[off_i:off_i + 3 * n] = np.tile(ok[off_p:off_p + n], 3)
+        off_i += 3 * n
+        off_p += n
+    err = np.abs(img[ok3] - fo["image"][ok3])
+    assert err.max() <= 1e-4 * max(np.abs(fo["image"][pix3]).max(), 1.0), err.max()
+    assert np.abs(f32(f["final_T"])[ok] - fo["final_T"][ok]).max() <= 1e-4
+    for k in ("n_contrib", "n_listed", "n_hit"):
+        np.testing.assert_array_equal(u32(f[k])[ok], fo[k][ok], err_msg=k)
+    log(f"[gpu] full workload: {int(sel.sum())} sampled tiles, {int(pix.sum())} px ({int((pix & amb).sum())} "
+        f"ambiguous), image max err {err.max():.2e}, listed/px {fo['n_listed'][pix].mean():.0f}")
+
+    dL = oracle.flat_images(gi.upstream_grads(scene, 7))
+    dL = np.where(pix3, dL, 0.0)
+    dL = mask_upstream(dL, amb, scene.cameras)
+    gpu = rast.render_bwd(sp, proj, bins, f["final_T"], f["n_contrib"],
+                          torch.as_tensor(dL.astype(np.float32), device="cuda"), want_grad2d=True)
+    torch.cuda.synchronize()
+    g2 = f32(gpu["grad2d"])[:VN * 10].reshape(VN, 10)
+    ref2 = conic_grads_to_factor(oracle.render_bwd(N, scene.cameras, orec, val, masked, dL, st), rec)
+    for k in range(10):
+        einf, e2 = norm_errors(g2[:, k], ref2[:, k])
+        assert einf <= 1e-3 and e2 <= 1e-3, (k, einf, e2)
+    ref = oracle.project_bwd(scene, factor_grads_to_conic(g2, rec), st)
+    got = dict(means=f32(gpu["mean"]).reshape(3, N).T, scales=f32(gpu["scale"]).reshape(3, N).T,
+               quats=f32(gpu["quat"]).reshape(4, N).T, opacities=f32(gpu["opacity"]), betas=f32(gpu["beta"]),
+               sh=f32(gpu["sh"]).reshape(3, N).T.reshape(N, 1, 3))
+    worst = 0.0
+    for k in PARAMS:
+        einf, e2 = norm_errors(got[k], ref[k])
+        worst = max(worst, einf, e2)
+        assert einf <= 1e-3 and e2 <= 1e-3, (k, einf, e2)
+    touched = (np.abs(g2).reshape(V, N, 10).max(axis=(0, 2)) > 0)
+    assert not np.abs(got["means"][~touched]).any()
+    log(f"[gpu] full workload: gradients of {int(touched.sum())} splats ok, worst {worst:.2e}")
