@@ -137,7 +137,7 @@ def main():
         del src, dst
 
     # ------------------------------------------------------------ sizing
-    rast = Rasterizer(scene.cameras, rs)
+    rast = Rasterizer(scene.cameras, rs, store_tile_ids=False)
     log("[bench] sizing run (eager, synchronous count)")
     first = rast.forward(sp, sync=True, counts=True)
     M = int(first["bins"]["M"])
@@ -206,7 +206,7 @@ def main():
         rasts, steps = [], []
         off = 0
         for v, cam in enumerate(scene.cameras):
-            r = Rasterizer([cam], rs)
+            r = Rasterizer([cam], rs, store_tile_ids=False)
             npx = 3 * cam.width * cam.height
             tv = target[off:off + npx]
             off += npx

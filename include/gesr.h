@@ -125,13 +125,17 @@ typedef struct {
 /* Binning outputs, DEVICE, caller-allocated.  `scratch` must hold at least
  * gesr_sizes.bin_scratch_bytes for the same (cams, V, n, settings, m_cap).
  *  tile_sorted[m_cap], val_sorted[m_cap]: instances sorted by the 64-bit key
- *      (global tile id << 32 | depth_key), stable with respect to emission in
- *      (view, splat, tile row, tile column) order; val = view * n + splat.
+ *      (global tile id << 32 | depth_key), equal keys by val; val = view * n +
+ *      splat, tile_sorted = the instance's global tile id.  tile_sorted may be
+ *      NULL (the renderers read only ranges and val_sorted).
  *  ranges[T][2]: [first, end) of each global tile in the sorted list, (0, 0)
  *      when empty.  Global tile ids number the tiles of view 0 row-major,
  *      then view 1, and so on.
  *  worklist[T]: global tile ids ordered by decreasing list length (ties by id).
- *  inst_base[V*n]: pre-sort instance id of the first instance of (view, splat).
+ *  inst_base[V*n]: exclusive scan of tiles_touched in (view, splat) order: the
+ *      instance slots of pair vi are inst_base[vi] + (row-major position of the
+ *      tile in the pair's rectangle); the backward's per-instance partials use
+ *      these slots.
  *  counters[4]: [0] = M (instances wanted), [1] = 1 if M > m_cap,
  *      [2] = min(M, m_cap); [3] is reserved.  Written on the device. */
 typedef struct {
@@ -182,7 +186,10 @@ gesr_status gesr_project(gesr_ctx* ctx, const gesr_splats* splats, const gesr_ca
 #define GESR_BIN_SYNC 1 /* read M back and fail with GESR_ERR_CAPACITY if M > m_cap */
 
 /* Tile binning: one instance per (view, splat, covered tile), sorted by the
- * (tile | depth) key (see gesr_bins).  With GESR_BIN_SYNC the call
+ * (tile | depth) key (see gesr_bins).  The pairs are radix-sorted by (view,
+ * depth); the lists are then built from the rectangles in two stable bucketing
+ * levels (pairs into tile rows, row entries into tiles) without sorting
+ * instances.  With GESR_BIN_SYNC the call
  * synchronises `stream` once after counting; if M > m_cap it returns
  * GESR_ERR_CAPACITY with *m_out = M and leaves the sorted lists undefined.
  * Without it the call never synchronises (capturable in a HIP graph): lists

@@ -7,6 +7,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <string>
 
 #include "gesr.h"
@@ -77,8 +78,7 @@ gesr_status check_settings(gesr_ctx* ctx, const gesr_settings* st) {
 struct Geometry {
     uint64_t total_tiles = 0, total_pixels = 0;
     uint64_t vn = 0;
-    uint64_t grid_len = 0;  // cells of the per-view tile counting grids
-    uint64_t max_cells = 0; // cells of the largest view's grid
+    uint64_t total_rows = 0;  // tile rows over all views
 };
 
 gesr_status check_cams(gesr_ctx* ctx, const gesr_camera* cams, int V, int n, const gesr_settings* st, Geometry* g) {
@@ -86,8 +86,7 @@ gesr_status check_cams(gesr_ctx* ctx, const gesr_camera* cams, int V, int n, con
     if (V < 1 || V > GESR_MAX_VIEWS) return fail(ctx, GESR_ERR_INVALID, "V = %d outside 1..%d", V, GESR_MAX_VIEWS);
     if (n < 0) return fail(ctx, GESR_ERR_INVALID, "n = %d is negative", n);
     uint64_t tiles = 0, pix = 0;
-    g->grid_len = 0;
-    g->max_cells = 0;
+    g->total_rows = 0;
     for (int v = 0; v < V; ++v) {
         const gesr_camera& c = cams[v];
         if (c.width < 1 || c.height < 1) return fail(ctx, GESR_ERR_INVALID, "view %d: width/height must be >= 1", v);
@@ -103,8 +102,7 @@ gesr_status check_cams(gesr_ctx* ctx, const gesr_camera* cams, int V, int n, con
         if (tx > 0xFFFFu || ty > 0xFFFFu) return fail(ctx, GESR_ERR_INVALID, "view %d: too many tiles per axis", v);
         tiles += tx * ty;
         pix += (uint64_t)c.width * (uint64_t)c.height;
-        g->grid_len += (tx + 1) * (ty + 1);
-        if ((tx + 1) * (ty + 1) > g->max_cells) g->max_cells = (tx + 1) * (ty + 1);
+        g->total_rows += ty;
     }
 
     if (3 * pix >= (1ull << 32)) return fail(ctx, GESR_ERR_INVALID, "3 * total pixels must be < 2^32");
@@ -140,7 +138,7 @@ DevCams dev_cams(const gesr_camera* cams, int V, const gesr_settings* st) {
     DevCams d;
     memset(&d, 0, sizeof d);
     d.V = V;
-    uint32_t tb = 0, pb = 0, gb = 0;
+    uint32_t tb = 0, pb = 0;
     for (int v = 0; v < V; ++v) {
         const gesr_camera& c = cams[v];
         DevView& w = d.v[v];
@@ -159,31 +157,32 @@ DevCams dev_cams(const gesr_camera* cams, int V, const gesr_settings* st) {
         w.tiles_y = (c.height + st->tile_h - 1) / st->tile_h;
         w.tile_base = tb;
         w.pix_base = pb;
-        w.grid_base = gb;
         tb += (uint32_t)(w.tiles_x * w.tiles_y);
         pb += (uint32_t)(c.width * c.height);
-        gb += (uint32_t)((w.tiles_x + 1) * (w.tiles_y + 1));
     }
     return d;
 }
 
 // Layout of gesr_bins.scratch (256-byte aligned sub-buffers).
 struct BinScratch {
-    uint32_t *d_keys_a, *d_vals_a, *d_keys_b, *d_vals_b;  // depth sort, [V*n]
-    uint32_t *cnt_sorted, *offsets;                       // [V*n]
-    uint32_t *i_keys, *i_vals;                            // instance sort partner, [m_cap]
+    uint32_t *d_keys_a, *d_vals_a, *d_keys_b, *d_vals_b;  // depth and view sort, [V*n]
+    uint32_t *rowlist, *rowcols;                          // row lists and their columns, [m_cap]
+    uint2* srect;                                         // rectangles in (view, depth) order, [V*n]
+    uint32_t *row_count, *row_start;                      // [total rows]
+    uint32_t *seg_chunks, *chunk_off;                     // [segments + 1]
+    uint32_t* mat;                                        // per-chunk bucket counts
+    uint64_t mat_chunks;
+    uint32_t* counters;                                   // [4]: row-list entries, overflow, listed
+    uint32_t* chunk_total;                                // [1]
     uint32_t *w_keys_a, *w_vals_a, *w_keys_b;             // worklist sort, [T]
     uint32_t *tile_count, *tile_start;                    // [T]
-    int* diff;                                            // counting grids
-    uint64_t diff_len;
-    int* partial_grids;                                   // per-chunk copies of the grids
     uint32_t *block_hist, *scan_partials;
     size_t bytes;
 };
 
 uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
 
-BinScratch carve(void* base, uint64_t vn, uint64_t m_cap, uint64_t T, uint64_t grid_len, uint64_t chunks) {
+BinScratch carve(void* base, const Geometry& g, const DevCams& dc, int n, uint64_t m_cap) {
     BinScratch s;
     size_t off = 0;
     char* b = (char*)base;
@@ -192,29 +191,33 @@ BinScratch carve(void* base, uint64_t vn, uint64_t m_cap, uint64_t T, uint64_t g
         off += ((count * 4 + 255) / 256) * 256;
         return p;
     };
-    const uint64_t vn1 = vn > 0 ? vn : 1;
-    const uint64_t T1 = T > 0 ? T : 1;
+    const uint64_t vn1 = g.vn > 0 ? g.vn : 1;
+    const uint64_t T1 = g.total_tiles > 0 ? g.total_tiles : 1;
+    const uint64_t nseg = std::max(is_segments(dc, 1), is_segments(dc, 2)) + 1;
     s.d_keys_a = take(vn1);
     s.d_vals_a = take(vn1);
     s.d_keys_b = take(vn1);
     s.d_vals_b = take(vn1);
-    s.cnt_sorted = take(vn1);
-    s.offsets = take(vn1);
-    s.i_keys = take(m_cap);
-    s.i_vals = take(m_cap);
+    s.rowlist = take(m_cap);
+    s.rowcols = take(m_cap);
+    s.srect = reinterpret_cast<uint2*>(take(2 * vn1));
+    s.row_count = take(g.total_rows + 1);
+    s.row_start = take(g.total_rows + 1);
+    s.seg_chunks = take(nseg);
+    s.chunk_off = take(nseg);
+    s.mat_chunks = std::max(is_chunk_bound(dc, 1, n, 0), is_chunk_bound(dc, 2, n, m_cap));
+    s.mat = take(s.mat_chunks * is_window());
+    s.counters = take(4);
+    s.chunk_total = take(1);
     s.w_keys_a = take(T1);
     s.w_vals_a = take(T1);
     s.w_keys_b = take(T1);
     s.tile_count = take(T1);
     s.tile_start = take(T1);
-    s.diff_len = grid_len > 0 ? grid_len : 1;
-    s.diff = (int*)take(s.diff_len);
-    s.partial_grids = (int*)take(s.diff_len * (chunks > 0 ? chunks : 1));
-    uint64_t maxcount = vn1 > m_cap ? vn1 : m_cap;
-    if (T1 > maxcount) maxcount = T1;
+    const uint64_t maxcount = std::max(vn1, T1);
     const uint64_t hist = 256ull * ceil_div(maxcount, SORT_TILE);
     s.block_hist = take(hist);
-    const uint64_t scan_items = hist > vn1 ? hist : vn1;
+    const uint64_t scan_items = std::max(std::max(hist, vn1), std::max(T1, std::max(g.total_rows + 1, nseg)));
     s.scan_partials = take(ceil_div(scan_items, SCAN_TILE) + 64);
     s.bytes = off;
     return s;
@@ -279,12 +282,14 @@ gesr_status check_bins(gesr_ctx* ctx, const gesr_bins* b, bool need_scratch) {
     if (!b) return fail(ctx, GESR_ERR_INVALID, "bins is NULL");
     if (b->m_cap < 1 || b->m_cap >= (1ull << 32))
         return fail(ctx, GESR_ERR_INVALID, "m_cap must be in [1, 2^32)");
-    const void* ptrs[6] = {b->tile_sorted, b->val_sorted, b->ranges, b->worklist, b->inst_base, b->counters};
-    const char* names[6] = {"tile_sorted", "val_sorted", "ranges", "worklist", "inst_base", "counters"};
-    for (int k = 0; k < 6; ++k) {
+    const void* ptrs[5] = {b->val_sorted, b->ranges, b->worklist, b->inst_base, b->counters};
+    const char* names[5] = {"val_sorted", "ranges", "worklist", "inst_base", "counters"};
+    for (int k = 0; k < 5; ++k) {
         if (!ptrs[k]) return fail(ctx, GESR_ERR_INVALID, "bins->%s is NULL", names[k]);
         if (!aligned16(ptrs[k])) return fail(ctx, GESR_ERR_INVALID, "bins->%s is not 16-byte aligned", names[k]);
     }
+    if (b->tile_sorted && !aligned16(b->tile_sorted))
+        return fail(ctx, GESR_ERR_INVALID, "bins->tile_sorted is not 16-byte aligned");
     if (need_scratch && (!b->scratch || !aligned16(b->scratch)))
         return fail(ctx, GESR_ERR_INVALID, "bins->scratch is NULL or not 16-byte aligned");
     return GESR_OK;
@@ -344,12 +349,12 @@ gesr_status gesr_query_sizes(gesr_ctx* ctx, const gesr_camera* cams, int V, int 
     Geometry g;
     GESR_TRY(check_cams(ctx, cams, V, n, st, &g));
     if (m_cap < 1 || m_cap >= (1ull << 32)) return fail(ctx, GESR_ERR_INVALID, "m_cap must be in [1, 2^32)");
-    BinScratch s = carve(nullptr, g.vn, m_cap, g.total_tiles, g.grid_len, corner_chunks(n));
+    BinScratch s = carve(nullptr, g, dev_cams(cams, V, st), n, m_cap);
     out->total_tiles = g.total_tiles;
     out->total_pixels = g.total_pixels;
     out->bin_scratch_bytes = s.bytes;
     out->bwd_workspace_bytes = carve_bwd(nullptr, g.vn, m_cap, g.total_tiles).bytes;
-    out->max_sort_blocks = ceil_div(m_cap, SORT_TILE);
+    out->max_sort_blocks = ceil_div(std::max<uint64_t>(g.vn, g.total_tiles), SORT_TILE);
     ctx->err.clear();
     return GESR_OK;
 }
@@ -390,12 +395,12 @@ gesr_status gesr_bin(gesr_ctx* ctx, const gesr_proj* proj, const gesr_camera* ca
     GESR_TRY(check_cams(ctx, cams, V, n, st, &g));
     GESR_TRY(check_proj(ctx, proj));
     GESR_TRY(check_bins(ctx, bins, true));
-    BinScratch s = carve(bins->scratch, g.vn, bins->m_cap, g.total_tiles, g.grid_len, corner_chunks(n));
+    const DevCams dc = dev_cams(cams, V, st);
+    BinScratch s = carve(bins->scratch, g, dc, n, bins->m_cap);
     if (bins->scratch_bytes < s.bytes)
         return fail(ctx, GESR_ERR_INVALID, "bins->scratch_bytes %zu < required %zu", bins->scratch_bytes, s.bytes);
     hipStream_t strm = (hipStream_t)stream;
     GESR_TRY(hip_check(ctx, hipSetDevice(ctx->device), "hipSetDevice"));
-    const DevCams dc = dev_cams(cams, V, st);
     const uint64_t T = g.total_tiles;
 
     // 1. depth order of the (view, splat) pairs: LSD passes over the 32 depth bits
@@ -403,11 +408,13 @@ gesr_status gesr_bin(gesr_ctx* ctx, const gesr_proj* proj, const gesr_camera* ca
     bool in_b = false;
     GESR_TRY(hip_check(ctx, radix_sort(proj->depth_key, nullptr, g.vn, nullptr, 32, 8, db, &in_b, strm),
                        "depth sort"));
-    const uint32_t* order = in_b ? s.d_vals_b : s.d_vals_a;
-    // 2. instance offsets in depth order; M -> counters[0]
-    GESR_TRY(hip_check(ctx, launch_gather_counts(order, proj->tiles_touched, s.cnt_sorted, g.vn, strm), "gather"));
-    GESR_TRY(hip_check(ctx, scan_exclusive(s.cnt_sorted, s.offsets, g.vn, s.scan_partials, bins->counters, strm),
-                       "offset scan"));
+    uint32_t* order = in_b ? s.d_vals_b : s.d_vals_a;
+    uint32_t* spare_keys = in_b ? s.d_keys_a : s.d_keys_b;
+    uint32_t* spare_vals = in_b ? s.d_vals_a : s.d_vals_b;
+    // 2. instance slots: exclusive scan of tiles_touched in pair order; M -> counters[0]
+    GESR_TRY(hip_check(ctx, scan_exclusive(proj->tiles_touched, bins->inst_base, g.vn, s.scan_partials,
+                                           bins->counters, strm),
+                       "instance slots"));
     GESR_TRY(hip_check(ctx, launch_set_counters(bins->counters, bins->m_cap, strm), "counters"));
     if (flags & GESR_BIN_SYNC) {
         uint32_t m = 0;
@@ -418,37 +425,58 @@ gesr_status gesr_bin(gesr_ctx* ctx, const gesr_proj* proj, const gesr_camera* ca
             return fail(ctx, GESR_ERR_CAPACITY, "M = %u instances exceed m_cap = %llu", m,
                         (unsigned long long)bins->m_cap);
     }
-    // 3. duplicate in depth order, then stable sort by tile id
-    const int tile_bits = bits_for(T);
-    const int passes = radix_passes(tile_bits, st->radix_bits);
-    SortBuffers ib;
-    uint32_t *dup_keys, *dup_vals;
-    if (passes % 2 == 1) {  // dup -> scratch (b), final pass lands in the outputs (a)
-        ib = SortBuffers{bins->tile_sorted, bins->val_sorted, s.i_keys, s.i_vals, s.block_hist, s.scan_partials};
-        dup_keys = s.i_keys;
-        dup_vals = s.i_vals;
-    } else {  // dup -> outputs (b); even number of passes returns there
-        ib = SortBuffers{s.i_keys, s.i_vals, bins->tile_sorted, bins->val_sorted, s.block_hist, s.scan_partials};
-        dup_keys = bins->tile_sorted;
-        dup_vals = bins->val_sorted;
+    // 3. stable pass on the view: pairs in (view, depth, pair) order
+    const uint32_t* order_vd = order;
+    if (bits_for((uint64_t)V) > 0 && g.vn > 0) {
+        GESR_TRY(hip_check(ctx, launch_view_keys(order, g.vn, (uint32_t)n, spare_keys, strm), "view keys"));
+        SortBuffers vb{s.d_keys_a == spare_keys ? s.d_keys_b : s.d_keys_a, spare_vals, nullptr, nullptr,
+                       s.block_hist, s.scan_partials};
+        bool vb_in_b = false;
+        GESR_TRY(hip_check(ctx, radix_sort(spare_keys, order, g.vn, nullptr, bits_for((uint64_t)V), 8, vb, &vb_in_b,
+                                           strm),
+                           "view sort"));
+        order_vd = spare_vals;
     }
+    // 4. row lists: every pair in the rows its rectangle covers (level 1)
+    GESR_TRY(hip_check(ctx, launch_gather_rects(order_vd, proj->tiles_touched, proj->rect, g.vn, s.srect, strm),
+                       "rectangles"));
+    IsArgs ia;
+    memset(&ia, 0, sizeof ia);
+    ia.n = n;
+    ia.vn = (uint32_t)g.vn;
+    ia.chunk_off = s.chunk_off;
+    ia.chunk_total = s.chunk_total;
+    ia.mat = s.mat;
+    ia.mat_chunks = s.mat_chunks;
+    ia.cams = dc;
+    IsArgs l1 = ia;
+    l1.items = order_vd;
+    l1.item_rect = s.srect;
+    l1.out_cols = s.rowcols;
+    l1.bucket_count = s.row_count;
+    l1.bucket_start = s.row_start;
+    l1.out_vals = s.rowlist;
+    l1.out_cap = bins->m_cap;
     GESR_TRY(hip_check(ctx,
-                       launch_duplicate(order, s.offsets, g.vn, n, proj->tiles_touched, proj->rect, dc, bins->m_cap,
-                                        bins->counters, dup_keys, dup_vals, bins->inst_base, strm),
-                       "duplicate"));
-    if (passes > 0) {
-        GESR_TRY(hip_check(ctx,
-                           radix_sort(dup_keys, dup_vals, bins->m_cap, bins->counters + 2, tile_bits,
-                                      st->radix_bits, ib, &in_b, strm),
-                           "tile sort"));
-    }
-    // 4. per-tile ranges from per-tile counts (counting grids of the rectangles)
+                       launch_interval_scatter(l1, 1, (uint32_t)g.total_rows, s.counters, s.seg_chunks,
+                                               s.scan_partials, strm),
+                       "row lists"));
+    GESR_TRY(hip_check(ctx, launch_set_counters(s.counters, bins->m_cap, strm), "row counters"));
+    // 5. tile lists: every row-list entry in the tiles of its columns (level 2)
+    IsArgs l2 = ia;
+    l2.items = s.rowlist;
+    l2.item_cols = s.rowcols;
+    l2.items_listed = s.counters + 2;
+    l2.row_start = s.row_start;
+    l2.row_count = s.row_count;
+    l2.bucket_count = s.tile_count;
+    l2.bucket_start = s.tile_start;
+    l2.out_vals = bins->val_sorted;
+    l2.out_keys = bins->tile_sorted;
+    l2.out_cap = bins->m_cap;
     GESR_TRY(hip_check(ctx,
-                       launch_tile_counts(proj->tiles_touched, proj->rect, n, dc, (int)g.max_cells, s.partial_grids,
-                                          s.diff, s.tile_count, strm),
-                       "tile counts"));
-    GESR_TRY(hip_check(ctx, scan_exclusive(s.tile_count, s.tile_start, T, s.scan_partials, nullptr, strm),
-                       "tile count scan"));
+                       launch_interval_scatter(l2, 2, (uint32_t)T, nullptr, s.seg_chunks, s.scan_partials, strm),
+                       "tile lists"));
     GESR_TRY(hip_check(ctx, launch_ranges_from_counts(s.tile_count, s.tile_start, T, bins->counters + 2,
                                                       bins->ranges, strm),
                        "ranges"));

@@ -272,153 +272,354 @@ hipError_t sort_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, u
 }
 
 // ----------------------------------------------------------------- binning
-__global__ __launch_bounds__(256) void k_gather_counts(const uint32_t* order, const uint32_t* tiles_touched,
-                                                       uint32_t* out, uint64_t count) {
+__global__ __launch_bounds__(256) void k_gather_rects(const uint32_t* order, const uint32_t* tiles_touched,
+                                                      const uint32_t* rect, uint64_t count, uint2* out) {
     const uint64_t k = (uint64_t)blockIdx.x * 256 + threadIdx.x;
-    if (k < count) out[k] = tiles_touched[order[k]];
+    if (k >= count) return;
+    const uint32_t p = order[k];
+    out[k] = tiles_touched[p] ? reinterpret_cast<const uint2*>(rect)[p] : make_uint2(0xFFFFFFFFu, 0u);
 }
 
-// Instance expansion, load-balanced: a block owns DUP_SPLATS consecutive
-// (view, splat) pairs in depth order and writes their instances cooperatively
-// (instance j finds its pair by binary search over the block's offsets in
-// LDS), so every store is coalesced however large the rectangles are.
-constexpr int DUP_SPLATS = 256;
+// keys[k] = view of the pair vals[k] (pairs are numbered view * n + splat).
+__global__ __launch_bounds__(256) void k_view_keys(const uint32_t* vals, uint64_t count, uint32_t n, uint32_t* keys) {
+    const uint64_t k = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k < count) keys[k] = vals[k] / n;
+}
 
-__global__ __launch_bounds__(256) void k_duplicate(const uint32_t* order, const uint32_t* offsets, uint64_t count,
-                                                   int n, const uint32_t* tiles_touched, const uint32_t* rect,
-                                                   DevCams cams, uint64_t m_cap, const uint32_t* total,
-                                                   uint32_t* keys, uint32_t* vals, uint32_t* inst_base) {
-    __shared__ uint32_t s_off[DUP_SPLATS + 1];
-    __shared__ uint32_t s_vi[DUP_SPLATS];
-    __shared__ uint32_t s_r0[DUP_SPLATS];   // tx0 | ty0 << 16
-    __shared__ uint32_t s_w[DUP_SPLATS];    // rectangle width in tiles
-    __shared__ uint32_t s_row[DUP_SPLATS];  // tile_base of the view
-    __shared__ uint32_t s_tx[DUP_SPLATS];   // tiles_x of the view
-    const uint64_t k0 = (uint64_t)blockIdx.x * DUP_SPLATS;
-    const uint64_t k = k0 + threadIdx.x;
-    const uint32_t m_total = *total;
-    if (k < count) {
-        const uint32_t vi = order[k];
-        const uint32_t off = offsets[k];
-        inst_base[vi] = off;
-        s_off[threadIdx.x] = off;
-        s_vi[threadIdx.x] = vi;
-        const uint2 r = reinterpret_cast<const uint2*>(rect)[vi];
-        s_r0[threadIdx.x] = r.x;
-        s_w[threadIdx.x] = (r.y & 0xFFFFu) - (r.x & 0xFFFFu) + 1u;
-        const DevView& w = cams.v[vi / (uint32_t)n];
-        s_row[threadIdx.x] = w.tile_base;
-        s_tx[threadIdx.x] = (uint32_t)w.tiles_x;
+// ------------------------------------------------- interval scatter (lists)
+// A tile's list is every pair whose tile rectangle covers it, in (depth, pair)
+// order.  Rectangles are products of a row interval and a column interval, so
+// the lists are built in two stable bucketing levels without sorting
+// instances:
+//   level 1: pairs of a view, in depth order, go to the rows [ty0, ty1] they
+//            cover (row lists, one entry per pair and row);
+//   level 2: a row list's pairs go to the columns [tx0, tx1] they cover
+//            (tile lists, one entry per instance).
+// Each level is split into segments: an ordered item list and a window of at
+// most IS_W consecutive buckets (level 1: a view's rows 128k..128k+127; level
+// 2: a row's tiles 128k..128k+127).  A segment's items are cut into chunks of
+// IS_CHUNK (one item per lane of 16 waves).  In a wave, the items covering
+// bucket b are one ballot, and an item's rank among them is the popcount of
+// the lanes below it, so the order of equal buckets is the item order.
+// Per-(chunk, bucket) counts are scanned over a segment's chunks, bucket
+// totals over all buckets, and the scatter writes each item at bucket start
+// + chunk prefix + earlier waves + rank.  All arithmetic is integer and the
+// result is unique, independent of scheduling.
+constexpr int IS_W = 128;
+constexpr int IS_CHUNK = 1024;
+constexpr int IS_THREADS = 1024;
+constexpr int IS_WAVES = IS_THREADS / 64;
+
+struct Seg {
+    uint32_t begin, end;  // item range
+    uint32_t bucket0;     // global bucket id of local bucket 0
+    int lo_off;           // first row (level 1) / column (level 2) of the window
+    int width;            // buckets in the window (1..IS_W)
+};
+
+// Segment s of a level: level 1 enumerates (view, row block), level 2
+// (view, row, column block), both view-major.
+template <int LEVEL>
+__device__ __forceinline__ Seg locate_segment(const IsArgs& a, uint32_t s) {
+    Seg g;
+    uint32_t row_base = 0;
+    for (int v = 0; v < a.cams.V; ++v) {
+        const DevView& w = a.cams.v[v];
+        if (LEVEL == 1) {
+            const uint32_t nb = ((uint32_t)w.tiles_y + IS_W - 1) / IS_W;
+            if (s < nb) {
+                g.lo_off = (int)s * IS_W;
+                g.width = min(IS_W, w.tiles_y - g.lo_off);
+                g.bucket0 = row_base + (uint32_t)g.lo_off;
+                g.begin = (uint32_t)v * (uint32_t)a.n;
+                g.end = g.begin + (uint32_t)a.n;
+                return g;
+            }
+            s -= nb;
+        } else {
+            const uint32_t nb = ((uint32_t)w.tiles_x + IS_W - 1) / IS_W;
+            const uint32_t cnt = nb * (uint32_t)w.tiles_y;
+            if (s < cnt) {
+                const uint32_t ty = s / nb, k = s % nb;
+                g.lo_off = (int)k * IS_W;
+                g.width = min(IS_W, w.tiles_x - g.lo_off);
+                g.bucket0 = w.tile_base + ty * (uint32_t)w.tiles_x + (uint32_t)g.lo_off;
+                const uint32_t r = row_base + ty;
+                const uint32_t listed = *a.items_listed;
+                const uint32_t b0 = a.row_start[r], b1 = b0 + a.row_count[r];
+                g.begin = b0 < listed ? b0 : listed;
+                g.end = b1 < listed ? b1 : listed;
+                return g;
+            }
+            s -= cnt;
+        }
+        row_base += (uint32_t)w.tiles_y;
+    }
+    g.begin = g.end = 0;
+    g.bucket0 = 0;
+    g.lo_off = 0;
+    g.width = 0;
+    return g;
+}
+
+// Item idx of a segment: its value and its bucket interval [a0, a1] (empty when
+// a0 > a1) before windowing, and (level 1) the columns carried to level 2.
+// Both inputs are read in item order (coalesced).
+template <int LEVEL>
+__device__ __forceinline__ void load_item(const IsArgs& a, uint32_t idx, uint32_t end, uint32_t& p, int& a0,
+                                          int& a1, uint32_t& cols) {
+    p = 0xFFFFFFFFu;
+    a0 = 1;
+    a1 = 0;
+    cols = 0;
+    if (idx >= end) return;
+    p = a.items[idx];
+    if (LEVEL == 1) {
+        const uint2 r = a.item_rect[idx];
+        if (r.x == 0xFFFFFFFFu) return;
+        a0 = (int)(r.x >> 16);
+        a1 = (int)(r.y >> 16);
+        cols = (r.x & 0xFFFFu) | (r.y << 16);
     } else {
-        s_off[threadIdx.x] = m_total;
-    }
-    if (threadIdx.x == 0) s_off[DUP_SPLATS] = (k0 + DUP_SPLATS < count) ? offsets[k0 + DUP_SPLATS] : m_total;
-    __syncthreads();
-    const uint64_t begin = s_off[0];
-    const uint64_t end = min<uint64_t>(s_off[DUP_SPLATS], m_cap);
-    for (uint64_t j = begin + threadIdx.x; j < end; j += 256) {
-        // largest l with s_off[l] <= j (pairs with no instances are skipped over)
-        int lo = 0, hi = DUP_SPLATS;
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if ((uint64_t)s_off[mid] <= j) lo = mid;
-            else hi = mid;
-        }
-        const uint32_t q = (uint32_t)(j - s_off[lo]);
-        const uint32_t w = s_w[lo];
-        const uint32_t r0 = s_r0[lo];
-        const uint32_t ty = (r0 >> 16) + q / w, tx = (r0 & 0xFFFFu) + q % w;
-        keys[j] = s_row[lo] + ty * s_tx[lo] + tx;
-        vals[j] = s_vi[lo];
+        const uint32_t c = a.item_cols[idx];
+        a0 = (int)(c & 0xFFFFu);
+        a1 = (int)(c >> 16);
     }
 }
 
-// Per-tile instance counts from the rectangles: +1/-1 at the four corners of
-// each rectangle in a per-view (tiles_y + 1) x (tiles_x + 1) difference grid,
-// then a 2-D prefix sum.  Each block accumulates the corners of one chunk of
-// CORNER_CHUNK splats of one view in an LDS copy of the grid (LDS atomics;
-// integer sums, exact) and writes it out whole; k_tile_counts adds the
-// chunks' grids in fixed order and takes the prefix sums.
-constexpr int CORNER_CHUNK = 16384;
-constexpr size_t MAX_CORNER_LDS = 64 * 1024;
-
-__global__ __launch_bounds__(256) void k_rect_corners(const uint32_t* tiles_touched, const uint32_t* rect, int n,
-                                                      DevCams cams, uint32_t chunks, int* partial_grids) {
-    extern __shared__ int s_grid[];
-    const int v = blockIdx.y;
-    const uint32_t c = blockIdx.x;
-    const DevView& w = cams.v[v];
-    const uint32_t gx = (uint32_t)w.tiles_x + 1u;
-    const uint32_t cells = gx * ((uint32_t)w.tiles_y + 1u);
-    for (uint32_t k = threadIdx.x; k < cells; k += 256) s_grid[k] = 0;
-    __syncthreads();
-    const uint64_t i0 = (uint64_t)c * CORNER_CHUNK;
-    const uint64_t i1 = min<uint64_t>(i0 + CORNER_CHUNK, (uint64_t)n);
-    for (uint64_t i = i0 + threadIdx.x; i < i1; i += 256) {
-        const uint64_t vi = (uint64_t)v * (uint64_t)n + i;
-        if (tiles_touched[vi] == 0) continue;
-        const uint2 r = reinterpret_cast<const uint2*>(rect)[vi];
-        const uint32_t tx0 = r.x & 0xFFFFu, ty0 = r.x >> 16, tx1 = (r.y & 0xFFFFu) + 1u, ty1 = (r.y >> 16) + 1u;
-        atomicAdd(&s_grid[ty0 * gx + tx0], 1);
-        atomicAdd(&s_grid[ty0 * gx + tx1], -1);
-        atomicAdd(&s_grid[ty1 * gx + tx0], -1);
-        atomicAdd(&s_grid[ty1 * gx + tx1], 1);
-    }
-    __syncthreads();
-    int* dst = partial_grids + (uint64_t)w.grid_base * chunks + (uint64_t)c * cells;
-    for (uint32_t k = threadIdx.x; k < cells; k += 256) dst[k] = s_grid[k];
+__device__ __forceinline__ int wave_min_i(int x) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) x = min(x, __shfl_xor(x, d, 64));
+    return x;
 }
 
-// Views whose grid does not fit in LDS: corners go straight to the global grid
-// with global atomics (exact; slower under contention).
-__global__ __launch_bounds__(256) void k_rect_corners_global(const uint32_t* tiles_touched, const uint32_t* rect,
-                                                             uint64_t count, int n, DevCams cams, int* grid) {
-    const uint64_t vi = (uint64_t)blockIdx.x * 256 + threadIdx.x;
-    if (vi >= count || tiles_touched[vi] == 0) return;
-    const DevView& w = cams.v[(uint32_t)vi / (uint32_t)n];
-    const uint32_t gx = (uint32_t)w.tiles_x + 1u;
-    int* g = grid + w.grid_base;
-    const uint2 r = reinterpret_cast<const uint2*>(rect)[vi];
-    const uint32_t tx0 = r.x & 0xFFFFu, ty0 = r.x >> 16, tx1 = (r.y & 0xFFFFu) + 1u, ty1 = (r.y >> 16) + 1u;
-    atomicAdd(&g[ty0 * gx + tx0], 1);
-    atomicAdd(&g[ty0 * gx + tx1], -1);
-    atomicAdd(&g[ty1 * gx + tx0], -1);
-    atomicAdd(&g[ty1 * gx + tx1], 1);
+__device__ __forceinline__ int wave_max_i(int x) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) x = max(x, __shfl_xor(x, d, 64));
+    return x;
 }
 
-// One block per view: sum the chunks' grids per cell (ascending chunk order;
-// chunks == 0: the grid already holds the sums), then row and column prefix
-// sums give each tile's instance count.
-__global__ __launch_bounds__(256) void k_tile_counts(DevCams cams, uint32_t chunks, const int* partial_grids,
-                                                     int* grid, uint32_t* counts) {
-    const int v = blockIdx.x;
-    const DevView& w = cams.v[v];
-    const int gx = w.tiles_x + 1;
-    const uint32_t cells = (uint32_t)gx * (uint32_t)(w.tiles_y + 1);
-    int* g = grid + w.grid_base;
-    const int* src = partial_grids + (uint64_t)w.grid_base * chunks;
-    if (chunks > 0)
-        for (uint32_t k = threadIdx.x; k < cells; k += 256) {
-            int acc = 0;
-            for (uint32_t c = 0; c < chunks; ++c) acc += src[(uint64_t)c * cells + k];
-            g[k] = acc;
+// Chunk id -> segment: the largest s with chunk_off[s] <= cg.
+__device__ __forceinline__ uint32_t chunk_segment(const uint32_t* chunk_off, uint32_t nseg, uint32_t cg) {
+    uint32_t lo = 0, hi = nseg;  // answer in [lo, hi)
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (chunk_off[mid] <= cg) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Number of chunks of every segment.
+template <int LEVEL>
+__global__ __launch_bounds__(256) void k_is_seg_chunks(IsArgs a, uint32_t* chunks) {
+    const uint32_t s = blockIdx.x * 256 + threadIdx.x;
+    if (s >= a.nseg) return;
+    const Seg g = locate_segment<LEVEL>(a, s);
+    chunks[s] = (g.end - g.begin + IS_CHUNK - 1) / IS_CHUNK;
+}
+
+// Inclusive prefix over the IS_W entries row[0..IS_W) by one wave (two per lane).
+__device__ __forceinline__ void wave_prefix_row(int* row) {
+    const uint32_t lane = __lane_id();
+    const int x0 = row[2 * lane], x1 = row[2 * lane + 1];
+    int inc = x0 + x1;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int y = __shfl_up(inc, d, 64);
+        if (lane >= (uint32_t)d) inc += y;
+    }
+    row[2 * lane] = inc - x1;
+    row[2 * lane + 1] = inc;
+}
+
+// Count pass (MODE 0) and scatter pass (MODE 1) over the chunks; persistent
+// blocks stride over the device-side chunk count.  Per-wave bucket counts come
+// from difference arrays (+1 at lo, -1 at hi + 1; integer LDS atomics, order
+// free).  The scatter ranks items by ballots, stages the chunk's entries in
+// LDS grouped by bucket (at most IS_STAGE at a time, bucket windows) and
+// writes each bucket's run contiguously.
+constexpr int IS_STAGE = 12288;
+
+template <int LEVEL, int MODE>
+__global__ __launch_bounds__(IS_THREADS) void k_is_chunks(IsArgs a) {
+    __shared__ int s_cnt[IS_WAVES][IS_W + 1];
+    __shared__ uint32_t s_ls[IS_W + 1];  // chunk-local first entry of each bucket
+    __shared__ uint32_t s_gb[IS_W];      // global position of that entry
+    constexpr int STAGE = MODE == 0 ? 1 : (LEVEL == 1 ? IS_STAGE / 2 : IS_STAGE);
+    // + 64 slots that absorb the writes of lanes not covering the current bucket
+    __shared__ uint32_t s_stage[STAGE + 64];
+    __shared__ uint32_t s_stage_c[LEVEL == 1 && MODE == 1 ? STAGE + 64 : 1];
+    const uint32_t lane = __lane_id(), wave = threadIdx.x / 64;
+    // a contiguous share of the chunks per block: the segment is looked up once
+    // and the next chunk's items are loaded while the current one is processed
+    const uint32_t total = min<uint64_t>(*a.chunk_total, a.mat_chunks);
+    const uint32_t per = (total + gridDim.x - 1) / gridDim.x;
+    const uint32_t cbeg = blockIdx.x * per, cend = min(cbeg + per, total);
+    if (cbeg >= cend) return;
+    uint32_t s = chunk_segment(a.chunk_off, a.nseg, cbeg);
+    uint32_t s_first = a.chunk_off[s], s_next = a.chunk_off[s + 1];
+    Seg g = locate_segment<LEVEL>(a, s);
+    uint32_t idx = g.begin + (cbeg - s_first) * IS_CHUNK + threadIdx.x;
+    uint32_t p, cols;
+    int a0, a1;
+    load_item<LEVEL>(a, idx, g.end, p, a0, a1, cols);
+    for (uint32_t cg = cbeg; cg < cend;) {
+        // bucket bases of this chunk (scatter) are independent of the LDS work below
+        uint32_t gb = 0;
+        if (MODE == 1 && threadIdx.x < (uint32_t)g.width)
+            gb = a.bucket_start[g.bucket0 + threadIdx.x] + a.mat[(uint64_t)cg * IS_W + threadIdx.x];
+        const int lo = max(a0 - g.lo_off, 0), hi = min(a1 - g.lo_off, g.width - 1);
+        const bool same = cg + 1 < cend && cg + 1 < s_next;
+        const uint32_t idx_n = idx + IS_CHUNK;
+        uint32_t p_n, cols_n;
+        int a0_n, a1_n;
+        load_item<LEVEL>(a, idx_n, same ? g.end : 0u, p_n, a0_n, a1_n, cols_n);
+        const bool any = lo <= hi;
+        for (int j = threadIdx.x; j < IS_WAVES * (IS_W + 1); j += IS_THREADS) (&s_cnt[0][0])[j] = 0;
+        __syncthreads();
+        if (any) {
+            atomicAdd(&s_cnt[wave][lo], 1);
+            atomicAdd(&s_cnt[wave][hi + 1], -1);
         }
-    __syncthreads();
-    for (int y = threadIdx.x; y < w.tiles_y; y += 256) {
-        int run = 0;
-        for (int x = 0; x < w.tiles_x; ++x) {
-            run += g[y * gx + x];
-            g[y * gx + x] = run;
+        __syncthreads();
+        wave_prefix_row(s_cnt[wave]);  // s_cnt[w][b]: items of wave w covering bucket b
+        __syncthreads();
+        if (MODE == 0) {
+            if (threadIdx.x < (uint32_t)g.width) {
+                int acc = 0;
+#pragma unroll
+                for (int w = 0; w < IS_WAVES; ++w) acc += s_cnt[w][threadIdx.x];
+                a.mat[(uint64_t)cg * IS_W + threadIdx.x] = (uint32_t)acc;
+            }
+        } else {
+            // s_cnt[w][b] -> entries of earlier waves; s_ls: chunk-local bucket starts
+            if (threadIdx.x < IS_W) {
+                const uint32_t b = threadIdx.x;
+                int run = 0;
+#pragma unroll
+                for (int w = 0; w < IS_WAVES; ++w) {
+                    const int c = s_cnt[w][b];
+                    s_cnt[w][b] = run;
+                    run += c;
+                }
+                s_ls[b + 1] = (int)b < g.width ? (uint32_t)run : 0u;
+                if (b == 0) s_ls[0] = 0u;
+                s_gb[b] = gb;
+            }
+            __syncthreads();
+            if (wave == 0) wave_prefix_row(reinterpret_cast<int*>(s_ls + 1));
+            __syncthreads();
+            const int lo_w = __builtin_amdgcn_readfirstlane(wave_min_i(any ? lo : IS_W));
+            const int hi_w = __builtin_amdgcn_readfirstlane(wave_max_i(any ? hi : -1));
+            for (int b0 = 0; b0 < g.width;) {
+                // largest b1 with the window's entries fitting the stage (one bucket
+                // holds at most IS_CHUNK <= IS_STAGE entries)
+                int l = b0 + 1, h = g.width;
+                while (l < h) {
+                    const int mid = (l + h + 1) >> 1;
+                    if (s_ls[mid] - s_ls[b0] <= (uint32_t)STAGE) l = mid;
+                    else h = mid - 1;
+                }
+                const int b1 = l;
+                const uint32_t off0 = s_ls[b0];
+                const int bs = max(lo_w, b0), be = min(hi_w, b1 - 1);
+                if (bs <= be) {
+                    // stage offsets of buckets bs.., two per lane, read back with readlane;
+                    // branch-free: every lane writes, those off the bucket to their own
+                    // spare slot (an empty item has lo > hi)
+                    const int k0 = bs + (int)lane, k1 = bs + 64 + (int)lane;
+                    const uint32_t o0 = k0 <= be ? s_ls[k0] - off0 + (uint32_t)s_cnt[wave][k0] : 0u;
+                    const uint32_t o1 = k1 <= be ? s_ls[k1] - off0 + (uint32_t)s_cnt[wave][k1] : 0u;
+                    const uint32_t spare = (uint32_t)STAGE + lane;
+                    const int nb = be - bs + 1;
+                    // b in [lo, hi] as one unsigned compare; empty items never match
+                    const uint32_t ulo = any ? (uint32_t)lo : 0x80000000u;
+                    const uint32_t uspan = any ? (uint32_t)(hi - lo) : 0u;
+                    auto stage = [&](int b, uint32_t base) {
+                        const bool hit = (uint32_t)b - ulo <= uspan;
+                        const uint64_t m = __builtin_amdgcn_ballot_w64(hit);
+                        const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
+                            (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                        const uint32_t sel = 0u - (uint32_t)hit;  // all ones on the bucket
+                        const uint32_t q = spare ^ ((base + rank) ^ spare) & sel;
+                        s_stage[q] = p;
+                        if (LEVEL == 1) s_stage_c[q] = cols;
+                    };
+                    const int na = nb < 64 ? nb : 64;
+                    for (int k = 0; k < na; ++k) stage(bs + k, (uint32_t)__builtin_amdgcn_readlane((int)o0, k));
+                    for (int k = 64; k < nb; ++k)
+                        stage(bs + k, (uint32_t)__builtin_amdgcn_readlane((int)o1, k - 64));
+                }
+                __syncthreads();
+                for (int b = b0 + (int)wave; b < b1; b += IS_WAVES) {
+                    const uint32_t n_b = s_ls[b + 1] - s_ls[b];
+                    const uint32_t src = s_ls[b] - off0, dst = s_gb[b];
+                    for (uint32_t j = lane; j < n_b; j += 64) {
+                        const uint32_t pos = dst + j;
+                        if (pos < a.out_cap) {
+                            a.out_vals[pos] = s_stage[src + j];
+                            if (LEVEL == 1) a.out_cols[pos] = s_stage_c[src + j];
+                            if (a.out_keys) a.out_keys[pos] = g.bucket0 + (uint32_t)b;
+                        }
+                    }
+                }
+                __syncthreads();
+                b0 = b1;
+            }
+        }
+        __syncthreads();
+        ++cg;
+        if (cg >= cend) break;
+        if (same) {
+            idx = idx_n;
+            p = p_n;
+            cols = cols_n;
+            a0 = a0_n;
+            a1 = a1_n;
+        } else {
+            while (cg >= s_next) {
+                ++s;
+                s_first = s_next;
+                s_next = a.chunk_off[s + 1];
+            }
+            g = locate_segment<LEVEL>(a, s);
+            idx = g.begin + (cg - s_first) * IS_CHUNK + threadIdx.x;
+            load_item<LEVEL>(a, idx, g.end, p, a0, a1, cols);
         }
     }
+}
+
+// Per (segment, bucket): exclusive scan of the chunk counts over the
+// segment's chunks (in place) and the bucket total.  Eight threads per bucket
+// each take a contiguous share of the chunks.
+constexpr int IS_PARTS = 8;
+
+template <int LEVEL>
+__global__ __launch_bounds__(IS_W * IS_PARTS) void k_is_prefix(IsArgs a) {
+    __shared__ uint32_t s_part[IS_PARTS][IS_W];
+    const uint32_t s = blockIdx.x, b = threadIdx.x % IS_W, part = threadIdx.x / IS_W;
+    const Seg g = locate_segment<LEVEL>(a, s);
+    const uint32_t c0 = a.chunk_off[s];
+    const uint32_t c1 = min<uint64_t>(a.chunk_off[s + 1], a.mat_chunks);
+    const uint32_t nch = c1 > c0 ? c1 - c0 : 0u;
+    const uint32_t per = (nch + IS_PARTS - 1) / IS_PARTS;
+    const uint32_t r0 = c0 + min(part * per, nch), r1 = c0 + min((part + 1) * per, nch);
+    const bool live = (int)b < g.width;
+    uint32_t sum = 0;
+    if (live)
+        for (uint32_t c = r0; c < r1; ++c) sum += a.mat[(uint64_t)c * IS_W + b];
+    s_part[part][b] = sum;
     __syncthreads();
-    for (int x = threadIdx.x; x < w.tiles_x; x += 256) {
-        int run = 0;
-        for (int y = 0; y < w.tiles_y; ++y) {
-            run += g[y * gx + x];
-            counts[w.tile_base + (uint32_t)(y * w.tiles_x + x)] = (uint32_t)run;
-        }
+    if (!live) return;
+    uint32_t acc = 0;
+    for (uint32_t q = 0; q < part; ++q) acc += s_part[q][b];
+    for (uint32_t c = r0; c < r1; ++c) {
+        const uint32_t x = a.mat[(uint64_t)c * IS_W + b];
+        a.mat[(uint64_t)c * IS_W + b] = acc;
+        acc += x;
     }
+    if (part == IS_PARTS - 1) a.bucket_count[g.bucket0 + b] = acc;
 }
 
 // ranges[t] = [start, start + count), clamped to the instances actually listed
@@ -518,49 +719,68 @@ hipError_t radix_sort(const uint32_t* keys_in, const uint32_t* vals_in, uint64_t
     return hipSuccess;
 }
 
-hipError_t launch_gather_counts(const uint32_t* order, const uint32_t* tiles_touched, uint32_t* out, uint64_t count,
-                                hipStream_t stream) {
+hipError_t launch_gather_rects(const uint32_t* order, const uint32_t* tiles_touched, const uint32_t* rect,
+                               uint64_t count, uint2* out, hipStream_t stream) {
     if (count == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_gather_counts, grid_for(count), dim3(256), 0, stream, order, tiles_touched, out, count);
+    hipLaunchKernelGGL(k_gather_rects, grid_for(count), dim3(256), 0, stream, order, tiles_touched, rect, count, out);
     return hipGetLastError();
 }
 
-hipError_t launch_duplicate(const uint32_t* order, const uint32_t* offsets, uint64_t count, int n,
-                            const uint32_t* tiles_touched, const uint32_t* rect, const DevCams& cams,
-                            uint64_t m_cap, const uint32_t* total, uint32_t* keys, uint32_t* vals,
-                            uint32_t* inst_base, hipStream_t stream) {
+hipError_t launch_view_keys(const uint32_t* vals, uint64_t count, uint32_t n, uint32_t* keys, hipStream_t stream) {
     if (count == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_duplicate, dim3((unsigned)((count + DUP_SPLATS - 1) / DUP_SPLATS)), dim3(256), 0, stream,
-                       order, offsets, count, n, tiles_touched, rect, cams, m_cap, total, keys, vals, inst_base);
+    hipLaunchKernelGGL(k_view_keys, grid_for(count), dim3(256), 0, stream, vals, count, n, keys);
     return hipGetLastError();
 }
 
-uint32_t corner_chunks(int n) { return (uint32_t)((n + CORNER_CHUNK - 1) / CORNER_CHUNK); }
-
-hipError_t launch_tile_counts(const uint32_t* tiles_touched, const uint32_t* rect, int n, const DevCams& cams,
-                              int max_cells, int* partial_grids, int* grid, uint32_t* counts, hipStream_t stream) {
-    if (n == 0) {  // no splats: every count is zero
-        uint64_t total = 0;
-        for (int v = 0; v < cams.V; ++v) total += (uint64_t)cams.v[v].tiles_x * cams.v[v].tiles_y;
-        hipLaunchKernelGGL(k_fill_u32, grid_for(total), dim3(256), 0, stream, counts, 0u, total);
-        return hipGetLastError();
+uint32_t is_segments(const DevCams& cams, int level) {
+    uint32_t s = 0;
+    for (int v = 0; v < cams.V; ++v) {
+        const DevView& w = cams.v[v];
+        if (level == 1) s += ((uint32_t)w.tiles_y + IS_W - 1) / IS_W;
+        else s += ((uint32_t)w.tiles_x + IS_W - 1) / IS_W * (uint32_t)w.tiles_y;
     }
-    uint32_t chunks = corner_chunks(n);
-    const size_t lds = (size_t)max_cells * sizeof(int);
-    if (lds <= MAX_CORNER_LDS) {
-        hipLaunchKernelGGL(k_rect_corners, dim3(chunks, (unsigned)cams.V), dim3(256), lds, stream, tiles_touched, rect,
-                           n, cams, chunks, partial_grids);
+    return s;
+}
+
+uint64_t is_chunk_bound(const DevCams& cams, int level, int n, uint64_t level2_items) {
+    uint64_t c = 0;
+    if (level == 1) {
+        c = (uint64_t)is_segments(cams, 1) * (((uint64_t)n + IS_CHUNK - 1) / IS_CHUNK);
     } else {
-        uint64_t cells = 0, vn = (uint64_t)cams.V * (uint64_t)n;
-        for (int v = 0; v < cams.V; ++v) cells += (uint64_t)(cams.v[v].tiles_x + 1) * (cams.v[v].tiles_y + 1);
-        hipLaunchKernelGGL(k_fill_u32, grid_for(cells), dim3(256), 0, stream, reinterpret_cast<uint32_t*>(grid), 0u,
-                           cells);
-        hipLaunchKernelGGL(k_rect_corners_global, grid_for(vn), dim3(256), 0, stream, tiles_touched, rect, vn, n, cams,
-                           grid);
-        chunks = 0;
+        uint32_t nb_max = 1;
+        for (int v = 0; v < cams.V; ++v) {
+            const uint32_t nb = ((uint32_t)cams.v[v].tiles_x + IS_W - 1) / IS_W;
+            if (nb > nb_max) nb_max = nb;
+        }
+        c = is_segments(cams, 2) + nb_max * ((level2_items + IS_CHUNK - 1) / IS_CHUNK);
     }
-    hipLaunchKernelGGL(k_tile_counts, dim3((unsigned)cams.V), dim3(256), 0, stream, cams, chunks, partial_grids, grid,
-                       counts);
+    return c > 0 ? c : 1;
+}
+
+uint32_t is_window() { return IS_W; }
+
+hipError_t launch_interval_scatter(IsArgs a, int level, uint32_t n_buckets, uint32_t* bucket_total,
+                                   uint32_t* seg_chunks, uint32_t* scan_partials, hipStream_t stream) {
+    a.nseg = is_segments(a.cams, level);
+    if (a.nseg == 0) return hipSuccess;
+    const uint32_t grid = (uint32_t)(a.mat_chunks < 1024 ? a.mat_chunks : 1024);
+    auto seg_k = level == 1 ? k_is_seg_chunks<1> : k_is_seg_chunks<2>;
+    hipLaunchKernelGGL(seg_k, dim3((a.nseg + 255) / 256), dim3(256), 0, stream, a, seg_chunks);
+    // chunk_off = exclusive scan of the chunk counts (nseg + 1 entries: the
+    // last one, from a zero count, is the total)
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, stream, seg_chunks + a.nseg, 0u, (uint64_t)1);
+    hipError_t e = scan_exclusive(seg_chunks, const_cast<uint32_t*>(a.chunk_off), (uint64_t)a.nseg + 1, scan_partials,
+                                  const_cast<uint32_t*>(a.chunk_total), stream);
+    if (e != hipSuccess) return e;
+    auto count_k = level == 1 ? k_is_chunks<1, 0> : k_is_chunks<2, 0>;
+    hipLaunchKernelGGL(count_k, dim3(grid), dim3(IS_THREADS), 0, stream, a);
+    auto prefix_k = level == 1 ? k_is_prefix<1> : k_is_prefix<2>;
+    hipLaunchKernelGGL(prefix_k, dim3(a.nseg), dim3(IS_W * IS_PARTS), 0, stream, a);
+    e = scan_exclusive(a.bucket_count, const_cast<uint32_t*>(a.bucket_start), n_buckets, scan_partials, bucket_total,
+                       stream);
+    if (e != hipSuccess) return e;
+    auto scatter_k = level == 1 ? k_is_chunks<1, 1> : k_is_chunks<2, 1>;
+    hipLaunchKernelGGL(scatter_k, dim3(grid), dim3(IS_THREADS), 0, stream, a);
     return hipGetLastError();
 }
 

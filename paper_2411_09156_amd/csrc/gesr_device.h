@@ -18,7 +18,6 @@ struct DevView {
     int tiles_x, tiles_y;
     uint32_t tile_base;  // first global tile id of the view
     uint32_t pix_base;   // first pixel of the view in the concatenated outputs
-    uint32_t grid_base;  // offset of the view's (tiles_y + 1) x (tiles_x + 1) counting grid
 };
 
 struct DevCams {

@@ -105,19 +105,44 @@ hipError_t radix_sort(const uint32_t* keys_in, const uint32_t* vals_in, uint64_t
 int radix_passes(int key_bits, int radix_bits);
 
 // Binning helper kernels.
-hipError_t launch_gather_counts(const uint32_t* order, const uint32_t* tiles_touched, uint32_t* out, uint64_t count,
-                                hipStream_t stream);
-hipError_t launch_duplicate(const uint32_t* order, const uint32_t* offsets, uint64_t count, int n,
-                            const uint32_t* tiles_touched, const uint32_t* rect, const DevCams& cams,
-                            uint64_t m_cap, const uint32_t* total, uint32_t* keys, uint32_t* vals,
-                            uint32_t* inst_base, hipStream_t stream);
-// Per-tile instance counts (difference grid of rectangle corners, 2-D prefix).
-// View v's (tiles_y + 1) x (tiles_x + 1) grid starts at cams.v[v].grid_base in
-// `grid`; `partial_grids` holds corner_chunks(n) copies of every grid.
-// max_cells: the largest view grid (its LDS copy must fit one workgroup).
-uint32_t corner_chunks(int n);
-hipError_t launch_tile_counts(const uint32_t* tiles_touched, const uint32_t* rect, int n, const DevCams& cams,
-                              int max_cells, int* partial_grids, int* grid, uint32_t* counts, hipStream_t stream);
+hipError_t launch_view_keys(const uint32_t* vals, uint64_t count, uint32_t n, uint32_t* keys, hipStream_t stream);
+// out[k] = rect[order[k]], or the empty rectangle (x = 0xFFFFFFFF) when the pair touches no tile.
+hipError_t launch_gather_rects(const uint32_t* order, const uint32_t* tiles_touched, const uint32_t* rect,
+                               uint64_t count, uint2* out, hipStream_t stream);
+
+// Interval scatter (tile lists from rectangles, see gesr_bin.hip).  Level 1
+// writes each pair into the row lists of the rows its rectangle covers; level
+// 2 writes each row-list entry into the tile lists of the columns it covers.
+struct IsArgs {
+    int n;
+    uint32_t vn;
+    const uint32_t* items;          // level 1: pairs in (view, depth) order; level 2: row lists
+    const uint2* item_rect;         // level 1: the items' tile rectangles (empty: x = 0xFFFFFFFF)
+    const uint32_t* item_cols;      // level 2: the items' columns, tx0 | tx1 << 16
+    const uint32_t* items_listed;   // level 2: valid entries of the row lists (device)
+    const uint32_t* row_start;      // level 2: [total rows]
+    const uint32_t* row_count;      // level 2: [total rows]
+    uint32_t* chunk_off;            // [segments + 1]
+    uint32_t* chunk_total;          // device
+    uint32_t nseg;                  // set by launch_interval_scatter
+    uint32_t* mat;                  // [mat_chunks][window] per-chunk bucket counts, then prefixes
+    uint64_t mat_chunks;
+    uint32_t* bucket_count;         // [buckets]
+    uint32_t* bucket_start;         // [buckets]
+    uint32_t* out_vals;             // [out_cap]
+    uint32_t* out_keys;             // nullable: bucket id of every entry
+    uint32_t* out_cols;             // level 1: columns of every entry (tx0 | tx1 << 16)
+    uint64_t out_cap;
+    DevCams cams;
+};
+uint32_t is_segments(const DevCams& cams, int level);
+// Upper bound on the chunks of a level (level2_items: capacity of the row lists).
+uint64_t is_chunk_bound(const DevCams& cams, int level, int n, uint64_t level2_items);
+uint32_t is_window();
+// seg_chunks: [segments + 1] scratch.  Writes bucket_count, bucket_start and
+// the bucket total (*bucket_total, device) and scatters the items.
+hipError_t launch_interval_scatter(IsArgs a, int level, uint32_t n_buckets, uint32_t* bucket_total,
+                                   uint32_t* seg_chunks, uint32_t* scan_partials, hipStream_t stream);
 hipError_t launch_ranges_from_counts(const uint32_t* counts, const uint32_t* starts, uint64_t total_tiles,
                                      const uint32_t* listed, uint32_t* ranges, hipStream_t stream);
 hipError_t launch_set_counters(uint32_t* counters, uint64_t m_cap, hipStream_t stream);

@@ -113,8 +113,11 @@ class Rasterizer:
     """One rasterizer per (camera set, settings).  Calls enqueue on torch's
     current stream; outputs are freshly allocated device tensors."""
 
-    def __init__(self, cameras, settings: RasterSettings, device: int = 0):
+    def __init__(self, cameras, settings: RasterSettings, device: int = 0, store_tile_ids: bool = True):
+        """store_tile_ids=False leaves bins["tile_sorted"] out (the renderers
+        read only the ranges and the sorted pair ids)."""
         self.lib = _lib.load()
+        self.store_tile_ids = store_tile_ids
         self.cameras = list(cameras)
         self.V = len(self.cameras)
         self.settings = settings
@@ -169,7 +172,7 @@ class Rasterizer:
     def alloc_bins(self, n: int, m_cap: int) -> dict:
         sz = self.sizes(n, m_cap)
         T = int(sz.total_tiles)
-        return dict(m_cap=int(m_cap), tile_sorted=self._empty(m_cap, torch.int32),
+        return dict(m_cap=int(m_cap), tile_sorted=self._empty(m_cap, torch.int32) if self.store_tile_ids else None,
                     val_sorted=self._empty(m_cap, torch.int32), ranges=self._empty(2 * T, torch.int32),
                     worklist=self._empty(T, torch.int32), inst_base=self._empty(self.V * n, torch.int32),
                     counters=self._empty(4, torch.int32),
@@ -181,7 +184,7 @@ class Rasterizer:
         c = _lib.Bins()
         c.m_cap = b["m_cap"]
         for k in ("tile_sorted", "val_sorted", "ranges", "worklist", "inst_base", "counters", "scratch"):
-            setattr(c, k, b[k].data_ptr())
+            setattr(c, k, b[k].data_ptr() if b[k] is not None else 0)
         c.scratch_bytes = b["scratch"].numel()
         return c
 

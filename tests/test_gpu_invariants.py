@@ -420,9 +420,7 @@ def test_full_benchmark_workload():
         assert ((tx >= rr[:, 0]) & (tx <= rr[:, 2]) & (ty >= rr[:, 1]) & (ty <= rr[:, 3])).all()
     lens = ranges[:, 1].astype(np.int64) - ranges[:, 0]
     np.testing.assert_array_equal(worklist, np.lexsort((np.arange(T), -np.minimum(lens, 0xFFFF))))
-    order = np.argsort(dk, kind="stable")
-    base = np.zeros(VN, np.int64)
-    base[order] = np.concatenate([[0], np.cumsum(tt[order].astype(np.int64))[:-1]])
+    base = np.concatenate([[0], np.cumsum(tt.astype(np.int64))[:-1]])
     np.testing.assert_array_equal(u32(bins["inst_base"])[:VN], base)
     log("[gpu] full workload: binning properties hold")
 
@@ -476,3 +474,18 @@ def test_full_benchmark_workload():
     touched = (np.abs(g2).reshape(V, N, 10).max(axis=(0, 2)) > 0)
     assert not np.abs(got["means"][~touched]).any()
     log(f"[gpu] full workload: gradients of {int(touched.sum())} splats ok, worst {worst:.2e}")
+
+
+def test_tile_ids_are_optional():
+    """Leaving tile_sorted out (NULL) changes nothing else."""
+    scene, st = gi.make_workload(3, n_override=20_000), oracle.Settings()
+    sp = splats_of(scene)
+    a = _rast(scene, st).forward(sp)
+    from paper_2411_09156_amd import Rasterizer
+    b = Rasterizer(scene.cameras, raster_settings(st), store_tile_ids=False).forward(sp)
+    assert b["bins"]["tile_sorted"] is None
+    M = int(a["bins"]["M"])
+    np.testing.assert_array_equal(u32(a["bins"]["val_sorted"])[:M], u32(b["bins"]["val_sorted"])[:M])
+    for k in ("ranges", "worklist", "inst_base"):
+        np.testing.assert_array_equal(u32(a["bins"][k]), u32(b["bins"][k]), err_msg=k)
+    np.testing.assert_array_equal(f32(a["image"]), f32(b["image"]))

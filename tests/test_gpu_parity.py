@@ -149,10 +149,8 @@ def test_bin_bit_exact(name):
     lens = ranges[:, 1].astype(np.int64) - ranges[:, 0]
     expect = np.lexsort((np.arange(len(lens)), -np.minimum(lens, 0xFFFF)))
     np.testing.assert_array_equal(g["worklist"], expect)
-    # instance bases: exclusive scan of tiles_touched in stable depth order
-    order = np.argsort(g["depth_key"], kind="stable")
-    base = np.zeros_like(order)
-    base[order] = np.concatenate([[0], np.cumsum(g["tiles_touched"][order].astype(np.int64))[:-1]])
+    # instance slots: exclusive scan of tiles_touched in pair order
+    base = np.concatenate([[0], np.cumsum(g["tiles_touched"].astype(np.int64))[:-1]])
     np.testing.assert_array_equal(g["inst_base"], base)
 
 
