@@ -164,7 +164,7 @@ typedef struct {
     uint64_t total_tiles;      /* T: tiles over all views */
     uint64_t total_pixels;     /* P: pixels over all views */
     size_t bin_scratch_bytes;  /* gesr_bins.scratch size for the given m_cap */
-    size_t bwd_workspace_bytes; /* backward workspace (tile cuts, partials) for m_cap */
+    size_t bwd_workspace_bytes; /* backward workspace (visited bits, partials) for m_cap */
     uint64_t max_sort_blocks;  /* informational */
 } gesr_sizes;
 
@@ -223,9 +223,10 @@ gesr_status gesr_render_fwd(gesr_ctx* ctx, const gesr_proj* proj, const gesr_bin
  * atomics; a fixed-order segmented sum per (view, splat) then feeds the
  * projection adjoint, summed over views in ascending order.
  * `workspace` (DEVICE, gesr_sizes.bwd_workspace_bytes) holds, in order and
- * 256-byte aligned: the per-tile cut keys (uint64 [T]), the screen-space
- * gradients (float [V*n][10]) and the per-instance partials (float
- * [m_cap][10]).  grad2d (DEVICE [V*n][10], nullable) receives the
+ * 256-byte aligned: the visited bits (uint32 [ceil(m_cap / 32)], one bit per
+ * instance slot), the screen-space gradients (float [V*n][10]) and the
+ * per-instance partials (float [m_cap][10], indexed by instance slot, see
+ * inst_base).  grad2d (DEVICE [V*n][10], nullable) receives the
  * screen-space gradients du, dv, dL00, dL10, dL11, dopacity, dbeta, dr, dg, db
  * (dbeta here is the falloff term only; the phi(beta) term is added in the
  * projection adjoint).  `out` arrays are overwritten.  Results are bitwise
@@ -237,13 +238,12 @@ gesr_status gesr_render_bwd(gesr_ctx* ctx, const gesr_splats* splats, const gesr
 
 /* The two halves of gesr_render_bwd, for callers that schedule or time them
  * separately.  gesr_render_bwd_tiles: the per-tile render adjoint.  Each tile
- * visits its list up to the deepest position any of its pixels composited,
+ * visits its list up to the deepest position any of its pixels composited and
  * writes one gradient partial (10 floats, grad2d order) per visited instance
- * into the workspace and records the (depth key << 32 | view * n + splat) of
- * its first unvisited position (all ones when none): lists are strictly
- * increasing in that key, so an instance was visited iff its key is below its
- * tile's cut.  gesr_project_bwd: per (view, splat), the fixed-order sum of its
- * visited partials, then the projection adjoint (Eq. 4, 6-7 and the EWA
+ * with a non-zero contribution into the workspace, setting the instance
+ * slot's visited bit (the bits are cleared first).  gesr_project_bwd: per
+ * (view, splat), the fixed-order sum of the partials whose bits are set, then
+ * the projection adjoint (Eq. 4, 6-7 and the EWA
  * passage of Sec. 3.2) summed over views in ascending order.  Arguments as in
  * gesr_render_bwd; n = splats->n. */
 gesr_status gesr_render_bwd_tiles(gesr_ctx* ctx, const gesr_proj* proj, const gesr_bins* bins,

@@ -225,7 +225,7 @@ BinScratch carve(void* base, const Geometry& g, const DevCams& dc, int n, uint64
 
 // Layout of the backward workspace (256-byte aligned sub-buffers).
 struct BwdWorkspace {
-    uint64_t* tile_cut;  // [T]
+    uint32_t* visited;   // [ceil(m_cap / 32)] bit per instance slot
     float* grad2d;       // [V*n][10]
     float* partials;     // [m_cap][10]
     size_t bytes;
@@ -240,7 +240,7 @@ BwdWorkspace carve_bwd(void* base, uint64_t vn, uint64_t m_cap, uint64_t T) {
         off += ((bytes + 255) / 256) * 256;
         return p;
     };
-    w.tile_cut = (uint64_t*)take((T > 0 ? T : 1) * 8);
+    w.visited = (uint32_t*)take(((m_cap + 31) / 32) * 4);
     w.grad2d = (float*)take((vn > 0 ? vn : 1) * GESR_PARTIAL_FLOATS * 4);
     w.partials = (float*)take(m_cap * GESR_PARTIAL_FLOATS * 4);
     w.bytes = off;
@@ -553,11 +553,12 @@ gesr_status gesr_render_bwd_tiles(gesr_ctx* ctx, const gesr_proj* proj, const ge
     a.dL_dimage = dL_dimage;
     a.partials = ws.partials;
     a.m_cap = (uint32_t)bins->m_cap;
-    a.depth_key = proj->depth_key;
-    a.tile_cut = ws.tile_cut;
+    a.visited = ws.visited;
     a.st = dev_settings(st);
     a.cams = dev_cams(cams, V, st);
     const int batch = st->batch > 0 ? st->batch : 64;
+    GESR_TRY(hip_check(ctx, launch_fill_u32(ws.visited, 0u, (bins->m_cap + 31) / 32, (hipStream_t)stream),
+                       "visited bits"));
     GESR_TRY(hip_check(ctx, launch_render_bwd(a, st->tile_w, st->tile_h, batch, (hipStream_t)stream),
                        "render_bwd launch"));
     ctx->err.clear();
@@ -587,17 +588,13 @@ gesr_status gesr_project_bwd(gesr_ctx* ctx, const gesr_splats* splats, const ges
     const DevCams dc = dev_cams(cams, V, st);
     float* g2 = grad2d ? grad2d : ws.grad2d;
     SegReduceArgs r;
-    r.n = splats->n;
     r.vn = (uint32_t)g.vn;
     r.tiles_touched = proj->tiles_touched;
-    r.rect = proj->rect;
     r.inst_base = bins->inst_base;
-    r.depth_key = proj->depth_key;
-    r.tile_cut = ws.tile_cut;
+    r.visited = ws.visited;
     r.partials = ws.partials;
     r.m_cap = bins->m_cap;
     r.grad2d = g2;
-    r.cams = dc;
     GESR_TRY(hip_check(ctx, launch_seg_reduce(r, (hipStream_t)stream), "seg_reduce launch"));
     ProjectBwdArgs b;
     b.n = splats->n;

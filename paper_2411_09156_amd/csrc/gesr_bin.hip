@@ -542,7 +542,7 @@ __global__ __launch_bounds__(IS_THREADS) void k_is_chunks(IsArgs a) {
                         const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
                             (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
                         const uint32_t sel = 0u - (uint32_t)hit;  // all ones on the bucket
-                        const uint32_t q = spare ^ ((base + rank) ^ spare) & sel;
+                        const uint32_t q = spare ^ (((base + rank) ^ spare) & sel);
                         s_stage[q] = p;
                         if (LEVEL == 1) s_stage_c[q] = cols;
                     };

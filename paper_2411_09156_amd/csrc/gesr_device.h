@@ -102,6 +102,13 @@ __device__ __forceinline__ float row_sum_lane15(float x) {
     return s;
 }
 
+// Sum over each group of four lanes (quad_perm swaps); every lane of the quad
+// holds the same total (the two orders agree by commutativity).
+__device__ __forceinline__ float quad_sum(float x) {
+    const float s = x + dpp<0xb1, 0xf, 0xf>(x);  // quad_perm [1, 0, 3, 2]
+    return s + dpp<0x4e, 0xf, 0xf>(s);           // quad_perm [2, 3, 0, 1]
+}
+
 __device__ __forceinline__ float wave_sum_lane63(float x) {
     float s = x + dpp<0x111, 0xf, 0xf>(x);   // row_shr:1
     s = s + dpp<0x112, 0xf, 0xf>(x);         // row_shr:2

@@ -29,20 +29,16 @@ struct ProjectBwdArgs {
     DevCams cams;
 };
 
-// Segmented sum of the per-instance partials of each (view, splat), skipping
-// instances the render adjoint never visited (key >= its tile's cut).
+// Segmented sum of the per-instance partials of each (view, splat), reading
+// only the instance slots whose bit the render adjoint set in `visited`.
 struct SegReduceArgs {
-    int n;
     uint32_t vn;
     const uint32_t* tiles_touched;
-    const uint32_t* rect;
     const uint32_t* inst_base;
-    const uint32_t* depth_key;
-    const uint64_t* tile_cut;
+    const uint32_t* visited;  // [ceil(m_cap / 32)] bit per instance slot
     const float* partials;
     uint64_t m_cap;
     float* grad2d;
-    DevCams cams;
 };
 
 struct RenderArgs {
@@ -63,9 +59,8 @@ struct RenderArgs {
     // backward
     const float* dL_dimage;
     float* partials;
-    uint32_t m_cap;  // capacity of partials (instances); only reached when the lists overflowed
-    const uint32_t* depth_key;
-    uint64_t* tile_cut;  // per tile: (depth_key, vi) of the first unvisited position
+    uint32_t m_cap;      // capacity of partials (instances); only reached when the lists overflowed
+    uint32_t* visited;   // bit per instance slot, set where non-zero partials were written
     DevSettings st;
     DevCams cams;
 };

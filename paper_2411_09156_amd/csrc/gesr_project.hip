@@ -498,14 +498,15 @@ __global__ __launch_bounds__(256) void k_project_bwd(ProjectBwdArgs a) {
     for (int k = 0; k < K * 3; ++k) a.g_sh[(size_t)k * n + i] = gsh[k];
 }
 
-// Sixteen lanes (one DPP row) per (view, splat): lane l of the row sums the
-// partials of instances l, l + 16, ... that the render adjoint visited, then
-// a fixed DPP tree adds the row.  The order depends only on the pair's own
-// instances, so a batch of views and views rendered one at a time give
-// identical sums.
+// Four lanes (one DPP quad) per (view, splat).  The pair's instance slots
+// are contiguous (inst_base[vi] + j); lane l of the quad takes the blocks of
+// 32 instances m = l, l + 4, ... and, in ascending order, adds the partials of
+// the block's visited instances (set bits); a fixed DPP tree then adds the
+// quad.  The order depends only on the pair's own instances, so a batch of
+// views and views rendered one at a time give identical sums.
 __global__ __launch_bounds__(256) void k_seg_reduce(SegReduceArgs a) {
     constexpr int NP = GESR_PARTIAL_FLOATS;
-    constexpr uint32_t L = 16;
+    constexpr uint32_t L = 4;
     const uint64_t vi = ((uint64_t)blockIdx.x * 256u + threadIdx.x) / L;
     const uint32_t lane = __lane_id() & (L - 1);
     const bool valid = vi < a.vn;
@@ -515,43 +516,47 @@ __global__ __launch_bounds__(256) void k_seg_reduce(SegReduceArgs a) {
     bool any = false;
     const uint32_t cnt = valid ? a.tiles_touched[vi] : 0u;
     if (cnt > 0) {
-        const DevView& w = a.cams.v[(uint32_t)vi / (uint32_t)a.n];
-        const uint2 r = reinterpret_cast<const uint2*>(a.rect)[vi];
-        const uint32_t tx0 = r.x & 0xFFFFu, ty0 = r.x >> 16, width = (r.y & 0xFFFFu) - tx0 + 1u;
-        const uint64_t key = ((uint64_t)a.depth_key[vi] << 32) | (uint32_t)vi;
         const uint64_t base = a.inst_base[vi];
-        const float rw = 1.0f / (float)width;
-        for (uint32_t j = lane; j < cnt; j += L) {
-            // (row, column) of instance j in the rectangle: j / width by a float
-            // reciprocal (exact for j < 2^24 after one correction step)
-            int32_t qy = (int32_t)((float)j * rw);
-            int32_t rx = (int32_t)j - qy * (int32_t)width;
-            if (rx < 0) {
-                --qy;
-                rx += (int32_t)width;
-            } else if (rx >= (int32_t)width) {
-                ++qy;
-                rx -= (int32_t)width;
-            }
-            const uint32_t ty = ty0 + (uint32_t)qy, tx = tx0 + (uint32_t)rx;
-            const uint32_t t = w.tile_base + ty * (uint32_t)w.tiles_x + tx;
-            if (key < a.tile_cut[t] && base + j < a.m_cap) {
-                const float2* src = reinterpret_cast<const float2*>(a.partials + (base + j) * NP);
+        const uint64_t nwords = (a.m_cap + 31) / 32;
+        for (uint32_t j0 = lane * 32u; j0 < cnt; j0 += L * 32u) {
+            // visited bits of instances j0 .. j0 + 31 of this pair
+            const uint64_t s0 = base + j0;
+            const uint64_t wi = s0 >> 5;
+            const uint32_t sh = (uint32_t)(s0 & 31u);
+            const uint32_t w0 = wi < nwords ? a.visited[wi] : 0u;
+            const uint32_t w1 = (sh != 0u && wi + 1 < nwords) ? a.visited[wi + 1] : 0u;
+            uint32_t bits = sh != 0u ? (w0 >> sh) | (w1 << (32u - sh)) : w0;
+            if (cnt - j0 < 32u) bits &= (1u << (cnt - j0)) - 1u;
+            // up to four visited partials in flight, then added in ascending order
+            while (bits != 0u) {
+                float2 v[4][NP / 2];
+                bool have[4];
 #pragma unroll
-                for (int k = 0; k < NP / 2; ++k) {
-                    const float2 p2 = src[k];
-                    acc[2 * k] += p2.x;
-                    acc[2 * k + 1] += p2.y;
+                for (int u = 0; u < 4; ++u) {
+                    have[u] = bits != 0u;
+                    const uint32_t b = have[u] ? (uint32_t)__builtin_ctz(bits) : 0u;
+                    bits &= bits - 1u;
+                    const float2* src = reinterpret_cast<const float2*>(a.partials + (s0 + b) * NP);
+#pragma unroll
+                    for (int k = 0; k < NP / 2; ++k) v[u][k] = have[u] ? src[k] : make_float2(0.f, 0.f);
                 }
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (have[u])
+#pragma unroll
+                        for (int k = 0; k < NP / 2; ++k) {
+                            acc[2 * k] += v[u][k].x;
+                            acc[2 * k + 1] += v[u][k].y;
+                        }
                 any = true;
             }
         }
     }
     if (__ballot(any) != 0ull) {
 #pragma unroll
-        for (int k = 0; k < NP; ++k) acc[k] = row_sum_lane15(acc[k]);
+        for (int k = 0; k < NP; ++k) acc[k] = quad_sum(acc[k]);
     }
-    // rows without visited instances hold zeros; lane 15 of each row writes
+    // quads without visited instances hold zeros; lane 3 of each quad writes
     if (valid && lane == L - 1) {
         float2* out = reinterpret_cast<float2*>(a.grad2d + (size_t)vi * NP);
 #pragma unroll
@@ -575,7 +580,7 @@ hipError_t launch_project(const ProjectArgs& a, int sh_degree, hipStream_t strea
 
 hipError_t launch_seg_reduce(const SegReduceArgs& a, hipStream_t stream) {
     if (a.vn == 0) return hipSuccess;
-    const uint64_t threads = (uint64_t)a.vn * 16;
+    const uint64_t threads = (uint64_t)a.vn * 4;
     hipLaunchKernelGGL(k_seg_reduce, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, stream, a);
     return hipGetLastError();
 }

@@ -93,6 +93,20 @@ __device__ __forceinline__ uint32_t instance_index(const RenderArgs& a, uint2 r,
     return inside && inst < a.m_cap ? inst : kNoInstance;
 }
 
+// Partials of one instance: written, and its slot's bit set, unless all ten
+// are zero (the segmented sum adding +-0 or skipping the slot gives the same
+// float result, since its running sums start at +0).
+__device__ __forceinline__ void write_partial(const RenderArgs& a, uint32_t slot, const float* s) {
+    bool nz = false;
+#pragma unroll
+    for (int k = 0; k < GESR_PARTIAL_FLOATS; ++k) nz |= s[k] != 0.0f;
+    if (!nz) return;
+    float2* dst = reinterpret_cast<float2*>(a.partials + (size_t)slot * GESR_PARTIAL_FLOATS);
+#pragma unroll
+    for (int k = 0; k < GESR_PARTIAL_FLOATS / 2; ++k) dst[k] = make_float2(s[2 * k], s[2 * k + 1]);
+    atomicOr(a.visited + (slot >> 5), 1u << (slot & 31u));
+}
+
 template <int TW, int TH, bool COUNT>
 __global__ __launch_bounds__(TW * TH) void k_render_fwd(RenderArgs a) {
     constexpr int NT = TW * TH;
@@ -184,18 +198,7 @@ __global__ __launch_bounds__(TW * TH) void k_render_bwd(RenderArgs a) {
     __syncthreads();
     uint32_t maxnc = 0;
     for (int w = 0; w < NW; ++w) maxnc = max(maxnc, sMax[w]);
-    const uint32_t end = ti.r0 + maxnc;
-    // Positions >= end are never visited; record the (depth, index) key of the
-    // first of them so the segmented sum can tell visited instances apart
-    // (a tile list is strictly increasing in that key).
-    if (threadIdx.x == 0) {
-        uint64_t cut = ~0ull;
-        if (end < ti.r1) {
-            const uint32_t vc = a.val_sorted[end];
-            cut = ((uint64_t)a.depth_key[vc] << 32) | vc;
-        }
-        a.tile_cut[t] = cut;
-    }
+    const uint32_t end = ti.r0 + maxnc;  // positions >= end contributed to no pixel
 
     for (uint32_t hi = end; hi > ti.r0;) {
         const uint32_t lo = (hi - ti.r0 > (uint32_t)BATCH) ? hi - BATCH : ti.r0;
@@ -273,9 +276,7 @@ __global__ __launch_bounds__(TW * TH) void k_render_bwd(RenderArgs a) {
             for (int w = 1; w < NW; ++w)
 #pragma unroll
                 for (int k = 0; k < NP; ++k) s[k] += sRed[w][jj][k];
-            float2* dst = reinterpret_cast<float2*>(a.partials + (size_t)sInst[jj] * NP);
-#pragma unroll
-            for (int k = 0; k < NP / 2; ++k) dst[k] = make_float2(s[2 * k], s[2 * k + 1]);
+            write_partial(a, sInst[jj], s);
         }
         __syncthreads();
         hi = lo;
@@ -389,7 +390,7 @@ __global__ __launch_bounds__(64) void k_render_bwd_wave16(RenderArgs a) {
     const uint32_t lt = t - w.tile_base;
     const uint32_t tx = lt % (uint32_t)w.tiles_x, ty = lt / (uint32_t)w.tiles_x;
     const uint2 rg = reinterpret_cast<const uint2*>(a.ranges)[t];
-    const uint32_t r0 = rg.x, r1 = rg.y;
+    const uint32_t r0 = rg.x;
     const uint32_t ch = (uint32_t)w.W * (uint32_t)w.H;
 
     float px[4], py[4], T[4], g0[4], g1[4], g2[4], Br[4], Bg[4], Bb[4];
@@ -419,15 +420,7 @@ __global__ __launch_bounds__(64) void k_render_bwd_wave16(RenderArgs a) {
         mymax = max(mymax, nc[q]);
     }
     const uint32_t maxnc = wave_max_u32(mymax);
-    const uint32_t end = r0 + maxnc;
-    if (lane == 0) {
-        uint64_t cut = ~0ull;
-        if (end < r1) {
-            const uint32_t vc = a.val_sorted[end];
-            cut = ((uint64_t)a.depth_key[vc] << 32) | vc;
-        }
-        a.tile_cut[t] = cut;
-    }
+    const uint32_t end = r0 + maxnc;  // positions >= end contributed to no pixel
 
     for (uint32_t hi = end; hi > r0;) {
         const uint32_t lo = (hi - r0 > (uint32_t)B) ? hi - B : r0;
@@ -496,11 +489,7 @@ __global__ __launch_bounds__(64) void k_render_bwd_wave16(RenderArgs a) {
             }
         }
         __syncthreads();
-        if ((int)lane < cnt && sInst[lane] != kNoInstance) {
-            float2* dst = reinterpret_cast<float2*>(a.partials + (size_t)sInst[lane] * NP);
-#pragma unroll
-            for (int k = 0; k < NP / 2; ++k) dst[k] = make_float2(sRed[lane][2 * k], sRed[lane][2 * k + 1]);
-        }
+        if ((int)lane < cnt && sInst[lane] != kNoInstance) write_partial(a, sInst[lane], sRed[lane]);
         __syncthreads();
         hi = lo;
     }

@@ -225,7 +225,7 @@ class Rasterizer:
         return out
 
     def alloc_workspace(self, n: int, m_cap: int) -> torch.Tensor:
-        """Backward workspace (tile cuts, screen-space gradients, partials)."""
+        """Backward workspace (visited bits, screen-space gradients, partials)."""
         return torch.empty(int(self.sizes(n, m_cap).bwd_workspace_bytes), dtype=torch.uint8, device=self.device)
 
     def render_bwd(self, sp: Splats, proj: dict, bins: dict, final_T, n_contrib, dL_dimage,
