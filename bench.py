@@ -44,7 +44,8 @@ BWD_LISTED, BWD_HIT = 9, 73
 # against a 1 GiB copy; profiles/drt-500k-8views_hbm_counters.md).  Valid only
 # for the kernel source it was measured on (fingerprint below); otherwise null.
 MEASURED_TRAFFIC = {"kernel": "render_bwd_tiles", "workload": "drt-batch-500k-8views",
-                    "fingerprint": "273f3327350ed4ea", "bytes": 4233280949}
+                    "fingerprint": "273f3327350ed4ea", "bytes": 4233280949,
+                    "settings": (16, 16, 0, 64)}  # tile_w, tile_h, variant, batch of the measured run
 
 
 def kernel_fingerprint():
@@ -67,6 +68,8 @@ def parse_args():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-per-view", action="store_true")
     p.add_argument("--no-graph", action="store_true")
+    p.add_argument("--no-autotune", action="store_true",
+                   help="keep --tile/--batch instead of the autotuner's choice")
     p.add_argument("--cpu-sample-views", default="0,1,2,3,4,5")
     p.add_argument("--calibrate-copy", type=int, default=0,
                    help="also run a plain device copy of this many MiB (hardware counter calibration)")
@@ -138,6 +141,13 @@ def main():
 
     # ------------------------------------------------------------ sizing
     rast = Rasterizer(scene.cameras, rs, store_tile_ids=False)
+    tune = None
+    if not args.no_autotune:
+        log("[bench] autotuning tile shape, renderer, LDS batch and depth-sort digit width")
+        tune = rast.autotune(sp, reps=3)
+        rs = rast.settings
+        log(f"[bench] autotune chose tile {tune['tile']} variant {tune['variant']} batch {tune['batch']} "
+            f"radix {tune['radix_bits']}")
     log("[bench] sizing run (eager, synchronous count)")
     first = rast.forward(sp, sync=True, counts=True)
     M = int(first["bins"]["M"])
@@ -270,7 +280,8 @@ def main():
     peak = VALU_SLOTS_PER_S / 1e12
     traffic = None
     if (dom == MEASURED_TRAFFIC["kernel"] and scene.name == MEASURED_TRAFFIC["workload"]
-            and kernel_fingerprint() == MEASURED_TRAFFIC["fingerprint"] and args.tile == "16x16"):
+            and kernel_fingerprint() == MEASURED_TRAFFIC["fingerprint"]
+            and (rs.tile_w, rs.tile_h, rs.variant, rs.batch or 64) == MEASURED_TRAFFIC["settings"]):
         traffic = MEASURED_TRAFFIC["bytes"]
     roofline = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3), "peak": round(peak, 3),
                 "unit": "Tslot/s", "frac": round(achieved / peak, 4), "traffic": traffic,
@@ -287,11 +298,13 @@ def main():
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": scene.name, "splats": N, "views": V, "pixels": P,
                    "resolutions": [f"{c.width}x{c.height}" for c in scene.cameras], "sh_degree": scene.sh_degree,
-                   "tile": args.tile, "graph": not args.no_graph, "instances": M},
+                   "tile": f"{rs.tile_w}x{rs.tile_h}", "variant": rs.variant, "batch": rs.batch or 64,
+                   "radix_bits": rs.radix_bits, "graph": not args.no_graph, "instances": M},
         "fragments": {"listed": n_listed, "hit": n_hit,
                       "listed_per_s": round(n_listed / (ms * 1e-3), 1), "hit_per_s": round(n_hit / (ms * 1e-3), 1)},
         "stages_ms": stage_ms, "eager_ms_per_step": round(eager_ms, 4), "per_view": per_view,
         "roofline": roofline, "cpu_baseline": cpu, "wall_s_timed": round(wall, 3),
+        "autotune": tune,
     }
     print(json.dumps(out), flush=True)
 

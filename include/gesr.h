@@ -82,8 +82,10 @@ typedef struct {
     float blur, znear, clip_fac;
     float bg[3];
     int32_t tile_w, tile_h; /* supported: 16x16, 32x16, 32x32, 8x8 */
-    int32_t batch;          /* splats staged per LDS batch in the renderers (0 = auto) */
-    int32_t radix_bits;     /* digit width of the instance sort, 4..8 */
+    int32_t batch;          /* splats staged per LDS round in the renderers: 0 (= 64), 32,
+                               64 or 128 (128 only for the four-wave 16x16 and the 32x16
+                               backward; other kernels clamp to what their tile holds) */
+    int32_t radix_bits;     /* digit width of the depth sort of the (view, splat) pairs, 4..8 */
     int32_t variant;        /* 16x16 renderers: 0 = one wave per tile (4 px per lane),
                                1 = one workgroup of four waves per tile */
     int32_t reserved[3];
@@ -253,6 +255,30 @@ gesr_status gesr_render_bwd_tiles(gesr_ctx* ctx, const gesr_proj* proj, const ge
 gesr_status gesr_project_bwd(gesr_ctx* ctx, const gesr_splats* splats, const gesr_proj* proj, const gesr_bins* bins,
                              const gesr_camera* cams, int V, const gesr_settings* st, void* workspace,
                              float* grad2d, const gesr_grads* out, void* stream);
+
+/* Autotuner (set-up call; it allocates, synchronises and is not capturable).
+ * Times the whole forward + backward pipeline (gesr_project, gesr_bin with
+ * capacity exactly M, gesr_render_fwd, gesr_render_bwd) on the caller's splats
+ * and cameras, `reps` timed repetitions after one warm-up, for each candidate
+ * (tile shape, 16x16 renderer variant, LDS batch), then for the best of those
+ * each depth-sort digit width 5..8, and writes the fastest into *inout (the
+ * numeric settings are kept).  The upstream gradient is a constant.  Device
+ * buffers for the trials are allocated with hipMalloc and freed before
+ * returning.  times_ms (HOST, nullable, max_trials entries) receives each
+ * trial's milliseconds per pipeline (-1 for a trial that could not run, e.g.
+ * out of memory), in the order the candidates are listed by
+ * gesr_autotune_candidate; *n_trials (nullable) the number of trials run.
+ * n = 0: nothing to time, *inout unchanged.  Errors: GESR_ERR_INVALID for bad
+ * arguments (reps outside 1..100), GESR_ERR_HIP if no candidate could run. */
+gesr_status gesr_autotune(gesr_ctx* ctx, const gesr_splats* splats, const gesr_camera* cams, int V,
+                          gesr_settings* inout, int reps, float* times_ms, int max_trials, int* n_trials,
+                          void* stream);
+
+/* Candidate k of the autotuner's trial list (k = 0 .. count - 1, where count is
+ * returned by gesr_autotune_candidate(-1, ...)): writes its tile shape, variant,
+ * batch and radix bits into *out (other fields untouched).  Returns the number
+ * of candidates for k = -1, else 0 on success and -1 when k is out of range. */
+int gesr_autotune_candidate(int k, gesr_settings* out);
 
 /* L1 photometric term of Eq. 8 (the (1 - lambda) L1 part):
  * grad[i] = scale * sign(image[i] - target[i]) (sign(0) = 0), DEVICE, count

@@ -24,7 +24,7 @@ PARTIAL_FLOATS = 10
 EXPORTS = (
     "gesr_ctx_create", "gesr_ctx_destroy", "gesr_last_error", "gesr_status_string", "gesr_default_settings",
     "gesr_query_sizes", "gesr_project", "gesr_bin", "gesr_render_fwd", "gesr_render_bwd", "gesr_render_bwd_tiles",
-    "gesr_project_bwd", "gesr_l1_grad",
+    "gesr_project_bwd", "gesr_l1_grad", "gesr_autotune", "gesr_autotune_candidate",
 )
 
 c_float_p = ctypes.POINTER(ctypes.c_float)
@@ -125,6 +125,11 @@ def load():
     lib.gesr_project_bwd.restype = st
     lib.gesr_l1_grad.argtypes = [vp, vp, vp, ctypes.c_uint64, ctypes.c_float, vp, vp]
     lib.gesr_l1_grad.restype = st
+    lib.gesr_autotune.argtypes = [vp, P(Splats), P(Camera), ctypes.c_int, P(Settings), ctypes.c_int, c_float_p,
+                                  ctypes.c_int, P(ctypes.c_int), vp]
+    lib.gesr_autotune.restype = st
+    lib.gesr_autotune_candidate.argtypes = [ctypes.c_int, P(Settings)]
+    lib.gesr_autotune_candidate.restype = ctypes.c_int
     _lib = lib
     return lib
 

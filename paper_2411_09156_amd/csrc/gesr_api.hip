@@ -70,7 +70,8 @@ gesr_status check_settings(gesr_ctx* ctx, const gesr_settings* st) {
                     st->tile_w, st->tile_h);
     if (st->radix_bits < 4 || st->radix_bits > 8)
         return fail(ctx, GESR_ERR_INVALID, "radix_bits %d outside 4..8", st->radix_bits);
-    if (st->batch < 0) return fail(ctx, GESR_ERR_INVALID, "batch must be >= 0");
+    if (st->batch != 0 && st->batch != 32 && st->batch != 64 && st->batch != 128)
+        return fail(ctx, GESR_ERR_INVALID, "batch %d not in {0, 32, 64, 128}", st->batch);
     if (st->variant < 0 || st->variant > 1) return fail(ctx, GESR_ERR_INVALID, "variant must be 0 or 1");
     return GESR_OK;
 }
@@ -406,7 +407,7 @@ gesr_status gesr_bin(gesr_ctx* ctx, const gesr_proj* proj, const gesr_camera* ca
     // 1. depth order of the (view, splat) pairs: LSD passes over the 32 depth bits
     SortBuffers db{s.d_keys_a, s.d_vals_a, s.d_keys_b, s.d_vals_b, s.block_hist, s.scan_partials};
     bool in_b = false;
-    GESR_TRY(hip_check(ctx, radix_sort(proj->depth_key, nullptr, g.vn, nullptr, 32, 8, db, &in_b, strm),
+    GESR_TRY(hip_check(ctx, radix_sort(proj->depth_key, nullptr, g.vn, nullptr, 32, st->radix_bits, db, &in_b, strm),
                        "depth sort"));
     uint32_t* order = in_b ? s.d_vals_b : s.d_vals_a;
     uint32_t* spare_keys = in_b ? s.d_keys_a : s.d_keys_b;
@@ -510,6 +511,7 @@ gesr_status gesr_render_fwd(gesr_ctx* ctx, const gesr_proj* proj, const gesr_bin
     a.rect = proj->rect;
     a.inst_base = bins->inst_base;
     a.n_items = (uint32_t)g.total_tiles;
+    a.batch = st->batch > 0 ? st->batch : 64;
     a.image = image;
     a.final_T = final_T;
     a.n_contrib = n_contrib;
@@ -548,6 +550,7 @@ gesr_status gesr_render_bwd_tiles(gesr_ctx* ctx, const gesr_proj* proj, const ge
     a.rect = proj->rect;
     a.inst_base = bins->inst_base;
     a.n_items = (uint32_t)g.total_tiles;
+    a.batch = st->batch > 0 ? st->batch : 64;
     a.final_T = const_cast<float*>(final_T);
     a.n_contrib = const_cast<uint32_t*>(n_contrib);
     a.dL_dimage = dL_dimage;
@@ -638,6 +641,242 @@ gesr_status gesr_l1_grad(gesr_ctx* ctx, const float* image, const float* target,
     if (!isfinite(scale)) return fail(ctx, GESR_ERR_INVALID, "scale must be finite");
     GESR_TRY(hip_check(ctx, hipSetDevice(ctx->device), "hipSetDevice"));
     GESR_TRY(hip_check(ctx, launch_l1_grad(image, target, count, scale, grad, (hipStream_t)stream), "l1 launch"));
+    ctx->err.clear();
+    return GESR_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ autotuner
+namespace {
+
+struct Candidate {
+    int tw, th, variant, batch, radix;
+};
+// Renderer candidates (digit width 8), then digit widths for the best of them.
+constexpr Candidate kRenderCands[] = {{16, 16, 0, 64, 8},  {16, 16, 0, 32, 8}, {16, 16, 1, 64, 8},
+                                      {16, 16, 1, 128, 8}, {8, 8, 0, 64, 8},   {32, 16, 0, 64, 8},
+                                      {32, 16, 0, 128, 8}, {32, 32, 0, 64, 8}};
+constexpr int kNumRender = (int)(sizeof(kRenderCands) / sizeof(kRenderCands[0]));
+constexpr int kRadixCands[] = {7, 6, 5};
+constexpr int kNumCands = kNumRender + (int)(sizeof(kRadixCands) / sizeof(kRadixCands[0]));
+
+// Device buffer owned by one trial.
+struct DevBuf {
+    void* p = nullptr;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+    }
+    bool alloc(size_t bytes) {
+        release();
+        if (hipMalloc(&p, bytes > 256 ? bytes : 256) != hipSuccess) {
+            p = nullptr;
+            (void)hipGetLastError();
+            return false;
+        }
+        return true;
+    }
+    template <class T>
+    T* as() const {
+        return static_cast<T*>(p);
+    }
+};
+
+size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+// Milliseconds per forward + backward pipeline for settings `st`, or -1.
+float autotune_trial(gesr_ctx* ctx, const gesr_splats* sp, const gesr_camera* cams, int V, const gesr_settings& st,
+                     int reps, hipStream_t strm) {
+    Geometry g;
+    if (check_cams(ctx, cams, V, sp->n, &st, &g) != GESR_OK) return -1.f;
+    const int n = sp->n;
+    const uint64_t vn = g.vn, P = g.total_pixels, T = g.total_tiles;
+    const uint64_t K = (uint64_t)(st.sh_degree + 1) * (uint64_t)(st.sh_degree + 1);
+    DevBuf projbuf;
+    const size_t o_tt = align256(vn * GESR_REC_FLOATS * 4), o_rect = o_tt + align256(vn * 4),
+                 o_dk = o_rect + align256(vn * 8), proj_bytes = o_dk + align256(vn * 4);
+    if (!projbuf.alloc(proj_bytes)) return -1.f;
+    char* pb = projbuf.as<char>();
+    gesr_proj proj;
+    proj.rec = reinterpret_cast<float*>(pb);
+    proj.tiles_touched = reinterpret_cast<uint32_t*>(pb + o_tt);
+    proj.rect = reinterpret_cast<uint32_t*>(pb + o_rect);
+    proj.depth_key = reinterpret_cast<uint32_t*>(pb + o_dk);
+    if (gesr_project(ctx, sp, cams, V, &st, &proj, strm) != GESR_OK) return -1.f;
+
+    // bins with capacity exactly M (as a capturable caller would size them)
+    DevBuf binbuf;
+    gesr_bins bins;
+    auto alloc_bins = [&](uint64_t m_cap) -> bool {
+        gesr_sizes sz;
+        if (gesr_query_sizes(ctx, cams, V, n, &st, m_cap, &sz) != GESR_OK) return false;
+        const size_t o_rng = align256(m_cap * 4), o_wl = o_rng + align256(T * 8), o_ib = o_wl + align256(T * 4),
+                     o_cnt = o_ib + align256((vn > 0 ? vn : 1) * 4), o_scr = o_cnt + 256,
+                     bytes = o_scr + align256(sz.bin_scratch_bytes);
+        if (!binbuf.alloc(bytes)) return false;
+        char* b = binbuf.as<char>();
+        bins.m_cap = m_cap;
+        bins.tile_sorted = nullptr;
+        bins.val_sorted = reinterpret_cast<uint32_t*>(b);
+        bins.ranges = reinterpret_cast<uint32_t*>(b + o_rng);
+        bins.worklist = reinterpret_cast<uint32_t*>(b + o_wl);
+        bins.inst_base = reinterpret_cast<uint32_t*>(b + o_ib);
+        bins.counters = reinterpret_cast<uint32_t*>(b + o_cnt);
+        bins.scratch = b + o_scr;
+        bins.scratch_bytes = sz.bin_scratch_bytes;
+        return true;
+    };
+    uint64_t m_cap = std::max<uint64_t>(4 * vn, 1024), M = 0;
+    for (int attempt = 0;; ++attempt) {
+        if (attempt == 3 || !alloc_bins(m_cap)) return -1.f;
+        uint64_t m = 0;
+        const gesr_status r = gesr_bin(ctx, &proj, cams, V, n, &st, &bins, GESR_BIN_SYNC, &m, strm);
+        if (r == GESR_OK) {
+            M = m;
+            break;
+        }
+        if (r != GESR_ERR_CAPACITY) return -1.f;
+        m_cap = m + 1;
+    }
+    if (std::max<uint64_t>(M, 1) != m_cap && !alloc_bins(std::max<uint64_t>(M, 1))) return -1.f;
+    gesr_sizes sz;
+    if (gesr_query_sizes(ctx, cams, V, n, &st, bins.m_cap, &sz) != GESR_OK) return -1.f;
+
+    DevBuf outbuf, wsbuf, gradbuf;
+    const size_t o_T = align256(3 * P * 4), o_nc = o_T + align256(P * 4), o_dL = o_nc + align256(P * 4),
+                 out_bytes = o_dL + align256(3 * P * 4);
+    if (!outbuf.alloc(out_bytes) || !wsbuf.alloc(sz.bwd_workspace_bytes)) return -1.f;
+    char* ob = outbuf.as<char>();
+    float* image = reinterpret_cast<float*>(ob);
+    float* final_T = reinterpret_cast<float*>(ob + o_T);
+    uint32_t* n_contrib = reinterpret_cast<uint32_t*>(ob + o_nc);
+    float* dL = reinterpret_cast<float*>(ob + o_dL);
+    const float unit = 1.0f / (float)(3 * (P > 0 ? P : 1));
+    uint32_t unit_bits;
+    memcpy(&unit_bits, &unit, 4);
+    if (launch_fill_u32(reinterpret_cast<uint32_t*>(dL), unit_bits, 3 * P, strm) != hipSuccess) return -1.f;
+    const uint64_t nn = (uint64_t)(n > 0 ? n : 1);
+    const size_t gsz[6] = {3 * nn * 4, 3 * nn * 4, 4 * nn * 4, nn * 4, nn * 4, 3 * K * nn * 4};
+    size_t goff[6], gbytes = 0;
+    for (int k = 0; k < 6; ++k) {
+        goff[k] = gbytes;
+        gbytes += align256(gsz[k]);
+    }
+    if (!gradbuf.alloc(gbytes)) return -1.f;
+    char* gb = gradbuf.as<char>();
+    gesr_grads grads;
+    grads.mean = reinterpret_cast<float*>(gb + goff[0]);
+    grads.scale = reinterpret_cast<float*>(gb + goff[1]);
+    grads.quat = reinterpret_cast<float*>(gb + goff[2]);
+    grads.opacity = reinterpret_cast<float*>(gb + goff[3]);
+    grads.beta = reinterpret_cast<float*>(gb + goff[4]);
+    grads.sh = reinterpret_cast<float*>(gb + goff[5]);
+
+    auto pipeline = [&]() -> bool {
+        return gesr_project(ctx, sp, cams, V, &st, &proj, strm) == GESR_OK &&
+               gesr_bin(ctx, &proj, cams, V, n, &st, &bins, 0, nullptr, strm) == GESR_OK &&
+               gesr_render_fwd(ctx, &proj, &bins, cams, V, n, &st, image, final_T, n_contrib, nullptr, strm) ==
+                   GESR_OK &&
+               gesr_render_bwd(ctx, sp, &proj, &bins, cams, V, &st, final_T, n_contrib, dL, wsbuf.p, nullptr,
+                               &grads, strm) == GESR_OK;
+    };
+    if (!pipeline()) return -1.f;  // warm-up
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return -1.f;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return -1.f;
+    }
+    float ms = -1.f;
+    bool ok = hipEventRecord(e0, strm) == hipSuccess;
+    for (int r = 0; ok && r < reps; ++r) ok = pipeline();
+    ok = ok && hipEventRecord(e1, strm) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+         hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (!ok) return -1.f;
+    // a capacity overflow would mean the timing covered truncated lists
+    uint32_t cnt[2] = {0, 0};
+    if (hipMemcpyAsync(cnt, bins.counters, sizeof cnt, hipMemcpyDeviceToHost, strm) != hipSuccess ||
+        hipStreamSynchronize(strm) != hipSuccess || cnt[1] != 0)
+        return -1.f;
+    return ms / (float)reps;
+}
+
+void apply_candidate(const Candidate& c, gesr_settings* s) {
+    s->tile_w = c.tw;
+    s->tile_h = c.th;
+    s->variant = c.variant;
+    s->batch = c.batch;
+    s->radix_bits = c.radix;
+}
+
+}  // namespace
+
+extern "C" {
+
+int gesr_autotune_candidate(int k, gesr_settings* out) {
+    if (k == -1) return kNumCands;
+    if (k < 0 || k >= kNumCands || !out) return -1;
+    if (k < kNumRender) apply_candidate(kRenderCands[k], out);
+    else out->radix_bits = kRadixCands[k - kNumRender];
+    return 0;
+}
+
+gesr_status gesr_autotune(gesr_ctx* ctx, const gesr_splats* splats, const gesr_camera* cams, int V,
+                          gesr_settings* inout, int reps, float* times_ms, int max_trials, int* n_trials,
+                          void* stream) {
+    if (!ctx) return GESR_ERR_INVALID;
+    if (!inout) return fail(ctx, GESR_ERR_INVALID, "inout is NULL");
+    if (reps < 1 || reps > 100) return fail(ctx, GESR_ERR_INVALID, "reps %d outside 1..100", reps);
+    if (times_ms && max_trials < 0) return fail(ctx, GESR_ERR_INVALID, "max_trials is negative");
+    GESR_TRY(check_settings(ctx, inout));
+    GESR_TRY(check_splats(ctx, splats, inout->sh_degree, false));
+    Geometry g;
+    GESR_TRY(check_cams(ctx, cams, V, splats->n, inout, &g));
+    if (n_trials) *n_trials = 0;
+    if (splats->n == 0) {
+        ctx->err.clear();
+        return GESR_OK;
+    }
+    GESR_TRY(hip_check(ctx, hipSetDevice(ctx->device), "hipSetDevice"));
+    hipStream_t strm = (hipStream_t)stream;
+    int trials = 0, best = -1;
+    float best_ms = 0.f;
+    auto record = [&](float ms) {
+        if (times_ms && trials < max_trials) times_ms[trials] = ms;
+        ++trials;
+    };
+    for (int k = 0; k < kNumRender; ++k) {
+        gesr_settings s = *inout;
+        apply_candidate(kRenderCands[k], &s);
+        const float ms = autotune_trial(ctx, splats, cams, V, s, reps, strm);
+        record(ms);
+        if (ms >= 0.f && (best < 0 || ms < best_ms)) {
+            best = k;
+            best_ms = ms;
+        }
+    }
+    if (best < 0) return fail(ctx, GESR_ERR_HIP, "no autotuner candidate could run");
+    gesr_settings chosen = *inout;
+    apply_candidate(kRenderCands[best], &chosen);
+    for (int k = 0; k < kNumCands - kNumRender; ++k) {
+        gesr_settings s = chosen;
+        s.radix_bits = kRadixCands[k];
+        const float ms = autotune_trial(ctx, splats, cams, V, s, reps, strm);
+        record(ms);
+        if (ms >= 0.f && ms < best_ms) {
+            best_ms = ms;
+            chosen.radix_bits = s.radix_bits;
+        }
+    }
+    *inout = chosen;
+    if (n_trials) *n_trials = trials;
     ctx->err.clear();
     return GESR_OK;
 }

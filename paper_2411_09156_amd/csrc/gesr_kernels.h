@@ -50,6 +50,7 @@ struct RenderArgs {
     const uint32_t* rect;
     const uint32_t* inst_base;
     uint32_t n_items;  // number of work items (tiles) in the worklist
+    int batch;         // records staged in LDS per round (one-wave renderers: 32 or 64)
     // forward outputs / backward inputs
     float* image;
     float* final_T;

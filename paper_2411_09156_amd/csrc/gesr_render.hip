@@ -286,9 +286,9 @@ __global__ __launch_bounds__(TW * TH) void k_render_bwd(RenderArgs a) {
 // Forward, one wave per 16x16 tile with 4 pixels per lane (one per 8x8
 // quadrant): a staged splat's LDS reads serve 256 pixels; the wave leaves the
 // tile once all its pixels have terminated.
-template <bool COUNT>
+template <bool COUNT, int B>
 __global__ __launch_bounds__(64) void k_render_fwd_wave16(RenderArgs a) {
-    constexpr int B = 64;
+    static_assert(B >= 1 && B <= 64, "one staged record per lane");
     __shared__ float4 sA[B], sB[B], sC[B];
     const uint32_t t = a.worklist[blockIdx.x];
     const DevSettings& st = a.st;
@@ -319,7 +319,7 @@ __global__ __launch_bounds__(64) void k_render_fwd_wave16(RenderArgs a) {
         const bool all_done = done[0] && done[1] && done[2] && done[3];
         if (__ballot(!all_done) == 0ull) break;
         const uint32_t pos = base + lane;
-        if (pos < r1) stage_record(a.rec, a.val_sorted[pos], sA[lane], sB[lane], sC[lane]);
+        if ((int)lane < B && pos < r1) stage_record(a.rec, a.val_sorted[pos], sA[lane], sB[lane], sC[lane]);
         __syncthreads();
         const int cnt = (int)min<uint32_t>(B, r1 - base);
         for (int j = 0; j < cnt; ++j) {
@@ -375,9 +375,10 @@ __global__ __launch_bounds__(64) void k_render_fwd_wave16(RenderArgs a) {
 // 8x8 quadrant (4 pixels per lane), so a staged splat's LDS reads and its
 // 10-value wave reduction serve 256 pixels, and no cross-wave reduction or
 // workgroup barrier beyond the wave itself is needed.
+template <int B>
 __global__ __launch_bounds__(64) void k_render_bwd_wave16(RenderArgs a) {
+    static_assert(B >= 1 && B <= 64, "one staged record per lane");
     constexpr int NP = GESR_PARTIAL_FLOATS;
-    constexpr int B = 64;
     __shared__ float4 sA[B], sB[B], sC[B];
     __shared__ uint32_t sInst[B];
     __shared__ float sRed[B][NP + 1];
@@ -516,10 +517,14 @@ hipError_t launch_render_fwd(const RenderArgs& a, int tw, int th, bool counts, h
     if (a.n_items == 0) return hipSuccess;
     if (tw == 16 && th == 16) {
         if (a.st.variant == 1) return fwd_shape<16, 16>(a, counts, s);
-        if (counts)
-            hipLaunchKernelGGL(k_render_fwd_wave16<true>, dim3(a.n_items), dim3(64), 0, s, a);
-        else
-            hipLaunchKernelGGL(k_render_fwd_wave16<false>, dim3(a.n_items), dim3(64), 0, s, a);
+        const bool small = a.batch == 32;
+        if (counts) {
+            if (small) hipLaunchKernelGGL((k_render_fwd_wave16<true, 32>), dim3(a.n_items), dim3(64), 0, s, a);
+            else hipLaunchKernelGGL((k_render_fwd_wave16<true, 64>), dim3(a.n_items), dim3(64), 0, s, a);
+        } else {
+            if (small) hipLaunchKernelGGL((k_render_fwd_wave16<false, 32>), dim3(a.n_items), dim3(64), 0, s, a);
+            else hipLaunchKernelGGL((k_render_fwd_wave16<false, 64>), dim3(a.n_items), dim3(64), 0, s, a);
+        }
         return hipGetLastError();
     }
     if (tw == 8 && th == 8) return fwd_shape<8, 8>(a, counts, s);
@@ -531,8 +536,10 @@ hipError_t launch_render_fwd(const RenderArgs& a, int tw, int th, bool counts, h
 hipError_t launch_render_bwd(const RenderArgs& a, int tw, int th, int batch, hipStream_t s) {
     if (a.n_items == 0) return hipSuccess;
     if (tw == 16 && th == 16) {
-        if (a.st.variant == 1) return bwd_shape<16, 16, 64>(a, s);  // one workgroup of 4 waves per tile
-        hipLaunchKernelGGL(k_render_bwd_wave16, dim3(a.n_items), dim3(64), 0, s, a);
+        if (a.st.variant == 1)  // one workgroup of 4 waves per tile
+            return batch >= 128 ? bwd_shape<16, 16, 128>(a, s) : bwd_shape<16, 16, 64>(a, s);
+        if (batch == 32) hipLaunchKernelGGL(k_render_bwd_wave16<32>, dim3(a.n_items), dim3(64), 0, s, a);
+        else hipLaunchKernelGGL(k_render_bwd_wave16<64>, dim3(a.n_items), dim3(64), 0, s, a);
         return hipGetLastError();
     }
     if (tw == 8 && th == 8) return bwd_shape<8, 8, 64>(a, s);

@@ -272,6 +272,34 @@ class Rasterizer:
         out.update(proj=proj, bins=bins)
         return out
 
+    def autotune(self, sp: Splats, reps: int = 3) -> dict:
+        """Times the fwd+bwd pipeline for the library's candidate (tile shape,
+        renderer variant, LDS batch) list and then depth-sort digit widths, on
+        these splats and cameras, and adopts the fastest.  Returns the chosen
+        settings and every trial's milliseconds (-1: could not run)."""
+        st = _lib.Settings()
+        ctypes.memmove(ctypes.byref(st), ctypes.byref(self.st_c), ctypes.sizeof(st))
+        ncand = self.lib.gesr_autotune_candidate(-1, None)
+        times = (ctypes.c_float * ncand)()
+        ntr = ctypes.c_int(0)
+        self._check(self.lib.gesr_autotune(self.ctx, ctypes.byref(sp.to_c()), self.cams_c, self.V, ctypes.byref(st),
+                                           int(reps), times, ncand, ctypes.byref(ntr), _stream()), self.ctx)
+        trials = []
+        for k in range(ntr.value):
+            c = _lib.Settings()  # zero tile: a digit-width trial (run with the chosen renderer)
+            self.lib.gesr_autotune_candidate(k, c)
+            stage = 1 if c.tile_w > 0 else 2
+            if stage == 2:
+                c.tile_w, c.tile_h, c.variant, c.batch = st.tile_w, st.tile_h, st.variant, st.batch
+            trials.append(dict(stage=stage, tile=f"{c.tile_w}x{c.tile_h}", variant=c.variant, batch=c.batch,
+                               radix_bits=c.radix_bits, ms=float(times[k])))
+        self.settings = dataclasses.replace(self.settings, tile_w=st.tile_w, tile_h=st.tile_h, variant=st.variant,
+                                            batch=st.batch, radix_bits=st.radix_bits)
+        self.st_c = self.settings.to_c()
+        self.m_cap_hint = 0
+        return dict(tile=f"{st.tile_w}x{st.tile_h}", variant=st.variant, batch=st.batch, radix_bits=st.radix_bits,
+                    trials=trials)
+
     def split_images(self, flat: torch.Tensor) -> List[torch.Tensor]:
         out, off = [], 0
         for w, h in self.views:

@@ -155,3 +155,53 @@ def test_null_and_misaligned_pointers_rejected_before_launch(lib):
 def test_status_strings(lib):
     for s in range(5):
         assert len(lib.gesr_status_string(s)) > 0
+
+
+def test_autotune_candidates_are_valid_settings(lib):
+    n = lib.gesr_autotune_candidate(-1, None)
+    assert n >= 8
+    ctx = _ctx(lib)
+    cams = cameras_to_c([_Cam(64, 48), _Cam(33, 17)])
+    seen = set()
+    for k in range(n):
+        st = RasterSettings().to_c()
+        assert lib.gesr_autotune_candidate(k, ctypes.byref(st)) == 0
+        out = _lib.Sizes()
+        assert lib.gesr_query_sizes(ctx, cams, 2, 100, ctypes.byref(st), 5000, ctypes.byref(out)) == _lib.GESR_OK
+        seen.add((st.tile_w, st.tile_h, st.variant, st.batch, st.radix_bits))
+    assert len(seen) == n
+    assert lib.gesr_autotune_candidate(n, ctypes.byref(_lib.Settings())) == -1
+    lib.gesr_ctx_destroy(ctx)
+
+
+def test_autotune_rejects_bad_arguments_on_the_host(lib):
+    ctx = _ctx(lib)
+    cams = cameras_to_c([_Cam()])
+    st = RasterSettings().to_c()
+    sp = _lib.Splats(10, 16, 32, 48, 64, 80, 96)
+    times = (ctypes.c_float * 4)()
+    nt = ctypes.c_int(-1)
+    for reps in (0, 101):
+        assert lib.gesr_autotune(ctx, ctypes.byref(sp), cams, 1, ctypes.byref(st), reps, times, 4, ctypes.byref(nt),
+                                 None) == _lib.GESR_ERR_INVALID
+    assert lib.gesr_autotune(ctx, ctypes.byref(sp), cams, 1, None, 3, times, 4, ctypes.byref(nt),
+                             None) == _lib.GESR_ERR_INVALID
+    # no splats: nothing to time, settings unchanged
+    empty = _lib.Splats(0, 0, 0, 0, 0, 0, 0)
+    before = (st.tile_w, st.tile_h, st.batch, st.radix_bits, st.variant)
+    assert lib.gesr_autotune(ctx, ctypes.byref(empty), cams, 1, ctypes.byref(st), 3, times, 4, ctypes.byref(nt),
+                             None) == _lib.GESR_OK
+    assert nt.value == 0 and (st.tile_w, st.tile_h, st.batch, st.radix_bits, st.variant) == before
+    lib.gesr_ctx_destroy(ctx)
+
+
+@pytest.mark.parametrize("batch,status", [(16, _lib.GESR_ERR_INVALID), (96, _lib.GESR_ERR_INVALID),
+                                          (32, _lib.GESR_OK), (128, _lib.GESR_OK)])
+def test_batch_values(lib, batch, status):
+    ctx = _ctx(lib)
+    cams = cameras_to_c([_Cam()])
+    st = RasterSettings().to_c()
+    st.batch = batch
+    out = _lib.Sizes()
+    assert lib.gesr_query_sizes(ctx, cams, 1, 10, ctypes.byref(st), 100, ctypes.byref(out)) == status
+    lib.gesr_ctx_destroy(ctx)

@@ -489,3 +489,25 @@ def test_tile_ids_are_optional():
     for k in ("ranges", "worklist", "inst_base"):
         np.testing.assert_array_equal(u32(a["bins"][k]), u32(b["bins"][k]), err_msg=k)
     np.testing.assert_array_equal(f32(a["image"]), f32(b["image"]))
+
+
+def test_autotuner_picks_a_candidate_that_renders_identically():
+    """Every candidate runs; the chosen settings are the fastest measured and
+    give the same image (images do not depend on tile shape or batch)."""
+    scene, st = gi.make_workload(1), oracle.Settings()
+    sp = splats_of(scene)
+    rast = _rast(scene, st)
+    ref = f32(rast.forward(sp)["image"])
+    res = rast.autotune(sp, reps=2)
+    log(f"[gpu] autotune: {res}")
+    trials = res["trials"]
+    assert len(trials) >= 8 and all(t["ms"] > 0 for t in trials)
+    stage1 = [t for t in trials if t["stage"] == 1]
+    best1 = min(stage1, key=lambda t: t["ms"])
+    assert (res["tile"], res["variant"], res["batch"]) == (best1["tile"], best1["variant"], best1["batch"])
+    # strict improvement replaces the incumbent (ties keep the earlier trial)
+    widths = [(best1["ms"], i, best1["radix_bits"]) for i in [0]] + \
+        [(t["ms"], i + 1, t["radix_bits"]) for i, t in enumerate(t for t in trials if t["stage"] == 2)]
+    assert res["radix_bits"] == min(widths)[2]
+    assert (rast.settings.tile_w, rast.settings.tile_h) == tuple(int(x) for x in res["tile"].split("x"))
+    np.testing.assert_array_equal(f32(rast.forward(sp)["image"]), ref)
