@@ -252,11 +252,21 @@ def check_projection(scene, g: dict, pr: dict) -> str:
     np.testing.assert_array_equal(r[:, 6], o[:, 6])
     np.testing.assert_array_less(np.abs(r[:, 7] - o[:, 7]), 1e-5 * o[:, 7] + 1e-30)
     np.testing.assert_array_less(np.abs(r[:, 8:11] - o[:, 8:11]), 1e-5)
+    # depth key: the float32 rounding of the depth.  A key may differ by one ulp
+    # only where the exact depth sits on a rounding midpoint (to 1e-12 relative):
+    # there a term far below float32 resolution decides the rounding (common when
+    # a view axis is aligned with a world axis).
     dk_o = pr["zbits"][both].astype(np.int64)
     dk_g = g["depth_key"][both].astype(np.int64)
     if dk_o.size:
         assert np.abs(dk_g - dk_o).max() <= 1
-    assert (dk_g != dk_o).sum() <= max(1, both.sum() // 100000)
+    dif = dk_g != dk_o
+    if dif.any():
+        za = np.minimum(dk_g[dif], dk_o[dif]).astype(np.uint32).view(np.float32).astype(np.float64)
+        zb = np.maximum(dk_g[dif], dk_o[dif]).astype(np.uint32).view(np.float32).astype(np.float64)
+        z64 = np.asarray(pr["depth"], np.float64)[both][dif]
+        tie = np.abs(z64 - 0.5 * (za + zb)) <= 1e-12 * np.abs(z64)
+        assert tie.all(), (int((~tie).sum()), z64[~tie][:4])
     diff = (g["tile_rect"][both] != pr["tile_rect"][both]).any(1)
     e = pr["edges"][both]
     near = (np.abs(e - np.round(e)) < 1e-3).any(1)

@@ -357,16 +357,20 @@ def _sample_tiles(ranges, worklist, grid, rng):
     return sel
 
 
-def test_full_benchmark_workload():
+@pytest.mark.parametrize("k", [3, 4, 5])
+def test_full_size_workload(k):
+    """k = 3: the benchmark workload (500k splats, 8 DRT views); 4: 1M flattened
+    splats, 4 views at 1957x1091, SH degree 3; 5: 3M splats in blobs, 16 views
+    at 1920x1080, SH degree 3."""
     torch = _torch()
-    scene = gi.make_workload(3)
-    st = oracle.Settings()
+    scene = gi.make_workload(k)
+    st = oracle.Settings(sh_degree=scene.sh_degree)
     N, V = scene.n, scene.n_views
     VN = N * V
     rast = _rast(scene, st)
     sp = splats_of(scene)
     M = int(rast.forward(sp, sync=True)["bins"]["M"])
-    log(f"[gpu] full workload: n={N} views={V} px={scene.n_pixels} M={M}")
+    log(f"[gpu] full workload {k}: n={N} views={V} px={scene.n_pixels} M={M}")
     torch.cuda.synchronize()
     # the benchmark's launch configuration: capacity exactly M, no synchronisation
     proj = rast.project(sp)
@@ -383,7 +387,7 @@ def test_full_benchmark_workload():
     rect = np.stack([r[:, 0] & 0xFFFF, r[:, 0] >> 16, r[:, 1] & 0xFFFF, r[:, 1] >> 16], 1).astype(np.int64)
     dk = u32(proj["depth_key"])[:VN]
     g = dict(rec=rec, tiles_touched=tt, tile_rect=rect.astype(np.int32), depth_key=dk)
-    log("[gpu] full workload: projection " + check_projection(scene, g, oracle.project(scene, st)))
+    log(f"[gpu] full workload {k}: projection " + check_projection(scene, g, oracle.project(scene, st)))
 
     # ---- binning: properties that determine the lists uniquely
     grid, T = oracle.tile_grid(scene.cameras, st.tile_w, st.tile_h)
@@ -422,7 +426,7 @@ def test_full_benchmark_workload():
     np.testing.assert_array_equal(worklist, np.lexsort((np.arange(T), -np.minimum(lens, 0xFFFF))))
     base = np.concatenate([[0], np.cumsum(tt.astype(np.int64))[:-1]])
     np.testing.assert_array_equal(u32(bins["inst_base"])[:VN], base)
-    log("[gpu] full workload: binning properties hold")
+    log(f"[gpu] full workload {k}: binning properties hold")
 
     # ---- render forward and backward on sampled tiles
     sel = _sample_tiles(ranges, worklist, grid, gi.sample_rng(13))
@@ -446,9 +450,9 @@ def test_full_benchmark_workload():
     err = np.abs(img[ok3] - fo["image"][ok3])
     assert err.max() <= 1e-4 * max(np.abs(fo["image"][pix3]).max(), 1.0), err.max()
     assert np.abs(f32(f["final_T"])[ok] - fo["final_T"][ok]).max() <= 1e-4
-    for k in ("n_contrib", "n_listed", "n_hit"):
-        np.testing.assert_array_equal(u32(f[k])[ok], fo[k][ok], err_msg=k)
-    log(f"[gpu] full workload: {int(sel.sum())} sampled tiles, {int(pix.sum())} px ({int((pix & amb).sum())} "
+    for name in ("n_contrib", "n_listed", "n_hit"):
+        np.testing.assert_array_equal(u32(f[name])[ok], fo[name][ok], err_msg=name)
+    log(f"[gpu] full workload {k}: {int(sel.sum())} sampled tiles, {int(pix.sum())} px ({int((pix & amb).sum())} "
         f"ambiguous), image max err {err.max():.2e}, listed/px {fo['n_listed'][pix].mean():.0f}")
 
     dL = oracle.flat_images(gi.upstream_grads(scene, 7))
@@ -459,21 +463,30 @@ def test_full_benchmark_workload():
     torch.cuda.synchronize()
     g2 = f32(gpu["grad2d"])[:VN * 10].reshape(VN, 10)
     ref2 = conic_grads_to_factor(oracle.render_bwd(N, scene.cameras, orec, val, masked, dL, st), rec)
-    for k in range(10):
-        einf, e2 = norm_errors(g2[:, k], ref2[:, k])
-        assert einf <= 1e-3 and e2 <= 1e-3, (k, einf, e2)
-    ref = oracle.project_bwd(scene, factor_grads_to_conic(g2, rec), st)
+    for c in range(10):
+        einf, e2 = norm_errors(g2[:, c], ref2[:, c])
+        assert einf <= 1e-3 and e2 <= 1e-3, (c, einf, e2)
+    K = (scene.sh_degree + 1) ** 2
     got = dict(means=f32(gpu["mean"]).reshape(3, N).T, scales=f32(gpu["scale"]).reshape(3, N).T,
                quats=f32(gpu["quat"]).reshape(4, N).T, opacities=f32(gpu["opacity"]), betas=f32(gpu["beta"]),
-               sh=f32(gpu["sh"]).reshape(3, N).T.reshape(N, 1, 3))
+               sh=f32(gpu["sh"]).reshape(K * 3, N).T.reshape(N, K, 3))
+    # splats the sampled tiles reach: the oracle's projection adjoint on that sub-scene;
+    # every other splat's gradient must be exactly zero
+    touched = np.abs(g2).reshape(V, N, 10).max(axis=(0, 2)) > 0
+    idx = np.nonzero(touched)[0]
+    sub = copy.copy(scene)
+    for f in ("means", "log_scales", "scales", "quats", "opacity_logits", "opacities", "betas", "sh"):
+        setattr(sub, f, getattr(scene, f)[idx])
+    g2_sub = g2.reshape(V, N, 10)[:, idx].reshape(-1, 10)
+    rec_sub = rec.reshape(V, N, 12)[:, idx].reshape(-1, 12)
+    ref = oracle.project_bwd(sub, factor_grads_to_conic(g2_sub, rec_sub), st)
     worst = 0.0
-    for k in PARAMS:
-        einf, e2 = norm_errors(got[k], ref[k])
+    for f in PARAMS:
+        einf, e2 = norm_errors(got[f][idx], ref[f])
         worst = max(worst, einf, e2)
-        assert einf <= 1e-3 and e2 <= 1e-3, (k, einf, e2)
-    touched = (np.abs(g2).reshape(V, N, 10).max(axis=(0, 2)) > 0)
-    assert not np.abs(got["means"][~touched]).any()
-    log(f"[gpu] full workload: gradients of {int(touched.sum())} splats ok, worst {worst:.2e}")
+        assert einf <= 1e-3 and e2 <= 1e-3, (f, einf, e2)
+        assert not np.abs(got[f][~touched]).any(), f
+    log(f"[gpu] full workload {k}: gradients of {int(touched.sum())} splats ok, worst {worst:.2e}")
 
 
 def test_tile_ids_are_optional():
