@@ -109,15 +109,51 @@ __device__ __forceinline__ float quad_sum(float x) {
     return s + dpp<0x4e, 0xf, 0xf>(s);           // quad_perm [2, 3, 0, 1]
 }
 
-__device__ __forceinline__ float wave_sum_lane63(float x) {
-    float s = x + dpp<0x111, 0xf, 0xf>(x);   // row_shr:1
-    s = s + dpp<0x112, 0xf, 0xf>(x);         // row_shr:2
-    s = s + dpp<0x113, 0xf, 0xf>(x);         // row_shr:3
-    s = s + dpp<0x114, 0xf, 0xe>(s);         // row_shr:4, banks 1..3
-    s = s + dpp<0x118, 0xf, 0xc>(s);         // row_shr:8, banks 2..3
-    s = s + dpp<0x142, 0xa, 0xf>(s);         // row_bcast:15 into rows 1, 3
-    s = s + dpp<0x143, 0xc, 0xf>(s);         // row_bcast:31 into rows 2, 3
-    return s;
+// Wave sums of ten per-lane values by a transposed butterfly: each step pairs
+// lanes that differ in one bit of the lane index and lets each keep (and add
+// its partner's copy of) half of the values it holds, so the work halves with
+// the data: row_ror:8 (bit 3, 10 -> 5 values), row_half_mirror (bit 2, 5 -> 3),
+// quad_perm swaps (bit 1, 3 -> 2; bit 0, 2 -> 1), then the four rows are added
+// by two cross-row shuffles.  Every lane ends with the total of value
+// wave_sum10_slot(lane) (>= 10: padding).  Fixed pattern, bitwise reproducible.
+__device__ __forceinline__ int wave_sum10_slot(uint32_t lane) {
+    const int b0 = lane & 1, b1 = (lane >> 1) & 1, b2 = (lane >> 2) & 1, b3 = (lane >> 3) & 1;
+    int t = b0;                 // index after the bit-0 step into the bit-1 step's 2 values
+    if (b1) t = t == 0 ? 2 : 3; // bit-1 lanes hold the third value (or padding)
+    if (t > 2) return 16;
+    int si = t;                 // index into the bit-2 step's 3 values
+    if (b2) si = t < 2 ? t + 3 : 5;
+    if (si > 4) return 16;
+    return si + 5 * b3;
+}
+
+__device__ __forceinline__ float wave_sum10(const float (&v)[10], uint32_t lane) {
+    const bool b0 = lane & 1, b1 = (lane >> 1) & 1, b2 = (lane >> 2) & 1, b3 = (lane >> 3) & 1;
+    float s[5];
+#pragma unroll
+    for (int p = 0; p < 5; ++p) {  // lanes l and l ^ 8: keep values p or p + 5
+        const float keep = b3 ? v[p + 5] : v[p], give = b3 ? v[p] : v[p + 5];
+        s[p] = keep + dpp<0x128, 0xf, 0xf>(give);  // row_ror:8
+    }
+    float t[3];
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {  // lanes l and l ^ 7 (bit 2 differs): keep p or p + 3
+        const float hi = p < 2 ? s[p + 3] : 0.0f;
+        const float keep = b2 ? hi : s[p], give = b2 ? s[p] : hi;
+        t[p] = keep + dpp<0x141, 0xf, 0xf>(give);  // row_half_mirror
+    }
+    float u[2];
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {  // lanes l and l ^ 2: keep p or p + 2
+        const float hi = p < 1 ? t[p + 2] : 0.0f;
+        const float keep = b1 ? hi : t[p], give = b1 ? t[p] : hi;
+        u[p] = keep + dpp<0x4e, 0xf, 0xf>(give);  // quad_perm [2, 3, 0, 1]
+    }
+    const float keep = b0 ? u[1] : u[0], give = b0 ? u[0] : u[1];
+    float w = keep + dpp<0xb1, 0xf, 0xf>(give);  // quad_perm [1, 0, 3, 2]
+    w += __shfl_xor(w, 16, 64);
+    w += __shfl_xor(w, 32, 64);
+    return w;
 }
 
 __device__ __forceinline__ uint32_t wave_max_u32(uint32_t x) {

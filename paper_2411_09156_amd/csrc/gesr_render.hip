@@ -170,6 +170,7 @@ __global__ __launch_bounds__(TW * TH) void k_render_bwd(RenderArgs a) {
     constexpr int NW = NT / 64;
     constexpr int NP = GESR_PARTIAL_FLOATS;
     static_assert(BATCH <= NT, "batch larger than the workgroup");
+    static_assert(NP == 10, "wave_sum10 reduces ten values");
     __shared__ float4 sA[BATCH], sB[BATCH], sC[BATCH];
     __shared__ uint32_t sInst[BATCH];
     __shared__ float sRed[NW][BATCH][NP];
@@ -199,6 +200,7 @@ __global__ __launch_bounds__(TW * TH) void k_render_bwd(RenderArgs a) {
     uint32_t maxnc = 0;
     for (int w = 0; w < NW; ++w) maxnc = max(maxnc, sMax[w]);
     const uint32_t end = ti.r0 + maxnc;  // positions >= end contributed to no pixel
+    const int slot = lane < 16 ? wave_sum10_slot(lane) : NP;  // value this lane writes after a reduction
 
     for (uint32_t hi = end; hi > ti.r0;) {
         const uint32_t lo = (hi - ti.r0 > (uint32_t)BATCH) ? hi - BATCH : ti.r0;
@@ -257,14 +259,10 @@ __global__ __launch_bounds__(TW * TH) void k_render_bwd(RenderArgs a) {
                 }
             }
             if (__ballot(act) != 0ull) {
-#pragma unroll
-                for (int k = 0; k < NP; ++k) gr[k] = wave_sum_lane63(gr[k]);
-                if (lane == 63)
-#pragma unroll
-                    for (int k = 0; k < NP; ++k) sRed[wave][j][k] = gr[k];
-            } else if (lane == 63) {
-#pragma unroll
-                for (int k = 0; k < NP; ++k) sRed[wave][j][k] = 0.f;
+                const float tot = wave_sum10(gr, lane);
+                if (slot < NP) sRed[wave][j][slot] = tot;
+            } else if ((int)lane < NP) {
+                sRed[wave][j][lane] = 0.f;
             }
         }
         __syncthreads();
@@ -379,6 +377,7 @@ template <int B>
 __global__ __launch_bounds__(64) void k_render_bwd_wave16(RenderArgs a) {
     static_assert(B >= 1 && B <= 64, "one staged record per lane");
     constexpr int NP = GESR_PARTIAL_FLOATS;
+    static_assert(NP == 10, "wave_sum10 reduces ten values");
     __shared__ float4 sA[B], sB[B], sC[B];
     __shared__ uint32_t sInst[B];
     __shared__ float sRed[B][NP + 1];
@@ -422,6 +421,7 @@ __global__ __launch_bounds__(64) void k_render_bwd_wave16(RenderArgs a) {
     }
     const uint32_t maxnc = wave_max_u32(mymax);
     const uint32_t end = r0 + maxnc;  // positions >= end contributed to no pixel
+    const int slot = lane < 16 ? wave_sum10_slot(lane) : NP;  // value this lane writes after a reduction
 
     for (uint32_t hi = end; hi > r0;) {
         const uint32_t lo = (hi - r0 > (uint32_t)B) ? hi - B : r0;
@@ -479,14 +479,10 @@ __global__ __launch_bounds__(64) void k_render_bwd_wave16(RenderArgs a) {
                 }
             }
             if (__ballot(act) != 0ull) {
-#pragma unroll
-                for (int k = 0; k < NP; ++k) gr[k] = wave_sum_lane63(gr[k]);
-                if (lane == 63)
-#pragma unroll
-                    for (int k = 0; k < NP; ++k) sRed[j][k] = gr[k];
-            } else if (lane == 63) {
-#pragma unroll
-                for (int k = 0; k < NP; ++k) sRed[j][k] = 0.f;
+                const float tot = wave_sum10(gr, lane);
+                if (slot < NP) sRed[j][slot] = tot;
+            } else if ((int)lane < NP) {
+                sRed[j][lane] = 0.f;
             }
         }
         __syncthreads();
