@@ -227,8 +227,8 @@ gesr_status gesr_render_fwd(gesr_ctx* ctx, const gesr_proj* proj, const gesr_bin
  * `workspace` (DEVICE, gesr_sizes.bwd_workspace_bytes) holds, in order and
  * 256-byte aligned: the visited bits (uint32 [ceil(m_cap / 32)], one bit per
  * instance slot), the screen-space gradients (float [V*n][10]) and the
- * per-instance partials (float [m_cap][10], indexed by instance slot, see
- * inst_base).  grad2d (DEVICE [V*n][10], nullable) receives the
+ * per-instance partials (float [m_cap][12]: the ten terms padded to twelve,
+ * indexed by instance slot, see inst_base).  grad2d (DEVICE [V*n][10], nullable) receives the
  * screen-space gradients du, dv, dL00, dL10, dL11, dopacity, dbeta, dr, dg, db
  * (dbeta here is the falloff term only; the phi(beta) term is added in the
  * projection adjoint).  `out` arrays are overwritten.  Results are bitwise

@@ -243,7 +243,7 @@ BwdWorkspace carve_bwd(void* base, uint64_t vn, uint64_t m_cap, uint64_t T) {
     };
     w.visited = (uint32_t*)take(((m_cap + 31) / 32) * 4);
     w.grad2d = (float*)take((vn > 0 ? vn : 1) * GESR_PARTIAL_FLOATS * 4);
-    w.partials = (float*)take(m_cap * GESR_PARTIAL_FLOATS * 4);
+    w.partials = (float*)take(m_cap * kPartialStride * 4);
     w.bytes = off;
     return w;
 }

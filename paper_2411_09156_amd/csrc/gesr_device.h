@@ -102,6 +102,11 @@ __device__ __forceinline__ float row_sum_lane15(float x) {
     return s;
 }
 
+// Stride of one instance partial in the backward workspace: the ten gradient
+// terms padded to twelve floats so a partial is three aligned 16-byte
+// accesses.
+constexpr int kPartialStride = 12;
+
 // Sum over each group of four lanes (quad_perm swaps); every lane of the quad
 // holds the same total (the two orders agree by commutativity).
 __device__ __forceinline__ float quad_sum(float x) {

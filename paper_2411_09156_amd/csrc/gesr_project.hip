@@ -529,25 +529,25 @@ __global__ __launch_bounds__(256) void k_seg_reduce(SegReduceArgs a) {
             if (cnt - j0 < 32u) bits &= (1u << (cnt - j0)) - 1u;
             // up to four visited partials in flight, then added in ascending order
             while (bits != 0u) {
-                float2 v[4][NP / 2];
+                float4 v[4][3];
                 bool have[4];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     have[u] = bits != 0u;
                     const uint32_t b = have[u] ? (uint32_t)__builtin_ctz(bits) : 0u;
                     bits &= bits - 1u;
-                    const float2* src = reinterpret_cast<const float2*>(a.partials + (s0 + b) * NP);
+                    const float4* src = reinterpret_cast<const float4*>(a.partials + (s0 + b) * kPartialStride);
 #pragma unroll
-                    for (int k = 0; k < NP / 2; ++k) v[u][k] = have[u] ? src[k] : make_float2(0.f, 0.f);
+                    for (int k = 0; k < 3; ++k) v[u][k] = have[u] ? src[k] : make_float4(0.f, 0.f, 0.f, 0.f);
                 }
 #pragma unroll
                 for (int u = 0; u < 4; ++u)
-                    if (have[u])
+                    if (have[u]) {
+                        const float t[12] = {v[u][0].x, v[u][0].y, v[u][0].z, v[u][0].w, v[u][1].x, v[u][1].y,
+                                             v[u][1].z, v[u][1].w, v[u][2].x, v[u][2].y, v[u][2].z, v[u][2].w};
 #pragma unroll
-                        for (int k = 0; k < NP / 2; ++k) {
-                            acc[2 * k] += v[u][k].x;
-                            acc[2 * k + 1] += v[u][k].y;
-                        }
+                        for (int k = 0; k < NP; ++k) acc[k] += t[k];
+                    }
                 any = true;
             }
         }

@@ -93,17 +93,18 @@ __device__ __forceinline__ uint32_t instance_index(const RenderArgs& a, uint2 r,
     return inside && inst < a.m_cap ? inst : kNoInstance;
 }
 
-// Partials of one instance: written, and its slot's bit set, unless all ten
-// are zero (the segmented sum adding +-0 or skipping the slot gives the same
+// Partials of one instance (ten terms in a twelve-float slot): written, and
+// its slot's bit set, unless all ten are zero (the segmented sum adding +-0 or skipping the slot gives the same
 // float result, since its running sums start at +0).
 __device__ __forceinline__ void write_partial(const RenderArgs& a, uint32_t slot, const float* s) {
     bool nz = false;
 #pragma unroll
     for (int k = 0; k < GESR_PARTIAL_FLOATS; ++k) nz |= s[k] != 0.0f;
     if (!nz) return;
-    float2* dst = reinterpret_cast<float2*>(a.partials + (size_t)slot * GESR_PARTIAL_FLOATS);
-#pragma unroll
-    for (int k = 0; k < GESR_PARTIAL_FLOATS / 2; ++k) dst[k] = make_float2(s[2 * k], s[2 * k + 1]);
+    float4* dst = reinterpret_cast<float4*>(a.partials + (size_t)slot * kPartialStride);
+    dst[0] = make_float4(s[0], s[1], s[2], s[3]);
+    dst[1] = make_float4(s[4], s[5], s[6], s[7]);
+    dst[2] = make_float4(s[8], s[9], 0.0f, 0.0f);
     atomicOr(a.visited + (slot >> 5), 1u << (slot & 31u));
 }
 
