@@ -29,22 +29,24 @@ METRIC = "fwd+bwd render Mpix/s, batched vs per-view, at ≤1e-4 rel err vs FP64
 WORKLOADS = {"plain": 1, "spheres": 2, "drt": 3, "surfels": 4, "blobs": 5}
 
 # MI355X: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz = 39.3e12 non-packed FP32 VALU
-# lane-slots per second (a transcendental occupies 4 slots); HBM3E 8 TB/s.
+# lane-slots per second.  A transcendental (v_exp/v_log/v_rcp) occupies 2 slots of
+# the same pipe (measured on gfx950: v_fma_f32 sustains 14.3 lanes/cycle/SIMD,
+# v_exp_f32 7.6, and mixes of the two add up to the FMA rate).  HBM3E 8 TB/s.
 VALU_SLOTS_PER_S = 256 * 64 * 2.4e9
 HBM_BYTES_PER_S = 8.0e12
 
 # Algorithmic VALU slots per fragment (see the design notes for the count):
-#   forward : 8 per listed fragment, +24 per hit (3 transcendentals)
-#   backward: 9 per listed fragment, +73 per hit (5 transcendentals, 10 sums)
-FWD_LISTED, FWD_HIT = 8, 24
-BWD_LISTED, BWD_HIT = 9, 73
+#   forward : 8 per listed fragment, +18 per hit (3 transcendentals x 2)
+#   backward: 9 per listed fragment, +63 per hit (5 transcendentals x 2, 10 sums)
+FWD_LISTED, FWD_HIT = 8, 18
+BWD_LISTED, BWD_HIT = 9, 63
 
 # HBM bytes per launch of the tile adjoint on the default workload, from two
 # rocprofv3 counter passes (FETCH_SIZE x2.0, WRITE_SIZE x1.0 after calibration
 # against a 1 GiB copy; profiles/drt-500k-8views_hbm_counters.md).  Valid only
 # for the kernel source it was measured on (fingerprint below); otherwise null.
 MEASURED_TRAFFIC = {"kernel": "render_bwd_tiles", "workload": "drt-batch-500k-8views",
-                    "fingerprint": "273f3327350ed4ea", "bytes": 4233280949,
+                    "fingerprint": "1f224158d93f0eec", "bytes": 4201878401,
                     "settings": (16, 16, 0, 64)}  # tile_w, tile_h, variant, batch of the measured run
 
 

@@ -394,15 +394,15 @@ __global__ __launch_bounds__(64) void k_render_bwd_wave16(RenderArgs a) {
     const uint32_t r0 = rg.x;
     const uint32_t ch = (uint32_t)w.W * (uint32_t)w.H;
 
-    float px[4], py[4], T[4], g0[4], g1[4], g2[4], Br[4], Bg[4], Bb[4];
+    // pixel centres: quadrant q adds (q & 1) * 8 and (q >> 1) * 8 to the lane's base
+    const float pxb = (float)(tx * 16 + (lane & 7)) + 0.5f, pyb = (float)(ty * 16 + (lane >> 3)) + 0.5f;
+    float T[4], g0[4], g1[4], g2[4], Br[4], Bg[4], Bb[4];
     uint32_t nc[4];
     uint32_t mymax = 0;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const int x = (int)tx * 16 + (q & 1) * 8 + (int)(lane & 7);
         const int y = (int)ty * 16 + (q >> 1) * 8 + (int)(lane >> 3);
-        px[q] = (float)x + 0.5f;
-        py[q] = (float)y + 0.5f;
         Br[q] = st.bg[0];
         Bg[q] = st.bg[1];
         Bb[q] = st.bg[2];
@@ -447,7 +447,7 @@ __global__ __launch_bounds__(64) void k_render_bwd_wave16(RenderArgs a) {
             for (int q = 0; q < 4; ++q) {
                 if (prel >= nc[q]) continue;
                 Fragment f;
-                const float qq = ges_q(ra, rb.x, px[q], py[q], f);
+                const float qq = ges_q(ra, rb.x, pxb + (float)((q & 1) * 8), pyb + (float)((q >> 1) * 8), f);
                 if (qq > rb.w) continue;
                 ges_alpha(qq, rb.z, rb.y, st, f);
                 if (f.alpha < st.alpha_min) continue;
