@@ -167,6 +167,10 @@ __global__ __launch_bounds__(TW * TH) void k_render_fwd(RenderArgs a) {
 
 template <int TW, int TH, int BATCH>
 __global__ __launch_bounds__(TW * TH) void k_render_bwd(RenderArgs a) {
+    // The gradient arithmetic may fuse multiply-adds; the alpha, threshold and
+    // transmittance evaluation shared with the forward is written with explicit
+    // fmaf (or has no multiply-add) and compiles identically in both kernels.
+#pragma clang fp contract(fast)
     constexpr int NT = TW * TH;
     constexpr int NW = NT / 64;
     constexpr int NP = GESR_PARTIAL_FLOATS;
@@ -376,6 +380,10 @@ __global__ __launch_bounds__(64) void k_render_fwd_wave16(RenderArgs a) {
 // workgroup barrier beyond the wave itself is needed.
 template <int B>
 __global__ __launch_bounds__(64) void k_render_bwd_wave16(RenderArgs a) {
+    // The gradient arithmetic may fuse multiply-adds; the alpha, threshold and
+    // transmittance evaluation shared with the forward is written with explicit
+    // fmaf (or has no multiply-add) and compiles identically in both kernels.
+#pragma clang fp contract(fast)
     static_assert(B >= 1 && B <= 64, "one staged record per lane");
     constexpr int NP = GESR_PARTIAL_FLOATS;
     static_assert(NP == 10, "wave_sum10 reduces ten values");
