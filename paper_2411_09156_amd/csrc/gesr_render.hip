@@ -318,12 +318,29 @@ __global__ __launch_bounds__(64) void k_render_fwd_wave16(RenderArgs a) {
         inside[q] = x < w.W && y < w.H;
         done[q] = !inside[q];
     }
+    // the next batch's records are loaded into registers while the current
+    // batch is rendered from LDS
+    float4 na = make_float4(0.f, 0.f, 0.f, 0.f), nb = na, nc = na;
+    auto fetch = [&](uint32_t b) {
+        const uint32_t pos = b + lane;
+        if ((int)lane < B && pos < r1) {
+            const float4* r = reinterpret_cast<const float4*>(a.rec + (size_t)a.val_sorted[pos] * GESR_REC_FLOATS);
+            na = r[0];
+            nb = r[1];
+            nc = r[2];
+        }
+    };
+    fetch(r0);
     for (uint32_t base = r0; base < r1; base += B) {
         const bool all_done = done[0] && done[1] && done[2] && done[3];
         if (__ballot(!all_done) == 0ull) break;
-        const uint32_t pos = base + lane;
-        if ((int)lane < B && pos < r1) stage_record(a.rec, a.val_sorted[pos], sA[lane], sB[lane], sC[lane]);
+        if ((int)lane < B && base + lane < r1) {
+            sA[lane] = na;
+            sB[lane] = make_float4(nb.x, nb.y, 0.5f * nb.z, nb.w);
+            sC[lane] = nc;
+        }
         __syncthreads();
+        if (base + B < r1) fetch(base + B);
         const int cnt = (int)min<uint32_t>(B, r1 - base);
         for (int j = 0; j < cnt; ++j) {
             const float4 ra = sA[j];
