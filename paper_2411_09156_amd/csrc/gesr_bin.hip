@@ -65,6 +65,32 @@ __global__ __launch_bounds__(256) void k_scan_reduce(const uint32_t* in, uint64_
     if (threadIdx.x == 0) partials[blockIdx.x] = tot;
 }
 
+// One block of 1024 threads: exclusive scan of up to SCAN_TOP_MAX values
+// (in may equal out), the total to *total (nullable).
+__global__ __launch_bounds__(1024) void k_scan_single(const uint32_t* in, uint32_t* out, uint32_t count,
+                                                      uint32_t* total) {
+    __shared__ uint32_t s_wave[17];
+    constexpr int PER = SCAN_TOP_MAX / 1024;
+    const uint32_t t = threadIdx.x;
+    uint32_t v[PER];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const uint32_t idx = t * PER + k;
+        v[k] = idx < count ? in[idx] : 0u;
+        sum += v[k];
+    }
+    uint32_t tot;
+    uint32_t run = block_exclusive_scan(sum, s_wave, &tot);
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const uint32_t idx = t * PER + k;
+        if (idx < count) out[idx] = run;
+        run += v[k];
+    }
+    if (t == 0 && total) *total = tot;
+}
+
 // One block of 1024 threads scans up to SCAN_TOP_MAX partials in place.
 __global__ __launch_bounds__(1024) void k_scan_top(uint32_t* partials, uint32_t nb, uint32_t* total) {
     __shared__ uint32_t s_wave[17];
@@ -675,6 +701,10 @@ hipError_t scan_exclusive(const uint32_t* in, uint32_t* out, uint64_t count, uin
                           hipStream_t stream) {
     if (count == 0) {
         if (total) hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, stream, total, 0u, (uint64_t)1);
+        return hipGetLastError();
+    }
+    if (count <= (uint64_t)SCAN_TOP_MAX) {  // one launch
+        hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(1024), 0, stream, in, out, (uint32_t)count, total);
         return hipGetLastError();
     }
     const uint64_t nb = (count + SCAN_TILE - 1) / SCAN_TILE;
