@@ -324,7 +324,8 @@ __global__ __launch_bounds__(256) void k_view_keys(const uint32_t* vals, uint64_
 // Each level is split into segments: an ordered item list and a window of at
 // most IS_W consecutive buckets (level 1: a view's rows 128k..128k+127; level
 // 2: a row's tiles 128k..128k+127).  A segment's items are cut into chunks of
-// IS_CHUNK (one item per lane of 16 waves).  In a wave, the items covering
+// IS_CHUNK (two items per lane of 16 waves; wave w holds items 128 w .. 128 w +
+// 127, the second 64 in its second word).  In a wave, the items covering
 // bucket b are one ballot, and an item's rank among them is the popcount of
 // the lanes below it, so the order of equal buckets is the item order.
 // Per-(chunk, bucket) counts are scanned over a segment's chunks, bucket
@@ -332,8 +333,9 @@ __global__ __launch_bounds__(256) void k_view_keys(const uint32_t* vals, uint64_
 // + chunk prefix + earlier waves + rank.  All arithmetic is integer and the
 // result is unique, independent of scheduling.
 constexpr int IS_W = 128;
-constexpr int IS_CHUNK = 1024;
+constexpr int IS_IPL = 2;                            // items per lane
 constexpr int IS_THREADS = 1024;
+constexpr int IS_CHUNK = IS_IPL * IS_THREADS;        // items per chunk
 constexpr int IS_WAVES = IS_THREADS / 64;
 
 struct Seg {
@@ -465,7 +467,7 @@ __device__ __forceinline__ void wave_prefix_row(int* row) {
 // free).  The scatter ranks items by ballots, stages the chunk's entries in
 // LDS grouped by bucket (at most IS_STAGE at a time, bucket windows) and
 // writes each bucket's run contiguously.
-constexpr int IS_STAGE = 12288;
+constexpr int IS_STAGE = 16384;
 
 template <int LEVEL, int MODE>
 __global__ __launch_bounds__(IS_THREADS) void k_is_chunks(IsArgs a) {
@@ -477,6 +479,7 @@ __global__ __launch_bounds__(IS_THREADS) void k_is_chunks(IsArgs a) {
     __shared__ uint32_t s_stage[STAGE + 64];
     __shared__ uint32_t s_stage_c[LEVEL == 1 && MODE == 1 ? STAGE + 64 : 1];
     const uint32_t lane = __lane_id(), wave = threadIdx.x / 64;
+    const uint32_t item0 = wave * (64 * IS_IPL) + lane;  // chunk-local index of this lane's first item
     // a contiguous share of the chunks per block: the segment is looked up once
     // and the next chunk's items are loaded while the current one is processed
     const uint32_t total = min<uint64_t>(*a.chunk_total, a.mat_chunks);
@@ -486,28 +489,39 @@ __global__ __launch_bounds__(IS_THREADS) void k_is_chunks(IsArgs a) {
     uint32_t s = chunk_segment(a.chunk_off, a.nseg, cbeg);
     uint32_t s_first = a.chunk_off[s], s_next = a.chunk_off[s + 1];
     Seg g = locate_segment<LEVEL>(a, s);
-    uint32_t idx = g.begin + (cbeg - s_first) * IS_CHUNK + threadIdx.x;
-    uint32_t p, cols;
-    int a0, a1;
-    load_item<LEVEL>(a, idx, g.end, p, a0, a1, cols);
+    uint32_t idx = g.begin + (cbeg - s_first) * IS_CHUNK + item0;
+    uint32_t p[IS_IPL], cols[IS_IPL];
+    int a0[IS_IPL], a1[IS_IPL];
+#pragma unroll
+    for (int u = 0; u < IS_IPL; ++u) load_item<LEVEL>(a, idx + 64 * u, g.end, p[u], a0[u], a1[u], cols[u]);
     for (uint32_t cg = cbeg; cg < cend;) {
         // bucket bases of this chunk (scatter) are independent of the LDS work below
         uint32_t gb = 0;
         if (MODE == 1 && threadIdx.x < (uint32_t)g.width)
             gb = a.bucket_start[g.bucket0 + threadIdx.x] + a.mat[(uint64_t)cg * IS_W + threadIdx.x];
-        const int lo = max(a0 - g.lo_off, 0), hi = min(a1 - g.lo_off, g.width - 1);
+        int lo[IS_IPL], hi[IS_IPL];
+        bool any[IS_IPL];
+#pragma unroll
+        for (int u = 0; u < IS_IPL; ++u) {
+            lo[u] = max(a0[u] - g.lo_off, 0);
+            hi[u] = min(a1[u] - g.lo_off, g.width - 1);
+            any[u] = lo[u] <= hi[u];
+        }
         const bool same = cg + 1 < cend && cg + 1 < s_next;
         const uint32_t idx_n = idx + IS_CHUNK;
-        uint32_t p_n, cols_n;
-        int a0_n, a1_n;
-        load_item<LEVEL>(a, idx_n, same ? g.end : 0u, p_n, a0_n, a1_n, cols_n);
-        const bool any = lo <= hi;
+        uint32_t p_n[IS_IPL], cols_n[IS_IPL];
+        int a0_n[IS_IPL], a1_n[IS_IPL];
+#pragma unroll
+        for (int u = 0; u < IS_IPL; ++u)
+            load_item<LEVEL>(a, idx_n + 64 * u, same ? g.end : 0u, p_n[u], a0_n[u], a1_n[u], cols_n[u]);
         for (int j = threadIdx.x; j < IS_WAVES * (IS_W + 1); j += IS_THREADS) (&s_cnt[0][0])[j] = 0;
         __syncthreads();
-        if (any) {
-            atomicAdd(&s_cnt[wave][lo], 1);
-            atomicAdd(&s_cnt[wave][hi + 1], -1);
-        }
+#pragma unroll
+        for (int u = 0; u < IS_IPL; ++u)
+            if (any[u]) {
+                atomicAdd(&s_cnt[wave][lo[u]], 1);
+                atomicAdd(&s_cnt[wave][hi[u] + 1], -1);
+            }
         __syncthreads();
         wave_prefix_row(s_cnt[wave]);  // s_cnt[w][b]: items of wave w covering bucket b
         __syncthreads();
@@ -536,11 +550,25 @@ __global__ __launch_bounds__(IS_THREADS) void k_is_chunks(IsArgs a) {
             __syncthreads();
             if (wave == 0) wave_prefix_row(reinterpret_cast<int*>(s_ls + 1));
             __syncthreads();
-            const int lo_w = __builtin_amdgcn_readfirstlane(wave_min_i(any ? lo : IS_W));
-            const int hi_w = __builtin_amdgcn_readfirstlane(wave_max_i(any ? hi : -1));
+            int lmin = IS_W, hmax = -1;
+#pragma unroll
+            for (int u = 0; u < IS_IPL; ++u)
+                if (any[u]) {
+                    lmin = min(lmin, lo[u]);
+                    hmax = max(hmax, hi[u]);
+                }
+            const int lo_w = __builtin_amdgcn_readfirstlane(wave_min_i(lmin));
+            const int hi_w = __builtin_amdgcn_readfirstlane(wave_max_i(hmax));
+            // b in [lo, hi] as one unsigned compare; empty items never match
+            uint32_t ulo[IS_IPL], uspan[IS_IPL];
+#pragma unroll
+            for (int u = 0; u < IS_IPL; ++u) {
+                ulo[u] = any[u] ? (uint32_t)lo[u] : 0x80000000u;
+                uspan[u] = any[u] ? (uint32_t)(hi[u] - lo[u]) : 0u;
+            }
             for (int b0 = 0; b0 < g.width;) {
                 // largest b1 with the window's entries fitting the stage (one bucket
-                // holds at most IS_CHUNK <= IS_STAGE entries)
+                // holds at most IS_CHUNK <= STAGE entries)
                 int l = b0 + 1, h = g.width;
                 while (l < h) {
                     const int mid = (l + h + 1) >> 1;
@@ -553,24 +581,26 @@ __global__ __launch_bounds__(IS_THREADS) void k_is_chunks(IsArgs a) {
                 if (bs <= be) {
                     // stage offsets of buckets bs.., two per lane, read back with readlane;
                     // branch-free: every lane writes, those off the bucket to their own
-                    // spare slot (an empty item has lo > hi)
+                    // spare slot
                     const int k0 = bs + (int)lane, k1 = bs + 64 + (int)lane;
                     const uint32_t o0 = k0 <= be ? s_ls[k0] - off0 + (uint32_t)s_cnt[wave][k0] : 0u;
                     const uint32_t o1 = k1 <= be ? s_ls[k1] - off0 + (uint32_t)s_cnt[wave][k1] : 0u;
                     const uint32_t spare = (uint32_t)STAGE + lane;
                     const int nb = be - bs + 1;
-                    // b in [lo, hi] as one unsigned compare; empty items never match
-                    const uint32_t ulo = any ? (uint32_t)lo : 0x80000000u;
-                    const uint32_t uspan = any ? (uint32_t)(hi - lo) : 0u;
                     auto stage = [&](int b, uint32_t base) {
-                        const bool hit = (uint32_t)b - ulo <= uspan;
-                        const uint64_t m = __builtin_amdgcn_ballot_w64(hit);
-                        const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
-                            (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-                        const uint32_t sel = 0u - (uint32_t)hit;  // all ones on the bucket
-                        const uint32_t q = spare ^ (((base + rank) ^ spare) & sel);
-                        s_stage[q] = p;
-                        if (LEVEL == 1) s_stage_c[q] = cols;
+                        // the wave's first word of items precedes its second
+#pragma unroll
+                        for (int u = 0; u < IS_IPL; ++u) {
+                            const bool hit = (uint32_t)b - ulo[u] <= uspan[u];
+                            const uint64_t m = __builtin_amdgcn_ballot_w64(hit);
+                            const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
+                                (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                            const uint32_t sel = 0u - (uint32_t)hit;  // all ones on the bucket
+                            const uint32_t q = spare ^ (((base + rank) ^ spare) & sel);
+                            s_stage[q] = p[u];
+                            if (LEVEL == 1) s_stage_c[q] = cols[u];
+                            base += (uint32_t)__popcll(m);
+                        }
                     };
                     const int na = nb < 64 ? nb : 64;
                     for (int k = 0; k < na; ++k) stage(bs + k, (uint32_t)__builtin_amdgcn_readlane((int)o0, k));
@@ -599,10 +629,13 @@ __global__ __launch_bounds__(IS_THREADS) void k_is_chunks(IsArgs a) {
         if (cg >= cend) break;
         if (same) {
             idx = idx_n;
-            p = p_n;
-            cols = cols_n;
-            a0 = a0_n;
-            a1 = a1_n;
+#pragma unroll
+            for (int u = 0; u < IS_IPL; ++u) {
+                p[u] = p_n[u];
+                cols[u] = cols_n[u];
+                a0[u] = a0_n[u];
+                a1[u] = a1_n[u];
+            }
         } else {
             while (cg >= s_next) {
                 ++s;
@@ -610,8 +643,9 @@ __global__ __launch_bounds__(IS_THREADS) void k_is_chunks(IsArgs a) {
                 s_next = a.chunk_off[s + 1];
             }
             g = locate_segment<LEVEL>(a, s);
-            idx = g.begin + (cg - s_first) * IS_CHUNK + threadIdx.x;
-            load_item<LEVEL>(a, idx, g.end, p, a0, a1, cols);
+            idx = g.begin + (cg - s_first) * IS_CHUNK + item0;
+#pragma unroll
+            for (int u = 0; u < IS_IPL; ++u) load_item<LEVEL>(a, idx + 64 * u, g.end, p[u], a0[u], a1[u], cols[u]);
         }
     }
 }
