@@ -69,13 +69,26 @@ __device__ __forceinline__ float ges_q(const float4& a, float L11, float px, flo
     return fmaf(f.t, f.t, f.w * f.w);
 }
 
-__device__ __forceinline__ void ges_alpha(float q, float half_beta, float opacity, const DevSettings& st, Fragment& f) {
+// alpha = min(opacity G, alpha_max) as one median-of-three: opacity G >= 0, so
+// med3(opacity G, 0, alpha_max) is that minimum (and needs no NaN quieting of
+// the kernel argument per fragment, as a min would).
+__device__ __forceinline__ void ges_alpha(float q, float half_beta, float opacity, const DevSettings& st,
+                                          float alpha_max, Fragment& f) {
     f.q = q;
     f.l2q = hw_log2(q);                    // -inf at q = 0
     f.P = hw_exp2(half_beta * f.l2q);      // q^(beta/2); 0 at q = 0
     f.G = hw_exp2(st.neg_kappa_log2e * f.P);
     f.oG = opacity * f.G;
-    f.alpha = fminf(st.alpha_max, f.oG);
+    f.alpha = __builtin_amdgcn_fmed3f(f.oG, 0.0f, alpha_max);
+}
+
+// A zero the compiler cannot treat as a constant.  Accumulators that start
+// from it are updated in place along nested branches; started from a literal
+// 0 the compiler re-materialises the zeros on every skipped branch level.
+__device__ __forceinline__ float opaque_zero() {
+    float z;
+    asm volatile("v_mov_b32 %0, 0" : "=v"(z));
+    return z;
 }
 
 // Wave-wide sum (64 lanes) by butterfly; every lane receives the total.

@@ -115,6 +115,7 @@ __global__ __launch_bounds__(TW * TH) void k_render_fwd(RenderArgs a) {
     const uint32_t t = a.worklist[blockIdx.x];
     const TileInfo ti = tile_info<TW, TH>(a, t);
     const DevSettings& st = a.st;
+    const float amax = st.alpha_max;
     const float px = (float)ti.x + 0.5f, py = (float)ti.y + 0.5f;
 
     float T = 1.0f, cr = 0.f, cg = 0.f, cb = 0.f;
@@ -134,7 +135,7 @@ __global__ __launch_bounds__(TW * TH) void k_render_fwd(RenderArgs a) {
                 const float q = ges_q(ra, rb.x, px, py, f);
                 if (COUNT) ++listed;
                 if (q > rb.w) continue;  // beyond the alpha_min footprint
-                ges_alpha(q, rb.z, rb.y, st, f);
+                ges_alpha(q, rb.z, rb.y, st, amax, f);
                 if (f.alpha < st.alpha_min) continue;
                 if (COUNT) ++hit;
                 const float Tn = T * (1.0f - f.alpha);
@@ -184,6 +185,7 @@ __global__ __launch_bounds__(TW * TH) void k_render_bwd(RenderArgs a) {
     const uint32_t t = a.worklist[blockIdx.x];
     const TileInfo ti = tile_info<TW, TH>(a, t);
     const DevSettings& st = a.st;
+    const float amax = st.alpha_max;
     const float px = (float)ti.x + 0.5f, py = (float)ti.y + 0.5f;
     const uint32_t lane = __lane_id(), wave = threadIdx.x >> 6;
 
@@ -222,7 +224,7 @@ __global__ __launch_bounds__(TW * TH) void k_render_bwd(RenderArgs a) {
             const uint32_t prel = hi - 1u - (uint32_t)j - ti.r0;  // 0-based list position
             float gr[NP];
 #pragma unroll
-            for (int k = 0; k < NP; ++k) gr[k] = 0.f;
+            for (int k = 0; k < NP; ++k) gr[k] = opaque_zero();
             bool act = false;
             if (prel < nc) {
                 const float4 ra = sA[j];
@@ -230,7 +232,7 @@ __global__ __launch_bounds__(TW * TH) void k_render_bwd(RenderArgs a) {
                 Fragment f;
                 const float q = ges_q(ra, rb.x, px, py, f);
                 if (q <= rb.w) {
-                    ges_alpha(q, rb.z, rb.y, st, f);
+                    ges_alpha(q, rb.z, rb.y, st, amax, f);
                     if (f.alpha >= st.alpha_min) {
                         act = true;
                         const float4 rc = sC[j];
@@ -295,6 +297,7 @@ __global__ __launch_bounds__(64) void k_render_fwd_wave16(RenderArgs a) {
     __shared__ float4 sA[B], sB[B], sC[B];
     const uint32_t t = a.worklist[blockIdx.x];
     const DevSettings& st = a.st;
+    const float amax = st.alpha_max;
     const uint32_t lane = __lane_id();
     const int v = view_of_tile(a.cams, t);
     const DevView& w = a.cams.v[v];
@@ -352,7 +355,7 @@ __global__ __launch_bounds__(64) void k_render_fwd_wave16(RenderArgs a) {
                 const float qq = ges_q(ra, rb.x, px[q], py[q], f);
                 if (COUNT) ++listed[q];
                 if (qq > rb.w) continue;  // beyond the alpha_min footprint
-                ges_alpha(qq, rb.z, rb.y, st, f);
+                ges_alpha(qq, rb.z, rb.y, st, amax, f);
                 if (f.alpha < st.alpha_min) continue;
                 if (COUNT) ++hit[q];
                 const float Tn = T[q] * (1.0f - f.alpha);
@@ -410,6 +413,7 @@ __global__ __launch_bounds__(64) void k_render_bwd_wave16(RenderArgs a) {
 
     const uint32_t t = a.worklist[blockIdx.x];
     const DevSettings& st = a.st;
+    const float amax = st.alpha_max;
     const uint32_t lane = __lane_id();
     const int v = view_of_tile(a.cams, t);
     const DevView& w = a.cams.v[v];
@@ -466,7 +470,7 @@ __global__ __launch_bounds__(64) void k_render_bwd_wave16(RenderArgs a) {
             const float4 rb = sB[j];
             float gr[NP];
 #pragma unroll
-            for (int k = 0; k < NP; ++k) gr[k] = 0.f;
+            for (int k = 0; k < NP; ++k) gr[k] = opaque_zero();
             bool act = false;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
@@ -474,7 +478,7 @@ __global__ __launch_bounds__(64) void k_render_bwd_wave16(RenderArgs a) {
                 Fragment f;
                 const float qq = ges_q(ra, rb.x, pxb + (float)((q & 1) * 8), pyb + (float)((q >> 1) * 8), f);
                 if (qq > rb.w) continue;
-                ges_alpha(qq, rb.z, rb.y, st, f);
+                ges_alpha(qq, rb.z, rb.y, st, amax, f);
                 if (f.alpha < st.alpha_min) continue;
                 act = true;
                 const float4 rc = sC[j];
