@@ -145,21 +145,45 @@ __device__ __forceinline__ int wave_sum10_slot(uint32_t lane) {
     return si + 5 * b3;
 }
 
+// The bit-3 and bit-2 steps need no selects: the half a lane keeps is the
+// one whose DPP add writes the lane's bank (banks are lane bits 2-3 of a row),
+// so each kept value is one masked v_add_f32_dpp of the value and its
+// partner's copy.  Written as one asm block (the compiler's DPP intrinsics
+// cannot express a bank-masked add whose unwritten lanes keep another add's
+// result); the block opens with 5 wait states (EXEC or VGPR writes just
+// before a DPP read), spaces each of its own DPP reads at least 2
+// instructions after the write of that register, and closes with 2 wait
+// states for DPP reads of its results.  In the bit-2 step the third value is
+// added over all banks: the bit-2 lanes' copy is padding and never reaches a
+// valid slot.
 __device__ __forceinline__ float wave_sum10(const float (&v)[10], uint32_t lane) {
-    const bool b0 = lane & 1, b1 = (lane >> 1) & 1, b2 = (lane >> 2) & 1, b3 = (lane >> 3) & 1;
-    float s[5];
-#pragma unroll
-    for (int p = 0; p < 5; ++p) {  // lanes l and l ^ 8: keep values p or p + 5
-        const float keep = b3 ? v[p + 5] : v[p], give = b3 ? v[p] : v[p + 5];
-        s[p] = keep + dpp<0x128, 0xf, 0xf>(give);  // row_ror:8
-    }
-    float t[3];
-#pragma unroll
-    for (int p = 0; p < 3; ++p) {  // lanes l and l ^ 7 (bit 2 differs): keep p or p + 3
-        const float hi = p < 2 ? s[p + 3] : 0.0f;
-        const float keep = b2 ? hi : s[p], give = b2 ? s[p] : hi;
-        t[p] = keep + dpp<0x141, 0xf, 0xf>(give);  // row_half_mirror
-    }
+    const bool b0 = lane & 1, b1 = (lane >> 1) & 1;
+    float s0, s1, s2, s3, s4, t[3];
+    asm volatile(
+        "s_nop 4\n"
+        // lanes l and l ^ 8 (row_ror:8): banks 0-1 keep value p, banks 2-3 value p + 5
+        "v_add_f32_dpp %[s0], %[v0], %[v0] row_ror:8 row_mask:0xf bank_mask:0x3\n"
+        "v_add_f32_dpp %[s0], %[v5], %[v5] row_ror:8 row_mask:0xf bank_mask:0xc\n"
+        "v_add_f32_dpp %[s1], %[v1], %[v1] row_ror:8 row_mask:0xf bank_mask:0x3\n"
+        "v_add_f32_dpp %[s1], %[v6], %[v6] row_ror:8 row_mask:0xf bank_mask:0xc\n"
+        "v_add_f32_dpp %[s2], %[v2], %[v2] row_ror:8 row_mask:0xf bank_mask:0x3\n"
+        "v_add_f32_dpp %[s2], %[v7], %[v7] row_ror:8 row_mask:0xf bank_mask:0xc\n"
+        "v_add_f32_dpp %[s3], %[v3], %[v3] row_ror:8 row_mask:0xf bank_mask:0x3\n"
+        "v_add_f32_dpp %[s3], %[v8], %[v8] row_ror:8 row_mask:0xf bank_mask:0xc\n"
+        "v_add_f32_dpp %[s4], %[v4], %[v4] row_ror:8 row_mask:0xf bank_mask:0x3\n"
+        "v_add_f32_dpp %[s4], %[v9], %[v9] row_ror:8 row_mask:0xf bank_mask:0xc\n"
+        // lanes l and l ^ 7 (row_half_mirror, bit 2 differs): banks 0 and 2 keep
+        // value p, banks 1 and 3 value p + 3
+        "v_add_f32_dpp %[t0], %[s0], %[s0] row_half_mirror row_mask:0xf bank_mask:0x5\n"
+        "v_add_f32_dpp %[t0], %[s3], %[s3] row_half_mirror row_mask:0xf bank_mask:0xa\n"
+        "v_add_f32_dpp %[t1], %[s1], %[s1] row_half_mirror row_mask:0xf bank_mask:0x5\n"
+        "v_add_f32_dpp %[t1], %[s4], %[s4] row_half_mirror row_mask:0xf bank_mask:0xa\n"
+        "v_add_f32_dpp %[t2], %[s2], %[s2] row_half_mirror row_mask:0xf bank_mask:0xf\n"
+        "s_nop 1"
+        : [s0] "=&v"(s0), [s1] "=&v"(s1), [s2] "=&v"(s2), [s3] "=&v"(s3), [s4] "=&v"(s4), [t0] "=&v"(t[0]),
+          [t1] "=&v"(t[1]), [t2] "=&v"(t[2])
+        : [v0] "v"(v[0]), [v1] "v"(v[1]), [v2] "v"(v[2]), [v3] "v"(v[3]), [v4] "v"(v[4]), [v5] "v"(v[5]),
+          [v6] "v"(v[6]), [v7] "v"(v[7]), [v8] "v"(v[8]), [v9] "v"(v[9]));
     float u[2];
 #pragma unroll
     for (int p = 0; p < 2; ++p) {  // lanes l and l ^ 2: keep p or p + 2
