@@ -37,9 +37,10 @@ HBM_BYTES_PER_S = 8.0e12
 
 # Algorithmic VALU slots per fragment (see the design notes for the count):
 #   forward : 8 per listed fragment, +18 per hit (3 transcendentals x 2)
-#   backward: 9 per listed fragment, +63 per hit (5 transcendentals x 2, 10 sums)
+#   backward: 9 per listed fragment, +48 per hit (5 transcendentals x 2, sums fused
+#             into multiply-adds)
 FWD_LISTED, FWD_HIT = 8, 18
-BWD_LISTED, BWD_HIT = 9, 63
+BWD_LISTED, BWD_HIT = 9, 48
 
 # HBM bytes per launch of the tile adjoint on the default workload, from two
 # rocprofv3 counter passes (FETCH_SIZE x2.0, WRITE_SIZE x1.0 after calibration

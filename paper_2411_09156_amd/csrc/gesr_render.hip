@@ -69,13 +69,41 @@ __device__ __forceinline__ TileInfo tile_info(const RenderArgs& a, uint32_t t) {
     return ti;
 }
 
-// Stage record `vi` into LDS as (u, v, L00, L10), (L11, o, beta/2, qmax), (r, g, b, -).
-__device__ __forceinline__ void stage_record(const float* rec, uint32_t vi, float4& sa, float4& sb, float4& sc) {
+// Stage record `vi` into LDS as (u, v, L00, L10), (L11, o, beta/2, qmax),
+// (r, g, b, -kappa beta); the last is the splat's factor of 2 dL/dq (below).
+__device__ __forceinline__ void stage_record(const float* rec, uint32_t vi, float kappa, float4& sa, float4& sb,
+                                             float4& sc) {
     const float4* r = reinterpret_cast<const float4*>(rec + (size_t)vi * GESR_REC_FLOATS);
-    float4 b = r[1];
+    const float4 b = r[1], c = r[2];
     sa = r[0];
     sb = make_float4(b.x, b.y, 0.5f * b.z, b.w);
-    sc = r[2];
+    sc = make_float4(c.x, c.y, c.z, -kappa * b.z);
+}
+
+// Adds the opacity, beta and footprint gradient terms of one composited
+// fragment to gr (partial layout: d/du, d/dv, d/dL00, d/dL10, d/dL11, d/do,
+// d/dbeta, d/dr, d/dg, d/db); dLda = dL/dalpha, c2 = -kappa ln2 / 2.  With
+// G = exp(-kappa P), P = q^(beta/2):
+//   dL/do    = dLda G                        (alpha = o G below the cap)
+//   dL/dbeta = dLda o G P (-kappa/2) ln q    = X log2(q) c2,  X = dLda o G P
+//   2 dL/dq  = dLda o G P (-kappa beta) / q  = X rc.w / q
+// and q = t^2 + w^2 with t = L00 dx + L10 dy, w = L11 dy, (dx, dy) = pixel - (u, v).
+__device__ __forceinline__ void add_fragment_grad(const Fragment& f, const float4& ra, const float4& rb,
+                                                  float rcw, float dLda, float alpha_max, float c2,
+                                                  float (&gr)[GESR_PARTIAL_FLOATS]) {
+    if (f.oG > alpha_max) return;  // alpha clamped: no gradient to o, beta or the footprint
+    gr[5] = fmaf(dLda, f.G, gr[5]);
+    if (!(f.q > 1e-30f)) return;   // pixel at the centre: dq/d(geometry) = 0
+    const float X = dLda * f.oG * f.P;
+    gr[6] = fmaf(X * f.l2q, c2, gr[6]);
+    const float d2 = X * rcw * hw_rcp(f.q);
+    const float tq = d2 * f.t, wq = d2 * f.w;
+    gr[0] = fmaf(-tq, ra.z, gr[0]);
+    gr[1] = fmaf(-tq, ra.w, gr[1]);
+    gr[1] = fmaf(-wq, rb.x, gr[1]);
+    gr[2] = fmaf(tq, f.dx, gr[2]);
+    gr[3] = fmaf(tq, f.dy, gr[3]);
+    gr[4] = fmaf(wq, f.dy, gr[4]);
 }
 
 constexpr uint32_t kNoInstance = 0xFFFFFFFFu;
@@ -124,7 +152,7 @@ __global__ __launch_bounds__(TW * TH) void k_render_fwd(RenderArgs a) {
     for (uint32_t base = ti.r0; base < ti.r1; base += NT) {
         if (__syncthreads_count(done) == NT) break;
         const uint32_t pos = base + threadIdx.x;
-        if (pos < ti.r1) stage_record(a.rec, a.val_sorted[pos], sA[threadIdx.x], sB[threadIdx.x], sC[threadIdx.x]);
+        if (pos < ti.r1) stage_record(a.rec, a.val_sorted[pos], st.kappa, sA[threadIdx.x], sB[threadIdx.x], sC[threadIdx.x]);
         __syncthreads();
         const int cnt = (int)min<uint32_t>(NT, ti.r1 - base);
         if (!done) {
@@ -186,6 +214,7 @@ __global__ __launch_bounds__(TW * TH) void k_render_bwd(RenderArgs a) {
     const TileInfo ti = tile_info<TW, TH>(a, t);
     const DevSettings& st = a.st;
     const float amax = st.alpha_max;
+    const float c2 = -0.5f * kLn2 * st.kappa;
     const float px = (float)ti.x + 0.5f, py = (float)ti.y + 0.5f;
     const uint32_t lane = __lane_id(), wave = threadIdx.x >> 6;
 
@@ -215,7 +244,7 @@ __global__ __launch_bounds__(TW * TH) void k_render_bwd(RenderArgs a) {
         if ((int)threadIdx.x < cnt) {
             const uint32_t pos = hi - 1u - threadIdx.x;
             const uint32_t vi = a.val_sorted[pos];
-            stage_record(a.rec, vi, sA[threadIdx.x], sB[threadIdx.x], sC[threadIdx.x]);
+            stage_record(a.rec, vi, st.kappa, sA[threadIdx.x], sB[threadIdx.x], sC[threadIdx.x]);
             const uint2 r = reinterpret_cast<const uint2*>(a.rect)[vi];
             sInst[threadIdx.x] = instance_index(a, r, vi, ti.tx, ti.ty);
         }
@@ -246,22 +275,7 @@ __global__ __launch_bounds__(TW * TH) void k_render_bwd(RenderArgs a) {
                         Bg = fmaf(f.alpha, rc.y - Bg, Bg);
                         Bb = fmaf(f.alpha, rc.z - Bb, Bb);
                         T = Tk;
-                        if (f.oG <= st.alpha_max) {
-                            gr[5] = dLda * f.G;
-                            const float dLdG = dLda * rb.y;
-                            if (f.q > 1e-30f) {
-                                const float kGP = -st.kappa * f.G * f.P;  // dG/dP * P
-                                const float dLdq = dLdG * kGP * rb.z * hw_rcp(f.q);
-                                gr[6] = dLdG * kGP * 0.5f * (f.l2q * kLn2);
-                                // q = t^2 + w^2, t = L00 dx + L10 dy, w = L11 dy, dx = px - u
-                                const float tq = 2.0f * dLdq * f.t, wq = 2.0f * dLdq * f.w;
-                                gr[0] = -tq * ra.z;
-                                gr[1] = -(tq * ra.w + wq * rb.x);
-                                gr[2] = tq * f.dx;
-                                gr[3] = tq * f.dy;
-                                gr[4] = wq * f.dy;
-                            }
-                        }
+                        add_fragment_grad(f, ra, rb, rc.w, dLda, st.alpha_max, c2, gr);
                     }
                 }
             }
@@ -414,6 +428,7 @@ __global__ __launch_bounds__(64) void k_render_bwd_wave16(RenderArgs a) {
     const uint32_t t = a.worklist[blockIdx.x];
     const DevSettings& st = a.st;
     const float amax = st.alpha_max;
+    const float c2 = -0.5f * kLn2 * st.kappa;
     const uint32_t lane = __lane_id();
     const int v = view_of_tile(a.cams, t);
     const DevView& w = a.cams.v[v];
@@ -459,7 +474,7 @@ __global__ __launch_bounds__(64) void k_render_bwd_wave16(RenderArgs a) {
         if ((int)lane < cnt) {
             const uint32_t pos = hi - 1u - lane;
             const uint32_t vi = a.val_sorted[pos];
-            stage_record(a.rec, vi, sA[lane], sB[lane], sC[lane]);
+            stage_record(a.rec, vi, st.kappa, sA[lane], sB[lane], sC[lane]);
             const uint2 r = reinterpret_cast<const uint2*>(a.rect)[vi];
             sInst[lane] = instance_index(a, r, vi, tx, ty);
         }
@@ -468,6 +483,7 @@ __global__ __launch_bounds__(64) void k_render_bwd_wave16(RenderArgs a) {
             const uint32_t prel = hi - 1u - (uint32_t)j - r0;  // 0-based list position
             const float4 ra = sA[j];
             const float4 rb = sB[j];
+            const float4 rc = sC[j];
             float gr[NP];
 #pragma unroll
             for (int k = 0; k < NP; ++k) gr[k] = opaque_zero();
@@ -481,7 +497,6 @@ __global__ __launch_bounds__(64) void k_render_bwd_wave16(RenderArgs a) {
                 ges_alpha(qq, rb.z, rb.y, st, amax, f);
                 if (f.alpha < st.alpha_min) continue;
                 act = true;
-                const float4 rc = sC[j];
                 const float Tk = T[q] * hw_rcp(1.0f - f.alpha);
                 const float aT = f.alpha * Tk;
                 gr[7] += aT * g0[q];
@@ -492,21 +507,7 @@ __global__ __launch_bounds__(64) void k_render_bwd_wave16(RenderArgs a) {
                 Bg[q] = fmaf(f.alpha, rc.y - Bg[q], Bg[q]);
                 Bb[q] = fmaf(f.alpha, rc.z - Bb[q], Bb[q]);
                 T[q] = Tk;
-                if (f.oG <= st.alpha_max) {
-                    gr[5] += dLda * f.G;
-                    const float dLdG = dLda * rb.y;
-                    if (f.q > 1e-30f) {
-                        const float kGP = -st.kappa * f.G * f.P;
-                        const float dLdq = dLdG * kGP * rb.z * hw_rcp(f.q);
-                        gr[6] += dLdG * kGP * 0.5f * (f.l2q * kLn2);
-                        const float tq = 2.0f * dLdq * f.t, wq = 2.0f * dLdq * f.w;
-                        gr[0] += -tq * ra.z;
-                        gr[1] += -(tq * ra.w + wq * rb.x);
-                        gr[2] += tq * f.dx;
-                        gr[3] += tq * f.dy;
-                        gr[4] += wq * f.dy;
-                    }
-                }
+                add_fragment_grad(f, ra, rb, rc.w, dLda, st.alpha_max, c2, gr);
             }
             if (__ballot(act) != 0ull) {
                 const float tot = wave_sum10(gr, lane);
