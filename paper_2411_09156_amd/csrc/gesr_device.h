@@ -90,6 +90,13 @@ __device__ __forceinline__ float opaque_zero() {
     asm volatile("v_mov_b32 %0, 0" : "=v"(z));
     return z;
 }
+// Two such zeros from one 64-bit move.
+__device__ __forceinline__ void opaque_zero2(float& a, float& b) {
+    uint64_t z;
+    asm volatile("v_mov_b64 %0, 0" : "=v"(z));
+    a = __uint_as_float((uint32_t)z);
+    b = __uint_as_float((uint32_t)(z >> 32));
+}
 
 // Wave-wide sum (64 lanes) by butterfly; every lane receives the total.
 __device__ __forceinline__ float wave_sum(float x) {

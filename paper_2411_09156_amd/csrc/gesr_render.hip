@@ -464,7 +464,7 @@ __global__ __launch_bounds__(64) void k_render_bwd_wave16(RenderArgs a) {
         }
         mymax = max(mymax, nc[q]);
     }
-    const uint32_t maxnc = wave_max_u32(mymax);
+    const uint32_t maxnc = __builtin_amdgcn_readfirstlane(wave_max_u32(mymax));  // uniform: scalar loop control
     const uint32_t end = r0 + maxnc;  // positions >= end contributed to no pixel
     const int slot = lane < 16 ? wave_sum10_slot(lane) : NP;  // value this lane writes after a reduction
 
@@ -486,7 +486,7 @@ __global__ __launch_bounds__(64) void k_render_bwd_wave16(RenderArgs a) {
             const float4 rc = sC[j];
             float gr[NP];
 #pragma unroll
-            for (int k = 0; k < NP; ++k) gr[k] = opaque_zero();
+            for (int k = 0; k < NP; k += 2) opaque_zero2(gr[k], gr[k + 1]);
             bool act = false;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
