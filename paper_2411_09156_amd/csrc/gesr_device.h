@@ -191,12 +191,13 @@ __device__ __forceinline__ float wave_sum10(const float (&v)[10], uint32_t lane)
           [t1] "=&v"(t[1]), [t2] "=&v"(t[2])
         : [v0] "v"(v[0]), [v1] "v"(v[1]), [v2] "v"(v[2]), [v3] "v"(v[3]), [v4] "v"(v[4]), [v5] "v"(v[5]),
           [v6] "v"(v[6]), [v7] "v"(v[7]), [v8] "v"(v[8]), [v9] "v"(v[9]));
+    // lanes l and l ^ 2 (quad_perm [2, 3, 0, 1]): keep value 0 or 2; value 1 is
+    // added on all lanes (the bit-1 lanes' copy is padding)
     float u[2];
-#pragma unroll
-    for (int p = 0; p < 2; ++p) {  // lanes l and l ^ 2: keep p or p + 2
-        const float hi = p < 1 ? t[p + 2] : 0.0f;
-        const float keep = b1 ? hi : t[p], give = b1 ? t[p] : hi;
-        u[p] = keep + dpp<0x4e, 0xf, 0xf>(give);  // quad_perm [2, 3, 0, 1]
+    {
+        const float keep = b1 ? t[2] : t[0], give = b1 ? t[0] : t[2];
+        u[0] = keep + dpp<0x4e, 0xf, 0xf>(give);
+        u[1] = t[1] + dpp<0x4e, 0xf, 0xf>(t[1]);
     }
     const float keep = b0 ? u[1] : u[0], give = b0 ? u[0] : u[1];
     float w = keep + dpp<0xb1, 0xf, 0xf>(give);  // quad_perm [1, 0, 3, 2]
