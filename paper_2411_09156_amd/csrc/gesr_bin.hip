@@ -1,12 +1,15 @@
 // Tile binning for the GES rasterizer (gfx950): prefix scans, a stable LSD
-// radix sort, instance duplication, per-tile ranges and the render worklist.
+// radix sort, the two-level interval scatter that builds the tile lists,
+// per-tile ranges and the render worklist.
 //
-// Every instance carries the 64-bit key (global tile id << 32 | depth bits).
-// All instances of one (view, splat) share its depth, so the LSD passes over
-// the 32 depth bits can run once per (view, splat) *before* duplication:
-// splats are first sorted by depth, duplicated in that order, and only the
-// tile-id bits are then sorted per instance.  Each pass is stable, so the
-// result is exactly the stable sort of the full key.
+// Every instance is ordered by the 64-bit key (global tile id << 32 | depth
+// bits), ties by (view, splat) index.  All instances of one (view, splat)
+// share its depth and its tiles form a rectangle, so no instance is ever
+// sorted: the (view, splat) pairs are radix-sorted by depth and then stably
+// by view; each pair is written, in that order, into the row lists of the
+// tile rows its rectangle covers, and each row-list entry into the tile lists
+// of the columns it covers.  Both writes are stable bucketings, so every tile
+// list holds its instances in exactly the order of the stable key sort.
 
 #include "gesr_device.h"
 #include "gesr_kernels.h"
