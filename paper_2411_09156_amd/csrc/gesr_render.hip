@@ -108,7 +108,7 @@ __device__ __forceinline__ void add_fragment_grad(const Fragment& f, const float
 
 constexpr uint32_t kNoInstance = 0xFFFFFFFFu;
 
-// Slot of the instance (splat vi, tile (tx, ty)) in the duplicate order: the
+// Slot of the instance (splat vi, tile (tx, ty)) in the pair-major order: the
 // splat's instance base plus the tile's row-major position in its rectangle.
 // When the lists overflowed their capacity the ranges no longer match the
 // truncated lists, so a listed splat may not cover the tile or its slot may lie
