@@ -134,6 +134,18 @@ __device__ __forceinline__ float quad_sum(float x) {
     return s + dpp<0x4e, 0xf, 0xf>(s);           // quad_perm [2, 3, 0, 1]
 }
 
+// Sum over each aligned group of L = 4, 8 or 16 lanes; every lane of the group
+// holds the total (each step adds two equal-shaped partial sums, so partners
+// agree by commutativity).
+template <int L>
+__device__ __forceinline__ float group_sum(float x) {
+    static_assert(L == 4 || L == 8 || L == 16, "group of 4, 8 or 16 lanes");
+    x = quad_sum(x);
+    if (L >= 8) x += dpp<0x141, 0xf, 0xf>(x);  // row_half_mirror: the other quad of the 8
+    if (L >= 16) x += dpp<0x128, 0xf, 0xf>(x); // row_ror:8: the other half of the row
+    return x;
+}
+
 // Wave sums of ten per-lane values by a transposed butterfly: each step pairs
 // lanes that differ in one bit of the lane index and lets each keep (and add
 // its partner's copy of) half of the values it holds, so the work halves with

@@ -498,15 +498,19 @@ __global__ __launch_bounds__(256) void k_project_bwd(ProjectBwdArgs a) {
     for (int k = 0; k < K * 3; ++k) a.g_sh[(size_t)k * n + i] = gsh[k];
 }
 
-// Four lanes (one DPP quad) per (view, splat).  The pair's instance slots
-// are contiguous (inst_base[vi] + j); lane l of the quad takes the blocks of
-// 32 instances m = l, l + 4, ... and, in ascending order, adds the partials of
-// the block's visited instances (set bits); a fixed DPP tree then adds the
-// quad.  The order depends only on the pair's own instances, so a batch of
-// views and views rendered one at a time give identical sums.
+// kSegLanes lanes (an aligned DPP group) per (view, splat).  The pair's
+// instance slots are contiguous (inst_base[vi] + j); lane l of the group takes
+// the blocks of 32 instances m = l, l + kSegLanes, ... and, in ascending
+// order, adds the partials of the block's visited instances (set bits); a
+// fixed DPP tree then adds the group.  The order depends only on the pair's
+// own instances, so a batch of views and views rendered one at a time give
+// identical sums.  Eight lanes: pairs of wide splats (hundreds of instances)
+// set the pace, and fewer lanes serialise their blocks.
+constexpr uint32_t kSegLanes = 8;
+
 __global__ __launch_bounds__(256) void k_seg_reduce(SegReduceArgs a) {
     constexpr int NP = GESR_PARTIAL_FLOATS;
-    constexpr uint32_t L = 4;
+    constexpr uint32_t L = kSegLanes;
     const uint64_t vi = ((uint64_t)blockIdx.x * 256u + threadIdx.x) / L;
     const uint32_t lane = __lane_id() & (L - 1);
     const bool valid = vi < a.vn;
@@ -554,9 +558,9 @@ __global__ __launch_bounds__(256) void k_seg_reduce(SegReduceArgs a) {
     }
     if (__ballot(any) != 0ull) {
 #pragma unroll
-        for (int k = 0; k < NP; ++k) acc[k] = quad_sum(acc[k]);
+        for (int k = 0; k < NP; ++k) acc[k] = group_sum<L>(acc[k]);
     }
-    // quads without visited instances hold zeros; lane 3 of each quad writes
+    // groups without visited instances hold zeros; the last lane of each group writes
     if (valid && lane == L - 1) {
         float2* out = reinterpret_cast<float2*>(a.grad2d + (size_t)vi * NP);
 #pragma unroll
@@ -580,7 +584,7 @@ hipError_t launch_project(const ProjectArgs& a, int sh_degree, hipStream_t strea
 
 hipError_t launch_seg_reduce(const SegReduceArgs& a, hipStream_t stream) {
     if (a.vn == 0) return hipSuccess;
-    const uint64_t threads = (uint64_t)a.vn * 4;
+    const uint64_t threads = (uint64_t)a.vn * kSegLanes;
     hipLaunchKernelGGL(k_seg_reduce, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, stream, a);
     return hipGetLastError();
 }
