@@ -154,16 +154,21 @@ def bin_instances(N, cameras, tile_rect, tiles_touched, zbits, st: Settings):
     return keys[:M], vals[:M], ranges
 
 
-def render_fwd(N, cameras, rec, vals, ranges, st: Settings) -> dict:
+def render_fwd(N, cameras, rec, vals, ranges, st: Settings, depth=None) -> dict:
+    """Tiled forward; with `depth` ([V*N] splat depths) also the extended
+    channels "depth" (sum alpha T z) and "alpha" (sum alpha T)."""
     P = sum(c.width * c.height for c in cameras)
     out = dict(image=np.zeros(3 * P), final_T=np.zeros(P), n_contrib=np.zeros(P, np.uint32),
                n_listed=np.zeros(P, np.uint32), n_hit=np.zeros(P, np.uint32), ambig=np.zeros(P, np.uint8))
+    if depth is not None:
+        out["depth"], out["alpha"] = np.zeros(P), np.zeros(P)
     vals = np.ascontiguousarray(vals, np.uint32)
     if vals.size == 0:
         vals = np.zeros(1, np.uint32)
     lib().orc_render_fwd(N, len(cameras), _p(views_array(cameras)), _p(st.array()), _p(_f64(rec)), _p(vals),
                          _p(np.ascontiguousarray(ranges, np.uint32)), _p(out["image"]), _p(out["final_T"]),
-                         _p(out["n_contrib"]), _p(out["n_listed"]), _p(out["n_hit"]), _p(out["ambig"]))
+                         _p(out["n_contrib"]), _p(out["n_listed"]), _p(out["n_hit"]), _p(out["ambig"]),
+                         _p(None if depth is None else _f64(depth)), _p(out.get("depth")), _p(out.get("alpha")))
     return out
 
 
@@ -178,33 +183,48 @@ def brute_fwd(N, cameras, rec, zbits, cull, st: Settings, pix_rect=None, window=
     return out
 
 
-def render_bwd(N, cameras, rec, vals, ranges, dL_dimage, st: Settings) -> np.ndarray:
+def render_bwd(N, cameras, rec, vals, ranges, dL_dimage, st: Settings, depth=None, dL_ddepth=None,
+               dL_dalpha=None) -> np.ndarray:
+    """grad2d [V*N, 11]: du, dv, dA, dB, dC, dopacity, dbeta, dr, dg, db, dz (dz
+    only from the extended channels, which need `depth`)."""
     V = len(cameras)
-    g2 = np.zeros((V * N, 10))
+    g2 = np.zeros((V * N, 11))
     vals = np.ascontiguousarray(vals, np.uint32)
     if vals.size == 0:
         vals = np.zeros(1, np.uint32)
     lib().orc_render_bwd(N, V, _p(views_array(cameras)), _p(st.array()), _p(_f64(rec)), _p(vals),
-                         _p(np.ascontiguousarray(ranges, np.uint32)), _p(_f64(dL_dimage)), _p(g2))
+                         _p(np.ascontiguousarray(ranges, np.uint32)), _p(_f64(dL_dimage)),
+                         _p(None if depth is None else _f64(depth)),
+                         _p(None if dL_ddepth is None else _f64(dL_ddepth)),
+                         _p(None if dL_dalpha is None else _f64(dL_dalpha)), _p(g2))
     return g2
 
 
-def window_fwdbwd(N, cameras, rec, zbits, cull, pix_rect, window, dL_dimage, watch, st: Settings):
-    """(sum_window dL.image, grad2d rows of `watch`, decision hash)."""
+def window_fwdbwd(N, cameras, rec, zbits, cull, pix_rect, window, dL_dimage, watch, st: Settings, depth=None,
+                  dL_ddepth=None, dL_dalpha=None):
+    """(sum_window dL.image [+ dL_ddepth.depth + dL_dalpha.alpha], grad2d rows
+    (11 columns) of `watch`, decision hash)."""
     watch = np.ascontiguousarray(watch, dtype=np.int64)
     loss = ctypes.c_double(0.0)
     dec = ctypes.c_uint64(0)
-    wg = np.zeros((max(len(watch), 1), 10))
+    wg = np.zeros((max(len(watch), 1), 11))
     lib().orc_window_fwdbwd(N, len(cameras), _p(views_array(cameras)), _p(st.array()), _p(_f64(rec)),
                             _p(np.ascontiguousarray(zbits, np.uint32)), _p(np.ascontiguousarray(cull, np.uint8)),
                             _p(np.ascontiguousarray(pix_rect, np.int32)),
-                            _p(np.ascontiguousarray(window, np.int32)), _p(_f64(dL_dimage)), len(watch),
+                            _p(np.ascontiguousarray(window, np.int32)), _p(_f64(dL_dimage)),
+                            _p(None if depth is None else _f64(depth)),
+                            _p(None if dL_ddepth is None else _f64(dL_ddepth)),
+                            _p(None if dL_dalpha is None else _f64(dL_dalpha)), len(watch),
                             _p(watch), ctypes.byref(loss), _p(wg), ctypes.byref(dec))
     return loss.value, wg[:len(watch)], dec.value
 
 
 def project_bwd(scene, grad2d, st: Settings) -> dict:
+    """grad2d [V*N, 10 or 11] (a missing dz column is zero) -> parameter gradients."""
     N, V = scene.n, scene.n_views
+    grad2d = np.asarray(grad2d, np.float64)
+    if grad2d.shape[1] == 10:
+        grad2d = np.concatenate([grad2d, np.zeros((grad2d.shape[0], 1))], axis=1)
     K = (st.sh_degree + 1) ** 2
     g = dict(means=np.zeros((N, 3)), scales=np.zeros((N, 3)), quats=np.zeros((N, 4)), opacities=np.zeros(N),
              betas=np.zeros(N), sh=np.zeros((N, K, 3)))
@@ -233,17 +253,20 @@ def num_threads() -> int:
 
 
 # ------------------------------------------------------------------ pipeline
-def forward(scene, st: Settings) -> dict:
-    """Full FP64 pipeline: project -> bin -> tiled render."""
+def forward(scene, st: Settings, channels: bool = False) -> dict:
+    """Full FP64 pipeline: project -> bin -> tiled render (with the extended
+    depth and alpha channels when `channels`)."""
     pr = project(scene, st)
     keys, vals, ranges = bin_instances(scene.n, scene.cameras, pr["tile_rect"], pr["tiles_touched"], pr["zbits"], st)
-    out = render_fwd(scene.n, scene.cameras, pr["rec"], vals, ranges, st)
+    out = render_fwd(scene.n, scene.cameras, pr["rec"], vals, ranges, st, depth=pr["depth"] if channels else None)
     out.update(proj=pr, keys=keys, vals=vals, ranges=ranges)
     return out
 
 
-def backward(scene, st: Settings, fwd: dict, dL_dimage) -> dict:
-    g2 = render_bwd(scene.n, scene.cameras, fwd["proj"]["rec"], fwd["vals"], fwd["ranges"], dL_dimage, st)
+def backward(scene, st: Settings, fwd: dict, dL_dimage, dL_ddepth=None, dL_dalpha=None) -> dict:
+    ext = dL_ddepth is not None or dL_dalpha is not None
+    g2 = render_bwd(scene.n, scene.cameras, fwd["proj"]["rec"], fwd["vals"], fwd["ranges"], dL_dimage, st,
+                    depth=fwd["proj"]["depth"] if ext else None, dL_ddepth=dL_ddepth, dL_dalpha=dL_dalpha)
     g = project_bwd(scene, g2, st)
     g["grad2d"] = g2
     return g

@@ -16,6 +16,10 @@
 //     read as 2 / (1 + exp(-rho (beta - 2))) so that phi(2) = 1.
 //   * Volume rendering, Eq. (5), evaluated as discrete front-to-back alpha
 //     blending (the "alpha-blending coefficients" of Sec. 3.3).
+//   * Depth maps of the extended rasterizer (Sec. 3.3, mesh extraction): the
+//     splat depth and a unit opacity composited like a colour over a zero
+//     background (the paper names the depth map, not its formula; this is the
+//     reading used).
 //
 // Everything is double precision.  Inputs arrive as float32 and are promoted
 // exactly.  The projection is written once as a template over the scalar
@@ -205,6 +209,7 @@ enum Cull : uint8_t { KEEP = 0, CULL_NEAR = 1, CULL_DET = 2, CULL_OPACITY = 3, C
 template <class S>
 struct Proj {
     S u, v, A, B, C, o, beta, rgb[3];
+    S z;  // camera-space depth of the centre (the extended rasterizer's depth channel)
     double depth = 0, qmax = 0, sig[3] = {0, 0, 0}, edges[4] = {0, 0, 0, 0};
     int pix[4] = {-1, -1, -2, -2}, tiles[4] = {-1, -1, -2, -2};
     uint32_t touched = 0;
@@ -223,6 +228,7 @@ Proj<S> project_one(const S mean[3], const S scale[3], const S quat[4], const S&
     for (int a = 0; a < 3; ++a)
         p[a] = vw.R[3 * a + 0] * mean[0] + vw.R[3 * a + 1] * mean[1] + vw.R[3 * a + 2] * mean[2] + vw.t[a];
     r.depth = val(p[2]);
+    r.z = p[2];
     if (!(val(p[2]) > st.znear)) { r.cull = std::isfinite(val(p[2])) ? CULL_NEAR : CULL_NONFINITE; return r; }
 
     // rotation of the normalised quaternion (w, x, y, z), Eq. (4)
@@ -363,22 +369,28 @@ inline uint8_t frag_ambiguity(const Frag& f, double Tnext, double band, double t
 
 struct PixelOut {
     double C[3];
+    double D, A;  // extended channels: sum alpha T z and sum alpha T (zero background)
     double T;
     uint32_t n_contrib, n_listed, n_hit;
     uint8_t ambig;
 };
 
 // One explicit list entry of a composited fragment (used by the adjoint).
-struct Hit { long idx; long row; double alpha, T; Frag f; };
+struct Hit { long idx; long row; double alpha, T, z; Frag f; };
 
 // Front-to-back compositing of one pixel over `list` (indices into rec, in
 // order).  Skips fragments with alpha < alpha_min; stops before compositing a
 // fragment that would take T below t_min.  n_contrib is the 1-based list
 // position of the last composited fragment.
+//
+// Extended channels (the depth maps of the mesh-extraction passage, Sec. 3.3):
+// depth and opacity composited like a colour channel over a zero background,
+// D = sum_k alpha_k T_k z_k and A = sum_k alpha_k T_k, with z the splat's
+// camera-space depth (`depth`, nullable: z = 0).
 template <class ListFn>
 PixelOut composite_pixel(long count, ListFn idx_at, const double* rec, double px, double py, const Settings& st,
-                         std::vector<Hit>* hits, const long* rows = nullptr) {
-    PixelOut o{{0, 0, 0}, 1.0, 0, 0, 0, 0};
+                         std::vector<Hit>* hits, const long* rows = nullptr, const double* depth = nullptr) {
+    PixelOut o{{0, 0, 0}, 0.0, 0.0, 1.0, 0, 0, 0, 0};
     double T = 1.0;
     double tband = st.ambig;  // relative error band of T
     for (long k = 0; k < count; ++k) {
@@ -396,7 +408,10 @@ PixelOut composite_pixel(long count, ListFn idx_at, const double* rec, double px
         o.C[0] += s.r * f.alpha * T;
         o.C[1] += s.g * f.alpha * T;
         o.C[2] += s.b * f.alpha * T;
-        if (hits) hits->push_back(Hit{idx, rows ? rows[k] : idx, f.alpha, T, f});
+        const double z = depth ? depth[idx] : 0.0;
+        o.D += z * f.alpha * T;
+        o.A += f.alpha * T;
+        if (hits) hits->push_back(Hit{idx, rows ? rows[k] : idx, f.alpha, T, z, f});
         T = Tn;
         tband = tnext_band;
         o.n_contrib = (uint32_t)(k + 1);
@@ -407,23 +422,32 @@ PixelOut composite_pixel(long count, ListFn idx_at, const double* rec, double px
 }
 
 // Adjoint of composite_pixel for one pixel, from its explicit hit list.
-// g = dL/dC (3 values); writes into grad2d rows (10 per splat-view index):
-// du, dv, dA, dB, dC, dopacity, dbeta, dr, dg, db.
-void pixel_adjoint(const std::vector<Hit>& hits, double Tfinal, const double* g, const double* rec,
-                   const Settings& st, double* grad2d) {
+// g = dL/dC (3 values), gD = dL/dD, gA = dL/dA; writes into grad2d rows (11 per
+// splat-view index): du, dv, dA, dB, dC, dopacity, dbeta, dr, dg, db, dz.
+// Every channel c with fragment values c_k and background b gives
+// dL/dalpha_k = T_k (c_k - B_k) g_c, where B_k is the channel composited
+// behind fragment k per unit T_{k+1} (B = alpha_k c_k + (1 - alpha_k) B moving
+// front-wards from B = b); depth has c_k = z_k, opacity c_k = 1, both b = 0.
+void pixel_adjoint(const std::vector<Hit>& hits, double Tfinal, const double* g, double gD, double gA,
+                   const double* rec, const Settings& st, double* grad2d) {
     double Bk[3] = {st.bg[0], st.bg[1], st.bg[2]};  // colour behind fragment k, per unit T_{k+1}
+    double BD = 0.0, BA = 0.0;                       // depth and opacity behind fragment k
     (void)Tfinal;
     for (long k = (long)hits.size() - 1; k >= 0; --k) {
         const Hit& h = hits[k];
         Rec s = load_rec(rec, h.idx);
-        double* gr = grad2d + 10 * h.row;
+        double* gr = grad2d + 11 * h.row;
         double col[3] = {s.r, s.g, s.b};
         double dL_dalpha = 0.0;
         for (int c = 0; c < 3; ++c) {
             gr[7 + c] += h.alpha * h.T * g[c];
             dL_dalpha += h.T * (col[c] - Bk[c]) * g[c];
         }
+        gr[10] += h.alpha * h.T * gD;
+        dL_dalpha += h.T * (h.z - BD) * gD + h.T * (1.0 - BA) * gA;
         for (int c = 0; c < 3; ++c) Bk[c] = h.alpha * col[c] + (1.0 - h.alpha) * Bk[c];
+        BD = h.alpha * h.z + (1.0 - h.alpha) * BD;
+        BA = h.alpha + (1.0 - h.alpha) * BA;
         const Frag& f = h.f;
         if (f.oG > st.alpha_max) continue;  // alpha clamped: no dependence on o or G
         gr[5] += dL_dalpha * f.G;
@@ -563,10 +587,12 @@ int orc_bin(int N, int V, const int32_t* tile_rect, const uint32_t* tiles_touche
 // Tiled forward: every pixel composites the sorted list of its tile.
 // Outputs (concatenated over views): image [3][H][W] per view, final_T,
 // n_contrib, n_listed, n_hit, ambig (bit0 alpha ~ alpha_min, bit1 oG ~ alpha_max,
-// bit2 T' ~ t_min).
+// bit2 T' ~ t_min); with `depth` ([V*N] splat depths) non-null, the extended
+// channels out_depth and out_alpha ([P] each, nullable).
 int orc_render_fwd(int N, int V, const double* views, const double* settings, const double* rec,
                    const uint32_t* vals, const uint32_t* ranges, double* image, double* final_T,
-                   uint32_t* n_contrib, uint32_t* n_listed, uint32_t* n_hit, uint8_t* ambig) {
+                   uint32_t* n_contrib, uint32_t* n_listed, uint32_t* n_hit, uint8_t* ambig, const double* depth,
+                   double* out_depth, double* out_alpha) {
     (void)N;
     Settings st = read_settings(settings);
     std::vector<View> vw = read_views(views, V, st.tile_w, st.tile_h);
@@ -578,12 +604,15 @@ int orc_render_fwd(int N, int V, const double* views, const double* settings, co
                 long t = w.tile_base + (y / st.tile_h) * w.tiles_x + x / st.tile_w;
                 uint32_t s0 = ranges[2 * t], s1 = ranges[2 * t + 1];
                 PixelOut po = composite_pixel(
-                    (long)s1 - s0, [&](long k) { return (long)vals[s0 + k]; }, rec, x + 0.5, y + 0.5, st, nullptr);
+                    (long)s1 - s0, [&](long k) { return (long)vals[s0 + k]; }, rec, x + 0.5, y + 0.5, st, nullptr,
+                    nullptr, depth);
                 long p = w.pix_base + y * w.W + x;
                 long HW = (long)w.W * w.H;
                 for (int c = 0; c < 3; ++c) image[3 * w.pix_base + c * HW + y * w.W + x] = po.C[c];
                 final_T[p] = po.T;
                 n_contrib[p] = po.n_contrib;
+                if (out_depth) out_depth[p] = po.D;
+                if (out_alpha) out_alpha[p] = po.A;
                 if (n_listed) n_listed[p] = po.n_listed;
                 if (n_hit) n_hit[p] = po.n_hit;
                 if (ambig) ambig[p] = po.ambig;
@@ -656,10 +685,13 @@ int orc_brute_fwd(int N, int V, const double* views, const double* settings, con
 
 // Render adjoint over the tiled lists: re-runs the forward per pixel keeping
 // the explicit list of composited fragments (alpha_k, T_k) and back-propagates
-// dL/dimage into grad2d [V*N][10] (du, dv, dA, dB, dC, dopacity, dbeta, dr, dg, db).
-// Accumulation uses one buffer per thread, summed in thread order.
+// dL/dimage (and, with `depth` non-null, dL/ddepth and dL/dalpha of the
+// extended channels, each nullable) into grad2d [V*N][11] (du, dv, dA, dB, dC,
+// dopacity, dbeta, dr, dg, db, dz).  Accumulation uses one buffer per thread,
+// summed in thread order.
 int orc_render_bwd(int N, int V, const double* views, const double* settings, const double* rec,
-                   const uint32_t* vals, const uint32_t* ranges, const double* dL_dimage, double* grad2d) {
+                   const uint32_t* vals, const uint32_t* ranges, const double* dL_dimage, const double* depth,
+                   const double* dL_ddepth, const double* dL_dalpha, double* grad2d) {
     Settings st = read_settings(settings);
     std::vector<View> vw = read_views(views, V, st.tile_w, st.tile_h);
     long VN = (long)V * N;
@@ -668,7 +700,7 @@ int orc_render_bwd(int N, int V, const double* views, const double* settings, co
 #pragma omp parallel
     {
         std::vector<double>& g2 = acc[thread_id()];
-        g2.assign(10 * VN, 0.0);
+        g2.assign(11 * VN, 0.0);
         std::vector<Hit> hits;
         for (int v = 0; v < V; ++v) {
             const View& w = vw[v];
@@ -680,28 +712,34 @@ int orc_render_bwd(int N, int V, const double* views, const double* settings, co
                     uint32_t s0 = ranges[2 * t], s1 = ranges[2 * t + 1];
                     hits.clear();
                     PixelOut po = composite_pixel(
-                        (long)s1 - s0, [&](long k) { return (long)vals[s0 + k]; }, rec, x + 0.5, y + 0.5, st, &hits);
+                        (long)s1 - s0, [&](long k) { return (long)vals[s0 + k]; }, rec, x + 0.5, y + 0.5, st, &hits,
+                        nullptr, depth);
                     double g[3];
                     for (int c = 0; c < 3; ++c) g[c] = dL_dimage[3 * w.pix_base + c * HW + y * w.W + x];
-                    pixel_adjoint(hits, po.T, g, rec, st, g2.data());
+                    const long p = w.pix_base + y * w.W + x;
+                    const double gD = (depth && dL_ddepth) ? dL_ddepth[p] : 0.0;
+                    const double gA = (depth && dL_dalpha) ? dL_dalpha[p] : 0.0;
+                    pixel_adjoint(hits, po.T, g, gD, gA, rec, st, g2.data());
                 }
         }
     }
-    std::fill(grad2d, grad2d + 10 * VN, 0.0);
+    std::fill(grad2d, grad2d + 11 * VN, 0.0);
     for (int k = 0; k < nt; ++k)
         if (!acc[k].empty())
-            for (long j = 0; j < 10 * VN; ++j) grad2d[j] += acc[k][j];
+            for (long j = 0; j < 11 * VN; ++j) grad2d[j] += acc[k][j];
     return 0;
 }
 
 // Window forward + adjoint by brute force with the pixel-rectangle filter:
 // pixels in window (V x 4, inclusive) only.  Returns sum over the window of
-// dL_dimage . image in *loss and, for the `n_watch` splat-view indices in
-// `watch`, their grad2d rows (n_watch x 10).  `decisions` receives a hash of
+// dL_dimage . image (+ dL_ddepth . D + dL_dalpha . A of the extended channels
+// when `depth` is non-null) in *loss and, for the `n_watch` splat-view indices
+// in `watch`, their grad2d rows (n_watch x 11).  `decisions` receives a hash of
 // every skip/terminate/clamp decision taken (for finite-difference checks).
 int orc_window_fwdbwd(int N, int V, const double* views, const double* settings, const double* rec,
                       const uint32_t* zbits, const uint8_t* cull, const int32_t* pix_rect, const int32_t* window,
-                      const double* dL_dimage, int n_watch, const long* watch, double* loss, double* watch_grad,
+                      const double* dL_dimage, const double* depth, const double* dL_ddepth,
+                      const double* dL_dalpha, int n_watch, const long* watch, double* loss, double* watch_grad,
                       uint64_t* decisions) {
     Settings st = read_settings(settings);
     std::vector<View> vw = read_views(views, V, st.tile_w, st.tile_h);
@@ -712,7 +750,7 @@ int orc_window_fwdbwd(int N, int V, const double* views, const double* settings,
     std::sort(wmap.begin(), wmap.end());
     double total = 0.0;
     uint64_t dh = 1469598103934665603ull;
-    std::fill(watch_grad, watch_grad + 10 * (long)n_watch, 0.0);
+    std::fill(watch_grad, watch_grad + 11 * (long)n_watch, 0.0);
     for (int v = 0; v < V; ++v) {
         const View& w = vw[v];
         int x0 = std::max(0, window[4 * v]), y0 = std::max(0, window[4 * v + 1]);
@@ -728,7 +766,7 @@ int orc_window_fwdbwd(int N, int V, const double* views, const double* settings,
         std::vector<long> list, rows;
         std::vector<Hit> hits;
         // gradients accumulate in a compact buffer with one row per candidate
-        std::vector<double> g2(10 * cand.size(), 0.0);
+        std::vector<double> g2(11 * cand.size(), 0.0);
         for (long y = y0; y <= y1; ++y)
             for (long x = x0; x <= x1; ++x) {
                 list.clear();
@@ -741,13 +779,17 @@ int orc_window_fwdbwd(int N, int V, const double* views, const double* settings,
                 }
                 hits.clear();
                 PixelOut po = composite_pixel((long)list.size(), [&](long k) { return list[k]; }, rec, x + 0.5,
-                                              y + 0.5, st, &hits, rows.data());
+                                              y + 0.5, st, &hits, rows.data(), depth);
                 double g[3];
                 for (int c = 0; c < 3; ++c) {
                     g[c] = dL_dimage[3 * w.pix_base + c * HW + y * w.W + x];
                     total += g[c] * po.C[c];
                 }
-                pixel_adjoint(hits, po.T, g, rec, st, g2.data());
+                const long p = w.pix_base + y * w.W + x;
+                const double gD = (depth && dL_ddepth) ? dL_ddepth[p] : 0.0;
+                const double gA = (depth && dL_dalpha) ? dL_dalpha[p] : 0.0;
+                total += gD * po.D + gA * po.A;
+                pixel_adjoint(hits, po.T, g, gD, gA, rec, st, g2.data());
                 for (const Hit& h : hits) {
                     uint64_t e = (uint64_t)h.idx * 1315423911ull + (uint64_t)(h.f.oG > st.alpha_max);
                     dh = (dh ^ e) * 1099511628211ull;
@@ -761,7 +803,7 @@ int orc_window_fwdbwd(int N, int V, const double* views, const double* settings,
             if (it != cand.end() && *it == pr.first) c = it - cand.begin();
             else for (size_t j = 0; j < cand.size(); ++j) if (cand[j] == pr.first) { c = (long)j; break; }
             if (c < 0) continue;
-            for (int j = 0; j < 10; ++j) watch_grad[10 * pr.second + j] += g2[10 * c + j];
+            for (int j = 0; j < 11; ++j) watch_grad[11 * pr.second + j] += g2[11 * c + j];
         }
     }
     *loss = total;
@@ -769,7 +811,7 @@ int orc_window_fwdbwd(int N, int V, const double* views, const double* settings,
     return 0;
 }
 
-// Projection adjoint: grad2d [V*N][10] -> gradients of the splat inputs,
+// Projection adjoint: grad2d [V*N][11] -> gradients of the splat inputs,
 // summed over views in ascending order.  The Jacobian of every projected
 // quantity with respect to (mean, scale, quat, opacity, beta) comes from
 // forward-mode dual numbers through project_one; the SH coefficients enter the
@@ -796,11 +838,11 @@ int orc_project_bwd(int N, int V, const double* means, const double* scales, con
             long idx = (long)v * N + i;
             Proj<D> p = project_one<D>(m, s, q, o, b, sh + (long)i * K * 3, vw[v], st);
             if (p.cull != KEEP) continue;
-            const double* g = grad2d + 10 * idx;
-            const D* outs[10] = {&p.u, &p.v, &p.A, &p.B, &p.C, &p.o, &p.beta, &p.rgb[0], &p.rgb[1], &p.rgb[2]};
+            const double* g = grad2d + 11 * idx;
+            const D* outs[11] = {&p.u, &p.v, &p.A, &p.B, &p.C, &p.o, &p.beta, &p.rgb[0], &p.rgb[1], &p.rgb[2], &p.z};
             for (int k = 0; k < 12; ++k) {
                 double acc = 0.0;
-                for (int j = 0; j < 10; ++j) acc += g[j] * outs[j]->d[k];
+                for (int j = 0; j < 11; ++j) acc += g[j] * outs[j]->d[k];
                 gacc[k] += acc;
             }
             // SH coefficients: d rgb_c / d k_lc = Y_lm(dir), zero on a clamped channel
