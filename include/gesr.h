@@ -46,7 +46,9 @@ typedef enum {
 
 #define GESR_MAX_VIEWS 32
 #define GESR_REC_FLOATS 12    /* floats per projected record */
-#define GESR_PARTIAL_FLOATS 10 /* floats per instance gradient partial */
+#define GESR_PARTIAL_FLOATS 10 /* colour and footprint terms of a gradient partial (du .. db) */
+#define GESR_GRAD2D_FLOATS 12  /* floats per grad2d row and per instance partial: the ten
+                                  terms, dz (depth channel, 0 without it) and a zero pad */
 
 typedef struct gesr_ctx gesr_ctx;
 
@@ -207,6 +209,26 @@ typedef struct {
     uint32_t* n_hit;
 } gesr_fwd_counts;
 
+/* Extended channels (the depth maps of the mesh-extraction passage of
+ * Sec. 3.3): the splat depth and a unit opacity composited like a colour over
+ * a zero background, with the colour's fragments and termination:
+ *   depth[p] = sum_k alpha_k T_k z_k   (z: camera-space depth of the centre,
+ *                                        the record's last field),
+ *   alpha[p] = sum_k alpha_k T_k = 1 - final_T[p].
+ * DEVICE float [P] each (P = total pixels, view-major); either may be NULL.
+ * The normalised depth is depth / alpha where alpha > 0. */
+typedef struct {
+    float* depth;
+    float* alpha;
+} gesr_fwd_channels;
+
+/* Upstream gradients of the extended channels: DEVICE float [P] each, either
+ * may be NULL (a zero gradient). */
+typedef struct {
+    const float* dL_ddepth;
+    const float* dL_dalpha;
+} gesr_bwd_channels;
+
 /* Forward compositing (Eq. 5 as front-to-back alpha blending).  Per pixel,
  * over its tile's sorted list: q from the conic at the pixel centre,
  * alpha = min(alpha_max, o exp(-kappa q^(beta/2))); fragments with
@@ -218,6 +240,15 @@ gesr_status gesr_render_fwd(gesr_ctx* ctx, const gesr_proj* proj, const gesr_bin
                             int V, int n, const gesr_settings* st, float* image, float* final_T,
                             uint32_t* n_contrib, const gesr_fwd_counts* counts, void* stream);
 
+/* gesr_render_fwd that also writes the extended channels (channels may be NULL:
+ * then it is gesr_render_fwd).  The colour outputs are bitwise those of
+ * gesr_render_fwd.  Channels need the one-wave 16x16 renderer (tile 16x16,
+ * variant 0); other settings return GESR_ERR_UNSUPPORTED. */
+gesr_status gesr_render_fwd_ext(gesr_ctx* ctx, const gesr_proj* proj, const gesr_bins* bins,
+                                const gesr_camera* cams, int V, int n, const gesr_settings* st, float* image,
+                                float* final_T, uint32_t* n_contrib, const gesr_fwd_counts* counts,
+                                const gesr_fwd_channels* channels, void* stream);
+
 /* Backward pass: adjoint of gesr_render_fwd and gesr_project for upstream
  * dL_dimage (same layout as image).  Transmittance is recovered per pixel by
  * division from final_T and n_contrib (no per-fragment state is stored in the
@@ -226,22 +257,35 @@ gesr_status gesr_render_fwd(gesr_ctx* ctx, const gesr_proj* proj, const gesr_bin
  * projection adjoint, summed over views in ascending order.
  * `workspace` (DEVICE, gesr_sizes.bwd_workspace_bytes) holds, in order and
  * 256-byte aligned: the visited bits (uint32 [ceil(m_cap / 32)], one bit per
- * instance slot), the screen-space gradients (float [V*n][10]) and the
- * per-instance partials (float [m_cap][12]: the ten terms padded to twelve,
- * indexed by instance slot, see inst_base).  grad2d (DEVICE [V*n][10], nullable) receives the
- * screen-space gradients du, dv, dL00, dL10, dL11, dopacity, dbeta, dr, dg, db
- * (dbeta here is the falloff term only; the phi(beta) term is added in the
- * projection adjoint).  `out` arrays are overwritten.  Results are bitwise
+ * instance slot), the screen-space gradients (float [V*n][12]) and the
+ * per-instance partials (float [m_cap][12], indexed by instance slot, see
+ * inst_base).  grad2d (DEVICE [V*n][12], 16-byte aligned, nullable) receives
+ * the screen-space gradients du, dv, dL00, dL10, dL11, dopacity, dbeta, dr,
+ * dg, db, dz and a zero pad (dbeta here is the falloff term only; the
+ * phi(beta) term is added in the projection adjoint; dz, the gradient of the
+ * centre's camera depth, comes only from the extended channels).  `out` arrays are overwritten.  Results are bitwise
  * reproducible, and identical whether views are batched or rendered alone. */
 gesr_status gesr_render_bwd(gesr_ctx* ctx, const gesr_splats* splats, const gesr_proj* proj, const gesr_bins* bins,
                             const gesr_camera* cams, int V, const gesr_settings* st, const float* final_T,
                             const uint32_t* n_contrib, const float* dL_dimage, void* workspace, float* grad2d,
                             const gesr_grads* out, void* stream);
 
+/* gesr_render_bwd with upstream gradients of the extended channels as well
+ * (channels may be NULL: then it is gesr_render_bwd).  Each channel adds to
+ * every composited fragment's dL/dalpha the term T_k (c_k - B_k) g, with
+ * c_k = z_k (depth) or 1 (alpha) and B_k the channel composited behind the
+ * fragment per unit transmittance; depth adds dz = alpha_k T_k g_depth.
+ * Same renderer requirement as gesr_render_fwd_ext. */
+gesr_status gesr_render_bwd_ext(gesr_ctx* ctx, const gesr_splats* splats, const gesr_proj* proj,
+                                const gesr_bins* bins, const gesr_camera* cams, int V, const gesr_settings* st,
+                                const float* final_T, const uint32_t* n_contrib, const float* dL_dimage,
+                                const gesr_bwd_channels* channels, void* workspace, float* grad2d,
+                                const gesr_grads* out, void* stream);
+
 /* The two halves of gesr_render_bwd, for callers that schedule or time them
  * separately.  gesr_render_bwd_tiles: the per-tile render adjoint.  Each tile
  * visits its list up to the deepest position any of its pixels composited and
- * writes one gradient partial (10 floats, grad2d order) per visited instance
+ * writes one gradient partial (grad2d order) per visited instance
  * with a non-zero contribution into the workspace, setting the instance
  * slot's visited bit (the bits are cleared first).  gesr_project_bwd: per
  * (view, splat), the fixed-order sum of the partials whose bits are set, then
@@ -252,6 +296,12 @@ gesr_status gesr_render_bwd_tiles(gesr_ctx* ctx, const gesr_proj* proj, const ge
                                   const gesr_camera* cams, int V, int n, const gesr_settings* st,
                                   const float* final_T, const uint32_t* n_contrib, const float* dL_dimage,
                                   void* workspace, void* stream);
+/* gesr_render_bwd_tiles with the extended channels' upstream gradients
+ * (channels may be NULL). */
+gesr_status gesr_render_bwd_tiles_ext(gesr_ctx* ctx, const gesr_proj* proj, const gesr_bins* bins,
+                                      const gesr_camera* cams, int V, int n, const gesr_settings* st,
+                                      const float* final_T, const uint32_t* n_contrib, const float* dL_dimage,
+                                      const gesr_bwd_channels* channels, void* workspace, void* stream);
 gesr_status gesr_project_bwd(gesr_ctx* ctx, const gesr_splats* splats, const gesr_proj* proj, const gesr_bins* bins,
                              const gesr_camera* cams, int V, const gesr_settings* st, void* workspace,
                              float* grad2d, const gesr_grads* out, void* stream);

@@ -20,10 +20,12 @@ GESR_BIN_SYNC = 1
 MAX_VIEWS = 32
 REC_FLOATS = 12
 PARTIAL_FLOATS = 10
+GRAD2D_FLOATS = 12  # du dv dL00 dL10 dL11 dop dbeta dr dg db dz + zero pad
 
 EXPORTS = (
     "gesr_ctx_create", "gesr_ctx_destroy", "gesr_last_error", "gesr_status_string", "gesr_default_settings",
     "gesr_query_sizes", "gesr_project", "gesr_bin", "gesr_render_fwd", "gesr_render_bwd", "gesr_render_bwd_tiles",
+    "gesr_render_fwd_ext", "gesr_render_bwd_ext", "gesr_render_bwd_tiles_ext",
     "gesr_project_bwd", "gesr_l1_grad", "gesr_autotune", "gesr_autotune_candidate",
 )
 
@@ -78,6 +80,14 @@ class FwdCounts(ctypes.Structure):
     _fields_ = [("n_listed", ctypes.c_void_p), ("n_hit", ctypes.c_void_p)]
 
 
+class FwdChannels(ctypes.Structure):
+    _fields_ = [("depth", ctypes.c_void_p), ("alpha", ctypes.c_void_p)]
+
+
+class BwdChannels(ctypes.Structure):
+    _fields_ = [("dL_ddepth", ctypes.c_void_p), ("dL_dalpha", ctypes.c_void_p)]
+
+
 _lib = None
 
 
@@ -114,12 +124,21 @@ def load():
     lib.gesr_render_fwd.argtypes = [vp, P(Proj), P(Bins), P(Camera), ctypes.c_int, ctypes.c_int, P(Settings),
                                     vp, vp, vp, P(FwdCounts), vp]
     lib.gesr_render_fwd.restype = st
+    lib.gesr_render_fwd_ext.argtypes = [vp, P(Proj), P(Bins), P(Camera), ctypes.c_int, ctypes.c_int, P(Settings),
+                                        vp, vp, vp, P(FwdCounts), P(FwdChannels), vp]
+    lib.gesr_render_fwd_ext.restype = st
     lib.gesr_render_bwd.argtypes = [vp, P(Splats), P(Proj), P(Bins), P(Camera), ctypes.c_int, P(Settings),
                                     vp, vp, vp, vp, vp, P(Grads), vp]
     lib.gesr_render_bwd.restype = st
+    lib.gesr_render_bwd_ext.argtypes = [vp, P(Splats), P(Proj), P(Bins), P(Camera), ctypes.c_int, P(Settings),
+                                        vp, vp, vp, P(BwdChannels), vp, vp, P(Grads), vp]
+    lib.gesr_render_bwd_ext.restype = st
     lib.gesr_render_bwd_tiles.argtypes = [vp, P(Proj), P(Bins), P(Camera), ctypes.c_int, ctypes.c_int, P(Settings),
                                           vp, vp, vp, vp, vp]
     lib.gesr_render_bwd_tiles.restype = st
+    lib.gesr_render_bwd_tiles_ext.argtypes = [vp, P(Proj), P(Bins), P(Camera), ctypes.c_int, ctypes.c_int,
+                                              P(Settings), vp, vp, vp, P(BwdChannels), vp, vp]
+    lib.gesr_render_bwd_tiles_ext.restype = st
     lib.gesr_project_bwd.argtypes = [vp, P(Splats), P(Proj), P(Bins), P(Camera), ctypes.c_int, P(Settings), vp, vp,
                                      P(Grads), vp]
     lib.gesr_project_bwd.restype = st

@@ -227,8 +227,8 @@ BinScratch carve(void* base, const Geometry& g, const DevCams& dc, int n, uint64
 // Layout of the backward workspace (256-byte aligned sub-buffers).
 struct BwdWorkspace {
     uint32_t* visited;   // [ceil(m_cap / 32)] bit per instance slot
-    float* grad2d;       // [V*n][10]
-    float* partials;     // [m_cap][10]
+    float* grad2d;       // [V*n][GESR_GRAD2D_FLOATS]
+    float* partials;     // [m_cap][kPartialStride]
     size_t bytes;
 };
 
@@ -242,7 +242,7 @@ BwdWorkspace carve_bwd(void* base, uint64_t vn, uint64_t m_cap, uint64_t T) {
         return p;
     };
     w.visited = (uint32_t*)take(((m_cap + 31) / 32) * 4);
-    w.grad2d = (float*)take((vn > 0 ? vn : 1) * GESR_PARTIAL_FLOATS * 4);
+    w.grad2d = (float*)take((vn > 0 ? vn : 1) * GESR_GRAD2D_FLOATS * 4);
     w.partials = (float*)take(m_cap * kPartialStride * 4);
     w.bytes = off;
     return w;
@@ -489,9 +489,25 @@ gesr_status gesr_bin(gesr_ctx* ctx, const gesr_proj* proj, const gesr_camera* ca
     return GESR_OK;
 }
 
+// The extended channels run only in the one-wave 16x16 renderers.
+static gesr_status check_channel_renderer(gesr_ctx* ctx, const gesr_settings* st) {
+    if (st->tile_w != 16 || st->tile_h != 16 || st->variant != 0)
+        return fail(ctx, GESR_ERR_UNSUPPORTED,
+                    "depth/alpha channels need tile 16x16 and variant 0 (got %dx%d, variant %d)", st->tile_w,
+                    st->tile_h, st->variant);
+    return GESR_OK;
+}
+
 gesr_status gesr_render_fwd(gesr_ctx* ctx, const gesr_proj* proj, const gesr_bins* bins, const gesr_camera* cams,
                             int V, int n, const gesr_settings* st, float* image, float* final_T, uint32_t* n_contrib,
                             const gesr_fwd_counts* counts, void* stream) {
+    return gesr_render_fwd_ext(ctx, proj, bins, cams, V, n, st, image, final_T, n_contrib, counts, nullptr, stream);
+}
+
+gesr_status gesr_render_fwd_ext(gesr_ctx* ctx, const gesr_proj* proj, const gesr_bins* bins,
+                                const gesr_camera* cams, int V, int n, const gesr_settings* st, float* image,
+                                float* final_T, uint32_t* n_contrib, const gesr_fwd_counts* counts,
+                                const gesr_fwd_channels* channels, void* stream) {
     if (!ctx) return GESR_ERR_INVALID;
     GESR_TRY(check_settings(ctx, st));
     Geometry g;
@@ -501,6 +517,8 @@ gesr_status gesr_render_fwd(gesr_ctx* ctx, const gesr_proj* proj, const gesr_bin
     if (!image || !final_T || !n_contrib) return fail(ctx, GESR_ERR_INVALID, "image/final_T/n_contrib is NULL");
     if (counts && (!counts->n_listed || !counts->n_hit))
         return fail(ctx, GESR_ERR_INVALID, "counts given with a NULL array");
+    const bool ext = channels && (channels->depth || channels->alpha);
+    if (ext) GESR_TRY(check_channel_renderer(ctx, st));
     RenderArgs a;
     memset(&a, 0, sizeof a);
     a.n = n;
@@ -517,6 +535,8 @@ gesr_status gesr_render_fwd(gesr_ctx* ctx, const gesr_proj* proj, const gesr_bin
     a.n_contrib = n_contrib;
     a.n_listed = counts ? counts->n_listed : nullptr;
     a.n_hit = counts ? counts->n_hit : nullptr;
+    a.out_depth = ext ? channels->depth : nullptr;
+    a.out_alpha = ext ? channels->alpha : nullptr;
     a.st = dev_settings(st);
     a.cams = dev_cams(cams, V, st);
     GESR_TRY(hip_check(ctx, hipSetDevice(ctx->device), "hipSetDevice"));
@@ -530,6 +550,14 @@ gesr_status gesr_render_bwd_tiles(gesr_ctx* ctx, const gesr_proj* proj, const ge
                                   const gesr_camera* cams, int V, int n, const gesr_settings* st,
                                   const float* final_T, const uint32_t* n_contrib, const float* dL_dimage,
                                   void* workspace, void* stream) {
+    return gesr_render_bwd_tiles_ext(ctx, proj, bins, cams, V, n, st, final_T, n_contrib, dL_dimage, nullptr,
+                                     workspace, stream);
+}
+
+gesr_status gesr_render_bwd_tiles_ext(gesr_ctx* ctx, const gesr_proj* proj, const gesr_bins* bins,
+                                      const gesr_camera* cams, int V, int n, const gesr_settings* st,
+                                      const float* final_T, const uint32_t* n_contrib, const float* dL_dimage,
+                                      const gesr_bwd_channels* channels, void* workspace, void* stream) {
     if (!ctx) return GESR_ERR_INVALID;
     GESR_TRY(check_settings(ctx, st));
     Geometry g;
@@ -538,6 +566,8 @@ gesr_status gesr_render_bwd_tiles(gesr_ctx* ctx, const gesr_proj* proj, const ge
     GESR_TRY(check_bins(ctx, bins, false));
     if (!final_T || !n_contrib || !dL_dimage) return fail(ctx, GESR_ERR_INVALID, "final_T/n_contrib/dL_dimage is NULL");
     if (!workspace || !aligned16(workspace)) return fail(ctx, GESR_ERR_INVALID, "workspace is NULL or misaligned");
+    const bool ext = channels && (channels->dL_ddepth || channels->dL_dalpha);
+    if (ext) GESR_TRY(check_channel_renderer(ctx, st));
     GESR_TRY(hip_check(ctx, hipSetDevice(ctx->device), "hipSetDevice"));
     const BwdWorkspace ws = carve_bwd(workspace, g.vn, bins->m_cap, g.total_tiles);
     RenderArgs a;
@@ -554,6 +584,8 @@ gesr_status gesr_render_bwd_tiles(gesr_ctx* ctx, const gesr_proj* proj, const ge
     a.final_T = const_cast<float*>(final_T);
     a.n_contrib = const_cast<uint32_t*>(n_contrib);
     a.dL_dimage = dL_dimage;
+    a.dL_ddepth = ext ? channels->dL_ddepth : nullptr;
+    a.dL_dalpha = ext ? channels->dL_dalpha : nullptr;
     a.partials = ws.partials;
     a.m_cap = (uint32_t)bins->m_cap;
     a.visited = ws.visited;
@@ -626,11 +658,20 @@ gesr_status gesr_render_bwd(gesr_ctx* ctx, const gesr_splats* splats, const gesr
                             const gesr_camera* cams, int V, const gesr_settings* st, const float* final_T,
                             const uint32_t* n_contrib, const float* dL_dimage, void* workspace, float* grad2d,
                             const gesr_grads* out, void* stream) {
+    return gesr_render_bwd_ext(ctx, splats, proj, bins, cams, V, st, final_T, n_contrib, dL_dimage, nullptr,
+                               workspace, grad2d, out, stream);
+}
+
+gesr_status gesr_render_bwd_ext(gesr_ctx* ctx, const gesr_splats* splats, const gesr_proj* proj,
+                                const gesr_bins* bins, const gesr_camera* cams, int V, const gesr_settings* st,
+                                const float* final_T, const uint32_t* n_contrib, const float* dL_dimage,
+                                const gesr_bwd_channels* channels, void* workspace, float* grad2d,
+                                const gesr_grads* out, void* stream) {
     if (!ctx) return GESR_ERR_INVALID;
     if (!splats) return fail(ctx, GESR_ERR_INVALID, "splats is NULL");
     if (!out) return fail(ctx, GESR_ERR_INVALID, "out is NULL");
-    GESR_TRY(gesr_render_bwd_tiles(ctx, proj, bins, cams, V, splats->n, st, final_T, n_contrib, dL_dimage, workspace,
-                                   stream));
+    GESR_TRY(gesr_render_bwd_tiles_ext(ctx, proj, bins, cams, V, splats->n, st, final_T, n_contrib, dL_dimage,
+                                       channels, workspace, stream));
     return gesr_project_bwd(ctx, splats, proj, bins, cams, V, st, workspace, grad2d, out, stream);
 }
 

@@ -23,7 +23,7 @@ struct ProjectBwdArgs {
     int n;
     const float *mean, *scale, *quat, *opacity, *beta, *sh;
     const uint32_t* tiles_touched;
-    const float* grad2d;  // [V*n][10] screen-space gradients
+    const float* grad2d;  // [V*n][GESR_GRAD2D_FLOATS] screen-space gradients
     float *g_mean, *g_scale, *g_quat, *g_opacity, *g_beta, *g_sh;
     DevSettings st;
     DevCams cams;
@@ -57,8 +57,12 @@ struct RenderArgs {
     uint32_t* n_contrib;
     uint32_t* n_listed;  // nullable
     uint32_t* n_hit;     // nullable
+    float* out_depth;    // extended channels (nullable; only the one-wave 16x16 renderer)
+    float* out_alpha;
     // backward
     const float* dL_dimage;
+    const float* dL_ddepth;  // extended channels' upstream gradients (nullable)
+    const float* dL_dalpha;
     float* partials;
     uint32_t m_cap;      // capacity of partials (instances); only reached when the lists overflowed
     uint32_t* visited;   // bit per instance slot, set where non-zero partials were written
@@ -69,6 +73,8 @@ struct RenderArgs {
 hipError_t launch_project(const ProjectArgs& a, int sh_degree, hipStream_t stream);
 hipError_t launch_project_bwd(const ProjectBwdArgs& a, int sh_degree, hipStream_t stream);
 hipError_t launch_seg_reduce(const SegReduceArgs& a, hipStream_t stream);
+// Channels (a.out_depth / a.out_alpha, a.dL_ddepth / a.dL_dalpha non-null) need
+// tile 16x16 with batch 32 or 64 (the one-wave renderers); callers check.
 hipError_t launch_render_fwd(const RenderArgs& a, int tile_w, int tile_h, bool counts, hipStream_t stream);
 hipError_t launch_render_bwd(const RenderArgs& a, int tile_w, int tile_h, int batch, hipStream_t stream);
 

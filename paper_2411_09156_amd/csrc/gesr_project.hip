@@ -356,13 +356,15 @@ __global__ __launch_bounds__(256) void k_project_bwd(ProjectBwdArgs a) {
         const size_t vi = (size_t)v * n + i;
         const uint32_t cnt = a.tiles_touched[vi];
         if (cnt == 0) continue;
-        float g2[GESR_PARTIAL_FLOATS];
-        const float2* src = reinterpret_cast<const float2*>(a.grad2d + vi * GESR_PARTIAL_FLOATS);
+        float g2[GESR_GRAD2D_FLOATS];
+        const float4* src = reinterpret_cast<const float4*>(a.grad2d + vi * GESR_GRAD2D_FLOATS);
 #pragma unroll
-        for (int k = 0; k < GESR_PARTIAL_FLOATS / 2; ++k) {
-            const float2 t2 = src[k];
-            g2[2 * k] = t2.x;
-            g2[2 * k + 1] = t2.y;
+        for (int k = 0; k < GESR_GRAD2D_FLOATS / 4; ++k) {
+            const float4 t4 = src[k];
+            g2[4 * k] = t4.x;
+            g2[4 * k + 1] = t4.y;
+            g2[4 * k + 2] = t4.z;
+            g2[4 * k + 3] = t4.w;
         }
         const float du = g2[0], dv = g2[1];
 
@@ -442,6 +444,8 @@ __global__ __launch_bounds__(256) void k_project_bwd(ProjectBwdArgs a) {
         dp[0] += du * w.fx * iz;
         dp[1] += dv * w.fy * iz;
         dp[2] += -(du * w.fx * vp.p[0] + dv * w.fy * vp.p[1]) * iz2;
+        // depth of the centre (extended channels): z = p[2]
+        dp[2] += g2[10];
         // p = W mean + t
         for (int k = 0; k < 3; ++k) lm[k] += w.R[k] * dp[0] + w.R[3 + k] * dp[1] + w.R[6 + k] * dp[2];
 
@@ -509,7 +513,7 @@ __global__ __launch_bounds__(256) void k_project_bwd(ProjectBwdArgs a) {
 constexpr uint32_t kSegLanes = 8;
 
 __global__ __launch_bounds__(256) void k_seg_reduce(SegReduceArgs a) {
-    constexpr int NP = GESR_PARTIAL_FLOATS;
+    constexpr int NP = GESR_PARTIAL_FLOATS + 1;  // the ten terms and dz
     constexpr uint32_t L = kSegLanes;
     const uint64_t vi = ((uint64_t)blockIdx.x * 256u + threadIdx.x) / L;
     const uint32_t lane = __lane_id() & (L - 1);
@@ -562,9 +566,10 @@ __global__ __launch_bounds__(256) void k_seg_reduce(SegReduceArgs a) {
     }
     // groups without visited instances hold zeros; the last lane of each group writes
     if (valid && lane == L - 1) {
-        float2* out = reinterpret_cast<float2*>(a.grad2d + (size_t)vi * NP);
-#pragma unroll
-        for (int k = 0; k < NP / 2; ++k) out[k] = make_float2(acc[2 * k], acc[2 * k + 1]);
+        float4* out = reinterpret_cast<float4*>(a.grad2d + (size_t)vi * GESR_GRAD2D_FLOATS);
+        out[0] = make_float4(acc[0], acc[1], acc[2], acc[3]);
+        out[1] = make_float4(acc[4], acc[5], acc[6], acc[7]);
+        out[2] = make_float4(acc[8], acc[9], acc[10], 0.0f);
     }
 }
 

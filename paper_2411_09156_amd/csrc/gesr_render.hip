@@ -121,18 +121,21 @@ __device__ __forceinline__ uint32_t instance_index(const RenderArgs& a, uint2 r,
     return inside && inst < a.m_cap ? inst : kNoInstance;
 }
 
-// Partials of one instance (ten terms in a twelve-float slot): written, and
-// its slot's bit set, unless all ten are zero (the segmented sum adding +-0 or skipping the slot gives the same
-// float result, since its running sums start at +0).
+// Partials of one instance (ten terms, dz with the extended channels, in a
+// twelve-float slot): written, and its slot's bit set, unless all are zero
+// (the segmented sum adding +-0 or skipping the slot gives the same float
+// result, since its running sums start at +0).
+template <bool EXT>
 __device__ __forceinline__ void write_partial(const RenderArgs& a, uint32_t slot, const float* s) {
+    constexpr int NT = EXT ? GESR_PARTIAL_FLOATS + 1 : GESR_PARTIAL_FLOATS;
     bool nz = false;
 #pragma unroll
-    for (int k = 0; k < GESR_PARTIAL_FLOATS; ++k) nz |= s[k] != 0.0f;
+    for (int k = 0; k < NT; ++k) nz |= s[k] != 0.0f;
     if (!nz) return;
     float4* dst = reinterpret_cast<float4*>(a.partials + (size_t)slot * kPartialStride);
     dst[0] = make_float4(s[0], s[1], s[2], s[3]);
     dst[1] = make_float4(s[4], s[5], s[6], s[7]);
-    dst[2] = make_float4(s[8], s[9], 0.0f, 0.0f);
+    dst[2] = make_float4(s[8], s[9], EXT ? s[10] : 0.0f, 0.0f);
     atomicOr(a.visited + (slot >> 5), 1u << (slot & 31u));
 }
 
@@ -295,7 +298,7 @@ __global__ __launch_bounds__(TW * TH) void k_render_bwd(RenderArgs a) {
             for (int w = 1; w < NW; ++w)
 #pragma unroll
                 for (int k = 0; k < NP; ++k) s[k] += sRed[w][jj][k];
-            write_partial(a, sInst[jj], s);
+            write_partial<false>(a, sInst[jj], s);
         }
         __syncthreads();
         hi = lo;
@@ -305,7 +308,8 @@ __global__ __launch_bounds__(TW * TH) void k_render_bwd(RenderArgs a) {
 // Forward, one wave per 16x16 tile with 4 pixels per lane (one per 8x8
 // quadrant): a staged splat's LDS reads serve 256 pixels; the wave leaves the
 // tile once all its pixels have terminated.
-template <bool COUNT, int B>
+// EXT: also the extended channels (depth composited over zero, alpha = 1 - T).
+template <bool COUNT, int B, bool EXT>
 __global__ __launch_bounds__(64) void k_render_fwd_wave16(RenderArgs a) {
     static_assert(B >= 1 && B <= 64, "one staged record per lane");
     __shared__ float4 sA[B], sB[B], sC[B];
@@ -320,7 +324,7 @@ __global__ __launch_bounds__(64) void k_render_fwd_wave16(RenderArgs a) {
     const uint2 rg = reinterpret_cast<const uint2*>(a.ranges)[t];
     const uint32_t r0 = rg.x, r1 = rg.y;
 
-    float px[4], py[4], T[4], cr[4], cg[4], cb[4];
+    float px[4], py[4], T[4], cr[4], cg[4], cb[4], cd[4];
     uint32_t contrib[4], listed[4], hit[4];
     bool done[4], inside[4];
 #pragma unroll
@@ -330,7 +334,7 @@ __global__ __launch_bounds__(64) void k_render_fwd_wave16(RenderArgs a) {
         px[q] = (float)x + 0.5f;
         py[q] = (float)y + 0.5f;
         T[q] = 1.0f;
-        cr[q] = cg[q] = cb[q] = 0.f;
+        cr[q] = cg[q] = cb[q] = cd[q] = 0.f;
         contrib[q] = listed[q] = hit[q] = 0;
         inside[q] = x < w.W && y < w.H;
         done[q] = !inside[q];
@@ -382,6 +386,7 @@ __global__ __launch_bounds__(64) void k_render_fwd_wave16(RenderArgs a) {
                 cr[q] = fmaf(rc.x, wgt, cr[q]);
                 cg[q] = fmaf(rc.y, wgt, cg[q]);
                 cb[q] = fmaf(rc.z, wgt, cb[q]);
+                if (EXT) cd[q] = fmaf(rc.w, wgt, cd[q]);  // rc.w: the splat's depth
                 T[q] = Tn;
                 contrib[q] = base + (uint32_t)j + 1u - r0;
             }
@@ -405,14 +410,20 @@ __global__ __launch_bounds__(64) void k_render_fwd_wave16(RenderArgs a) {
             a.n_listed[pix] = listed[q];
             a.n_hit[pix] = hit[q];
         }
+        if (EXT) {
+            if (a.out_depth) a.out_depth[pix] = cd[q];
+            if (a.out_alpha) a.out_alpha[pix] = 1.0f - T[q];
+        }
     }
 }
 
 // Backward, one wave per 16x16 tile: lane l owns pixel (l & 7, l >> 3) of each
 // 8x8 quadrant (4 pixels per lane), so a staged splat's LDS reads and its
 // 10-value wave reduction serve 256 pixels, and no cross-wave reduction or
-// workgroup barrier beyond the wave itself is needed.
-template <int B>
+// workgroup barrier beyond the wave itself is needed.  EXT: the extended
+// channels' upstream gradients too (depth and opacity as colour channels over
+// a zero background; the depth term dz is the eleventh partial value).
+template <int B, bool EXT>
 __global__ __launch_bounds__(64) void k_render_bwd_wave16(RenderArgs a) {
     // The gradient arithmetic may fuse multiply-adds; the alpha, threshold and
     // transmittance evaluation shared with the forward is written with explicit
@@ -423,7 +434,8 @@ __global__ __launch_bounds__(64) void k_render_bwd_wave16(RenderArgs a) {
     static_assert(NP == 10, "wave_sum10 reduces ten values");
     __shared__ float4 sA[B], sB[B], sC[B];
     __shared__ uint32_t sInst[B];
-    __shared__ float sRed[B][NP + 1];
+    __shared__ float sRed[B][NP + 1];  // column NP: dz (extended channels)
+    __shared__ float sZ[EXT ? B : 1];   // staged splat depths (extended channels)
 
     const uint32_t t = a.worklist[blockIdx.x];
     const DevSettings& st = a.st;
@@ -441,6 +453,7 @@ __global__ __launch_bounds__(64) void k_render_bwd_wave16(RenderArgs a) {
     // pixel centres: quadrant q adds (q & 1) * 8 and (q >> 1) * 8 to the lane's base
     const float pxb = (float)(tx * 16 + (lane & 7)) + 0.5f, pyb = (float)(ty * 16 + (lane >> 3)) + 0.5f;
     float T[4], g0[4], g1[4], g2[4], Br[4], Bg[4], Bb[4];
+    float gD[4], gA[4], BD[4], BA[4];  // extended channels: upstream gradients, depth and opacity behind
     uint32_t nc[4];
     uint32_t mymax = 0;
 #pragma unroll
@@ -452,6 +465,7 @@ __global__ __launch_bounds__(64) void k_render_bwd_wave16(RenderArgs a) {
         Bb[q] = st.bg[2];
         T[q] = 0.f;
         g0[q] = g1[q] = g2[q] = 0.f;
+        gD[q] = gA[q] = BD[q] = BA[q] = 0.f;
         nc[q] = 0;
         if (x < w.W && y < w.H) {
             const uint32_t local = (uint32_t)y * (uint32_t)w.W + (uint32_t)x;
@@ -461,6 +475,10 @@ __global__ __launch_bounds__(64) void k_render_bwd_wave16(RenderArgs a) {
             g0[q] = a.dL_dimage[img];
             g1[q] = a.dL_dimage[img + ch];
             g2[q] = a.dL_dimage[img + 2 * ch];
+            if (EXT) {
+                if (a.dL_ddepth) gD[q] = a.dL_ddepth[pix];
+                if (a.dL_dalpha) gA[q] = a.dL_dalpha[pix];
+            }
         }
         mymax = max(mymax, nc[q]);
     }
@@ -475,6 +493,7 @@ __global__ __launch_bounds__(64) void k_render_bwd_wave16(RenderArgs a) {
             const uint32_t pos = hi - 1u - lane;
             const uint32_t vi = a.val_sorted[pos];
             stage_record(a.rec, vi, st.kappa, sA[lane], sB[lane], sC[lane]);
+            if (EXT) sZ[lane] = a.rec[(size_t)vi * GESR_REC_FLOATS + 11];
             const uint2 r = reinterpret_cast<const uint2*>(a.rect)[vi];
             sInst[lane] = instance_index(a, r, vi, tx, ty);
         }
@@ -484,9 +503,11 @@ __global__ __launch_bounds__(64) void k_render_bwd_wave16(RenderArgs a) {
             const float4 ra = sA[j];
             const float4 rb = sB[j];
             const float4 rc = sC[j];
-            float gr[NP];
+            const float z = EXT ? sZ[j] : 0.0f;
+            float gr[NP], gz = 0.0f;
 #pragma unroll
             for (int k = 0; k < NP; k += 2) opaque_zero2(gr[k], gr[k + 1]);
+            if (EXT) gz = opaque_zero();
             bool act = false;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
@@ -502,22 +523,32 @@ __global__ __launch_bounds__(64) void k_render_bwd_wave16(RenderArgs a) {
                 gr[7] += aT * g0[q];
                 gr[8] += aT * g1[q];
                 gr[9] += aT * g2[q];
-                const float dLda = Tk * ((rc.x - Br[q]) * g0[q] + (rc.y - Bg[q]) * g1[q] + (rc.z - Bb[q]) * g2[q]);
+                float dLda = Tk * ((rc.x - Br[q]) * g0[q] + (rc.y - Bg[q]) * g1[q] + (rc.z - Bb[q]) * g2[q]);
                 Br[q] = fmaf(f.alpha, rc.x - Br[q], Br[q]);
                 Bg[q] = fmaf(f.alpha, rc.y - Bg[q], Bg[q]);
                 Bb[q] = fmaf(f.alpha, rc.z - Bb[q], Bb[q]);
+                if (EXT) {
+                    dLda += Tk * ((z - BD[q]) * gD[q] + (1.0f - BA[q]) * gA[q]);
+                    gz += aT * gD[q];
+                    BD[q] = fmaf(f.alpha, z - BD[q], BD[q]);
+                    BA[q] = fmaf(f.alpha, 1.0f - BA[q], BA[q]);
+                }
                 T[q] = Tk;
                 add_fragment_grad(f, ra, rb, rc.w, dLda, st.alpha_max, c2, gr);
             }
             if (__ballot(act) != 0ull) {
                 const float tot = wave_sum10(gr, lane);
                 if (slot < NP) sRed[j][slot] = tot;
-            } else if ((int)lane < NP) {
+                if (EXT) {
+                    const float tz = wave_sum(gz);
+                    if (lane == 0) sRed[j][NP] = tz;
+                }
+            } else if ((int)lane < (EXT ? NP + 1 : NP)) {
                 sRed[j][lane] = 0.f;
             }
         }
         __syncthreads();
-        if ((int)lane < cnt && sInst[lane] != kNoInstance) write_partial(a, sInst[lane], sRed[lane]);
+        if ((int)lane < cnt && sInst[lane] != kNoInstance) write_partial<EXT>(a, sInst[lane], sRed[lane]);
         __syncthreads();
         hi = lo;
     }
@@ -544,13 +575,22 @@ hipError_t launch_render_fwd(const RenderArgs& a, int tw, int th, bool counts, h
     if (a.n_items == 0) return hipSuccess;
     if (tw == 16 && th == 16) {
         if (a.st.variant == 1) return fwd_shape<16, 16>(a, counts, s);
-        const bool small = a.batch == 32;
-        if (counts) {
-            if (small) hipLaunchKernelGGL((k_render_fwd_wave16<true, 32>), dim3(a.n_items), dim3(64), 0, s, a);
-            else hipLaunchKernelGGL((k_render_fwd_wave16<true, 64>), dim3(a.n_items), dim3(64), 0, s, a);
+        const bool small = a.batch == 32, ext = a.out_depth || a.out_alpha;
+        const dim3 grid(a.n_items), block(64);
+        if (ext) {
+            if (counts) {
+                if (small) hipLaunchKernelGGL((k_render_fwd_wave16<true, 32, true>), grid, block, 0, s, a);
+                else hipLaunchKernelGGL((k_render_fwd_wave16<true, 64, true>), grid, block, 0, s, a);
+            } else {
+                if (small) hipLaunchKernelGGL((k_render_fwd_wave16<false, 32, true>), grid, block, 0, s, a);
+                else hipLaunchKernelGGL((k_render_fwd_wave16<false, 64, true>), grid, block, 0, s, a);
+            }
+        } else if (counts) {
+            if (small) hipLaunchKernelGGL((k_render_fwd_wave16<true, 32, false>), grid, block, 0, s, a);
+            else hipLaunchKernelGGL((k_render_fwd_wave16<true, 64, false>), grid, block, 0, s, a);
         } else {
-            if (small) hipLaunchKernelGGL((k_render_fwd_wave16<false, 32>), dim3(a.n_items), dim3(64), 0, s, a);
-            else hipLaunchKernelGGL((k_render_fwd_wave16<false, 64>), dim3(a.n_items), dim3(64), 0, s, a);
+            if (small) hipLaunchKernelGGL((k_render_fwd_wave16<false, 32, false>), grid, block, 0, s, a);
+            else hipLaunchKernelGGL((k_render_fwd_wave16<false, 64, false>), grid, block, 0, s, a);
         }
         return hipGetLastError();
     }
@@ -565,8 +605,15 @@ hipError_t launch_render_bwd(const RenderArgs& a, int tw, int th, int batch, hip
     if (tw == 16 && th == 16) {
         if (a.st.variant == 1)  // one workgroup of 4 waves per tile
             return batch >= 128 ? bwd_shape<16, 16, 128>(a, s) : bwd_shape<16, 16, 64>(a, s);
-        if (batch == 32) hipLaunchKernelGGL(k_render_bwd_wave16<32>, dim3(a.n_items), dim3(64), 0, s, a);
-        else hipLaunchKernelGGL(k_render_bwd_wave16<64>, dim3(a.n_items), dim3(64), 0, s, a);
+        const bool ext = a.dL_ddepth || a.dL_dalpha;
+        const dim3 grid(a.n_items), block(64);
+        if (ext) {
+            if (batch == 32) hipLaunchKernelGGL((k_render_bwd_wave16<32, true>), grid, block, 0, s, a);
+            else hipLaunchKernelGGL((k_render_bwd_wave16<64, true>), grid, block, 0, s, a);
+        } else {
+            if (batch == 32) hipLaunchKernelGGL((k_render_bwd_wave16<32, false>), grid, block, 0, s, a);
+            else hipLaunchKernelGGL((k_render_bwd_wave16<64, false>), grid, block, 0, s, a);
+        }
         return hipGetLastError();
     }
     if (tw == 8 && th == 8) return bwd_shape<8, 8, 64>(a, s);

@@ -209,7 +209,9 @@ class Rasterizer:
                 self.m_cap_hint = max(self.m_cap_hint, int(m.value * 1.05) + 1024)
             return b
 
-    def render_fwd(self, proj: dict, bins: dict, n: int, counts: bool = False) -> dict:
+    def render_fwd(self, proj: dict, bins: dict, n: int, counts: bool = False, channels: bool = False) -> dict:
+        """Forward compositing; `channels` adds the extended depth (sum alpha T z)
+        and alpha (1 - final_T) maps, [P] each."""
         P = self.n_pixels
         out = dict(image=self._empty(3 * P), final_T=self._empty(P), n_contrib=self._empty(P, torch.int32))
         cnt = None
@@ -217,11 +219,17 @@ class Rasterizer:
             out["n_listed"] = self._empty(P, torch.int32)
             out["n_hit"] = self._empty(P, torch.int32)
             cnt = _lib.FwdCounts(out["n_listed"].data_ptr(), out["n_hit"].data_ptr())
-        self._check(self.lib.gesr_render_fwd(self.ctx, ctypes.byref(self._proj_c(proj)),
-                                             ctypes.byref(self._bins_c(bins)), self.cams_c, self.V, n,
-                                             ctypes.byref(self.st_c), out["image"].data_ptr(),
-                                             out["final_T"].data_ptr(), out["n_contrib"].data_ptr(),
-                                             ctypes.byref(cnt) if cnt is not None else None, _stream()), self.ctx)
+        chn = None
+        if channels:
+            out["depth"] = self._empty(P)
+            out["alpha"] = self._empty(P)
+            chn = _lib.FwdChannels(out["depth"].data_ptr(), out["alpha"].data_ptr())
+        self._check(self.lib.gesr_render_fwd_ext(self.ctx, ctypes.byref(self._proj_c(proj)),
+                                                 ctypes.byref(self._bins_c(bins)), self.cams_c, self.V, n,
+                                                 ctypes.byref(self.st_c), out["image"].data_ptr(),
+                                                 out["final_T"].data_ptr(), out["n_contrib"].data_ptr(),
+                                                 ctypes.byref(cnt) if cnt is not None else None,
+                                                 ctypes.byref(chn) if chn is not None else None, _stream()), self.ctx)
         return out
 
     def alloc_workspace(self, n: int, m_cap: int) -> torch.Tensor:
@@ -229,19 +237,30 @@ class Rasterizer:
         return torch.empty(int(self.sizes(n, m_cap).bwd_workspace_bytes), dtype=torch.uint8, device=self.device)
 
     def render_bwd(self, sp: Splats, proj: dict, bins: dict, final_T, n_contrib, dL_dimage,
-                   want_grad2d: bool = False) -> dict:
-        ws = self.render_bwd_tiles(proj, bins, sp.n, final_T, n_contrib, dL_dimage)
+                   want_grad2d: bool = False, dL_ddepth=None, dL_dalpha=None) -> dict:
+        ws = self.render_bwd_tiles(proj, bins, sp.n, final_T, n_contrib, dL_dimage, dL_ddepth=dL_ddepth,
+                                   dL_dalpha=dL_dalpha)
         return self.project_bwd(sp, proj, bins, ws, want_grad2d=want_grad2d)
 
-    def render_bwd_tiles(self, proj: dict, bins: dict, n: int, final_T, n_contrib, dL_dimage, workspace=None):
-        """Per-tile render adjoint only: returns the backward workspace."""
+    def render_bwd_tiles(self, proj: dict, bins: dict, n: int, final_T, n_contrib, dL_dimage, workspace=None,
+                         dL_ddepth=None, dL_dalpha=None):
+        """Per-tile render adjoint only (with the extended channels' upstream
+        gradients when given): returns the backward workspace."""
         if workspace is None:
             workspace = self.alloc_workspace(n, bins["m_cap"])
         dL = dL_dimage.contiguous()
-        self._check(self.lib.gesr_render_bwd_tiles(self.ctx, ctypes.byref(self._proj_c(proj)),
-                                                   ctypes.byref(self._bins_c(bins)), self.cams_c, self.V, n,
-                                                   ctypes.byref(self.st_c), final_T.data_ptr(), n_contrib.data_ptr(),
-                                                   dL.data_ptr(), workspace.data_ptr(), _stream()), self.ctx)
+        gd = dL_ddepth.contiguous() if dL_ddepth is not None else None
+        ga = dL_dalpha.contiguous() if dL_dalpha is not None else None
+        chn = None
+        if gd is not None or ga is not None:
+            chn = _lib.BwdChannels(gd.data_ptr() if gd is not None else None,
+                                   ga.data_ptr() if ga is not None else None)
+        self._check(self.lib.gesr_render_bwd_tiles_ext(self.ctx, ctypes.byref(self._proj_c(proj)),
+                                                       ctypes.byref(self._bins_c(bins)), self.cams_c, self.V, n,
+                                                       ctypes.byref(self.st_c), final_T.data_ptr(),
+                                                       n_contrib.data_ptr(), dL.data_ptr(),
+                                                       ctypes.byref(chn) if chn is not None else None,
+                                                       workspace.data_ptr(), _stream()), self.ctx)
         return workspace
 
     def project_bwd(self, sp: Splats, proj: dict, bins: dict, workspace, want_grad2d: bool = False) -> dict:
@@ -249,7 +268,7 @@ class Rasterizer:
         g = dict(mean=torch.empty_like(sp.mean), scale=torch.empty_like(sp.scale), quat=torch.empty_like(sp.quat),
                  opacity=torch.empty_like(sp.opacity), beta=torch.empty_like(sp.beta), sh=torch.empty_like(sp.sh))
         gc = _lib.Grads(*(g[k].data_ptr() for k in ("mean", "scale", "quat", "opacity", "beta", "sh")))
-        grad2d = self._empty(self.V * sp.n * _lib.PARTIAL_FLOATS) if want_grad2d else None
+        grad2d = self._empty(self.V * sp.n * _lib.GRAD2D_FLOATS) if want_grad2d else None
         self._check(self.lib.gesr_project_bwd(self.ctx, ctypes.byref(sp.to_c()), ctypes.byref(self._proj_c(proj)),
                                               ctypes.byref(self._bins_c(bins)), self.cams_c, self.V,
                                               ctypes.byref(self.st_c), workspace.data_ptr(),
@@ -265,10 +284,11 @@ class Rasterizer:
                                           float(scale), grad.data_ptr(), _stream()), self.ctx)
         return grad
 
-    def forward(self, sp: Splats, sync: bool = True, m_cap: Optional[int] = None, counts: bool = False):
+    def forward(self, sp: Splats, sync: bool = True, m_cap: Optional[int] = None, counts: bool = False,
+                channels: bool = False):
         proj = self.project(sp)
         bins = self.bin(proj, sp.n, m_cap=m_cap, sync=sync)
-        out = self.render_fwd(proj, bins, sp.n, counts=counts)
+        out = self.render_fwd(proj, bins, sp.n, counts=counts, channels=channels)
         out.update(proj=proj, bins=bins)
         return out
 

@@ -84,7 +84,8 @@ def run_gpu_bwd(scene, st: oracle.Settings, res: dict, dL) -> dict:
     torch.cuda.synchronize()
     N, V = scene.n, scene.n_views
     K = (st.sh_degree + 1) ** 2
-    return dict(grad2d=f32(g["grad2d"])[:N * V * 10].reshape(N * V, 10),
+    # grad2d rows: du dv dL00 dL10 dL11 dop dbeta dr dg db dz and a zero pad
+    return dict(grad2d=f32(g["grad2d"])[:N * V * 12].reshape(N * V, 12)[:, :11],
                 means=f32(g["mean"]).reshape(3, N).T, scales=f32(g["scale"]).reshape(3, N).T,
                 quats=f32(g["quat"]).reshape(4, N).T, opacities=f32(g["opacity"]), betas=f32(g["beta"]),
                 sh=f32(g["sh"]).reshape(K * 3, N).T.reshape(N, K, 3))

@@ -170,7 +170,7 @@ def test_batched_equals_per_view_bitwise():
         np.testing.assert_array_equal(fv["image"][:3 * P], fb["image"][off_i:off_i + 3 * P])
         np.testing.assert_array_equal(fv["final_T"][:P], fb["final_T"][off_p:off_p + P])
         np.testing.assert_array_equal(fv["n_contrib"][:P], fb["n_contrib"][off_p:off_p + P])
-        np.testing.assert_array_equal(gv["grad2d"][:N * 10], gb["grad2d"][v * N * 10:(v + 1) * N * 10])
+        np.testing.assert_array_equal(gv["grad2d"][:N * 12], gb["grad2d"][v * N * 12:(v + 1) * N * 12])
         # views accumulate in ascending order in float32, starting from zero
         acc = {k: gv[k].copy() for k in gv if k != "grad2d"} if acc is None else \
             {k: (acc[k] + gv[k]).astype(np.float32) for k in acc}
@@ -461,7 +461,7 @@ def test_full_size_workload(k):
     gpu = rast.render_bwd(sp, proj, bins, f["final_T"], f["n_contrib"],
                           torch.as_tensor(dL.astype(np.float32), device="cuda"), want_grad2d=True)
     torch.cuda.synchronize()
-    g2 = f32(gpu["grad2d"])[:VN * 10].reshape(VN, 10)
+    g2 = f32(gpu["grad2d"])[:VN * 12].reshape(VN, 12)[:, :11]
     ref2 = conic_grads_to_factor(oracle.render_bwd(N, scene.cameras, orec, val, masked, dL, st), rec)
     for c in range(10):
         einf, e2 = norm_errors(g2[:, c], ref2[:, c])
@@ -472,12 +472,12 @@ def test_full_size_workload(k):
                sh=f32(gpu["sh"]).reshape(K * 3, N).T.reshape(N, K, 3))
     # splats the sampled tiles reach: the oracle's projection adjoint on that sub-scene;
     # every other splat's gradient must be exactly zero
-    touched = np.abs(g2).reshape(V, N, 10).max(axis=(0, 2)) > 0
+    touched = np.abs(g2).reshape(V, N, 11).max(axis=(0, 2)) > 0
     idx = np.nonzero(touched)[0]
     sub = copy.copy(scene)
     for f in ("means", "log_scales", "scales", "quats", "opacity_logits", "opacities", "betas", "sh"):
         setattr(sub, f, getattr(scene, f)[idx])
-    g2_sub = g2.reshape(V, N, 10)[:, idx].reshape(-1, 10)
+    g2_sub = g2.reshape(V, N, 11)[:, idx].reshape(-1, 11)
     rec_sub = rec.reshape(V, N, 12)[:, idx].reshape(-1, 12)
     ref = oracle.project_bwd(sub, factor_grads_to_conic(g2_sub, rec_sub), st)
     worst = 0.0
