@@ -41,13 +41,18 @@ HBM_BYTES_PER_S = 8.0e12
 #             into multiply-adds)
 FWD_LISTED, FWD_HIT = 8, 18
 BWD_LISTED, BWD_HIT = 9, 48
+# with the extended depth and alpha channels (--channels): the forward adds one
+# depth multiply-add per hit; the adjoint adds the two channels' dL/dalpha terms
+# (2 differences, a multiply and 2 multiply-adds), the dz term and the two
+# behind-accumulator updates (8)
+FWD_HIT_CHANNELS, BWD_HIT_CHANNELS = 19, 56
 
 # HBM bytes per launch of the tile adjoint on the default workload, from two
 # rocprofv3 counter passes (FETCH_SIZE x2.0, WRITE_SIZE x1.0 after calibration
 # against a 1 GiB copy; profiles/drt-500k-8views_hbm_counters.md).  Valid only
 # for the kernel source it was measured on (fingerprint below); otherwise null.
 MEASURED_TRAFFIC = {"kernel": "render_bwd_tiles", "workload": "drt-batch-500k-8views",
-                    "fingerprint": "286c6a8fab76ac86", "bytes": 4179403799,
+                    "fingerprint": "5250e482c3f24352", "bytes": 4178504602,
                     "settings": (16, 16, 0, 64)}  # tile_w, tile_h, variant, batch of the measured run
 
 
@@ -74,6 +79,9 @@ def parse_args():
     p.add_argument("--no-autotune", action="store_true",
                    help="keep --tile/--batch instead of the autotuner's choice")
     p.add_argument("--cpu-sample-views", default="0,1,2,3,4,5")
+    p.add_argument("--channels", action="store_true",
+                   help="extended rasterizer: depth and alpha maps in the forward and seeded synthetic upstream "
+                        "gradients for them in the backward (16x16 one-wave renderer; implies --no-autotune)")
     p.add_argument("--calibrate-copy", type=int, default=0,
                    help="also run a plain device copy of this many MiB (hardware counter calibration)")
     return p.parse_args()
@@ -106,8 +114,18 @@ def main():
     rs = RasterSettings(sh_degree=scene.sh_degree, tile_w=tw, tile_h=th, batch=args.batch)
     sp = Splats.from_aos(scene.means, scene.scales, scene.quats, scene.opacities, scene.betas, scene.sh)
     target = torch.as_tensor(np.concatenate([t.reshape(-1) for t in gi.target_images(scene, k)]), device="cuda")
+    chan = None
+    if args.channels:
+        # upstream gradients of the depth and alpha maps (a stand-in for a depth
+        # or mask loss): seeded normals scaled like the L1 image gradient
+        rng = np.random.default_rng([k, 77])
+        chan = tuple(torch.as_tensor((rng.standard_normal(P) / (3 * P)).astype(np.float32), device="cuda")
+                     for _ in range(2))
+        if not args.no_autotune:
+            log("[bench] --channels: the extended channels run in the 16x16 one-wave renderer; autotuning is skipped")
+            args.no_autotune = True
 
-    def make_step(rast, sp, target, m_cap, events=None):
+    def make_step(rast, sp, target, m_cap, events=None, chan=None):
         n = sp.n
         scale = 1.0 / float(target.numel())
 
@@ -121,11 +139,13 @@ def main():
             rec(1)
             bins = rast.bin(proj, n, m_cap=m_cap, sync=False)
             rec(2)
-            f = rast.render_fwd(proj, bins, n)
+            f = rast.render_fwd(proj, bins, n, channels=chan is not None)
             rec(3)
             dL = rast.l1_grad(f["image"], target, scale)
             rec(4)
-            ws = rast.render_bwd_tiles(proj, bins, n, f["final_T"], f["n_contrib"], dL)
+            ws = rast.render_bwd_tiles(proj, bins, n, f["final_T"], f["n_contrib"], dL,
+                                       dL_ddepth=None if chan is None else chan[0],
+                                       dL_dalpha=None if chan is None else chan[1])
             rec(5)
             g = rast.project_bwd(sp, proj, bins, ws)
             rec(6)
@@ -162,7 +182,7 @@ def main():
     log(f"[bench] M={M} instances, listed={n_listed}, hit={n_hit}")
 
     # ---------------------------------------------------- batched, graph
-    step = make_step(rast, sp, target, m_cap)
+    step = make_step(rast, sp, target, m_cap, chan=chan)
     for _ in range(max(args.warmup, 1)):
         step()
     torch.cuda.synchronize()
@@ -201,7 +221,7 @@ def main():
     # ------------------------------------- per-stage times (eager, events)
     names = ["project", "bin", "render_fwd", "l1_grad", "render_bwd_tiles", "seg_reduce+project_bwd"]
     evs = [torch.cuda.Event(enable_timing=True) for _ in range(7)]
-    tstep = make_step(rast, sp, target, m_cap, evs)
+    tstep = make_step(rast, sp, target, m_cap, evs, chan=chan)
     tstep()
     torch.cuda.synchronize()
     acc = np.zeros(6)
@@ -217,17 +237,19 @@ def main():
     if not args.no_per_view:
         log("[bench] per-view pipelines")
         rasts, steps = [], []
-        off = 0
+        off = offp = 0
         for v, cam in enumerate(scene.cameras):
             r = Rasterizer([cam], rs, store_tile_ids=False)
             npx = 3 * cam.width * cam.height
             tv = target[off:off + npx]
+            cv = None if chan is None else tuple(c[offp:offp + npx // 3] for c in chan)
             off += npx
+            offp += npx // 3
             fv = r.forward(sp, sync=True)
             mv = int(fv["bins"]["M"])
             del fv
             rasts.append(r)
-            steps.append(make_step(r, sp, tv, mv))
+            steps.append(make_step(r, sp, tv, mv, chan=cv))
 
         def per_view_step():
             total = None
@@ -275,14 +297,15 @@ def main():
                     "batched_speedup_vs_graph": None if pv_graph_ms is None else round(pv_graph_ms / ms, 3)}
 
     # ------------------------------------------------------------ roofline
-    fwd_slots = FWD_LISTED * n_listed + FWD_HIT * n_hit
-    bwd_slots = BWD_LISTED * n_listed + BWD_HIT * n_hit
+    fwd_hit, bwd_hit = (FWD_HIT_CHANNELS, BWD_HIT_CHANNELS) if args.channels else (FWD_HIT, BWD_HIT)
+    fwd_slots = FWD_LISTED * n_listed + fwd_hit * n_hit
+    bwd_slots = BWD_LISTED * n_listed + bwd_hit * n_hit
     kern = {"render_fwd": fwd_slots, "render_bwd_tiles": bwd_slots}
     dom = max(kern, key=lambda kk: stage_ms[kk])
     achieved = kern[dom] / (stage_ms[dom] * 1e-3) / 1e12
     peak = VALU_SLOTS_PER_S / 1e12
     traffic = None
-    if (dom == MEASURED_TRAFFIC["kernel"] and scene.name == MEASURED_TRAFFIC["workload"]
+    if (not args.channels and dom == MEASURED_TRAFFIC["kernel"] and scene.name == MEASURED_TRAFFIC["workload"]
             and kernel_fingerprint() == MEASURED_TRAFFIC["fingerprint"]
             and (rs.tile_w, rs.tile_h, rs.variant, rs.batch or 64) == MEASURED_TRAFFIC["settings"]):
         traffic = MEASURED_TRAFFIC["bytes"]
@@ -293,7 +316,7 @@ def main():
     # ------------------------------------------------------- CPU baseline
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(scene, k, [int(x) for x in args.cpu_sample_views.split(",")], rs)
+        cpu = cpu_baseline(scene, k, [int(x) for x in args.cpu_sample_views.split(",")], rs, args.channels)
 
     out = {
         "metric": METRIC, "value": round(value, 2), "unit": "Mpix/s", "n_gpus": 1, "steps": args.steps,
@@ -302,7 +325,8 @@ def main():
         "config": {"workload": scene.name, "splats": N, "views": V, "pixels": P,
                    "resolutions": [f"{c.width}x{c.height}" for c in scene.cameras], "sh_degree": scene.sh_degree,
                    "tile": f"{rs.tile_w}x{rs.tile_h}", "variant": rs.variant, "batch": rs.batch or 64,
-                   "radix_bits": rs.radix_bits, "graph": not args.no_graph, "instances": M},
+                   "radix_bits": rs.radix_bits, "graph": not args.no_graph, "instances": M,
+                   "channels": bool(args.channels)},
         "fragments": {"listed": n_listed, "hit": n_hit,
                       "listed_per_s": round(n_listed / (ms * 1e-3), 1), "hit_per_s": round(n_hit / (ms * 1e-3), 1)},
         "stages_ms": stage_ms, "eager_ms_per_step": round(eager_ms, 4), "per_view": per_view,
@@ -312,9 +336,11 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline(scene, k, views, rs):
+def cpu_baseline(scene, k, views, rs, channels=False):
     """The FP64 oracle (as it stands) on the same workload restricted to a
-    subset of its views: project, bin, render, L1 gradient, backward."""
+    subset of its views: project, bin, render, L1 gradient, backward (with the
+    depth and alpha channels and seeded upstream gradients for them when
+    `channels`)."""
     import copy
 
     import numpy as np
@@ -328,13 +354,19 @@ def cpu_baseline(scene, k, views, rs):
     tgt = oracle.flat_images([targets[v] for v in views])
     log(f"[bench] cpu baseline: oracle on views {views} ({sub.n_pixels} px) with {oracle.num_threads()} threads")
     t0 = time.perf_counter()
-    fo = oracle.forward(sub, st)
+    fo = oracle.forward(sub, st, channels=channels)
     dL = np.sign(fo["image"] - tgt) / tgt.size
-    oracle.backward(sub, st, fo, dL)
+    if channels:
+        rng = np.random.default_rng([k, 78])
+        oracle.backward(sub, st, fo, dL, dL_ddepth=rng.standard_normal(sub.n_pixels) / (3 * sub.n_pixels),
+                        dL_dalpha=rng.standard_normal(sub.n_pixels) / (3 * sub.n_pixels))
+    else:
+        oracle.backward(sub, st, fo, dL)
     dt = time.perf_counter() - t0
     return {"value": round(sub.n_pixels / dt / 1e6, 4), "unit": "Mpix/s", "cores": oracle.num_threads(),
             "kind": "oracle", "seconds": round(dt, 2),
-            "sample": f"views {views} of the workload ({sub.n_pixels} px, all {scene.n} splats), FP64 fwd+bwd"}
+            "sample": f"views {views} of the workload ({sub.n_pixels} px, all {scene.n} splats), FP64 fwd+bwd"
+                      + (" with the depth and alpha channels" if channels else "")}
 
 
 if __name__ == "__main__":
