@@ -236,6 +236,29 @@ def project_bwd(scene, grad2d, st: Settings) -> dict:
     return g
 
 
+def surface_points(scene, rec, vals, ranges, depth_map, alpha_map, pixels, st: Settings, n_samples: int = 32,
+                   level: float = 0.3, span: float = 3.0, min_alpha: float = 0.5) -> dict:
+    """Level-set surface points along the rays of `pixels` (global pixel ids):
+    points [R, 3], normals [R, 3], valid [R], dominant [R] (pair index of g or
+    -1), t_star [R], margins [R, 3] (see orc_surface_points)."""
+    N, V = scene.n, scene.n_views
+    pixels = np.ascontiguousarray(pixels, dtype=np.int64)
+    R = len(pixels)
+    out = dict(points=np.zeros((max(R, 1), 3)), normals=np.zeros((max(R, 1), 3)), valid=np.zeros(max(R, 1), np.int32),
+               dominant=np.zeros(max(R, 1), np.int64), t_star=np.zeros(max(R, 1)), margins=np.zeros((max(R, 1), 3)))
+    vals = np.ascontiguousarray(vals, np.uint32)
+    if vals.size == 0:
+        vals = np.zeros(1, np.uint32)
+    lib().orc_surface_points(N, V, _p(_f64(scene.means)), _p(_f64(scene.scales)), _p(_f64(scene.quats)),
+                             _p(_f64(scene.opacities)), _p(_f64(scene.betas)), _p(views_array(scene.cameras)),
+                             _p(st.array()), _p(_f64(rec)), _p(vals), _p(np.ascontiguousarray(ranges, np.uint32)),
+                             _p(_f64(depth_map)), _p(_f64(alpha_map)), _p(pixels), ctypes.c_long(R), int(n_samples),
+                             ctypes.c_double(level), ctypes.c_double(span), ctypes.c_double(min_alpha),
+                             _p(out["points"]), _p(out["normals"]), _p(out["valid"]), _p(out["dominant"]),
+                             _p(out["t_star"]), _p(out["margins"]))
+    return {k: v[:R] for k, v in out.items()}
+
+
 def sh_basis(degree: int, dirs) -> np.ndarray:
     dirs = _f64(dirs)
     n = dirs.shape[0]

@@ -866,6 +866,163 @@ int orc_project_bwd(int N, int V, const double* means, const double* scales, con
     return 0;
 }
 
+// Level-set surface points along depth-map rays (Sec. 3.3, mesh extraction).
+// Readings (the paper gives the procedure, not its constants or its choice of
+// the distribution g):
+//   * ray of pixel p of view v: from the camera centre through the pixel
+//     centre, unit direction w; origin x0 = the depth-map point at distance
+//     t0 = (D/A) |d_c| along w (D, A the extended channels, d_c the camera-space
+//     direction with unit z, so t0 w has camera depth D/A); rays with
+//     A < min_alpha carry no surface;
+//   * density (Eq. 9): d(x) = sum_i o_i exp(-kappa m_i(x)^beta_i), m_i the 3-D
+//     Mahalanobis distance under Sigma_i = M_i M_i^T, M_i = R(q_i) diag(phi s_i)
+//     (Eq. 4, 6), over the candidates of the pixel: the splats in its tile's
+//     list whose screen footprint covers it (q <= qmax), since a splat outside
+//     it has density below alpha_min-level on the ray;
+//   * g = the candidate with the largest term o_i exp(-kappa m_i(x0)^beta_i)
+//     (the dominating distribution g* of Eq. 10); sigma_g(w) = |M_g^T w|;
+//   * K samples t_k = t0 + span sigma_g (2k/(K-1) - 1); the first k with
+//     d_k < level <= d_{k+1} brackets the surface closest to the camera; t* by
+//     linear interpolation; the normal is grad f / |grad f| with
+//     f = s sqrt(-2 log d), i.e. -grad d / |grad d| at x0 + t* w.
+// Outputs per ray: points [R][3], normals [R][3], valid [R], dominant [R]
+// (pair index v*N + i of g, -1 if none), t_star [R] and margins [R][3]: the
+// relative gap between the two largest terms at x0, min over the bracketing
+// samples of |d_k - level| / level, and |A - min_alpha| (decision margins).
+static void surface_M(const double* scale, const double* quat, double beta, const Settings& st, double M[9]) {
+    double qn = std::sqrt(quat[0] * quat[0] + quat[1] * quat[1] + quat[2] * quat[2] + quat[3] * quat[3]);
+    double w = quat[0] / qn, x = quat[1] / qn, y = quat[2] / qn, z = quat[3] / qn;
+    double Rq[9] = {1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y),
+                    2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x),
+                    2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)};
+    double phi = 2.0 / (1.0 + std::exp(-st.rho * (beta - 2.0)));
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) M[3 * a + b] = Rq[3 * a + b] * phi * scale[b];
+}
+
+// o exp(-kappa m^beta) at x and (optionally) its gradient with respect to x.
+static double surface_term(const double M[9], const double* mu, double o, double beta, const double x[3],
+                           const Settings& st, double grad[3]) {
+    // m^2 = |M^-1 (x - mu)|^2 with M = R diag(d): M^-1 = diag(1/d) R^T
+    double dx[3] = {x[0] - mu[0], x[1] - mu[1], x[2] - mu[2]};
+    double Minv[9];
+    double det = M[0] * (M[4] * M[8] - M[5] * M[7]) - M[1] * (M[3] * M[8] - M[5] * M[6]) +
+                 M[2] * (M[3] * M[7] - M[4] * M[6]);
+    Minv[0] = (M[4] * M[8] - M[5] * M[7]) / det; Minv[1] = (M[2] * M[7] - M[1] * M[8]) / det;
+    Minv[2] = (M[1] * M[5] - M[2] * M[4]) / det; Minv[3] = (M[5] * M[6] - M[3] * M[8]) / det;
+    Minv[4] = (M[0] * M[8] - M[2] * M[6]) / det; Minv[5] = (M[2] * M[3] - M[0] * M[5]) / det;
+    Minv[6] = (M[3] * M[7] - M[4] * M[6]) / det; Minv[7] = (M[1] * M[6] - M[0] * M[7]) / det;
+    Minv[8] = (M[0] * M[4] - M[1] * M[3]) / det;
+    double y[3];
+    for (int a = 0; a < 3; ++a) y[a] = Minv[3 * a] * dx[0] + Minv[3 * a + 1] * dx[1] + Minv[3 * a + 2] * dx[2];
+    double m2 = y[0] * y[0] + y[1] * y[1] + y[2] * y[2];
+    double P = m2 > 0.0 ? std::pow(m2, 0.5 * beta) : 0.0;
+    double val = o * std::exp(-st.kappa * P);
+    if (grad) {
+        // d/dx exp(-kappa (m^2)^(beta/2)) = -kappa (beta/2) (m^2)^(beta/2 - 1) 2 Minv^T y exp(...)
+        double c = (m2 > 0.0) ? -st.kappa * beta * std::pow(m2, 0.5 * beta - 1.0) * val : 0.0;
+        for (int a = 0; a < 3; ++a) grad[a] = c * (Minv[a] * y[0] + Minv[3 + a] * y[1] + Minv[6 + a] * y[2]);
+    }
+    return val;
+}
+
+int orc_surface_points(int N, int V, const double* means, const double* scales, const double* quats,
+                       const double* opac, const double* betas, const double* views, const double* settings,
+                       const double* rec, const uint32_t* vals, const uint32_t* ranges, const double* depth_map,
+                       const double* alpha_map, const long* pixels, long R, int K, double level, double span,
+                       double min_alpha, double* points, double* normals, int32_t* valid, long* dominant,
+                       double* t_star, double* margins) {
+    Settings st = read_settings(settings);
+    std::vector<View> vw = read_views(views, V, st.tile_w, st.tile_h);
+#pragma omp parallel for schedule(dynamic, 4)
+    for (long r = 0; r < R; ++r) {
+        for (int a = 0; a < 3; ++a) { points[3 * r + a] = 0.0; normals[3 * r + a] = 0.0; margins[3 * r + a] = 0.0; }
+        valid[r] = 0;
+        dominant[r] = -1;
+        t_star[r] = 0.0;
+        long p = pixels[r];
+        int v = 0;
+        while (v + 1 < V && vw[v + 1].pix_base <= p) ++v;
+        const View& w = vw[v];
+        long local = p - w.pix_base;
+        int px = (int)(local % w.W), py = (int)(local / w.W);
+        double A = alpha_map[p], D = depth_map[p];
+        margins[3 * r + 2] = std::fabs(A - min_alpha);
+        if (!(A >= min_alpha) || !(A > 0.0)) continue;
+        // ray: camera-space direction with unit z, to world space by R^T
+        double dc[3] = {(px + 0.5 - w.cx) / w.fx, (py + 0.5 - w.cy) / w.fy, 1.0};
+        double nd = std::sqrt(dc[0] * dc[0] + dc[1] * dc[1] + 1.0);
+        double wd[3];
+        for (int a = 0; a < 3; ++a) wd[a] = (w.R[a] * dc[0] + w.R[3 + a] * dc[1] + w.R[6 + a] * dc[2]) / nd;
+        double t0 = (D / A) * nd;
+        // candidates: the tile's list entries whose screen footprint covers the pixel
+        long t = w.tile_base + (py / st.tile_h) * w.tiles_x + px / st.tile_w;
+        std::vector<long> cand;
+        for (uint32_t k = ranges[2 * t]; k < ranges[2 * t + 1]; ++k) {
+            long idx = vals[k];
+            Rec s = load_rec(rec, idx);
+            Frag f = eval_frag(s, px + 0.5, py + 0.5, st);
+            if (f.q <= s.qmax) cand.push_back(idx);
+        }
+        if (cand.empty()) continue;
+        std::vector<double> Ms(9 * cand.size());
+        for (size_t c = 0; c < cand.size(); ++c) {
+            long i = cand[c] % N;
+            surface_M(scales + 3 * i, quats + 4 * i, betas[i], st, &Ms[9 * c]);
+        }
+        double x0[3] = {w.campos[0] + t0 * wd[0], w.campos[1] + t0 * wd[1], w.campos[2] + t0 * wd[2]};
+        double best = -1.0, second = -1.0;
+        long bc = -1;
+        for (size_t c = 0; c < cand.size(); ++c) {
+            long i = cand[c] % N;
+            double val = surface_term(&Ms[9 * c], means + 3 * i, opac[i], betas[i], x0, st, nullptr);
+            if (val > best) { second = best; best = val; bc = (long)c; }
+            else if (val > second) second = val;
+        }
+        dominant[r] = cand[bc];
+        margins[3 * r] = best > 0.0 ? (best - std::max(second, 0.0)) / best : 0.0;
+        const double* Mg = &Ms[9 * bc];
+        double sg = 0.0;
+        for (int b = 0; b < 3; ++b) {
+            double c = Mg[b] * wd[0] + Mg[3 + b] * wd[1] + Mg[6 + b] * wd[2];  // (M^T w)_b
+            sg += c * c;
+        }
+        sg = std::sqrt(sg);
+        std::vector<double> tk(K), dk(K, 0.0);
+        for (int k = 0; k < K; ++k) {
+            tk[k] = t0 + span * sg * (2.0 * k / (K - 1) - 1.0);
+            double x[3] = {w.campos[0] + tk[k] * wd[0], w.campos[1] + tk[k] * wd[1], w.campos[2] + tk[k] * wd[2]};
+            for (size_t c = 0; c < cand.size(); ++c) {
+                long i = cand[c] % N;
+                dk[k] += surface_term(&Ms[9 * c], means + 3 * i, opac[i], betas[i], x, st, nullptr);
+            }
+        }
+        int kc = -1;
+        for (int k = 0; k + 1 < K; ++k)
+            if (dk[k] < level && dk[k + 1] >= level) { kc = k; break; }
+        if (kc < 0) continue;
+        double mg = std::fabs(dk[kc] - level);
+        mg = std::min(mg, std::fabs(dk[kc + 1] - level));
+        for (int k = 0; k < kc; ++k) mg = std::min(mg, std::fabs(dk[k] - level));
+        margins[3 * r + 1] = mg / level;
+        double ts = tk[kc] + (level - dk[kc]) / (dk[kc + 1] - dk[kc]) * (tk[kc + 1] - tk[kc]);
+        double xs[3] = {w.campos[0] + ts * wd[0], w.campos[1] + ts * wd[1], w.campos[2] + ts * wd[2]};
+        double gd[3] = {0.0, 0.0, 0.0};
+        for (size_t c = 0; c < cand.size(); ++c) {
+            long i = cand[c] % N;
+            double g3[3];
+            surface_term(&Ms[9 * c], means + 3 * i, opac[i], betas[i], xs, st, g3);
+            for (int a = 0; a < 3; ++a) gd[a] += g3[a];
+        }
+        double gn = std::sqrt(gd[0] * gd[0] + gd[1] * gd[1] + gd[2] * gd[2]);
+        if (!(gn > 0.0)) continue;
+        for (int a = 0; a < 3; ++a) { points[3 * r + a] = xs[a]; normals[3 * r + a] = -gd[a] / gn; }
+        t_star[r] = ts;
+        valid[r] = 1;
+    }
+    return 0;
+}
+
 // Real SH basis (for tests): n directions (x, y, z) -> n x (deg+1)^2 values.
 int orc_sh_basis(int degree, long n, const double* dirs, double* out) {
     int K = (degree + 1) * (degree + 1);
