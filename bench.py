@@ -46,6 +46,10 @@ BWD_LISTED, BWD_HIT = 9, 48
 # (2 differences, a multiply and 2 multiply-adds), the dz term and the two
 # behind-accumulator updates (8)
 FWD_HIT_CHANNELS, BWD_HIT_CHANNELS = 19, 56
+# surface points (--surface): per (candidate splat, sample) the affine Mahalanobis
+# vector and its square (6 multiply-adds), log2, scale, exp2, scale, exp2
+# (3 transcendentals x 2 + 2), the opacity and the accumulation: 16 slots
+SURFACE_SLOTS_PER_SAMPLE = 16
 
 # HBM bytes per launch of the tile adjoint on the default workload, from two
 # rocprofv3 counter passes (FETCH_SIZE x2.0, WRITE_SIZE x1.0 after calibration
@@ -79,6 +83,8 @@ def parse_args():
     p.add_argument("--no-autotune", action="store_true",
                    help="keep --tile/--batch instead of the autotuner's choice")
     p.add_argument("--cpu-sample-views", default="0,1,2,3,4,5")
+    p.add_argument("--surface", type=int, default=0,
+                   help="also time level-set surface points for this many covered pixels (32 samples per ray)")
     p.add_argument("--channels", action="store_true",
                    help="extended rasterizer: depth and alpha maps in the forward and seeded synthetic upstream "
                         "gradients for them in the backward (16x16 one-wave renderer; implies --no-autotune)")
@@ -313,6 +319,43 @@ def main():
                 "unit": "Tslot/s", "frac": round(achieved / peak, 4), "traffic": traffic,
                 "algorithmic_slots_per_launch": int(kern[dom])}
 
+    # ------------------------------------------------------ surface points
+    surface = None
+    if args.surface > 0:
+        if (rs.tile_w, rs.tile_h, rs.variant) != (16, 16, 0):
+            log("[bench] --surface needs the 16x16 one-wave renderer; skipped")
+        else:
+            K_S = 32
+            fx = rast.forward(sp, sync=True, channels=True)
+            alpha_h = fx["alpha"].cpu().numpy()
+            cov = np.nonzero(alpha_h >= 0.5)[0]
+            pick = np.random.default_rng([k, 79]).choice(cov, min(args.surface, cov.size), replace=False)
+            pix_t = torch.as_tensor(pick.astype(np.int32), device="cuda")
+            run_s = lambda: rast.surface_points(sp, fx["proj"], fx["bins"], fx["depth"], fx["alpha"], pix_t,  # noqa
+                                                n_samples=K_S)
+            sres = run_s()
+            for _ in range(args.warmup):
+                run_s()
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(args.steps):
+                run_s()
+            e1.record()
+            torch.cuda.synchronize()
+            s_ms = e0.elapsed_time(e1) / args.steps
+            cand = int(sres["n_candidates"].to(torch.int64).sum().item())
+            valid = float(sres["points"][:, 3].mean().item())
+            s_ach = cand * K_S * SURFACE_SLOTS_PER_SAMPLE / (s_ms * 1e-3) / 1e12
+            surface = {"rays": int(pick.size), "samples_per_ray": K_S, "ms": round(s_ms, 4),
+                       "rays_per_s": round(pick.size / (s_ms * 1e-3), 1), "valid_fraction": round(valid, 4),
+                       "candidates_per_ray": round(cand / max(pick.size, 1), 1),
+                       "roofline": {"bound": "alu", "kernel": "surface_points", "achieved": round(s_ach, 3),
+                                    "peak": round(VALU_SLOTS_PER_S / 1e12, 3), "unit": "Tslot/s",
+                                    "frac": round(s_ach / (VALU_SLOTS_PER_S / 1e12), 4),
+                                    "algorithmic_slots_per_launch": cand * K_S * SURFACE_SLOTS_PER_SAMPLE}}
+            log(f"[bench] surface points: {pick.size} rays in {s_ms:.3f} ms, valid {valid:.3f}")
+            del fx
+
     # ------------------------------------------------------- CPU baseline
     cpu = None
     if not args.no_cpu_baseline:
@@ -333,6 +376,8 @@ def main():
         "roofline": roofline, "cpu_baseline": cpu, "wall_s_timed": round(wall, 3),
         "autotune": tune,
     }
+    if surface is not None:
+        out["surface"] = surface
     print(json.dumps(out), flush=True)
 
 

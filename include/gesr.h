@@ -330,6 +330,46 @@ gesr_status gesr_autotune(gesr_ctx* ctx, const gesr_splats* splats, const gesr_c
  * of candidates for k = -1, else 0 on success and -1 when k is out of range. */
 int gesr_autotune_candidate(int k, gesr_settings* out);
 
+/* Level-set surface points (the sampling step of the mesh extraction,
+ * Sec. 3.3).  For each of the R pixels in `pixels` (DEVICE uint32 [R], global
+ * pixel ids of the concatenated views) the ray from the camera centre through
+ * the pixel centre starts at the depth-map point, at camera depth
+ * depth[p] / alpha[p] (DEVICE float [P] each, the extended channels of
+ * gesr_render_fwd_ext; rays with alpha < min_alpha give no point).  The
+ * density of Eq. 9, d(x) = sum_i o_i exp(-kappa m_i(x)^beta_i) with m_i the 3-D
+ * Mahalanobis distance under Sigma_i = M_i M_i^T, M_i = R(q_i) diag(phi s_i),
+ * is summed over the splats of the pixel's tile list whose screen footprint
+ * covers the pixel (q <= qmax); g is the splat with the largest term at the
+ * depth-map point and sigma_g(w) = |M_g^T w| for the ray direction w.
+ * n_samples points spread evenly over +-span sigma_g(w) around it; the first
+ * pair with d_k < level <= d_{k+1} brackets the surface closest to the camera
+ * and the point is placed by linear interpolation; its normal is
+ * -grad d / |grad d| (the direction of grad f for the SDF of Eq. 11).
+ * Outputs (DEVICE float [R][4], 16-byte aligned): points (x, y, z, valid 1/0)
+ * and normals (nx, ny, nz, t* = distance from the camera centre along w);
+ * dominant (DEVICE uint32 [R], nullable): g as view * n + splat, 0xFFFFFFFF
+ * when the ray has no candidate or alpha < min_alpha; n_candidates (DEVICE
+ * uint32 [R], nullable): the number of candidate splats of the ray (0 when
+ * alpha < min_alpha).  workspace: DEVICE, at least GESR_SURFACE_BYTES_PER_SPLAT
+ * * n bytes, 16-byte aligned (per-splat frames, overwritten).  proj and bins are the
+ * same step's (records and tile lists).  Errors: GESR_ERR_INVALID for
+ * n_samples outside 2..GESR_SURFACE_MAX_SAMPLES, level <= 0, span <= 0, NULL
+ * arrays or a misaligned workspace. */
+#define GESR_SURFACE_MAX_SAMPLES 32
+#define GESR_SURFACE_BYTES_PER_SPLAT 64
+typedef struct {
+    int32_t n_samples; /* samples per ray, 2..GESR_SURFACE_MAX_SAMPLES (32) */
+    float level;       /* density level of the surface (0.3) */
+    float span;        /* half-width of the sampled interval in sigma_g(w) (3) */
+    float min_alpha;   /* rays whose alpha map value is below this give no point (0.5) */
+} gesr_surface_settings;
+
+gesr_status gesr_surface_points(gesr_ctx* ctx, const gesr_splats* splats, const gesr_proj* proj,
+                                const gesr_bins* bins, const gesr_camera* cams, int V, const gesr_settings* st,
+                                const gesr_surface_settings* ss, const float* depth, const float* alpha,
+                                const uint32_t* pixels, uint32_t n_rays, float* points, float* normals,
+                                uint32_t* dominant, uint32_t* n_candidates, void* workspace, void* stream);
+
 /* L1 photometric term of Eq. 8 (the (1 - lambda) L1 part):
  * grad[i] = scale * sign(image[i] - target[i]) (sign(0) = 0), DEVICE, count
  * elements. */

@@ -25,7 +25,7 @@ GRAD2D_FLOATS = 12  # du dv dL00 dL10 dL11 dop dbeta dr dg db dz + zero pad
 EXPORTS = (
     "gesr_ctx_create", "gesr_ctx_destroy", "gesr_last_error", "gesr_status_string", "gesr_default_settings",
     "gesr_query_sizes", "gesr_project", "gesr_bin", "gesr_render_fwd", "gesr_render_bwd", "gesr_render_bwd_tiles",
-    "gesr_render_fwd_ext", "gesr_render_bwd_ext", "gesr_render_bwd_tiles_ext",
+    "gesr_render_fwd_ext", "gesr_render_bwd_ext", "gesr_render_bwd_tiles_ext", "gesr_surface_points",
     "gesr_project_bwd", "gesr_l1_grad", "gesr_autotune", "gesr_autotune_candidate",
 )
 
@@ -88,6 +88,15 @@ class BwdChannels(ctypes.Structure):
     _fields_ = [("dL_ddepth", ctypes.c_void_p), ("dL_dalpha", ctypes.c_void_p)]
 
 
+SURFACE_MAX_SAMPLES = 32
+SURFACE_BYTES_PER_SPLAT = 64
+
+
+class SurfaceSettings(ctypes.Structure):
+    _fields_ = [("n_samples", ctypes.c_int32), ("level", ctypes.c_float), ("span", ctypes.c_float),
+                ("min_alpha", ctypes.c_float)]
+
+
 _lib = None
 
 
@@ -142,6 +151,9 @@ def load():
     lib.gesr_project_bwd.argtypes = [vp, P(Splats), P(Proj), P(Bins), P(Camera), ctypes.c_int, P(Settings), vp, vp,
                                      P(Grads), vp]
     lib.gesr_project_bwd.restype = st
+    lib.gesr_surface_points.argtypes = [vp, P(Splats), P(Proj), P(Bins), P(Camera), ctypes.c_int, P(Settings),
+                                        P(SurfaceSettings), vp, vp, vp, ctypes.c_uint32, vp, vp, vp, vp, vp, vp]
+    lib.gesr_surface_points.restype = st
     lib.gesr_l1_grad.argtypes = [vp, vp, vp, ctypes.c_uint64, ctypes.c_float, vp, vp]
     lib.gesr_l1_grad.restype = st
     lib.gesr_autotune.argtypes = [vp, P(Splats), P(Camera), ctypes.c_int, P(Settings), ctypes.c_int, c_float_p,

@@ -675,6 +675,66 @@ gesr_status gesr_render_bwd_ext(gesr_ctx* ctx, const gesr_splats* splats, const 
     return gesr_project_bwd(ctx, splats, proj, bins, cams, V, st, workspace, grad2d, out, stream);
 }
 
+gesr_status gesr_surface_points(gesr_ctx* ctx, const gesr_splats* splats, const gesr_proj* proj,
+                                const gesr_bins* bins, const gesr_camera* cams, int V, const gesr_settings* st,
+                                const gesr_surface_settings* ss, const float* depth, const float* alpha,
+                                const uint32_t* pixels, uint32_t n_rays, float* points, float* normals,
+                                uint32_t* dominant, uint32_t* n_candidates, void* workspace, void* stream) {
+    if (!ctx) return GESR_ERR_INVALID;
+    GESR_TRY(check_settings(ctx, st));
+    GESR_TRY(check_splats(ctx, splats, st->sh_degree, false));
+    Geometry g;
+    GESR_TRY(check_cams(ctx, cams, V, splats->n, st, &g));
+    GESR_TRY(check_proj(ctx, proj));
+    GESR_TRY(check_bins(ctx, bins, false));
+    if (!ss) return fail(ctx, GESR_ERR_INVALID, "surface settings are NULL");
+    if (ss->n_samples < 2 || ss->n_samples > GESR_SURFACE_MAX_SAMPLES)
+        return fail(ctx, GESR_ERR_INVALID, "n_samples %d outside 2..%d", ss->n_samples, GESR_SURFACE_MAX_SAMPLES);
+    if (!(ss->level > 0.f) || !(ss->span > 0.f) || !(ss->min_alpha >= 0.f))
+        return fail(ctx, GESR_ERR_INVALID, "level and span must be > 0, min_alpha >= 0");
+    if (n_rays == 0) {
+        ctx->err.clear();
+        return GESR_OK;
+    }
+    if (!depth || !alpha || !pixels || !points || !normals)
+        return fail(ctx, GESR_ERR_INVALID, "depth/alpha/pixels/points/normals is NULL");
+    if (!aligned16(points) || !aligned16(normals)) return fail(ctx, GESR_ERR_INVALID, "points/normals misaligned");
+    if (splats->n > 0 && (!workspace || !aligned16(workspace)))
+        return fail(ctx, GESR_ERR_INVALID, "workspace is NULL or misaligned");
+    SurfaceArgs a;
+    memset(&a, 0, sizeof a);
+    a.n = splats->n;
+    a.mean = splats->mean;
+    a.scale = splats->scale;
+    a.quat = splats->quat;
+    a.opacity = splats->opacity;
+    a.beta = splats->beta;
+    a.rec = proj->rec;
+    a.val_sorted = bins->val_sorted;
+    a.ranges = bins->ranges;
+    a.depth = depth;
+    a.alpha = alpha;
+    a.pixels = pixels;
+    a.n_rays = n_rays;
+    a.n_samples = ss->n_samples;
+    a.level = ss->level;
+    a.span = ss->span;
+    a.min_alpha = ss->min_alpha;
+    a.tile_w = st->tile_w;
+    a.tile_h = st->tile_h;
+    a.points = points;
+    a.normals = normals;
+    a.dominant = dominant;
+    a.n_candidates = n_candidates;
+    a.frames = (float*)workspace;
+    a.st = dev_settings(st);
+    a.cams = dev_cams(cams, V, st);
+    GESR_TRY(hip_check(ctx, hipSetDevice(ctx->device), "hipSetDevice"));
+    GESR_TRY(hip_check(ctx, launch_surface_points(a, (hipStream_t)stream), "surface_points launch"));
+    ctx->err.clear();
+    return GESR_OK;
+}
+
 gesr_status gesr_l1_grad(gesr_ctx* ctx, const float* image, const float* target, uint64_t count, float scale,
                          float* grad, void* stream) {
     if (!ctx) return GESR_ERR_INVALID;

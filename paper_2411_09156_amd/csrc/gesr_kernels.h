@@ -70,6 +70,30 @@ struct RenderArgs {
     DevCams cams;
 };
 
+// Level-set surface points along depth-map rays (gesr_surface.hip).
+struct SurfaceArgs {
+    int n;
+    const float *mean, *scale, *quat, *opacity, *beta;  // splat parameters, SoA
+    const float* rec;
+    const uint32_t* val_sorted;
+    const uint32_t* ranges;
+    const float* depth;   // [P] extended channels of the forward
+    const float* alpha;   // [P]
+    const uint32_t* pixels;
+    uint32_t n_rays;
+    int n_samples;
+    float level, span, min_alpha;
+    int tile_w, tile_h;
+    float* points;        // [R][4]: x, y, z, valid
+    float* normals;       // [R][4]: nx, ny, nz, t*
+    uint32_t* dominant;   // [R] nullable
+    uint32_t* n_candidates;  // [R] nullable
+    float* frames;        // [n][16] per-splat M^-1, mean, opacity, beta/2 (workspace)
+    DevSettings st;
+    DevCams cams;
+};
+hipError_t launch_surface_points(const SurfaceArgs& a, hipStream_t stream);
+
 hipError_t launch_project(const ProjectArgs& a, int sh_degree, hipStream_t stream);
 hipError_t launch_project_bwd(const ProjectBwdArgs& a, int sh_degree, hipStream_t stream);
 hipError_t launch_seg_reduce(const SegReduceArgs& a, hipStream_t stream);

@@ -278,6 +278,29 @@ class Rasterizer:
             g["grad2d"] = grad2d
         return g
 
+    def surface_points(self, sp: Splats, proj: dict, bins: dict, depth, alpha, pixels, n_samples: int = 32,
+                       level: float = 0.3, span: float = 3.0, min_alpha: float = 0.5) -> dict:
+        """Level-set surface points along the rays of `pixels` (int tensor of
+        global pixel ids) from the extended depth and alpha maps: points [R, 4]
+        (x, y, z, valid), normals [R, 4] (nx, ny, nz, t*), dominant [R],
+        n_candidates [R]."""
+        pix = pixels.to(device=self.device, dtype=torch.int32).contiguous()
+        R = pix.numel()
+        out = dict(points=torch.zeros(max(R, 1), 4, dtype=torch.float32, device=self.device),
+                   normals=torch.zeros(max(R, 1), 4, dtype=torch.float32, device=self.device),
+                   dominant=torch.zeros(max(R, 1), dtype=torch.int32, device=self.device),
+                   n_candidates=torch.zeros(max(R, 1), dtype=torch.int32, device=self.device))
+        ss = _lib.SurfaceSettings(int(n_samples), float(level), float(span), float(min_alpha))
+        ws = torch.empty(max(sp.n, 1) * _lib.SURFACE_BYTES_PER_SPLAT // 4, dtype=torch.float32, device=self.device)
+        self._check(self.lib.gesr_surface_points(self.ctx, ctypes.byref(sp.to_c()), ctypes.byref(self._proj_c(proj)),
+                                                 ctypes.byref(self._bins_c(bins)), self.cams_c, self.V,
+                                                 ctypes.byref(self.st_c), ctypes.byref(ss), depth.data_ptr(),
+                                                 alpha.data_ptr(), pix.data_ptr(), R, out["points"].data_ptr(),
+                                                 out["normals"].data_ptr(), out["dominant"].data_ptr(),
+                                                 out["n_candidates"].data_ptr(), ws.data_ptr(), _stream()),
+                    self.ctx)
+        return {k: v[:R] for k, v in out.items()}
+
     def l1_grad(self, image, target, scale: float):
         grad = torch.empty_like(image)
         self._check(self.lib.gesr_l1_grad(self.ctx, image.data_ptr(), target.data_ptr(), image.numel(),
