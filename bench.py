@@ -330,6 +330,17 @@ def main():
             alpha_h = fx["alpha"].cpu().numpy()
             cov = np.nonzero(alpha_h >= 0.5)[0]
             pick = np.random.default_rng([k, 79]).choice(cov, min(args.surface, cov.size), replace=False)
+            # grouped by tile, so the rays a wave serves share their tile's list
+            cams = scene.cameras
+            widths = np.array([c.width for c in cams])
+            pbase = np.cumsum([0] + [c.width * c.height for c in cams])
+            tx_n = (widths + rs.tile_w - 1) // rs.tile_w
+            tbase = np.cumsum([0] + [int(tx_n[j]) * ((c.height + rs.tile_h - 1) // rs.tile_h)
+                                     for j, c in enumerate(cams)])
+            vv = np.searchsorted(pbase, pick, side="right") - 1
+            loc = pick - pbase[vv]
+            tile = tbase[vv] + (loc // widths[vv]) // rs.tile_h * tx_n[vv] + (loc % widths[vv]) // rs.tile_w
+            pick = pick[np.argsort(tile, kind="stable")]
             pix_t = torch.as_tensor(pick.astype(np.int32), device="cuda")
             run_s = lambda: rast.surface_points(sp, fx["proj"], fx["bins"], fx["depth"], fx["alpha"], pix_t,  # noqa
                                                 n_samples=K_S)

@@ -12,7 +12,7 @@
 // linear interpolation, and the normal is -grad d / |grad d| (the direction of
 // grad f for the SDF of Eq. 11).
 //
-// One wave per ray; lanes stride over the tile list.  Along the ray each
+// Sixteen lanes per ray (four rays per wave) stride over the tile list.  Along the ray each
 // candidate's Mahalanobis vector is affine in the ray parameter, y(s) = a + s b
 // (a = M^-1 (x0 - mu), b = M^-1 w, s = t - t0), so a sample costs two
 // multiply-adds plus the falloff.  Each lane keeps its partial density of every
@@ -116,62 +116,78 @@ __device__ __forceinline__ float affine_term(const Affine& f, float s, const Dev
 }
 
 // Calls body(frame, list position) for every candidate of pixel (px, py)
-// among the lane's list entries rg.x + lane, + 64, ...: the splats whose screen
-// footprint covers the pixel (q <= qmax, the renderers' test).  The next
-// entry's splat id is loaded while the current entry is processed.
-template <class F>
-__device__ __forceinline__ void for_candidates(const SurfaceArgs& A, uint2 rg, uint32_t lane, float px, float py,
+// among the list entries rg.x + u, + S, + 2S, ... (u: the lane's place among
+// the S lanes of its ray): the splats whose screen footprint covers the pixel
+// (q <= qmax, the renderers' test).  The next entry's splat id is loaded while
+// the current entry is processed.
+template <int S, class F>
+__device__ __forceinline__ void for_candidates(const SurfaceArgs& A, uint2 rg, uint32_t u, float px, float py,
                                                F&& body) {
-    uint32_t k = rg.x + lane;
+    uint32_t k = rg.x + u;
     uint32_t vi = k < rg.y ? A.val_sorted[k] : 0u;
-    for (; k < rg.y; k += 64) {
+    for (; k < rg.y; k += S) {
         const float4* r = reinterpret_cast<const float4*>(A.rec + (size_t)vi * GESR_REC_FLOATS);
         const float4 ra = r[0], rb = r[1];
         Frame fr;
         load_frame(A.frames, vi % (uint32_t)A.n, fr);
-        const uint32_t kn = k + 64;
+        const uint32_t kn = k + S;
         vi = kn < rg.y ? A.val_sorted[kn] : 0u;
         Fragment f;
         if (ges_q(ra, rb.x, px, py, f) <= rb.w) body(fr, k);
     }
 }
 
+// Sum over the 16 lanes of a ray's group (xor steps stay inside the group).
+__device__ __forceinline__ float group16_sum(float x) {
+#pragma unroll
+    for (int m = 8; m >= 1; m >>= 1) x += __shfl_xor(x, m, 64);
+    return x;
+}
+
+// Four rays per wave, sixteen lanes each.  Rays of the same tile (the caller
+// passes pixels grouped by tile) traverse the same list in lockstep, so the
+// four lanes that load one entry hit the same addresses; rays of different
+// tiles are simply handled side by side.
+constexpr int kRaysPerWave = 4, kLanesPerRay = 64 / kRaysPerWave;
+
 __global__ __launch_bounds__(64) void k_surface_points(SurfaceArgs A) {
     __shared__ float sPart[64][kMaxSamples + 1];
-    const uint32_t ray = blockIdx.x, lane = __lane_id();
+    __shared__ float sDen[kRaysPerWave][kMaxSamples];
+    const uint32_t lane = __lane_id(), slot = lane / kLanesPerRay, u = lane % kLanesPerRay;
+    const uint32_t ray = blockIdx.x * kRaysPerWave + slot;
+    const bool has_ray = ray < A.n_rays;
     const DevSettings& st = A.st;
-    float4* out_p = reinterpret_cast<float4*>(A.points) + ray;
-    float4* out_n = reinterpret_cast<float4*>(A.normals) + ray;
-    const uint32_t pix = A.pixels[ray];
+    const DevView* views = A.cams.v;
+    const uint32_t pix = has_ray ? A.pixels[ray] : 0u;
     int v = 0;
-    while (v + 1 < A.cams.V && A.cams.v[v + 1].pix_base <= pix) ++v;
-    const DevView& w = A.cams.v[v];
+    while (v + 1 < A.cams.V && views[v + 1].pix_base <= pix) ++v;
+    const DevView& w = views[v];
     const uint32_t local = pix - w.pix_base;
     const int px = (int)(local % (uint32_t)w.W), py = (int)(local / (uint32_t)w.W);
-    const float alpha = A.alpha[pix], depth = A.depth[pix];
-    if (lane == 0 && A.dominant) A.dominant[ray] = 0xFFFFFFFFu;
-    if (lane == 0 && A.n_candidates) A.n_candidates[ray] = 0u;
-    if (lane == 0) {
-        *out_p = make_float4(0.f, 0.f, 0.f, 0.f);
-        *out_n = make_float4(0.f, 0.f, 0.f, 0.f);
+    const float alpha = has_ray ? A.alpha[pix] : 0.f, depth = has_ray ? A.depth[pix] : 0.f;
+    if (has_ray && u == 0) {
+        reinterpret_cast<float4*>(A.points)[ray] = make_float4(0.f, 0.f, 0.f, 0.f);
+        reinterpret_cast<float4*>(A.normals)[ray] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (A.dominant) A.dominant[ray] = 0xFFFFFFFFu;
+        if (A.n_candidates) A.n_candidates[ray] = 0u;
     }
-    if (!(alpha >= A.min_alpha) || !(alpha > 0.f)) return;
+    bool live = has_ray && alpha >= A.min_alpha && alpha > 0.f;
     // ray: camera-space direction with unit z, rotated to world space by R^T
     const float dc[3] = {((float)px + 0.5f - w.cx) / w.fx, ((float)py + 0.5f - w.cy) / w.fy, 1.0f};
     const float nd = sqrtf(dc[0] * dc[0] + dc[1] * dc[1] + 1.0f);
     float wd[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) wd[a] = (w.R[a] * dc[0] + w.R[3 + a] * dc[1] + w.R[6 + a] * dc[2]) / nd;
-    const float t0 = depth / alpha * nd;
+    const float t0 = live ? depth / alpha * nd : 0.f;
     const float x0[3] = {w.campos[0] + t0 * wd[0], w.campos[1] + t0 * wd[1], w.campos[2] + t0 * wd[2]};
     const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
     const uint32_t t = w.tile_base + (uint32_t)(py / A.tile_h) * (uint32_t)w.tiles_x + (uint32_t)(px / A.tile_w);
-    const uint2 rg = reinterpret_cast<const uint2*>(A.ranges)[t];
+    uint2 rg = live ? reinterpret_cast<const uint2*>(A.ranges)[t] : make_uint2(0u, 0u);
 
     // pass 1: the dominating splat at x0 (largest term; ties to the earliest list position)
     float best = -1.0f;
     uint32_t best_pos = 0xFFFFFFFFu, ncand = 0;
-    for_candidates(A, rg, lane, fpx, fpy, [&](const Frame& fr, uint32_t k) {
+    for_candidates<kLanesPerRay>(A, rg, u, fpx, fpy, [&](const Frame& fr, uint32_t k) {
         ++ncand;
         Affine f;
         frame_affine(fr, x0, wd, f);
@@ -182,7 +198,7 @@ __global__ __launch_bounds__(64) void k_surface_points(SurfaceArgs A) {
         }
     });
 #pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) {
+    for (int m = kLanesPerRay / 2; m >= 1; m >>= 1) {
         const float ob = __shfl_xor(best, m, 64);
         const uint32_t op = (uint32_t)__shfl_xor((int)best_pos, m, 64);
         if (ob > best || (ob == best && op < best_pos)) {
@@ -190,16 +206,14 @@ __global__ __launch_bounds__(64) void k_surface_points(SurfaceArgs A) {
             best_pos = op;
         }
     }
-    if (A.n_candidates) {
-        const uint32_t tot = (uint32_t)wave_sum((float)ncand);  // exact below 2^24
-        if (lane == 0) A.n_candidates[ray] = tot;
-    }
-    if (best_pos == 0xFFFFFFFFu) return;  // no candidate
-    const uint32_t g_vi = A.val_sorted[best_pos];
-    if (lane == 0 && A.dominant) A.dominant[ray] = g_vi;
+    const uint32_t tot = (uint32_t)group16_sum((float)ncand);  // exact below 2^24
+    if (live && u == 0 && A.n_candidates) A.n_candidates[ray] = tot;
+    live = live && best_pos != 0xFFFFFFFFu;
+    const uint32_t g_vi = live ? A.val_sorted[best_pos] : 0u;
+    if (live && u == 0 && A.dominant) A.dominant[ray] = g_vi;
     // sigma_g(w) = |M_g^T w| = |diag(ps) R^T w|
-    float sg;
-    {
+    float sg = 0.f;
+    if (live) {
         float R[9], ps[3];
         splat_frame(A, g_vi % (uint32_t)A.n, R, ps);
         float acc = 0.f;
@@ -210,6 +224,7 @@ __global__ __launch_bounds__(64) void k_surface_points(SurfaceArgs A) {
         }
         sg = sqrtf(acc);
     }
+    if (!live) rg = make_uint2(0u, 0u);
     const int K = A.n_samples;
     const float step = 2.0f * A.span * sg / (float)(K - 1), s0 = -A.span * sg;
 
@@ -217,7 +232,7 @@ __global__ __launch_bounds__(64) void k_surface_points(SurfaceArgs A) {
     float part[kMaxSamples];
 #pragma unroll
     for (int k = 0; k < kMaxSamples; ++k) part[k] = 0.f;
-    for_candidates(A, rg, lane, fpx, fpy, [&](const Frame& fr, uint32_t) {
+    for_candidates<kLanesPerRay>(A, rg, u, fpx, fpy, [&](const Frame& fr, uint32_t) {
         Affine f;
         frame_affine(fr, x0, wd, f);
 #pragma unroll
@@ -227,22 +242,32 @@ __global__ __launch_bounds__(64) void k_surface_points(SurfaceArgs A) {
 #pragma unroll
     for (int j = 0; j < kMaxSamples; ++j) sPart[lane][j] = part[j];
     __syncthreads();
-    float dk = 0.f;  // lane j: density of sample j, summed in lane order
-    if ((int)lane < K)
-        for (int l = 0; l < 64; ++l) dk += sPart[l][lane];
-    const float dk1 = __shfl_down(dk, 1, 64);
-    const bool cross = (int)lane + 1 < K && dk < A.level && dk1 >= A.level;
-    const uint64_t cm = __ballot(cross);
-    if (cm == 0ull) return;
-    const int kc = __builtin_ctzll(cm);
-    const float d0 = __shfl(dk, kc, 64), d1 = __shfl(dk, kc + 1, 64);
-    const float sa = fmaf((float)kc, step, s0);
-    const float ss = sa + (A.level - d0) / (d1 - d0) * step;
+    // densities: sample j of the ray summed over its 16 lanes in lane order
+    for (int j = (int)u; j < K; j += kLanesPerRay) {
+        float d = 0.f;
+        for (int l = 0; l < kLanesPerRay; ++l) d += sPart[slot * kLanesPerRay + l][j];
+        sDen[slot][j] = d;
+    }
+    __syncthreads();
+    int kc = -1;
+    if (live)
+        for (int k = 0; k + 1 < K; ++k)
+            if (sDen[slot][k] < A.level && sDen[slot][k + 1] >= A.level) {
+                kc = k;
+                break;
+            }
+    live = live && kc >= 0;
+    float ss = 0.f;
+    if (live) {
+        const float d0 = sDen[slot][kc], d1 = sDen[slot][kc + 1];
+        ss = fmaf((float)kc, step, s0) + (A.level - d0) / (d1 - d0) * step;
+    }
+    if (!live) rg = make_uint2(0u, 0u);
 
     // pass 3: density gradient at x0 + ss w
     float gd[3] = {0.f, 0.f, 0.f};
     const float xs[3] = {x0[0] + ss * wd[0], x0[1] + ss * wd[1], x0[2] + ss * wd[2]};
-    for_candidates(A, rg, lane, fpx, fpy, [&](const Frame& fr, uint32_t) {
+    for_candidates<kLanesPerRay>(A, rg, u, fpx, fpy, [&](const Frame& fr, uint32_t) {
         const float d[3] = {xs[0] - fr.mu[0], xs[1] - fr.mu[1], xs[2] - fr.mu[2]};
         float y[3], m2 = 0.f;
 #pragma unroll
@@ -261,13 +286,11 @@ __global__ __launch_bounds__(64) void k_surface_points(SurfaceArgs A) {
             gd[a] = fmaf(coef, fr.m[a] * y[0] + fr.m[3 + a] * y[1] + fr.m[6 + a] * y[2], gd[a]);
     });
 #pragma unroll
-    for (int a = 0; a < 3; ++a) gd[a] = wave_sum(gd[a]);
+    for (int a = 0; a < 3; ++a) gd[a] = group16_sum(gd[a]);
     const float gn = sqrtf(gd[0] * gd[0] + gd[1] * gd[1] + gd[2] * gd[2]);
-    if (!(gn > 0.f)) return;
-    if (lane == 0) {
-        const float ts = t0 + ss;
-        *out_p = make_float4(x0[0] + ss * wd[0], x0[1] + ss * wd[1], x0[2] + ss * wd[2], 1.0f);
-        *out_n = make_float4(-gd[0] / gn, -gd[1] / gn, -gd[2] / gn, ts);
+    if (live && gn > 0.f && u == 0) {
+        reinterpret_cast<float4*>(A.points)[ray] = make_float4(xs[0], xs[1], xs[2], 1.0f);
+        reinterpret_cast<float4*>(A.normals)[ray] = make_float4(-gd[0] / gn, -gd[1] / gn, -gd[2] / gn, t0 + ss);
     }
 }
 
@@ -277,7 +300,8 @@ hipError_t launch_surface_points(const SurfaceArgs& a, hipStream_t stream) {
     if (a.n_rays == 0) return hipSuccess;
     if (a.n_samples < 2 || a.n_samples > kMaxSamples) return hipErrorInvalidValue;
     if (a.n > 0) hipLaunchKernelGGL(k_surface_frames, dim3((a.n + 255) / 256), dim3(256), 0, stream, a);
-    hipLaunchKernelGGL(k_surface_points, dim3(a.n_rays), dim3(64), 0, stream, a);
+    hipLaunchKernelGGL(k_surface_points, dim3((a.n_rays + kRaysPerWave - 1) / kRaysPerWave), dim3(64), 0, stream,
+                       a);
     return hipGetLastError();
 }
 
