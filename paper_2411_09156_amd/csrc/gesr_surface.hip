@@ -12,7 +12,7 @@
 // linear interpolation, and the normal is -grad d / |grad d| (the direction of
 // grad f for the SDF of Eq. 11).
 //
-// Sixteen lanes per ray (four rays per wave) stride over the tile list.  Along the ray each
+// Eight lanes per ray (eight rays per wave) stride over the tile list.  Along the ray each
 // candidate's Mahalanobis vector is affine in the ray parameter, y(s) = a + s b
 // (a = M^-1 (x0 - mu), b = M^-1 w, s = t - t0), so a sample costs two
 // multiply-adds plus the falloff.  Each lane keeps its partial density of every
@@ -137,18 +137,19 @@ __device__ __forceinline__ void for_candidates(const SurfaceArgs& A, uint2 rg, u
     }
 }
 
-// Sum over the 16 lanes of a ray's group (xor steps stay inside the group).
-__device__ __forceinline__ float group16_sum(float x) {
+// Sum over the L lanes of a ray's group (xor steps stay inside the group).
+template <int L>
+__device__ __forceinline__ float lane_group_sum(float x) {
 #pragma unroll
-    for (int m = 8; m >= 1; m >>= 1) x += __shfl_xor(x, m, 64);
+    for (int m = L / 2; m >= 1; m >>= 1) x += __shfl_xor(x, m, 64);
     return x;
 }
 
-// Four rays per wave, sixteen lanes each.  Rays of the same tile (the caller
+// Eight rays per wave, eight lanes each.  Rays of the same tile (the caller
 // passes pixels grouped by tile) traverse the same list in lockstep, so the
-// four lanes that load one entry hit the same addresses; rays of different
-// tiles are simply handled side by side.
-constexpr int kRaysPerWave = 4, kLanesPerRay = 64 / kRaysPerWave;
+// lanes that load one entry for different rays hit the same addresses; rays of
+// different tiles are simply handled side by side.
+constexpr int kRaysPerWave = 8, kLanesPerRay = 64 / kRaysPerWave;
 
 __global__ __launch_bounds__(64) void k_surface_points(SurfaceArgs A) {
     __shared__ float sPart[64][kMaxSamples + 1];
@@ -206,7 +207,7 @@ __global__ __launch_bounds__(64) void k_surface_points(SurfaceArgs A) {
             best_pos = op;
         }
     }
-    const uint32_t tot = (uint32_t)group16_sum((float)ncand);  // exact below 2^24
+    const uint32_t tot = (uint32_t)lane_group_sum<kLanesPerRay>((float)ncand);  // exact below 2^24
     if (live && u == 0 && A.n_candidates) A.n_candidates[ray] = tot;
     live = live && best_pos != 0xFFFFFFFFu;
     const uint32_t g_vi = live ? A.val_sorted[best_pos] : 0u;
@@ -242,7 +243,7 @@ __global__ __launch_bounds__(64) void k_surface_points(SurfaceArgs A) {
 #pragma unroll
     for (int j = 0; j < kMaxSamples; ++j) sPart[lane][j] = part[j];
     __syncthreads();
-    // densities: sample j of the ray summed over its 16 lanes in lane order
+    // densities: sample j of the ray summed over its lanes in lane order
     for (int j = (int)u; j < K; j += kLanesPerRay) {
         float d = 0.f;
         for (int l = 0; l < kLanesPerRay; ++l) d += sPart[slot * kLanesPerRay + l][j];
@@ -286,7 +287,7 @@ __global__ __launch_bounds__(64) void k_surface_points(SurfaceArgs A) {
             gd[a] = fmaf(coef, fr.m[a] * y[0] + fr.m[3 + a] * y[1] + fr.m[6 + a] * y[2], gd[a]);
     });
 #pragma unroll
-    for (int a = 0; a < 3; ++a) gd[a] = group16_sum(gd[a]);
+    for (int a = 0; a < 3; ++a) gd[a] = lane_group_sum<kLanesPerRay>(gd[a]);
     const float gn = sqrtf(gd[0] * gd[0] + gd[1] * gd[1] + gd[2] * gd[2]);
     if (live && gn > 0.f && u == 0) {
         reinterpret_cast<float4*>(A.points)[ray] = make_float4(xs[0], xs[1], xs[2], 1.0f);
