@@ -275,6 +275,70 @@ def num_threads() -> int:
     return int(lib().orc_num_threads())
 
 
+# ---------------------------------------------------------------- optimiser
+@dataclass
+class AdamSettings:
+    """Per-group learning rates (3DGS practice, which Sec. 4.2 defers to, and
+    the paper's 1.5e-3 for the shape parameter), Adam's constants and the
+    weight of the opacity-entropy term (Sec. 4.2: binary opacities)."""
+    lr_mean: float = 1.6e-4
+    lr_scale: float = 5e-3
+    lr_quat: float = 1e-3
+    lr_opacity: float = 0.05
+    lr_beta: float = 1.5e-3
+    lr_sh_dc: float = 2.5e-3
+    lr_sh_rest: float = 2.5e-3 / 20
+    beta1: float = 0.9
+    beta2: float = 0.999
+    eps: float = 1e-15
+    entropy_weight: float = 0.0
+
+
+RAW_KEYS = ("means", "log_scales", "quats", "opacity_logits", "betas", "sh")
+
+
+def adam_raw_grads(raw: dict, grads: dict, st: AdamSettings) -> dict:
+    """Gradients of the optimised (raw) parameters from those of the activated
+    ones: scale = exp(log_scale), opacity = sigmoid(logit), plus the opacity
+    entropy term entropy_weight * mean_i H(o_i), H(o) = -o ln o - (1-o) ln(1-o),
+    whose derivative in the logit is -logit o (1 - o)."""
+    s = np.exp(np.asarray(raw["log_scales"], np.float64))
+    lg = np.asarray(raw["opacity_logits"], np.float64)
+    o = 1.0 / (1.0 + np.exp(-lg))
+    n = max(len(lg), 1)
+    g = {"means": np.asarray(grads["means"], np.float64), "quats": np.asarray(grads["quats"], np.float64),
+         "betas": np.asarray(grads["betas"], np.float64), "sh": np.asarray(grads["sh"], np.float64)}
+    g["log_scales"] = np.asarray(grads["scales"], np.float64) * s
+    g["opacity_logits"] = (np.asarray(grads["opacities"], np.float64) * o * (1 - o)
+                           + st.entropy_weight / n * (-lg) * o * (1 - o))
+    return g
+
+
+def adam_step(raw: dict, m: dict, v: dict, grads: dict, step: int, st: AdamSettings):
+    """One Adam step (bias-corrected, step >= 1) of every raw parameter group
+    with its learning rate; returns (raw, m, v, activated) with activated =
+    dict(scales=exp(log_scales), opacities=sigmoid(logits))."""
+    g = adam_raw_grads(raw, grads, st)
+    lrs = {"means": st.lr_mean, "log_scales": st.lr_scale, "quats": st.lr_quat, "opacity_logits": st.lr_opacity,
+           "betas": st.lr_beta}
+    c1 = 1.0 - st.beta1 ** step
+    c2 = 1.0 - st.beta2 ** step
+    out_p, out_m, out_v = {}, {}, {}
+    for k in RAW_KEYS:
+        p = np.asarray(raw[k], np.float64)
+        mk = st.beta1 * np.asarray(m[k], np.float64) + (1 - st.beta1) * g[k]
+        vk = st.beta2 * np.asarray(v[k], np.float64) + (1 - st.beta2) * g[k] ** 2
+        if k == "sh":
+            lr = np.full(p.shape, st.lr_sh_rest)
+            lr[:, 0, :] = st.lr_sh_dc
+        else:
+            lr = lrs[k]
+        out_p[k] = p - lr * (mk / c1) / (np.sqrt(vk / c2) + st.eps)
+        out_m[k], out_v[k] = mk, vk
+    act = {"scales": np.exp(out_p["log_scales"]), "opacities": 1.0 / (1.0 + np.exp(-out_p["opacity_logits"]))}
+    return out_p, out_m, out_v, act
+
+
 # ------------------------------------------------------------------ pipeline
 def forward(scene, st: Settings, channels: bool = False) -> dict:
     """Full FP64 pipeline: project -> bin -> tiled render (with the extended
