@@ -376,6 +376,58 @@ gesr_status gesr_surface_points(gesr_ctx* ctx, const gesr_splats* splats, const 
 gesr_status gesr_l1_grad(gesr_ctx* ctx, const float* image, const float* target, uint64_t count, float scale,
                          float* grad, void* stream);
 
+/* Optimised (raw) splat parameters, DEVICE float32, structure-of-arrays with
+ * the layouts of gesr_splats: mean[3][n], log_scale[3][n] (scale =
+ * exp(log_scale)), quat[4][n], opacity_logit[n] (opacity = sigmoid(logit)),
+ * beta[n], sh[sh_coeffs * 3][n].  The same struct holds Adam's first and
+ * second moments. */
+typedef struct {
+    int32_t n;
+    int32_t sh_coeffs; /* K = (sh_degree + 1)^2, 1..16 */
+    float* mean;
+    float* log_scale;
+    float* quat;
+    float* opacity_logit;
+    float* beta;
+    float* sh;
+} gesr_params;
+
+/* Adam with one learning rate per parameter group (the training schedule of
+ * Sec. 4.2: 1.5e-3 for the shape parameter beta; the others follow 3DGS
+ * practice) and the opacity-entropy term of Sec. 4.2 (binary opacities).
+ * gesr_default_adam_settings() fills lr_mean 1.6e-4, lr_scale 5e-3, lr_quat
+ * 1e-3, lr_opacity 0.05, lr_beta 1.5e-3, lr_sh_dc 2.5e-3, lr_sh_rest
+ * 1.25e-4, beta1 0.9, beta2 0.999, eps 1e-15, entropy_weight 0, step 1. */
+typedef struct {
+    float lr_mean, lr_scale, lr_quat, lr_opacity, lr_beta, lr_sh_dc, lr_sh_rest;
+    float beta1, beta2, eps;
+    float entropy_weight; /* weight w of w * mean_i H(opacity_i), H the binary entropy */
+    int32_t step;         /* 1-based step number t of the bias corrections 1 - beta^t */
+    int32_t reserved[4];
+} gesr_adam_settings;
+
+void gesr_default_adam_settings(gesr_adam_settings* s);
+
+/* One fused Adam step of every raw parameter, in place, from the gradients of
+ * the activated parameters that gesr_render_bwd writes (`grads`, layouts of
+ * gesr_splats):
+ *   g_log_scale = g_scale * exp(log_scale),
+ *   g_logit = (g_opacity + (w / n) * (-logit)) * o (1 - o),  o = sigmoid(logit)
+ *     (the second term is the derivative of w * mean_i H(o_i)),
+ *   m = beta1 m + (1 - beta1) g,  v = beta2 v + (1 - beta2) g^2,
+ *   p -= lr * (m / (1 - beta1^t)) / (sqrt(v / (1 - beta2^t)) + eps),
+ * with lr by group (SH coefficient 0 uses lr_sh_dc, the rest lr_sh_rest).
+ * Also writes the activated parameters of the updated values for the next
+ * forward: scale_out[3][n] = exp(log_scale), opacity_out[n] = sigmoid(logit)
+ * (DEVICE, caller-owned; these may be the gesr_splats arrays the renderer
+ * reads).  `p`, `m`, `v` must have equal n and sh_coeffs and no aliasing.
+ * Errors: GESR_ERR_INVALID for NULL or misaligned (16-byte) arrays, mismatched
+ * sizes, step < 1, non-finite or negative learning rates, beta1/beta2 outside
+ * [0, 1), eps <= 0; nothing is enqueued then. */
+gesr_status gesr_adam_step(gesr_ctx* ctx, const gesr_params* p, const gesr_params* m, const gesr_params* v,
+                           const gesr_grads* grads, const gesr_adam_settings* st, float* scale_out,
+                           float* opacity_out, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

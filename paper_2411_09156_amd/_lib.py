@@ -26,7 +26,8 @@ EXPORTS = (
     "gesr_ctx_create", "gesr_ctx_destroy", "gesr_last_error", "gesr_status_string", "gesr_default_settings",
     "gesr_query_sizes", "gesr_project", "gesr_bin", "gesr_render_fwd", "gesr_render_bwd", "gesr_render_bwd_tiles",
     "gesr_render_fwd_ext", "gesr_render_bwd_ext", "gesr_render_bwd_tiles_ext", "gesr_surface_points",
-    "gesr_project_bwd", "gesr_l1_grad", "gesr_autotune", "gesr_autotune_candidate",
+    "gesr_project_bwd", "gesr_l1_grad", "gesr_autotune", "gesr_autotune_candidate", "gesr_default_adam_settings",
+    "gesr_adam_step",
 )
 
 c_float_p = ctypes.POINTER(ctypes.c_float)
@@ -97,6 +98,20 @@ class SurfaceSettings(ctypes.Structure):
                 ("min_alpha", ctypes.c_float)]
 
 
+class Params(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("sh_coeffs", ctypes.c_int32), ("mean", ctypes.c_void_p),
+                ("log_scale", ctypes.c_void_p), ("quat", ctypes.c_void_p), ("opacity_logit", ctypes.c_void_p),
+                ("beta", ctypes.c_void_p), ("sh", ctypes.c_void_p)]
+
+
+class AdamSettings(ctypes.Structure):
+    _fields_ = [("lr_mean", ctypes.c_float), ("lr_scale", ctypes.c_float), ("lr_quat", ctypes.c_float),
+                ("lr_opacity", ctypes.c_float), ("lr_beta", ctypes.c_float), ("lr_sh_dc", ctypes.c_float),
+                ("lr_sh_rest", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
+                ("eps", ctypes.c_float), ("entropy_weight", ctypes.c_float), ("step", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
+
+
 _lib = None
 
 
@@ -161,6 +176,10 @@ def load():
     lib.gesr_autotune.restype = st
     lib.gesr_autotune_candidate.argtypes = [ctypes.c_int, P(Settings)]
     lib.gesr_autotune_candidate.restype = ctypes.c_int
+    lib.gesr_default_adam_settings.argtypes = [P(AdamSettings)]
+    lib.gesr_default_adam_settings.restype = None
+    lib.gesr_adam_step.argtypes = [vp, P(Params), P(Params), P(Params), P(Grads), P(AdamSettings), vp, vp, vp]
+    lib.gesr_adam_step.restype = st
     _lib = lib
     return lib
 

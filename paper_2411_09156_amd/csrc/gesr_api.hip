@@ -746,6 +746,90 @@ gesr_status gesr_l1_grad(gesr_ctx* ctx, const float* image, const float* target,
     return GESR_OK;
 }
 
+void gesr_default_adam_settings(gesr_adam_settings* s) {
+    if (!s) return;
+    memset(s, 0, sizeof *s);
+    s->lr_mean = 1.6e-4f;
+    s->lr_scale = 5e-3f;
+    s->lr_quat = 1e-3f;
+    s->lr_opacity = 0.05f;
+    s->lr_beta = 1.5e-3f;
+    s->lr_sh_dc = 2.5e-3f;
+    s->lr_sh_rest = 2.5e-3f / 20.0f;
+    s->beta1 = 0.9f;
+    s->beta2 = 0.999f;
+    s->eps = 1e-15f;
+    s->entropy_weight = 0.0f;
+    s->step = 1;
+}
+
+gesr_status gesr_adam_step(gesr_ctx* ctx, const gesr_params* p, const gesr_params* m, const gesr_params* v,
+                           const gesr_grads* grads, const gesr_adam_settings* st, float* scale_out,
+                           float* opacity_out, void* stream) {
+    if (!ctx) return GESR_ERR_INVALID;
+    if (!p || !m || !v || !grads || !st) return fail(ctx, GESR_ERR_INVALID, "NULL argument");
+    if (p->n < 0) return fail(ctx, GESR_ERR_INVALID, "params->n is negative");
+    if (p->sh_coeffs < 1 || p->sh_coeffs > 16) return fail(ctx, GESR_ERR_INVALID, "sh_coeffs %d outside 1..16",
+                                                           p->sh_coeffs);
+    if (m->n != p->n || v->n != p->n || m->sh_coeffs != p->sh_coeffs || v->sh_coeffs != p->sh_coeffs)
+        return fail(ctx, GESR_ERR_INVALID, "params and moments differ in n or sh_coeffs");
+    if (st->step < 1) return fail(ctx, GESR_ERR_INVALID, "step must be >= 1");
+    const float lrs[7] = {st->lr_mean, st->lr_scale, st->lr_quat, st->lr_opacity, st->lr_beta, st->lr_sh_dc,
+                          st->lr_sh_rest};
+    for (float lr : lrs)
+        if (!(lr >= 0.f) || !isfinite(lr)) return fail(ctx, GESR_ERR_INVALID, "learning rates must be finite and >= 0");
+    if (!(st->beta1 >= 0.f && st->beta1 < 1.f) || !(st->beta2 >= 0.f && st->beta2 < 1.f))
+        return fail(ctx, GESR_ERR_INVALID, "beta1 and beta2 must be in [0, 1)");
+    if (!(st->eps > 0.f) || !isfinite(st->eps)) return fail(ctx, GESR_ERR_INVALID, "eps must be finite and > 0");
+    if (!isfinite(st->entropy_weight)) return fail(ctx, GESR_ERR_INVALID, "entropy_weight must be finite");
+    const int n = p->n;
+    if (n > 0) {
+        const gesr_params* sets[3] = {p, m, v};
+        for (const gesr_params* q : sets) {
+            const void* ptrs[6] = {q->mean, q->log_scale, q->quat, q->opacity_logit, q->beta, q->sh};
+            for (const void* ptr : ptrs)
+                if (!ptr || !aligned16(ptr))
+                    return fail(ctx, GESR_ERR_INVALID, "parameter or moment array NULL or not 16-byte aligned");
+        }
+        const void* gp[8] = {grads->mean, grads->scale, grads->quat, grads->opacity, grads->beta, grads->sh,
+                             scale_out, opacity_out};
+        for (const void* ptr : gp)
+            if (!ptr || !aligned16(ptr))
+                return fail(ctx, GESR_ERR_INVALID, "gradient or output array NULL or not 16-byte aligned");
+    }
+    AdamArgs a{};
+    a.n = n;
+    a.p = *p;
+    a.m = *m;
+    a.v = *v;
+    a.g_mean = grads->mean;
+    a.g_scale = grads->scale;
+    a.g_quat = grads->quat;
+    a.g_opacity = grads->opacity;
+    a.g_beta = grads->beta;
+    a.g_sh = grads->sh;
+    a.lr_mean = st->lr_mean;
+    a.lr_scale = st->lr_scale;
+    a.lr_quat = st->lr_quat;
+    a.lr_opacity = st->lr_opacity;
+    a.lr_beta = st->lr_beta;
+    a.lr_sh_dc = st->lr_sh_dc;
+    a.lr_sh_rest = st->lr_sh_rest;
+    a.beta1 = st->beta1;
+    a.beta2 = st->beta2;
+    a.eps = st->eps;
+    // bias corrections in double on the host, rounded once
+    a.inv_c1 = (float)(1.0 / (1.0 - pow((double)st->beta1, (double)st->step)));
+    a.inv_c2 = (float)(1.0 / (1.0 - pow((double)st->beta2, (double)st->step)));
+    a.entropy_scale = n > 0 ? (float)((double)st->entropy_weight / (double)n) : 0.f;
+    a.scale_out = scale_out;
+    a.opacity_out = opacity_out;
+    GESR_TRY(hip_check(ctx, hipSetDevice(ctx->device), "hipSetDevice"));
+    GESR_TRY(hip_check(ctx, launch_adam_step(a, 12 + 3 * p->sh_coeffs, (hipStream_t)stream), "adam launch"));
+    ctx->err.clear();
+    return GESR_OK;
+}
+
 }  // extern "C"
 
 // ------------------------------------------------------------------ autotuner

@@ -177,4 +177,19 @@ hipError_t launch_worklist_keys(const uint32_t* ranges, uint64_t total_tiles, ui
 hipError_t launch_l1_grad(const float* image, const float* target, uint64_t count, float scale, float* grad,
                           hipStream_t stream);
 
+// Fused Adam step (gesr_optim.hip).  Rows of the parameter matrix: mean 0-2,
+// log scale 3-5, quaternion 6-9, logit 10, beta 11, SH 12 .. 12 + 3K - 1.
+struct AdamArgs {
+    int n;
+    gesr_params p, m, v;
+    const float *g_mean, *g_scale, *g_quat, *g_opacity, *g_beta, *g_sh;
+    float lr_mean, lr_scale, lr_quat, lr_opacity, lr_beta, lr_sh_dc, lr_sh_rest;
+    float beta1, beta2, eps;
+    float inv_c1, inv_c2;   // 1 / (1 - beta^t)
+    float entropy_scale;    // w / n
+    float* scale_out;
+    float* opacity_out;
+};
+hipError_t launch_adam_step(const AdamArgs& a, int rows, hipStream_t stream);
+
 }  // namespace gesr

@@ -205,3 +205,59 @@ def test_batch_values(lib, batch, status):
     out = _lib.Sizes()
     assert lib.gesr_query_sizes(ctx, cams, 1, 10, ctypes.byref(st), 100, ctypes.byref(out)) == status
     lib.gesr_ctx_destroy(ctx)
+
+
+def test_adam_structs_and_defaults(lib, tmp_path):
+    """gesr_params / gesr_adam_settings layouts against gcc, and the defaults
+    against the binding's AdamConfig."""
+    from paper_2411_09156_amd.optim import AdamConfig
+    src = tmp_path / "adam.c"
+    src.write_text("""
+#include <stdio.h>
+#include <stddef.h>
+#include "gesr.h"
+int main(void) {
+  printf("%zu %zu %zu %zu\\n", sizeof(gesr_params), sizeof(gesr_adam_settings), offsetof(gesr_params, sh),
+         offsetof(gesr_adam_settings, step));
+  return 0;
+}
+""")
+    exe = tmp_path / "adam"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    assert got == [ctypes.sizeof(_lib.Params), ctypes.sizeof(_lib.AdamSettings), _lib.Params.sh.offset,
+                   _lib.AdamSettings.step.offset]
+    s = _lib.AdamSettings()
+    lib.gesr_default_adam_settings(ctypes.byref(s))
+    d = AdamConfig()
+    for f in ("lr_mean", "lr_scale", "lr_quat", "lr_opacity", "lr_beta", "lr_sh_dc", "lr_sh_rest", "beta1", "beta2",
+              "eps", "entropy_weight"):
+        assert getattr(s, f) == pytest.approx(getattr(d, f), rel=1e-7), f
+    assert s.step == 1
+
+
+def test_adam_step_rejects_bad_arguments_on_the_host(lib):
+    ctx = _ctx(lib)
+    ok = _lib.Params(10, 1, 16, 32, 48, 64, 80, 96)
+    g = _lib.Grads(16, 32, 48, 64, 80, 96)
+    st = _lib.AdamSettings()
+    lib.gesr_default_adam_settings(ctypes.byref(st))
+
+    def call(p=ok, m=ok, v=ok, s=st, so=16, oo=32):
+        return lib.gesr_adam_step(ctx, ctypes.byref(p), ctypes.byref(m), ctypes.byref(v), ctypes.byref(g),
+                                  ctypes.byref(s) if s is not None else None, so, oo, None)
+    assert call(s=None) == _lib.GESR_ERR_INVALID
+    assert call(m=_lib.Params(11, 1, 16, 32, 48, 64, 80, 96)) == _lib.GESR_ERR_INVALID
+    assert call(v=_lib.Params(10, 4, 16, 32, 48, 64, 80, 96)) == _lib.GESR_ERR_INVALID
+    assert call(p=_lib.Params(10, 17, 16, 32, 48, 64, 80, 96)) == _lib.GESR_ERR_INVALID
+    assert call(p=_lib.Params(10, 1, 16, 32, 48, 0, 80, 96)) == _lib.GESR_ERR_INVALID
+    assert call(v=_lib.Params(10, 1, 16, 32, 48, 64, 84, 96)) == _lib.GESR_ERR_INVALID
+    assert "aligned" in lib.gesr_last_error(ctx).decode()
+    assert call(oo=0) == _lib.GESR_ERR_INVALID
+    for field, value in (("step", 0), ("beta1", 1.0), ("beta2", -0.1), ("eps", 0.0), ("lr_beta", -1e-3),
+                         ("lr_mean", float("nan")), ("entropy_weight", float("inf"))):
+        bad = _lib.AdamSettings()
+        lib.gesr_default_adam_settings(ctypes.byref(bad))
+        setattr(bad, field, value)
+        assert call(s=bad) == _lib.GESR_ERR_INVALID, field
+    lib.gesr_ctx_destroy(ctx)

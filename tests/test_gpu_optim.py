@@ -1,0 +1,172 @@
+"""GPU parity of the fused optimiser step (gesr_adam_step: Adam with per-group
+learning rates and the opacity-entropy term of the training schedule,
+Sec. 4.2) against the FP64 oracle on the same float32 inputs, over several
+consecutive steps.
+
+Tolerance, derived from float32 arithmetic (unit roundoff 6e-8, bound taken
+as 1e-6, a 16x margin over a handful of roundings): the raw gradient errs by
+1e-6 of the magnitude of its terms (|g_o| o(1 - o) + |w/n logit| o(1 - o) for
+the logit, |g_raw| otherwise); the moments by 1e-6 of the magnitudes of their
+summands plus the gradient's error carried through them; the parameter by 1e-6 |p| plus the update's own error, which is the
+moment error carried through lr m^ / (sqrt(v^) + eps) plus 1e-6 of the update.
+The bound is evaluated element by element from the oracle's float64 values.
+The oracle runs with the float32 values of the settings the kernel receives
+(beta2 = 0.999 rounds to 0.99900001, which moves 1 - beta2 by 1.3e-5).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from tests.gpu_util import log
+
+pytestmark = pytest.mark.gpu
+
+GRAD_KEYS = ("means", "scales", "quats", "opacities", "betas", "sh")
+FIELDS = dict(means="mean", log_scales="log_scale", quats="quat", opacity_logits="opacity_logit", betas="beta",
+              sh="sh")
+GFIELDS = dict(means="mean", scales="scale", quats="quat", opacities="opacity", betas="beta", sh="sh")
+U = 1e-6
+
+
+def _f32(x):
+    return np.asarray(x, np.float32).astype(np.float64)
+
+
+def _inputs(rng, n, K):
+    raw = {"means": rng.standard_normal((n, 3)), "log_scales": rng.uniform(-5, -1, (n, 3)),
+           "quats": rng.standard_normal((n, 4)), "opacity_logits": rng.uniform(-6, 6, n),
+           "betas": rng.uniform(0.5, 4, n), "sh": rng.standard_normal((n, K, 3)) * 0.2}
+    return {k: _f32(v) for k, v in raw.items()}
+
+
+def _grads(rng, n, K):
+    # magnitudes spread over decades, a few exact zeros
+    def g(shape):
+        x = rng.standard_normal(shape) * 10.0 ** rng.uniform(-6, 0, shape)
+        x[rng.random(shape) < 0.02] = 0.0
+        return _f32(x)
+    return {"means": g((n, 3)), "scales": g((n, 3)), "quats": g((n, 4)), "opacities": g(n), "betas": g(n),
+            "sh": g((n, K, 3))}
+
+
+def _settings32(**kw):
+    """Oracle settings holding the float32 values gesr_adam_settings carries."""
+    st = oracle.AdamSettings(**kw)
+    for k, v in vars(st).items():
+        setattr(st, k, float(np.float32(v)))
+    return st
+
+
+def _to_soa(raw, n, K):
+    from paper_2411_09156_amd.optim import RawParams
+    return RawParams.from_aos(raw["means"], raw["log_scales"], raw["quats"], raw["opacity_logits"], raw["betas"],
+                              raw["sh"])
+
+
+def _from_soa(rp, n, K):
+    f = lambda t: t.detach().cpu().numpy().astype(np.float64)  # noqa: E731
+    return {"means": f(rp.mean).T.copy(), "log_scales": f(rp.log_scale).T.copy(), "quats": f(rp.quat).T.copy(),
+            "opacity_logits": f(rp.opacity_logit), "betas": f(rp.beta), "sh": f(rp.sh).T.reshape(n, K, 3).copy()}
+
+
+def _grads_soa(gr, n, K):
+    import torch
+    t = lambda x, rows: torch.as_tensor(np.asarray(x, np.float32).reshape(n, rows).T.copy(), device="cuda")  # noqa
+    return {"mean": t(gr["means"], 3), "scale": t(gr["scales"], 3), "quat": t(gr["quats"], 4),
+            "opacity": torch.as_tensor(np.asarray(gr["opacities"], np.float32), device="cuda"),
+            "beta": torch.as_tensor(np.asarray(gr["betas"], np.float32), device="cuda"),
+            "sh": t(gr["sh"], 3 * K)}
+
+
+def _bounds(p0, m0, v0, gr, step, st):
+    """Element-wise error bounds of (p, m, v) after one float32 step (module docstring)."""
+    n = len(p0["opacity_logits"])
+    g = oracle.adam_raw_grads(p0, gr, st)
+    lg = p0["opacity_logits"]
+    o = 1 / (1 + np.exp(-lg))
+    gmag = {k: np.abs(g[k]) for k in g}
+    gmag["opacity_logits"] = (np.abs(gr["opacities"]) + abs(st.entropy_weight) / max(n, 1) * np.abs(lg)) * o * (1 - o)
+    c1, c2 = 1 - st.beta1 ** step, 1 - st.beta2 ** step
+    lrs = {"means": st.lr_mean, "log_scales": st.lr_scale, "quats": st.lr_quat, "opacity_logits": st.lr_opacity,
+           "betas": st.lr_beta}
+    out = {}
+    for k in oracle.RAW_KEYS:
+        eg = U * gmag[k]
+        em = U * (st.beta1 * np.abs(m0[k]) + (1 - st.beta1) * gmag[k]) + (1 - st.beta1) * eg
+        ev = U * (st.beta2 * np.abs(v0[k]) + (1 - st.beta2) * gmag[k] ** 2) + 2 * (1 - st.beta2) * gmag[k] * eg
+        m = st.beta1 * m0[k] + (1 - st.beta1) * g[k]
+        v = st.beta2 * v0[k] + (1 - st.beta2) * g[k] ** 2
+        if k == "sh":
+            lr = np.full(m.shape, st.lr_sh_rest)
+            lr[:, 0] = st.lr_sh_dc
+        else:
+            lr = lrs[k]
+        den = np.sqrt(v / c2) + st.eps
+        u = lr * (m / c1) / den
+        # d u / d v = -u / (2 den) * sqrt(1/(c2 v)), bounded via sqrt(v) <= den sqrt(c2)
+        eu = lr * em / c1 / den + np.abs(u) * (U + ev / np.maximum(2 * v, 1e-300))
+        out[k] = (U * np.abs(p0[k]) + eu, em, ev)
+    return out
+
+
+def _check(step, got, ref, bounds, what):
+    worst = 0.0
+    for k in oracle.RAW_KEYS:
+        for j, name in enumerate(("p", "m", "v")):
+            a, b, e = got[j][k], ref[j][k], bounds[k][j]
+            # the next step starts from float32 values: allow their rounding too
+            tol = e + 1e-7 * np.abs(b) + 1e-38
+            bad = np.abs(a - b) > tol
+            assert not bad.any(), (what, step, name, k, np.argwhere(bad)[:5], a[bad][:5], b[bad][:5])
+            worst = max(worst, float(np.max(np.abs(a - b) / tol, initial=0.0)))
+    return worst
+
+
+@pytest.mark.parametrize("n,K,w", [(1037, 4, 0.0), (1037, 16, 0.3), (1, 1, 0.5), (70001, 9, 0.1)])
+def test_adam_step_matches_oracle(n, K, w):
+    import torch
+    from paper_2411_09156_amd.optim import AdamConfig, SplatAdam
+    log(f"[gpu] adam n={n} K={K} entropy={w}")
+    rng = np.random.default_rng(1000 + n + K)
+    p = _inputs(rng, n, K)
+    cfg = AdamConfig(entropy_weight=w)
+    st = _settings32(entropy_weight=w)
+    opt = SplatAdam(_to_soa(p, n, K), cfg)
+    m = {k: np.zeros_like(v) for k, v in p.items()}
+    v = {k: np.zeros_like(x) for k, x in p.items()}
+    worst = 0.0
+    for step in range(1, 4):
+        gr = _grads(rng, n, K)
+        opt.step(_grads_soa(gr, n, K))
+        torch.cuda.synchronize()
+        got = (_from_soa(opt.raw, n, K), _from_soa(opt.m, n, K), _from_soa(opt.v, n, K))
+        ref = oracle.adam_step(p, m, v, gr, step, st)
+        worst = max(worst, _check(step, got, ref[:3], _bounds(p, m, v, gr, step, st), "adam"))
+        # activated outputs of the updated raw values (exp and sigmoid in float32: rtol 1e-6)
+        act = ref[3]
+        np.testing.assert_allclose(opt.splats.scale.cpu().numpy().T, np.exp(got[0]["log_scales"]), rtol=1e-6)
+        np.testing.assert_allclose(opt.splats.opacity.cpu().numpy(), 1 / (1 + np.exp(-got[0]["opacity_logits"])),
+                                   rtol=1e-6, atol=1e-12)
+        assert np.allclose(opt.splats.scale.cpu().numpy().T, act["scales"], rtol=1e-5)
+        # continue both sides from the GPU's float32 state
+        p, m, v = got
+    log(f"[gpu] adam n={n} K={K}: worst error / bound {worst:.3f}")
+
+
+def test_adam_step_empty_and_errors():
+    """n = 0 enqueues nothing; invalid settings raise before launch."""
+    import torch
+    from paper_2411_09156_amd._lib import GESR_ERR_INVALID, GesrError
+    from paper_2411_09156_amd.optim import AdamConfig, RawParams, SplatAdam
+    e = lambda *s: torch.zeros(*s, device="cuda")  # noqa: E731
+    opt = SplatAdam(RawParams(e(3, 0), e(3, 0), e(4, 0), e(0), e(0), e(3, 0)))
+    g = dict(mean=e(3, 0), scale=e(3, 0), quat=e(4, 0), opacity=e(0), beta=e(0), sh=e(3, 0))
+    opt.step(g)
+    torch.cuda.synchronize()
+    assert opt.t == 1
+    rng = np.random.default_rng(5)
+    p = _inputs(rng, 8, 1)
+    opt = SplatAdam(_to_soa(p, 8, 1), AdamConfig(beta1=1.0))
+    with pytest.raises(GesrError) as ei:
+        opt.step(_grads_soa(_grads(rng, 8, 1), 8, 1))
+    assert ei.value.status == GESR_ERR_INVALID and opt.t == 0
