@@ -10,8 +10,9 @@ dynamic-resolution batch: 500,000 splats, 8 ring views at 1/8 .. 1 of
 
 Printed: one JSON line with Mpix/s (pixels of all views per second of
 fwd+bwd), the per-view comparison, per-stage times from HIP events on the
-launch stream, the roofline of the dominant kernel and the FP64 oracle timed
-on the host cores over a bounded sample.
+launch stream, the roofline of the dominant kernel, the FP64 oracle timed
+on the host cores over a bounded sample, and a training-step leg (the same
+graph followed by the fused Adam step, with the Adam kernel's HBM roofline).
 """
 from __future__ import annotations
 
@@ -85,6 +86,10 @@ def parse_args():
     p.add_argument("--cpu-sample-views", default="0,1,2,3,4,5")
     p.add_argument("--surface", type=int, default=0,
                    help="also time level-set surface points for this many covered pixels (32 samples per ray)")
+    p.add_argument("--no-train", action="store_true",
+                   help="skip the training-step leg (fwd+bwd graph followed by the fused Adam step)")
+    p.add_argument("--entropy", type=float, default=0.0,
+                   help="weight of the opacity-entropy term in the training-step leg")
     p.add_argument("--channels", action="store_true",
                    help="extended rasterizer: depth and alpha maps in the forward and seeded synthetic upstream "
                         "gradients for them in the backward (16x16 one-wave renderer; implies --no-autotune)")
@@ -367,6 +372,11 @@ def main():
             log(f"[bench] surface points: {pick.size} rays in {s_ms:.3f} ms, valid {valid:.3f}")
             del fx
 
+    # ------------------------------------------- training step with Adam
+    train = None
+    if not args.no_train:
+        train = train_leg(args, scene, rast, target, M, make_step, P)
+
     # ------------------------------------------------------- CPU baseline
     cpu = None
     if not args.no_cpu_baseline:
@@ -389,7 +399,82 @@ def main():
     }
     if surface is not None:
         out["surface"] = surface
+    if train is not None:
+        out["train"] = train
     print(json.dumps(out), flush=True)
+
+
+def train_leg(args, scene, rast, target, M, make_step, P):
+    """Training step of the schedule (Sec. 4.2): the batched fwd+bwd graph on
+    the optimiser's activated parameters, then one fused Adam step of the raw
+    parameters (with the opacity-entropy term), repeated; and the Adam kernel
+    alone against the HBM roofline."""
+    import numpy as np
+    import torch
+
+    from paper_2411_09156_amd.optim import AdamConfig, RawParams, SplatAdam
+    log("[bench] training steps: fwd+bwd graph, then the fused Adam step")
+    op = np.clip(np.asarray(scene.opacities, np.float64), 1e-6, 1 - 1e-6)
+    raw = RawParams.from_aos(scene.means, np.log(np.asarray(scene.scales, np.float64)), scene.quats,
+                             np.log(op / (1 - op)), scene.betas, scene.sh)
+    opt = SplatAdam(raw, AdamConfig(entropy_weight=args.entropy))
+    m_cap = int(M * 1.5) + 4096  # the footprints move while training
+    step = make_step(rast, opt.splats, target, m_cap)
+    step()
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        step()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(graph):
+        f, g, bins = step()
+
+    def l1():
+        return float((f["image"][:3 * P] - target).abs().mean().item())
+    graph.replay()
+    torch.cuda.synchronize()
+    l1_first = l1()
+    for _ in range(args.warmup):
+        graph.replay()
+        opt.step(g)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        graph.replay()
+        opt.step(g)
+    e1.record()
+    torch.cuda.synchronize()
+    tr_ms = e0.elapsed_time(e1) / args.steps
+    graph.replay()
+    torch.cuda.synchronize()
+    l1_last = l1()
+    overflow = int(bins["counters"].cpu().numpy().view(np.uint32)[1])
+    # the Adam kernel alone (events on the stream it is launched on)
+    e0.record()
+    for _ in range(args.steps):
+        opt.step(g)
+    e1.record()
+    torch.cuda.synchronize()
+    adam_ms = e0.elapsed_time(e1) / args.steps
+    n, K = scene.n, opt.raw.sh_coeffs
+    rows = 12 + 3 * K
+    # per splat: read p, m, v, g and write p, m, v for every row; write the
+    # activated scale (3 rows) and opacity
+    bytes_launch = n * (rows * 7 * 4 + 4 * 4)
+    ach = bytes_launch / (adam_ms * 1e-3)
+    log(f"[bench] train step {tr_ms:.3f} ms (Adam {adam_ms:.4f} ms), L1 {l1_first:.5f} -> {l1_last:.5f}")
+    return {"ms_per_step": round(tr_ms, 4), "mpix_s": round(P / (tr_ms * 1e-3) / 1e6, 2),
+            "steps": args.steps + args.warmup, "l1_first": round(l1_first, 6), "l1_last": round(l1_last, 6),
+            "instance_overflow": bool(overflow), "entropy_weight": args.entropy,
+            "adam": {"ms": round(adam_ms, 4), "rows": rows,
+                     "roofline": {"bound": "hbm", "kernel": "adam_step", "achieved": round(ach / 1e9, 1),
+                                  "peak": HBM_BYTES_PER_S / 1e9, "unit": "GB/s",
+                                  "frac": round(ach / HBM_BYTES_PER_S, 4), "traffic": None,
+                                  "algorithmic_bytes_per_launch": bytes_launch}}}
 
 
 def cpu_baseline(scene, k, views, rs, channels=False):

@@ -5,6 +5,8 @@
 // the opacity-entropy term, and the activated scale and opacity written for
 // the next forward.  One pass over every parameter element: HBM-bound.
 
+#include <type_traits>
+
 #include "gesr_device.h"
 #include "gesr_kernels.h"
 
@@ -12,8 +14,41 @@ namespace gesr {
 
 namespace {
 
+struct Vec1 {
+    float x[1];
+};
+struct Vec4 {
+    float x[4];
+};
+template <int VEC>
+using VecT = typename std::conditional<VEC == 4, Vec4, Vec1>::type;
+
+template <int VEC>
+__device__ __forceinline__ VecT<VEC> ld(const float* p) {
+    VecT<VEC> r;
+    if constexpr (VEC == 4) {
+        const float4 q = *reinterpret_cast<const float4*>(p);
+        r.x[0] = q.x; r.x[1] = q.y; r.x[2] = q.z; r.x[3] = q.w;
+    } else {
+        r.x[0] = *p;
+    }
+    return r;
+}
+
+template <int VEC>
+__device__ __forceinline__ void st(float* p, const VecT<VEC>& r) {
+    if constexpr (VEC == 4) {
+        *reinterpret_cast<float4*>(p) = make_float4(r.x[0], r.x[1], r.x[2], r.x[3]);
+    } else {
+        *p = r.x[0];
+    }
+}
+
+// One thread updates VEC consecutive elements of one parameter row (VEC = 4
+// needs n % 4 == 0 so that every row starts 16-byte aligned).
+template <int VEC>
 __global__ __launch_bounds__(256) void k_adam_step(AdamArgs a) {
-    const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+    const uint32_t i = (blockIdx.x * 256u + threadIdx.x) * VEC;
     const uint32_t row = blockIdx.y;
     if (i >= (uint32_t)a.n) return;
     const size_t n = (size_t)a.n;
@@ -41,33 +76,47 @@ __global__ __launch_bounds__(256) void k_adam_step(AdamArgs a) {
         lr = row < 15 ? a.lr_sh_dc : a.lr_sh_rest;
     }
     const size_t k = off + i;
-    const float pk = p[k];
-    float gk = g[k];
-    if (kind == 1) {
-        gk *= expf(pk);  // d scale / d log scale
-    } else if (kind == 2) {
-        // o (1 - o) = e / (1 + e)^2 with e = exp(-|logit|): no cancellation in 1 - o
-        const float e = expf(-fabsf(pk));
-        const float r = 1.0f / (1.0f + e);
-        const float dodl = e * r * r;
-        // entropy_weight * mean H(o): dH/dlogit = -logit o (1 - o)
-        gk = fmaf(gk, dodl, a.entropy_scale * (-pk) * dodl);
+    VecT<VEC> pk = ld<VEC>(p + k), gk = ld<VEC>(g + k), mk = ld<VEC>(m + k), vk = ld<VEC>(v + k), act;
+#pragma unroll
+    for (int j = 0; j < VEC; ++j) {
+        const float x = pk.x[j];
+        float gj = gk.x[j];
+        if (kind == 1) {
+            gj *= expf(x);  // d scale / d log scale
+        } else if (kind == 2) {
+            // o (1 - o) = e / (1 + e)^2 with e = exp(-|logit|): no cancellation in 1 - o
+            const float e = expf(-fabsf(x));
+            const float r = 1.0f / (1.0f + e);
+            const float dodl = e * r * r;
+            // entropy_weight * mean H(o): dH/dlogit = -logit o (1 - o)
+            gj = fmaf(gj, dodl, a.entropy_scale * (-x) * dodl);
+        }
+        const float mj = fmaf(a.beta1, mk.x[j], (1.0f - a.beta1) * gj);
+        const float vj = fmaf(a.beta2, vk.x[j], (1.0f - a.beta2) * gj * gj);
+        const float pn = x - lr * (mj * a.inv_c1) / (sqrtf(vj * a.inv_c2) + a.eps);
+        pk.x[j] = pn;
+        mk.x[j] = mj;
+        vk.x[j] = vj;
+        act.x[j] = kind == 1 ? expf(pn) : 1.0f / (1.0f + expf(-pn));
     }
-    const float mk = fmaf(a.beta1, m[k], (1.0f - a.beta1) * gk);
-    const float vk = fmaf(a.beta2, v[k], (1.0f - a.beta2) * gk * gk);
-    const float pn = pk - lr * (mk * a.inv_c1) / (sqrtf(vk * a.inv_c2) + a.eps);
-    p[k] = pn;
-    m[k] = mk;
-    v[k] = vk;
-    if (kind == 1) a.scale_out[k] = expf(pn);
-    else if (kind == 2) a.opacity_out[i] = 1.0f / (1.0f + expf(-pn));
+    st<VEC>(p + k, pk);
+    st<VEC>(m + k, mk);
+    st<VEC>(v + k, vk);
+    if (kind == 1) st<VEC>(a.scale_out + k, act);
+    else if (kind == 2) st<VEC>(a.opacity_out + i, act);
 }
 
 }  // namespace
 
 hipError_t launch_adam_step(const AdamArgs& a, int rows, hipStream_t stream) {
     if (a.n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_adam_step, dim3((unsigned)((a.n + 255) / 256), (unsigned)rows), dim3(256), 0, stream, a);
+    if (a.n % 4 == 0) {
+        const unsigned quads = (unsigned)(a.n / 4);
+        hipLaunchKernelGGL(k_adam_step<4>, dim3((quads + 255) / 256, (unsigned)rows), dim3(256), 0, stream, a);
+    } else {
+        hipLaunchKernelGGL(k_adam_step<1>, dim3((unsigned)((a.n + 255) / 256), (unsigned)rows), dim3(256), 0,
+                           stream, a);
+    }
     return hipGetLastError();
 }
 

@@ -1,7 +1,8 @@
 """GPU parity of the fused optimiser step (gesr_adam_step: Adam with per-group
 learning rates and the opacity-entropy term of the training schedule,
 Sec. 4.2) against the FP64 oracle on the same float32 inputs, over several
-consecutive steps.
+consecutive steps.  Sizes that are multiples of 4 take the kernel's float4
+path, the others its scalar path.
 
 Tolerance, derived from float32 arithmetic (unit roundoff 6e-8, bound taken
 as 1e-6, a 16x margin over a handful of roundings): the raw gradient errs by
@@ -122,7 +123,8 @@ def _check(step, got, ref, bounds, what):
     return worst
 
 
-@pytest.mark.parametrize("n,K,w", [(1037, 4, 0.0), (1037, 16, 0.3), (1, 1, 0.5), (70001, 9, 0.1)])
+@pytest.mark.parametrize("n,K,w", [(1037, 4, 0.0), (1037, 16, 0.3), (1, 1, 0.5), (70001, 9, 0.1), (4096, 16, 0.2),
+                                   (70000, 1, 0.1)])
 def test_adam_step_matches_oracle(n, K, w):
     import torch
     from paper_2411_09156_amd.optim import AdamConfig, SplatAdam
