@@ -460,6 +460,14 @@ def train_leg(args, scene, rast, target, M, make_step, P):
     e1.record()
     torch.cuda.synchronize()
     adam_ms = e0.elapsed_time(e1) / args.steps
+    # one pruning pass of the trained state (opacity and shape thresholds 0.5);
+    # the interval includes the read-back of the kept count
+    from paper_2411_09156_amd.optim import prune
+    e0.record()
+    kept = prune(opt.raw, opt.m, opt.v, 0.5, 0.5)[0].n
+    e1.record()
+    torch.cuda.synchronize()
+    prune_ms = e0.elapsed_time(e1)
     n, K = scene.n, opt.raw.sh_coeffs
     rows = 12 + 3 * K
     # per splat: read p, m, v, g and write p, m, v for every row; write the
@@ -470,6 +478,7 @@ def train_leg(args, scene, rast, target, M, make_step, P):
     return {"ms_per_step": round(tr_ms, 4), "mpix_s": round(P / (tr_ms * 1e-3) / 1e6, 2),
             "steps": args.steps + args.warmup, "l1_first": round(l1_first, 6), "l1_last": round(l1_last, 6),
             "instance_overflow": bool(overflow), "entropy_weight": args.entropy,
+            "prune": {"ms_incl_readback": round(prune_ms, 4), "kept": kept, "of": scene.n},
             "adam": {"ms": round(adam_ms, 4), "rows": rows,
                      "roofline": {"bound": "hbm", "kernel": "adam_step", "achieved": round(ach / 1e9, 1),
                                   "peak": HBM_BYTES_PER_S / 1e9, "unit": "GB/s",

@@ -428,6 +428,47 @@ gesr_status gesr_adam_step(gesr_ctx* ctx, const gesr_params* p, const gesr_param
                            const gesr_grads* grads, const gesr_adam_settings* st, float* scale_out,
                            float* opacity_out, void* stream);
 
+/* Pruning rule of the training schedule (Sec. 4.2: splats whose opacity falls
+ * below 0.5 are removed; the shape pruning threshold 0.5 is read as a lower
+ * bound on beta, since beta -> 0 flattens exp(-kappa q^(beta/2)) into an
+ * unbounded footprint).  The opacity test is taken on the logit so that both
+ * sides of a comparison see the same float32 number: a splat is kept iff
+ *   logit >= float32(ln(min_opacity / (1 - min_opacity)))  and  beta >= min_beta.
+ * min_opacity = 0 or min_beta <= 0 disables that test. */
+typedef struct {
+    float min_opacity; /* in [0, 1); 0.5 in the paper */
+    float min_beta;
+} gesr_prune_settings;
+
+/* Workspace bytes gesr_prune needs for n splats.  Host-only. */
+size_t gesr_prune_workspace_size(int n);
+
+/* Stable compaction of the kept splats: the raw parameters `p` and, when `m`
+ * and `v` are given (both or neither), Adam's moments, into `out_p` (`out_m`,
+ * `out_v`), whose arrays must each hold as many floats as the corresponding
+ * input array (rows x n).  The outputs are written packed with row stride
+ * n_kept, in the input order: row r of an output array occupies
+ * [r * n_kept, (r + 1) * n_kept); their n and sh_coeffs fields are ignored.
+ * Optional scale_out[3][n_kept] and opacity_out[n_kept] receive the activated
+ * values of the kept splats.  n_kept (DEVICE, one uint32) receives the count;
+ * the call never synchronises (read n_kept back before using the outputs'
+ * sizes).  Inputs and outputs must not overlap.  All arrays DEVICE, 16-byte
+ * aligned.  GESR_ERR_INVALID for NULL or misaligned arrays, a workspace
+ * smaller than gesr_prune_workspace_size(n), min_opacity outside [0, 1) or a
+ * non-finite min_beta; nothing is enqueued then. */
+gesr_status gesr_prune(gesr_ctx* ctx, const gesr_params* p, const gesr_params* m, const gesr_params* v,
+                       const gesr_prune_settings* ps, const gesr_params* out_p, const gesr_params* out_m,
+                       const gesr_params* out_v, float* scale_out, float* opacity_out, uint32_t* n_kept,
+                       void* workspace, size_t workspace_bytes, void* stream);
+
+/* Shape reset of the training schedule (Sec. 4.2: every 1000 iterations),
+ * read as: beta of every splat set to `value` (2, the Gaussian case, where
+ * phi(beta) = 1), and beta's Adam moments in `m` and `v` (nullable) zeroed so
+ * that the optimiser restarts that parameter.  GESR_ERR_INVALID for a NULL p
+ * or beta array, a non-positive or non-finite value. */
+gesr_status gesr_shape_reset(gesr_ctx* ctx, const gesr_params* p, const gesr_params* m, const gesr_params* v,
+                             float value, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

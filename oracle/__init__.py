@@ -339,6 +339,39 @@ def adam_step(raw: dict, m: dict, v: dict, grads: dict, step: int, st: AdamSetti
     return out_p, out_m, out_v, act
 
 
+def prune_keep(raw: dict, min_opacity: float, min_beta: float) -> np.ndarray:
+    """Keep mask of the pruning rule (Sec. 4.2: opacity below 0.5 removed; the
+    shape threshold read as a lower bound on beta).  The opacity test is
+    taken on the float32 logit against the float32 value of
+    ln(min_opacity / (1 - min_opacity)), the same comparison the GPU makes;
+    a threshold of 0 disables its test."""
+    lg = np.asarray(raw["opacity_logits"], np.float32)
+    keep = np.ones(lg.shape[0], bool)
+    if min_opacity > 0:
+        keep &= lg >= np.float32(np.log(np.float64(np.float32(min_opacity)) / (1.0 - np.float64(np.float32(min_opacity)))))
+    if min_beta > 0:
+        keep &= np.asarray(raw["betas"], np.float32) >= np.float32(min_beta)
+    return keep
+
+
+def prune(raw: dict, m: dict, v: dict, min_opacity: float, min_beta: float):
+    """The kept splats of raw (and of the moments m, v when given), in order."""
+    keep = prune_keep(raw, min_opacity, min_beta)
+    sel = lambda d: None if d is None else {k: np.asarray(d[k])[keep] for k in RAW_KEYS}  # noqa: E731
+    return sel(raw), sel(m), sel(v), keep
+
+
+def shape_reset(raw: dict, m: dict, v: dict, value: float):
+    """Shape reset (Sec. 4.2, every 1000 iterations), read as beta := value for
+    every splat with beta's moments zeroed."""
+    out = [None if d is None else {k: np.array(d[k], copy=True) for k in RAW_KEYS} for d in (raw, m, v)]
+    out[0]["betas"][:] = value
+    for d in out[1:]:
+        if d is not None:
+            d["betas"][:] = 0.0
+    return tuple(out)
+
+
 # ------------------------------------------------------------------ pipeline
 def forward(scene, st: Settings, channels: bool = False) -> dict:
     """Full FP64 pipeline: project -> bin -> tiled render (with the extended

@@ -27,7 +27,7 @@ EXPORTS = (
     "gesr_query_sizes", "gesr_project", "gesr_bin", "gesr_render_fwd", "gesr_render_bwd", "gesr_render_bwd_tiles",
     "gesr_render_fwd_ext", "gesr_render_bwd_ext", "gesr_render_bwd_tiles_ext", "gesr_surface_points",
     "gesr_project_bwd", "gesr_l1_grad", "gesr_autotune", "gesr_autotune_candidate", "gesr_default_adam_settings",
-    "gesr_adam_step",
+    "gesr_adam_step", "gesr_prune_workspace_size", "gesr_prune", "gesr_shape_reset",
 )
 
 c_float_p = ctypes.POINTER(ctypes.c_float)
@@ -112,6 +112,10 @@ class AdamSettings(ctypes.Structure):
                 ("reserved", ctypes.c_int32 * 4)]
 
 
+class PruneSettings(ctypes.Structure):
+    _fields_ = [("min_opacity", ctypes.c_float), ("min_beta", ctypes.c_float)]
+
+
 _lib = None
 
 
@@ -180,6 +184,13 @@ def load():
     lib.gesr_default_adam_settings.restype = None
     lib.gesr_adam_step.argtypes = [vp, P(Params), P(Params), P(Params), P(Grads), P(AdamSettings), vp, vp, vp]
     lib.gesr_adam_step.restype = st
+    lib.gesr_prune_workspace_size.argtypes = [ctypes.c_int]
+    lib.gesr_prune_workspace_size.restype = ctypes.c_size_t
+    lib.gesr_prune.argtypes = [vp, P(Params), P(Params), P(Params), P(PruneSettings), P(Params), P(Params),
+                               P(Params), vp, vp, vp, vp, ctypes.c_size_t, vp]
+    lib.gesr_prune.restype = st
+    lib.gesr_shape_reset.argtypes = [vp, P(Params), P(Params), P(Params), ctypes.c_float, vp]
+    lib.gesr_shape_reset.restype = st
     _lib = lib
     return lib
 

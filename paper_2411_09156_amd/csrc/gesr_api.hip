@@ -830,6 +830,98 @@ gesr_status gesr_adam_step(gesr_ctx* ctx, const gesr_params* p, const gesr_param
     return GESR_OK;
 }
 
+size_t gesr_prune_workspace_size(int n) { return n < 0 ? 0 : prune_workspace_bytes(n); }
+
+namespace {
+// The six arrays of a gesr_params in the kernels' order, with their row counts.
+void param_arrays(const gesr_params* q, float* out[6]) {
+    out[0] = q->mean;
+    out[1] = q->log_scale;
+    out[2] = q->quat;
+    out[3] = q->opacity_logit;
+    out[4] = q->beta;
+    out[5] = q->sh;
+}
+}  // namespace
+
+gesr_status gesr_prune(gesr_ctx* ctx, const gesr_params* p, const gesr_params* m, const gesr_params* v,
+                       const gesr_prune_settings* ps, const gesr_params* out_p, const gesr_params* out_m,
+                       const gesr_params* out_v, float* scale_out, float* opacity_out, uint32_t* n_kept,
+                       void* workspace, size_t workspace_bytes, void* stream) {
+    if (!ctx) return GESR_ERR_INVALID;
+    if (!p || !ps || !out_p || !n_kept) return fail(ctx, GESR_ERR_INVALID, "NULL argument");
+    if ((m == nullptr) != (v == nullptr)) return fail(ctx, GESR_ERR_INVALID, "give both moments or neither");
+    if (m && (!out_m || !out_v)) return fail(ctx, GESR_ERR_INVALID, "moment outputs missing");
+    if (p->n < 0) return fail(ctx, GESR_ERR_INVALID, "params->n is negative");
+    if (p->sh_coeffs < 1 || p->sh_coeffs > 16)
+        return fail(ctx, GESR_ERR_INVALID, "sh_coeffs %d outside 1..16", p->sh_coeffs);
+    if (m && (m->n != p->n || v->n != p->n || m->sh_coeffs != p->sh_coeffs || v->sh_coeffs != p->sh_coeffs))
+        return fail(ctx, GESR_ERR_INVALID, "params and moments differ in n or sh_coeffs");
+    if (!(ps->min_opacity >= 0.f && ps->min_opacity < 1.f))
+        return fail(ctx, GESR_ERR_INVALID, "min_opacity must be in [0, 1)");
+    if (!isfinite(ps->min_beta)) return fail(ctx, GESR_ERR_INVALID, "min_beta must be finite");
+    if (!aligned16(n_kept)) return fail(ctx, GESR_ERR_INVALID, "n_kept is not 16-byte aligned");
+    const int n = p->n;
+    const size_t need = prune_workspace_bytes(n);
+    if (!workspace || !aligned16(workspace) || workspace_bytes < need)
+        return fail(ctx, GESR_ERR_INVALID, "workspace NULL, misaligned or smaller than %zu bytes", need);
+    PruneArgs a{};
+    a.n = n;
+    const gesr_params* ins[3] = {p, m, v};
+    const gesr_params* outs[3] = {out_p, out_m, out_v};
+    for (int s = 0; s < 3; ++s) {
+        if (!ins[s]) continue;
+        float* in6[6];
+        float* out6[6];
+        param_arrays(ins[s], in6);
+        param_arrays(outs[s], out6);
+        for (int k = 0; k < 6; ++k) {
+            if (n > 0 && (!in6[k] || !aligned16(in6[k]) || !out6[k] || !aligned16(out6[k])))
+                return fail(ctx, GESR_ERR_INVALID, "parameter array NULL or not 16-byte aligned");
+            if (s == 0) a.in_p[k] = in6[k], a.out_p[k] = out6[k];
+            if (s == 1) a.in_m[k] = in6[k], a.out_m[k] = out6[k];
+            if (s == 2) a.in_v[k] = in6[k], a.out_v[k] = out6[k];
+        }
+    }
+    if (n > 0 && ((scale_out && !aligned16(scale_out)) || (opacity_out && !aligned16(opacity_out))))
+        return fail(ctx, GESR_ERR_INVALID, "scale_out or opacity_out not 16-byte aligned");
+    a.logit = p->opacity_logit;
+    a.beta = p->beta;
+    a.t_logit = ps->min_opacity > 0.f
+                    ? (float)log((double)ps->min_opacity / (1.0 - (double)ps->min_opacity))
+                    : -INFINITY;
+    a.min_beta = ps->min_beta > 0.f ? ps->min_beta : -INFINITY;
+    const uint32_t nb = prune_blocks(n);
+    uint32_t* w = (uint32_t*)workspace;
+    a.n_kept = n_kept;
+    a.bits = w;
+    a.counts = w + (size_t)nb * 32;
+    a.offsets = a.counts + nb;
+    uint32_t* partials = a.offsets + nb;
+    a.scale_out = scale_out;
+    a.opacity_out = opacity_out;
+    GESR_TRY(hip_check(ctx, hipSetDevice(ctx->device), "hipSetDevice"));
+    GESR_TRY(hip_check(ctx, launch_prune(a, 12 + 3 * p->sh_coeffs, partials, (hipStream_t)stream), "prune launch"));
+    ctx->err.clear();
+    return GESR_OK;
+}
+
+gesr_status gesr_shape_reset(gesr_ctx* ctx, const gesr_params* p, const gesr_params* m, const gesr_params* v,
+                             float value, void* stream) {
+    if (!ctx) return GESR_ERR_INVALID;
+    if (!p) return fail(ctx, GESR_ERR_INVALID, "params is NULL");
+    if (p->n < 0) return fail(ctx, GESR_ERR_INVALID, "params->n is negative");
+    if (!(value > 0.f) || !isfinite(value)) return fail(ctx, GESR_ERR_INVALID, "value must be finite and > 0");
+    if (p->n > 0 && !p->beta) return fail(ctx, GESR_ERR_INVALID, "params->beta is NULL");
+    if ((m && m->n != p->n) || (v && v->n != p->n)) return fail(ctx, GESR_ERR_INVALID, "moments differ in n");
+    GESR_TRY(hip_check(ctx, hipSetDevice(ctx->device), "hipSetDevice"));
+    GESR_TRY(hip_check(ctx, launch_shape_reset(p->beta, m ? m->beta : nullptr, v ? v->beta : nullptr, p->n, value,
+                                               (hipStream_t)stream),
+                       "shape reset launch"));
+    ctx->err.clear();
+    return GESR_OK;
+}
+
 }  // extern "C"
 
 // ------------------------------------------------------------------ autotuner

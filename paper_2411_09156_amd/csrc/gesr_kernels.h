@@ -192,4 +192,29 @@ struct AdamArgs {
 };
 hipError_t launch_adam_step(const AdamArgs& a, int rows, hipStream_t stream);
 
+// Stable compaction of the splats kept by the pruning rule (gesr_optim.hip).
+constexpr uint32_t PRUNE_BLOCK = 1024;  // splats per flag / scatter block
+struct PruneArgs {
+    int n;
+    const float* logit;
+    const float* beta;
+    float t_logit, min_beta;  // keep iff logit >= t_logit and beta >= min_beta
+    uint32_t* bits;           // [blocks * 32] keep bits
+    uint32_t* counts;         // [blocks]
+    uint32_t* offsets;        // [blocks], exclusive scan of counts
+    uint32_t* n_kept;         // device total
+    const float* in_p[6];     // mean, log scale, quaternion, logit, beta, SH
+    const float* in_m[6];     // nullable (all or none)
+    const float* in_v[6];
+    float* out_p[6];
+    float* out_m[6];
+    float* out_v[6];
+    float* scale_out;         // nullable: exp(log scale) of the kept splats
+    float* opacity_out;       // nullable: sigmoid(logit) of the kept splats
+};
+uint32_t prune_blocks(int n);
+size_t prune_workspace_bytes(int n);
+hipError_t launch_prune(PruneArgs a, int rows, uint32_t* partials, hipStream_t stream);
+hipError_t launch_shape_reset(float* beta, float* m, float* v, int n, float value, hipStream_t stream);
+
 }  // namespace gesr

@@ -106,7 +106,118 @@ __global__ __launch_bounds__(256) void k_adam_step(AdamArgs a) {
     else if (kind == 2) st<VEC>(a.opacity_out + i, act);
 }
 
+// ---------------------------------------------------------------- pruning
+// Flags of PRUNE_BLOCK splats per block: one bit per splat (keep), and the
+// block's count of kept splats.  Lane l of wave w evaluates splats
+// base + j * 256 + w * 64 + l, so one ballot gives two consecutive words.
+__global__ __launch_bounds__(256) void k_prune_flags(PruneArgs a) {
+    const uint32_t b = blockIdx.x;
+    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+    __shared__ uint32_t s_cnt[16];
+    for (int j = 0; j < 4; ++j) {
+        const uint32_t i = b * PRUNE_BLOCK + j * 256u + wave * 64u + lane;
+        bool keep = false;
+        if (i < (uint32_t)a.n) keep = a.logit[i] >= a.t_logit && a.beta[i] >= a.min_beta;
+        const uint64_t bal = __ballot(keep);
+        const uint32_t word = (b * PRUNE_BLOCK + j * 256u + wave * 64u) >> 5;
+        if (lane == 0) {
+            a.bits[word] = (uint32_t)bal;
+            a.bits[word + 1] = (uint32_t)(bal >> 32);
+            s_cnt[j * 4 + wave] = (uint32_t)__popcll(bal);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t c = 0;
+        for (int k = 0; k < 16; ++k) c += s_cnt[k];
+        a.counts[b] = c;
+    }
+}
+
+// Stable compaction of one parameter row (blockIdx.y) for PRUNE_BLOCK splats:
+// kept splat i goes to column offsets[b] + (kept splats before it in the
+// block); rows are packed with stride n_kept (read from the device).
+__global__ __launch_bounds__(256) void k_prune_scatter(PruneArgs a) {
+    const uint32_t b = blockIdx.x;
+    const uint32_t row = blockIdx.y;
+    __shared__ uint32_t s_bits[32], s_pre[32];
+    if (threadIdx.x < 32) s_bits[threadIdx.x] = a.bits[b * 32u + threadIdx.x];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t c = 0;
+        for (int k = 0; k < 32; ++k) {
+            s_pre[k] = c;
+            c += (uint32_t)__popc(s_bits[k]);
+        }
+    }
+    __syncthreads();
+    const size_t n = (size_t)a.n;
+    const size_t nk = (size_t)*a.n_kept;
+    const uint32_t base = a.offsets[b];
+    // row -> (array, row within it) in the order of the Adam step
+    int arr, rr;
+    if (row < 3) { arr = 0; rr = row; }
+    else if (row < 6) { arr = 1; rr = row - 3; }
+    else if (row < 10) { arr = 2; rr = row - 6; }
+    else if (row == 10) { arr = 3; rr = 0; }
+    else if (row == 11) { arr = 4; rr = 0; }
+    else { arr = 5; rr = row - 12; }
+    const bool with_moments = a.in_m[0] != nullptr;
+    for (int j = 0; j < 4; ++j) {
+        const uint32_t loc = j * 256u + threadIdx.x;
+        const uint32_t i = b * PRUNE_BLOCK + loc;
+        if (i >= (uint32_t)a.n) break;
+        const uint32_t w = s_bits[loc >> 5];
+        if (!((w >> (loc & 31u)) & 1u)) continue;
+        const size_t dst = (size_t)base + s_pre[loc >> 5] + (uint32_t)__popc(w & ((1u << (loc & 31u)) - 1u));
+        const size_t src = (size_t)rr * n + i, dsto = (size_t)rr * nk + dst;
+        const float x = a.in_p[arr][src];
+        a.out_p[arr][dsto] = x;
+        if (with_moments) {
+            a.out_m[arr][dsto] = a.in_m[arr][src];
+            a.out_v[arr][dsto] = a.in_v[arr][src];
+        }
+        if (arr == 1 && a.scale_out) a.scale_out[dsto] = expf(x);
+        if (arr == 3 && a.opacity_out) a.opacity_out[dst] = 1.0f / (1.0f + expf(-x));
+    }
+}
+
+__global__ __launch_bounds__(256) void k_shape_reset(float* beta, float* m, float* v, int n, float value) {
+    const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+    if (i >= (uint32_t)n) return;
+    beta[i] = value;
+    if (m) m[i] = 0.0f;
+    if (v) v[i] = 0.0f;
+}
+
 }  // namespace
+
+uint32_t prune_blocks(int n) { return (uint32_t)(((uint64_t)n + PRUNE_BLOCK - 1) / PRUNE_BLOCK); }
+
+size_t prune_workspace_bytes(int n) {
+    const uint64_t nb = prune_blocks(n);
+    const uint64_t partials = (nb + SCAN_TILE - 1) / SCAN_TILE;
+    // bits (32 words per block), counts, offsets, scan partials, kept total
+    return (size_t)(4 * (nb * 32 + 2 * nb + partials + 1) + 16);
+}
+
+hipError_t launch_prune(PruneArgs a, int rows, uint32_t* partials, hipStream_t stream) {
+    const uint32_t nb = prune_blocks(a.n);
+    if (nb == 0) {
+        return launch_fill_u32(a.n_kept, 0u, 1, stream);
+    }
+    hipLaunchKernelGGL(k_prune_flags, dim3(nb), dim3(256), 0, stream, a);
+    hipError_t e = scan_exclusive(a.counts, a.offsets, nb, partials, a.n_kept, stream);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_prune_scatter, dim3(nb, (unsigned)rows), dim3(256), 0, stream, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_shape_reset(float* beta, float* m, float* v, int n, float value, hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_shape_reset, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, beta, m, v, n, value);
+    return hipGetLastError();
+}
 
 hipError_t launch_adam_step(const AdamArgs& a, int rows, hipStream_t stream) {
     if (a.n == 0) return hipSuccess;

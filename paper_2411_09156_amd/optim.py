@@ -78,10 +78,88 @@ class RawParams:
         def t(x):
             return torch.as_tensor(x, dtype=torch.float32).to(device)
         n = t(opacity_logits).shape[0]
-        shc = t(sh).reshape(n, -1)
+        shc = t(sh)
+        width = 1
+        for d in shc.shape[1:]:
+            width *= int(d)
+        shc = shc.reshape(n, width)
         return RawParams(t(means).reshape(n, 3).t().contiguous(), t(log_scales).reshape(n, 3).t().contiguous(),
                          t(quats).reshape(n, 4).t().contiguous(), t(opacity_logits).contiguous(),
                          t(betas).contiguous(), shc.t().contiguous())
+
+
+_ctxs = {}
+
+
+def _ctx(device: int):
+    """One library context per device for the free functions below (kept for
+    the life of the process)."""
+    lib = _lib.load()
+    if device not in _ctxs:
+        ctx = ctypes.c_void_p()
+        st = lib.gesr_ctx_create(device, ctypes.byref(ctx))
+        if st != _lib.GESR_OK:
+            raise _lib.GesrError(st, lib.gesr_status_string(st).decode())
+        _ctxs[device] = ctx
+    return lib, _ctxs[device]
+
+
+def _rows(raw: RawParams):
+    return (3, 3, 4, 1, 1, 3 * raw.sh_coeffs)
+
+
+def prune(raw: RawParams, m: RawParams = None, v: RawParams = None, min_opacity: float = 0.5,
+          min_beta: float = 0.5, device: int = 0):
+    """Stable compaction of the splats kept by the pruning rule (gesr_prune).
+    Returns (raw, m, v, scale, opacity) of the kept splats (m and v None when
+    not given; scale and opacity activated).  Synchronises once to read the
+    kept count."""
+    lib, ctx = _ctx(device)
+    n = raw.n
+
+    def alloc_like(src):
+        return RawParams(*(torch.empty_like(getattr(src, k)) for k in RAW_FIELDS))
+    out_p = alloc_like(raw)
+    out_m = alloc_like(m) if m is not None else None
+    out_v = alloc_like(v) if v is not None else None
+    dev = raw.opacity_logit.device
+    scale = torch.empty_like(raw.log_scale)
+    opacity = torch.empty_like(raw.opacity_logit)
+    n_kept = torch.zeros(4, dtype=torch.int32, device=dev)
+    wsb = int(lib.gesr_prune_workspace_size(n))
+    ws = torch.empty(max(wsb, 16), dtype=torch.uint8, device=dev)
+    ps = _lib.PruneSettings(float(min_opacity), float(min_beta))
+
+    def ref(x):
+        return ctypes.byref(x.to_c()) if x is not None else None
+    st = lib.gesr_prune(ctx, ref(raw), ref(m), ref(v), ctypes.byref(ps), ref(out_p), ref(out_m), ref(out_v),
+                        scale.data_ptr(), opacity.data_ptr(), n_kept.data_ptr(), ws.data_ptr(), wsb, _stream())
+    if st != _lib.GESR_OK:
+        raise _lib.GesrError(st, lib.gesr_last_error(ctx).decode())
+    nk = int(n_kept[0].item())
+
+    def packed(x):
+        if x is None:
+            return None
+        views = []
+        for k, r in zip(RAW_FIELDS, _rows(raw)):
+            flat = getattr(x, k).reshape(-1)[:r * nk]
+            views.append(flat.view(nk) if k in ("opacity_logit", "beta") else flat.view(r, nk))
+        return RawParams(*views)
+    return (packed(out_p), packed(out_m), packed(out_v), scale.reshape(-1)[:3 * nk].view(3, nk),
+            opacity[:nk])
+
+
+def shape_reset(raw: RawParams, m: RawParams = None, v: RawParams = None, value: float = 2.0,
+                device: int = 0) -> None:
+    """Sets beta of every splat to `value` and zeroes its moments (gesr_shape_reset)."""
+    lib, ctx = _ctx(device)
+
+    def ref(x):
+        return ctypes.byref(x.to_c()) if x is not None else None
+    st = lib.gesr_shape_reset(ctx, ref(raw), ref(m), ref(v), float(value), _stream())
+    if st != _lib.GESR_OK:
+        raise _lib.GesrError(st, lib.gesr_last_error(ctx).decode())
 
 
 class SplatAdam:
@@ -123,3 +201,15 @@ class SplatAdam:
         if st != _lib.GESR_OK:
             self.t -= 1
             raise _lib.GesrError(st, self.lib.gesr_last_error(self.ctx).decode())
+
+    def prune(self, min_opacity: float = 0.5, min_beta: float = 0.5) -> int:
+        """Removes pruned splats from the parameters, moments and activated
+        buffers (new tensors; the step counter continues).  Returns the kept
+        count."""
+        raw, m, v, scale, opacity = prune(self.raw, self.m, self.v, min_opacity, min_beta)
+        self.raw, self.m, self.v = raw, m, v
+        self.splats = Splats(raw.mean, scale, raw.quat, opacity, raw.beta, raw.sh)
+        return raw.n
+
+    def shape_reset(self, value: float = 2.0) -> None:
+        shape_reset(self.raw, self.m, self.v, value)

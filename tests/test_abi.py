@@ -261,3 +261,30 @@ def test_adam_step_rejects_bad_arguments_on_the_host(lib):
         setattr(bad, field, value)
         assert call(s=bad) == _lib.GESR_ERR_INVALID, field
     lib.gesr_ctx_destroy(ctx)
+
+
+def test_prune_and_shape_reset_reject_bad_arguments_on_the_host(lib):
+    ctx = _ctx(lib)
+    ok = _lib.Params(10, 1, 16, 32, 48, 64, 80, 96)
+    ps = _lib.PruneSettings(0.5, 0.5)
+    need = lib.gesr_prune_workspace_size(10)
+    assert need >= 4 * (32 + 2) and lib.gesr_prune_workspace_size(3_000_000) > need
+
+    def call(p=ok, m=None, v=None, s=ps, om=None, ov=None, nk=16, ws=16, wsb=None):
+        r = lambda x: ctypes.byref(x) if x is not None else None  # noqa: E731
+        return lib.gesr_prune(ctx, r(p), r(m), r(v), r(s), ctypes.byref(ok), r(om), r(ov), None, None, nk, ws,
+                              need if wsb is None else wsb, None)
+    assert call(s=None) == _lib.GESR_ERR_INVALID
+    assert call(m=ok) == _lib.GESR_ERR_INVALID  # v missing
+    assert call(m=ok, v=ok) == _lib.GESR_ERR_INVALID  # moment outputs missing
+    assert call(nk=0) == _lib.GESR_ERR_INVALID
+    assert call(wsb=need - 1) == _lib.GESR_ERR_INVALID
+    assert call(ws=8) == _lib.GESR_ERR_INVALID
+    assert call(s=_lib.PruneSettings(1.0, 0.5)) == _lib.GESR_ERR_INVALID
+    assert call(s=_lib.PruneSettings(0.5, float("nan"))) == _lib.GESR_ERR_INVALID
+    assert call(p=_lib.Params(10, 1, 16, 32, 48, 0, 80, 96)) == _lib.GESR_ERR_INVALID
+    assert lib.gesr_shape_reset(ctx, ctypes.byref(ok), None, None, 0.0, None) == _lib.GESR_ERR_INVALID
+    assert lib.gesr_shape_reset(ctx, None, None, None, 2.0, None) == _lib.GESR_ERR_INVALID
+    assert lib.gesr_shape_reset(ctx, ctypes.byref(_lib.Params(10, 1, 16, 32, 48, 64, 0, 96)), None, None, 2.0,
+                                None) == _lib.GESR_ERR_INVALID
+    lib.gesr_ctx_destroy(ctx)

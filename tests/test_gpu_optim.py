@@ -172,3 +172,75 @@ def test_adam_step_empty_and_errors():
     with pytest.raises(GesrError) as ei:
         opt.step(_grads_soa(_grads(rng, 8, 1), 8, 1))
     assert ei.value.status == GESR_ERR_INVALID and opt.t == 0
+
+
+@pytest.mark.parametrize("n,K,mo,mb", [(5000, 4, 0.5, 0.5), (1025, 16, 0.5, 0.5), (1024, 1, 0.3, 0.0),
+                                       (1023, 9, 0.0, 1.0), (1, 1, 0.5, 0.5), (3000, 1, 0.0, 0.0),
+                                       (2048, 4, 0.9999, 5.0), (0, 1, 0.5, 0.5)])
+def test_prune_matches_oracle_bit_exact(n, K, mo, mb):
+    """Stable compaction (gesr_prune) against the oracle's mask indexing:
+    identical kept set, order and values for parameters and moments; the
+    activated outputs within float32 exp and sigmoid error."""
+    import torch
+    from paper_2411_09156_amd.optim import prune
+    log(f"[gpu] prune n={n} K={K} min_opacity={mo} min_beta={mb}")
+    rng = np.random.default_rng(2000 + n + K)
+    p = _inputs(rng, n, K)
+    p["opacity_logits"] = _f32(rng.uniform(-3, 3, n))
+    p["betas"] = _f32(rng.uniform(0.2, 4, n))
+    if n >= 8:  # values on the thresholds
+        p["opacity_logits"][:4] = _f32([0.0, -0.0, -1e-7, 1e-7])
+        p["betas"][4:8] = _f32([mb, np.nextafter(np.float32(mb), np.float32(0)), 0.5, 1.0])
+    m = {k: _f32(rng.standard_normal(np.shape(x))) for k, x in p.items()}
+    v = {k: _f32(rng.uniform(0, 1, np.shape(x))) for k, x in p.items()}
+    P, M, Vv = _to_soa(p, n, K), _to_soa(m, n, K), _to_soa(v, n, K)
+    rp, rm, rv, scale, opacity = prune(P, M, Vv, mo, mb)
+    torch.cuda.synchronize()
+    ep, em, ev, keep = oracle.prune(p, m, v, mo, mb)
+    nk = int(keep.sum())
+    assert rp.n == nk
+    for got, ref in ((rp, ep), (rm, em), (rv, ev)):
+        g = _from_soa(got, nk, K)
+        for k in oracle.RAW_KEYS:
+            np.testing.assert_array_equal(g[k], ref[k], err_msg=k)
+    np.testing.assert_allclose(scale.cpu().numpy().T, np.exp(ep["log_scales"]), rtol=1e-6)
+    np.testing.assert_allclose(opacity.cpu().numpy(), 1 / (1 + np.exp(-ep["opacity_logits"])), rtol=1e-6)
+    # without moments
+    rp2, rm2, rv2, _, _ = prune(P, None, None, mo, mb)
+    assert rm2 is None and rv2 is None and rp2.n == nk
+    np.testing.assert_array_equal(_from_soa(rp2, nk, K)["sh"], ep["sh"])
+    log(f"[gpu] prune n={n}: kept {nk}")
+
+
+def test_shape_reset_and_training_bookkeeping():
+    """gesr_shape_reset against the oracle; SplatAdam.prune keeps the
+    optimiser state of the kept splats and the step counter."""
+    import torch
+    from paper_2411_09156_amd.optim import SplatAdam, shape_reset
+    rng = np.random.default_rng(7)
+    n, K = 3001, 4
+    p = _inputs(rng, n, K)
+    m = {k: _f32(rng.standard_normal(np.shape(x))) for k, x in p.items()}
+    P, M = _to_soa(p, n, K), _to_soa(m, n, K)
+    shape_reset(P, M, None, 2.0)
+    torch.cuda.synchronize()
+    ep, em, _ = oracle.shape_reset(p, m, None, 2.0)
+    for got, ref in ((P, ep), (M, em)):
+        g = _from_soa(got, n, K)
+        for k in oracle.RAW_KEYS:
+            np.testing.assert_array_equal(g[k], ref[k], err_msg=k)
+    opt = SplatAdam(_to_soa(p, n, K))
+    for _ in range(2):
+        opt.step(_grads_soa(_grads(rng, n, K), n, K))
+    before = (_from_soa(opt.raw, n, K), _from_soa(opt.m, n, K), _from_soa(opt.v, n, K))
+    nk = opt.prune(0.5, 0.5)
+    torch.cuda.synchronize()
+    ref = oracle.prune(*before, 0.5, 0.5)
+    assert nk == int(ref[3].sum()) and opt.t == 2 and opt.splats.n == nk
+    for got, r in zip((opt.raw, opt.m, opt.v), ref[:3]):
+        g = _from_soa(got, nk, K)
+        for k in oracle.RAW_KEYS:
+            np.testing.assert_array_equal(g[k], r[k], err_msg=k)
+    opt.step(_grads_soa(_grads(rng, nk, K), nk, K))
+    torch.cuda.synchronize()
+    assert opt.t == 3

@@ -94,3 +94,45 @@ def test_raw_gradients_match_central_differences(w):
             rm[k].reshape(-1)[j] -= h
             fd = (loss(rp) - loss(rm)) / (2 * h)
             assert g[k].reshape(-1)[j] == pytest.approx(fd, rel=1e-7, abs=1e-9), (k, j)
+
+
+def test_prune_hand_example():
+    """Opacity 0.5 and beta 0.5 thresholds: logit 0 is kept (opacity exactly
+    0.5), -1e-7 is not; beta 0.5 is kept, 0.4 is not; order and moments follow."""
+    lg = np.array([-1.0, 0.0, 0.3, -1e-7, 2.0, -0.0])
+    be = np.array([1.0, 0.4, 0.6, 3.0, 0.5, 2.0])
+    n = 6
+    raw = {"means": np.arange(18.0).reshape(n, 3), "log_scales": np.zeros((n, 3)), "quats": np.zeros((n, 4)),
+           "opacity_logits": lg, "betas": be, "sh": np.arange(n * 3.0).reshape(n, 1, 3)}
+    m = {k: v + 100 for k, v in raw.items()}
+    p, pm, pv, keep = oracle.prune(raw, m, None, 0.5, 0.5)
+    assert keep.tolist() == [False, False, True, False, True, True]
+    assert p["means"][:, 0].tolist() == [6.0, 12.0, 15.0]
+    assert pm["betas"].tolist() == [100.6, 100.5, 102.0]
+    assert pv is None
+    # thresholds of 0 keep everything
+    assert oracle.prune_keep(raw, 0.0, 0.0).all()
+
+
+def test_prune_opacity_rule_matches_sigmoid_away_from_the_threshold():
+    """keep == (sigmoid(logit) >= min_opacity) wherever the opacity is not
+    within 1e-6 of the threshold."""
+    rng = np.random.default_rng(3)
+    lg = rng.uniform(-8, 8, 20000).astype(np.float32).astype(np.float64)
+    raw = {"opacity_logits": lg, "betas": np.ones_like(lg)}
+    for mo in (0.005, 0.3, 0.5, 0.9):
+        keep = oracle.prune_keep(raw, mo, 0.0)
+        o = 1 / (1 + np.exp(-lg))
+        far = np.abs(o - mo) > 1e-6
+        np.testing.assert_array_equal(keep[far], (o >= mo)[far])
+        assert 0 < keep.sum() < keep.size
+
+
+def test_shape_reset():
+    rng = np.random.default_rng(4)
+    n, K = 7, 4
+    raw, m = _raw(rng, n, K), _raw(rng, n, K)
+    p2, m2, v2 = oracle.shape_reset(raw, m, None, 2.0)
+    assert (p2["betas"] == 2.0).all() and (m2["betas"] == 0.0).all() and v2 is None
+    np.testing.assert_array_equal(p2["means"], raw["means"])
+    assert not (raw["betas"] == 2.0).any()  # inputs untouched
