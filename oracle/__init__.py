@@ -259,6 +259,45 @@ def surface_points(scene, rec, vals, ranges, depth_map, alpha_map, pixels, st: S
     return {k: v[:R] for k, v in out.items()}
 
 
+def knn(means, K: int = 16) -> np.ndarray:
+    """Neighbour lists [N, K] (int32): slot 0 = the splat itself, then its
+    K - 1 nearest other centres by (squared distance, index); -1 pads when
+    N < K (see orc_knn)."""
+    means = _f64(means).reshape(-1, 3)
+    N = means.shape[0]
+    out = np.zeros((max(N, 1), K), np.int32)
+    lib().orc_knn(int(N), _p(means), int(K), _p(out))
+    return out[:N]
+
+
+def gsr(scene, st: Settings, nbrs, xi, mask=None, w_sdf: float = 1.0, w_nor: float = 1.0,
+        grads: bool = True) -> dict:
+    """Surface regulariser of Sec. 3.3 (Eq. 9-13) on one sample per splat
+    (see orc_gsr for the readings).  scene: any object with means, scales,
+    quats, opacities, betas (activated, float64-promotable); nbrs [N, K];
+    xi [N, 3]; mask [N] (nullable).  Returns per-sample l_sdf, l_nor, gstar
+    (slot), margins [N, 5] and, when `grads`, the gradients of
+    sum_j mask_j (w_sdf l_sdf + w_nor l_nor) as means/scales/quats/opacities/betas."""
+    means = _f64(scene.means).reshape(-1, 3)
+    N = means.shape[0]
+    nbrs = np.ascontiguousarray(nbrs, np.int32).reshape(N, -1)
+    K = nbrs.shape[1]
+    out = dict(l_sdf=np.zeros(max(N, 1)), l_nor=np.zeros(max(N, 1)), gstar=np.zeros(max(N, 1), np.int32),
+               margins=np.zeros((max(N, 1), 5)))
+    g = np.zeros((max(N, 1), 12)) if grads else None
+    m = None if mask is None else np.ascontiguousarray(mask, np.uint8)
+    lib().orc_gsr(int(N), _p(means), _p(_f64(scene.scales).reshape(-1, 3)), _p(_f64(scene.quats).reshape(-1, 4)),
+                  _p(_f64(scene.opacities)), _p(_f64(scene.betas)), _p(st.array()), int(K), _p(nbrs),
+                  _p(_f64(xi).reshape(-1, 3)), _p(m), ctypes.c_double(w_sdf), ctypes.c_double(w_nor),
+                  _p(out["l_sdf"]), _p(out["l_nor"]), _p(out["gstar"]), _p(out["margins"]), _p(g))
+    res = {k: v[:N] for k, v in out.items()}
+    if grads:
+        g = g[:N]
+        res["grads"] = dict(means=g[:, 0:3], scales=g[:, 3:6], quats=g[:, 6:10], opacities=g[:, 10],
+                            betas=g[:, 11])
+    return res
+
+
 def sh_basis(degree: int, dirs) -> np.ndarray:
     dirs = _f64(dirs)
     n = dirs.shape[0]

@@ -29,6 +29,7 @@
 // adjoint uses explicit per-pixel fragment lists (no transmittance division).
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -1027,6 +1028,235 @@ int orc_surface_points(int N, int V, const double* means, const double* scales, 
 int orc_sh_basis(int degree, long n, const double* dirs, double* out) {
     int K = (degree + 1) * (degree + 1);
     for (long i = 0; i < n; ++i) sh_basis<double>(degree, dirs[3 * i], dirs[3 * i + 1], dirs[3 * i + 2], out + K * i);
+    return 0;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------ surface regulariser (GSR)
+// Sec. 3.3, Eq. (9)-(13), with the neighbour lists of Sec. 4.2 (16 nearest
+// centres, refreshed periodically).  Readings (the paper leaves these open):
+//   * Neighbourhood N(j) of splat j: j itself in slot 0, then its K - 1
+//     nearest other centres by (squared distance, index).
+//   * Sample set X: one point per (selected) splat, x_j = mu_j + M_j xi_j with
+//     M = R diag(phi s) (Eq. 4, 6) and xi_j given (standard normal draws made
+//     by the caller), so x depends on splat j's parameters.
+//   * d(x) of Eq. (9) sums o_i exp(-kappa m_i^beta_i) over N(j) (kappa = 1/2
+//     is the printed 1/2, m_i the Mahalanobis distance under M_i).
+//   * g* is the neighbour with the largest term at x; its normal n is the
+//     rotation column of its smallest scale, s_min = phi s of that axis.
+//   * Eq. (10) with s_min^beta (the falloff of Eq. 9 along the normal of a
+//     flat splat of opacity 1): dbar = exp(-kappa (|h| / s_min)^beta*),
+//     h = <x - mu_g*, n>; equal to the printed form at beta = 2.
+//   * Eq. (11): f = sigma s_min sqrt(-ln d / kappa) (the printed -2 log d at
+//     kappa = 1/2), sigma = sign(h) (+1 at 0) for both f and fbar; d is
+//     floored at 1e-30 and -ln d clamped at 0 (f = 0 where d >= 1).
+//   * Eq. (12): l_sdf = |fbar - f|.  Eq. (13): l_nor = |grad f / |grad f| - n|^2
+//     with grad f / |grad f| = -sigma grad d / |grad d| (0 when grad d = 0).
+//   * The loss of a sample is w_sdf l_sdf + w_nor l_nor; its gradient is the
+//     exact derivative with every discrete choice (N(j), g*, its axis, sigma,
+//     the clamps) held fixed.
+// Parity: pinned by brute-force neighbour lists, closed forms of lone and
+// paired splats and central differences of the loss.
+namespace {
+
+template <int D> Dual<D> log(const Dual<D>& a) {
+    Dual<D> r(std::log(a.v)); for (int k = 0; k < D; ++k) r.d[k] = a.d[k] / a.v; return r;
+}
+using std::log;
+template <class S> S powS(const S& a, const S& b) { return exp(b * log(a)); }
+template <class S> S absS(const S& a) { return val(a) < 0.0 ? -a : a; }
+
+constexpr double kGsrFloor = 1e-30;
+
+struct GsrInfo {
+    int gstar = 0, kstar = 0;
+    // decision margins: g* (relative gap of the two largest terms), sigma
+    // (|h| / s_min), the kink of |fbar - f| (relative), the clamp at d = 1
+    // (|ln d|), the normal axis (relative gap of the two smallest scales)
+    double margins[5] = {0, 0, 0, 0, 0};
+};
+
+template <class S>
+void gsr_rot(const S q[4], S R[9]) {
+    S qn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    S w = q[0] / qn, x = q[1] / qn, y = q[2] / qn, z = q[3] / qn;
+    R[0] = 1.0 - 2.0 * (y * y + z * z); R[1] = 2.0 * (x * y - w * z); R[2] = 2.0 * (x * z + w * y);
+    R[3] = 2.0 * (x * y + w * z); R[4] = 1.0 - 2.0 * (x * x + z * z); R[5] = 2.0 * (y * z - w * x);
+    R[6] = 2.0 * (x * z - w * y); R[7] = 2.0 * (y * z + w * x); R[8] = 1.0 - 2.0 * (x * x + y * y);
+}
+
+// Loss terms of one sample.  Parameter arrays hold the K neighbours in slot
+// order (slot 0 = the sampled splat).
+template <class S>
+void gsr_sample(int K, const S (*mean)[3], const S (*scale)[3], const S (*quat)[4], const S* opac, const S* beta,
+                const double xi[3], const Settings& st, S& l_sdf, S& l_nor, GsrInfo& info) {
+    std::vector<std::array<S, 9>> R(K);
+    std::vector<std::array<S, 3>> sig(K);
+    for (int i = 0; i < K; ++i) {
+        gsr_rot(quat[i], R[i].data());
+        S phi = 2.0 / (1.0 + exp(-st.rho * (beta[i] - 2.0)));
+        for (int k = 0; k < 3; ++k) sig[i][k] = phi * scale[i][k];
+    }
+    // the sample x = mu_0 + R_0 diag(sig_0) xi
+    S x[3];
+    for (int a = 0; a < 3; ++a) {
+        x[a] = mean[0][a];
+        for (int k = 0; k < 3; ++k) x[a] = x[a] + R[0][3 * a + k] * (sig[0][k] * xi[k]);
+    }
+    // Eq. (9) and its gradient in x
+    S d(0.0), gd[3] = {S(0.0), S(0.0), S(0.0)};
+    double best = -1.0, second = -1.0;
+    int gs = 0;
+    for (int i = 0; i < K; ++i) {
+        S dx[3] = {x[0] - mean[i][0], x[1] - mean[i][1], x[2] - mean[i][2]};
+        S y[3];
+        for (int k = 0; k < 3; ++k)
+            y[k] = (R[i][k] * dx[0] + R[i][3 + k] * dx[1] + R[i][6 + k] * dx[2]) / sig[i][k];
+        S q = y[0] * y[0] + y[1] * y[1] + y[2] * y[2];
+        S T, c(0.0);
+        if (val(q) > 0.0) {
+            S P = powS(q, beta[i] * 0.5);
+            T = opac[i] * exp(-st.kappa * P);
+            c = -st.kappa * beta[i] * P / q * T;  // dT/dq * 2
+        } else {
+            T = opac[i];
+        }
+        d = d + T;
+        for (int a = 0; a < 3; ++a)
+            gd[a] = gd[a] + c * (R[i][3 * a] * y[0] / sig[i][0] + R[i][3 * a + 1] * y[1] / sig[i][1] +
+                                 R[i][3 * a + 2] * y[2] / sig[i][2]);
+        if (val(T) > best) { second = best; best = val(T); gs = i; }
+        else if (val(T) > second) second = val(T);
+    }
+    info.gstar = gs;
+    info.margins[0] = best > 0.0 ? (best - std::max(second, 0.0)) / best : 0.0;
+    // normal and s_min of g*
+    int ks = 0;
+    for (int k = 1; k < 3; ++k) if (val(sig[gs][k]) < val(sig[gs][ks])) ks = k;
+    double s2 = 1e300;
+    for (int k = 0; k < 3; ++k) if (k != ks) s2 = std::min(s2, val(sig[gs][k]));
+    info.kstar = ks;
+    info.margins[4] = (s2 - val(sig[gs][ks])) / val(sig[gs][ks]);
+    S n[3] = {R[gs][ks], R[gs][3 + ks], R[gs][6 + ks]};
+    S smin = sig[gs][ks];
+    S h = (x[0] - mean[gs][0]) * n[0] + (x[1] - mean[gs][1]) * n[1] + (x[2] - mean[gs][2]) * n[2];
+    double sg = val(h) >= 0.0 ? 1.0 : -1.0;
+    info.margins[1] = std::fabs(val(h)) / val(smin);
+    S r = absS(h) / smin;
+    S A = val(r) > 0.0 ? powS(r, beta[gs] * 0.5) : S(0.0);  // fbar / (sigma s_min)
+    S Ld = val(d) > kGsrFloor ? -log(d) : S(-std::log(kGsrFloor));
+    info.margins[3] = std::fabs(val(Ld));
+    S B = val(Ld) > 0.0 ? sqrt(Ld / st.kappa) : S(0.0);  // f / (sigma s_min)
+    S diff = A - B;
+    info.margins[2] = std::fabs(val(diff)) / std::max(std::max(val(A), val(B)), 1e-300);
+    l_sdf = smin * absS(diff);
+    S g2 = gd[0] * gd[0] + gd[1] * gd[1] + gd[2] * gd[2];
+    if (val(g2) > 0.0) {
+        S gn = sqrt(g2);
+        l_nor = S(0.0);
+        for (int a = 0; a < 3; ++a) {
+            S e = -sg * gd[a] / gn - n[a];
+            l_nor = l_nor + e * e;
+        }
+    } else {
+        l_nor = S(0.0);
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+// Neighbour lists: knn[j][0] = j, then the K - 1 nearest other centres by
+// (squared distance, index) (brute force).
+int orc_knn(int N, const double* means, int K, int32_t* knn) {
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int j = 0; j < N; ++j) {
+        std::vector<std::pair<double, int>> dist;
+        dist.reserve(N);
+        for (int i = 0; i < N; ++i) {
+            if (i == j) continue;
+            double dx = means[3 * i] - means[3 * j], dy = means[3 * i + 1] - means[3 * j + 1],
+                   dz = means[3 * i + 2] - means[3 * j + 2];
+            dist.emplace_back(dx * dx + dy * dy + dz * dz, i);
+        }
+        int m = std::min(K - 1, (int)dist.size());
+        std::partial_sort(dist.begin(), dist.begin() + m, dist.end());
+        knn[(long)j * K] = j;
+        for (int s = 1; s < K; ++s) knn[(long)j * K + s] = s - 1 < m ? dist[s - 1].second : -1;
+    }
+    return 0;
+}
+
+// GSR losses and gradients.  knn [N][K] (slot 0 = j); xi [N][3]; mask [N]
+// (nullable: every sample); per sample l_sdf, l_nor, gstar (neighbour slot),
+// margins [N][5]; grads [N][12] (mean 3, scale 3, quat 4, opacity, beta) of
+// sum_j mask_j (w_sdf l_sdf + w_nor l_nor), accumulated when non-null.
+int orc_gsr(int N, const double* means, const double* scales, const double* quats, const double* opac,
+            const double* betas, const double* settings, int K, const int32_t* knn, const double* xi,
+            const uint8_t* mask, double w_sdf, double w_nor, double* l_sdf, double* l_nor, int32_t* gstar,
+            double* margins, double* grads) {
+    Settings st = read_settings(settings);
+    int nt = nthreads();
+    std::vector<std::vector<double>> tg(grads ? nt : 0, std::vector<double>(grads ? (size_t)N * 12 : 0, 0.0));
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int j = 0; j < N; ++j) {
+        l_sdf[j] = l_nor[j] = 0.0;
+        gstar[j] = -1;
+        for (int k = 0; k < 5; ++k) margins[5 * j + k] = 0.0;
+        if (mask && !mask[j]) continue;
+        const int32_t* nb = knn + (long)j * K;
+        std::vector<double> mu(3 * K), sc(3 * K), qu(4 * K), op(K), be(K);
+        for (int s = 0; s < K; ++s) {
+            long i = nb[s];
+            for (int a = 0; a < 3; ++a) { mu[3 * s + a] = means[3 * i + a]; sc[3 * s + a] = scales[3 * i + a]; }
+            for (int a = 0; a < 4; ++a) qu[4 * s + a] = quats[4 * i + a];
+            op[s] = opac[i];
+            be[s] = betas[i];
+        }
+        GsrInfo info;
+        double ls, ln;
+        gsr_sample<double>(K, reinterpret_cast<const double(*)[3]>(mu.data()),
+                           reinterpret_cast<const double(*)[3]>(sc.data()),
+                           reinterpret_cast<const double(*)[4]>(qu.data()), op.data(), be.data(), xi + 3 * j, st, ls,
+                           ln, info);
+        l_sdf[j] = ls;
+        l_nor[j] = ln;
+        gstar[j] = info.gstar;
+        for (int k = 0; k < 5; ++k) margins[5 * j + k] = info.margins[k];
+        if (!grads) continue;
+        double* g = tg[thread_id()].data();
+        using D12 = Dual<12>;
+        std::vector<D12> dm(3 * K), ds(3 * K), dq(4 * K), dop(K), db(K);
+        for (int s = 0; s < K; ++s) {
+            for (int a = 0; a < 3; ++a) { dm[3 * s + a] = D12(mu[3 * s + a]); ds[3 * s + a] = D12(sc[3 * s + a]); }
+            for (int a = 0; a < 4; ++a) dq[4 * s + a] = D12(qu[4 * s + a]);
+            dop[s] = D12(op[s]);
+            db[s] = D12(be[s]);
+        }
+        for (int s = 0; s < K; ++s) {
+            // seed neighbour s's twelve parameters
+            for (int a = 0; a < 3; ++a) { dm[3 * s + a].d[a] = 1.0; ds[3 * s + a].d[3 + a] = 1.0; }
+            for (int a = 0; a < 4; ++a) dq[4 * s + a].d[6 + a] = 1.0;
+            dop[s].d[10] = 1.0;
+            db[s].d[11] = 1.0;
+            GsrInfo di;
+            D12 a_sdf, a_nor;
+            gsr_sample<D12>(K, reinterpret_cast<const D12(*)[3]>(dm.data()),
+                            reinterpret_cast<const D12(*)[3]>(ds.data()), reinterpret_cast<const D12(*)[4]>(dq.data()),
+                            dop.data(), db.data(), xi + 3 * j, st, a_sdf, a_nor, di);
+            long i = nb[s];
+            for (int k = 0; k < 12; ++k) g[12 * i + k] += w_sdf * a_sdf.d[k] + w_nor * a_nor.d[k];
+            for (int a = 0; a < 3; ++a) { dm[3 * s + a].d[a] = 0.0; ds[3 * s + a].d[3 + a] = 0.0; }
+            for (int a = 0; a < 4; ++a) dq[4 * s + a].d[6 + a] = 0.0;
+            dop[s].d[10] = 0.0;
+            db[s].d[11] = 0.0;
+        }
+    }
+    if (grads)
+        for (int t = 0; t < nt; ++t)
+            for (long k = 0; k < (long)N * 12; ++k) grads[k] += tg[t][k];
     return 0;
 }
 
