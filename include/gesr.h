@@ -469,6 +469,65 @@ gesr_status gesr_prune(gesr_ctx* ctx, const gesr_params* p, const gesr_params* m
 gesr_status gesr_shape_reset(gesr_ctx* ctx, const gesr_params* p, const gesr_params* m, const gesr_params* v,
                              float value, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Surface regulariser (Sec. 3.3, Eq. 9-13; neighbour lists of Sec. 4.2).
+ * ------------------------------------------------------------------------ */
+#define GESR_KNN_MAX 16
+
+/* Workspace bytes of gesr_knn for n splats and k neighbours.  Host-only. */
+size_t gesr_knn_workspace_size(int n, int k);
+
+/* Neighbour lists of the density of Eq. 9 (Sec. 4.2: 16 nearest splats,
+ * refreshed periodically): knn[j][0] = j, then the k - 1 nearest other
+ * centres by squared distance (float32), ties by index; 0xFFFFFFFF pads the
+ * rows when n < k.  Also the inverse lists: inv_entries[inv_offsets[i] ..
+ * inv_offsets[i + 1]) are the entries e = j * k + s with knn[j][s] = i, in
+ * increasing e (inv_offsets [n + 1], inv_entries [n * k]).  Reads the means
+ * of `splats` only.  DEVICE arrays, 16-byte aligned; the call never
+ * synchronises.  GESR_ERR_INVALID for k outside 1..16, n * k >= 2^32, NULL or
+ * misaligned arrays, or a workspace smaller than gesr_knn_workspace_size. */
+gesr_status gesr_knn(gesr_ctx* ctx, const gesr_splats* splats, int k, uint32_t* knn, uint32_t* inv_offsets,
+                     uint32_t* inv_entries, void* workspace, size_t workspace_bytes, void* stream);
+
+/* Weights of the two regulariser terms (lambda_1, lambda_2 of Eq. 14, which
+ * the paper does not give; fold the 1 / |X| of Eq. 12-13 in as well). */
+typedef struct {
+    float w_sdf;
+    float w_nor;
+} gesr_gsr_settings;
+
+/* Workspace bytes of gesr_gsr (frames, and partials when gradients are
+ * wanted).  Host-only. */
+size_t gesr_gsr_workspace_size(int n, int k, int with_grads);
+
+/* Surface-regulariser losses and gradients on one sample per splat:
+ *   x_j = mu_j + R_j diag(phi s_j) xi_j  (xi DEVICE [3][n], e.g. standard
+ *   normal draws; samples with mask[j] == 0 are skipped, mask nullable);
+ *   d(x) = sum over knn[j] of o_i exp(-kappa m_i(x)^beta_i)  (Eq. 9);
+ *   g* = the neighbour with the largest term, n = its rotation column of the
+ *   smallest scale, s_min = phi s of that axis, h = <x - mu_g*, n>;
+ *   ideal density (Eq. 10, with s_min^beta: the falloff of Eq. 9 along the
+ *   normal of a flat splat of opacity 1) exp(-kappa (|h| / s_min)^beta*);
+ *   SDF (Eq. 11) f = sign(h) s_min sqrt(-ln d / kappa) for both densities
+ *   (d floored at 1e-30, f = 0 where d >= 1);
+ *   l_sdf = |fbar - f| (Eq. 12), l_nor = |-sign(h) grad d / |grad d| - n|^2
+ *   (Eq. 13; 0 where grad d = 0).
+ * kappa and rho come from `st`.  sample_out [n][4] (DEVICE, nullable):
+ * l_sdf, l_nor, g*'s slot in knn[j] (-1 when masked), d.  losses [2] (DEVICE,
+ * nullable): the sums of l_sdf and l_nor over the samples, in a fixed order.
+ * When `grads` is non-null, the gradient of
+ * sum_j (w_sdf l_sdf + w_nor l_nor) with respect to mean, scale, quat,
+ * opacity and beta (activated, layouts of gesr_splats) is ADDED to it, each
+ * splat's terms summed in inverse-list order (no atomics; every discrete
+ * choice held fixed); grads->sh is not touched.  The workspace needs
+ * gesr_gsr_workspace_size(n, k, grads != NULL) bytes.  GESR_ERR_INVALID for
+ * NULL or misaligned arrays, k outside 1..16, non-finite weights or a small
+ * workspace. */
+gesr_status gesr_gsr(gesr_ctx* ctx, const gesr_splats* splats, const gesr_settings* st, int k, const uint32_t* knn,
+                     const uint32_t* inv_offsets, const uint32_t* inv_entries, const float* xi, const uint8_t* mask,
+                     const gesr_gsr_settings* gs, float* sample_out, float* losses, const gesr_grads* grads,
+                     void* workspace, size_t workspace_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -276,14 +276,14 @@ def gsr(scene, st: Settings, nbrs, xi, mask=None, w_sdf: float = 1.0, w_nor: flo
     (see orc_gsr for the readings).  scene: any object with means, scales,
     quats, opacities, betas (activated, float64-promotable); nbrs [N, K];
     xi [N, 3]; mask [N] (nullable).  Returns per-sample l_sdf, l_nor, gstar
-    (slot), margins [N, 5] and, when `grads`, the gradients of
+    (slot), margins [N, 7] and, when `grads`, the gradients of
     sum_j mask_j (w_sdf l_sdf + w_nor l_nor) as means/scales/quats/opacities/betas."""
     means = _f64(scene.means).reshape(-1, 3)
     N = means.shape[0]
     nbrs = np.ascontiguousarray(nbrs, np.int32).reshape(N, -1)
     K = nbrs.shape[1]
     out = dict(l_sdf=np.zeros(max(N, 1)), l_nor=np.zeros(max(N, 1)), gstar=np.zeros(max(N, 1), np.int32),
-               margins=np.zeros((max(N, 1), 5)))
+               margins=np.zeros((max(N, 1), 7)))
     g = np.zeros((max(N, 1), 12)) if grads else None
     m = None if mask is None else np.ascontiguousarray(mask, np.uint8)
     lib().orc_gsr(int(N), _p(means), _p(_f64(scene.scales).reshape(-1, 3)), _p(_f64(scene.quats).reshape(-1, 4)),

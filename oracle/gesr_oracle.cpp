@@ -1052,7 +1052,9 @@ int orc_sh_basis(int degree, long n, const double* dirs, double* out) {
 //     kappa = 1/2), sigma = sign(h) (+1 at 0) for both f and fbar; d is
 //     floored at 1e-30 and -ln d clamped at 0 (f = 0 where d >= 1).
 //   * Eq. (12): l_sdf = |fbar - f|.  Eq. (13): l_nor = |grad f / |grad f| - n|^2
-//     with grad f / |grad f| = -sigma grad d / |grad d| (0 when grad d = 0).
+//     with grad f / |grad f| = -sigma grad d / |grad d|; 0 unless d and
+//     |grad d| both exceed 1e-30 (below that the SDF or its direction is
+//     undefined in float32).
 //   * The loss of a sample is w_sdf l_sdf + w_nor l_nor; its gradient is the
 //     exact derivative with every discrete choice (N(j), g*, its axis, sigma,
 //     the clamps) held fixed.
@@ -1072,9 +1074,13 @@ constexpr double kGsrFloor = 1e-30;
 struct GsrInfo {
     int gstar = 0, kstar = 0;
     // decision margins: g* (relative gap of the two largest terms), sigma
-    // (|h| / s_min), the kink of |fbar - f| (relative), the clamp at d = 1
-    // (|ln d|), the normal axis (relative gap of the two smallest scales)
-    double margins[5] = {0, 0, 0, 0, 0};
+    // (|h| / |x - mu_g*|, the relative conditioning of h), the kink of
+    // |fbar - f| (relative), the clamp at d = 1 (|ln d|), the normal axis
+    // (relative gap of the two smallest scales), the conditioning of the
+    // normal term (|grad d| / sum_i |grad T_i|: its direction is
+    // ill-conditioned where the terms cancel), and the floors of d and
+    // |grad d| (min of |ln(d / 1e-30)| and |ln(|grad d| / 1e-30)|)
+    double margins[7] = {0, 0, 0, 0, 0, 0, 0};
 };
 
 template <class S>
@@ -1106,7 +1112,7 @@ void gsr_sample(int K, const S (*mean)[3], const S (*scale)[3], const S (*quat)[
     }
     // Eq. (9) and its gradient in x
     S d(0.0), gd[3] = {S(0.0), S(0.0), S(0.0)};
-    double best = -1.0, second = -1.0;
+    double best = -1.0, second = -1.0, gsum = 0.0;
     int gs = 0;
     for (int i = 0; i < K; ++i) {
         S dx[3] = {x[0] - mean[i][0], x[1] - mean[i][1], x[2] - mean[i][2]};
@@ -1123,9 +1129,14 @@ void gsr_sample(int K, const S (*mean)[3], const S (*scale)[3], const S (*quat)[
             T = opac[i];
         }
         d = d + T;
-        for (int a = 0; a < 3; ++a)
-            gd[a] = gd[a] + c * (R[i][3 * a] * y[0] / sig[i][0] + R[i][3 * a + 1] * y[1] / sig[i][1] +
-                                 R[i][3 * a + 2] * y[2] / sig[i][2]);
+        double gi2 = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            S ga = c * (R[i][3 * a] * y[0] / sig[i][0] + R[i][3 * a + 1] * y[1] / sig[i][1] +
+                        R[i][3 * a + 2] * y[2] / sig[i][2]);
+            gd[a] = gd[a] + ga;
+            gi2 += val(ga) * val(ga);
+        }
+        gsum += std::sqrt(gi2);
         if (val(T) > best) { second = best; best = val(T); gs = i; }
         else if (val(T) > second) second = val(T);
     }
@@ -1142,7 +1153,11 @@ void gsr_sample(int K, const S (*mean)[3], const S (*scale)[3], const S (*quat)[
     S smin = sig[gs][ks];
     S h = (x[0] - mean[gs][0]) * n[0] + (x[1] - mean[gs][1]) * n[1] + (x[2] - mean[gs][2]) * n[2];
     double sg = val(h) >= 0.0 ? 1.0 : -1.0;
-    info.margins[1] = std::fabs(val(h)) / val(smin);
+    {
+        double xm2 = 0.0;
+        for (int a = 0; a < 3; ++a) xm2 += (val(x[a]) - val(mean[gs][a])) * (val(x[a]) - val(mean[gs][a]));
+        info.margins[1] = xm2 > 0.0 ? std::fabs(val(h)) / std::sqrt(xm2) : 0.0;
+    }
     S r = absS(h) / smin;
     S A = val(r) > 0.0 ? powS(r, beta[gs] * 0.5) : S(0.0);  // fbar / (sigma s_min)
     S Ld = val(d) > kGsrFloor ? -log(d) : S(-std::log(kGsrFloor));
@@ -1152,7 +1167,12 @@ void gsr_sample(int K, const S (*mean)[3], const S (*scale)[3], const S (*quat)[
     info.margins[2] = std::fabs(val(diff)) / std::max(std::max(val(A), val(B)), 1e-300);
     l_sdf = smin * absS(diff);
     S g2 = gd[0] * gd[0] + gd[1] * gd[1] + gd[2] * gd[2];
-    if (val(g2) > 0.0) {
+    info.margins[5] = gsum > 0.0 ? std::sqrt(val(g2)) / gsum : 0.0;
+    const double gabs = std::sqrt(val(g2));
+    info.margins[6] = std::min(val(d) > 0.0 ? std::fabs(std::log(val(d) / kGsrFloor)) : 0.0,
+                               gabs > 0.0 ? std::fabs(std::log(gabs / kGsrFloor)) : 0.0);
+    // the normal term needs the SDF (d above its floor) and a direction
+    if (val(d) > kGsrFloor && gabs > kGsrFloor) {
         S gn = sqrt(g2);
         l_nor = S(0.0);
         for (int a = 0; a < 3; ++a) {
@@ -1191,7 +1211,7 @@ int orc_knn(int N, const double* means, int K, int32_t* knn) {
 
 // GSR losses and gradients.  knn [N][K] (slot 0 = j); xi [N][3]; mask [N]
 // (nullable: every sample); per sample l_sdf, l_nor, gstar (neighbour slot),
-// margins [N][5]; grads [N][12] (mean 3, scale 3, quat 4, opacity, beta) of
+// margins [N][7]; grads [N][12] (mean 3, scale 3, quat 4, opacity, beta) of
 // sum_j mask_j (w_sdf l_sdf + w_nor l_nor), accumulated when non-null.
 int orc_gsr(int N, const double* means, const double* scales, const double* quats, const double* opac,
             const double* betas, const double* settings, int K, const int32_t* knn, const double* xi,
@@ -1204,7 +1224,7 @@ int orc_gsr(int N, const double* means, const double* scales, const double* quat
     for (int j = 0; j < N; ++j) {
         l_sdf[j] = l_nor[j] = 0.0;
         gstar[j] = -1;
-        for (int k = 0; k < 5; ++k) margins[5 * j + k] = 0.0;
+        for (int k = 0; k < 7; ++k) margins[7 * j + k] = 0.0;
         if (mask && !mask[j]) continue;
         const int32_t* nb = knn + (long)j * K;
         std::vector<double> mu(3 * K), sc(3 * K), qu(4 * K), op(K), be(K);
@@ -1224,7 +1244,7 @@ int orc_gsr(int N, const double* means, const double* scales, const double* quat
         l_sdf[j] = ls;
         l_nor[j] = ln;
         gstar[j] = info.gstar;
-        for (int k = 0; k < 5; ++k) margins[5 * j + k] = info.margins[k];
+        for (int k = 0; k < 7; ++k) margins[7 * j + k] = info.margins[k];
         if (!grads) continue;
         double* g = tg[thread_id()].data();
         using D12 = Dual<12>;

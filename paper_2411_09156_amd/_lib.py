@@ -27,8 +27,10 @@ EXPORTS = (
     "gesr_query_sizes", "gesr_project", "gesr_bin", "gesr_render_fwd", "gesr_render_bwd", "gesr_render_bwd_tiles",
     "gesr_render_fwd_ext", "gesr_render_bwd_ext", "gesr_render_bwd_tiles_ext", "gesr_surface_points",
     "gesr_project_bwd", "gesr_l1_grad", "gesr_autotune", "gesr_autotune_candidate", "gesr_default_adam_settings",
-    "gesr_adam_step", "gesr_prune_workspace_size", "gesr_prune", "gesr_shape_reset",
+    "gesr_adam_step", "gesr_prune_workspace_size", "gesr_prune", "gesr_shape_reset", "gesr_knn_workspace_size",
+    "gesr_knn", "gesr_gsr_workspace_size", "gesr_gsr",
 )
+KNN_MAX = 16
 
 c_float_p = ctypes.POINTER(ctypes.c_float)
 c_u32_p = ctypes.POINTER(ctypes.c_uint32)
@@ -116,6 +118,10 @@ class PruneSettings(ctypes.Structure):
     _fields_ = [("min_opacity", ctypes.c_float), ("min_beta", ctypes.c_float)]
 
 
+class GsrSettings(ctypes.Structure):
+    _fields_ = [("w_sdf", ctypes.c_float), ("w_nor", ctypes.c_float)]
+
+
 _lib = None
 
 
@@ -191,6 +197,15 @@ def load():
     lib.gesr_prune.restype = st
     lib.gesr_shape_reset.argtypes = [vp, P(Params), P(Params), P(Params), ctypes.c_float, vp]
     lib.gesr_shape_reset.restype = st
+    lib.gesr_knn_workspace_size.argtypes = [ctypes.c_int, ctypes.c_int]
+    lib.gesr_knn_workspace_size.restype = ctypes.c_size_t
+    lib.gesr_knn.argtypes = [vp, P(Splats), ctypes.c_int, vp, vp, vp, vp, ctypes.c_size_t, vp]
+    lib.gesr_knn.restype = st
+    lib.gesr_gsr_workspace_size.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    lib.gesr_gsr_workspace_size.restype = ctypes.c_size_t
+    lib.gesr_gsr.argtypes = [vp, P(Splats), P(Settings), ctypes.c_int, vp, vp, vp, vp, vp, P(GsrSettings), vp, vp,
+                             P(Grads), vp, ctypes.c_size_t, vp]
+    lib.gesr_gsr.restype = st
     _lib = lib
     return lib
 

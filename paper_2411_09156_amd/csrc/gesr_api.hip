@@ -922,6 +922,110 @@ gesr_status gesr_shape_reset(gesr_ctx* ctx, const gesr_params* p, const gesr_par
     return GESR_OK;
 }
 
+size_t gesr_knn_workspace_size(int n, int k) {
+    if (n < 0 || k < 1 || k > GESR_KNN_MAX) return 0;
+    return (size_t)knn_layout(n, k).words * 4 + 256;
+}
+
+gesr_status gesr_knn(gesr_ctx* ctx, const gesr_splats* splats, int k, uint32_t* knn, uint32_t* inv_offsets,
+                     uint32_t* inv_entries, void* workspace, size_t workspace_bytes, void* stream) {
+    if (!ctx) return GESR_ERR_INVALID;
+    if (!splats) return fail(ctx, GESR_ERR_INVALID, "splats is NULL");
+    if (splats->n < 0) return fail(ctx, GESR_ERR_INVALID, "splats->n is negative");
+    if (k < 1 || k > GESR_KNN_MAX) return fail(ctx, GESR_ERR_INVALID, "k = %d outside 1..%d", k, GESR_KNN_MAX);
+    const int n = splats->n;
+    if ((uint64_t)n * (uint64_t)k >= (1ull << 32)) return fail(ctx, GESR_ERR_INVALID, "n * k must be < 2^32");
+    if (!inv_offsets || !aligned16(inv_offsets)) return fail(ctx, GESR_ERR_INVALID, "inv_offsets NULL or misaligned");
+    if (n > 0) {
+        const void* ptrs[3] = {splats->mean, knn, inv_entries};
+        for (const void* ptr : ptrs)
+            if (!ptr || !aligned16(ptr)) return fail(ctx, GESR_ERR_INVALID, "array NULL or not 16-byte aligned");
+    }
+    const size_t need = gesr_knn_workspace_size(n, k);
+    if (!workspace || !aligned16(workspace) || workspace_bytes < need)
+        return fail(ctx, GESR_ERR_INVALID, "workspace NULL, misaligned or smaller than %zu bytes", need);
+    // 256-byte alignment of the sub-buffers
+    uint32_t* ws = (uint32_t*)(((uintptr_t)workspace + 255) & ~(uintptr_t)255);
+    GESR_TRY(hip_check(ctx, hipSetDevice(ctx->device), "hipSetDevice"));
+    GESR_TRY(hip_check(ctx, launch_knn(splats->mean, n, k, knn, inv_offsets, inv_entries, ws, (hipStream_t)stream),
+                       "knn launch"));
+    ctx->err.clear();
+    return GESR_OK;
+}
+
+size_t gesr_gsr_workspace_size(int n, int k, int with_grads) {
+    if (n < 0 || k < 1 || k > GESR_KNN_MAX) return 0;
+    const size_t n1 = (size_t)(n > 0 ? n : 1);
+    size_t floats = n1 * GSR_FRAME_FLOATS + n1 * 4;
+    if (with_grads) floats += n1 * (size_t)k * GSR_PARTIAL_FLOATS;
+    return floats * 4 + 256;
+}
+
+gesr_status gesr_gsr(gesr_ctx* ctx, const gesr_splats* splats, const gesr_settings* st, int k, const uint32_t* knn,
+                     const uint32_t* inv_offsets, const uint32_t* inv_entries, const float* xi, const uint8_t* mask,
+                     const gesr_gsr_settings* gs, float* sample_out, float* losses, const gesr_grads* grads,
+                     void* workspace, size_t workspace_bytes, void* stream) {
+    if (!ctx) return GESR_ERR_INVALID;
+    if (!splats || !st || !gs) return fail(ctx, GESR_ERR_INVALID, "NULL argument");
+    GESR_TRY(check_settings(ctx, st));
+    if (splats->n < 0) return fail(ctx, GESR_ERR_INVALID, "splats->n is negative");
+    if (k < 1 || k > GESR_KNN_MAX) return fail(ctx, GESR_ERR_INVALID, "k = %d outside 1..%d", k, GESR_KNN_MAX);
+    if (!isfinite(gs->w_sdf) || !isfinite(gs->w_nor)) return fail(ctx, GESR_ERR_INVALID, "weights must be finite");
+    const int n = splats->n;
+    if ((uint64_t)n * (uint64_t)k >= (1ull << 32)) return fail(ctx, GESR_ERR_INVALID, "n * k must be < 2^32");
+    if (n > 0) {
+        const void* ptrs[8] = {splats->mean, splats->scale, splats->quat, splats->opacity, splats->beta, knn,
+                               xi, inv_offsets};
+        for (const void* ptr : ptrs)
+            if (!ptr || !aligned16(ptr)) return fail(ctx, GESR_ERR_INVALID, "array NULL or not 16-byte aligned");
+        if (sample_out && !aligned16(sample_out)) return fail(ctx, GESR_ERR_INVALID, "sample_out not 16-byte aligned");
+        if (grads) {
+            const void* gp[6] = {grads->mean, grads->scale, grads->quat, grads->opacity, grads->beta, inv_entries};
+            for (const void* ptr : gp)
+                if (!ptr || !aligned16(ptr))
+                    return fail(ctx, GESR_ERR_INVALID, "gradient or inverse-list array NULL or misaligned");
+        }
+    }
+    if (losses && !aligned16(losses)) return fail(ctx, GESR_ERR_INVALID, "losses not 16-byte aligned");
+    const size_t need = gesr_gsr_workspace_size(n, k, grads != nullptr);
+    if (!workspace || !aligned16(workspace) || workspace_bytes < need)
+        return fail(ctx, GESR_ERR_INVALID, "workspace NULL, misaligned or smaller than %zu bytes", need);
+    float* ws = (float*)(((uintptr_t)workspace + 255) & ~(uintptr_t)255);
+    const size_t n1 = (size_t)(n > 0 ? n : 1);
+    GsrArgs a{};
+    a.n = n;
+    a.k = k;
+    a.mean = splats->mean;
+    a.scale = splats->scale;
+    a.quat = splats->quat;
+    a.opacity = splats->opacity;
+    a.beta = splats->beta;
+    a.knn = knn;
+    a.inv_offsets = inv_offsets;
+    a.inv_entries = inv_entries;
+    a.xi = xi;
+    a.mask = mask;
+    a.kappa = st->kappa;
+    a.rho = st->rho;
+    a.w_sdf = gs->w_sdf;
+    a.w_nor = gs->w_nor;
+    a.frames = ws;
+    a.sample_out = sample_out ? sample_out : ws + n1 * GSR_FRAME_FLOATS;
+    a.partials = grads ? ws + n1 * GSR_FRAME_FLOATS + n1 * 4 : nullptr;
+    a.losses = losses;
+    if (grads) {
+        a.g_mean = grads->mean;
+        a.g_scale = grads->scale;
+        a.g_quat = grads->quat;
+        a.g_opacity = grads->opacity;
+        a.g_beta = grads->beta;
+    }
+    GESR_TRY(hip_check(ctx, hipSetDevice(ctx->device), "hipSetDevice"));
+    GESR_TRY(hip_check(ctx, launch_gsr(a, (hipStream_t)stream), "gsr launch"));
+    ctx->err.clear();
+    return GESR_OK;
+}
+
 }  // extern "C"
 
 // ------------------------------------------------------------------ autotuner

@@ -131,7 +131,7 @@ def test_gradients_match_central_differences(w_sdf, w_nor):
     base = oracle.gsr(sc, st, nb, xi, w_sdf=w_sdf, w_nor=w_nor)
     # keep samples whose discrete choices are far from their thresholds
     m = base["margins"]
-    mask = ((m[:, 0] > 1e-2) & (m[:, 1] > 1e-3) & (m[:, 2] > 1e-3) & (m[:, 3] > 1e-3) & (m[:, 4] > 1e-2))
+    mask = ((m[:, 0] > 1e-2) & (m[:, 1] > 1e-3) & (m[:, 2] > 1e-3) & (m[:, 3] > 1e-3) & (m[:, 4] > 1e-2) & (m[:, 6] > 1e-3))
     assert mask.sum() >= 12
     res = oracle.gsr(sc, st, nb, xi, mask=mask.astype(np.uint8), w_sdf=w_sdf, w_nor=w_nor)
 
