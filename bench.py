@@ -11,8 +11,9 @@ dynamic-resolution batch: 500,000 splats, 8 ring views at 1/8 .. 1 of
 Printed: one JSON line with Mpix/s (pixels of all views per second of
 fwd+bwd), the per-view comparison, per-stage times from HIP events on the
 launch stream, the roofline of the dominant kernel, the FP64 oracle timed
-on the host cores over a bounded sample, and a training-step leg (the same
-graph followed by the fused Adam step, with the Adam kernel's HBM roofline).
+on the host cores over a bounded sample, a training-step leg (the same
+graph followed by the fused Adam step, with the Adam kernel's HBM roofline)
+and a surface-regulariser leg (neighbour lists, losses and gradients).
 """
 from __future__ import annotations
 
@@ -88,6 +89,8 @@ def parse_args():
                    help="also time level-set surface points for this many covered pixels (32 samples per ray)")
     p.add_argument("--no-train", action="store_true",
                    help="skip the training-step leg (fwd+bwd graph followed by the fused Adam step)")
+    p.add_argument("--no-gsr", action="store_true",
+                   help="skip the surface-regulariser leg (neighbour lists, losses and gradients)")
     p.add_argument("--entropy", type=float, default=0.0,
                    help="weight of the opacity-entropy term in the training-step leg")
     p.add_argument("--channels", action="store_true",
@@ -377,6 +380,11 @@ def main():
     if not args.no_train:
         train = train_leg(args, scene, rast, target, M, make_step, P)
 
+    # ------------------------------------------- surface regulariser (GSR)
+    gsr_out = None
+    if not args.no_gsr:
+        gsr_out = gsr_leg(args, scene, sp, rs)
+
     # ------------------------------------------------------- CPU baseline
     cpu = None
     if not args.no_cpu_baseline:
@@ -401,6 +409,8 @@ def main():
         out["surface"] = surface
     if train is not None:
         out["train"] = train
+    if gsr_out is not None:
+        out["gsr"] = gsr_out
     print(json.dumps(out), flush=True)
 
 
@@ -484,6 +494,55 @@ def train_leg(args, scene, rast, target, M, make_step, P):
                                   "peak": HBM_BYTES_PER_S / 1e9, "unit": "GB/s",
                                   "frac": round(ach / HBM_BYTES_PER_S, 4), "traffic": None,
                                   "algorithmic_bytes_per_launch": bytes_launch}}}
+
+
+def gsr_leg(args, scene, sp, rs):
+    """Surface regulariser of Sec. 3.3 (Eq. 9-13) on the workload's splats:
+    the 16-neighbour lists with their inverse (one refresh), then one sample
+    per splat with losses and gradients, against the HBM roofline of its
+    algorithmic bytes."""
+    import numpy as np
+    import torch
+
+    from paper_2411_09156_amd.gsr import gsr, knn
+    log("[bench] surface regulariser: neighbour lists, then losses and gradients")
+    n = sp.n
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    nb = knn(sp, 16)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(args.steps):
+        nb = knn(sp, 16)
+    e1.record()
+    torch.cuda.synchronize()
+    knn_ms = e0.elapsed_time(e1) / args.steps
+    xi = torch.as_tensor(np.random.default_rng(31).standard_normal((3, n)).astype(np.float32), device="cuda")
+    grads = {k: torch.zeros_like(getattr(sp, k)) for k in ("mean", "scale", "quat", "opacity", "beta")}
+    w = 1.0 / n
+    out = gsr(sp, rs, nb, xi, w_sdf=w, w_nor=w, grads=grads)
+    for _ in range(args.warmup):
+        gsr(sp, rs, nb, xi, w_sdf=w, w_nor=w, grads=grads)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(args.steps):
+        out = gsr(sp, rs, nb, xi, w_sdf=w, w_nor=w, grads=grads)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    losses = out["losses"].cpu().numpy().astype(np.float64) / n
+    # algorithmic HBM bytes per splat: frames (48 B of parameters read, 96 B
+    # written), the loss pass (own frame 96, xi 12, list 64, partials 16 x 48
+    # written, per-sample results 16), the gather (inverse list 68, partials
+    # 768, gradients 48 read + 48 written) and the loss sum (16)
+    per_splat = 48 + 96 + (96 + 12 + 64 + 768 + 16) + (68 + 768 + 96) + 16
+    ach = per_splat * n / (ms * 1e-3)
+    log(f"[bench] gsr: knn {knn_ms:.3f} ms, losses + gradients {ms:.3f} ms, L_sdf {losses[0]:.4g} L_nor {losses[1]:.4g}")
+    return {"splats": n, "neighbours": 16, "knn_ms": round(knn_ms, 4), "ms": round(ms, 4),
+            "samples_per_s": round(n / (ms * 1e-3), 1), "l_sdf": round(float(losses[0]), 6),
+            "l_nor": round(float(losses[1]), 6),
+            "roofline": {"bound": "hbm", "kernel": "gsr (frames + loss + gather + sum)", "achieved": round(ach / 1e9, 1),
+                         "peak": HBM_BYTES_PER_S / 1e9, "unit": "GB/s", "frac": round(ach / HBM_BYTES_PER_S, 4),
+                         "traffic": None, "algorithmic_bytes_per_launch": per_splat * n}}
 
 
 def cpu_baseline(scene, k, views, rs, channels=False):

@@ -480,14 +480,17 @@ size_t gesr_knn_workspace_size(int n, int k);
 /* Neighbour lists of the density of Eq. 9 (Sec. 4.2: 16 nearest splats,
  * refreshed periodically): knn[j][0] = j, then the k - 1 nearest other
  * centres by squared distance (float32), ties by index; 0xFFFFFFFF pads the
- * rows when n < k.  Also the inverse lists: inv_entries[inv_offsets[i] ..
- * inv_offsets[i + 1]) are the entries e = j * k + s with knn[j][s] = i, in
- * increasing e (inv_offsets [n + 1], inv_entries [n * k]).  Reads the means
- * of `splats` only.  DEVICE arrays, 16-byte aligned; the call never
- * synchronises.  GESR_ERR_INVALID for k outside 1..16, n * k >= 2^32, NULL or
- * misaligned arrays, or a workspace smaller than gesr_knn_workspace_size. */
-gesr_status gesr_knn(gesr_ctx* ctx, const gesr_splats* splats, int k, uint32_t* knn, uint32_t* inv_offsets,
-                     uint32_t* inv_entries, void* workspace, size_t workspace_bytes, void* stream);
+ * rows when n < k.  order [n]: the splats sorted by the cell of the search
+ * grid (a spatial order; gesr_gsr runs its samples in it).  Inverse lists:
+ * inv_entries[inv_offsets[i] .. inv_offsets[i + 1]) are the entries
+ * e = p * k + s with knn[order[p]][s] = i, in increasing e (inv_offsets
+ * [n + 1], inv_entries [n * k]).  Reads the means of `splats` only.  DEVICE
+ * arrays, 16-byte aligned; the call never synchronises.  GESR_ERR_INVALID for
+ * k outside 1..16, n * k >= 2^32, NULL or misaligned arrays, or a workspace
+ * smaller than gesr_knn_workspace_size. */
+gesr_status gesr_knn(gesr_ctx* ctx, const gesr_splats* splats, int k, uint32_t* knn, uint32_t* order,
+                     uint32_t* inv_offsets, uint32_t* inv_entries, void* workspace, size_t workspace_bytes,
+                     void* stream);
 
 /* Weights of the two regulariser terms (lambda_1, lambda_2 of Eq. 14, which
  * the paper does not give; fold the 1 / |X| of Eq. 12-13 in as well). */
@@ -512,6 +515,7 @@ size_t gesr_gsr_workspace_size(int n, int k, int with_grads);
  *   (d floored at 1e-30, f = 0 where d >= 1);
  *   l_sdf = |fbar - f| (Eq. 12), l_nor = |-sign(h) grad d / |grad d| - n|^2
  *   (Eq. 13; 0 where grad d = 0).
+ * knn, order and the inverse lists are gesr_knn's for the same k.
  * kappa and rho come from `st`.  sample_out [n][4] (DEVICE, nullable):
  * l_sdf, l_nor, g*'s slot in knn[j] (-1 when masked), d.  losses [2] (DEVICE,
  * nullable): the sums of l_sdf and l_nor over the samples, in a fixed order.
@@ -524,7 +528,8 @@ size_t gesr_gsr_workspace_size(int n, int k, int with_grads);
  * NULL or misaligned arrays, k outside 1..16, non-finite weights or a small
  * workspace. */
 gesr_status gesr_gsr(gesr_ctx* ctx, const gesr_splats* splats, const gesr_settings* st, int k, const uint32_t* knn,
-                     const uint32_t* inv_offsets, const uint32_t* inv_entries, const float* xi, const uint8_t* mask,
+                     const uint32_t* order, const uint32_t* inv_offsets, const uint32_t* inv_entries, const float* xi,
+                     const uint8_t* mask,
                      const gesr_gsr_settings* gs, float* sample_out, float* losses, const gesr_grads* grads,
                      void* workspace, size_t workspace_bytes, void* stream);
 

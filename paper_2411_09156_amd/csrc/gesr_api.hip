@@ -927,8 +927,9 @@ size_t gesr_knn_workspace_size(int n, int k) {
     return (size_t)knn_layout(n, k).words * 4 + 256;
 }
 
-gesr_status gesr_knn(gesr_ctx* ctx, const gesr_splats* splats, int k, uint32_t* knn, uint32_t* inv_offsets,
-                     uint32_t* inv_entries, void* workspace, size_t workspace_bytes, void* stream) {
+gesr_status gesr_knn(gesr_ctx* ctx, const gesr_splats* splats, int k, uint32_t* knn, uint32_t* order,
+                     uint32_t* inv_offsets, uint32_t* inv_entries, void* workspace, size_t workspace_bytes,
+                     void* stream) {
     if (!ctx) return GESR_ERR_INVALID;
     if (!splats) return fail(ctx, GESR_ERR_INVALID, "splats is NULL");
     if (splats->n < 0) return fail(ctx, GESR_ERR_INVALID, "splats->n is negative");
@@ -937,7 +938,7 @@ gesr_status gesr_knn(gesr_ctx* ctx, const gesr_splats* splats, int k, uint32_t* 
     if ((uint64_t)n * (uint64_t)k >= (1ull << 32)) return fail(ctx, GESR_ERR_INVALID, "n * k must be < 2^32");
     if (!inv_offsets || !aligned16(inv_offsets)) return fail(ctx, GESR_ERR_INVALID, "inv_offsets NULL or misaligned");
     if (n > 0) {
-        const void* ptrs[3] = {splats->mean, knn, inv_entries};
+        const void* ptrs[4] = {splats->mean, knn, order, inv_entries};
         for (const void* ptr : ptrs)
             if (!ptr || !aligned16(ptr)) return fail(ctx, GESR_ERR_INVALID, "array NULL or not 16-byte aligned");
     }
@@ -947,7 +948,8 @@ gesr_status gesr_knn(gesr_ctx* ctx, const gesr_splats* splats, int k, uint32_t* 
     // 256-byte alignment of the sub-buffers
     uint32_t* ws = (uint32_t*)(((uintptr_t)workspace + 255) & ~(uintptr_t)255);
     GESR_TRY(hip_check(ctx, hipSetDevice(ctx->device), "hipSetDevice"));
-    GESR_TRY(hip_check(ctx, launch_knn(splats->mean, n, k, knn, inv_offsets, inv_entries, ws, (hipStream_t)stream),
+    GESR_TRY(hip_check(ctx, launch_knn(splats->mean, n, k, knn, order, inv_offsets, inv_entries, ws,
+                                       (hipStream_t)stream),
                        "knn launch"));
     ctx->err.clear();
     return GESR_OK;
@@ -957,12 +959,13 @@ size_t gesr_gsr_workspace_size(int n, int k, int with_grads) {
     if (n < 0 || k < 1 || k > GESR_KNN_MAX) return 0;
     const size_t n1 = (size_t)(n > 0 ? n : 1);
     size_t floats = n1 * GSR_FRAME_FLOATS + n1 * 4;
-    if (with_grads) floats += n1 * (size_t)k * GSR_PARTIAL_FLOATS;
+    if (with_grads) floats += n1 * (size_t)k * GSR_PARTIAL_FLOATS + n1 * GSR_PARTIAL_FLOATS + n1;
     return floats * 4 + 256;
 }
 
 gesr_status gesr_gsr(gesr_ctx* ctx, const gesr_splats* splats, const gesr_settings* st, int k, const uint32_t* knn,
-                     const uint32_t* inv_offsets, const uint32_t* inv_entries, const float* xi, const uint8_t* mask,
+                     const uint32_t* order, const uint32_t* inv_offsets, const uint32_t* inv_entries, const float* xi,
+                     const uint8_t* mask,
                      const gesr_gsr_settings* gs, float* sample_out, float* losses, const gesr_grads* grads,
                      void* workspace, size_t workspace_bytes, void* stream) {
     if (!ctx) return GESR_ERR_INVALID;
@@ -974,8 +977,8 @@ gesr_status gesr_gsr(gesr_ctx* ctx, const gesr_splats* splats, const gesr_settin
     const int n = splats->n;
     if ((uint64_t)n * (uint64_t)k >= (1ull << 32)) return fail(ctx, GESR_ERR_INVALID, "n * k must be < 2^32");
     if (n > 0) {
-        const void* ptrs[8] = {splats->mean, splats->scale, splats->quat, splats->opacity, splats->beta, knn,
-                               xi, inv_offsets};
+        const void* ptrs[9] = {splats->mean, splats->scale, splats->quat, splats->opacity, splats->beta, knn,
+                               order, xi, inv_offsets};
         for (const void* ptr : ptrs)
             if (!ptr || !aligned16(ptr)) return fail(ctx, GESR_ERR_INVALID, "array NULL or not 16-byte aligned");
         if (sample_out && !aligned16(sample_out)) return fail(ctx, GESR_ERR_INVALID, "sample_out not 16-byte aligned");
@@ -1001,6 +1004,7 @@ gesr_status gesr_gsr(gesr_ctx* ctx, const gesr_splats* splats, const gesr_settin
     a.opacity = splats->opacity;
     a.beta = splats->beta;
     a.knn = knn;
+    a.order = order;
     a.inv_offsets = inv_offsets;
     a.inv_entries = inv_entries;
     a.xi = xi;
@@ -1012,6 +1016,8 @@ gesr_status gesr_gsr(gesr_ctx* ctx, const gesr_splats* splats, const gesr_settin
     a.frames = ws;
     a.sample_out = sample_out ? sample_out : ws + n1 * GSR_FRAME_FLOATS;
     a.partials = grads ? ws + n1 * GSR_FRAME_FLOATS + n1 * 4 : nullptr;
+    a.staged = grads ? a.partials + n1 * (size_t)k * GSR_PARTIAL_FLOATS : nullptr;
+    a.rank = grads ? reinterpret_cast<uint32_t*>(a.staged + n1 * GSR_PARTIAL_FLOATS) : nullptr;
     a.losses = losses;
     if (grads) {
         a.g_mean = grads->mean;

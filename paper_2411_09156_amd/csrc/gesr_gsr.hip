@@ -4,11 +4,14 @@
 //
 // Neighbour lists (knn[j][0] = j, then the k - 1 nearest other centres by
 // squared distance, ties by index) come from a uniform grid over the centres'
-// bounding box: the centres are radix-sorted by cell, and each query (one
+// bounding box: the centres are radix-sorted by the Morton code of their
+// cell, and each query (one
 // thread, in cell order so that a wave's queries share cells) scans shells of
 // cells around its own until the (k-1)-th distance is below the distance to
-// any unscanned cell.  The inverse lists (for every splat, the (sample, slot)
-// entries that name it) are a stable sort of the list entries by neighbour.
+// any unscanned cell.  The cell order is kept: the regulariser runs its
+// samples in it.  The inverse lists (for every splat, the entries p * k + s,
+// p a position in the cell order, that name it) are a stable sort of the
+// entries by neighbour.
 //
 // The loss runs one sample per splat: x_j = mu_j + R_j diag(phi s_j) xi_j.
 // Pass 1 over the neighbours sums the terms o exp(-kappa q^(beta/2)) of Eq. 9
@@ -103,21 +106,41 @@ __device__ __forceinline__ int cell_coord(float v, float lo, float inv_cs, int G
     return c < 0 ? 0 : (c >= G ? G - 1 : c);
 }
 
+// Morton (Z-order) code of a cell, 8 bits per axis: cells close in space
+// are close in the sort order, which the regulariser's gathers rely on.
+__device__ __forceinline__ uint32_t spread3(uint32_t v) {
+    v &= 0xFFu;
+    v = (v | (v << 8)) & 0x0300F00Fu;
+    v = (v | (v << 4)) & 0x030C30C3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+__device__ __forceinline__ uint32_t compact3(uint32_t v) {
+    v &= 0x09249249u;
+    v = (v | (v >> 2)) & 0x030C30C3u;
+    v = (v | (v >> 4)) & 0x0300F00Fu;
+    v = (v | (v >> 8)) & 0xFFu;
+    return v;
+}
+
 __global__ __launch_bounds__(256) void k_knn_cells(const float* mean, int n, const KnnGrid* g, uint32_t* keys) {
     const uint32_t i = blockIdx.x * 256u + threadIdx.x;
     if (i >= (uint32_t)n) return;
     int c[3];
     for (int a = 0; a < 3; ++a) c[a] = cell_coord(mean[(size_t)a * n + i], g->lo[a], g->inv_cs, g->dim[a]);
-    keys[i] = (uint32_t)c[0] + (uint32_t)g->dim[0] * ((uint32_t)c[1] + (uint32_t)g->dim[1] * (uint32_t)c[2]);
+    keys[i] = spread3((uint32_t)c[0]) | (spread3((uint32_t)c[1]) << 1) | (spread3((uint32_t)c[2]) << 2);
 }
 
-// [start, end) of every cell in the cell-sorted order (cells start empty).
-__global__ __launch_bounds__(256) void k_knn_ranges(const uint32_t* keys, int n, uint32_t* start, uint32_t* end) {
+// [start, end) of every cell (indexed x + X (y + Y z)) in the Morton-sorted
+// order (cells start empty).
+__global__ __launch_bounds__(256) void k_knn_ranges(const uint32_t* keys, int n, const KnnGrid* g, uint32_t* start,
+                                                    uint32_t* end) {
     const uint32_t p = blockIdx.x * 256u + threadIdx.x;
     if (p >= (uint32_t)n) return;
-    const uint32_t c = keys[p];
-    if (p == 0 || keys[p - 1] != c) start[c] = p;
-    if (p + 1 == (uint32_t)n || keys[p + 1] != c) end[c] = p + 1;
+    const uint32_t m = keys[p];
+    const uint32_t c = compact3(m) + (uint32_t)g->dim[0] * (compact3(m >> 1) + (uint32_t)g->dim[1] * compact3(m >> 2));
+    if (p == 0 || keys[p - 1] != m) start[c] = p;
+    if (p + 1 == (uint32_t)n || keys[p + 1] != m) end[c] = p + 1;
 }
 
 // Scans one cell's centres into the sorted candidate list (d2, index) of
@@ -219,11 +242,15 @@ __global__ __launch_bounds__(256) void k_knn_self(int n, uint32_t* knn) {
     if (i < (uint32_t)n) knn[i] = i;
 }
 
-// Inverse-list keys: the neighbour named by each entry, n for padding.
-__global__ __launch_bounds__(256) void k_inv_keys(const uint32_t* knn, uint64_t total, uint32_t n, uint32_t* keys) {
+// Inverse-list keys in sample (cell) order: entry e = p * k + s is slot s of
+// the list of splat order[p]; its key is the neighbour it names, n for padding.
+__global__ __launch_bounds__(256) void k_inv_keys(const uint32_t* knn, const uint32_t* order, uint64_t total,
+                                                  uint32_t k, uint32_t n, uint32_t* keys) {
     const uint64_t e = (uint64_t)blockIdx.x * 256u + threadIdx.x;
     if (e >= total) return;
-    const uint32_t v = knn[e];
+    const uint32_t e32 = (uint32_t)e;  // n * k < 2^32
+    const uint32_t p = e32 / k, s = e32 - p * k;
+    const uint32_t v = knn[(size_t)order[p] * k + s];
     keys[e] = v < n ? v : n;
 }
 
@@ -243,9 +270,11 @@ __global__ __launch_bounds__(256) void k_inv_offsets(const uint32_t* keys, uint6
 
 // ---------------------------------------------------------------- loss
 // Per-splat frame: R (row-major 9), sigma = phi s (3), mu (3), opacity, beta,
-// phi, normalised quaternion (4), 1 / |q|.
+// phi, normalised quaternion (4), 1 / |q|, 1 / sigma (3), 1 / beta, 1 / o:
+// the reciprocals are taken once per splat, so the per-neighbour loops
+// multiply instead of dividing.
 struct GFrame {
-    float R[9], sig[3], mu[3], o, beta, phi, qn[4], inv_q;
+    float R[9], sig[3], mu[3], o, beta, phi, qn[4], inv_q, isig[3], ibeta, io;
 };
 
 __global__ __launch_bounds__(256) void k_gsr_frames(GsrArgs a) {
@@ -259,7 +288,7 @@ __global__ __launch_bounds__(256) void k_gsr_frames(GsrArgs a) {
     const float w = q[0] * inv, x = q[1] * inv, y = q[2] * inv, z = q[3] * inv;
     const float beta = a.beta[i];
     const float phi = 2.0f / (1.0f + expf(-a.rho * (beta - 2.0f)));
-    float f[24];
+    float f[GSR_FRAME_FLOATS];
     f[0] = 1.f - 2.f * (y * y + z * z); f[1] = 2.f * (x * y - w * z); f[2] = 2.f * (x * z + w * y);
     f[3] = 2.f * (x * y + w * z); f[4] = 1.f - 2.f * (x * x + z * z); f[5] = 2.f * (y * z - w * x);
     f[6] = 2.f * (x * z - w * y); f[7] = 2.f * (y * z + w * x); f[8] = 1.f - 2.f * (x * x + y * y);
@@ -272,16 +301,20 @@ __global__ __launch_bounds__(256) void k_gsr_frames(GsrArgs a) {
     f[17] = phi;
     f[18] = w; f[19] = x; f[20] = y; f[21] = z;
     f[22] = inv;
-    f[23] = 0.f;
-    float4* dst = reinterpret_cast<float4*>(a.frames + (size_t)i * 24);
-    for (int c = 0; c < 6; ++c) dst[c] = make_float4(f[4 * c], f[4 * c + 1], f[4 * c + 2], f[4 * c + 3]);
+    for (int c = 0; c < 3; ++c) f[23 + c] = 1.0f / f[9 + c];
+    f[26] = 1.0f / beta;
+    f[27] = f[15] > 0.f ? 1.0f / f[15] : 0.f;
+    for (int c = 28; c < GSR_FRAME_FLOATS; ++c) f[c] = 0.f;
+    float4* dst = reinterpret_cast<float4*>(a.frames + (size_t)i * GSR_FRAME_FLOATS);
+    for (int c = 0; c < GSR_FRAME_FLOATS / 4; ++c)
+        dst[c] = make_float4(f[4 * c], f[4 * c + 1], f[4 * c + 2], f[4 * c + 3]);
 }
 
 __device__ __forceinline__ GFrame load_gframe(const float* frames, uint32_t i) {
-    const float4* s = reinterpret_cast<const float4*>(frames + (size_t)i * 24);
-    float f[24];
+    const float4* s = reinterpret_cast<const float4*>(frames + (size_t)i * GSR_FRAME_FLOATS);
+    float f[28];  // the rest of the line is padding
 #pragma unroll
-    for (int c = 0; c < 6; ++c) {
+    for (int c = 0; c < 7; ++c) {
         const float4 v = s[c];
         f[4 * c] = v.x; f[4 * c + 1] = v.y; f[4 * c + 2] = v.z; f[4 * c + 3] = v.w;
     }
@@ -299,13 +332,17 @@ __device__ __forceinline__ GFrame load_gframe(const float* frames, uint32_t i) {
 #pragma unroll
     for (int c = 0; c < 4; ++c) g.qn[c] = f[18 + c];
     g.inv_q = f[22];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) g.isig[c] = f[23 + c];
+    g.ibeta = f[26];
+    g.io = f[27];
     return g;
 }
 
 // One Eq. 9 term at x: the Mahalanobis vector a = diag(1/sig) R^T (x - mu),
 // q = |a|^2, T = o exp(-kappa q^(beta/2)), c = dT/dq * 2 = -kappa beta q^(beta/2-1) T.
 struct Term {
-    float dx[3], a[3], q, P, T, c, lq;
+    float dx[3], a[3], q, iq, P, T, c, lq;
 };
 
 // x - mu is formed as (mu_0 - mu) + M_0 xi: rounding x itself to float32
@@ -314,14 +351,16 @@ __device__ __forceinline__ Term eval_term(const GFrame& f, const float mu0[3], c
     Term t;
     for (int c = 0; c < 3; ++c) t.dx[c] = (mu0[c] - f.mu[c]) + d0[c];
     for (int k = 0; k < 3; ++k)
-        t.a[k] = (f.R[k] * t.dx[0] + f.R[3 + k] * t.dx[1] + f.R[6 + k] * t.dx[2]) / f.sig[k];
+        t.a[k] = (f.R[k] * t.dx[0] + f.R[3 + k] * t.dx[1] + f.R[6 + k] * t.dx[2]) * f.isig[k];
     t.q = t.a[0] * t.a[0] + t.a[1] * t.a[1] + t.a[2] * t.a[2];
     if (t.q > 0.f) {
+        t.iq = __builtin_amdgcn_rcpf(t.q);
         t.lq = logf(t.q);
         t.P = expf(0.5f * f.beta * t.lq);
         t.T = f.o * expf(-kappa * t.P);
-        t.c = -kappa * f.beta * t.P / t.q * t.T;
+        t.c = -kappa * f.beta * t.P * t.iq * t.T;
     } else {
+        t.iq = 0.f;
         t.lq = 0.f;
         t.P = 0.f;
         t.T = f.o;
@@ -346,12 +385,34 @@ __device__ __forceinline__ void rot_adjoint(const GFrame& f, const float G[9], f
     out[3] = (g[3] - z * dot) * f.inv_q;
 }
 
+// Workgroups are dealt to the eight XCDs round robin; renumber them so that
+// each XCD (with its own L2) takes one contiguous range of the work.
+__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nblocks) {
+    const uint32_t per = (nblocks + 7u) / 8u;
+    const uint32_t xcd = b % 8u, slot = b / 8u;
+    const uint32_t full = nblocks % 8u == 0 ? 8u : nblocks % 8u;  // XCDs that get `per` blocks
+    const uint32_t base = xcd < full ? xcd * per : full * per + (xcd - full) * (per - 1u);
+    return base + slot;
+}
+
+// Samples run in the cell order of the neighbour lists, so that the
+// neighbours a wave (and an XCD's L2) gathers overlap; partials are stored at
+// the sample's position in that order (the inverse lists refer to these
+// positions).  A sample's list is staged in LDS.
 __global__ __launch_bounds__(128) void k_gsr_loss(GsrArgs a) {
-    const uint32_t j = blockIdx.x * 128u + threadIdx.x;
-    if (j >= (uint32_t)a.n) return;
+    __shared__ uint32_t s_nb[GESR_KNN_MAX][128];
+    const uint32_t p = xcd_block(blockIdx.x, gridDim.x) * 128u + threadIdx.x;
+    if (p >= (uint32_t)a.n) return;
+    const uint32_t j = a.order[p];
     const int K = a.k;
-    const uint32_t* nb = a.knn + (size_t)j * K;
-    float* part = a.partials ? a.partials + (size_t)j * K * GSR_PARTIAL_FLOATS : nullptr;
+    {
+        const uint32_t* row = a.knn + (size_t)j * K;
+        for (int s = 0; s < K; ++s) s_nb[s][threadIdx.x] = row[s];
+    }
+    // each thread reads back only its own column: no barrier needed
+    const uint32_t* nbl = &s_nb[0][threadIdx.x];
+#define nb_at(s) nbl[(s) * 128]
+    float* part = a.partials ? a.partials + (size_t)p * K * GSR_PARTIAL_FLOATS : nullptr;
     const bool on = a.mask == nullptr || a.mask[j] != 0;
     if (!on) {
         if (part)
@@ -375,22 +436,28 @@ __global__ __launch_bounds__(128) void k_gsr_loss(GsrArgs a) {
     // pass 1: d, grad d, g*
     float d = 0.f, gd[3] = {0.f, 0.f, 0.f}, best = -1.f;
     int gs = 0;
+    // the next neighbour's frame is loaded while this one is evaluated
+    // (padding slots, n < k, load slot 0's frame and are skipped)
+    GFrame fn = load_gframe(a.frames, j);
     for (int s = 0; s < K; ++s) {
-        const uint32_t i = nb[s];
+        const uint32_t i = nb_at(s);
+        const GFrame f = fn;
+        if (s + 1 < K) {
+            const uint32_t i1 = nb_at(s + 1);
+            fn = load_gframe(a.frames, i1 < (uint32_t)a.n ? i1 : j);
+        }
         if (i >= (uint32_t)a.n) continue;
-        const GFrame f = load_gframe(a.frames, i);
         const Term t = eval_term(f, f0.mu, d0, kappa);
         d += t.T;
-        for (int r = 0; r < 3; ++r)
-            gd[r] += t.c * (f.R[3 * r] * t.a[0] / f.sig[0] + f.R[3 * r + 1] * t.a[1] / f.sig[1] +
-                            f.R[3 * r + 2] * t.a[2] / f.sig[2]);
+        const float as[3] = {t.a[0] * f.isig[0], t.a[1] * f.isig[1], t.a[2] * f.isig[2]};
+        for (int r = 0; r < 3; ++r) gd[r] += t.c * (f.R[3 * r] * as[0] + f.R[3 * r + 1] * as[1] + f.R[3 * r + 2] * as[2]);
         if (t.T > best) {
             best = t.T;
             gs = s;
         }
     }
     // SDF terms of g* (Eq. 10-13)
-    const GFrame fg = load_gframe(a.frames, nb[gs]);
+    const GFrame fg = load_gframe(a.frames, nb_at(gs));
     int ks = 0;
     if (fg.sig[1] < fg.sig[ks]) ks = 1;
     if (fg.sig[2] < fg.sig[ks]) ks = 2;
@@ -457,27 +524,35 @@ __global__ __launch_bounds__(128) void k_gsr_loss(GsrArgs a) {
     float gx[3] = {L_h * nrm[0], L_h * nrm[1], L_h * nrm[2]};  // dl / dx
 
     // pass 2, slot 0 last (it also carries the sample point's dependence)
+    {
+        const uint32_t il = nb_at(K - 1);
+        fn = load_gframe(a.frames, il < (uint32_t)a.n ? il : j);
+    }
     for (int s = K - 1; s >= 0; --s) {
         float* ps = part + (size_t)s * GSR_PARTIAL_FLOATS;
-        const uint32_t i = nb[s];
+        const uint32_t i = nb_at(s);
+        const GFrame f = fn;
+        if (s > 0) {
+            const uint32_t i1 = nb_at(s - 1);
+            fn = load_gframe(a.frames, i1 < (uint32_t)a.n ? i1 : j);
+        }
         if (i >= (uint32_t)a.n) {
             for (int c = 0; c < GSR_PARTIAL_FLOATS / 4; ++c)
                 reinterpret_cast<float4*>(ps)[c] = make_float4(0.f, 0.f, 0.f, 0.f);
             continue;
         }
-        const GFrame f = load_gframe(a.frames, i);
         const Term t = eval_term(f, f0.mu, d0, kappa);
         // b = diag(1/sig) R^T u, scaled by gmax like u
         float b[3];
-        for (int k = 0; k < 3; ++k) b[k] = (f.R[k] * u[0] + f.R[3 + k] * u[1] + f.R[6 + k] * u[2]) / f.sig[k];
+        for (int k = 0; k < 3; ++k) b[k] = (f.R[k] * u[0] + f.R[3 + k] * u[1] + f.R[6 + k] * u[2]) * f.isig[k];
         const float ab = t.a[0] * b[0] + t.a[1] * b[1] + t.a[2] * b[2];
         // S = L_d T + c (a . b); cg = c / gmax pairs with the scaled b
         const float cg = t.c * inv_gmax;
         float dcdq = 0.f, dTdb = 0.f, dcdb = 0.f;
         if (t.q > 0.f) {
-            dcdq = (0.5f * f.beta - 1.f) / t.q - kappa * 0.5f * f.beta * t.P / t.q;  // (dc/dq) / c
+            dcdq = ((0.5f * f.beta - 1.f) - kappa * 0.5f * f.beta * t.P) * t.iq;  // (dc/dq) / c
             dTdb = -0.5f * kappa * t.P * t.lq * t.T;
-            dcdb = 1.f / f.beta + 0.5f * t.lq - 0.5f * kappa * t.P * t.lq;           // (dc/dbeta) / c
+            dcdb = f.ibeta + 0.5f * t.lq - 0.5f * kappa * t.P * t.lq;           // (dc/dbeta) / c
         }
         float dSa[3], dSb[3];
         for (int k = 0; k < 3; ++k) {
@@ -485,16 +560,20 @@ __global__ __launch_bounds__(128) void k_gsr_loss(GsrArgs a) {
             dSb[k] = cg * t.a[k];
         }
         float g_mu[3], g_sig[3], G[9];
+        float sa[3], sb[3];
+        for (int k = 0; k < 3; ++k) {
+            sa[k] = dSa[k] * f.isig[k];
+            sb[k] = dSb[k] * f.isig[k];
+        }
         for (int r2 = 0; r2 < 3; ++r2) {
-            const float v = f.R[3 * r2] * dSa[0] / f.sig[0] + f.R[3 * r2 + 1] * dSa[1] / f.sig[1] +
-                            f.R[3 * r2 + 2] * dSa[2] / f.sig[2];
+            const float v = f.R[3 * r2] * sa[0] + f.R[3 * r2 + 1] * sa[1] + f.R[3 * r2 + 2] * sa[2];
             gx[r2] += v;
             g_mu[r2] = -v;
         }
-        for (int k = 0; k < 3; ++k) g_sig[k] = -(t.a[k] * dSa[k] + b[k] * dSb[k]) / f.sig[k];
+        for (int k = 0; k < 3; ++k) g_sig[k] = -(t.a[k] * sa[k] + b[k] * sb[k]);
         for (int r2 = 0; r2 < 3; ++r2)
-            for (int k = 0; k < 3; ++k) G[3 * r2 + k] = (dSa[k] * t.dx[r2] + dSb[k] * u[r2]) / f.sig[k];
-        float g_o = f.o > 0.f ? (L_d * t.T + cg * ab) / f.o : 0.f;
+            for (int k = 0; k < 3; ++k) G[3 * r2 + k] = sa[k] * t.dx[r2] + sb[k] * u[r2];
+        float g_o = (L_d * t.T + cg * ab) * f.io;
         float g_beta = L_d * dTdb + ab * cg * dcdb;
         if (s == gs) {
             for (int c = 0; c < 3; ++c) {
@@ -523,30 +602,70 @@ __global__ __launch_bounds__(128) void k_gsr_loss(GsrArgs a) {
         o4[2] = make_float4(g_q[2], g_q[3], g_o, g_beta);
     }
 }
+#undef nb_at
 
-// Adds each splat's partials, in inverse-list order, into the gradients.
+// Gradient of each splat: the sum of its partials in inverse-list order.
+// Splats run in the cell order: a splat's entries come from its spatial
+// neighbours, whose partials sit near its own position in that order.  The
+// sums go to a staging row at that position; k_gsr_apply adds them into the
+// gradients in index order, so both the partial reads and the gradient
+// updates stay coalesced.
 __global__ __launch_bounds__(256) void k_gsr_gather(GsrArgs a) {
-    const uint32_t i = blockIdx.x * 256u + threadIdx.x;
-    if (i >= (uint32_t)a.n) return;
+    const uint32_t q = xcd_block(blockIdx.x, gridDim.x) * 256u + threadIdx.x;
+    if (q >= (uint32_t)a.n) return;
+    const uint32_t i = a.order[q];
+    a.rank[i] = q;
     float acc[GSR_PARTIAL_FLOATS];
 #pragma unroll
     for (int c = 0; c < GSR_PARTIAL_FLOATS; ++c) acc[c] = 0.f;
     const uint32_t e0 = a.inv_offsets[i], e1 = a.inv_offsets[i + 1];
-    for (uint32_t e = e0; e < e1; ++e) {
-        const float4* p = reinterpret_cast<const float4*>(a.partials + (size_t)a.inv_entries[e] * GSR_PARTIAL_FLOATS);
-        const float4 v0 = p[0], v1 = p[1], v2 = p[2];
-        acc[0] += v0.x; acc[1] += v0.y; acc[2] += v0.z; acc[3] += v0.w;
-        acc[4] += v1.x; acc[5] += v1.y; acc[6] += v1.z; acc[7] += v1.w;
-        acc[8] += v2.x; acc[9] += v2.y; acc[10] += v2.z; acc[11] += v2.w;
+    // four entries per step: their loads are independent and overlap; the
+    // sums still run in entry order
+    for (uint32_t e = e0; e < e1; e += 4) {
+        float4 v[4][3];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            if (e + t < e1) {
+                const float4* p =
+                    reinterpret_cast<const float4*>(a.partials + (size_t)a.inv_entries[e + t] * GSR_PARTIAL_FLOATS);
+                v[t][0] = p[0];
+                v[t][1] = p[1];
+                v[t][2] = p[2];
+            } else {
+                v[t][0] = v[t][1] = v[t][2] = make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            acc[0] += v[t][0].x; acc[1] += v[t][0].y; acc[2] += v[t][0].z; acc[3] += v[t][0].w;
+            acc[4] += v[t][1].x; acc[5] += v[t][1].y; acc[6] += v[t][1].z; acc[7] += v[t][1].w;
+            acc[8] += v[t][2].x; acc[9] += v[t][2].y; acc[10] += v[t][2].z; acc[11] += v[t][2].w;
+        }
     }
+    float4* st = reinterpret_cast<float4*>(a.staged + (size_t)q * GSR_PARTIAL_FLOATS);
+    st[0] = make_float4(acc[0], acc[1], acc[2], acc[3]);
+    st[1] = make_float4(acc[4], acc[5], acc[6], acc[7]);
+    st[2] = make_float4(acc[8], acc[9], acc[10], acc[11]);
+}
+
+__global__ __launch_bounds__(256) void k_gsr_apply(GsrArgs a) {
+    const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+    if (i >= (uint32_t)a.n) return;
+    const float4* p = reinterpret_cast<const float4*>(a.staged + (size_t)a.rank[i] * GSR_PARTIAL_FLOATS);
+    const float4 v0 = p[0], v1 = p[1], v2 = p[2];
     const size_t n = (size_t)a.n;
-    for (int c = 0; c < 3; ++c) {
-        a.g_mean[c * n + i] += acc[c];
-        a.g_scale[c * n + i] += acc[3 + c];
-    }
-    for (int c = 0; c < 4; ++c) a.g_quat[c * n + i] += acc[6 + c];
-    a.g_opacity[i] += acc[10];
-    a.g_beta[i] += acc[11];
+    a.g_mean[i] += v0.x;
+    a.g_mean[n + i] += v0.y;
+    a.g_mean[2 * n + i] += v0.z;
+    a.g_scale[i] += v0.w;
+    a.g_scale[n + i] += v1.x;
+    a.g_scale[2 * n + i] += v1.y;
+    a.g_quat[i] += v1.z;
+    a.g_quat[n + i] += v1.w;
+    a.g_quat[2 * n + i] += v2.x;
+    a.g_quat[3 * n + i] += v2.y;
+    a.g_opacity[i] += v2.z;
+    a.g_beta[i] += v2.w;
 }
 
 // Sums of the per-sample losses in a fixed order (one workgroup).
@@ -612,8 +731,8 @@ static int bits_for(uint64_t v) {
     return b;
 }
 
-hipError_t launch_knn(const float* mean, int n, int k, uint32_t* knn, uint32_t* inv_offsets, uint32_t* inv_entries,
-                      uint32_t* ws, hipStream_t stream) {
+hipError_t launch_knn(const float* mean, int n, int k, uint32_t* knn, uint32_t* order_out, uint32_t* inv_offsets,
+                      uint32_t* inv_entries, uint32_t* ws, hipStream_t stream) {
     if (n == 0) return launch_fill_u32(inv_offsets, 0u, 1, stream);
     const KnnLayout L = knn_layout(n, k);
     KnnGrid* grid = reinterpret_cast<KnnGrid*>(ws + L.o_grid);
@@ -621,17 +740,20 @@ hipError_t launch_knn(const float* mean, int n, int k, uint32_t* knn, uint32_t* 
     hipLaunchKernelGGL(k_knn_bounds, dim3(L.bound_parts), dim3(256), 0, stream, mean, n, parts);
     hipLaunchKernelGGL(k_knn_grid, dim3(1), dim3(64), 0, stream, parts, (int)L.bound_parts, n, L.cell_cap, grid);
     hipLaunchKernelGGL(k_knn_cells, dim3(blocks(n, 256)), dim3(256), 0, stream, mean, n, grid, ws + L.o_keys);
-    SortBuffers sb{ws + L.o_ka, ws + L.o_va, ws + L.o_kb, ws + L.o_vb, ws + L.o_hist, ws + L.o_scan};
+    // three 8-bit passes over the 24-bit Morton keys end in the "a" buffers:
+    // the sorted values land in order_out
+    SortBuffers sb{ws + L.o_ka, order_out, ws + L.o_kb, ws + L.o_vb, ws + L.o_hist, ws + L.o_scan};
     bool in_b = false;
     hipError_t e = radix_sort(ws + L.o_keys, nullptr, (uint64_t)n, nullptr, 24, 8, sb, &in_b, stream);
     if (e != hipSuccess) return e;
-    const uint32_t* skeys = in_b ? sb.keys_b : sb.keys_a;
-    const uint32_t* order = in_b ? sb.vals_b : sb.vals_a;
+    if (in_b) return hipErrorInvalidValue;  // not reached with an odd number of passes
+    const uint32_t* skeys = sb.keys_a;
+    const uint32_t* order = order_out;
     e = launch_fill_u32(ws + L.o_start, 0u, L.cell_cap, stream);
     if (e != hipSuccess) return e;
     e = launch_fill_u32(ws + L.o_end, 0u, L.cell_cap, stream);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_knn_ranges, dim3(blocks(n, 256)), dim3(256), 0, stream, skeys, n, ws + L.o_start,
+    hipLaunchKernelGGL(k_knn_ranges, dim3(blocks(n, 256)), dim3(256), 0, stream, skeys, n, grid, ws + L.o_start,
                        ws + L.o_end);
     const dim3 qg(blocks(n, 256)), qb(256);
     const uint32_t *cs0 = ws + L.o_start, *ce0 = ws + L.o_end;
@@ -646,8 +768,8 @@ hipError_t launch_knn(const float* mean, int n, int k, uint32_t* knn, uint32_t* 
     }
     // inverse lists: stable sort of the entries by the neighbour they name
     const uint64_t total = (uint64_t)n * k;
-    hipLaunchKernelGGL(k_inv_keys, dim3(blocks(total, 256)), dim3(256), 0, stream, knn, total, (uint32_t)n,
-                       ws + L.o_keys);
+    hipLaunchKernelGGL(k_inv_keys, dim3(blocks(total, 256)), dim3(256), 0, stream, knn, order, total, (uint32_t)k,
+                       (uint32_t)n, ws + L.o_keys);
     SortBuffers ib{ws + L.o_ka, inv_entries, ws + L.o_kb, ws + L.o_vb, ws + L.o_hist, ws + L.o_scan};
     // an even number of passes leaves the result in (keys_b, vals_b): route the
     // values so that they end in inv_entries
@@ -668,7 +790,10 @@ hipError_t launch_gsr(GsrArgs a, hipStream_t stream) {
     }
     hipLaunchKernelGGL(k_gsr_frames, dim3(blocks(a.n, 256)), dim3(256), 0, stream, a);
     hipLaunchKernelGGL(k_gsr_loss, dim3(blocks(a.n, 128)), dim3(128), 0, stream, a);
-    if (a.partials) hipLaunchKernelGGL(k_gsr_gather, dim3(blocks(a.n, 256)), dim3(256), 0, stream, a);
+    if (a.partials) {
+        hipLaunchKernelGGL(k_gsr_gather, dim3(blocks(a.n, 256)), dim3(256), 0, stream, a);
+        hipLaunchKernelGGL(k_gsr_apply, dim3(blocks(a.n, 256)), dim3(256), 0, stream, a);
+    }
     if (a.losses) hipLaunchKernelGGL(k_gsr_sum, dim3(1), dim3(1024), 0, stream, a.sample_out, a.n, a.losses);
     return hipGetLastError();
 }

@@ -229,22 +229,25 @@ struct KnnLayout {
     uint64_t o_grid, o_parts, o_keys, o_ka, o_va, o_kb, o_vb, o_hist, o_scan, o_start, o_end, words;
 };
 KnnLayout knn_layout(int n, int k);
-hipError_t launch_knn(const float* mean, int n, int k, uint32_t* knn, uint32_t* inv_offsets, uint32_t* inv_entries,
-                      uint32_t* ws, hipStream_t stream);
+hipError_t launch_knn(const float* mean, int n, int k, uint32_t* knn, uint32_t* order_out, uint32_t* inv_offsets,
+                      uint32_t* inv_entries, uint32_t* ws, hipStream_t stream);
 
 constexpr int GSR_PARTIAL_FLOATS = 12;  // mean 3, scale 3, quaternion 4, opacity, beta
-constexpr int GSR_FRAME_FLOATS = 24;
+constexpr int GSR_FRAME_FLOATS = 32;  // one 128-byte line per splat
 struct GsrArgs {
     int n, k;
     const float *mean, *scale, *quat, *opacity, *beta;
     const uint32_t* knn;
+    const uint32_t* order;  // samples in cell order
     const uint32_t* inv_offsets;
     const uint32_t* inv_entries;
     const float* xi;        // [3][n]
     const uint8_t* mask;    // nullable
     float kappa, rho, w_sdf, w_nor;
-    float* frames;          // [n][24]
-    float* partials;        // [n][k][12], null: no gradients
+    float* frames;          // [n][GSR_FRAME_FLOATS]
+    float* partials;        // [n][k][12] by position in `order`, null: no gradients
+    float* staged;          // [n][12] per-splat sums by position in `order`
+    uint32_t* rank;         // [n] position of each splat in `order`
     float* sample_out;      // [n][4]: l_sdf, l_nor, g* slot (-1 when masked), d
     float* losses;          // nullable: sums of l_sdf and l_nor
     float *g_mean, *g_scale, *g_quat, *g_opacity, *g_beta;

@@ -5,7 +5,8 @@ Neighbour lists: the GPU ranks by float32 squared distance, the oracle by
 float64; a row may differ only where the neighbours it swaps lie within the
 float32 error band of each other's distance (relative 1e-5), and the lists
 must agree as sets of float64 distances within that band.  The inverse lists
-are checked exactly against a stable sort of the GPU's own lists.
+are checked exactly against a stable sort of the GPU's own lists taken in its
+cell order (a permutation of the splats).
 
 Losses and gradients: the oracle gets the GPU's lists and the same xi.
 Samples whose oracle decision margins lie inside the float32 band are masked
@@ -102,8 +103,10 @@ def test_knn_matches_oracle(kind, n, k):
     got = nb["knn"].cpu().numpy().astype(np.int64)  # padding 0xFFFFFFFF reads as -1
     want = oracle.knn(sc.means.astype(np.float64), k).astype(np.int64)
     differ = _check_knn(sc.means, got, want, k)
-    # inverse lists: a stable sort of the GPU's own entries by neighbour
-    flat = got.reshape(-1)
+    # inverse lists: a stable sort of the GPU's own entries, in cell order, by neighbour
+    order_g = nb["order"].cpu().numpy().astype(np.int64)
+    np.testing.assert_array_equal(np.sort(order_g), np.arange(n))
+    flat = got[order_g].reshape(-1)
     valid = flat >= 0
     order = np.argsort(np.where(valid, flat, n), kind="stable")[:int(valid.sum())]
     offs = nb["inv_offsets"].cpu().numpy().astype(np.int64)
