@@ -958,8 +958,9 @@ gesr_status gesr_knn(gesr_ctx* ctx, const gesr_splats* splats, int k, uint32_t* 
 size_t gesr_gsr_workspace_size(int n, int k, int with_grads) {
     if (n < 0 || k < 1 || k > GESR_KNN_MAX) return 0;
     const size_t n1 = (size_t)(n > 0 ? n : 1);
-    size_t floats = n1 * GSR_FRAME_FLOATS + n1 * 4;
-    if (with_grads) floats += n1 * (size_t)k * GSR_PARTIAL_FLOATS + n1 * GSR_PARTIAL_FLOATS + n1;
+    const size_t nparts = (n1 + GSR_SUM_BLOCK - 1) / GSR_SUM_BLOCK;
+    size_t floats = n1 * GSR_FRAME_FLOATS + n1 * 4 + ((2 * nparts + 63) & ~(size_t)63);
+    if (with_grads) floats += n1 * (size_t)k * GSR_PARTIAL_STRIDE + n1 * GSR_PARTIAL_FLOATS + n1;
     return floats * 4 + 256;
 }
 
@@ -1015,8 +1016,10 @@ gesr_status gesr_gsr(gesr_ctx* ctx, const gesr_splats* splats, const gesr_settin
     a.w_nor = gs->w_nor;
     a.frames = ws;
     a.sample_out = sample_out ? sample_out : ws + n1 * GSR_FRAME_FLOATS;
-    a.partials = grads ? ws + n1 * GSR_FRAME_FLOATS + n1 * 4 : nullptr;
-    a.staged = grads ? a.partials + n1 * (size_t)k * GSR_PARTIAL_FLOATS : nullptr;
+    const size_t nparts = (n1 + GSR_SUM_BLOCK - 1) / GSR_SUM_BLOCK;
+    a.sum_parts = ws + n1 * GSR_FRAME_FLOATS + n1 * 4;
+    a.partials = grads ? a.sum_parts + ((2 * nparts + 63) & ~(size_t)63) : nullptr;
+    a.staged = grads ? a.partials + n1 * (size_t)k * GSR_PARTIAL_STRIDE : nullptr;
     a.rank = grads ? reinterpret_cast<uint32_t*>(a.staged + n1 * GSR_PARTIAL_FLOATS) : nullptr;
     a.losses = losses;
     if (grads) {

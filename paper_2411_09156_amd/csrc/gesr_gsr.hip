@@ -412,11 +412,11 @@ __global__ __launch_bounds__(128) void k_gsr_loss(GsrArgs a) {
     // each thread reads back only its own column: no barrier needed
     const uint32_t* nbl = &s_nb[0][threadIdx.x];
 #define nb_at(s) nbl[(s) * 128]
-    float* part = a.partials ? a.partials + (size_t)p * K * GSR_PARTIAL_FLOATS : nullptr;
+    float* part = a.partials ? a.partials + (size_t)p * K * GSR_PARTIAL_STRIDE : nullptr;
     const bool on = a.mask == nullptr || a.mask[j] != 0;
     if (!on) {
         if (part)
-            for (int s = 0; s < K * GSR_PARTIAL_FLOATS / 4; ++s)
+            for (int s = 0; s < K * GSR_PARTIAL_STRIDE / 4; ++s)
                 reinterpret_cast<float4*>(part)[s] = make_float4(0.f, 0.f, 0.f, 0.f);
         a.sample_out[(size_t)j * 4 + 0] = 0.f;
         a.sample_out[(size_t)j * 4 + 1] = 0.f;
@@ -529,7 +529,7 @@ __global__ __launch_bounds__(128) void k_gsr_loss(GsrArgs a) {
         fn = load_gframe(a.frames, il < (uint32_t)a.n ? il : j);
     }
     for (int s = K - 1; s >= 0; --s) {
-        float* ps = part + (size_t)s * GSR_PARTIAL_FLOATS;
+        float* ps = part + (size_t)s * GSR_PARTIAL_STRIDE;
         const uint32_t i = nb_at(s);
         const GFrame f = fn;
         if (s > 0) {
@@ -627,7 +627,7 @@ __global__ __launch_bounds__(256) void k_gsr_gather(GsrArgs a) {
         for (int t = 0; t < 4; ++t) {
             if (e + t < e1) {
                 const float4* p =
-                    reinterpret_cast<const float4*>(a.partials + (size_t)a.inv_entries[e + t] * GSR_PARTIAL_FLOATS);
+                    reinterpret_cast<const float4*>(a.partials + (size_t)a.inv_entries[e + t] * GSR_PARTIAL_STRIDE);
                 v[t][0] = p[0];
                 v[t][1] = p[1];
                 v[t][2] = p[2];
@@ -668,13 +668,42 @@ __global__ __launch_bounds__(256) void k_gsr_apply(GsrArgs a) {
     a.g_beta[i] += v2.w;
 }
 
-// Sums of the per-sample losses in a fixed order (one workgroup).
-__global__ __launch_bounds__(1024) void k_gsr_sum(const float* sample_out, int n, float* losses) {
+// Sums of the per-sample losses in a fixed order: each block adds
+// GSR_SUM_BLOCK samples by a fixed tree, then one block adds the block sums.
+__global__ __launch_bounds__(256) void k_gsr_sum_blocks(const float* sample_out, int n, float* parts) {
+    __shared__ float s0[256], s1[256];
+    const uint32_t base = blockIdx.x * (uint32_t)GSR_SUM_BLOCK;
+    float a0 = 0.f, a1 = 0.f;
+    for (uint32_t t = threadIdx.x; t < (uint32_t)GSR_SUM_BLOCK; t += 256u) {
+        const uint32_t j = base + t;
+        if (j < (uint32_t)n) {
+            const float2 v = *reinterpret_cast<const float2*>(sample_out + (size_t)j * 4);
+            a0 += v.x;
+            a1 += v.y;
+        }
+    }
+    s0[threadIdx.x] = a0;
+    s1[threadIdx.x] = a1;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < (unsigned)w) {
+            s0[threadIdx.x] += s0[threadIdx.x + w];
+            s1[threadIdx.x] += s1[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        parts[2 * blockIdx.x] = s0[0];
+        parts[2 * blockIdx.x + 1] = s1[0];
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_gsr_sum(const float* parts, int nparts, float* losses) {
     __shared__ float s0[1024], s1[1024];
     float a0 = 0.f, a1 = 0.f;
-    for (int j = threadIdx.x; j < n; j += 1024) {
-        a0 += sample_out[(size_t)j * 4];
-        a1 += sample_out[(size_t)j * 4 + 1];
+    for (int b = threadIdx.x; b < nparts; b += 1024) {
+        a0 += parts[2 * b];
+        a1 += parts[2 * b + 1];
     }
     s0[threadIdx.x] = a0;
     s1[threadIdx.x] = a1;
@@ -794,7 +823,11 @@ hipError_t launch_gsr(GsrArgs a, hipStream_t stream) {
         hipLaunchKernelGGL(k_gsr_gather, dim3(blocks(a.n, 256)), dim3(256), 0, stream, a);
         hipLaunchKernelGGL(k_gsr_apply, dim3(blocks(a.n, 256)), dim3(256), 0, stream, a);
     }
-    if (a.losses) hipLaunchKernelGGL(k_gsr_sum, dim3(1), dim3(1024), 0, stream, a.sample_out, a.n, a.losses);
+    if (a.losses) {
+        const unsigned nparts = blocks(a.n, GSR_SUM_BLOCK);
+        hipLaunchKernelGGL(k_gsr_sum_blocks, dim3(nparts), dim3(256), 0, stream, a.sample_out, a.n, a.sum_parts);
+        hipLaunchKernelGGL(k_gsr_sum, dim3(1), dim3(1024), 0, stream, a.sum_parts, (int)nparts, a.losses);
+    }
     return hipGetLastError();
 }
 

@@ -233,6 +233,8 @@ hipError_t launch_knn(const float* mean, int n, int k, uint32_t* knn, uint32_t* 
                       uint32_t* inv_entries, uint32_t* ws, hipStream_t stream);
 
 constexpr int GSR_PARTIAL_FLOATS = 12;  // mean 3, scale 3, quaternion 4, opacity, beta
+constexpr int GSR_PARTIAL_STRIDE = 16;  // one aligned 64-byte record per (sample, slot)
+constexpr int GSR_SUM_BLOCK = 4096;     // samples per first-level loss-sum block
 constexpr int GSR_FRAME_FLOATS = 32;  // one 128-byte line per splat
 struct GsrArgs {
     int n, k;
@@ -245,11 +247,12 @@ struct GsrArgs {
     const uint8_t* mask;    // nullable
     float kappa, rho, w_sdf, w_nor;
     float* frames;          // [n][GSR_FRAME_FLOATS]
-    float* partials;        // [n][k][12] by position in `order`, null: no gradients
+    float* partials;        // [n][k][16] by position in `order`, null: no gradients
     float* staged;          // [n][12] per-splat sums by position in `order`
     uint32_t* rank;         // [n] position of each splat in `order`
     float* sample_out;      // [n][4]: l_sdf, l_nor, g* slot (-1 when masked), d
     float* losses;          // nullable: sums of l_sdf and l_nor
+    float* sum_parts;       // [ceil(n / GSR_SUM_BLOCK)][2] first-level sums
     float *g_mean, *g_scale, *g_quat, *g_opacity, *g_beta;
 };
 hipError_t launch_gsr(GsrArgs a, hipStream_t stream);
