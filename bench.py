@@ -530,11 +530,11 @@ def gsr_leg(args, scene, sp, rs):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / args.steps
     losses = out["losses"].cpu().numpy().astype(np.float64) / n
-    # algorithmic HBM bytes per splat: frames (48 B of parameters read, 96 B
-    # written), the loss pass (own frame 96, xi 12, list 64, partials 16 x 48
+    # algorithmic HBM bytes per splat: frames (48 B of parameters read, 64 B
+    # written), the loss pass (own frame 64, xi 12, list 64, partials 16 x 48
     # written, per-sample results 16), the gather (inverse list 68, partials
     # 768, gradients 48 read + 48 written) and the loss sum (16)
-    per_splat = 48 + 96 + (96 + 12 + 64 + 768 + 16) + (68 + 768 + 96) + 16
+    per_splat = 48 + 64 + (64 + 12 + 64 + 768 + 16) + (68 + 768 + 96) + 16
     ach = per_splat * n / (ms * 1e-3)
     log(f"[bench] gsr: knn {knn_ms:.3f} ms, losses + gradients {ms:.3f} ms, L_sdf {losses[0]:.4g} L_nor {losses[1]:.4g}")
     return {"splats": n, "neighbours": 16, "knn_ms": round(knn_ms, 4), "ms": round(ms, 4),

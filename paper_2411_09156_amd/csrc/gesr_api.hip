@@ -959,7 +959,8 @@ size_t gesr_gsr_workspace_size(int n, int k, int with_grads) {
     if (n < 0 || k < 1 || k > GESR_KNN_MAX) return 0;
     const size_t n1 = (size_t)(n > 0 ? n : 1);
     const size_t nparts = (n1 + GSR_SUM_BLOCK - 1) / GSR_SUM_BLOCK;
-    size_t floats = n1 * GSR_FRAME_FLOATS + n1 * 4 + ((2 * nparts + 63) & ~(size_t)63);
+    // frames, per-sample results and loss partials, rounded to 256 bytes
+    size_t floats = (n1 * GSR_FRAME_FLOATS + n1 * 4 + 2 * nparts + 63) & ~(size_t)63;
     if (with_grads) floats += n1 * (size_t)k * GSR_PARTIAL_STRIDE + n1 * GSR_PARTIAL_FLOATS + n1;
     return floats * 4 + 256;
 }
@@ -1018,7 +1019,8 @@ gesr_status gesr_gsr(gesr_ctx* ctx, const gesr_splats* splats, const gesr_settin
     a.sample_out = sample_out ? sample_out : ws + n1 * GSR_FRAME_FLOATS;
     const size_t nparts = (n1 + GSR_SUM_BLOCK - 1) / GSR_SUM_BLOCK;
     a.sum_parts = ws + n1 * GSR_FRAME_FLOATS + n1 * 4;
-    a.partials = grads ? a.sum_parts + ((2 * nparts + 63) & ~(size_t)63) : nullptr;
+    // partial records start 256-byte aligned
+    a.partials = grads ? ws + ((n1 * GSR_FRAME_FLOATS + n1 * 4 + 2 * nparts + 63) & ~(size_t)63) : nullptr;
     a.staged = grads ? a.partials + n1 * (size_t)k * GSR_PARTIAL_STRIDE : nullptr;
     a.rank = grads ? reinterpret_cast<uint32_t*>(a.staged + n1 * GSR_PARTIAL_FLOATS) : nullptr;
     a.losses = losses;

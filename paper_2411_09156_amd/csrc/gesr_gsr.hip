@@ -269,10 +269,10 @@ __global__ __launch_bounds__(256) void k_inv_offsets(const uint32_t* keys, uint6
 }
 
 // ---------------------------------------------------------------- loss
-// Per-splat frame: R (row-major 9), sigma = phi s (3), mu (3), opacity, beta,
-// phi, normalised quaternion (4), 1 / |q|, 1 / sigma (3), 1 / beta, 1 / o:
-// the reciprocals are taken once per splat, so the per-neighbour loops
-// multiply instead of dividing.
+// Per-splat frame, one 64-byte record: normalised quaternion (4), mu (3),
+// opacity, 1 / sigma (3) with sigma = phi s, beta, sigma (3), 1 / |q|.  The
+// rotation, phi, 1 / beta and 1 / o are rebuilt from it where they are used,
+// which halves the frames the regulariser gathers per neighbour.
 struct GFrame {
     float R[9], sig[3], mu[3], o, beta, phi, qn[4], inv_q, isig[3], ibeta, io;
 };
@@ -285,57 +285,51 @@ __global__ __launch_bounds__(256) void k_gsr_frames(GsrArgs a) {
     for (int c = 0; c < 4; ++c) q[c] = a.quat[c * n + i];
     const float qq = q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
     const float inv = 1.0f / sqrtf(qq);
-    const float w = q[0] * inv, x = q[1] * inv, y = q[2] * inv, z = q[3] * inv;
     const float beta = a.beta[i];
     const float phi = 2.0f / (1.0f + expf(-a.rho * (beta - 2.0f)));
     float f[GSR_FRAME_FLOATS];
-    f[0] = 1.f - 2.f * (y * y + z * z); f[1] = 2.f * (x * y - w * z); f[2] = 2.f * (x * z + w * y);
-    f[3] = 2.f * (x * y + w * z); f[4] = 1.f - 2.f * (x * x + z * z); f[5] = 2.f * (y * z - w * x);
-    f[6] = 2.f * (x * z - w * y); f[7] = 2.f * (y * z + w * x); f[8] = 1.f - 2.f * (x * x + y * y);
+    for (int c = 0; c < 4; ++c) f[c] = q[c] * inv;
     for (int c = 0; c < 3; ++c) {
-        f[9 + c] = phi * a.scale[c * n + i];
-        f[12 + c] = a.mean[c * n + i];
+        f[4 + c] = a.mean[c * n + i];
+        const float sg = phi * a.scale[c * n + i];
+        f[8 + c] = 1.0f / sg;
+        f[12 + c] = sg;
     }
-    f[15] = a.opacity[i];
-    f[16] = beta;
-    f[17] = phi;
-    f[18] = w; f[19] = x; f[20] = y; f[21] = z;
-    f[22] = inv;
-    for (int c = 0; c < 3; ++c) f[23 + c] = 1.0f / f[9 + c];
-    f[26] = 1.0f / beta;
-    f[27] = f[15] > 0.f ? 1.0f / f[15] : 0.f;
-    for (int c = 28; c < GSR_FRAME_FLOATS; ++c) f[c] = 0.f;
+    f[7] = a.opacity[i];
+    f[11] = beta;
+    f[15] = inv;
     float4* dst = reinterpret_cast<float4*>(a.frames + (size_t)i * GSR_FRAME_FLOATS);
     for (int c = 0; c < GSR_FRAME_FLOATS / 4; ++c)
         dst[c] = make_float4(f[4 * c], f[4 * c + 1], f[4 * c + 2], f[4 * c + 3]);
 }
 
-__device__ __forceinline__ GFrame load_gframe(const float* frames, uint32_t i) {
+__device__ __forceinline__ GFrame load_gframe(const float* frames, uint32_t i, float rho) {
     const float4* s = reinterpret_cast<const float4*>(frames + (size_t)i * GSR_FRAME_FLOATS);
-    float f[28];  // the rest of the line is padding
+    float f[GSR_FRAME_FLOATS];
 #pragma unroll
-    for (int c = 0; c < 7; ++c) {
+    for (int c = 0; c < GSR_FRAME_FLOATS / 4; ++c) {
         const float4 v = s[c];
         f[4 * c] = v.x; f[4 * c + 1] = v.y; f[4 * c + 2] = v.z; f[4 * c + 3] = v.w;
     }
     GFrame g;
+    const float w = f[0], x = f[1], y = f[2], z = f[3];
+    g.R[0] = 1.f - 2.f * (y * y + z * z); g.R[1] = 2.f * (x * y - w * z); g.R[2] = 2.f * (x * z + w * y);
+    g.R[3] = 2.f * (x * y + w * z); g.R[4] = 1.f - 2.f * (x * x + z * z); g.R[5] = 2.f * (y * z - w * x);
+    g.R[6] = 2.f * (x * z - w * y); g.R[7] = 2.f * (y * z + w * x); g.R[8] = 1.f - 2.f * (x * x + y * y);
 #pragma unroll
-    for (int c = 0; c < 9; ++c) g.R[c] = f[c];
+    for (int c = 0; c < 4; ++c) g.qn[c] = f[c];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        g.sig[c] = f[9 + c];
-        g.mu[c] = f[12 + c];
+        g.mu[c] = f[4 + c];
+        g.isig[c] = f[8 + c];
+        g.sig[c] = f[12 + c];
     }
-    g.o = f[15];
-    g.beta = f[16];
-    g.phi = f[17];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) g.qn[c] = f[18 + c];
-    g.inv_q = f[22];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) g.isig[c] = f[23 + c];
-    g.ibeta = f[26];
-    g.io = f[27];
+    g.o = f[7];
+    g.beta = f[11];
+    g.inv_q = f[15];
+    g.phi = 2.0f / (1.0f + expf(-rho * (g.beta - 2.0f)));
+    g.ibeta = __builtin_amdgcn_rcpf(g.beta);
+    g.io = g.o > 0.f ? __builtin_amdgcn_rcpf(g.o) : 0.f;
     return g;
 }
 
@@ -425,7 +419,7 @@ __global__ __launch_bounds__(128) void k_gsr_loss(GsrArgs a) {
         return;
     }
     const float kappa = a.kappa;
-    const GFrame f0 = load_gframe(a.frames, j);
+    const GFrame f0 = load_gframe(a.frames, j, a.rho);
     float xi[3];
     for (int c = 0; c < 3; ++c) xi[c] = a.xi[(size_t)c * a.n + j];
     // the sample x = mu_0 + d0, d0 = R_0 diag(sig_0) xi, kept as the pair
@@ -438,13 +432,13 @@ __global__ __launch_bounds__(128) void k_gsr_loss(GsrArgs a) {
     int gs = 0;
     // the next neighbour's frame is loaded while this one is evaluated
     // (padding slots, n < k, load slot 0's frame and are skipped)
-    GFrame fn = load_gframe(a.frames, j);
+    GFrame fn = load_gframe(a.frames, j, a.rho);
     for (int s = 0; s < K; ++s) {
         const uint32_t i = nb_at(s);
         const GFrame f = fn;
         if (s + 1 < K) {
             const uint32_t i1 = nb_at(s + 1);
-            fn = load_gframe(a.frames, i1 < (uint32_t)a.n ? i1 : j);
+            fn = load_gframe(a.frames, i1 < (uint32_t)a.n ? i1 : j, a.rho);
         }
         if (i >= (uint32_t)a.n) continue;
         const Term t = eval_term(f, f0.mu, d0, kappa);
@@ -457,7 +451,7 @@ __global__ __launch_bounds__(128) void k_gsr_loss(GsrArgs a) {
         }
     }
     // SDF terms of g* (Eq. 10-13)
-    const GFrame fg = load_gframe(a.frames, nb_at(gs));
+    const GFrame fg = load_gframe(a.frames, nb_at(gs), a.rho);
     int ks = 0;
     if (fg.sig[1] < fg.sig[ks]) ks = 1;
     if (fg.sig[2] < fg.sig[ks]) ks = 2;
@@ -526,7 +520,7 @@ __global__ __launch_bounds__(128) void k_gsr_loss(GsrArgs a) {
     // pass 2, slot 0 last (it also carries the sample point's dependence)
     {
         const uint32_t il = nb_at(K - 1);
-        fn = load_gframe(a.frames, il < (uint32_t)a.n ? il : j);
+        fn = load_gframe(a.frames, il < (uint32_t)a.n ? il : j, a.rho);
     }
     for (int s = K - 1; s >= 0; --s) {
         float* ps = part + (size_t)s * GSR_PARTIAL_STRIDE;
@@ -534,7 +528,7 @@ __global__ __launch_bounds__(128) void k_gsr_loss(GsrArgs a) {
         const GFrame f = fn;
         if (s > 0) {
             const uint32_t i1 = nb_at(s - 1);
-            fn = load_gframe(a.frames, i1 < (uint32_t)a.n ? i1 : j);
+            fn = load_gframe(a.frames, i1 < (uint32_t)a.n ? i1 : j, a.rho);
         }
         if (i >= (uint32_t)a.n) {
             for (int c = 0; c < GSR_PARTIAL_FLOATS / 4; ++c)

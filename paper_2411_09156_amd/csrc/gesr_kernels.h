@@ -235,7 +235,7 @@ hipError_t launch_knn(const float* mean, int n, int k, uint32_t* knn, uint32_t* 
 constexpr int GSR_PARTIAL_FLOATS = 12;  // mean 3, scale 3, quaternion 4, opacity, beta
 constexpr int GSR_PARTIAL_STRIDE = 16;  // one aligned 64-byte record per (sample, slot)
 constexpr int GSR_SUM_BLOCK = 4096;     // samples per first-level loss-sum block
-constexpr int GSR_FRAME_FLOATS = 32;  // one 128-byte line per splat
+constexpr int GSR_FRAME_FLOATS = 16;  // one 64-byte record per splat
 struct GsrArgs {
     int n, k;
     const float *mean, *scale, *quat, *opacity, *beta;
