@@ -143,17 +143,28 @@ __global__ __launch_bounds__(256) void k_knn_ranges(const uint32_t* keys, int n,
     if (p + 1 == (uint32_t)n || keys[p + 1] != m) end[c] = p + 1;
 }
 
+// Centres in the sorted order, (x, y, z, index bits): a cell's centres are
+// one contiguous run of 16-byte records.
+__global__ __launch_bounds__(256) void k_knn_sorted_pos(const float* mean, int n, const uint32_t* order,
+                                                        float4* pos) {
+    const uint32_t p = blockIdx.x * 256u + threadIdx.x;
+    if (p >= (uint32_t)n) return;
+    const uint32_t i = order[p];
+    pos[p] = make_float4(mean[i], mean[(size_t)n + i], mean[2 * (size_t)n + i], __uint_as_float(i));
+}
+
 // Scans one cell's centres into the sorted candidate list (d2, index) of
 // WANT entries.
 template <int WANT>
 __device__ __forceinline__ void scan_cell(uint32_t c, const uint32_t* start, const uint32_t* end,
-                                          const uint32_t* order, const float* mean, size_t n, uint32_t self, float px,
-                                          float py, float pz, float* bd, uint32_t* bi, int& have) {
+                                          const float4* pos, uint32_t self, float px, float py, float pz, float* bd,
+                                          uint32_t* bi, int& have) {
     const uint32_t e = end[c];
     for (uint32_t q = start[c]; q < e; ++q) {
-        const uint32_t j = order[q];
+        const float4 v = pos[q];
+        const uint32_t j = __float_as_uint(v.w);
         if (j == self) continue;
-        const float dx = mean[j] - px, dy = mean[n + j] - py, dz = mean[2 * n + j] - pz;
+        const float dx = v.x - px, dy = v.y - py, dz = v.z - pz;
         const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
         if (d2 > bd[WANT - 1] || (d2 == bd[WANT - 1] && j >= bi[WANT - 1])) continue;
         // insert (d2, j), shifting the larger entries up
@@ -176,15 +187,14 @@ __device__ __forceinline__ void scan_cell(uint32_t c, const uint32_t* start, con
 // One query per thread, in cell order.  bd/bi hold the K - 1 nearest others
 // sorted by (distance^2, index).
 template <int K>
-__global__ __launch_bounds__(256) void k_knn_query(const float* mean, int n, const KnnGrid* gp,
-                                                   const uint32_t* order, const uint32_t* start,
-                                                   const uint32_t* end, uint32_t* knn) {
+__global__ __launch_bounds__(256) void k_knn_query(const float4* pos, int n, const KnnGrid* gp,
+                                                   const uint32_t* start, const uint32_t* end, uint32_t* knn) {
     const uint32_t p = blockIdx.x * 256u + threadIdx.x;
     if (p >= (uint32_t)n) return;
     const KnnGrid g = *gp;
-    const size_t nn = (size_t)n;
-    const uint32_t i = order[p];
-    const float px = mean[i], py = mean[nn + i], pz = mean[2 * nn + i];
+    const float4 me = pos[p];
+    const uint32_t i = __float_as_uint(me.w);
+    const float px = me.x, py = me.y, pz = me.z;
     const int cx = cell_coord(px, g.lo[0], g.inv_cs, g.dim[0]);
     const int cy = cell_coord(py, g.lo[1], g.inv_cs, g.dim[1]);
     const int cz = cell_coord(pz, g.lo[2], g.inv_cs, g.dim[2]);
@@ -207,14 +217,12 @@ __global__ __launch_bounds__(256) void k_knn_query(const float* mean, int n, con
                 const uint32_t row = (uint32_t)g.dim[0] * ((uint32_t)y + (uint32_t)g.dim[1] * (uint32_t)z);
                 if (r == 0 || abs(z - cz) == r || abs(y - cy) == r) {
                     for (int x = x0; x <= x1; ++x)
-                        scan_cell<want>(row + (uint32_t)x, start, end, order, mean, nn, i, px, py, pz, bd, bi, have);
+                        scan_cell<want>(row + (uint32_t)x, start, end, pos, i, px, py, pz, bd, bi, have);
                 } else {  // inner rows of the shell: its two end cells
                     if (cx - r >= 0)
-                        scan_cell<want>(row + (uint32_t)(cx - r), start, end, order, mean, nn, i, px, py, pz, bd,
-                                        bi, have);
+                        scan_cell<want>(row + (uint32_t)(cx - r), start, end, pos, i, px, py, pz, bd, bi, have);
                     if (cx + r < g.dim[0])
-                        scan_cell<want>(row + (uint32_t)(cx + r), start, end, order, mean, nn, i, px, py, pz, bd,
-                                        bi, have);
+                        scan_cell<want>(row + (uint32_t)(cx + r), start, end, pos, i, px, py, pz, bd, bi, have);
                 }
             }
         // every unscanned centre lies outside the cube of cells within r
@@ -742,6 +750,7 @@ KnnLayout knn_layout(int n, int k) {
     L.o_hist = take(256ull * ((sort_n + SORT_TILE - 1) / SORT_TILE));
     const uint64_t hist_n = 256ull * ((sort_n + SORT_TILE - 1) / SORT_TILE);
     L.o_scan = take((std::max<uint64_t>(hist_n, sort_n) + SCAN_TILE - 1) / SCAN_TILE + 64);
+    L.o_pos = take(4 * n1);
     L.o_start = take(L.cell_cap);
     L.o_end = take(L.cell_cap);
     L.words = off;
@@ -780,9 +789,11 @@ hipError_t launch_knn(const float* mean, int n, int k, uint32_t* knn, uint32_t* 
                        ws + L.o_end);
     const dim3 qg(blocks(n, 256)), qb(256);
     const uint32_t *cs0 = ws + L.o_start, *ce0 = ws + L.o_end;
+    float4* pos = reinterpret_cast<float4*>(ws + L.o_pos);
+    hipLaunchKernelGGL(k_knn_sorted_pos, qg, qb, 0, stream, mean, n, order, pos);
     switch (k) {
 #define GESR_KNN_CASE(KK) \
-    case KK: hipLaunchKernelGGL(k_knn_query<KK>, qg, qb, 0, stream, mean, n, grid, order, cs0, ce0, knn); break;
+    case KK: hipLaunchKernelGGL(k_knn_query<KK>, qg, qb, 0, stream, pos, n, grid, cs0, ce0, knn); break;
         GESR_KNN_CASE(2) GESR_KNN_CASE(3) GESR_KNN_CASE(4) GESR_KNN_CASE(5) GESR_KNN_CASE(6) GESR_KNN_CASE(7)
         GESR_KNN_CASE(8) GESR_KNN_CASE(9) GESR_KNN_CASE(10) GESR_KNN_CASE(11) GESR_KNN_CASE(12)
         GESR_KNN_CASE(13) GESR_KNN_CASE(14) GESR_KNN_CASE(15) GESR_KNN_CASE(16)

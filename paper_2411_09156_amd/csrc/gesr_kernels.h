@@ -226,7 +226,7 @@ struct KnnGrid {
 // Word offsets of the neighbour-list workspace.
 struct KnnLayout {
     uint32_t bound_parts, cell_cap;
-    uint64_t o_grid, o_parts, o_keys, o_ka, o_va, o_kb, o_vb, o_hist, o_scan, o_start, o_end, words;
+    uint64_t o_grid, o_parts, o_keys, o_ka, o_va, o_kb, o_vb, o_hist, o_scan, o_pos, o_start, o_end, words;
 };
 KnnLayout knn_layout(int n, int k);
 hipError_t launch_knn(const float* mean, int n, int k, uint32_t* knn, uint32_t* order_out, uint32_t* inv_offsets,
