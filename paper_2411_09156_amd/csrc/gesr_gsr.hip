@@ -414,12 +414,16 @@ __global__ __launch_bounds__(128) void k_gsr_loss(GsrArgs a) {
     // each thread reads back only its own column: no barrier needed
     const uint32_t* nbl = &s_nb[0][threadIdx.x];
 #define nb_at(s) nbl[(s) * 128]
-    float* part = a.partials ? a.partials + (size_t)p * K * GSR_PARTIAL_STRIDE : nullptr;
+    // partial records are slot-major: (sample position p, slot s) at s * n + p,
+    // so a wave's records of one slot are contiguous
+    float* part = a.partials ? a.partials + (size_t)p * GSR_PARTIAL_STRIDE : nullptr;
+    const size_t slot_stride = (size_t)a.n * GSR_PARTIAL_STRIDE;
     const bool on = a.mask == nullptr || a.mask[j] != 0;
     if (!on) {
         if (part)
-            for (int s = 0; s < K * GSR_PARTIAL_STRIDE / 4; ++s)
-                reinterpret_cast<float4*>(part)[s] = make_float4(0.f, 0.f, 0.f, 0.f);
+            for (int s = 0; s < K; ++s)
+                for (int c = 0; c < GSR_PARTIAL_FLOATS / 4; ++c)
+                    reinterpret_cast<float4*>(part + s * slot_stride)[c] = make_float4(0.f, 0.f, 0.f, 0.f);
         a.sample_out[(size_t)j * 4 + 0] = 0.f;
         a.sample_out[(size_t)j * 4 + 1] = 0.f;
         a.sample_out[(size_t)j * 4 + 2] = -1.f;
@@ -531,7 +535,7 @@ __global__ __launch_bounds__(128) void k_gsr_loss(GsrArgs a) {
         fn = load_gframe(a.frames, il < (uint32_t)a.n ? il : j, a.rho);
     }
     for (int s = K - 1; s >= 0; --s) {
-        float* ps = part + (size_t)s * GSR_PARTIAL_STRIDE;
+        float* ps = part + (size_t)s * slot_stride;
         const uint32_t i = nb_at(s);
         const GFrame f = fn;
         if (s > 0) {
@@ -628,8 +632,11 @@ __global__ __launch_bounds__(256) void k_gsr_gather(GsrArgs a) {
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
             if (e + t < e1) {
-                const float4* p =
-                    reinterpret_cast<const float4*>(a.partials + (size_t)a.inv_entries[e + t] * GSR_PARTIAL_STRIDE);
+                // entry p * k + s -> record s * n + p
+                const uint32_t en = a.inv_entries[e + t];
+                const uint32_t pp = en / (uint32_t)a.k, ss = en - pp * (uint32_t)a.k;
+                const float4* p = reinterpret_cast<const float4*>(
+                    a.partials + ((size_t)ss * (size_t)a.n + pp) * GSR_PARTIAL_STRIDE);
                 v[t][0] = p[0];
                 v[t][1] = p[1];
                 v[t][2] = p[2];

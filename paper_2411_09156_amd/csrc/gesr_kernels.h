@@ -247,7 +247,7 @@ struct GsrArgs {
     const uint8_t* mask;    // nullable
     float kappa, rho, w_sdf, w_nor;
     float* frames;          // [n][GSR_FRAME_FLOATS]
-    float* partials;        // [n][k][16] by position in `order`, null: no gradients
+    float* partials;        // [k][n][16] slot-major records by position in `order`, null: no gradients
     float* staged;          // [n][12] per-splat sums by position in `order`
     uint32_t* rank;         // [n] position of each splat in `order`
     float* sample_out;      // [n][4]: l_sdf, l_nor, g* slot (-1 when masked), d
