@@ -484,13 +484,14 @@ size_t gesr_knn_workspace_size(int n, int k);
  * grid (a spatial order; gesr_gsr runs its samples in it).  Inverse lists:
  * inv_entries[inv_offsets[i] .. inv_offsets[i + 1]) are the entries
  * e = p * k + s with knn[order[p]][s] = i, in increasing e (inv_offsets
- * [n + 1], inv_entries [n * k]).  Reads the means of `splats` only.  DEVICE
- * arrays, 16-byte aligned; the call never synchronises.  GESR_ERR_INVALID for
- * k outside 1..16, n * k >= 2^32, NULL or misaligned arrays, or a workspace
- * smaller than gesr_knn_workspace_size. */
+ * [n + 1], inv_entries [n * k]); inv_slot [n * k] is their inverse,
+ * inv_slot[inv_entries[t]] = t (undefined for padding entries).  Reads the
+ * means of `splats` only.  DEVICE arrays, 16-byte aligned; the call never
+ * synchronises.  GESR_ERR_INVALID for k outside 1..16, n * k >= 2^32, NULL or
+ * misaligned arrays, or a workspace smaller than gesr_knn_workspace_size. */
 gesr_status gesr_knn(gesr_ctx* ctx, const gesr_splats* splats, int k, uint32_t* knn, uint32_t* order,
-                     uint32_t* inv_offsets, uint32_t* inv_entries, void* workspace, size_t workspace_bytes,
-                     void* stream);
+                     uint32_t* inv_offsets, uint32_t* inv_entries, uint32_t* inv_slot, void* workspace,
+                     size_t workspace_bytes, void* stream);
 
 /* Weights of the two regulariser terms (lambda_1, lambda_2 of Eq. 14, which
  * the paper does not give; fold the 1 / |X| of Eq. 12-13 in as well). */
@@ -515,20 +516,21 @@ size_t gesr_gsr_workspace_size(int n, int k, int with_grads);
  *   (d floored at 1e-30, f = 0 where d >= 1);
  *   l_sdf = |fbar - f| (Eq. 12), l_nor = |-sign(h) grad d / |grad d| - n|^2
  *   (Eq. 13; 0 where grad d = 0).
- * knn, order and the inverse lists are gesr_knn's for the same k.
+ * knn, order, inv_offsets and inv_slot are gesr_knn's for the same k.
  * kappa and rho come from `st`.  sample_out [n][4] (DEVICE, nullable):
  * l_sdf, l_nor, g*'s slot in knn[j] (-1 when masked), d.  losses [2] (DEVICE,
  * nullable): the sums of l_sdf and l_nor over the samples, in a fixed order.
  * When `grads` is non-null, the gradient of
  * sum_j (w_sdf l_sdf + w_nor l_nor) with respect to mean, scale, quat,
  * opacity and beta (activated, layouts of gesr_splats) is ADDED to it, each
- * splat's terms summed in inverse-list order (no atomics; every discrete
- * choice held fixed); grads->sh is not touched.  The workspace needs
+ * splat's terms summed in inverse-list order (the partial of entry e is
+ * written to record inv_slot[e], so a splat's records are contiguous; no
+ * atomics; every discrete choice held fixed); grads->sh is not touched.  The workspace needs
  * gesr_gsr_workspace_size(n, k, grads != NULL) bytes.  GESR_ERR_INVALID for
  * NULL or misaligned arrays, k outside 1..16, non-finite weights or a small
  * workspace. */
 gesr_status gesr_gsr(gesr_ctx* ctx, const gesr_splats* splats, const gesr_settings* st, int k, const uint32_t* knn,
-                     const uint32_t* order, const uint32_t* inv_offsets, const uint32_t* inv_entries, const float* xi,
+                     const uint32_t* order, const uint32_t* inv_offsets, const uint32_t* inv_slot, const float* xi,
                      const uint8_t* mask,
                      const gesr_gsr_settings* gs, float* sample_out, float* losses, const gesr_grads* grads,
                      void* workspace, size_t workspace_bytes, void* stream);

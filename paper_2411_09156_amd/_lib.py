@@ -199,7 +199,7 @@ def load():
     lib.gesr_shape_reset.restype = st
     lib.gesr_knn_workspace_size.argtypes = [ctypes.c_int, ctypes.c_int]
     lib.gesr_knn_workspace_size.restype = ctypes.c_size_t
-    lib.gesr_knn.argtypes = [vp, P(Splats), ctypes.c_int, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
+    lib.gesr_knn.argtypes = [vp, P(Splats), ctypes.c_int, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
     lib.gesr_knn.restype = st
     lib.gesr_gsr_workspace_size.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int]
     lib.gesr_gsr_workspace_size.restype = ctypes.c_size_t

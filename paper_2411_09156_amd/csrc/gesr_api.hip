@@ -928,8 +928,8 @@ size_t gesr_knn_workspace_size(int n, int k) {
 }
 
 gesr_status gesr_knn(gesr_ctx* ctx, const gesr_splats* splats, int k, uint32_t* knn, uint32_t* order,
-                     uint32_t* inv_offsets, uint32_t* inv_entries, void* workspace, size_t workspace_bytes,
-                     void* stream) {
+                     uint32_t* inv_offsets, uint32_t* inv_entries, uint32_t* inv_slot, void* workspace,
+                     size_t workspace_bytes, void* stream) {
     if (!ctx) return GESR_ERR_INVALID;
     if (!splats) return fail(ctx, GESR_ERR_INVALID, "splats is NULL");
     if (splats->n < 0) return fail(ctx, GESR_ERR_INVALID, "splats->n is negative");
@@ -938,7 +938,7 @@ gesr_status gesr_knn(gesr_ctx* ctx, const gesr_splats* splats, int k, uint32_t* 
     if ((uint64_t)n * (uint64_t)k >= (1ull << 32)) return fail(ctx, GESR_ERR_INVALID, "n * k must be < 2^32");
     if (!inv_offsets || !aligned16(inv_offsets)) return fail(ctx, GESR_ERR_INVALID, "inv_offsets NULL or misaligned");
     if (n > 0) {
-        const void* ptrs[4] = {splats->mean, knn, order, inv_entries};
+        const void* ptrs[5] = {splats->mean, knn, order, inv_entries, inv_slot};
         for (const void* ptr : ptrs)
             if (!ptr || !aligned16(ptr)) return fail(ctx, GESR_ERR_INVALID, "array NULL or not 16-byte aligned");
     }
@@ -948,7 +948,7 @@ gesr_status gesr_knn(gesr_ctx* ctx, const gesr_splats* splats, int k, uint32_t* 
     // 256-byte alignment of the sub-buffers
     uint32_t* ws = (uint32_t*)(((uintptr_t)workspace + 255) & ~(uintptr_t)255);
     GESR_TRY(hip_check(ctx, hipSetDevice(ctx->device), "hipSetDevice"));
-    GESR_TRY(hip_check(ctx, launch_knn(splats->mean, n, k, knn, order, inv_offsets, inv_entries, ws,
+    GESR_TRY(hip_check(ctx, launch_knn(splats->mean, n, k, knn, order, inv_offsets, inv_entries, inv_slot, ws,
                                        (hipStream_t)stream),
                        "knn launch"));
     ctx->err.clear();
@@ -961,12 +961,12 @@ size_t gesr_gsr_workspace_size(int n, int k, int with_grads) {
     const size_t nparts = (n1 + GSR_SUM_BLOCK - 1) / GSR_SUM_BLOCK;
     // frames, per-sample results and loss partials, rounded to 256 bytes
     size_t floats = (n1 * GSR_FRAME_FLOATS + n1 * 4 + 2 * nparts + 63) & ~(size_t)63;
-    if (with_grads) floats += n1 * (size_t)k * GSR_PARTIAL_STRIDE + n1 * GSR_PARTIAL_FLOATS + n1;
+    if (with_grads) floats += n1 * (size_t)k * GSR_PARTIAL_STRIDE;
     return floats * 4 + 256;
 }
 
 gesr_status gesr_gsr(gesr_ctx* ctx, const gesr_splats* splats, const gesr_settings* st, int k, const uint32_t* knn,
-                     const uint32_t* order, const uint32_t* inv_offsets, const uint32_t* inv_entries, const float* xi,
+                     const uint32_t* order, const uint32_t* inv_offsets, const uint32_t* inv_slot, const float* xi,
                      const uint8_t* mask,
                      const gesr_gsr_settings* gs, float* sample_out, float* losses, const gesr_grads* grads,
                      void* workspace, size_t workspace_bytes, void* stream) {
@@ -985,7 +985,7 @@ gesr_status gesr_gsr(gesr_ctx* ctx, const gesr_splats* splats, const gesr_settin
             if (!ptr || !aligned16(ptr)) return fail(ctx, GESR_ERR_INVALID, "array NULL or not 16-byte aligned");
         if (sample_out && !aligned16(sample_out)) return fail(ctx, GESR_ERR_INVALID, "sample_out not 16-byte aligned");
         if (grads) {
-            const void* gp[6] = {grads->mean, grads->scale, grads->quat, grads->opacity, grads->beta, inv_entries};
+            const void* gp[6] = {grads->mean, grads->scale, grads->quat, grads->opacity, grads->beta, inv_slot};
             for (const void* ptr : gp)
                 if (!ptr || !aligned16(ptr))
                     return fail(ctx, GESR_ERR_INVALID, "gradient or inverse-list array NULL or misaligned");
@@ -1008,7 +1008,7 @@ gesr_status gesr_gsr(gesr_ctx* ctx, const gesr_splats* splats, const gesr_settin
     a.knn = knn;
     a.order = order;
     a.inv_offsets = inv_offsets;
-    a.inv_entries = inv_entries;
+    a.inv_slot = inv_slot;
     a.xi = xi;
     a.mask = mask;
     a.kappa = st->kappa;
@@ -1021,8 +1021,6 @@ gesr_status gesr_gsr(gesr_ctx* ctx, const gesr_splats* splats, const gesr_settin
     a.sum_parts = ws + n1 * GSR_FRAME_FLOATS + n1 * 4;
     // partial records start 256-byte aligned
     a.partials = grads ? ws + ((n1 * GSR_FRAME_FLOATS + n1 * 4 + 2 * nparts + 63) & ~(size_t)63) : nullptr;
-    a.staged = grads ? a.partials + n1 * (size_t)k * GSR_PARTIAL_STRIDE : nullptr;
-    a.rank = grads ? reinterpret_cast<uint32_t*>(a.staged + n1 * GSR_PARTIAL_FLOATS) : nullptr;
     a.losses = losses;
     if (grads) {
         a.g_mean = grads->mean;

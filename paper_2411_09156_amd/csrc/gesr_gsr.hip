@@ -19,9 +19,10 @@
 // Eq. 10-13 and their adjoints (with respect to d, grad d and the g* frame).
 // Pass 2 revisits the neighbours, takes every term's derivative with respect
 // to its own splat and to x, adds the g* terms and, last, the dependence of x
-// on the sampled splat, and writes one 12-float partial per (sample, slot).
-// A gather over the inverse lists adds the partials of each splat, in entry
-// order, into the gradients: deterministic, no atomics.
+// on the sampled splat, and writes one 12-float partial per (sample, slot) to
+// that entry's position in the inverse lists.  A gather then adds each
+// splat's contiguous records, in entry order, into the gradients:
+// deterministic, no atomics.
 
 #include <math.h>
 
@@ -276,6 +277,16 @@ __global__ __launch_bounds__(256) void k_inv_offsets(const uint32_t* keys, uint6
     }
 }
 
+// Position of every valid entry in the inverse order: the regulariser writes
+// the partial of entry e to record inv_slot[e], so that each splat's records
+// are contiguous for the gather.
+__global__ __launch_bounds__(256) void k_inv_slots(const uint32_t* inv_entries, const uint32_t* inv_offsets,
+                                                   uint32_t n, uint32_t* inv_slot) {
+    const uint32_t pos = blockIdx.x * 256u + threadIdx.x;
+    if (pos >= inv_offsets[n]) return;
+    inv_slot[inv_entries[pos]] = pos;
+}
+
 // ---------------------------------------------------------------- loss
 // Per-splat frame, one 64-byte record: normalised quaternion (4), mu (3),
 // opacity, 1 / sigma (3) with sigma = phi s, beta, sigma (3), 1 / |q|.  The
@@ -403,6 +414,7 @@ __device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nblocks) {
 // positions).  A sample's list is staged in LDS.
 __global__ __launch_bounds__(128) void k_gsr_loss(GsrArgs a) {
     __shared__ uint32_t s_nb[GESR_KNN_MAX][128];
+    __shared__ uint32_t s_slot[GESR_KNN_MAX][128];
     const uint32_t p = xcd_block(blockIdx.x, gridDim.x) * 128u + threadIdx.x;
     if (p >= (uint32_t)a.n) return;
     const uint32_t j = a.order[p];
@@ -410,20 +422,27 @@ __global__ __launch_bounds__(128) void k_gsr_loss(GsrArgs a) {
     {
         const uint32_t* row = a.knn + (size_t)j * K;
         for (int s = 0; s < K; ++s) s_nb[s][threadIdx.x] = row[s];
+        if (a.partials) {
+            const uint32_t* srow = a.inv_slot + (size_t)p * K;
+            for (int s = 0; s < K; ++s) s_slot[s][threadIdx.x] = srow[s];
+        }
     }
     // each thread reads back only its own column: no barrier needed
     const uint32_t* nbl = &s_nb[0][threadIdx.x];
+    const uint32_t* sll = &s_slot[0][threadIdx.x];
 #define nb_at(s) nbl[(s) * 128]
-    // partial records are slot-major: (sample position p, slot s) at s * n + p,
-    // so a wave's records of one slot are contiguous
-    float* part = a.partials ? a.partials + (size_t)p * GSR_PARTIAL_STRIDE : nullptr;
-    const size_t slot_stride = (size_t)a.n * GSR_PARTIAL_STRIDE;
+    // the partial of slot s goes to record inv_slot[p * k + s]: each splat's
+    // records end up contiguous, in inverse-list order
+#define rec_at(s) (a.partials + (size_t)sll[(s) * 128] * GSR_PARTIAL_STRIDE)
+    const bool with_part = a.partials != nullptr;
     const bool on = a.mask == nullptr || a.mask[j] != 0;
     if (!on) {
-        if (part)
-            for (int s = 0; s < K; ++s)
+        if (with_part)
+            for (int s = 0; s < K; ++s) {
+                if (nb_at(s) >= (uint32_t)a.n) continue;  // padding slots have no record
                 for (int c = 0; c < GSR_PARTIAL_FLOATS / 4; ++c)
-                    reinterpret_cast<float4*>(part + s * slot_stride)[c] = make_float4(0.f, 0.f, 0.f, 0.f);
+                    reinterpret_cast<float4*>(rec_at(s))[c] = make_float4(0.f, 0.f, 0.f, 0.f);
+            }
         a.sample_out[(size_t)j * 4 + 0] = 0.f;
         a.sample_out[(size_t)j * 4 + 1] = 0.f;
         a.sample_out[(size_t)j * 4 + 2] = -1.f;
@@ -507,7 +526,7 @@ __global__ __launch_bounds__(128) void k_gsr_loss(GsrArgs a) {
     a.sample_out[(size_t)j * 4 + 1] = l_nor;
     a.sample_out[(size_t)j * 4 + 2] = (float)gs;
     a.sample_out[(size_t)j * 4 + 3] = d;
-    if (!part) return;
+    if (!with_part) return;
 
     // adjoints of the sample's loss w_sdf l_sdf + w_nor l_nor
     const float ws = a.w_sdf, wn = a.w_nor;
@@ -535,18 +554,14 @@ __global__ __launch_bounds__(128) void k_gsr_loss(GsrArgs a) {
         fn = load_gframe(a.frames, il < (uint32_t)a.n ? il : j, a.rho);
     }
     for (int s = K - 1; s >= 0; --s) {
-        float* ps = part + (size_t)s * slot_stride;
         const uint32_t i = nb_at(s);
         const GFrame f = fn;
         if (s > 0) {
             const uint32_t i1 = nb_at(s - 1);
             fn = load_gframe(a.frames, i1 < (uint32_t)a.n ? i1 : j, a.rho);
         }
-        if (i >= (uint32_t)a.n) {
-            for (int c = 0; c < GSR_PARTIAL_FLOATS / 4; ++c)
-                reinterpret_cast<float4*>(ps)[c] = make_float4(0.f, 0.f, 0.f, 0.f);
-            continue;
-        }
+        if (i >= (uint32_t)a.n) continue;  // padding slot: no record
+        float* ps = rec_at(s);
         const Term t = eval_term(f, f0.mu, d0, kappa);
         // b = diag(1/sig) R^T u, scaled by gmax like u
         float b[3];
@@ -609,34 +624,24 @@ __global__ __launch_bounds__(128) void k_gsr_loss(GsrArgs a) {
     }
 }
 #undef nb_at
+#undef rec_at
 
-// Gradient of each splat: the sum of its partials in inverse-list order.
-// Splats run in the cell order: a splat's entries come from its spatial
-// neighbours, whose partials sit near its own position in that order.  The
-// sums go to a staging row at that position; k_gsr_apply adds them into the
-// gradients in index order, so both the partial reads and the gradient
-// updates stay coalesced.
+// Gradient of each splat: the sum of its records, which the loss kernel wrote
+// contiguously in inverse-list order, added into the gradients.  Four
+// records per step keep several loads in flight; the sum runs in order.
 __global__ __launch_bounds__(256) void k_gsr_gather(GsrArgs a) {
-    const uint32_t q = xcd_block(blockIdx.x, gridDim.x) * 256u + threadIdx.x;
-    if (q >= (uint32_t)a.n) return;
-    const uint32_t i = a.order[q];
-    a.rank[i] = q;
+    const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+    if (i >= (uint32_t)a.n) return;
     float acc[GSR_PARTIAL_FLOATS];
 #pragma unroll
     for (int c = 0; c < GSR_PARTIAL_FLOATS; ++c) acc[c] = 0.f;
     const uint32_t e0 = a.inv_offsets[i], e1 = a.inv_offsets[i + 1];
-    // four entries per step: their loads are independent and overlap; the
-    // sums still run in entry order
     for (uint32_t e = e0; e < e1; e += 4) {
         float4 v[4][3];
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
             if (e + t < e1) {
-                // entry p * k + s -> record s * n + p
-                const uint32_t en = a.inv_entries[e + t];
-                const uint32_t pp = en / (uint32_t)a.k, ss = en - pp * (uint32_t)a.k;
-                const float4* p = reinterpret_cast<const float4*>(
-                    a.partials + ((size_t)ss * (size_t)a.n + pp) * GSR_PARTIAL_STRIDE);
+                const float4* p = reinterpret_cast<const float4*>(a.partials + (size_t)(e + t) * GSR_PARTIAL_STRIDE);
                 v[t][0] = p[0];
                 v[t][1] = p[1];
                 v[t][2] = p[2];
@@ -651,30 +656,14 @@ __global__ __launch_bounds__(256) void k_gsr_gather(GsrArgs a) {
             acc[8] += v[t][2].x; acc[9] += v[t][2].y; acc[10] += v[t][2].z; acc[11] += v[t][2].w;
         }
     }
-    float4* st = reinterpret_cast<float4*>(a.staged + (size_t)q * GSR_PARTIAL_FLOATS);
-    st[0] = make_float4(acc[0], acc[1], acc[2], acc[3]);
-    st[1] = make_float4(acc[4], acc[5], acc[6], acc[7]);
-    st[2] = make_float4(acc[8], acc[9], acc[10], acc[11]);
-}
-
-__global__ __launch_bounds__(256) void k_gsr_apply(GsrArgs a) {
-    const uint32_t i = blockIdx.x * 256u + threadIdx.x;
-    if (i >= (uint32_t)a.n) return;
-    const float4* p = reinterpret_cast<const float4*>(a.staged + (size_t)a.rank[i] * GSR_PARTIAL_FLOATS);
-    const float4 v0 = p[0], v1 = p[1], v2 = p[2];
     const size_t n = (size_t)a.n;
-    a.g_mean[i] += v0.x;
-    a.g_mean[n + i] += v0.y;
-    a.g_mean[2 * n + i] += v0.z;
-    a.g_scale[i] += v0.w;
-    a.g_scale[n + i] += v1.x;
-    a.g_scale[2 * n + i] += v1.y;
-    a.g_quat[i] += v1.z;
-    a.g_quat[n + i] += v1.w;
-    a.g_quat[2 * n + i] += v2.x;
-    a.g_quat[3 * n + i] += v2.y;
-    a.g_opacity[i] += v2.z;
-    a.g_beta[i] += v2.w;
+    for (int c = 0; c < 3; ++c) {
+        a.g_mean[c * n + i] += acc[c];
+        a.g_scale[c * n + i] += acc[3 + c];
+    }
+    for (int c = 0; c < 4; ++c) a.g_quat[c * n + i] += acc[6 + c];
+    a.g_opacity[i] += acc[10];
+    a.g_beta[i] += acc[11];
 }
 
 // Sums of the per-sample losses in a fixed order: each block adds
@@ -771,7 +760,7 @@ static int bits_for(uint64_t v) {
 }
 
 hipError_t launch_knn(const float* mean, int n, int k, uint32_t* knn, uint32_t* order_out, uint32_t* inv_offsets,
-                      uint32_t* inv_entries, uint32_t* ws, hipStream_t stream) {
+                      uint32_t* inv_entries, uint32_t* inv_slot, uint32_t* ws, hipStream_t stream) {
     if (n == 0) return launch_fill_u32(inv_offsets, 0u, 1, stream);
     const KnnLayout L = knn_layout(n, k);
     KnnGrid* grid = reinterpret_cast<KnnGrid*>(ws + L.o_grid);
@@ -821,6 +810,8 @@ hipError_t launch_knn(const float* mean, int n, int k, uint32_t* knn, uint32_t* 
     const uint32_t* ikeys = in_b ? ib.keys_b : ib.keys_a;
     hipLaunchKernelGGL(k_inv_offsets, dim3(blocks(total + 1, 256)), dim3(256), 0, stream, ikeys, total, (uint32_t)n,
                        inv_offsets);
+    hipLaunchKernelGGL(k_inv_slots, dim3(blocks(total, 256)), dim3(256), 0, stream, inv_entries, inv_offsets,
+                       (uint32_t)n, inv_slot);
     return hipGetLastError();
 }
 
@@ -831,10 +822,7 @@ hipError_t launch_gsr(GsrArgs a, hipStream_t stream) {
     }
     hipLaunchKernelGGL(k_gsr_frames, dim3(blocks(a.n, 256)), dim3(256), 0, stream, a);
     hipLaunchKernelGGL(k_gsr_loss, dim3(blocks(a.n, 128)), dim3(128), 0, stream, a);
-    if (a.partials) {
-        hipLaunchKernelGGL(k_gsr_gather, dim3(blocks(a.n, 256)), dim3(256), 0, stream, a);
-        hipLaunchKernelGGL(k_gsr_apply, dim3(blocks(a.n, 256)), dim3(256), 0, stream, a);
-    }
+    if (a.partials) hipLaunchKernelGGL(k_gsr_gather, dim3(blocks(a.n, 256)), dim3(256), 0, stream, a);
     if (a.losses) {
         const unsigned nparts = blocks(a.n, GSR_SUM_BLOCK);
         hipLaunchKernelGGL(k_gsr_sum_blocks, dim3(nparts), dim3(256), 0, stream, a.sample_out, a.n, a.sum_parts);

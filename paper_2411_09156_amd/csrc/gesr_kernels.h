@@ -230,7 +230,7 @@ struct KnnLayout {
 };
 KnnLayout knn_layout(int n, int k);
 hipError_t launch_knn(const float* mean, int n, int k, uint32_t* knn, uint32_t* order_out, uint32_t* inv_offsets,
-                      uint32_t* inv_entries, uint32_t* ws, hipStream_t stream);
+                      uint32_t* inv_entries, uint32_t* inv_slot, uint32_t* ws, hipStream_t stream);
 
 constexpr int GSR_PARTIAL_FLOATS = 12;  // mean 3, scale 3, quaternion 4, opacity, beta
 constexpr int GSR_PARTIAL_STRIDE = 16;  // one aligned 64-byte record per (sample, slot)
@@ -242,14 +242,12 @@ struct GsrArgs {
     const uint32_t* knn;
     const uint32_t* order;  // samples in cell order
     const uint32_t* inv_offsets;
-    const uint32_t* inv_entries;
+    const uint32_t* inv_slot;  // [n * k]: record of entry p * k + s
     const float* xi;        // [3][n]
     const uint8_t* mask;    // nullable
     float kappa, rho, w_sdf, w_nor;
     float* frames;          // [n][GSR_FRAME_FLOATS]
-    float* partials;        // [k][n][16] slot-major records by position in `order`, null: no gradients
-    float* staged;          // [n][12] per-splat sums by position in `order`
-    uint32_t* rank;         // [n] position of each splat in `order`
+    float* partials;        // [n * k][16] records in inverse-list order, null: no gradients
     float* sample_out;      // [n][4]: l_sdf, l_nor, g* slot (-1 when masked), d
     float* losses;          // nullable: sums of l_sdf and l_nor
     float* sum_parts;       // [ceil(n / GSR_SUM_BLOCK)][2] first-level sums

@@ -31,14 +31,16 @@ def knn(sp: Splats, k: int = 16, device: int = 0) -> dict:
     out = dict(knn=torch.empty(max(n * k, 1), dtype=torch.int32, device=dev),
                order=torch.empty(max(n, 1), dtype=torch.int32, device=dev),
                inv_offsets=torch.empty(n + 1, dtype=torch.int32, device=dev),
-               inv_entries=torch.empty(max(n * k, 1), dtype=torch.int32, device=dev), k=k)
+               inv_entries=torch.empty(max(n * k, 1), dtype=torch.int32, device=dev),
+               inv_slot=torch.empty(max(n * k, 1), dtype=torch.int32, device=dev), k=k)
     wsb = int(lib.gesr_knn_workspace_size(n, k))
     ws = torch.empty(max(wsb, 16), dtype=torch.uint8, device=dev)
     _check(lib, ctx, lib.gesr_knn(ctx, ctypes.byref(sp.to_c()), int(k), out["knn"].data_ptr(),
                                   out["order"].data_ptr(), out["inv_offsets"].data_ptr(), out["inv_entries"].data_ptr(),
-                                  ws.data_ptr(), wsb, _stream()))
+                                  out["inv_slot"].data_ptr(), ws.data_ptr(), wsb, _stream()))
     out["knn"] = out["knn"][:n * k].view(n, k)
     out["inv_entries"] = out["inv_entries"][:n * k]
+    out["inv_slot"] = out["inv_slot"][:n * k]
     out["order"] = out["order"][:n]
     return out
 
@@ -64,7 +66,7 @@ def gsr(sp: Splats, settings: RasterSettings, nbrs: dict, xi: torch.Tensor, mask
     gs = _lib.GsrSettings(float(w_sdf), float(w_nor))
     st_c = settings.to_c()
     _check(lib, ctx, lib.gesr_gsr(ctx, ctypes.byref(sp.to_c()), ctypes.byref(st_c), k, nbrs["knn"].data_ptr(),
-                                  nbrs["order"].data_ptr(), nbrs["inv_offsets"].data_ptr(), nbrs["inv_entries"].data_ptr(), xi.data_ptr(),
+                                  nbrs["order"].data_ptr(), nbrs["inv_offsets"].data_ptr(), nbrs["inv_slot"].data_ptr(), xi.data_ptr(),
                                   m.data_ptr() if m is not None else None, ctypes.byref(gs), sample_out.data_ptr(),
                                   losses.data_ptr(), ctypes.byref(gc) if gc is not None else None, ws.data_ptr(),
                                   wsb, _stream()))

@@ -6,7 +6,8 @@ float64; a row may differ only where the neighbours it swaps lie within the
 float32 error band of each other's distance (relative 1e-5), and the lists
 must agree as sets of float64 distances within that band.  The inverse lists
 are checked exactly against a stable sort of the GPU's own lists taken in its
-cell order (a permutation of the splats).
+cell order (a permutation of the splats), and the entry-to-record map as their
+inverse.
 
 Losses and gradients: the oracle gets the GPU's lists and the same xi.
 Samples whose oracle decision margins lie inside the float32 band are masked
@@ -113,6 +114,8 @@ def test_knn_matches_oracle(kind, n, k):
     ent = nb["inv_entries"].cpu().numpy().astype(np.int64)[:int(valid.sum())]
     np.testing.assert_array_equal(ent, order)
     np.testing.assert_array_equal(offs, np.searchsorted(flat[order], np.arange(n + 1), side="left"))
+    slot = nb["inv_slot"].cpu().numpy().astype(np.int64)
+    np.testing.assert_array_equal(slot[ent], np.arange(ent.size))
     log(f"[gpu] knn {kind} n={n}: {differ} rows differ within the float32 band")
 
 
