@@ -240,3 +240,47 @@ def test_gsr_full_size_sampled():
     np.testing.assert_allclose(so[r, 0], ref["l_sdf"][r], rtol=2e-3, atol=1e-6 * np.abs(ref["l_sdf"][r]).max())
     np.testing.assert_allclose(so[r, 1], ref["l_nor"][r], rtol=1e-3, atol=1e-5)
     log(f"[gpu] gsr full size: {len(r)} sampled samples agree")
+
+
+@pytest.mark.parametrize("n,k", [(9, 16), (1, 16), (300, 5), (200, 1), (64, 16)])
+def test_gsr_small_and_padded_lists(n, k):
+    """Lists shorter than k (n < k pads them), other list lengths, a lone
+    splat, and a mask that drops every other sample: same bars as above."""
+    import torch
+    from paper_2411_09156_amd import RasterSettings
+    from paper_2411_09156_amd.gsr import gsr, knn
+    log(f"[gpu] gsr small n={n} k={k}")
+    sc = _scene("cube", n, 4)
+    sc.scales = (sc.scales * (2000.0 / max(n, 1)) ** (1.0 / 3.0)).astype(np.float32)
+    sp = _splats(sc)
+    nb = knn(sp, k)
+    torch.cuda.synchronize()
+    nbrs = nb["knn"].cpu().numpy().astype(np.int64).astype(np.int32)
+    xi = np.random.default_rng([n, k]).standard_normal((n, 3)).astype(np.float32)
+    st = oracle.Settings()
+    first = oracle.gsr(sc, st, nbrs, xi, grads=False)
+    mask = _clear(first["margins"]) & (np.arange(n) % 2 == 0)
+    ref = oracle.gsr(sc, st, nbrs, xi, mask=mask.astype(np.uint8), w_sdf=0.6, w_nor=0.4)
+    grads = {g: torch.zeros_like(getattr(sp, g)) for g in ("mean", "scale", "quat", "opacity", "beta")}
+    out = gsr(sp, RasterSettings(), nb, torch.as_tensor(xi.T.copy(), device="cuda"),
+              mask=torch.as_tensor(mask.astype(np.uint8), device="cuda"), w_sdf=0.6, w_nor=0.4, grads=grads)
+    torch.cuda.synchronize()
+    so = out["sample_out"].cpu().numpy().astype(np.float64)
+    np.testing.assert_array_equal(so[mask, 2].astype(np.int64), ref["gstar"][mask])
+    assert (so[~mask, 2] == -1).all()
+    for c, key, bar in ((0, "l_sdf", 1e-4), (1, "l_nor", 1e-3)):
+        einf, e2 = norm_errors(so[:, c], ref[key])
+        assert einf <= bar and e2 <= bar, (key, einf, e2)
+    groups = (("mean", "means", 3), ("scale", "scales", 3), ("quat", "quats", 4), ("opacity", "opacities", 1),
+              ("beta", "betas", 1))
+    # a group whose reference vanishes (k = 1: a lone splat's losses do not
+    # depend on its rotation) is held to 1e-3 of the largest group's norm
+    scale = max(np.abs(ref["grads"][rk]).max(initial=0.0) for _, rk, _ in groups)
+    for gk, rk, w in groups:
+        g = grads[gk].cpu().numpy().astype(np.float64).reshape(w, -1).T
+        r = ref["grads"][rk].reshape(-1, w)
+        if np.abs(r).max(initial=0.0) < 1e-6 * scale:
+            assert np.abs(g - r).max(initial=0.0) <= 1e-3 * scale, gk
+            continue
+        einf, e2 = norm_errors(g, r)
+        assert einf <= 1e-3 and e2 <= 1e-3, (gk, einf, e2)
