@@ -109,7 +109,7 @@ def main():
     args = parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU design "
-              "(views sharded across GPUs, one gradient all-reduce) is described in DESIGN.md but not built.",
+              "(views sharded across GPUs, one gradient all-reduce) is not built.",
               file=sys.stderr)
         sys.exit(2)
 

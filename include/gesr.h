@@ -41,7 +41,7 @@ typedef enum {
     GESR_ERR_INVALID = 1,     /* bad argument; nothing enqueued */
     GESR_ERR_CAPACITY = 2,    /* instance count exceeds bins->m_cap (see gesr_bin) */
     GESR_ERR_HIP = 3,         /* HIP runtime error */
-    GESR_ERR_UNSUPPORTED = 4  /* valid but not supported by this build (e.g. tile shape) */
+    GESR_ERR_UNSUPPORTED = 4  /* valid but not supported by the library (e.g. tile shape) */
 } gesr_status;
 
 #define GESR_MAX_VIEWS 32
