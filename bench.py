@@ -188,12 +188,13 @@ def main():
     log("[bench] sizing run (eager, synchronous count)")
     first = rast.forward(sp, sync=True, counts=True)
     M = int(first["bins"]["M"])
+    listed_inst = int(first["bins"]["counters"][3].item())
     m_cap = M
     n_listed = int(first["n_listed"].to(torch.int64).sum().item())
     n_hit = int(first["n_hit"].to(torch.int64).sum().item())
     del first
     torch.cuda.synchronize()
-    log(f"[bench] M={M} instances, listed={n_listed}, hit={n_hit}")
+    log(f"[bench] M={M} instance slots, {listed_inst} in the tile lists, listed={n_listed}, hit={n_hit}")
 
     # ---------------------------------------------------- batched, graph
     step = make_step(rast, sp, target, m_cap, chan=chan)
@@ -398,6 +399,7 @@ def main():
                    "resolutions": [f"{c.width}x{c.height}" for c in scene.cameras], "sh_degree": scene.sh_degree,
                    "tile": f"{rs.tile_w}x{rs.tile_h}", "variant": rs.variant, "batch": rs.batch or 64,
                    "radix_bits": rs.radix_bits, "graph": not args.no_graph, "instances": M,
+                   "listed_instances": listed_inst,
                    "channels": bool(args.channels)},
         "fragments": {"listed": n_listed, "hit": n_hit,
                       "listed_per_s": round(n_listed / (ms * 1e-3), 1), "hit_per_s": round(n_hit / (ms * 1e-3), 1)},

@@ -140,8 +140,10 @@ typedef struct {
  *      instance slots of pair vi are inst_base[vi] + (row-major position of the
  *      tile in the pair's rectangle); the backward's per-instance partials use
  *      these slots.
- *  counters[4]: [0] = M (instances wanted), [1] = 1 if M > m_cap,
- *      [2] = min(M, m_cap); [3] is reserved.  Written on the device. */
+ *  counters[4]: [0] = M (instance slots: the tiles of every pair's
+ *      rectangle), [1] = 1 if M > m_cap, [2] = min(M, m_cap), [3] = the
+ *      instances in the tile lists (<= M: each rectangle row keeps only the
+ *      columns its ellipse reaches).  Written on the device. */
 typedef struct {
     uint64_t m_cap;
     uint32_t* tile_sorted;
@@ -190,10 +192,17 @@ gesr_status gesr_project(gesr_ctx* ctx, const gesr_splats* splats, const gesr_ca
 #define GESR_BIN_SYNC 1 /* read M back and fail with GESR_ERR_CAPACITY if M > m_cap */
 
 /* Tile binning: one instance per (view, splat, covered tile), sorted by the
- * (tile | depth) key (see gesr_bins).  The pairs are radix-sorted by (view,
- * depth); the lists are then built from the rectangles in two stable bucketing
- * levels (pairs into tile rows, row entries into tiles) without sorting
- * instances.  With GESR_BIN_SYNC the call
+ * (tile | depth) key (see gesr_bins).  A pair covers the tiles of its
+ * rectangle's rows whose columns the footprint ellipse reaches within that
+ * row: with q = (L00 dx + L10 dy)^2 + (L11 dy)^2 <= Q, Q = qmax (1 + 2^-8),
+ * the x-extent of the ellipse over the row's band [ty th, (ty + 1) th) in
+ * float32 with correctly rounded square roots and quotients, as tile columns
+ * clamped to the rectangle (a superset of the tiles holding a pixel centre
+ * with q <= qmax).  The pairs are radix-sorted by (view, depth); the lists
+ * are then built in two stable bucketing levels (pairs into tile rows, row
+ * entries into the tiles of their columns) without sorting instances.
+ * Instance slots (inst_base, the backward's partials) keep the rectangle
+ * layout.  With GESR_BIN_SYNC the call
  * synchronises `stream` once after counting; if M > m_cap it returns
  * GESR_ERR_CAPACITY with *m_out = M and leaves the sorted lists undefined.
  * Without it the call never synchronises (capturable in a HIP graph): lists

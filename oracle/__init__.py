@@ -139,8 +139,28 @@ def project(scene, st: Settings) -> dict:
     return r
 
 
-def bin_instances(N, cameras, tile_rect, tiles_touched, zbits, st: Settings):
-    """Stable-sorted (keys, vals, ranges[T, 2]) of the (tile | depth) instances."""
+def factor_record(rec) -> np.ndarray:
+    """Float32 record in the factored layout the binning decision reads:
+    u, v, L00, L10, L11, opacity, beta, qmax (columns 0-7 of 12) with
+    A = L00^2, B = L00 L10, C = L10^2 + L11^2 from the conic (A, B, C)."""
+    r = np.asarray(rec, np.float64).reshape(-1, 11)
+    out = np.zeros((r.shape[0], 12), np.float32)
+    A, B, C = r[:, 2], r[:, 3], r[:, 4]
+    with np.errstate(invalid="ignore", divide="ignore"):
+        L00 = np.sqrt(A)
+        L10 = B / L00
+        L11 = np.sqrt(np.maximum(C - L10 * L10, 0.0))
+    out[:, 0:2] = r[:, 0:2]
+    out[:, 2], out[:, 3], out[:, 4] = L00, L10, L11
+    out[:, 5:8] = r[:, 5:8]
+    return out
+
+
+def bin_instances(N, cameras, tile_rect, tiles_touched, zbits, st: Settings, rec):
+    """Stable-sorted (keys, vals, ranges[T, 2]) of the (tile | depth) instances:
+    each rectangle row keeps the columns its footprint ellipse reaches, decided
+    in float32 from `rec` ([V*N, 12] records in the factored layout of
+    factor_record; see row_columns_f32)."""
     V = len(cameras)
     tiles_touched = np.ascontiguousarray(tiles_touched, dtype=np.uint32)
     M = int(lib().orc_bin_count(ctypes.c_long(V * N), _p(tiles_touched)))
@@ -148,10 +168,23 @@ def bin_instances(N, cameras, tile_rect, tiles_touched, zbits, st: Settings):
     keys = np.zeros(max(M, 1), np.uint64)
     vals = np.zeros(max(M, 1), np.uint32)
     ranges = np.zeros((T, 2), np.uint32)
-    lib().orc_bin(N, V, _p(np.ascontiguousarray(tile_rect, np.int32)), _p(tiles_touched),
-                  _p(np.ascontiguousarray(zbits, np.uint32)), _p(views_array(cameras)), st.tile_w, st.tile_h,
-                  _p(keys), _p(vals), _p(ranges))
-    return keys[:M], vals[:M], ranges
+    rec = _f64(np.asarray(rec, np.float64).reshape(-1, 12)) if V * N > 0 else np.zeros((1, 12))
+    lib().orc_bin.restype = ctypes.c_long
+    L = int(lib().orc_bin(N, V, _p(np.ascontiguousarray(tile_rect, np.int32)), _p(tiles_touched),
+                          _p(np.ascontiguousarray(zbits, np.uint32)), _p(views_array(cameras)), st.tile_w, st.tile_h,
+                          _p(rec), _p(keys), _p(vals), _p(ranges)))
+    return keys[:L], vals[:L], ranges
+
+
+def bin_pair_counts(tile_rect, tiles_touched, rec, st: Settings) -> np.ndarray:
+    """Instances per pair under the per-row column rule of bin_instances."""
+    tiles_touched = np.ascontiguousarray(tiles_touched, dtype=np.uint32)
+    VN = tiles_touched.size
+    out = np.zeros(max(VN, 1), np.uint32)
+    rec = _f64(np.asarray(rec, np.float64).reshape(-1, 12)) if VN else np.zeros((1, 12))
+    lib().orc_bin_pair_counts(ctypes.c_long(VN), _p(np.ascontiguousarray(tile_rect, np.int32)), _p(tiles_touched),
+                              _p(rec), st.tile_w, st.tile_h, _p(out))
+    return out[:VN]
 
 
 def render_fwd(N, cameras, rec, vals, ranges, st: Settings, depth=None) -> dict:
@@ -416,7 +449,8 @@ def forward(scene, st: Settings, channels: bool = False) -> dict:
     """Full FP64 pipeline: project -> bin -> tiled render (with the extended
     depth and alpha channels when `channels`)."""
     pr = project(scene, st)
-    keys, vals, ranges = bin_instances(scene.n, scene.cameras, pr["tile_rect"], pr["tiles_touched"], pr["zbits"], st)
+    keys, vals, ranges = bin_instances(scene.n, scene.cameras, pr["tile_rect"], pr["tiles_touched"], pr["zbits"], st,
+                                       factor_record(pr["rec"]))
     out = render_fwd(scene.n, scene.cameras, pr["rec"], vals, ranges, st, depth=pr["depth"] if channels else None)
     out.update(proj=pr, keys=keys, vals=vals, ranges=ranges)
     return out

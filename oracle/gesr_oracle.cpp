@@ -468,6 +468,47 @@ void pixel_adjoint(const std::vector<Hit>& hits, double Tfinal, const double* g,
     }
 }
 
+// Tile columns of row ty that a pair's footprint ellipse reaches, decided in
+// float32 (the precision of the records the lists are built from): with
+// q = (L00 dx + L10 dy)^2 + (L11 dy)^2 and Q = qmax (1 + 2^-8), the x-extent
+// of {q <= Q} over the row's band [ty th, (ty + 1) th) -- at the ellipse's
+// rightmost (leftmost) point when that lies in the band, else at the band end
+// nearest to it -- as tile columns intersected with [c0, c1].  Empty rows give
+// c0 > c1; a non-finite value keeps [c0, c1].  IEEE float square roots and
+// quotients are correctly rounded, as are the GPU's.
+void row_columns_f32(const double* rec, int ty, int tw, int th, int* c0, int* c1) {
+    const float u = (float)rec[0], v = (float)rec[1], l00 = (float)rec[2], l10 = (float)rec[3], l11 = (float)rec[4];
+    const float qmax = (float)rec[7];
+    const float Q = qmax + qmax * 0.00390625f;
+    const float d0 = (float)(ty * th) - v;
+    const float d1 = (float)((ty + 1) * th) - v;
+    const float sq = std::sqrt(Q);
+    const float ym = sq / l11;
+    const float lo = d0 > -ym ? d0 : -ym;
+    const float hi = d1 < ym ? d1 : ym;
+    if (!(lo <= hi)) {
+        if (lo > hi) *c0 = *c1 + 1;
+        return;
+    }
+    const float rr = std::sqrt(l10 * l10 + l11 * l11);
+    const float dyr = -(l10 * sq) / (l11 * rr);
+    const float tr = dyr < lo ? lo : (dyr > hi ? hi : dyr);
+    const float tl = -dyr < lo ? lo : (-dyr > hi ? hi : -dyr);
+    const float sr = Q - (l11 * tr) * (l11 * tr);
+    const float sl = Q - (l11 * tl) * (l11 * tl);
+    const float xr = (-(l10 * tr) + std::sqrt(sr > 0.f ? sr : 0.f)) / l00;
+    const float xl = (-(l10 * tl) - std::sqrt(sl > 0.f ? sl : 0.f)) / l00;
+    const float X0 = u + xl, X1 = u + xr;
+    if (!(X0 <= X1) || !(X1 - X0 < 1e30f)) return;
+    const float inv = 1.0f / (float)tw;
+    const float f0 = std::floor(X0 * inv), f1 = std::floor(X1 * inv);
+    const int a = *c0, b = *c1;
+    const int n0 = f0 < (float)a ? a : (f0 > (float)b ? b + 1 : (int)f0);
+    const int n1 = f1 > (float)b ? b : (f1 < (float)a ? a - 1 : (int)f1);
+    *c0 = n0;
+    *c1 = n1;
+}
+
 int nthreads() {
 #ifdef _OPENMP
     return omp_get_max_threads();
@@ -554,8 +595,9 @@ long orc_total_tiles(int V, const double* views, int tile_w, int tile_h) {
 // (view, splat, tile-row, tile-column) order with key = tile << 32 | bits(z32)
 // and value = view * N + splat; stable sort by key; ranges[t] = [first, end)
 // of tile t in the sorted list ((0, 0) when empty).
-int orc_bin(int N, int V, const int32_t* tile_rect, const uint32_t* tiles_touched, const uint32_t* zbits,
-            const double* views, int tile_w, int tile_h, uint64_t* keys, uint32_t* vals, uint32_t* ranges) {
+long orc_bin(int N, int V, const int32_t* tile_rect, const uint32_t* tiles_touched, const uint32_t* zbits,
+             const double* views, int tile_w, int tile_h, const double* rec, uint64_t* keys, uint32_t* vals,
+             uint32_t* ranges) {
     std::vector<View> vw = read_views(views, V, tile_w, tile_h);
     long T = vw.back().tile_base + (long)vw.back().tiles_x * vw.back().tiles_y;
     std::vector<std::pair<uint64_t, uint32_t>> inst;
@@ -564,11 +606,14 @@ int orc_bin(int N, int V, const int32_t* tile_rect, const uint32_t* tiles_touche
             long o = (long)v * N + i;
             if (tiles_touched[o] == 0) continue;
             const int32_t* r = tile_rect + 4 * o;
-            for (int ty = r[1]; ty <= r[3]; ++ty)
-                for (int tx = r[0]; tx <= r[2]; ++tx) {
+            for (int ty = r[1]; ty <= r[3]; ++ty) {
+                int c0 = r[0], c1 = r[2];
+                row_columns_f32(rec + 12 * o, ty, tile_w, tile_h, &c0, &c1);
+                for (int tx = c0; tx <= c1; ++tx) {
                     uint64_t tile = (uint64_t)(vw[v].tile_base + (long)ty * vw[v].tiles_x + tx);
                     inst.emplace_back((tile << 32) | zbits[o], (uint32_t)o);
                 }
+            }
         }
     std::stable_sort(inst.begin(), inst.end(),
                      [](const std::pair<uint64_t, uint32_t>& a, const std::pair<uint64_t, uint32_t>& b) {
@@ -581,6 +626,26 @@ int orc_bin(int N, int V, const int32_t* tile_rect, const uint32_t* tiles_touche
         uint64_t t = inst[k].first >> 32;
         if (k == 0 || (inst[k - 1].first >> 32) != t) ranges[2 * t] = (uint32_t)k;
         ranges[2 * t + 1] = (uint32_t)(k + 1);
+    }
+    return (long)inst.size();
+}
+
+// Instances per pair under the same per-row column rule as orc_bin (counts
+// only; VN pairs, rec [VN][12] factored records).
+int orc_bin_pair_counts(long VN, const int32_t* tile_rect, const uint32_t* tiles_touched, const double* rec,
+                        int tile_w, int tile_h, uint32_t* counts) {
+#pragma omp parallel for schedule(dynamic, 4096)
+    for (long o = 0; o < VN; ++o) {
+        uint32_t c = 0;
+        if (tiles_touched[o] != 0) {
+            const int32_t* r = tile_rect + 4 * o;
+            for (int ty = r[1]; ty <= r[3]; ++ty) {
+                int c0 = r[0], c1 = r[2];
+                row_columns_f32(rec + 12 * o, ty, tile_w, tile_h, &c0, &c1);
+                if (c1 >= c0) c += (uint32_t)(c1 - c0 + 1);
+            }
+        }
+        counts[o] = c;
     }
     return 0;
 }

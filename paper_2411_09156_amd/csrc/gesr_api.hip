@@ -438,7 +438,8 @@ gesr_status gesr_bin(gesr_ctx* ctx, const gesr_proj* proj, const gesr_camera* ca
                            "view sort"));
         order_vd = spare_vals;
     }
-    // 4. row lists: every pair in the rows its rectangle covers (level 1)
+    // 4. row lists: every pair in the rows its rectangle covers (level 1), each
+    //    entry with the columns its ellipse reaches in that row
     GESR_TRY(hip_check(ctx, launch_gather_rects(order_vd, proj->tiles_touched, proj->rect, g.vn, s.srect, strm),
                        "rectangles"));
     IsArgs ia;
@@ -458,6 +459,9 @@ gesr_status gesr_bin(gesr_ctx* ctx, const gesr_proj* proj, const gesr_camera* ca
     l1.bucket_start = s.row_start;
     l1.out_vals = s.rowlist;
     l1.out_cap = bins->m_cap;
+    l1.row_rec = proj->rec;  // each row entry carries its own row's columns
+    l1.tile_w = st->tile_w;
+    l1.tile_h = st->tile_h;
     GESR_TRY(hip_check(ctx,
                        launch_interval_scatter(l1, 1, (uint32_t)g.total_rows, s.counters, s.seg_chunks,
                                                s.scan_partials, strm),
@@ -476,7 +480,8 @@ gesr_status gesr_bin(gesr_ctx* ctx, const gesr_proj* proj, const gesr_camera* ca
     l2.out_keys = bins->tile_sorted;
     l2.out_cap = bins->m_cap;
     GESR_TRY(hip_check(ctx,
-                       launch_interval_scatter(l2, 2, (uint32_t)T, nullptr, s.seg_chunks, s.scan_partials, strm),
+                       launch_interval_scatter(l2, 2, (uint32_t)T, bins->counters + 3, s.seg_chunks, s.scan_partials,
+                                               strm),
                        "tile lists"));
     GESR_TRY(hip_check(ctx, launch_ranges_from_counts(s.tile_count, s.tile_start, T, bins->counters + 2,
                                                       bins->ranges, strm),

@@ -393,9 +393,65 @@ __device__ __forceinline__ Seg locate_segment(const IsArgs& a, uint32_t s) {
     return g;
 }
 
+// The ellipse of a projected record, q = (L00 dx + L10 dy)^2 + (L11 dy)^2 <= Q
+// with Q its footprint bound widened by 2^-8 (so that float32 rounding can
+// only widen what follows).
+struct Ellipse {
+    float u, v, l00, l10, l11, Q;
+};
+
+__device__ __forceinline__ Ellipse load_ellipse(const float* rec, uint32_t vi) {
+    const float4* r = reinterpret_cast<const float4*>(rec + (size_t)vi * GESR_REC_FLOATS);
+    const float4 a = r[0], b = r[1];
+    Ellipse e;
+    e.u = a.x;
+    e.v = a.y;
+    e.l00 = a.z;
+    e.l10 = a.w;
+    e.l11 = b.x;
+    e.Q = b.w + b.w * 0.00390625f;
+    return e;
+}
+
+// Columns of tile row ty that the ellipse can reach: the x-extent of the
+// ellipse over the row's band [ty th, (ty + 1) th) (continuous, a superset of
+// its pixel centres), as tile columns clamped to [tx0, tx1]; tx0 | tx1 << 16
+// unchanged when a value is not finite, 1 | 0 << 16 (empty) when the band
+// misses the ellipse.  Over a band the right end x_r(dy) = (-L10 dy +
+// sqrt(Q - (L11 dy)^2)) / L00 is concave, so its maximum is at the ellipse's
+// rightmost point clamped into the band (the left end mirrors it).  Square
+// roots (sqrtf) and quotients (__fdiv_rn) are correctly rounded, so the
+// decision is reproducible.
+__device__ __forceinline__ uint32_t row_columns(const Ellipse& e, int ty, int tw, int th, int tx0, int tx1) {
+    const uint32_t full = (uint32_t)tx0 | ((uint32_t)tx1 << 16);
+    const float d0 = (float)(ty * th) - e.v;
+    const float d1 = (float)((ty + 1) * th) - e.v;
+    const float sq = sqrtf(e.Q);
+    const float ym = __fdiv_rn(sq, e.l11);
+    const float lo = d0 > -ym ? d0 : -ym;
+    const float hi = d1 < ym ? d1 : ym;
+    if (!(lo <= hi)) return (lo > hi) ? 1u : full;  // empty band (NaN: keep the rectangle)
+    const float rr = sqrtf(e.l10 * e.l10 + e.l11 * e.l11);
+    const float dyr = __fdiv_rn(-(e.l10 * sq), e.l11 * rr);  // dy of the rightmost point
+    const float tr = dyr < lo ? lo : (dyr > hi ? hi : dyr);
+    const float tl = -dyr < lo ? lo : (-dyr > hi ? hi : -dyr);
+    const float sr = e.Q - (e.l11 * tr) * (e.l11 * tr);
+    const float sl = e.Q - (e.l11 * tl) * (e.l11 * tl);
+    const float xr = __fdiv_rn(-(e.l10 * tr) + sqrtf(sr > 0.f ? sr : 0.f), e.l00);
+    const float xl = __fdiv_rn(-(e.l10 * tl) - sqrtf(sl > 0.f ? sl : 0.f), e.l00);
+    const float X0 = e.u + xl, X1 = e.u + xr;
+    if (!(X0 <= X1) || !(X1 - X0 < 1e30f)) return full;
+    const float inv = 1.0f / (float)tw;  // tile widths are powers of two: exact
+    const float f0 = floorf(X0 * inv), f1 = floorf(X1 * inv);
+    const int c0 = f0 < (float)tx0 ? tx0 : (f0 > (float)tx1 ? tx1 + 1 : (int)f0);
+    const int c1 = f1 > (float)tx1 ? tx1 : (f1 < (float)tx0 ? tx0 - 1 : (int)f1);
+    if (c0 > c1) return 1u;
+    return (uint32_t)c0 | ((uint32_t)c1 << 16);
+}
+
 // Item idx of a segment: its value and its bucket interval [a0, a1] (empty when
-// a0 > a1) before windowing, and (level 1) the columns carried to level 2.
-// Both inputs are read in item order (coalesced).
+// a0 > a1) before windowing, and (level 1) the rectangle's columns.  Both
+// inputs are read in item order (coalesced).
 template <int LEVEL>
 __device__ __forceinline__ void load_item(const IsArgs& a, uint32_t idx, uint32_t end, uint32_t& p, int& a0,
                                           int& a1, uint32_t& cols) {
@@ -617,8 +673,17 @@ __global__ __launch_bounds__(IS_THREADS) void k_is_chunks(IsArgs a) {
                     for (uint32_t j = lane; j < n_b; j += 64) {
                         const uint32_t pos = dst + j;
                         if (pos < a.out_cap) {
-                            a.out_vals[pos] = s_stage[src + j];
-                            if (LEVEL == 1) a.out_cols[pos] = s_stage_c[src + j];
+                            const uint32_t pv = s_stage[src + j];
+                            a.out_vals[pos] = pv;
+                            if (LEVEL == 1) {
+                                // the columns of the pair's rectangle that its ellipse
+                                // reaches in this entry's row (view row g.lo_off + b)
+                                uint32_t c = s_stage_c[src + j];
+                                if (a.row_rec != nullptr)
+                                    c = row_columns(load_ellipse(a.row_rec, pv), g.lo_off + b, a.tile_w, a.tile_h,
+                                                    (int)(c & 0xFFFFu), (int)(c >> 16));
+                                a.out_cols[pos] = c;
+                            }
                             if (a.out_keys) a.out_keys[pos] = g.bucket0 + (uint32_t)b;
                         }
                     }

@@ -159,6 +159,8 @@ struct IsArgs {
     uint32_t* out_keys;             // nullable: bucket id of every entry
     uint32_t* out_cols;             // level 1: columns of every entry (tx0 | tx1 << 16)
     uint64_t out_cap;
+    const float* row_rec;           // level 1 (nullable): projected records; each entry then carries
+    int tile_w, tile_h;             //   the columns its ellipse reaches in the entry's row
     DevCams cams;
 };
 uint32_t is_segments(const DevCams& cams, int level);

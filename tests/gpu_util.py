@@ -57,7 +57,8 @@ def run_gpu(scene, st: oracle.Settings, counts=True, rast=None, **kw) -> dict:
     cnt = u32(b["counters"])
     res["M"] = int(cnt[0])
     res["overflow"] = int(cnt[1])
-    M = min(res["M"], b["m_cap"])
+    res["listed"] = int(cnt[3])
+    M = min(res["listed"], b["m_cap"])
     res["tile_sorted"] = u32(b["tile_sorted"])[:M]
     res["val_sorted"] = u32(b["val_sorted"])[:M]
     T = b["total_tiles"]

@@ -134,13 +134,16 @@ def test_project(name):
 
 @pytest.mark.parametrize("name", CASES)
 def test_bin_bit_exact(name):
-    """Oracle binning of the GPU's own per-splat results (rect, depth key) equals
-    the GPU's sorted instance list, ranges, count and instance bases exactly."""
+    """Oracle binning of the GPU's own per-splat results (record, rect, depth
+    key) equals the GPU's sorted instance list, ranges, counts and instance
+    bases exactly (each rectangle row's columns decided in float32 from the
+    record on both sides)."""
     scene, st, g = _run(name)
     keys, vals, ranges = oracle.bin_instances(scene.n, scene.cameras, g["tile_rect"], g["tiles_touched"],
-                                              g["depth_key"], st)
+                                              g["depth_key"], st, g["rec"])
     assert g["overflow"] == 0
-    assert g["M"] == len(vals)
+    assert g["M"] == int(g["tiles_touched"].astype(np.int64).sum()) >= g["listed"]
+    assert g["listed"] == len(vals)
     np.testing.assert_array_equal(g["val_sorted"], vals)
     np.testing.assert_array_equal(g["tile_sorted"].astype(np.uint64), keys >> np.uint64(32))
     np.testing.assert_array_equal(g["depth_key"][g["val_sorted"]].astype(np.uint64), keys & np.uint64(0xFFFFFFFF))

@@ -297,16 +297,21 @@ def test_compositing_invariants_on_plain_workload():
 # ------------------------------------------------------------------- binning
 def test_binning_brute_force():
     """Tile binning (tile | depth keys, stable order): tiles_touched equals the
-    number of tiles meeting each pixel rectangle, the sorted list equals a
-    lexicographic sort on (tile, z32, view*N + splat), and ranges partition [0, M)."""
+    number of tiles meeting each pixel rectangle; the lists hold, per pair, a
+    subset of its rectangle's tiles that contains every tile with a pixel
+    centre inside the footprint (q <= qmax, brute force in float64 over all
+    pixels) and drops some of the others; they are sorted by (tile, z32,
+    view*N + splat) and the ranges partition them."""
     st = oracle.Settings(tile_w=8, tile_h=8)
     sc = gi.tiny_scene(5, n=30, width=50, height=37, n_views=2)
     pr = oracle.project(sc, st)
     grid, T = oracle.tile_grid(sc.cameras, 8, 8)
     N = sc.n
-    inst = []
+    rect_total = 0
+    need = set()
     for v, cam in enumerate(sc.cameras):
         tx_n, ty_n, base = grid[v]
+        ys, xs = np.mgrid[0:cam.height, 0:cam.width]
         for i in range(N):
             o = v * N + i
             cnt = 0
@@ -316,13 +321,29 @@ def test_binning_brute_force():
                     for tx in range(tx_n):
                         if tx * 8 <= x1 and tx * 8 + 7 >= x0 and ty * 8 <= y1 and ty * 8 + 7 >= y0:
                             cnt += 1
-                            inst.append((base + ty * tx_n + tx, int(pr["zbits"][o]), o))
+                u, vv, A, B, C = pr["rec"][o, :5]
+                dx, dy = xs + 0.5 - u, ys + 0.5 - vv
+                q = A * dx * dx + 2 * B * dx * dy + C * dy * dy
+                for y, x in zip(*np.nonzero(q <= pr["rec"][o, 7])):
+                    need.add((base + (y // 8) * tx_n + x // 8, o))
             assert pr["tiles_touched"][o] == cnt
-    inst.sort()
-    keys, vals, ranges = oracle.bin_instances(N, sc.cameras, pr["tile_rect"], pr["tiles_touched"], pr["zbits"], st)
-    assert len(vals) == len(inst) > 100
+            rect_total += cnt
+    keys, vals, ranges = oracle.bin_instances(N, sc.cameras, pr["tile_rect"], pr["tiles_touched"], pr["zbits"], st,
+                                              oracle.factor_record(pr["rec"]))
+    tiles = (keys >> np.uint64(32)).astype(np.int64)
+    listed = set(zip(tiles.tolist(), vals.tolist()))
+    assert len(listed) == len(vals) > 100
+    assert need <= listed
+    assert len(vals) < rect_total
+    for t, o in listed:  # inside the pair's rectangle
+        v = o // N
+        tx_n, ty_n, base = grid[v]
+        tx, ty = (t - base) % tx_n, (t - base) // tx_n
+        r = pr["tile_rect"][o]
+        assert r[0] <= tx <= r[2] and r[1] <= ty <= r[3]
+    inst = sorted((int(t), int(pr["zbits"][o]), int(o)) for t, o in listed)
     np.testing.assert_array_equal(vals, [e[2] for e in inst])
-    np.testing.assert_array_equal(keys >> np.uint64(32), [e[0] for e in inst])
+    np.testing.assert_array_equal(tiles, [e[0] for e in inst])
     np.testing.assert_array_equal(keys & np.uint64(0xFFFFFFFF), [e[1] for e in inst])
     lens = ranges[:, 1].astype(np.int64) - ranges[:, 0]
     assert lens.sum() == len(vals)
