@@ -56,7 +56,8 @@ SURFACE_SLOTS_PER_SAMPLE = 16
 # HBM bytes per launch of the tile adjoint on the default workload, from two
 # rocprofv3 counter passes (FETCH_SIZE x2.0, WRITE_SIZE x1.0 after calibration
 # against a 1 GiB copy; profiles/drt-500k-8views_hbm_counters.md).  Valid only
-# for the kernel source it was measured on (fingerprint below); otherwise null.
+# for the kernel source it was measured on (fingerprint below: the kernel and the
+# binning that builds the tile lists it walks); otherwise null.
 MEASURED_TRAFFIC = {"kernel": "render_bwd_tiles", "workload": "drt-batch-500k-8views",
                     "fingerprint": "5250e482c3f24352", "bytes": 4178504602,
                     "settings": (16, 16, 0, 64)}  # tile_w, tile_h, variant, batch of the measured run
@@ -65,7 +66,7 @@ MEASURED_TRAFFIC = {"kernel": "render_bwd_tiles", "workload": "drt-batch-500k-8v
 def kernel_fingerprint():
     import hashlib
     h = hashlib.sha256()
-    for f in ("gesr_render.hip", "gesr_device.h"):
+    for f in ("gesr_render.hip", "gesr_device.h", "gesr_bin.hip"):
         with open(os.path.join(ROOT, "paper_2411_09156_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -352,6 +352,62 @@ def test_binning_brute_force():
         assert all(k >> 32 == t for k in keys[s0:s1])
 
 
+def _box_min_q(l00, l10, l11, dx0, dx1, dy0, dy1):
+    """Minimum over the box [dx0, dx1] x [dy0, dy1] of the convex quadratic
+    q = (l00 dx + l10 dy)^2 + (l11 dy)^2 (float64): 0 when the box holds the
+    centre, else the least of the four edge minima, each a one-dimensional
+    quadratic minimised at its clamped stationary point."""
+    a, b, c = l00 * l00, l00 * l10, l10 * l10 + l11 * l11
+
+    def q(dx, dy):
+        return a * dx * dx + 2 * b * dx * dy + c * dy * dy
+    if dx0 <= 0 <= dx1 and dy0 <= 0 <= dy1:
+        return 0.0
+    best = np.inf
+    for dx in (dx0, dx1):  # vertical edges: q(dy) minimal at dy = -b dx / c
+        best = min(best, q(dx, min(max(-b * dx / c, dy0), dy1)))
+    for dy in (dy0, dy1):  # horizontal edges: dx = -b dy / a
+        best = min(best, q(min(max(-b * dy / a, dx0), dx1), dy))
+    return best
+
+
+@pytest.mark.parametrize("tile", [(8, 8), (16, 16), (32, 16)])
+def test_tile_lists_are_the_tiles_the_widened_ellipse_meets(tile):
+    """Reading of the tile coverage: within its rectangle a pair is listed in
+    exactly the tiles whose box meets the ellipse q <= Q, Q = qmax (1 + 2^-8),
+    checked against the minimum of q over each tile box (an independent
+    characterisation of the oracle's per-row x-extents), except where that
+    minimum lies within float32 rounding of Q."""
+    tw, th = tile
+    st = oracle.Settings(tile_w=tw, tile_h=th)
+    sc = gi.tiny_scene(11, n=300, width=97, height=75, n_views=2)
+    pr = oracle.project(sc, st)
+    rec = oracle.factor_record(pr["rec"])
+    grid, _ = oracle.tile_grid(sc.cameras, tw, th)
+    keys, vals, _ = oracle.bin_instances(sc.n, sc.cameras, pr["tile_rect"], pr["tiles_touched"], pr["zbits"], st, rec)
+    listed = set(zip((keys >> np.uint64(32)).astype(np.int64).tolist(), vals.tolist()))
+    checked = near = dropped = 0
+    for o in range(len(sc.cameras) * sc.n):
+        if pr["tiles_touched"][o] == 0:
+            continue
+        tx_n, _, base = grid[o // sc.n]
+        u, v, l00, l10, l11 = (float(x) for x in rec[o, :5])
+        qmax = np.float32(rec[o, 7])
+        Q = float(qmax + qmax * np.float32(2.0 ** -8))
+        tx0, ty0, tx1, ty1 = (int(x) for x in pr["tile_rect"][o])
+        for ty in range(ty0, ty1 + 1):
+            for tx in range(tx0, tx1 + 1):
+                m = _box_min_q(l00, l10, l11, tx * tw - u, (tx + 1) * tw - u, ty * th - v, (ty + 1) * th - v)
+                if abs(m - Q) <= 1e-4 * Q:
+                    near += 1
+                    continue
+                checked += 1
+                is_listed = (base + ty * tx_n + tx, o) in listed
+                assert is_listed == (m < Q), (o, tx, ty, m, Q)
+                dropped += not is_listed
+    assert checked > 1000 and dropped >= 50 and near < 0.01 * checked
+
+
 def test_depth_key_is_float32_rounding_of_depth():
     st = oracle.Settings()
     sc = gi.tiny_scene(1, n=50)
