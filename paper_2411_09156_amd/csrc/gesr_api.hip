@@ -169,6 +169,7 @@ struct BinScratch {
     uint32_t *d_keys_a, *d_vals_a, *d_keys_b, *d_vals_b;  // depth and view sort, [V*n]
     uint32_t *rowlist, *rowcols;                          // row lists and their columns, [m_cap]
     uint2* srect;                                         // rectangles in (view, depth) order, [V*n]
+    float4* sell;                                         // footprint ellipses in that order, [2 V*n]
     uint32_t *row_count, *row_start;                      // [total rows]
     uint32_t *seg_chunks, *chunk_off;                     // [segments + 1]
     uint32_t* mat;                                        // per-chunk bucket counts
@@ -202,6 +203,7 @@ BinScratch carve(void* base, const Geometry& g, const DevCams& dc, int n, uint64
     s.rowlist = take(m_cap);
     s.rowcols = take(m_cap);
     s.srect = reinterpret_cast<uint2*>(take(2 * vn1));
+    s.sell = reinterpret_cast<float4*>(take(8 * vn1));
     s.row_count = take(g.total_rows + 1);
     s.row_start = take(g.total_rows + 1);
     s.seg_chunks = take(nseg);
@@ -440,7 +442,9 @@ gesr_status gesr_bin(gesr_ctx* ctx, const gesr_proj* proj, const gesr_camera* ca
     }
     // 4. row lists: every pair in the rows its rectangle covers (level 1), each
     //    entry with the columns its ellipse reaches in that row
-    GESR_TRY(hip_check(ctx, launch_gather_rects(order_vd, proj->tiles_touched, proj->rect, g.vn, s.srect, strm),
+    GESR_TRY(hip_check(ctx,
+                       launch_gather_rects(order_vd, proj->tiles_touched, proj->rect, proj->rec, g.vn, s.srect,
+                                           s.sell, strm),
                        "rectangles"));
     IsArgs ia;
     memset(&ia, 0, sizeof ia);
@@ -459,7 +463,7 @@ gesr_status gesr_bin(gesr_ctx* ctx, const gesr_proj* proj, const gesr_camera* ca
     l1.bucket_start = s.row_start;
     l1.out_vals = s.rowlist;
     l1.out_cap = bins->m_cap;
-    l1.row_rec = proj->rec;  // each row entry carries its own row's columns
+    l1.item_ell = s.sell;  // each row entry carries its own row's columns
     l1.tile_w = st->tile_w;
     l1.tile_h = st->tile_h;
     GESR_TRY(hip_check(ctx,

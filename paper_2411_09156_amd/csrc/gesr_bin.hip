@@ -301,12 +301,72 @@ hipError_t sort_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, u
 }
 
 // ----------------------------------------------------------------- binning
+// The footprint ellipse of a projected record, q = (L00 dx + L10 dy)^2 +
+// (L11 dy)^2 <= Q, with Q its bound qmax widened by 2^-8 (so that float32
+// rounding can only widen what follows), and the two row-independent
+// quantities of its per-row extents: ym = sqrt(Q) / L11, the half-height, and
+// dyr = -L10 sqrt(Q) / (L11 sqrt(L10^2 + L11^2)), the dy of its rightmost
+// point (the leftmost is at -dyr).  Stored per item as (u, v, L00, L10),
+// (L11, Q, ym, dyr).  Square roots (sqrtf) and quotients (__fdiv_rn) are
+// correctly rounded, so the values are reproducible.
+__device__ __forceinline__ void row_ellipse(const float* rec, uint32_t vi, float4& e0, float4& e1) {
+    const float4* r = reinterpret_cast<const float4*>(rec + (size_t)vi * GESR_REC_FLOATS);
+    const float4 a = r[0], b = r[1];
+    const float l10 = a.w, l11 = b.x;
+    const float Q = b.w + b.w * 0.00390625f;
+    const float sq = sqrtf(Q);
+    const float rr = sqrtf(l10 * l10 + l11 * l11);
+    e0 = a;
+    e1 = make_float4(l11, Q, __fdiv_rn(sq, l11), __fdiv_rn(-(l10 * sq), l11 * rr));
+}
+
+// Columns of tile row ty that the ellipse (e0, e1) can reach: the x-extent of
+// the ellipse over the row's band [ty th, (ty + 1) th) (continuous, a superset
+// of its pixel centres), as tile columns clamped to [tx0, tx1]; tx0 | tx1 << 16
+// unchanged when a value is not finite, 1 | 0 << 16 (empty) when the band
+// misses the ellipse.  Over a band the right end x_r(dy) = (-L10 dy +
+// sqrt(Q - (L11 dy)^2)) / L00 is concave, so its maximum is at the ellipse's
+// rightmost point clamped into the band (the left end mirrors it).
+__device__ __forceinline__ uint32_t row_columns(const float4& e0, const float4& e1, int ty, int tw, int th, int tx0,
+                                                int tx1) {
+    const float u = e0.x, v = e0.y, l00 = e0.z, l10 = e0.w;
+    const float l11 = e1.x, Q = e1.y, ym = e1.z, dyr = e1.w;
+    const uint32_t full = (uint32_t)tx0 | ((uint32_t)tx1 << 16);
+    const float d0 = (float)(ty * th) - v;
+    const float d1 = (float)((ty + 1) * th) - v;
+    const float lo = d0 > -ym ? d0 : -ym;
+    const float hi = d1 < ym ? d1 : ym;
+    if (!(lo <= hi)) return (lo > hi) ? 1u : full;  // empty band (NaN: keep the rectangle)
+    const float tr = dyr < lo ? lo : (dyr > hi ? hi : dyr);
+    const float tl = -dyr < lo ? lo : (-dyr > hi ? hi : -dyr);
+    const float sr = Q - (l11 * tr) * (l11 * tr);
+    const float sl = Q - (l11 * tl) * (l11 * tl);
+    const float xr = __fdiv_rn(-(l10 * tr) + sqrtf(sr > 0.f ? sr : 0.f), l00);
+    const float xl = __fdiv_rn(-(l10 * tl) - sqrtf(sl > 0.f ? sl : 0.f), l00);
+    const float X0 = u + xl, X1 = u + xr;
+    if (!(X0 <= X1) || !(X1 - X0 < 1e30f)) return full;
+    const float inv = 1.0f / (float)tw;  // tile widths are powers of two: exact
+    const float f0 = floorf(X0 * inv), f1 = floorf(X1 * inv);
+    const int c0 = f0 < (float)tx0 ? tx0 : (f0 > (float)tx1 ? tx1 + 1 : (int)f0);
+    const int c1 = f1 > (float)tx1 ? tx1 : (f1 < (float)tx0 ? tx0 - 1 : (int)f1);
+    if (c0 > c1) return 1u;
+    return (uint32_t)c0 | ((uint32_t)c1 << 16);
+}
+
 __global__ __launch_bounds__(256) void k_gather_rects(const uint32_t* order, const uint32_t* tiles_touched,
-                                                      const uint32_t* rect, uint64_t count, uint2* out) {
+                                                      const uint32_t* rect, const float* rec, uint64_t count,
+                                                      uint2* out, float4* ell) {
     const uint64_t k = (uint64_t)blockIdx.x * 256 + threadIdx.x;
     if (k >= count) return;
     const uint32_t p = order[k];
-    out[k] = tiles_touched[p] ? reinterpret_cast<const uint2*>(rect)[p] : make_uint2(0xFFFFFFFFu, 0u);
+    const bool touched = tiles_touched[p] != 0;
+    out[k] = touched ? reinterpret_cast<const uint2*>(rect)[p] : make_uint2(0xFFFFFFFFu, 0u);
+    if (ell != nullptr) {
+        float4 e0 = make_float4(0.f, 0.f, 0.f, 0.f), e1 = e0;
+        if (touched) row_ellipse(rec, p, e0, e1);
+        ell[2 * k] = e0;
+        ell[2 * k + 1] = e1;
+    }
 }
 
 // keys[k] = view of the pair vals[k] (pairs are numbered view * n + splat).
@@ -391,62 +451,6 @@ __device__ __forceinline__ Seg locate_segment(const IsArgs& a, uint32_t s) {
     g.lo_off = 0;
     g.width = 0;
     return g;
-}
-
-// The ellipse of a projected record, q = (L00 dx + L10 dy)^2 + (L11 dy)^2 <= Q
-// with Q its footprint bound widened by 2^-8 (so that float32 rounding can
-// only widen what follows).
-struct Ellipse {
-    float u, v, l00, l10, l11, Q;
-};
-
-__device__ __forceinline__ Ellipse load_ellipse(const float* rec, uint32_t vi) {
-    const float4* r = reinterpret_cast<const float4*>(rec + (size_t)vi * GESR_REC_FLOATS);
-    const float4 a = r[0], b = r[1];
-    Ellipse e;
-    e.u = a.x;
-    e.v = a.y;
-    e.l00 = a.z;
-    e.l10 = a.w;
-    e.l11 = b.x;
-    e.Q = b.w + b.w * 0.00390625f;
-    return e;
-}
-
-// Columns of tile row ty that the ellipse can reach: the x-extent of the
-// ellipse over the row's band [ty th, (ty + 1) th) (continuous, a superset of
-// its pixel centres), as tile columns clamped to [tx0, tx1]; tx0 | tx1 << 16
-// unchanged when a value is not finite, 1 | 0 << 16 (empty) when the band
-// misses the ellipse.  Over a band the right end x_r(dy) = (-L10 dy +
-// sqrt(Q - (L11 dy)^2)) / L00 is concave, so its maximum is at the ellipse's
-// rightmost point clamped into the band (the left end mirrors it).  Square
-// roots (sqrtf) and quotients (__fdiv_rn) are correctly rounded, so the
-// decision is reproducible.
-__device__ __forceinline__ uint32_t row_columns(const Ellipse& e, int ty, int tw, int th, int tx0, int tx1) {
-    const uint32_t full = (uint32_t)tx0 | ((uint32_t)tx1 << 16);
-    const float d0 = (float)(ty * th) - e.v;
-    const float d1 = (float)((ty + 1) * th) - e.v;
-    const float sq = sqrtf(e.Q);
-    const float ym = __fdiv_rn(sq, e.l11);
-    const float lo = d0 > -ym ? d0 : -ym;
-    const float hi = d1 < ym ? d1 : ym;
-    if (!(lo <= hi)) return (lo > hi) ? 1u : full;  // empty band (NaN: keep the rectangle)
-    const float rr = sqrtf(e.l10 * e.l10 + e.l11 * e.l11);
-    const float dyr = __fdiv_rn(-(e.l10 * sq), e.l11 * rr);  // dy of the rightmost point
-    const float tr = dyr < lo ? lo : (dyr > hi ? hi : dyr);
-    const float tl = -dyr < lo ? lo : (-dyr > hi ? hi : -dyr);
-    const float sr = e.Q - (e.l11 * tr) * (e.l11 * tr);
-    const float sl = e.Q - (e.l11 * tl) * (e.l11 * tl);
-    const float xr = __fdiv_rn(-(e.l10 * tr) + sqrtf(sr > 0.f ? sr : 0.f), e.l00);
-    const float xl = __fdiv_rn(-(e.l10 * tl) - sqrtf(sl > 0.f ? sl : 0.f), e.l00);
-    const float X0 = e.u + xl, X1 = e.u + xr;
-    if (!(X0 <= X1) || !(X1 - X0 < 1e30f)) return full;
-    const float inv = 1.0f / (float)tw;  // tile widths are powers of two: exact
-    const float f0 = floorf(X0 * inv), f1 = floorf(X1 * inv);
-    const int c0 = f0 < (float)tx0 ? tx0 : (f0 > (float)tx1 ? tx1 + 1 : (int)f0);
-    const int c1 = f1 > (float)tx1 ? tx1 : (f1 < (float)tx0 ? tx0 - 1 : (int)f1);
-    if (c0 > c1) return 1u;
-    return (uint32_t)c0 | ((uint32_t)c1 << 16);
 }
 
 // Item idx of a segment: its value and its bucket interval [a0, a1] (empty when
@@ -536,7 +540,10 @@ __global__ __launch_bounds__(IS_THREADS) void k_is_chunks(IsArgs a) {
     constexpr int STAGE = MODE == 0 ? 1 : (LEVEL == 1 ? IS_STAGE / 2 : IS_STAGE);
     // + 64 slots that absorb the writes of lanes not covering the current bucket
     __shared__ uint32_t s_stage[STAGE + 64];
-    __shared__ uint32_t s_stage_c[LEVEL == 1 && MODE == 1 ? STAGE + 64 : 1];
+    // level 1: the chunk's item values and rectangle columns; the stage holds
+    // chunk-local item indices
+    __shared__ uint32_t s_item_p[LEVEL == 1 && MODE == 1 ? IS_CHUNK : 1];
+    __shared__ uint32_t s_item_c[LEVEL == 1 && MODE == 1 ? IS_CHUNK : 1];
     const uint32_t lane = __lane_id(), wave = threadIdx.x / 64;
     const uint32_t item0 = wave * (64 * IS_IPL) + lane;  // chunk-local index of this lane's first item
     // a contiguous share of the chunks per block: the segment is looked up once
@@ -574,6 +581,13 @@ __global__ __launch_bounds__(IS_THREADS) void k_is_chunks(IsArgs a) {
         for (int u = 0; u < IS_IPL; ++u)
             load_item<LEVEL>(a, idx_n + 64 * u, same ? g.end : 0u, p_n[u], a0_n[u], a1_n[u], cols_n[u]);
         for (int j = threadIdx.x; j < IS_WAVES * (IS_W + 1); j += IS_THREADS) (&s_cnt[0][0])[j] = 0;
+        if (LEVEL == 1 && MODE == 1) {
+#pragma unroll
+            for (int u = 0; u < IS_IPL; ++u) {
+                s_item_p[item0 + 64 * u] = p[u];
+                s_item_c[item0 + 64 * u] = cols[u];
+            }
+        }
         __syncthreads();
 #pragma unroll
         for (int u = 0; u < IS_IPL; ++u)
@@ -656,8 +670,7 @@ __global__ __launch_bounds__(IS_THREADS) void k_is_chunks(IsArgs a) {
                                 (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
                             const uint32_t sel = 0u - (uint32_t)hit;  // all ones on the bucket
                             const uint32_t q = spare ^ (((base + rank) ^ spare) & sel);
-                            s_stage[q] = p[u];
-                            if (LEVEL == 1) s_stage_c[q] = cols[u];
+                            s_stage[q] = LEVEL == 1 ? item0 + 64u * (uint32_t)u : p[u];
                             base += (uint32_t)__popcll(m);
                         }
                     };
@@ -673,16 +686,20 @@ __global__ __launch_bounds__(IS_THREADS) void k_is_chunks(IsArgs a) {
                     for (uint32_t j = lane; j < n_b; j += 64) {
                         const uint32_t pos = dst + j;
                         if (pos < a.out_cap) {
-                            const uint32_t pv = s_stage[src + j];
-                            a.out_vals[pos] = pv;
                             if (LEVEL == 1) {
                                 // the columns of the pair's rectangle that its ellipse
                                 // reaches in this entry's row (view row g.lo_off + b)
-                                uint32_t c = s_stage_c[src + j];
-                                if (a.row_rec != nullptr)
-                                    c = row_columns(load_ellipse(a.row_rec, pv), g.lo_off + b, a.tile_w, a.tile_h,
+                                const uint32_t li = s_stage[src + j];
+                                uint32_t c = s_item_c[li];
+                                if (a.item_ell != nullptr) {
+                                    const float4* e = a.item_ell + 2 * ((size_t)(idx - item0) + li);
+                                    c = row_columns(e[0], e[1], g.lo_off + b, a.tile_w, a.tile_h,
                                                     (int)(c & 0xFFFFu), (int)(c >> 16));
+                                }
+                                a.out_vals[pos] = s_item_p[li];
                                 a.out_cols[pos] = c;
+                            } else {
+                                a.out_vals[pos] = s_stage[src + j];
                             }
                             if (a.out_keys) a.out_keys[pos] = g.bucket0 + (uint32_t)b;
                         }
@@ -852,9 +869,10 @@ hipError_t radix_sort(const uint32_t* keys_in, const uint32_t* vals_in, uint64_t
 }
 
 hipError_t launch_gather_rects(const uint32_t* order, const uint32_t* tiles_touched, const uint32_t* rect,
-                               uint64_t count, uint2* out, hipStream_t stream) {
+                               const float* rec, uint64_t count, uint2* out, float4* ell, hipStream_t stream) {
     if (count == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_gather_rects, grid_for(count), dim3(256), 0, stream, order, tiles_touched, rect, count, out);
+    hipLaunchKernelGGL(k_gather_rects, grid_for(count), dim3(256), 0, stream, order, tiles_touched, rect, rec, count,
+                       out, ell);
     return hipGetLastError();
 }
 

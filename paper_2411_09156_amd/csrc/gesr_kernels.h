@@ -132,9 +132,10 @@ int radix_passes(int key_bits, int radix_bits);
 
 // Binning helper kernels.
 hipError_t launch_view_keys(const uint32_t* vals, uint64_t count, uint32_t n, uint32_t* keys, hipStream_t stream);
-// out[k] = rect[order[k]], or the empty rectangle (x = 0xFFFFFFFF) when the pair touches no tile.
+// out[k] = rect[order[k]], or the empty rectangle (x = 0xFFFFFFFF) when the pair touches no tile;
+// with ell (nullable, [2 count]) also the pair's footprint ellipse and its per-row constants.
 hipError_t launch_gather_rects(const uint32_t* order, const uint32_t* tiles_touched, const uint32_t* rect,
-                               uint64_t count, uint2* out, hipStream_t stream);
+                               const float* rec, uint64_t count, uint2* out, float4* ell, hipStream_t stream);
 
 // Interval scatter (tile lists from rectangles, see gesr_bin.hip).  Level 1
 // writes each pair into the row lists of the rows its rectangle covers; level
@@ -159,8 +160,8 @@ struct IsArgs {
     uint32_t* out_keys;             // nullable: bucket id of every entry
     uint32_t* out_cols;             // level 1: columns of every entry (tx0 | tx1 << 16)
     uint64_t out_cap;
-    const float* row_rec;           // level 1 (nullable): projected records; each entry then carries
-    int tile_w, tile_h;             //   the columns its ellipse reaches in the entry's row
+    const float4* item_ell;         // level 1 (nullable): per item, the footprint ellipse; each entry
+    int tile_w, tile_h;             //   then carries the columns it reaches in the entry's row
     DevCams cams;
 };
 uint32_t is_segments(const DevCams& cams, int level);
