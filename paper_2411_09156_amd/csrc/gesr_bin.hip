@@ -533,7 +533,7 @@ __device__ __forceinline__ void wave_prefix_row(int* row) {
 constexpr int IS_STAGE = 16384;
 
 template <int LEVEL, int MODE>
-__global__ __launch_bounds__(IS_THREADS) void k_is_chunks(IsArgs a) {
+__global__ __launch_bounds__(IS_THREADS) __attribute__((amdgpu_waves_per_eu(8))) void k_is_chunks(IsArgs a) {
     __shared__ int s_cnt[IS_WAVES][IS_W + 1];
     __shared__ uint32_t s_ls[IS_W + 1];  // chunk-local first entry of each bucket
     __shared__ uint32_t s_gb[IS_W];      // global position of that entry
