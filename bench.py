@@ -59,7 +59,7 @@ SURFACE_SLOTS_PER_SAMPLE = 16
 # for the kernel source it was measured on (fingerprint below: the kernel and the
 # binning that builds the tile lists it walks); otherwise null.
 MEASURED_TRAFFIC = {"kernel": "render_bwd_tiles", "workload": "drt-batch-500k-8views",
-                    "fingerprint": "b689436ca59f87f2", "bytes": 3031997417,
+                    "fingerprint": "f65776227758fe87", "bytes": 3031883827,
                     "settings": (16, 16, 0, 64)}  # tile_w, tile_h, variant, batch of the measured run
 
 
