@@ -376,14 +376,15 @@ __global__ __launch_bounds__(256) void k_view_keys(const uint32_t* vals, uint64_
 }
 
 // ------------------------------------------------- interval scatter (lists)
-// A tile's list is every pair whose tile rectangle covers it, in (depth, pair)
-// order.  Rectangles are products of a row interval and a column interval, so
-// the lists are built in two stable bucketing levels without sorting
-// instances:
+// A tile's list is every pair whose footprint reaches it, in (depth, pair)
+// order: within its tile rectangle, a pair covers in each row one interval of
+// columns (those its ellipse reaches over the row), so the lists are built in
+// two stable bucketing levels without sorting instances:
 //   level 1: pairs of a view, in depth order, go to the rows [ty0, ty1] they
-//            cover (row lists, one entry per pair and row);
-//   level 2: a row list's pairs go to the columns [tx0, tx1] they cover
-//            (tile lists, one entry per instance).
+//            cover (row lists, one entry per pair and row, carrying that
+//            row's column interval);
+//   level 2: a row list's pairs go to the columns of their interval (tile
+//            lists, one entry per instance).
 // Each level is split into segments: an ordered item list and a window of at
 // most IS_W consecutive buckets (level 1: a view's rows 128k..128k+127; level
 // 2: a row's tiles 128k..128k+127).  A segment's items are cut into chunks of
@@ -393,8 +394,8 @@ __global__ __launch_bounds__(256) void k_view_keys(const uint32_t* vals, uint64_
 // the lanes below it, so the order of equal buckets is the item order.
 // Per-(chunk, bucket) counts are scanned over a segment's chunks, bucket
 // totals over all buckets, and the scatter writes each item at bucket start
-// + chunk prefix + earlier waves + rank.  All arithmetic is integer and the
-// result is unique, independent of scheduling.
+// + chunk prefix + earlier waves + rank.  The bucketing arithmetic is integer
+// and the result is unique, independent of scheduling.
 constexpr int IS_W = 128;
 constexpr int IS_IPL = 2;                            // items per lane
 constexpr int IS_THREADS = 1024;
