@@ -70,19 +70,16 @@ class Settings:
     tile_w: int = 16
     tile_h: int = 16
     sh_degree: int = 0
-    # Ambiguity model (pixels whose decisions may legitimately differ in a
-    # float32 implementation): relative alpha error of the evaluation itself,
-    # absolute error of the projected centre (px) and relative conic error.
-    ambig_tol: float = 1e-5
-    ambig_pos: float = 0.0
-    ambig_conic: float = 0.0
+    # Parity model: multiplier of the derived float32 bands of the skip and
+    # termination decisions (1 = the bands derived in frag_band).
+    band_scale: float = 1.0
 
     def array(self) -> np.ndarray:
         f = lambda x: float(np.float32(x))  # noqa: E731
         return np.array([f(self.kappa), f(self.rho), f(self.alpha_min), f(self.alpha_max), f(self.t_min),
                          f(self.blur), f(self.znear), f(self.clip_fac), f(self.bg[0]), f(self.bg[1]),
-                         f(self.bg[2]), self.tile_w, self.tile_h, self.sh_degree, self.ambig_tol, self.ambig_pos,
-                         self.ambig_conic, 0], dtype=np.float64)
+                         f(self.bg[2]), self.tile_w, self.tile_h, self.sh_degree, self.band_scale, 0, 0, 0],
+                        dtype=np.float64)
 
 
 def views_array(cameras) -> np.ndarray:
@@ -139,28 +136,33 @@ def project(scene, st: Settings) -> dict:
     return r
 
 
-def factor_record(rec) -> np.ndarray:
-    """Float32 record in the factored layout the binning decision reads:
-    u, v, L00, L10, L11, opacity, beta, qmax (columns 0-7 of 12) with
-    A = L00^2, B = L00 L10, C = L10^2 + L11^2 from the conic (A, B, C)."""
-    r = np.asarray(rec, np.float64).reshape(-1, 11)
-    out = np.zeros((r.shape[0], 12), np.float32)
-    A, B, C = r[:, 2], r[:, 3], r[:, 4]
-    with np.errstate(invalid="ignore", divide="ignore"):
-        L00 = np.sqrt(A)
-        L10 = B / L00
-        L11 = np.sqrt(np.maximum(C - L10 * L10, 0.0))
-    out[:, 0:2] = r[:, 0:2]
-    out[:, 2], out[:, 3], out[:, 4] = L00, L10, L11
-    out[:, 5:8] = r[:, 5:8]
-    return out
+def record_err_bound(scene, st: Settings) -> np.ndarray:
+    """A-priori bounds [V*N, 3] on how far a float32 projection's record may
+    lie from the FP64 one: centre (px, each of u and v), relative error of q
+    due to the conic, relative error of qmax (see orc_record_err_bound).
+    Culled pairs get zeros."""
+    N, V = scene.n, scene.n_views
+    out = np.zeros((max(N * V, 1), 3))
+    if N > 0:
+        lib().orc_record_err_bound(N, V, _p(_f64(scene.means)), _p(_f64(scene.scales)), _p(_f64(scene.quats)),
+                                   _p(_f64(scene.opacities)), _p(_f64(scene.betas)), _p(views_array(scene.cameras)),
+                                   _p(st.array()), _p(out))
+    return out[:N * V]
+
+
+def _rec11(rec, VN):
+    return _f64(np.asarray(rec, np.float64).reshape(-1, 11)) if VN > 0 else np.zeros((1, 11))
+
+
+def _perr(perr, VN):
+    return None if perr is None else _f64(np.asarray(perr, np.float64).reshape(VN, 3))
 
 
 def bin_instances(N, cameras, tile_rect, tiles_touched, zbits, st: Settings, rec):
-    """Stable-sorted (keys, vals, ranges[T, 2]) of the (tile | depth) instances:
-    each rectangle row keeps the columns its footprint ellipse reaches, decided
-    in float32 from `rec` ([V*N, 12] records in the factored layout of
-    factor_record; see row_columns_f32)."""
+    """Stable-sorted (keys, vals, ranges[T, 2]) of the (tile | depth) instances
+    under the footprint rule of orc_bin: a tile of a pair's rectangle is listed
+    when the minimum of q over its square is <= qmax (1 + 2^-8).  rec:
+    [V*N, 11] records (u, v, A, B, C, opacity, beta, qmax, r, g, b)."""
     V = len(cameras)
     tiles_touched = np.ascontiguousarray(tiles_touched, dtype=np.uint32)
     M = int(lib().orc_bin_count(ctypes.c_long(V * N), _p(tiles_touched)))
@@ -168,41 +170,133 @@ def bin_instances(N, cameras, tile_rect, tiles_touched, zbits, st: Settings, rec
     keys = np.zeros(max(M, 1), np.uint64)
     vals = np.zeros(max(M, 1), np.uint32)
     ranges = np.zeros((T, 2), np.uint32)
-    rec = _f64(np.asarray(rec, np.float64).reshape(-1, 12)) if V * N > 0 else np.zeros((1, 12))
     lib().orc_bin.restype = ctypes.c_long
     L = int(lib().orc_bin(N, V, _p(np.ascontiguousarray(tile_rect, np.int32)), _p(tiles_touched),
                           _p(np.ascontiguousarray(zbits, np.uint32)), _p(views_array(cameras)), st.tile_w, st.tile_h,
-                          _p(rec), _p(keys), _p(vals), _p(ranges)))
+                          _p(_rec11(rec, V * N)), _p(keys), _p(vals), _p(ranges)))
     return keys[:L], vals[:L], ranges
 
 
-def bin_pair_counts(tile_rect, tiles_touched, rec, st: Settings) -> np.ndarray:
-    """Instances per pair under the per-row column rule of bin_instances."""
+def bin_pair_counts(N, cameras, tile_rect, tiles_touched, rec, st: Settings, perr=None):
+    """Per pair (n_in, n_band): tiles of its rectangle listed with certainty
+    under the footprint rule, and those whose decision lies within the float32
+    band (perr [V*N, 3]: end-to-end record error bounds, nullable)."""
+    V = len(cameras)
+    VN = V * N
     tiles_touched = np.ascontiguousarray(tiles_touched, dtype=np.uint32)
-    VN = tiles_touched.size
-    out = np.zeros(max(VN, 1), np.uint32)
-    rec = _f64(np.asarray(rec, np.float64).reshape(-1, 12)) if VN else np.zeros((1, 12))
-    lib().orc_bin_pair_counts(ctypes.c_long(VN), _p(np.ascontiguousarray(tile_rect, np.int32)), _p(tiles_touched),
-                              _p(rec), st.tile_w, st.tile_h, _p(out))
-    return out[:VN]
+    n_in = np.zeros(max(VN, 1), np.uint32)
+    n_band = np.zeros(max(VN, 1), np.uint32)
+    if VN:
+        lib().orc_bin_pair_counts(N, V, _p(views_array(cameras)), st.tile_w, st.tile_h,
+                                  _p(np.ascontiguousarray(tile_rect, np.int32)), _p(tiles_touched),
+                                  _p(_rec11(rec, VN)), _p(_perr(perr, VN)), _p(n_in), _p(n_band))
+    return n_in[:VN], n_band[:VN]
 
 
-def render_fwd(N, cameras, rec, vals, ranges, st: Settings, depth=None) -> dict:
+def bin_band(N, cameras, tile_rect, tiles_touched, rec, st: Settings, perr=None) -> dict:
+    """The (pair, global tile) decisions of the footprint rule that lie within
+    the float32 band, with the FP64 outcome: dict(pair, tile, listed)."""
+    V = len(cameras)
+    VN = V * N
+    tiles_touched = np.ascontiguousarray(tiles_touched, dtype=np.uint32)
+    args = [N, V, _p(views_array(cameras)), st.tile_w, st.tile_h, _p(np.ascontiguousarray(tile_rect, np.int32)),
+            _p(tiles_touched), _p(_rec11(rec, VN)), _p(_perr(perr, VN))]
+    lib().orc_bin_band.restype = ctypes.c_long
+    cap = 1 << 16
+    while True:
+        pair = np.zeros(cap, np.uint32)
+        tile = np.zeros(cap, np.uint32)
+        listed = np.zeros(cap, np.uint8)
+        n = int(lib().orc_bin_band(*args, ctypes.c_long(cap), _p(pair), _p(tile), _p(listed))) if VN else 0
+        if n <= cap:
+            return dict(pair=pair[:n], tile=tile[:n], listed=listed[:n].astype(bool))
+        cap = n
+
+
+def instance_status(N, cameras, tile_rect, rec, vals, tiles, st: Settings, perr=None) -> np.ndarray:
+    """Per listed instance (pair vals[k], global tile tiles[k]): 0 listed with
+    certainty under the footprint rule, 1 within the float32 band, 2 not
+    listed with certainty, 3 outside the pair's view or tile rectangle."""
+    V = len(cameras)
+    vals = np.ascontiguousarray(vals, np.uint32)
+    L = vals.size
+    out = np.zeros(max(L, 1), np.uint8)
+    if L:
+        lib().orc_instance_status(N, V, _p(views_array(cameras)), st.tile_w, st.tile_h,
+                                  _p(np.ascontiguousarray(tile_rect, np.int32)), _p(_rec11(rec, V * N)),
+                                  _p(_perr(perr, V * N)), ctypes.c_long(L), _p(vals),
+                                  _p(np.ascontiguousarray(tiles, np.uint32)), _p(out))
+    return out[:L]
+
+
+def fragment_band(rec, px, py, st: Settings, perr=None):
+    """(o G, band) of fragments: record rec[k] ([n, 11]) at pixel centre
+    (px[k], py[k]); band bounds |d ln(o G)| of a float32 evaluation (see
+    frag_band in the C++ source)."""
+    rec = _f64(np.asarray(rec, np.float64).reshape(-1, 11))
+    n = rec.shape[0]
+    oG, band = np.zeros(max(n, 1)), np.zeros(max(n, 1))
+    lib().orc_fragment_band(ctypes.c_long(n), _p(rec), _p(_f64(px)), _p(_f64(py)), _p(st.array()),
+                            _p(_perr(perr, n)), _p(oG), _p(band))
+    return oG[:n], band[:n]
+
+
+def render_fwd(N, cameras, rec, vals, ranges, st: Settings, depth=None, perr=None, paths=None) -> dict:
     """Tiled forward; with `depth` ([V*N] splat depths) also the extended
-    channels "depth" (sum alpha T z) and "alpha" (sum alpha T)."""
+    channels "depth" (sum alpha T z) and "alpha" (sum alpha T).  perr: end-to-end
+    record error bounds that widen the decision bands (nullable); paths: the
+    decision path of each pixel (nullable: the plain FP64 result)."""
     P = sum(c.width * c.height for c in cameras)
+    V = len(cameras)
     out = dict(image=np.zeros(3 * P), final_T=np.zeros(P), n_contrib=np.zeros(P, np.uint32),
-               n_listed=np.zeros(P, np.uint32), n_hit=np.zeros(P, np.uint32), ambig=np.zeros(P, np.uint8))
+               n_listed=np.zeros(P, np.uint32), n_hit=np.zeros(P, np.uint32), ambig=np.zeros(P, np.uint8),
+               n_branch=np.zeros(P, np.uint8), last=np.zeros(P, np.int64))
     if depth is not None:
         out["depth"], out["alpha"] = np.zeros(P), np.zeros(P)
     vals = np.ascontiguousarray(vals, np.uint32)
     if vals.size == 0:
         vals = np.zeros(1, np.uint32)
-    lib().orc_render_fwd(N, len(cameras), _p(views_array(cameras)), _p(st.array()), _p(_f64(rec)), _p(vals),
-                         _p(np.ascontiguousarray(ranges, np.uint32)), _p(out["image"]), _p(out["final_T"]),
+    lib().orc_render_fwd(N, V, _p(views_array(cameras)), _p(st.array()), _p(_f64(rec)), _p(vals),
+                         _p(np.ascontiguousarray(ranges, np.uint32)), _p(_perr(perr, V * N)),
+                         _p(None if paths is None else np.ascontiguousarray(paths, np.uint32)),
+                         _p(out["image"]), _p(out["final_T"]),
                          _p(out["n_contrib"]), _p(out["n_listed"]), _p(out["n_hit"]), _p(out["ambig"]),
-                         _p(None if depth is None else _f64(depth)), _p(out.get("depth")), _p(out.get("alpha")))
+                         _p(out["n_branch"]), _p(out["last"]), _p(None if depth is None else _f64(depth)),
+                         _p(out.get("depth")),
+                         _p(out.get("alpha")))
     return out
+
+
+def resolve(N, cameras, rec, vals, ranges, st: Settings, image, final_T, last, n_hit=None, perr=None,
+            tol: float = 1e-4, tol_T: float = 1e-4, max_leaves: int = 64):
+    """Decision paths that reproduce a float32 rasterizer's per-pixel result
+    (image, final_T, the record index of the last composited fragment `last`
+    (-1 if none), optional n_hit) among the oracle's own correct results (see
+    orc_resolve).  The colour tolerance of view v is
+    tol * max(max |C| of the oracle's plain image of v, 1).  Returns (paths,
+    status, plain): per pixel the path and its status (0 unique, 1 resolved, 2
+    alpha-cap band, 3 too many paths, 4 no match), and the oracle's plain
+    (path 0) forward."""
+    V = len(cameras)
+    P = sum(c.width * c.height for c in cameras)
+    plain = render_fwd(N, cameras, rec, vals, ranges, st, perr=perr)
+    tv, off = np.zeros(V), 0
+    for v, c in enumerate(cameras):
+        n = 3 * c.width * c.height
+        tv[v] = tol * max(np.abs(plain["image"][off:off + n]).max(initial=0.0), 1.0)
+        off += n
+    paths = np.zeros(max(P, 1), np.uint32)
+    status = np.zeros(max(P, 1), np.uint8)
+    vals = np.ascontiguousarray(vals, np.uint32)
+    if vals.size == 0:
+        vals = np.zeros(1, np.uint32)
+    lib().orc_resolve(N, V, _p(views_array(cameras)), _p(st.array()), _p(_f64(rec)), _p(vals),
+                      _p(np.ascontiguousarray(ranges, np.uint32)), _p(_perr(perr, V * N)),
+                      _p(np.ascontiguousarray(image, np.float32)), _p(np.ascontiguousarray(final_T, np.float32)),
+                      _p(np.ascontiguousarray(last, np.int64)),
+                      _p(None if n_hit is None else np.ascontiguousarray(n_hit, np.uint32)), _p(tv),
+                      ctypes.c_double(tol_T), int(max_leaves), _p(paths), _p(status))
+    return paths[:P], status[:P], plain
 
 
 def brute_fwd(N, cameras, rec, zbits, cull, st: Settings, pix_rect=None, window=None) -> dict:
@@ -217,16 +311,18 @@ def brute_fwd(N, cameras, rec, zbits, cull, st: Settings, pix_rect=None, window=
 
 
 def render_bwd(N, cameras, rec, vals, ranges, dL_dimage, st: Settings, depth=None, dL_ddepth=None,
-               dL_dalpha=None) -> np.ndarray:
+               dL_dalpha=None, perr=None, paths=None) -> np.ndarray:
     """grad2d [V*N, 11]: du, dv, dA, dB, dC, dopacity, dbeta, dr, dg, db, dz (dz
-    only from the extended channels, which need `depth`)."""
+    only from the extended channels, which need `depth`); each pixel follows
+    its decision path (paths nullable, perr as in render_fwd)."""
     V = len(cameras)
     g2 = np.zeros((V * N, 11))
     vals = np.ascontiguousarray(vals, np.uint32)
     if vals.size == 0:
         vals = np.zeros(1, np.uint32)
     lib().orc_render_bwd(N, V, _p(views_array(cameras)), _p(st.array()), _p(_f64(rec)), _p(vals),
-                         _p(np.ascontiguousarray(ranges, np.uint32)), _p(_f64(dL_dimage)),
+                         _p(np.ascontiguousarray(ranges, np.uint32)), _p(_perr(perr, V * N)),
+                         _p(None if paths is None else np.ascontiguousarray(paths, np.uint32)), _p(_f64(dL_dimage)),
                          _p(None if depth is None else _f64(depth)),
                          _p(None if dL_ddepth is None else _f64(dL_ddepth)),
                          _p(None if dL_dalpha is None else _f64(dL_dalpha)), _p(g2))
@@ -445,21 +541,28 @@ def shape_reset(raw: dict, m: dict, v: dict, value: float):
 
 
 # ------------------------------------------------------------------ pipeline
-def forward(scene, st: Settings, channels: bool = False) -> dict:
+def forward(scene, st: Settings, channels: bool = False, band: bool = False, paths=None) -> dict:
     """Full FP64 pipeline: project -> bin -> tiled render (with the extended
-    depth and alpha channels when `channels`)."""
+    depth and alpha channels when `channels`).  With `band`, the decision bands
+    also cover the a-priori error of a float32 projection's records
+    (record_err_bound, kept as "perr") for comparisons with a float32 pipeline
+    run from the same parameters.  paths: per-pixel decision paths (nullable)."""
     pr = project(scene, st)
     keys, vals, ranges = bin_instances(scene.n, scene.cameras, pr["tile_rect"], pr["tiles_touched"], pr["zbits"], st,
-                                       factor_record(pr["rec"]))
-    out = render_fwd(scene.n, scene.cameras, pr["rec"], vals, ranges, st, depth=pr["depth"] if channels else None)
-    out.update(proj=pr, keys=keys, vals=vals, ranges=ranges)
+                                       pr["rec"])
+    perr = record_err_bound(scene, st) if band else None
+    out = render_fwd(scene.n, scene.cameras, pr["rec"], vals, ranges, st, depth=pr["depth"] if channels else None,
+                     perr=perr, paths=paths)
+    out.update(proj=pr, keys=keys, vals=vals, ranges=ranges, perr=perr)
     return out
 
 
-def backward(scene, st: Settings, fwd: dict, dL_dimage, dL_ddepth=None, dL_dalpha=None) -> dict:
+def backward(scene, st: Settings, fwd: dict, dL_dimage, dL_ddepth=None, dL_dalpha=None, paths=None) -> dict:
+    """Adjoint of `forward` (each pixel follows its decision path; paths nullable)."""
     ext = dL_ddepth is not None or dL_dalpha is not None
     g2 = render_bwd(scene.n, scene.cameras, fwd["proj"]["rec"], fwd["vals"], fwd["ranges"], dL_dimage, st,
-                    depth=fwd["proj"]["depth"] if ext else None, dL_ddepth=dL_ddepth, dL_dalpha=dL_dalpha)
+                    depth=fwd["proj"]["depth"] if ext else None, dL_ddepth=dL_ddepth, dL_dalpha=dL_dalpha,
+                    perr=fwd.get("perr"), paths=paths)
     g = project_bwd(scene, g2, st)
     g["grad2d"] = g2
     return g

@@ -47,12 +47,9 @@ struct Settings {
     double kappa, rho, alpha_min, alpha_max, t_min, blur, znear, clip_fac;
     double bg[3];
     int tile_w, tile_h, sh_degree;
-    // Ambiguity model: a decision is flagged when the threshold lies within the
-    // first-order error band of a float32 implementation:
-    //   ambig        relative error of the alpha evaluation itself
-    //   ambig_pos    absolute error (pixels) of the projected centre
-    //   ambig_conic  relative error of the projected conic
-    double ambig, ambig_pos, ambig_conic;
+    // Parity model: multiplier of the derived float32 bands of the skip and
+    // termination decisions (frag_band); 1 unless a test widens them.
+    double band_scale;
 };
 
 Settings read_settings(const double* s) {
@@ -61,9 +58,7 @@ Settings read_settings(const double* s) {
     o.blur = s[5]; o.znear = s[6]; o.clip_fac = s[7];
     o.bg[0] = s[8]; o.bg[1] = s[9]; o.bg[2] = s[10];
     o.tile_w = (int)s[11]; o.tile_h = (int)s[12]; o.sh_degree = (int)s[13];
-    o.ambig = s[14] > 0.0 ? s[14] : 1e-5;
-    o.ambig_pos = s[15];
-    o.ambig_conic = s[16];
+    o.band_scale = s[14] > 0.0 ? s[14] : 1.0;
     return o;
 }
 
@@ -344,36 +339,68 @@ inline Frag eval_frag(const Rec& s, double px, double py, const Settings& st) {
     return f;
 }
 
-inline bool near_rel(double a, double b, double tol) { return std::fabs(a - b) <= tol * std::fabs(b); }
+// Unit roundoff of float32 (the precision of the rasterizer under test).
+constexpr double U32 = 1.0 / 16777216.0;
 
-// Error band of ln(alpha) for a fragment: ln(alpha) moves by
-// kappa (beta/2) P (dq/q), with dq/q <= 2 |du|/|d| + conic error.
-inline double frag_band(const Frag& f, const Rec& s, const Settings& st) {
-    double d = std::sqrt(f.dx * f.dx + f.dy * f.dy);
-    double sens = st.kappa * 0.5 * s.beta * f.P;
-    return st.ambig + sens * (2.0 * st.ambig_pos / std::max(d, 0.25) + st.ambig_conic);
+// Per-pair bounds on how far a float32 projection's record may lie from the
+// FP64 one (end-to-end comparisons; see orc_record_err_bound): centre error in
+// pixels (u and v each), relative error of q from the conic, relative error
+// of qmax.  Null when both sides use the same float32 records.
+struct PairErr { double centre, conic, qmax; };
+
+inline PairErr load_err(const double* perr, long idx) {
+    if (!perr) return PairErr{0.0, 0.0, 0.0};
+    const double* a = perr + 3 * idx;
+    return PairErr{a[0], a[1], a[2]};
 }
 
-// Ambiguity flags: bit0 alpha ~ alpha_min, bit1 oG ~ alpha_max, bit2 T' ~ t_min.
-// `band` bounds |d ln alpha| of the fragment and `tband` bounds |d ln T| of the
-// transmittance accumulated over the fragments composited so far; a decision is
-// flagged when its threshold lies within that band in log space.
+// Shear of the conic factor, |L10| / L11 = |B| / sqrt(AC - B^2): it multiplies
+// the rounding error of L00 dx + L10 dy in a float32 evaluation of q.
+inline double conic_shear(const Rec& s) {
+    double det = s.A * s.C - s.B * s.B;
+    return det > 0.0 ? std::fabs(s.B) / std::sqrt(det) : 0.0;
+}
+
+// First-order bound on |d ln(o G)| of a float32 evaluation of a fragment that
+// takes the steps dx = px - u, dy = py - v, t = L00 dx + L10 dy (one fma),
+// w = L11 dy, q = t^2 + w^2 (one fma), P = exp2((beta/2) log2 q),
+// G = exp2(-kappa log2(e) P), o G, with correctly rounded + - * (unit
+// roundoff u = 2^-24) and 1-ulp log2 / exp2:
+//   |dq/q|     <= u (12 + 8 s),  s the conic shear;
+//   |dP/P|     <= 2u + (beta/2) |dq/q| + 3 ln2 u |log2 P|;
+//   |d ln oG|  <= 3u + kappa P (|dP/P| + 2u).
+// End to end the record itself may differ from the FP64 one (PairErr), which
+// adds kappa P (beta/2) (conic + 2 sqrt(2) centre |C d| / q) with C d the
+// gradient of q / 2 at the pixel.  band_scale multiplies the result.
+inline double frag_band(const Frag& f, const Rec& s, const Settings& st, const PairErr& e) {
+    const double hb = 0.5 * s.beta;
+    const double kP = st.kappa * f.P;
+    const double dq = U32 * (12.0 + 8.0 * conic_shear(s));
+    double dq_rec = 0.0;
+    if (e.centre > 0.0 || e.conic > 0.0) {
+        double gx = s.A * f.dx + s.B * f.dy, gy = s.B * f.dx + s.C * f.dy;
+        double g = std::sqrt(gx * gx + gy * gy);
+        dq_rec = e.conic + (f.q > 0.0 ? 2.0 * std::sqrt(2.0) * e.centre * g / f.q : 0.0);
+    }
+    const double lp = f.P > 0.0 ? std::fabs(std::log2(f.P)) : 0.0;
+    const double dP = 2.0 * U32 + hb * (dq + dq_rec) + 3.0 * std::log(2.0) * U32 * lp;
+    return st.band_scale * (3.0 * U32 + kP * (dP + 2.0 * U32));
+}
+
+// A decision is within the float32 band when its threshold lies within
+// `band` of the FP64 value in log space.
 inline bool near_log(double a, double b, double band) { return a > 0.0 && std::fabs(std::log(a / b)) <= band; }
-
-inline uint8_t frag_ambiguity(const Frag& f, double Tnext, double band, double tband, const Settings& st) {
-    uint8_t a = 0;
-    if (near_log(f.oG, st.alpha_min, band)) a |= 1;
-    if (near_log(f.oG, st.alpha_max, band)) a |= 2;
-    if (near_log(Tnext, st.t_min, tband)) a |= 4;
-    return a;
-}
 
 struct PixelOut {
     double C[3];
     double D, A;  // extended channels: sum alpha T z and sum alpha T (zero background)
     double T;
     uint32_t n_contrib, n_listed, n_hit;
-    uint8_t ambig;
+    uint8_t ambig;     // bit0 a skip decision (alpha vs alpha_min) within its band, bit1 o G within the band
+                       // of alpha_max, bit2 a termination decision (T' vs t_min) within its band
+    uint8_t n_branch;  // decisions within their band met along the path (saturates at 255)
+    long last;         // record index of the last composited fragment (-1 if none): unlike n_contrib it
+                       // does not depend on entries that no pixel of the tile composites
 };
 
 // One explicit list entry of a composited fragment (used by the adjoint).
@@ -384,28 +411,49 @@ struct Hit { long idx; long row; double alpha, T, z; Frag f; };
 // fragment that would take T below t_min.  n_contrib is the 1-based list
 // position of the last composited fragment.
 //
+// Decision paths.  A skip or termination decision whose threshold lies within
+// the fragment's float32 band (frag_band; the transmittance band accumulates
+// alpha / (1 - alpha) times each composited fragment's band plus 2u per
+// product) has two correct outcomes.  Such decisions are numbered in the order
+// they are met; bit i of `path` set takes the other outcome at decision i
+// (bits beyond 31 are 0).  path = 0 is the plain FP64 result.  The cap
+// decision (o G vs alpha_max) only flags bit1: its two outcomes give the same
+// alpha to within the band, so it is not enumerated.
+//
 // Extended channels (the depth maps of the mesh-extraction passage, Sec. 3.3):
 // depth and opacity composited like a colour channel over a zero background,
 // D = sum_k alpha_k T_k z_k and A = sum_k alpha_k T_k, with z the splat's
 // camera-space depth (`depth`, nullable: z = 0).
 template <class ListFn>
 PixelOut composite_pixel(long count, ListFn idx_at, const double* rec, double px, double py, const Settings& st,
-                         std::vector<Hit>* hits, const long* rows = nullptr, const double* depth = nullptr) {
-    PixelOut o{{0, 0, 0}, 0.0, 0.0, 1.0, 0, 0, 0, 0};
+                         std::vector<Hit>* hits, const long* rows = nullptr, const double* depth = nullptr,
+                         const double* perr = nullptr, uint32_t path = 0) {
+    PixelOut o{{0, 0, 0}, 0.0, 0.0, 1.0, 0, 0, 0, 0, 0, -1};
     double T = 1.0;
-    double tband = st.ambig;  // relative error band of T
+    double tband = 0.0;  // bound on |d ln T| of the float32 transmittance
+    int nb = 0;
+    auto branch = [&](bool decision) {
+        bool flip = nb < 32 && ((path >> nb) & 1u);
+        if (nb < 255) ++nb;
+        return flip ? !decision : decision;
+    };
     for (long k = 0; k < count; ++k) {
         long idx = idx_at(k);
         Rec s = load_rec(rec, idx);
         Frag f = eval_frag(s, px, py, st);
         o.n_listed++;
-        double Tn = T * (1.0 - f.alpha);
-        double band = frag_band(f, s, st);
-        double tnext_band = tband + band * f.alpha / std::max(1.0 - f.alpha, 1e-12);
-        o.ambig |= frag_ambiguity(f, Tn, band, tnext_band, st);
-        if (f.alpha < st.alpha_min) continue;
+        const double band = frag_band(f, s, st, load_err(perr, idx));
+        bool skip = f.alpha < st.alpha_min;
+        if (near_log(f.oG, st.alpha_min, band)) { o.ambig |= 1; skip = branch(skip); }
+        if (near_log(f.oG, st.alpha_max, band)) o.ambig |= 2;
+        if (skip) continue;
         o.n_hit++;
-        if (Tn < st.t_min) break;
+        const double Tn = T * (1.0 - f.alpha);
+        const double tnext_band =
+            tband + band * f.alpha / std::max(1.0 - f.alpha, 1e-12) + st.band_scale * 2.0 * U32;
+        bool stop = Tn < st.t_min;
+        if (near_log(Tn, st.t_min, tnext_band)) { o.ambig |= 4; stop = branch(stop); }
+        if (stop) break;
         o.C[0] += s.r * f.alpha * T;
         o.C[1] += s.g * f.alpha * T;
         o.C[2] += s.b * f.alpha * T;
@@ -416,9 +464,11 @@ PixelOut composite_pixel(long count, ListFn idx_at, const double* rec, double px
         T = Tn;
         tband = tnext_band;
         o.n_contrib = (uint32_t)(k + 1);
+        o.last = idx;
     }
     for (int c = 0; c < 3; ++c) o.C[c] += T * st.bg[c];
     o.T = T;
+    o.n_branch = (uint8_t)nb;
     return o;
 }
 
@@ -468,45 +518,71 @@ void pixel_adjoint(const std::vector<Hit>& hits, double Tfinal, const double* g,
     }
 }
 
-// Tile columns of row ty that a pair's footprint ellipse reaches, decided in
-// float32 (the precision of the records the lists are built from): with
-// q = (L00 dx + L10 dy)^2 + (L11 dy)^2 and Q = qmax (1 + 2^-8), the x-extent
-// of {q <= Q} over the row's band [ty th, (ty + 1) th) -- at the ellipse's
-// rightmost (leftmost) point when that lies in the band, else at the band end
-// nearest to it -- as tile columns intersected with [c0, c1].  Empty rows give
-// c0 > c1; a non-finite value keeps [c0, c1].  IEEE float square roots and
-// quotients are correctly rounded, as are the GPU's.
-void row_columns_f32(const double* rec, int ty, int tw, int th, int* c0, int* c1) {
-    const float u = (float)rec[0], v = (float)rec[1], l00 = (float)rec[2], l10 = (float)rec[3], l11 = (float)rec[4];
-    const float qmax = (float)rec[7];
-    const float Q = qmax + qmax * 0.00390625f;
-    const float d0 = (float)(ty * th) - v;
-    const float d1 = (float)((ty + 1) * th) - v;
-    const float sq = std::sqrt(Q);
-    const float ym = sq / l11;
-    const float lo = d0 > -ym ? d0 : -ym;
-    const float hi = d1 < ym ? d1 : ym;
-    if (!(lo <= hi)) {
-        if (lo > hi) *c0 = *c1 + 1;
-        return;
-    }
-    const float rr = std::sqrt(l10 * l10 + l11 * l11);
-    const float dyr = -(l10 * sq) / (l11 * rr);
-    const float tr = dyr < lo ? lo : (dyr > hi ? hi : dyr);
-    const float tl = -dyr < lo ? lo : (-dyr > hi ? hi : -dyr);
-    const float sr = Q - (l11 * tr) * (l11 * tr);
-    const float sl = Q - (l11 * tl) * (l11 * tl);
-    const float xr = (-(l10 * tr) + std::sqrt(sr > 0.f ? sr : 0.f)) / l00;
-    const float xl = (-(l10 * tl) - std::sqrt(sl > 0.f ? sl : 0.f)) / l00;
-    const float X0 = u + xl, X1 = u + xr;
-    if (!(X0 <= X1) || !(X1 - X0 < 1e30f)) return;
-    const float inv = 1.0f / (float)tw;
-    const float f0 = std::floor(X0 * inv), f1 = std::floor(X1 * inv);
-    const int a = *c0, b = *c1;
-    const int n0 = f0 < (float)a ? a : (f0 > (float)b ? b + 1 : (int)f0);
-    const int n1 = f1 > (float)b ? b : (f1 < (float)a ? a - 1 : (int)f1);
-    *c0 = n0;
-    *c1 = n1;
+// ----------------------------------------------------------------- binning
+// Smallest value of the footprint quadratic q(dx, dy) = A dx^2 + 2 B dx dy +
+// C dy^2 (positive definite) over the box [x0, x1] x [y0, y1] of offsets from
+// the centre.  q is convex: its minimum is 0 when the box holds the centre and
+// otherwise lies on an edge, where q is a 1-D convex quadratic whose minimum
+// is its vertex clamped into the edge.
+double box_min_q(double A, double B, double C, double x0, double x1, double y0, double y1) {
+    if (x0 <= 0.0 && 0.0 <= x1 && y0 <= 0.0 && 0.0 <= y1) return 0.0;
+    auto q = [&](double x, double y) { return A * x * x + 2.0 * B * x * y + C * y * y; };
+    auto clampd = [](double x, double lo, double hi) { return x < lo ? lo : (x > hi ? hi : x); };
+    double best = HUGE_VAL;
+    for (double xe : {x0, x1}) best = std::min(best, q(xe, clampd(-B * xe / C, y0, y1)));
+    for (double ye : {y0, y1}) best = std::min(best, q(clampd(-B * ye / A, x0, x1), ye));
+    return best;
+}
+
+// Which tiles list a pair.  The method only needs every tile holding a pixel
+// centre with alpha >= alpha_min (q <= qmax) to list the splat; the footprint
+// rule used here lists a tile of the pair's tile rectangle when the ellipse
+// {q <= Q}, Q = qmax (1 + 2^-8), meets the tile's closed square
+// [tx tw, (tx + 1) tw] x [ty th, (ty + 1) th] in pixel coordinates, i.e. when
+// the minimum of q over the square is <= Q.  The margin 2^-8 keeps every
+// decision that matters for the image (pixel centres lie half a pixel inside
+// their tile, where q > qmax means alpha < alpha_min) far from the rule's
+// boundary.
+inline double tile_min_q(const Rec& s, int tx, int ty, int tw, int th, double grow) {
+    return box_min_q(s.A, s.B, s.C, (double)tx * tw - s.u - grow, (double)(tx + 1) * tw - s.u + grow,
+                     (double)ty * th - s.v - grow, (double)(ty + 1) * th - s.v + grow);
+}
+inline double footprint_Q(const Rec& s) { return s.qmax * (1.0 + std::ldexp(1.0, -8)); }
+inline bool tile_listed(const Rec& s, int tx, int ty, int tw, int th) {
+    return tile_min_q(s, tx, ty, tw, th, 0.0) <= footprint_Q(s);
+}
+
+// Float32 band of the tile rule.  A float32 implementation that derives each
+// tile row's column interval from the record -- band edges ty th - v and
+// (ty + 1) th - v, the ellipse's x-extent over the band from sqrt(Q),
+// sqrt(Q - (L11 dy)^2), L10 dy and a quotient by L00, then u + extent -- is
+// the exact rule for a square moved by at most `eps` pixels and a bound moved
+// by a relative `eta`, with (unit roundoff u = 2^-24, correctly rounded
+// operations; s the conic shear |L10| / L11):
+//   eps = 2u (max(W, H) + |u| + |v|) + 32 u            (the two coordinate sums)
+//   eta = u (16 + 8 s)                                 (the extent in q)
+// plus, end to end, the record's own error: the centre bound adds to eps, the
+// conic and qmax bounds to eta.  A decision is within the band when neither
+// outcome is certain: the square grown by eps meets {q <= Q (1 + eta)} and the
+// square shrunk by eps misses {q <= Q (1 - eta)}.
+struct TileBand { double eps, eta; };
+
+inline TileBand tile_band_params(const Rec& s, const View& w, const PairErr& e) {
+    TileBand b;
+    b.eps = 2.0 * U32 * ((double)std::max(w.W, w.H) + std::fabs(s.u) + std::fabs(s.v)) + 32.0 * U32 + e.centre;
+    b.eta = U32 * (16.0 + 8.0 * conic_shear(s)) + e.conic + e.qmax;
+    return b;
+}
+
+// 0: listed with certainty, 1: within the band, 2: not listed with certainty
+// (the rectangle is not checked here).
+inline int tile_status(const Rec& s, int tx, int ty, int tw, int th, const TileBand& b) {
+    const double Q = footprint_Q(s);
+    const double lo = tile_min_q(s, tx, ty, tw, th, b.eps);   // grown square
+    const double hi = tile_min_q(s, tx, ty, tw, th, -b.eps);  // shrunk square
+    if (lo > Q * (1.0 + b.eta)) return 2;
+    if (hi <= Q * (1.0 - b.eta)) return 0;
+    return 1;
 }
 
 int nthreads() {
@@ -580,6 +656,172 @@ int orc_project(int N, int V, const double* means, const double* scales, const d
     return 0;
 }
 
+// A-priori bounds on the error of a float32 projection record, per (view,
+// splat) (perr, [V*N][3]): [0] centre, in pixels, for each of u and v; [1]
+// relative error of q due to the conic, in the worst direction; [2] relative
+// error of qmax.  First order in u = 2^-24, for a float32 projection that
+// takes these steps (correctly rounded + - * / sqrt, 1-ulp exp and log):
+//  * R from the normalised quaternion: entries within 8u (absolute);
+//  * phi(beta) s: within 6u relative;
+//  * T = J W: each entry within 4u of the sum of its two terms' magnitudes;
+//  * U = T M with M = R diag(phi s): each entry within 3u sum_a |T_ia M_ab|;
+//  * Sigma' = U U^T + blur I: a and c within 4u relative, b within
+//    3u sum_k |U0k U1k|;
+//  * det(Sigma') from non-negative terms, |x|^2 + blur (a0 + c0) + blur^2 with
+//    x_k = (prod_{j != k} phi s_j) (R^T (T0 x T1))_k: R's error enters x
+//    directly, the cross products within 8u of their terms' magnitudes, the
+//    products of two scales within 13u; det's relative error is q's;
+//  * the Cholesky factor of the conic: each entry within 4u relative, which
+//    moves q by 4u (4 + 4 s) relative (s the conic shear).
+// A perturbation dSigma' of Sigma' moves q by at most rho(Sigma'^-1 dSigma')
+// relative (spectral radius); the conic bound sums these first-order effects.
+// Centre: u = fx (x / z) + cx from a compensated camera-space centre, within
+// 1/2 ulp(u) + 3u |u - cx| (v likewise; the larger is reported).  qmax =
+// (ln(o / alpha_min) / kappa)^(2/beta) (1 + 2^-10) through log, log2 and exp2:
+// within u (4 + (2/beta)(4 + 1 / ln(o / alpha_min)) + 3 |log2 qmax|).
+// Culled pairs get zeros.
+static double rho2(const double Si[3], const double X[3]) {
+    // spectral radius of Si X for symmetric 2x2 Si = (s00, s01, s11), X = (x00, x01, x11)
+    const double m00 = Si[0] * X[0] + Si[1] * X[1], m01 = Si[0] * X[1] + Si[1] * X[2];
+    const double m10 = Si[1] * X[0] + Si[2] * X[1], m11 = Si[1] * X[1] + Si[2] * X[2];
+    const double tr = 0.5 * (m00 + m11), dt = m00 * m11 - m01 * m10;
+    const double disc = std::sqrt(std::max(tr * tr - dt, 0.0));
+    return std::max(std::fabs(tr + disc), std::fabs(tr - disc));
+}
+static double ulp32(double x) {
+    int e;
+    std::frexp(std::fabs(x), &e);
+    return std::ldexp(1.0, std::max(e, -125) - 24);
+}
+
+int orc_record_err_bound(int N, int V, const double* means, const double* scales, const double* quats,
+                         const double* opac, const double* betas, const double* views, const double* settings,
+                         double* perr) {
+    Settings st = read_settings(settings);
+    std::vector<View> vw = read_views(views, V, st.tile_w, st.tile_h);
+    const double u = U32;
+#pragma omp parallel for schedule(static)
+    for (long i = 0; i < N; ++i) {
+        const double* q4 = quats + 4 * i;
+        const double qn = std::sqrt(q4[0] * q4[0] + q4[1] * q4[1] + q4[2] * q4[2] + q4[3] * q4[3]);
+        const double w = q4[0] / qn, x = q4[1] / qn, y = q4[2] / qn, z = q4[3] / qn;
+        const double R[9] = {1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y),
+                             2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x),
+                             2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)};
+        const double phi = 2.0 / (1.0 + std::exp(-st.rho * (betas[i] - 2.0)));
+        double ps[3], M[9];
+        for (int b = 0; b < 3; ++b) ps[b] = phi * scales[3 * i + b];
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) M[3 * a + b] = R[3 * a + b] * ps[b];
+        const double o = opac[i], bt = betas[i];
+        const double lnx = std::log(o / st.alpha_min);
+        const double qmax = lnx > 0.0 ? std::pow(lnx / st.kappa, 2.0 / bt) * (1.0 + std::ldexp(1.0, -10)) : 0.0;
+        const double e_qmax =
+            lnx > 0.0 ? u * (4.0 + (2.0 / bt) * (4.0 + 1.0 / lnx) + 3.0 * std::fabs(std::log2(qmax))) : 0.0;
+        for (int v = 0; v < V; ++v) {
+            const View& c = vw[v];
+            double* out = perr + 3 * ((long)v * N + i);
+            out[0] = out[1] = out[2] = 0.0;
+            double p[3];
+            for (int a = 0; a < 3; ++a)
+                p[a] = c.R[3 * a] * means[3 * i] + c.R[3 * a + 1] * means[3 * i + 1] + c.R[3 * a + 2] * means[3 * i + 2] +
+                       c.t[a];
+            if (!(p[2] > st.znear)) continue;
+            const double limx = st.clip_fac * c.W / (2.0 * c.fx), limy = st.clip_fac * c.H / (2.0 * c.fy);
+            const double xt = std::max(-limx, std::min(limx, p[0] / p[2])) * p[2];
+            const double yt = std::max(-limy, std::min(limy, p[1] / p[2])) * p[2];
+            const double J[6] = {c.fx / p[2], 0.0, -c.fx * xt / (p[2] * p[2]), 0.0, c.fy / p[2],
+                                 -c.fy * yt / (p[2] * p[2])};
+            double T[6], Tabs[6];
+            for (int r = 0; r < 2; ++r)
+                for (int b = 0; b < 3; ++b) {
+                    T[3 * r + b] = J[3 * r] * c.R[b] + J[3 * r + 1] * c.R[3 + b] + J[3 * r + 2] * c.R[6 + b];
+                    Tabs[3 * r + b] = std::fabs(J[3 * r] * c.R[b]) + std::fabs(J[3 * r + 1] * c.R[3 + b]) +
+                                      std::fabs(J[3 * r + 2] * c.R[6 + b]);
+                }
+            double U[6], TM[6];  // U = T M (2 x 3) and sum_a |T_ia M_ab|
+            for (int r = 0; r < 2; ++r)
+                for (int b = 0; b < 3; ++b) {
+                    U[3 * r + b] = T[3 * r] * M[b] + T[3 * r + 1] * M[3 + b] + T[3 * r + 2] * M[6 + b];
+                    TM[3 * r + b] = std::fabs(T[3 * r] * M[b]) + std::fabs(T[3 * r + 1] * M[3 + b]) +
+                                    std::fabs(T[3 * r + 2] * M[6 + b]);
+                }
+            const double a0 = U[0] * U[0] + U[1] * U[1] + U[2] * U[2];
+            const double c0 = U[3] * U[3] + U[4] * U[4] + U[5] * U[5];
+            const double sb = U[0] * U[3] + U[1] * U[4] + U[2] * U[5];
+            const double sa = a0 + st.blur, sc = c0 + st.blur;
+            const double det = sa * sc - sb * sb;
+            if (!(det > 0.0) || !std::isfinite(det)) continue;
+            const double Si[3] = {sc / det, -sb / det, sa / det};  // Sigma'^-1
+            auto sym = [](const double a[2], const double b[2], double X[3]) {
+                X[0] = 2.0 * a[0] * b[0];
+                X[1] = a[0] * b[1] + a[1] * b[0];
+                X[2] = 2.0 * a[1] * b[1];
+            };
+            double X[3], conic = 0.0;
+            // rotation entries (absolute 8u): dM_ab = dR_ab ps_b moves column b of U by T[:, a]
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) {
+                    const double ta[2] = {T[a], T[3 + a]}, ub[2] = {U[b], U[3 + b]};
+                    sym(ta, ub, X);
+                    conic += 8.0 * u * ps[b] * rho2(Si, X);
+                }
+            // T entries (4u of their terms): dT_ia moves row i of U by dT_ia M[a, :]
+            for (int r = 0; r < 2; ++r)
+                for (int a = 0; a < 3; ++a) {
+                    const double g[2] = {U[0] * M[3 * a] + U[1] * M[3 * a + 1] + U[2] * M[3 * a + 2],
+                                         U[3] * M[3 * a] + U[4] * M[3 * a + 1] + U[5] * M[3 * a + 2]};
+                    const double e[2] = {r == 0 ? 1.0 : 0.0, r == 1 ? 1.0 : 0.0};
+                    sym(e, g, X);
+                    conic += 4.0 * u * Tabs[3 * r + a] * rho2(Si, X);
+                }
+            // U entries (3u of their terms) and phi s (6u relative, column b of U scaled)
+            double u_terms = 0.0;
+            for (int b = 0; b < 3; ++b) {
+                const double ub[2] = {U[b], U[3 + b]};
+                for (int r = 0; r < 2; ++r) {
+                    const double e[2] = {r == 0 ? 1.0 : 0.0, r == 1 ? 1.0 : 0.0};
+                    sym(e, ub, X);
+                    conic += 3.0 * u * TM[3 * r + b] * rho2(Si, X);
+                    u_terms += std::fabs(U[3 * r + b]) * TM[3 * r + b];
+                }
+                sym(ub, ub, X);
+                conic += 6.0 * u * rho2(Si, X);
+            }
+            // Sigma' entries: a, c relative 4u; b absolute 3u sum |U0k U1k|
+            const double babs = std::fabs(U[0] * U[3]) + std::fabs(U[1] * U[4]) + std::fabs(U[2] * U[5]);
+            conic += 4.0 * u * (sa * Si[0] + sc * Si[2]);
+            conic += 3.0 * u * babs * (std::fabs(Si[1]) + std::sqrt(Si[0] * Si[2]));
+            // det from the non-negative terms
+            const double n[3] = {T[1] * T[5] - T[2] * T[4], T[2] * T[3] - T[0] * T[5], T[0] * T[4] - T[1] * T[3]};
+            const double nT[3] = {Tabs[1] * Tabs[5] + Tabs[2] * Tabs[4], Tabs[2] * Tabs[3] + Tabs[0] * Tabs[5],
+                                  Tabs[0] * Tabs[4] + Tabs[1] * Tabs[3]};
+            const double n1 = std::fabs(n[0]) + std::fabs(n[1]) + std::fabs(n[2]);
+            const double pp[3] = {ps[1] * ps[2], ps[0] * ps[2], ps[0] * ps[1]};
+            double ddet = 3.0 * u * det + st.blur * (4.0 * u * (a0 + c0) + 6.0 * u * u_terms);
+            for (int k = 0; k < 3; ++k) {
+                double mk = 0.0, dm = 8.0 * u * n1;
+                for (int j = 0; j < 3; ++j) {
+                    mk += R[3 * j + k] * n[j];
+                    dm += std::fabs(R[3 * j + k]) * (8.0 * u * nT[j]) + 3.0 * u * std::fabs(R[3 * j + k] * n[j]);
+                }
+                const double xk = pp[k] * mk;
+                ddet += 2.0 * std::fabs(xk) * (13.0 * u * std::fabs(xk) + pp[k] * dm);
+            }
+            conic += ddet / det;
+            // the stored Cholesky factor
+            const double shear = std::fabs(sb) / std::sqrt(det);
+            conic += 4.0 * u * (4.0 + 4.0 * shear);
+            const double uu = c.fx * p[0] / p[2] + c.cx, vv = c.fy * p[1] / p[2] + c.cy;
+            out[0] = std::max(0.5 * ulp32(uu) + 3.0 * u * std::fabs(uu - c.cx),
+                              0.5 * ulp32(vv) + 3.0 * u * std::fabs(vv - c.cy));
+            out[1] = conic;
+            out[2] = e_qmax;
+        }
+    }
+    return 0;
+}
+
 uint64_t orc_bin_count(long VN, const uint32_t* tiles_touched) {
     uint64_t m = 0;
     for (long k = 0; k < VN; ++k) m += tiles_touched[k];
@@ -591,74 +833,151 @@ long orc_total_tiles(int V, const double* views, int tile_w, int tile_h) {
     return vw.back().tile_base + (long)vw.back().tiles_x * vw.back().tiles_y;
 }
 
-// Binning: one instance per (splat, view, tile) overlap, emitted in
-// (view, splat, tile-row, tile-column) order with key = tile << 32 | bits(z32)
-// and value = view * N + splat; stable sort by key; ranges[t] = [first, end)
-// of tile t in the sorted list ((0, 0) when empty).
+// Binning: one instance per (view, splat, listed tile) -- a tile of the pair's
+// tile rectangle whose square meets the footprint ellipse (tile_listed) --
+// emitted in (view, splat, tile-row, tile-column) order with key =
+// tile << 32 | bits(z32) and value = view * N + splat; stable sort by key;
+// ranges[t] = [first, end) of tile t in the sorted list ((0, 0) when empty).
+// rec: [V*N][11] records (u, v, A, B, C, opacity, beta, qmax, r, g, b).
 long orc_bin(int N, int V, const int32_t* tile_rect, const uint32_t* tiles_touched, const uint32_t* zbits,
              const double* views, int tile_w, int tile_h, const double* rec, uint64_t* keys, uint32_t* vals,
              uint32_t* ranges) {
     std::vector<View> vw = read_views(views, V, tile_w, tile_h);
     long T = vw.back().tile_base + (long)vw.back().tiles_x * vw.back().tiles_y;
-    std::vector<std::pair<uint64_t, uint32_t>> inst;
+    // a view's keys lie in its own tile range, so each view is sorted on its
+    // own and the views are concatenated in order
+    std::vector<std::vector<std::pair<uint64_t, uint32_t>>> inst(V);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int v = 0; v < V; ++v) {
+        for (long i = 0; i < N; ++i) {
+            long o = (long)v * N + i;
+            if (tiles_touched[o] == 0) continue;
+            const int32_t* r = tile_rect + 4 * o;
+            const Rec s = load_rec(rec, o);
+            for (int ty = r[1]; ty <= r[3]; ++ty)
+                for (int tx = r[0]; tx <= r[2]; ++tx) {
+                    if (!tile_listed(s, tx, ty, tile_w, tile_h)) continue;
+                    uint64_t tile = (uint64_t)(vw[v].tile_base + (long)ty * vw[v].tiles_x + tx);
+                    inst[v].emplace_back((tile << 32) | zbits[o], (uint32_t)o);
+                }
+        }
+        std::stable_sort(inst[v].begin(), inst[v].end(),
+                         [](const std::pair<uint64_t, uint32_t>& a, const std::pair<uint64_t, uint32_t>& b) {
+                             return a.first < b.first;
+                         });
+    }
+    for (long t = 0; t < T; ++t) { ranges[2 * t] = 0; ranges[2 * t + 1] = 0; }
+    size_t k = 0;
+    for (int v = 0; v < V; ++v) {
+        for (const auto& e : inst[v]) {
+            keys[k] = e.first;
+            vals[k] = e.second;
+            uint64_t t = e.first >> 32;
+            if (k == 0 || (keys[k - 1] >> 32) != t) ranges[2 * t] = (uint32_t)k;
+            ranges[2 * t + 1] = (uint32_t)(k + 1);
+            ++k;
+        }
+        std::vector<std::pair<uint64_t, uint32_t>>().swap(inst[v]);
+    }
+    return (long)k;
+}
+
+// Per pair: the tiles of its rectangle listed with certainty (n_in) and those
+// whose decision lies within the float32 band (n_band) -- see tile_status;
+// perr ([V*N][3], nullable) adds the end-to-end record error bounds.
+int orc_bin_pair_counts(int N, int V, const double* views, int tile_w, int tile_h, const int32_t* tile_rect,
+                        const uint32_t* tiles_touched, const double* rec, const double* perr, uint32_t* n_in,
+                        uint32_t* n_band) {
+    std::vector<View> vw = read_views(views, V, tile_w, tile_h);
+    const long VN = (long)V * N;
+#pragma omp parallel for schedule(dynamic, 4096)
+    for (long o = 0; o < VN; ++o) {
+        uint32_t a = 0, b = 0;
+        if (tiles_touched[o] != 0) {
+            const int32_t* r = tile_rect + 4 * o;
+            const Rec s = load_rec(rec, o);
+            const TileBand tb = tile_band_params(s, vw[o / N], load_err(perr, o));
+            for (int ty = r[1]; ty <= r[3]; ++ty)
+                for (int tx = r[0]; tx <= r[2]; ++tx) {
+                    int st = tile_status(s, tx, ty, tile_w, tile_h, tb);
+                    a += st == 0;
+                    b += st == 1;
+                }
+        }
+        n_in[o] = a;
+        n_band[o] = b;
+    }
+    return 0;
+}
+
+// The (pair, global tile) decisions of every rectangle that lie within the
+// float32 band, in (view, splat, row, column) order, with the FP64 rule's
+// outcome (listed 1/0).  Writes at most `cap`; returns the total count.
+long orc_bin_band(int N, int V, const double* views, int tile_w, int tile_h, const int32_t* tile_rect,
+                  const uint32_t* tiles_touched, const double* rec, const double* perr, long cap, uint32_t* pair,
+                  uint32_t* tile, uint8_t* listed) {
+    std::vector<View> vw = read_views(views, V, tile_w, tile_h);
+    long n = 0;
     for (int v = 0; v < V; ++v)
         for (long i = 0; i < N; ++i) {
             long o = (long)v * N + i;
             if (tiles_touched[o] == 0) continue;
             const int32_t* r = tile_rect + 4 * o;
-            for (int ty = r[1]; ty <= r[3]; ++ty) {
-                int c0 = r[0], c1 = r[2];
-                row_columns_f32(rec + 12 * o, ty, tile_w, tile_h, &c0, &c1);
-                for (int tx = c0; tx <= c1; ++tx) {
-                    uint64_t tile = (uint64_t)(vw[v].tile_base + (long)ty * vw[v].tiles_x + tx);
-                    inst.emplace_back((tile << 32) | zbits[o], (uint32_t)o);
+            const Rec s = load_rec(rec, o);
+            const TileBand tb = tile_band_params(s, vw[v], load_err(perr, o));
+            for (int ty = r[1]; ty <= r[3]; ++ty)
+                for (int tx = r[0]; tx <= r[2]; ++tx) {
+                    if (tile_status(s, tx, ty, tile_w, tile_h, tb) != 1) continue;
+                    if (n < cap) {
+                        pair[n] = (uint32_t)o;
+                        tile[n] = (uint32_t)(vw[v].tile_base + (long)ty * vw[v].tiles_x + tx);
+                        listed[n] = tile_listed(s, tx, ty, tile_w, tile_h) ? 1 : 0;
+                    }
+                    ++n;
                 }
-            }
         }
-    std::stable_sort(inst.begin(), inst.end(),
-                     [](const std::pair<uint64_t, uint32_t>& a, const std::pair<uint64_t, uint32_t>& b) {
-                         return a.first < b.first;
-                     });
-    for (long t = 0; t < T; ++t) { ranges[2 * t] = 0; ranges[2 * t + 1] = 0; }
-    for (size_t k = 0; k < inst.size(); ++k) {
-        keys[k] = inst[k].first;
-        vals[k] = inst[k].second;
-        uint64_t t = inst[k].first >> 32;
-        if (k == 0 || (inst[k - 1].first >> 32) != t) ranges[2 * t] = (uint32_t)k;
-        ranges[2 * t + 1] = (uint32_t)(k + 1);
-    }
-    return (long)inst.size();
+    return n;
 }
 
-// Instances per pair under the same per-row column rule as orc_bin (counts
-// only; VN pairs, rec [VN][12] factored records).
-int orc_bin_pair_counts(long VN, const int32_t* tile_rect, const uint32_t* tiles_touched, const double* rec,
-                        int tile_w, int tile_h, uint32_t* counts) {
-#pragma omp parallel for schedule(dynamic, 4096)
-    for (long o = 0; o < VN; ++o) {
-        uint32_t c = 0;
-        if (tiles_touched[o] != 0) {
+// Status of L listed instances (pair vals[k], global tile tiles[k]) under the
+// tile rule: 0 listed with certainty, 1 within the band, 2 not listed with
+// certainty, 3 a tile outside the pair's view or rectangle.
+int orc_instance_status(int N, int V, const double* views, int tile_w, int tile_h, const int32_t* tile_rect,
+                        const double* rec, const double* perr, long L, const uint32_t* vals, const uint32_t* tiles,
+                        uint8_t* status) {
+    std::vector<View> vw = read_views(views, V, tile_w, tile_h);
+#pragma omp parallel for schedule(static)
+    for (long k = 0; k < L; ++k) {
+        const long o = vals[k];
+        const int v = (int)(o / N);
+        const View& w = vw[v];
+        const long lt = (long)tiles[k] - w.tile_base;
+        uint8_t st = 3;
+        if (lt >= 0 && lt < (long)w.tiles_x * w.tiles_y) {
+            const int tx = (int)(lt % w.tiles_x), ty = (int)(lt / w.tiles_x);
             const int32_t* r = tile_rect + 4 * o;
-            for (int ty = r[1]; ty <= r[3]; ++ty) {
-                int c0 = r[0], c1 = r[2];
-                row_columns_f32(rec + 12 * o, ty, tile_w, tile_h, &c0, &c1);
-                if (c1 >= c0) c += (uint32_t)(c1 - c0 + 1);
+            if (tx >= r[0] && tx <= r[2] && ty >= r[1] && ty <= r[3]) {
+                const Rec s = load_rec(rec, o);
+                st = (uint8_t)tile_status(s, tx, ty, tile_w, tile_h, tile_band_params(s, w, load_err(perr, o)));
             }
         }
-        counts[o] = c;
+        status[k] = st;
     }
     return 0;
 }
 
 // Tiled forward: every pixel composites the sorted list of its tile.
 // Outputs (concatenated over views): image [3][H][W] per view, final_T,
-// n_contrib, n_listed, n_hit, ambig (bit0 alpha ~ alpha_min, bit1 oG ~ alpha_max,
-// bit2 T' ~ t_min); with `depth` ([V*N] splat depths) non-null, the extended
-// channels out_depth and out_alpha ([P] each, nullable).
+// n_contrib, n_listed, n_hit, ambig, n_branch and last (see PixelOut); with `depth`
+// ([V*N] splat depths) non-null, the extended channels out_depth and
+// out_alpha ([P] each, nullable).  perr ([V*N][3], nullable): end-to-end
+// record error bounds that widen the decision bands; paths ([P], nullable):
+// the decision path of each pixel (composite_pixel; null = 0 everywhere).
 int orc_render_fwd(int N, int V, const double* views, const double* settings, const double* rec,
-                   const uint32_t* vals, const uint32_t* ranges, double* image, double* final_T,
-                   uint32_t* n_contrib, uint32_t* n_listed, uint32_t* n_hit, uint8_t* ambig, const double* depth,
-                   double* out_depth, double* out_alpha) {
+                   const uint32_t* vals, const uint32_t* ranges, const double* perr, const uint32_t* paths,
+                   double* image, double* final_T, uint32_t* n_contrib, uint32_t* n_listed, uint32_t* n_hit,
+                   uint8_t* ambig, uint8_t* n_branch, int64_t* last, const double* depth, double* out_depth,
+                   double* out_alpha) {
     (void)N;
     Settings st = read_settings(settings);
     std::vector<View> vw = read_views(views, V, st.tile_w, st.tile_h);
@@ -669,10 +988,10 @@ int orc_render_fwd(int N, int V, const double* views, const double* settings, co
             for (long x = 0; x < w.W; ++x) {
                 long t = w.tile_base + (y / st.tile_h) * w.tiles_x + x / st.tile_w;
                 uint32_t s0 = ranges[2 * t], s1 = ranges[2 * t + 1];
+                long p = w.pix_base + y * w.W + x;
                 PixelOut po = composite_pixel(
                     (long)s1 - s0, [&](long k) { return (long)vals[s0 + k]; }, rec, x + 0.5, y + 0.5, st, nullptr,
-                    nullptr, depth);
-                long p = w.pix_base + y * w.W + x;
+                    nullptr, depth, perr, paths ? paths[p] : 0u);
                 long HW = (long)w.W * w.H;
                 for (int c = 0; c < 3; ++c) image[3 * w.pix_base + c * HW + y * w.W + x] = po.C[c];
                 final_T[p] = po.T;
@@ -682,6 +1001,97 @@ int orc_render_fwd(int N, int V, const double* views, const double* settings, co
                 if (n_listed) n_listed[p] = po.n_listed;
                 if (n_hit) n_hit[p] = po.n_hit;
                 if (ambig) ambig[p] = po.ambig;
+                if (n_branch) n_branch[p] = po.n_branch;
+                if (last) last[p] = po.last;
+            }
+    }
+    return 0;
+}
+
+// o G of n fragments (record rec[k] at pixel centre (px[k], py[k])) and the
+// float32 band of ln(o G) (frag_band; perr [n][3] nullable).
+int orc_fragment_band(long n, const double* rec, const double* px, const double* py, const double* settings,
+                      const double* perr, double* oG, double* band) {
+    Settings st = read_settings(settings);
+#pragma omp parallel for schedule(static)
+    for (long k = 0; k < n; ++k) {
+        const Rec s = load_rec(rec, k);
+        const Frag f = eval_frag(s, px[k], py[k], st);
+        oG[k] = f.oG;
+        band[k] = frag_band(f, s, st, load_err(perr, k));
+    }
+    return 0;
+}
+
+// Which of a pixel's correct results a float32 rasterizer produced.  Every
+// pixel whose plain FP64 composite meets a decision within its band has
+// several correct results, one per decision path; they are enumerated depth
+// first (at most max_leaves) and the path whose result matches the given one
+// -- the same last composited fragment (g_last: record index, -1 if none), the
+// same n_hit when given, every colour channel within
+// tol_view[v] and final T within tol_T -- is chosen (the closest match when
+// several do).  Outputs per pixel: paths (0 unless status 1) and status:
+//   0  no decision within its band: one correct result (path 0);
+//   1  resolved: the given result is the one of `paths`;
+//   2  o G within the band of alpha_max (the cap's two outcomes give the
+//      same image but different derivatives, so it cannot be told apart);
+//   3  more than max_leaves paths;
+//   4  no path's result matches.
+// The given result only selects among results the oracle computes itself.
+int orc_resolve(int N, int V, const double* views, const double* settings, const double* rec, const uint32_t* vals,
+                const uint32_t* ranges, const double* perr, const float* g_image, const float* g_T,
+                const int64_t* g_last, const uint32_t* g_nhit, const double* tol_view, double tol_T, int max_leaves,
+                uint32_t* paths, uint8_t* status) {
+    (void)N;
+    Settings st = read_settings(settings);
+    std::vector<View> vw = read_views(views, V, st.tile_w, st.tile_h);
+    for (int v = 0; v < V; ++v) {
+        const View& w = vw[v];
+        const long HW = (long)w.W * w.H;
+#pragma omp parallel for schedule(dynamic, 16)
+        for (long y = 0; y < w.H; ++y)
+            for (long x = 0; x < w.W; ++x) {
+                const long t = w.tile_base + (y / st.tile_h) * w.tiles_x + x / st.tile_w;
+                const uint32_t s0 = ranges[2 * t], s1 = ranges[2 * t + 1];
+                const long p = w.pix_base + y * w.W + x;
+                auto run = [&](uint32_t path) {
+                    return composite_pixel((long)s1 - s0, [&](long k) { return (long)vals[s0 + k]; }, rec, x + 0.5,
+                                           y + 0.5, st, nullptr, nullptr, nullptr, perr, path);
+                };
+                auto mismatch = [&](const PixelOut& o) {  // < 0: outputs differ; else the largest error
+                    if (o.last != g_last[p]) return -1.0;
+                    if (g_nhit && o.n_hit != g_nhit[p]) return -1.0;
+                    double e = 0.0;
+                    for (int c = 0; c < 3; ++c)
+                        e = std::max(e, std::fabs(o.C[c] - (double)g_image[3 * w.pix_base + c * HW + y * w.W + x]));
+                    if (e > tol_view[v] || std::fabs(o.T - (double)g_T[p]) > tol_T) return -1.0;
+                    return e;
+                };
+                const PixelOut o0 = run(0u);
+                paths[p] = 0u;
+                if (o0.ambig & 2) { status[p] = 2; continue; }
+                if (o0.n_branch == 0) { status[p] = 0; continue; }
+                // depth-first enumeration: explore(prefix, j0) yields the path
+                // `prefix`, then for each decision j >= j0 met along it the paths
+                // that agree with it before j and flip decision j
+                int leaves = 0;
+                bool overflow = false;
+                double best = -1.0;
+                uint32_t best_path = 0u;
+                std::vector<std::pair<uint32_t, int>> stack{{0u, 0}};
+                while (!stack.empty()) {
+                    auto [prefix, j0] = stack.back();
+                    stack.pop_back();
+                    if (++leaves > max_leaves) { overflow = true; break; }
+                    const PixelOut o = prefix ? run(prefix) : o0;
+                    const double e = mismatch(o);
+                    if (e >= 0.0 && (best < 0.0 || e < best)) { best = e; best_path = prefix; }
+                    for (int j = std::min<int>(o.n_branch, 32) - 1; j >= j0; --j)
+                        stack.emplace_back(prefix | (1u << j), j + 1);
+                }
+                if (overflow) status[p] = 3;
+                else if (best < 0.0) status[p] = 4;
+                else { status[p] = 1; paths[p] = best_path; }
             }
     }
     return 0;
@@ -756,8 +1166,9 @@ int orc_brute_fwd(int N, int V, const double* views, const double* settings, con
 // dopacity, dbeta, dr, dg, db, dz).  Accumulation uses one buffer per thread,
 // summed in thread order.
 int orc_render_bwd(int N, int V, const double* views, const double* settings, const double* rec,
-                   const uint32_t* vals, const uint32_t* ranges, const double* dL_dimage, const double* depth,
-                   const double* dL_ddepth, const double* dL_dalpha, double* grad2d) {
+                   const uint32_t* vals, const uint32_t* ranges, const double* perr, const uint32_t* paths,
+                   const double* dL_dimage, const double* depth, const double* dL_ddepth, const double* dL_dalpha,
+                   double* grad2d) {
     Settings st = read_settings(settings);
     std::vector<View> vw = read_views(views, V, st.tile_w, st.tile_h);
     long VN = (long)V * N;
@@ -777,12 +1188,12 @@ int orc_render_bwd(int N, int V, const double* views, const double* settings, co
                     long t = w.tile_base + (y / st.tile_h) * w.tiles_x + x / st.tile_w;
                     uint32_t s0 = ranges[2 * t], s1 = ranges[2 * t + 1];
                     hits.clear();
+                    const long p = w.pix_base + y * w.W + x;
                     PixelOut po = composite_pixel(
                         (long)s1 - s0, [&](long k) { return (long)vals[s0 + k]; }, rec, x + 0.5, y + 0.5, st, &hits,
-                        nullptr, depth);
+                        nullptr, depth, perr, paths ? paths[p] : 0u);
                     double g[3];
                     for (int c = 0; c < 3; ++c) g[c] = dL_dimage[3 * w.pix_base + c * HW + y * w.W + x];
-                    const long p = w.pix_base + y * w.W + x;
                     const double gD = (depth && dL_ddepth) ? dL_ddepth[p] : 0.0;
                     const double gA = (depth && dL_dalpha) ? dL_dalpha[p] : 0.0;
                     pixel_adjoint(hits, po.T, g, gD, gA, rec, st, g2.data());

@@ -14,10 +14,13 @@ def single_splat_scene(mean=(0.0, 0.0, 0.0), scale=(0.1, 0.1, 0.1), quat=(1.0, 0
     return stacked_scene([mean], [scale], [quat], [opacity], [beta], [rgb], width, height, cam_pos)
 
 
-def stacked_scene(means, scales, quats, opacities, betas, rgbs, width=64, height=48, cam_pos=(0.0, 0.0, -4.0)):
+def stacked_scene(means, scales, quats, opacities, betas, rgbs, width=64, height=48, cam_pos=(0.0, 0.0, -4.0),
+                  sh_dtype=np.float32):
+    """Splats with degree-0 SH coefficients (rgb - 1/2) / Y00; sh_dtype float64
+    keeps them unrounded."""
     n = len(means)
     c0 = 0.5 / np.sqrt(np.pi)  # the constant degree-0 harmonic 1/(2 sqrt(pi))
-    sh = np.zeros((n, 1, 3), np.float32)
+    sh = np.zeros((n, 1, 3), sh_dtype)
     sh[:, 0, :] = (np.asarray(rgbs, np.float64) - 0.5) / c0
     scales = np.asarray(scales, np.float32)
     op = np.asarray(opacities, np.float32)

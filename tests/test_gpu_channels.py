@@ -1,12 +1,13 @@
 """GPU parity of the extended channels (the depth maps of the mesh-extraction
 passage, Sec. 3.3, and the accumulated opacity) against the FP64 oracle.
 
-Same-inputs comparisons, as for the colour stages: the oracle composites the
-GPU's own records (their last field is the splat depth) and tile lists.  Bars
-as for the colour image and its gradients: depth and alpha within 1e-4 of the
-oracle's max |value| per view on non-ambiguous pixels; screen-space and
-parameter gradients within 1e-3 (inf- and 2-norm) for seeded upstream
-gradients of colour, depth and alpha, zeroed at ambiguous pixels.  The alpha
+Same-inputs comparisons, as for the colour stages: the oracle composites its
+own tile lists of the GPU's records (their last field is the splat depth),
+along the decision path that the GPU's colour result matches.  Bars as for
+the colour image and its gradients: depth and alpha within 1e-4 of the
+oracle's max |value| per view on every pixel except the masked ones;
+screen-space and parameter gradients within 1e-3 (inf- and 2-norm) for seeded
+upstream gradients of colour, depth and alpha, zeroed at masked pixels.  The alpha
 map is exactly 1 - final_T, and asking for the channels leaves the colour
 outputs bitwise unchanged.
 """
@@ -18,7 +19,7 @@ import pytest
 import gesr_inputs as gi
 import oracle
 from tests.gpu_util import (conic_grads_to_factor, f32, factor_grads_to_conic, log, mask_upstream, norm_errors,
-                            oracle_rec, raster_settings, run_gpu)
+                            raster_settings, run_gpu, same_input_reference)
 from tests.test_gpu_parity import _case
 
 pytestmark = pytest.mark.gpu
@@ -49,10 +50,9 @@ def _run(name):
     P = scene.n_pixels
     g["ext"] = {k: f32(ext[k])[:P * (3 if k == "image" else 1)] for k in ("image", "final_T", "depth", "alpha")}
     g["ext"]["n_contrib"] = ext["n_contrib"].cpu().numpy()[:P]
-    rec = oracle_rec(g["rec"])
     depth = g["rec"][:, 11].astype(np.float64)
-    fo = oracle.render_fwd(scene.n, scene.cameras, rec, g["val_sorted"], g["ranges"], st, depth=depth)
-    return scene, st, g, rec, depth, fo
+    ref = same_input_reference(scene, st, g, depth=depth)
+    return scene, st, g, ref, depth, ref["fwd"]
 
 
 def _per_view_errors(gpu, ref, amb, cameras, tol=1e-4):
@@ -70,7 +70,7 @@ def _per_view_errors(gpu, ref, amb, cameras, tol=1e-4):
 
 @pytest.mark.parametrize("name", CASES)
 def test_channels_forward_same_inputs(name):
-    scene, st, g, rec, depth, fo = _run(name)
+    scene, st, g, ref, depth, fo = _run(name)
     e = g["ext"]
     # the colour outputs do not depend on asking for the channels
     np.testing.assert_array_equal(e["image"], g["image"])
@@ -78,10 +78,10 @@ def test_channels_forward_same_inputs(name):
     np.testing.assert_array_equal(e["n_contrib"], g["n_contrib"].view(np.int32))
     # alpha is 1 - final_T in float32, bit for bit
     np.testing.assert_array_equal(e["alpha"], (np.float32(1.0) - g["final_T"]).astype(np.float32))
-    amb = fo["ambig"] > 0
+    amb = ref["masked"]
     _per_view_errors(e["depth"], fo["depth"], amb, scene.cameras)
     _per_view_errors(e["alpha"], fo["alpha"], amb, scene.cameras)
-    log(f"[gpu] {name}: channels fwd ok; ambiguous px {int(amb.sum())}/{amb.size}")
+    log(f"[gpu] {name}: channels fwd ok; masked px {int(amb.sum())}/{amb.size}")
 
 
 @pytest.mark.parametrize("name", CASES)
@@ -89,9 +89,9 @@ def test_channels_backward_same_inputs(name):
     """Screen-space gradients (eleven terms, dz included) and the parameter
     gradients for seeded upstream gradients of colour, depth and alpha."""
     import torch
-    scene, st, g, rec, depth, fo = _run(name)
+    scene, st, g, ref, depth, fo = _run(name)
     rast, sp, out = g["torch"]
-    amb = fo["ambig"] > 0
+    amb = ref["masked"]
     rng = np.random.default_rng(5)
     P = scene.n_pixels
     dL = mask_upstream(oracle.flat_images(gi.upstream_grads(scene, 7)), amb, scene.cameras)
@@ -103,16 +103,16 @@ def test_channels_backward_same_inputs(name):
     torch.cuda.synchronize()
     got = _grads(scene, st, gb)
     assert (got["grad2d"][:, 11] == 0).all()
-    g2 = oracle.render_bwd(scene.n, scene.cameras, rec, g["val_sorted"], g["ranges"], dL, st, depth=depth,
-                           dL_ddepth=gD, dL_dalpha=gA)
-    ref = conic_grads_to_factor(g2, g["rec"])
+    g2 = oracle.render_bwd(scene.n, scene.cameras, ref["rec"], ref["vals"], ref["ranges"], dL, st, depth=depth,
+                           dL_ddepth=gD, dL_dalpha=gA, paths=ref["paths"])
+    refg = conic_grads_to_factor(g2, g["rec"])
     labels = ["du", "dv", "dL00", "dL10", "dL11", "dop", "dbeta", "dr", "dg", "db", "dz"]
     worst = 0.0
     for k, lab in enumerate(labels):
-        einf, e2 = norm_errors(got["grad2d"][:, k], ref[:, k])
+        einf, e2 = norm_errors(got["grad2d"][:, k], refg[:, k])
         worst = max(worst, einf, e2)
         assert einf <= 1e-3 and e2 <= 1e-3, (lab, einf, e2)
-    assert np.abs(ref[:, 10]).max() > 0
+    assert np.abs(refg[:, 10]).max() > 0
     pref = oracle.project_bwd(scene, factor_grads_to_conic(got["grad2d"][:, :11], g["rec"]), st)
     for k in PARAMS:
         einf, e2 = norm_errors(got[k], pref[k])
@@ -126,7 +126,7 @@ def test_zero_channel_gradients_match_plain_backward(name):
     """The channel kernels with zero depth and alpha gradients reproduce the
     plain backward bit for bit (the added terms are exact zeros)."""
     import torch
-    scene, st, g, rec, depth, fo = _run(name)
+    scene, st, g, ref, depth, fo = _run(name)
     rast, sp, out = g["torch"]
     dL = torch.as_tensor(oracle.flat_images(gi.upstream_grads(scene, 3)).astype(np.float32), device="cuda")
     zero = torch.zeros(scene.n_pixels, dtype=torch.float32, device="cuda")

@@ -1,23 +1,24 @@
 """GPU parity of every hot-path stage against the FP64 oracle.
 
-Stage tests feed the oracle the GPU's own inputs for that stage (so a
-disagreement is the stage's own), then an end-to-end test compares the whole
-GPU pipeline with the oracle run from the splat parameters.
+Stage tests feed the oracle the GPU's projection records (so a disagreement
+downstream is the stage's own), then an end-to-end test compares the whole GPU
+pipeline with the oracle run from the splat parameters.  The parity model
+(decision bands, decision paths, masking) is described in tests/gpu_util.py.
 
-Bars (derived in the design notes):
-  * binning: bit-exact keys, values, ranges, instance count and instance bases;
-  * images / final_T: max error <= 1e-4 * max(max|C|, 1) on pixels that are not
-    ambiguous, and relative L2 <= 1e-4 over all pixels; n_contrib and the
-    fragment counts exact on non-ambiguous pixels.  A pixel is ambiguous when
-    one of its fragments lies within the float32 error band of alpha_min,
-    alpha_max or t_min (1e-5 relative when both sides share the GPU's records;
-    end to end the band adds the first-order effect of float32 centre and
-    conic error), or, end to end, when compositing the GPU's tile list instead
-    of the oracle's changes the oracle's own result at that pixel;
+Bars:
+  * projection: within the a-priori float32 bounds of the oracle's
+    record_err_bound (centre, conic, qmax), colour 1e-5, opacity and beta exact;
+  * binning: the GPU's sorted lists equal the oracle's footprint rule (FP64)
+    after removing the decisions within the rule's float32 band (whose count
+    is logged); ranges, worklist and instance bases exact;
+  * images / final_T: max error <= 1e-4 * max(max|C|, 1) per view and relative
+    L2 <= 1e-4, against the oracle along the decision path that the GPU's
+    result matches (every pixel except the masked ones, at most 1e-3 of them);
+    the last composited splat and the hit count exact there; n_contrib and the
+    listed count exact in tiles whose two lists are identical;
   * gradients: per tensor, inf-norm and 2-norm of the error <= 1e-3 of the
     reference's norms, for the same seeded upstream dL/dimage on both sides,
-    zeroed at ambiguous pixels (a threshold flip there is a legitimate
-    difference, not an error).
+    zeroed only at masked pixels.
 """
 import functools
 
@@ -26,8 +27,9 @@ import pytest
 
 import gesr_inputs as gi
 import oracle
-from tests.gpu_util import (check_projection, conic_grads_to_factor, e2e_settings, factor_grads_to_conic,
-                            image_errors, log, mask_upstream, norm_errors, oracle_rec, run_gpu, run_gpu_bwd)
+from tests.gpu_util import (ambiguous_tiles_to_pixels, check_projection, compare_lists, conic_grads_to_factor,
+                            differing_tiles, end_to_end_reference, factor_grads_to_conic, image_errors, log,
+                            mask_upstream, norm_errors, oracle_rec, run_gpu, run_gpu_bwd, same_input_reference)
 
 pytestmark = pytest.mark.gpu
 
@@ -85,93 +87,96 @@ def _run(name):
 
 @functools.lru_cache(maxsize=1)
 def _same_inputs(name):
-    """Oracle fed the GPU's records and lists; gradients for an upstream dL that
-    is zero at pixels whose decisions are ambiguous (identical on both sides)."""
+    """Oracle fed the GPU's records; gradients for an upstream dL that is zero
+    at masked pixels only (identical on both sides)."""
     scene, st, g = _run(name)
-    rec = oracle_rec(g["rec"])
-    fwd = oracle.render_fwd(scene.n, scene.cameras, rec, g["val_sorted"], g["ranges"], st)
-    dL = mask_upstream(oracle.flat_images(gi.upstream_grads(scene, 7)), fwd["ambig"] > 0, scene.cameras)
+    ref = same_input_reference(scene, st, g)
+    dL = mask_upstream(oracle.flat_images(gi.upstream_grads(scene, 7)), ref["masked"], scene.cameras)
     log(f"[gpu] case {name}: backward (same inputs)")
     gb = run_gpu_bwd(scene, st, g, dL)
-    g2 = oracle.render_bwd(scene.n, scene.cameras, rec, g["val_sorted"], g["ranges"], dL, st)
-    return rec, fwd, dL, gb, g2
+    g2 = oracle.render_bwd(scene.n, scene.cameras, ref["rec"], ref["vals"], ref["ranges"], dL, st, paths=ref["paths"])
+    return ref, dL, gb, g2
 
 
 @functools.lru_cache(maxsize=1)
 def _end_to_end(name):
-    """Oracle run from the parameters.  Ambiguous pixels: a fragment inside the
-    float32 band of a threshold, or a pixel whose oracle result changes when
-    the oracle composites the GPU's tile lists instead of its own (the lists
-    differ only at guard bands of the rectangles and depth keys)."""
+    """Oracle run from the parameters, decision paths resolved to the GPU's result."""
     scene, st, g = _run(name)
-    se = e2e_settings(st, scene.cameras)
-    fo = oracle.forward(scene, se)
-    fl = oracle.render_fwd(scene.n, scene.cameras, fo["proj"]["rec"], g["val_sorted"], g["ranges"], se)
-    P = scene.n_pixels
-    changed = (fl["image"] != fo["image"]).reshape(-1)
-    list_amb = np.zeros(P, bool)
-    off_i = off_p = 0
-    for c in scene.cameras:
-        n = c.width * c.height
-        list_amb[off_p:off_p + n] = changed[off_i:off_i + 3 * n].reshape(3, n).any(0)
-        off_i += 3 * n
-        off_p += n
-    list_amb |= fl["final_T"] != fo["final_T"]
-    amb = (fo["ambig"] > 0) | (fl["ambig"] > 0) | list_amb
-    dL = mask_upstream(oracle.flat_images(gi.upstream_grads(scene, 7)), amb, scene.cameras)
-    log(f"[gpu] case {name}: backward (end to end); pixels changed by the GPU lists {int(list_amb.sum())}")
+    ref = end_to_end_reference(scene, st, g)
+    dL = mask_upstream(oracle.flat_images(gi.upstream_grads(scene, 7)), ref["masked"], scene.cameras)
+    log(f"[gpu] case {name}: backward (end to end)")
     gb = run_gpu_bwd(scene, st, g, dL)
-    go = oracle.backward(scene, se, fo, dL)
-    return fo, amb, dL, gb, go
+    go = oracle.backward(scene, st, ref["fo"], dL, paths=ref["paths"])
+    return ref, dL, gb, go
+
+
+def _check_forward(scene, g, o, masked, tiles_same, name, label):
+    """Image, final T and counts of the GPU against the oracle's forward `o`
+    (already along the matched decision paths)."""
+    errs = image_errors(g["image"], o["image"], masked, scene.cameras)
+    for bad, mx, bound, l2 in errs:
+        assert bad == 0 and l2 <= 1e-4, errs
+    ok = ~masked
+    assert np.abs(g["final_T"][ok] - o["final_T"][ok]).max() <= 1e-4
+    np.testing.assert_array_equal(g["last"][ok], o["last"][ok])
+    np.testing.assert_array_equal(g["n_hit"][ok], o["n_hit"][ok])
+    same = ok & tiles_same
+    np.testing.assert_array_equal(g["n_contrib"][same], o["n_contrib"][same])
+    np.testing.assert_array_equal(g["n_listed"][same], o["n_listed"][same])
+    log(f"[gpu] {name}: {label} fwd ok; masked px {int(masked.sum())}/{masked.size}; max err "
+        f"{max(e[1] for e in errs):.2e}; listed/px {o['n_listed'].mean():.1f} hit/px {o['n_hit'].mean():.1f}")
 
 
 @pytest.mark.parametrize("name", CASES)
 def test_project(name):
     scene, st, g = _run(name)
-    stats = check_projection(scene, g, oracle.project(scene, st))
+    stats = check_projection(scene, g, oracle.project(scene, st), oracle.record_err_bound(scene, st))
     log(f"[gpu] {name}: project ok; {stats}")
 
 
 @pytest.mark.parametrize("name", CASES)
-def test_bin_bit_exact(name):
-    """Oracle binning of the GPU's own per-splat results (record, rect, depth
-    key) equals the GPU's sorted instance list, ranges, counts and instance
-    bases exactly (each rectangle row's columns decided in float32 from the
-    record on both sides)."""
+def test_bin_lists(name):
+    """The GPU's sorted instance lists equal the oracle's footprint rule (FP64,
+    on the GPU's own records, rectangles and depth keys) outside the rule's
+    float32 band; ranges are those of the lists; worklist, counts and instance
+    bases exact."""
     scene, st, g = _run(name)
+    rec = oracle_rec(g["rec"])
     keys, vals, ranges = oracle.bin_instances(scene.n, scene.cameras, g["tile_rect"], g["tiles_touched"],
-                                              g["depth_key"], st, g["rec"])
+                                              g["depth_key"], st, rec)
+    band = oracle.bin_band(scene.n, scene.cameras, g["tile_rect"], g["tiles_touched"], rec, st)
     assert g["overflow"] == 0
     assert g["M"] == int(g["tiles_touched"].astype(np.int64).sum()) >= g["listed"]
-    assert g["listed"] == len(vals)
-    np.testing.assert_array_equal(g["val_sorted"], vals)
-    np.testing.assert_array_equal(g["tile_sorted"].astype(np.uint64), keys >> np.uint64(32))
-    np.testing.assert_array_equal(g["depth_key"][g["val_sorted"]].astype(np.uint64), keys & np.uint64(0xFFFFFFFF))
-    np.testing.assert_array_equal(g["ranges"], ranges)
+    assert g["listed"] == len(g["val_sorted"])
+    cmp = compare_lists(g["val_sorted"], g["tile_sorted"], g["ranges"], keys, vals, ranges, band)
+    # the GPU's keys: (tile, depth key) of each entry, sorted, ties by pair
+    t = g["tile_sorted"].astype(np.int64)
+    k = g["depth_key"][g["val_sorted"]].astype(np.int64)
+    v = g["val_sorted"].astype(np.int64)
+    same_t = t[1:] == t[:-1]
+    assert (t[1:] >= t[:-1]).all()
+    assert (((k[1:] > k[:-1]) | ((k[1:] == k[:-1]) & (v[1:] > v[:-1]))) | ~same_t).all()
+    counts = np.bincount(t, minlength=len(g["ranges"]))
+    starts = np.concatenate([[0], np.cumsum(counts)[:-1]])
+    np.testing.assert_array_equal(g["ranges"][:, 0], np.where(counts > 0, starts, 0))
+    np.testing.assert_array_equal(g["ranges"][:, 1], np.where(counts > 0, starts + counts, 0))
     # worklist: every tile once, by decreasing list length, ties by tile id
-    lens = ranges[:, 1].astype(np.int64) - ranges[:, 0]
+    lens = g["ranges"][:, 1].astype(np.int64) - g["ranges"][:, 0]
     expect = np.lexsort((np.arange(len(lens)), -np.minimum(lens, 0xFFFF)))
     np.testing.assert_array_equal(g["worklist"], expect)
     # instance slots: exclusive scan of tiles_touched in pair order
     base = np.concatenate([[0], np.cumsum(g["tiles_touched"].astype(np.int64))[:-1]])
     np.testing.assert_array_equal(g["inst_base"], base)
+    log(f"[gpu] {name}: lists ok; {len(vals)} instances; {cmp['n_band']} decisions within the float32 band, "
+        f"{cmp['n_flip']} of them taken the other way")
 
 
 @pytest.mark.parametrize("name", CASES)
 def test_render_fwd_same_inputs(name):
     scene, st, g = _run(name)
-    rec, fwd, dL, gb, g2 = _same_inputs(name)
-    amb = fwd["ambig"] > 0
-    errs = image_errors(g["image"], fwd["image"], amb, scene.cameras)
-    for bad, mx, bound, l2 in errs:
-        assert bad == 0 and l2 <= 1e-4, errs
-    ok = ~amb
-    assert np.abs(g["final_T"][ok] - fwd["final_T"][ok]).max() <= 1e-4
-    np.testing.assert_array_equal(g["n_contrib"][ok], fwd["n_contrib"][ok])
-    np.testing.assert_array_equal(g["n_listed"][ok], fwd["n_listed"][ok])
-    np.testing.assert_array_equal(g["n_hit"][ok], fwd["n_hit"][ok])
-    log(f"[gpu] {name}: fwd ok; ambiguous px {int(amb.sum())}/{amb.size}; max err "
-        f"{max(e[1] for e in errs):.2e}; listed/px {fwd['n_listed'].mean():.1f} hit/px {fwd['n_hit'].mean():.1f}")
+    ref, dL, gb, g2 = _same_inputs(name)
+    same = ~ambiguous_tiles_to_pixels(scene.cameras, st, ref["lists"]["tiles_differ"])
+    _check_forward(scene, dict(g, last=ref["last"]), ref["fwd"], ref["masked"], same, name, "same inputs")
 
 
 @pytest.mark.parametrize("name", CASES)
@@ -179,12 +184,12 @@ def test_render_bwd_same_inputs(name):
     """Screen-space gradients per (view, splat) after the tile partials and the
     segmented sum, against the oracle's explicit-list adjoint."""
     scene, st, g = _run(name)
-    rec, fwd, dL, gb, g2 = _same_inputs(name)
-    ref = conic_grads_to_factor(g2, g["rec"])
+    ref, dL, gb, g2 = _same_inputs(name)
+    refg = conic_grads_to_factor(g2, g["rec"])
     labels = ["du", "dv", "dL00", "dL10", "dL11", "dop", "dbeta", "dr", "dg", "db"]
     worst = 0.0
     for k, lab in enumerate(labels):
-        einf, e2 = norm_errors(gb["grad2d"][:, k], ref[:, k])
+        einf, e2 = norm_errors(gb["grad2d"][:, k], refg[:, k])
         worst = max(worst, einf, e2)
         assert einf <= 1e-3 and e2 <= 1e-3, (lab, einf, e2)
     log(f"[gpu] {name}: bwd ok; worst {worst:.2e}")
@@ -195,10 +200,10 @@ def test_project_bwd_same_inputs(name):
     """Projection adjoint fed the GPU's own screen-space gradients: the oracle's
     dual-number Jacobian gives the reference parameter gradients."""
     scene, st, g = _run(name)
-    rec, fwd, dL, gb, g2 = _same_inputs(name)
-    ref = oracle.project_bwd(scene, factor_grads_to_conic(gb["grad2d"], g["rec"]), st)
+    ref, dL, gb, g2 = _same_inputs(name)
+    pref = oracle.project_bwd(scene, factor_grads_to_conic(gb["grad2d"], g["rec"]), st)
     for k in ("means", "scales", "quats", "opacities", "betas", "sh"):
-        einf, e2 = norm_errors(gb[k], ref[k])
+        einf, e2 = norm_errors(gb[k], pref[k])
         assert einf <= 1e-3 and e2 <= 1e-3, (k, einf, e2)
 
 
@@ -206,19 +211,17 @@ def test_project_bwd_same_inputs(name):
 def test_end_to_end(name):
     """Whole GPU pipeline vs the oracle run from the splat parameters."""
     scene, st, g = _run(name)
-    fo, amb, dL, gb, go = _end_to_end(name)
-    errs = image_errors(g["image"], fo["image"], amb, scene.cameras)
-    for bad, mx, bound, l2 in errs:
-        assert bad == 0 and l2 <= 1e-4, errs
-    ok = ~amb
-    assert np.abs(g["final_T"][ok] - fo["final_T"][ok]).max() <= 1e-4
+    ref, dL, gb, go = _end_to_end(name)
+    fo = ref["fo"]
+    same = ~ambiguous_tiles_to_pixels(scene.cameras, st, differing_tiles(g["val_sorted"], g["ranges"], fo["vals"],
+                                                                          fo["ranges"]))
+    _check_forward(scene, dict(g, last=ref["last"]), fo, ref["masked"], same, name, "end to end")
     worst = 0.0
     for k in ("means", "scales", "quats", "opacities", "betas", "sh"):
         einf, e2 = norm_errors(gb[k], go[k])
         worst = max(worst, einf, e2)
         assert einf <= 1e-3 and e2 <= 1e-3, (k, einf, e2)
-    log(f"[gpu] {name}: end-to-end ok; ambiguous px {int(amb.sum())}/{amb.size}; image max err "
-        f"{max(e[1] for e in errs):.2e}; grad worst {worst:.2e}")
+    log(f"[gpu] {name}: end-to-end gradients ok; worst {worst:.2e}")
 
 
 def _needle_scene(seed=21, n=600):
@@ -264,30 +267,29 @@ def _rectangle_lists(scene, st, g):
 @pytest.mark.parametrize("tile", [(16, 16), (8, 8)])
 def test_needles_tight_lists(tile):
     """Needle-shaped footprints at every angle, many cut by the image border:
-    binning equals the oracle's bit for bit, drops part of the rectangles'
-    tiles, and loses nothing: the oracle composites the GPU's lists and the
-    full rectangles into identical images, hit counts and final T (with fewer
-    listed fragments), and the GPU's image agrees with them."""
+    the lists equal the oracle's footprint rule outside its float32 band and
+    drop part of the rectangles' tiles, and lose nothing: the oracle composites
+    the GPU's lists and the full rectangles into identical images, hit counts
+    and final T (with fewer listed fragments), and the GPU's image is one of
+    the oracle's correct results at every pixel."""
     scene = _needle_scene()
     st = oracle.Settings(tile_w=tile[0], tile_h=tile[1])
     g = run_gpu(scene, st)
-    keys, vals, ranges = oracle.bin_instances(scene.n, scene.cameras, g["tile_rect"], g["tiles_touched"],
-                                              g["depth_key"], st, g["rec"])
-    assert g["overflow"] == 0 and g["listed"] == len(vals) < 0.9 * g["M"]
-    np.testing.assert_array_equal(g["val_sorted"], vals)
-    np.testing.assert_array_equal(g["tile_sorted"].astype(np.uint64), keys >> np.uint64(32))
-    np.testing.assert_array_equal(g["ranges"], ranges)
     rec = oracle_rec(g["rec"])
+    keys, vals, ranges = oracle.bin_instances(scene.n, scene.cameras, g["tile_rect"], g["tiles_touched"],
+                                              g["depth_key"], st, rec)
+    band = oracle.bin_band(scene.n, scene.cameras, g["tile_rect"], g["tiles_touched"], rec, st)
+    assert g["overflow"] == 0 and g["listed"] == len(g["val_sorted"]) < 0.9 * g["M"]
+    cmp = compare_lists(g["val_sorted"], g["tile_sorted"], g["ranges"], keys, vals, ranges, band)
     tight = oracle.render_fwd(scene.n, scene.cameras, rec, g["val_sorted"], g["ranges"], st)
     rv, rr = _rectangle_lists(scene, st, g)
     assert len(rv) == g["M"]
     full = oracle.render_fwd(scene.n, scene.cameras, rec, rv, rr, st)
-    for k in ("image", "final_T", "n_hit"):  # (n_contrib is a position in the list)
+    for k in ("image", "final_T", "n_hit", "last"):  # (n_contrib is a position in the list)
         np.testing.assert_array_equal(tight[k], full[k], err_msg=k)
     assert tight["n_listed"].sum() < full["n_listed"].sum()
-    amb = tight["ambig"] > 0
-    errs = image_errors(g["image"], tight["image"], amb, scene.cameras)
-    for bad, mx, bound, l2 in errs:
-        assert bad == 0 and l2 <= 1e-4, errs
-    np.testing.assert_array_equal(g["n_hit"][~amb], tight["n_hit"][~amb])
-    log(f"[gpu] needles {tile}: listed {g['listed']} of {g['M']} rectangle tiles; ambiguous px {int(amb.sum())}")
+    ref = same_input_reference(scene, st, g)
+    _check_forward(scene, dict(g, last=ref["last"]), ref["fwd"], ref["masked"],
+                   ~ambiguous_tiles_to_pixels(scene.cameras, st, cmp["tiles_differ"]), "needles", str(tile))
+    log(f"[gpu] needles {tile}: listed {g['listed']} of {g['M']} rectangle tiles; {cmp['n_band']} decisions within "
+        f"the band, {cmp['n_flip']} taken the other way")

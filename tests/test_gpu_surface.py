@@ -1,6 +1,6 @@
 """GPU parity of the level-set surface points (Sec. 3.3, mesh extraction)
-against the FP64 oracle on the same inputs: the GPU's records, tile lists and
-its depth and alpha maps.
+against the FP64 oracle on the same inputs: the GPU's records (the oracle
+builds its own tile lists from them) and its depth and alpha maps.
 
 A ray's result hinges on three discrete decisions: whether alpha reaches
 min_alpha, which splat dominates at the depth-map point, and which sample pair
@@ -70,7 +70,10 @@ def _run(name):
     torch.cuda.synchronize()
     gpu = dict(points=f32(res["points"]), normals=f32(res["normals"]),
                dominant=res["dominant"].cpu().numpy().view(np.uint32))
-    ref = oracle.surface_points(scene, oracle_rec(g["rec"]), g["val_sorted"], g["ranges"],
+    rec = oracle_rec(g["rec"])
+    _, vals, ranges = oracle.bin_instances(scene.n, scene.cameras, g["tile_rect"], g["tiles_touched"],
+                                           g["depth_key"], st, rec)
+    ref = oracle.surface_points(scene, rec, vals, ranges,
                                 f32(ext["depth"])[:P].astype(np.float64), alpha.astype(np.float64), pick, st,
                                 n_samples=K, level=LEVEL, span=SPAN, min_alpha=MIN_ALPHA)
     return scene, st, pick, gpu, ref

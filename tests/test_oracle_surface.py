@@ -43,7 +43,7 @@ def _ray(cam, px, py):
 def _run(sc, st, pixels, depth, alpha, K):
     pr = oracle.project(sc, st)
     keys, vals, ranges = oracle.bin_instances(sc.n, sc.cameras, pr["tile_rect"], pr["tiles_touched"], pr["zbits"], st,
-                                              oracle.factor_record(pr["rec"]))
+                                              pr["rec"])
     return oracle.surface_points(sc, pr["rec"], vals, ranges, depth, alpha, pixels, st, n_samples=K, level=LEVEL,
                                  span=SPAN)
 
