@@ -268,11 +268,11 @@ def render_fwd(N, cameras, rec, vals, ranges, st: Settings, depth=None, perr=Non
 
 
 def resolve(N, cameras, rec, vals, ranges, st: Settings, image, final_T, last, n_hit=None, perr=None,
-            tol: float = 1e-4, tol_T: float = 1e-4, max_leaves: int = 64):
+            tol: float = 1e-4, tol_T: float = 1e-4, max_leaves: int = 64, n_listed=None):
     """Decision paths that reproduce a float32 rasterizer's per-pixel result
     (image, final_T, the record index of the last composited fragment `last`
-    (-1 if none), optional n_hit) among the oracle's own correct results (see
-    orc_resolve).  The colour tolerance of view v is
+    (-1 if none), optional n_hit and n_listed (entries 0xFFFFFFFF not compared))
+    among the oracle's own correct results (see orc_resolve).  The colour tolerance of view v is
     tol * max(max |C| of the oracle's plain image of v, 1).  Returns (paths,
     status, plain): per pixel the path and its status (0 unique, 1 resolved, 2
     alpha-cap band, 3 too many paths, 4 no match), and the oracle's plain
@@ -294,7 +294,8 @@ def resolve(N, cameras, rec, vals, ranges, st: Settings, image, final_T, last, n
                       _p(np.ascontiguousarray(ranges, np.uint32)), _p(_perr(perr, V * N)),
                       _p(np.ascontiguousarray(image, np.float32)), _p(np.ascontiguousarray(final_T, np.float32)),
                       _p(np.ascontiguousarray(last, np.int64)),
-                      _p(None if n_hit is None else np.ascontiguousarray(n_hit, np.uint32)), _p(tv),
+                      _p(None if n_hit is None else np.ascontiguousarray(n_hit, np.uint32)),
+                      _p(None if n_listed is None else np.ascontiguousarray(n_listed, np.uint32)), _p(tv),
                       ctypes.c_double(tol_T), int(max_leaves), _p(paths), _p(status))
     return paths[:P], status[:P], plain
 

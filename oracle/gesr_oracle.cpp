@@ -813,8 +813,10 @@ int orc_record_err_bound(int N, int V, const double* means, const double* scales
             const double shear = std::fabs(sb) / std::sqrt(det);
             conic += 4.0 * u * (4.0 + 4.0 * shear);
             const double uu = c.fx * p[0] / p[2] + c.cx, vv = c.fy * p[1] / p[2] + c.cy;
+            // (+ 2^-40 of the magnitudes: the FP64 reference's own rounding)
             out[0] = std::max(0.5 * ulp32(uu) + 3.0 * u * std::fabs(uu - c.cx),
-                              0.5 * ulp32(vv) + 3.0 * u * std::fabs(vv - c.cy));
+                              0.5 * ulp32(vv) + 3.0 * u * std::fabs(vv - c.cy)) +
+                     std::ldexp(std::fabs(uu) + std::fabs(vv) + c.cx + c.cy, -40);
             out[1] = conic;
             out[2] = e_qmax;
         }
@@ -1028,7 +1030,9 @@ int orc_fragment_band(long n, const double* rec, const double* px, const double*
 // several correct results, one per decision path; they are enumerated depth
 // first (at most max_leaves) and the path whose result matches the given one
 // -- the same last composited fragment (g_last: record index, -1 if none), the
-// same n_hit when given, every colour channel within
+// same n_hit and n_listed when given (g_nlisted entries of 0xFFFFFFFF are not
+// compared: n_listed counts list entries, so it is compared only where both
+// sides built the same list), every colour channel within
 // tol_view[v] and final T within tol_T -- is chosen (the closest match when
 // several do).  Outputs per pixel: paths (0 unless status 1) and status:
 //   0  no decision within its band: one correct result (path 0);
@@ -1040,8 +1044,8 @@ int orc_fragment_band(long n, const double* rec, const double* px, const double*
 // The given result only selects among results the oracle computes itself.
 int orc_resolve(int N, int V, const double* views, const double* settings, const double* rec, const uint32_t* vals,
                 const uint32_t* ranges, const double* perr, const float* g_image, const float* g_T,
-                const int64_t* g_last, const uint32_t* g_nhit, const double* tol_view, double tol_T, int max_leaves,
-                uint32_t* paths, uint8_t* status) {
+                const int64_t* g_last, const uint32_t* g_nhit, const uint32_t* g_nlisted, const double* tol_view,
+                double tol_T, int max_leaves, uint32_t* paths, uint8_t* status) {
     (void)N;
     Settings st = read_settings(settings);
     std::vector<View> vw = read_views(views, V, st.tile_w, st.tile_h);
@@ -1061,6 +1065,7 @@ int orc_resolve(int N, int V, const double* views, const double* settings, const
                 auto mismatch = [&](const PixelOut& o) {  // < 0: outputs differ; else the largest error
                     if (o.last != g_last[p]) return -1.0;
                     if (g_nhit && o.n_hit != g_nhit[p]) return -1.0;
+                    if (g_nlisted && g_nlisted[p] != 0xFFFFFFFFu && o.n_listed != g_nlisted[p]) return -1.0;
                     double e = 0.0;
                     for (int c = 0; c < 3; ++c)
                         e = std::max(e, std::fabs(o.C[c] - (double)g_image[3 * w.pix_base + c * HW + y * w.W + x]));

@@ -178,6 +178,15 @@ def check_resolution(status, plain, g_image, g_final_T, last, label) -> np.ndarr
     return masked
 
 
+def listed_where_same(scene, st, g: dict, tiles_differ):
+    """The GPU's per-pixel listed-fragment counts where its tile list equals
+    the oracle's, 0xFFFFFFFF (not compared) elsewhere; None without counts."""
+    if "n_listed" not in g:
+        return None
+    px = ambiguous_tiles_to_pixels(scene.cameras, st, tiles_differ)
+    return np.where(px, np.uint32(0xFFFFFFFF), np.asarray(g["n_listed"], np.uint32)).astype(np.uint32)
+
+
 def same_input_reference(scene, st, g: dict, depth=None) -> dict:
     """The oracle fed the GPU's projection records: its own tile lists from
     them (compared with the GPU's outside the band), each pixel's decision path
@@ -189,7 +198,8 @@ def same_input_reference(scene, st, g: dict, depth=None) -> dict:
     lists = compare_lists(g["val_sorted"], g["tile_sorted"], g["ranges"], keys, vals, ranges, band)
     last = last_composited(scene.cameras, st, g["val_sorted"], g["ranges"], g["n_contrib"])
     paths, status, plain = oracle.resolve(scene.n, scene.cameras, rec, vals, ranges, st, g["image"], g["final_T"],
-                                          last, g.get("n_hit"))
+                                          last, g.get("n_hit"),
+                                          n_listed=listed_where_same(scene, st, g, lists["tiles_differ"]))
     masked = check_resolution(status, plain, g["image"], g["final_T"], last, "same inputs")
     fwd = oracle.render_fwd(scene.n, scene.cameras, rec, vals, ranges, st, depth=depth, paths=paths)
     return dict(rec=rec, keys=keys, vals=vals, ranges=ranges, band=band, lists=lists, last=last, paths=paths,
@@ -203,8 +213,10 @@ def end_to_end_reference(scene, st, g: dict, channels: bool = False) -> dict:
     fo = oracle.forward(scene, st, band=True)
     last = last_composited(scene.cameras, st, g["val_sorted"], g["ranges"], g["n_contrib"])
     pr = fo["proj"]
+    differ = differing_tiles(g["val_sorted"], g["ranges"], fo["vals"], fo["ranges"])
     paths, status, plain = oracle.resolve(scene.n, scene.cameras, pr["rec"], fo["vals"], fo["ranges"], st,
-                                          g["image"], g["final_T"], last, g.get("n_hit"), perr=fo["perr"])
+                                          g["image"], g["final_T"], last, g.get("n_hit"), perr=fo["perr"],
+                                          n_listed=listed_where_same(scene, st, g, differ))
     masked = check_resolution(status, plain, g["image"], g["final_T"], last, "end to end")
     fwd = oracle.render_fwd(scene.n, scene.cameras, pr["rec"], fo["vals"], fo["ranges"], st,
                             depth=pr["depth"] if channels else None, perr=fo["perr"], paths=paths)
