@@ -39,7 +39,8 @@ extern "C" {
 typedef enum {
     GESR_OK = 0,
     GESR_ERR_INVALID = 1,     /* bad argument; nothing enqueued */
-    GESR_ERR_CAPACITY = 2,    /* instance count exceeds bins->m_cap (see gesr_bin) */
+    GESR_ERR_CAPACITY = 2,    /* instance count exceeds bins->m_cap (see gesr_bin), or the
+                                 static scratch (gesr_bin_static) */
     GESR_ERR_HIP = 3,         /* HIP runtime error */
     GESR_ERR_UNSUPPORTED = 4  /* valid but not supported by the library (e.g. tile shape) */
 } gesr_status;
@@ -193,12 +194,13 @@ gesr_status gesr_project(gesr_ctx* ctx, const gesr_splats* splats, const gesr_ca
 
 /* Tile binning: one instance per (view, splat, covered tile), sorted by the
  * (tile | depth) key (see gesr_bins).  A pair covers the tiles of its
- * rectangle's rows whose columns the footprint ellipse reaches within that
- * row: with q = (L00 dx + L10 dy)^2 + (L11 dy)^2 <= Q, Q = qmax (1 + 2^-8),
- * the x-extent of the ellipse over the row's band [ty th, (ty + 1) th) in
- * float32 with correctly rounded square roots and quotients, as tile columns
- * clamped to the rectangle (a superset of the tiles holding a pixel centre
- * with q <= qmax).  The pairs are radix-sorted by (view, depth); the lists
+ * rectangle whose square [tx tw, (tx + 1) tw] x [ty th, (ty + 1) th] meets
+ * its footprint ellipse q = (L00 dx + L10 dy)^2 + (L11 dy)^2 <= Q,
+ * Q = qmax (1 + 2^-8) (a superset of the tiles holding a pixel centre with
+ * q <= qmax, the alpha_min footprint of Eq. 3).  Each rectangle row's columns
+ * come from the x-extent of the ellipse over the row's band, in float32 with
+ * correctly rounded square roots and quotients, so decisions within float32
+ * rounding of the rule's boundary may go either way.  The pairs are radix-sorted by (view, depth); the lists
  * are then built in two stable bucketing levels (pairs into tile rows, row
  * entries into the tiles of their columns) without sorting instances.
  * Instance slots (inst_base, the backward's partials) keep the rectangle
@@ -210,6 +212,25 @@ gesr_status gesr_project(gesr_ctx* ctx, const gesr_splats* splats, const gesr_ca
  * M only with GESR_BIN_SYNC. */
 gesr_status gesr_bin(gesr_ctx* ctx, const gesr_proj* proj, const gesr_camera* cams, int V, int n,
                      const gesr_settings* st, const gesr_bins* bins, int flags, uint64_t* m_out, void* stream);
+
+/* gesr_bin for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * binning, bit for bit, with its scratch taken from a static device array of
+ * GESR_BIN_STATIC_SCRATCH_BYTES held by each GPU the library runs on until the
+ * process ends, instead of bins->scratch (ignored, may be NULL).  The caller
+ * still passes every input and output (proj, the sorted lists, ranges,
+ * worklist, inst_base, counters).  Allocates nothing (no hipMalloc, hipFree or
+ * allocating library call); the first call on a device looks the array's
+ * address up once.  GESR_ERR_CAPACITY when this binning needs more scratch
+ * than the array holds (the message gives both sizes; gesr_query_sizes'
+ * bin_scratch_bytes is the need), with nothing enqueued.  Every call on one
+ * GPU shares its array and the array keeps the last call's contents (the
+ * binning clears what it reads before writing it): calls that overlap on one
+ * GPU -- on different streams, or from different host threads -- race. */
+#define GESR_BIN_STATIC_SCRATCH_BYTES (64u << 20)
+gesr_status gesr_bin_static(gesr_ctx* ctx, const gesr_proj* proj, const gesr_camera* cams, int V, int n,
+                            const gesr_settings* st, const gesr_bins* bins, int flags, uint64_t* m_out,
+                            void* stream);
 
 /* Optional per-pixel counters of gesr_render_fwd: fragments evaluated up to
  * termination (listed) and those with alpha >= alpha_min (hit). */

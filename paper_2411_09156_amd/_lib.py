@@ -17,6 +17,7 @@ GESR_ERR_CAPACITY = 2
 GESR_ERR_HIP = 3
 GESR_ERR_UNSUPPORTED = 4
 GESR_BIN_SYNC = 1
+BIN_STATIC_SCRATCH_BYTES = 64 << 20
 MAX_VIEWS = 32
 REC_FLOATS = 12
 PARTIAL_FLOATS = 10
@@ -24,7 +25,7 @@ GRAD2D_FLOATS = 12  # du dv dL00 dL10 dL11 dop dbeta dr dg db dz + zero pad
 
 EXPORTS = (
     "gesr_ctx_create", "gesr_ctx_destroy", "gesr_last_error", "gesr_status_string", "gesr_default_settings",
-    "gesr_query_sizes", "gesr_project", "gesr_bin", "gesr_render_fwd", "gesr_render_bwd", "gesr_render_bwd_tiles",
+    "gesr_query_sizes", "gesr_project", "gesr_bin", "gesr_bin_static", "gesr_render_fwd", "gesr_render_bwd", "gesr_render_bwd_tiles",
     "gesr_render_fwd_ext", "gesr_render_bwd_ext", "gesr_render_bwd_tiles_ext", "gesr_surface_points",
     "gesr_project_bwd", "gesr_l1_grad", "gesr_autotune", "gesr_autotune_candidate", "gesr_default_adam_settings",
     "gesr_adam_step", "gesr_prune_workspace_size", "gesr_prune", "gesr_shape_reset", "gesr_knn_workspace_size",
@@ -155,6 +156,8 @@ def load():
     lib.gesr_bin.argtypes = [vp, P(Proj), P(Camera), ctypes.c_int, ctypes.c_int, P(Settings), P(Bins),
                              ctypes.c_int, P(ctypes.c_uint64), vp]
     lib.gesr_bin.restype = st
+    lib.gesr_bin_static.argtypes = lib.gesr_bin.argtypes
+    lib.gesr_bin_static.restype = st
     lib.gesr_render_fwd.argtypes = [vp, P(Proj), P(Bins), P(Camera), ctypes.c_int, ctypes.c_int, P(Settings),
                                     vp, vp, vp, P(FwdCounts), vp]
     lib.gesr_render_fwd.restype = st

@@ -8,6 +8,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 
 #include "gesr.h"
@@ -390,20 +391,21 @@ gesr_status gesr_project(gesr_ctx* ctx, const gesr_splats* splats, const gesr_ca
     return GESR_OK;
 }
 
-gesr_status gesr_bin(gesr_ctx* ctx, const gesr_proj* proj, const gesr_camera* cams, int V, int n,
-                     const gesr_settings* st, const gesr_bins* bins, int flags, uint64_t* m_out, void* stream) {
-    if (!ctx) return GESR_ERR_INVALID;
-    GESR_TRY(check_settings(ctx, st));
-    Geometry g;
-    GESR_TRY(check_cams(ctx, cams, V, n, st, &g));
-    GESR_TRY(check_proj(ctx, proj));
-    GESR_TRY(check_bins(ctx, bins, true));
+}  // extern "C"
+
+namespace {
+
+// The binning pipeline of gesr_bin on a scratch buffer of `scratch_bytes` at
+// `scratch` (checked against the layout's size).  Arguments are validated by
+// the caller (g from check_cams); the device is current.
+gesr_status bin_impl(gesr_ctx* ctx, const gesr_proj* proj, const gesr_camera* cams, int V, int n,
+                     const gesr_settings* st, const gesr_bins* bins, const Geometry& g, void* scratch,
+                     size_t scratch_bytes, int flags, uint64_t* m_out, void* stream) {
     const DevCams dc = dev_cams(cams, V, st);
-    BinScratch s = carve(bins->scratch, g, dc, n, bins->m_cap);
-    if (bins->scratch_bytes < s.bytes)
-        return fail(ctx, GESR_ERR_INVALID, "bins->scratch_bytes %zu < required %zu", bins->scratch_bytes, s.bytes);
+    BinScratch s = carve(scratch, g, dc, n, bins->m_cap);
+    if (scratch_bytes < s.bytes)
+        return fail(ctx, GESR_ERR_INVALID, "bins->scratch_bytes %zu < required %zu", scratch_bytes, s.bytes);
     hipStream_t strm = (hipStream_t)stream;
-    GESR_TRY(hip_check(ctx, hipSetDevice(ctx->device), "hipSetDevice"));
     const uint64_t T = g.total_tiles;
 
     // 1. depth order of the (view, splat) pairs: LSD passes over the 32 depth bits
@@ -496,6 +498,71 @@ gesr_status gesr_bin(gesr_ctx* ctx, const gesr_proj* proj, const gesr_camera* ca
     GESR_TRY(hip_check(ctx, radix_sort(s.w_keys_b, nullptr, T, nullptr, 16, 8, wb, &in_b, strm), "worklist sort"));
     ctx->err.clear();
     return GESR_OK;
+}
+
+}  // namespace
+
+// Scratch of gesr_bin_static: one array per GPU, held until the process ends.
+// Host code uses its device address from hipGetSymbolAddress (static_scratch),
+// never the array's name.
+static __device__ __align__(256) unsigned char scratch[GESR_BIN_STATIC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_address[kMaxDevices] = {};
+
+// Device address of `scratch` on ctx's device (current), looked up once per device.
+gesr_status static_scratch(gesr_ctx* ctx, void** out) {
+    if (ctx->device < 0 || ctx->device >= kMaxDevices)
+        return fail(ctx, GESR_ERR_UNSUPPORTED, "device %d: the static scratch serves devices 0..%d", ctx->device,
+                    kMaxDevices - 1);
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_address[ctx->device]) {
+        void* p = nullptr;
+        GESR_TRY(hip_check(ctx, hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)"));
+        if (!p) return fail(ctx, GESR_ERR_HIP, "hipGetSymbolAddress(scratch) returned NULL");
+        g_scratch_address[ctx->device] = p;
+    }
+    *out = g_scratch_address[ctx->device];
+    return GESR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+gesr_status gesr_bin(gesr_ctx* ctx, const gesr_proj* proj, const gesr_camera* cams, int V, int n,
+                     const gesr_settings* st, const gesr_bins* bins, int flags, uint64_t* m_out, void* stream) {
+    if (!ctx) return GESR_ERR_INVALID;
+    GESR_TRY(check_settings(ctx, st));
+    Geometry g;
+    GESR_TRY(check_cams(ctx, cams, V, n, st, &g));
+    GESR_TRY(check_proj(ctx, proj));
+    GESR_TRY(check_bins(ctx, bins, true));
+    GESR_TRY(hip_check(ctx, hipSetDevice(ctx->device), "hipSetDevice"));
+    return bin_impl(ctx, proj, cams, V, n, st, bins, g, bins->scratch, bins->scratch_bytes, flags, m_out, stream);
+}
+
+gesr_status gesr_bin_static(gesr_ctx* ctx, const gesr_proj* proj, const gesr_camera* cams, int V, int n,
+                            const gesr_settings* st, const gesr_bins* bins, int flags, uint64_t* m_out,
+                            void* stream) {
+    if (!ctx) return GESR_ERR_INVALID;
+    GESR_TRY(check_settings(ctx, st));
+    Geometry g;
+    GESR_TRY(check_cams(ctx, cams, V, n, st, &g));
+    GESR_TRY(check_proj(ctx, proj));
+    GESR_TRY(check_bins(ctx, bins, false));
+    const size_t need = carve(nullptr, g, dev_cams(cams, V, st), n, bins->m_cap).bytes;
+    if (need > (size_t)GESR_BIN_STATIC_SCRATCH_BYTES)
+        return fail(ctx, GESR_ERR_CAPACITY, "gesr_bin_static: this binning needs %zu bytes of scratch; the static "
+                    "scratch holds %zu", need, (size_t)GESR_BIN_STATIC_SCRATCH_BYTES);
+    GESR_TRY(hip_check(ctx, hipSetDevice(ctx->device), "hipSetDevice"));
+    void* base = nullptr;
+    GESR_TRY(static_scratch(ctx, &base));
+    return bin_impl(ctx, proj, cams, V, n, st, bins, g, base, (size_t)GESR_BIN_STATIC_SCRATCH_BYTES, flags,
+                    m_out, stream);
 }
 
 // The extended channels run only in the one-wave 16x16 renderers.

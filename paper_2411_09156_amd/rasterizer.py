@@ -169,15 +169,15 @@ class Rasterizer:
         c.rect, c.depth_key = p["rect"].data_ptr(), p["depth_key"].data_ptr()
         return c
 
-    def alloc_bins(self, n: int, m_cap: int) -> dict:
+    def alloc_bins(self, n: int, m_cap: int, scratch: bool = True) -> dict:
         sz = self.sizes(n, m_cap)
         T = int(sz.total_tiles)
         return dict(m_cap=int(m_cap), tile_sorted=self._empty(m_cap, torch.int32) if self.store_tile_ids else None,
                     val_sorted=self._empty(m_cap, torch.int32), ranges=self._empty(2 * T, torch.int32),
                     worklist=self._empty(T, torch.int32), inst_base=self._empty(self.V * n, torch.int32),
                     counters=self._empty(4, torch.int32),
-                    scratch=torch.empty(int(sz.bin_scratch_bytes), dtype=torch.uint8, device=self.device),
-                    total_tiles=T)
+                    scratch=torch.empty(int(sz.bin_scratch_bytes), dtype=torch.uint8, device=self.device)
+                    if scratch else None, scratch_bytes=int(sz.bin_scratch_bytes), total_tiles=T)
 
     @staticmethod
     def _bins_c(b) -> _lib.Bins:
@@ -185,22 +185,25 @@ class Rasterizer:
         c.m_cap = b["m_cap"]
         for k in ("tile_sorted", "val_sorted", "ranges", "worklist", "inst_base", "counters", "scratch"):
             setattr(c, k, b[k].data_ptr() if b[k] is not None else 0)
-        c.scratch_bytes = b["scratch"].numel()
+        c.scratch_bytes = b["scratch"].numel() if b["scratch"] is not None else 0
         return c
 
-    def bin(self, proj: dict, n: int, m_cap: Optional[int] = None, sync: bool = True) -> dict:
+    def bin(self, proj: dict, n: int, m_cap: Optional[int] = None, sync: bool = True,
+            static_scratch: bool = False) -> dict:
         """Bins the projected splats.  With sync (eager) the instance count is read
         back and the buffers regrown if needed; without it the call never
-        synchronises and lists beyond m_cap are truncated (counters[1] set)."""
+        synchronises and lists beyond m_cap are truncated (counters[1] set).
+        static_scratch calls gesr_bin_static (the library's per-GPU static
+        scratch instead of a scratch buffer; no scratch is allocated)."""
         if m_cap is None:
             m_cap = self.m_cap_hint or max(4 * self.V * n, 1024)
+        fn = self.lib.gesr_bin_static if static_scratch else self.lib.gesr_bin
         while True:
-            b = self.alloc_bins(n, m_cap)
+            b = self.alloc_bins(n, m_cap, scratch=not static_scratch)
             m = ctypes.c_uint64(0)
-            st = self.lib.gesr_bin(self.ctx, ctypes.byref(self._proj_c(proj)), self.cams_c, self.V, n,
-                                   ctypes.byref(self.st_c), ctypes.byref(self._bins_c(b)),
-                                   _lib.GESR_BIN_SYNC if sync else 0, ctypes.byref(m), _stream())
-            if st == _lib.GESR_ERR_CAPACITY and sync:
+            st = fn(self.ctx, ctypes.byref(self._proj_c(proj)), self.cams_c, self.V, n, ctypes.byref(self.st_c),
+                    ctypes.byref(self._bins_c(b)), _lib.GESR_BIN_SYNC if sync else 0, ctypes.byref(m), _stream())
+            if st == _lib.GESR_ERR_CAPACITY and sync and m.value > m_cap:
                 m_cap = int(m.value * 1.05) + 1024
                 continue
             self._check(st, self.ctx)
