@@ -541,6 +541,93 @@ def shape_reset(raw: dict, m: dict, v: dict, value: float):
     return tuple(out)
 
 
+# ------------------------------------------------------- photometric loss (Eq. 8)
+@dataclass
+class LossSettings:
+    """Eq. 8: L = (1 - lambda) L1 + lambda L_SSIM with L_SSIM = 1 - SSIM (Sec. 3.2;
+    lambda = 0.2).  SSIM's window and constants are not given in the paper;
+    the reading is the usual one: an 11 x 11 Gaussian window of standard
+    deviation 1.5, C1 = 0.01^2, C2 = 0.03^2 (images in [0, 1]), zero padding,
+    the map averaged over channels and pixels."""
+    lam: float = 0.2
+    c1: float = 0.01 ** 2
+    c2: float = 0.03 ** 2
+    sigma: float = 1.5
+    radius: int = 5
+
+
+def gaussian_window(radius: int, sigma: float) -> np.ndarray:
+    """Normalised 1-D Gaussian weights at offsets -radius..radius."""
+    x = np.arange(-radius, radius + 1, dtype=np.float64)
+    g = np.exp(-x * x / (2.0 * sigma * sigma))
+    return g / g.sum()
+
+
+def window_sum(a, g1) -> np.ndarray:
+    """sum_{i,j} g1[i] g1[j] a[y + i - r, x + j - r] over the window, with
+    zero outside the image (r = radius); the window is symmetric, so this is
+    also its own adjoint."""
+    a = np.asarray(a, np.float64)
+    r = (len(g1) - 1) // 2
+    H, W = a.shape
+    p = np.zeros((H + 2 * r, W + 2 * r))
+    p[r:r + H, r:r + W] = a
+    out = np.zeros((H, W))
+    for i in range(2 * r + 1):
+        for j in range(2 * r + 1):
+            out += (g1[i] * g1[j]) * p[i:i + H, j:j + W]
+    return out
+
+
+def ssim_terms(X, Y, ls: LossSettings):
+    """Per-pixel SSIM map of two single-channel images and its partial
+    derivatives with respect to the window moments mu_x = G*X, m2x = G*X^2,
+    mxy = G*(X Y): S = (2 mu_x mu_y + C1)(2 s_xy + C2) / ((mu_x^2 + mu_y^2 + C1)
+    (s_x^2 + s_y^2 + C2)) with s_x^2 = m2x - mu_x^2, s_xy = mxy - mu_x mu_y."""
+    g1 = gaussian_window(ls.radius, ls.sigma)
+    X = np.asarray(X, np.float64)
+    Y = np.asarray(Y, np.float64)
+    mx, my = window_sum(X, g1), window_sum(Y, g1)
+    sxx = window_sum(X * X, g1) - mx * mx
+    syy = window_sum(Y * Y, g1) - my * my
+    sxy = window_sum(X * Y, g1) - mx * my
+    N1, N2 = 2 * mx * my + ls.c1, 2 * sxy + ls.c2
+    D1, D2 = mx * mx + my * my + ls.c1, sxx + syy + ls.c2
+    S = N1 * N2 / (D1 * D2)
+    # dS/dmu_x (through mu_x, s_x^2 and s_xy), dS/dm2x, dS/dmxy
+    d_m1 = 2 * my * N2 / (D1 * D2) - 2 * mx * S / D1 + 2 * mx * S / D2 - 2 * my * N1 / (D1 * D2)
+    d_m2 = -S / D2
+    d_mxy = 2 * N1 / (D1 * D2)
+    return S, d_m1, d_m2, d_mxy, g1
+
+
+def photometric_loss(image, target, cameras, ls: LossSettings = LossSettings()):
+    """Eq. 8 per view, images in the flat CHW-per-view layout: returns
+    (loss [V], dL/dimage) with L = sum_v L_v, L_v = (1 - lambda) mean|X - Y| +
+    lambda (1 - mean SSIM) over the view's 3 H W values (sign(0) = 0)."""
+    image = np.asarray(image, np.float64)
+    target = np.asarray(target, np.float64)
+    loss = np.zeros(len(cameras))
+    grad = np.zeros_like(image)
+    off = 0
+    for v, c in enumerate(cameras):
+        n = 3 * c.width * c.height
+        X = image[off:off + n].reshape(3, c.height, c.width)
+        Y = target[off:off + n].reshape(3, c.height, c.width)
+        G = np.zeros_like(X)
+        ssim_sum = 0.0
+        for ch in range(3):
+            S, a, b, cc, g1 = ssim_terms(X[ch], Y[ch], ls)
+            ssim_sum += S.sum()
+            # L_SSIM = 1 - mean S: the moments' adjoint, each a window sum
+            dS = window_sum(a, g1) + 2 * X[ch] * window_sum(b, g1) + Y[ch] * window_sum(cc, g1)
+            G[ch] = (1 - ls.lam) * np.sign(X[ch] - Y[ch]) / n - ls.lam * dS / n
+        loss[v] = (1 - ls.lam) * np.abs(X - Y).sum() / n + ls.lam * (1.0 - ssim_sum / n)
+        grad[off:off + n] = G.reshape(-1)
+        off += n
+    return loss, grad
+
+
 # ------------------------------------------------------------------ pipeline
 def forward(scene, st: Settings, channels: bool = False, band: bool = False, paths=None) -> dict:
     """Full FP64 pipeline: project -> bin -> tiled render (with the extended
