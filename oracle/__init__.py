@@ -628,6 +628,59 @@ def photometric_loss(image, target, cameras, ls: LossSettings = LossSettings()):
     return loss, grad
 
 
+# ------------------------------------------------ surface-alignment regulariser
+def rotation_columns(quats):
+    """Rotation matrices [N, 3, 3] of quaternions (w, x, y, z), normalised."""
+    q = np.asarray(quats, np.float64)
+    q = q / np.linalg.norm(q, axis=1, keepdims=True)
+    w, x, y, z = q.T
+    return np.stack([np.stack([1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)], 1),
+                     np.stack([2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)], 1),
+                     np.stack([2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)], 1)], 1)
+
+
+def surface_alignment(scales, quats, normals, w_scale: float = 0.1, w_normal: float = 0.1):
+    """Surface-alignment regulariser of the flattened-splat workload (the paper
+    flattens its splats toward the surface, Sec. 3.3, without giving this loss;
+    reading): L = w_scale mean_i min_k s_ik + w_normal mean_i (1 - <n_i, m_i>^2)
+    with n_i = R(q_i) e_k*, k* = the axis of the smallest scale (lowest index on
+    ties) and m_i the splat's true surface normal (sign-free).  Returns
+    (L_scale, L_normal, dict(scales, quats) of dL/d(scales, raw quats)), the
+    discrete choice k* held fixed."""
+    s = np.asarray(scales, np.float64)
+    q = np.asarray(quats, np.float64)
+    m = np.asarray(normals, np.float64)
+    N = s.shape[0]
+    k = np.argmin(s, axis=1)
+    idx = np.arange(N)
+    R = rotation_columns(q)
+    n = R[idx, :, k]
+    d = np.einsum("ij,ij->i", n, m)
+    L_s = w_scale * s[idx, k].sum() / max(N, 1)
+    L_n = w_normal * (1.0 - d * d).sum() / max(N, 1)
+    gs = np.zeros_like(s)
+    gs[idx, k] = w_scale / max(N, 1)
+    gn = (-2.0 * w_normal / max(N, 1)) * d[:, None] * m  # dL/dn
+    # column k of R as a function of the normalised quaternion (w, x, y, z)
+    qn = q / np.linalg.norm(q, axis=1, keepdims=True)
+    w, x, y, z = qn.T
+    zero = np.zeros(N)
+    J = np.empty((N, 3, 4))  # d column / d (w, x, y, z)
+    J0 = np.stack([np.stack([zero, zero, -4 * y, -4 * z], 1), np.stack([2 * z, 2 * y, 2 * x, 2 * w], 1),
+                   np.stack([-2 * y, 2 * z, -2 * w, 2 * x], 1)], 1)
+    J1 = np.stack([np.stack([-2 * z, 2 * y, 2 * x, -2 * w], 1), np.stack([zero, -4 * x, zero, -4 * z], 1),
+                   np.stack([2 * x, 2 * w, 2 * z, 2 * y], 1)], 1)
+    J2 = np.stack([np.stack([2 * y, 2 * z, 2 * w, 2 * x], 1), np.stack([-2 * x, -2 * w, 2 * z, 2 * y], 1),
+                   np.stack([zero, -4 * x, -4 * y, zero], 1)], 1)
+    for kk, Jk in enumerate((J0, J1, J2)):
+        J[k == kk] = Jk[k == kk]
+    g_qn = np.einsum("ij,ijk->ik", gn, J)
+    # through the normalisation q -> q / |q|
+    nq = np.linalg.norm(q, axis=1, keepdims=True)
+    g_q = (g_qn - np.einsum("ij,ij->i", g_qn, qn)[:, None] * qn) / nq
+    return L_s, L_n, dict(scales=gs, quats=g_q)
+
+
 # ------------------------------------------------------------------ pipeline
 def forward(scene, st: Settings, channels: bool = False, band: bool = False, paths=None) -> dict:
     """Full FP64 pipeline: project -> bin -> tiled render (with the extended
