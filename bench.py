@@ -56,8 +56,9 @@ SURFACE_SLOTS_PER_SAMPLE = 16
 # HBM bytes per launch of the tile adjoint on the default workload, from two
 # rocprofv3 counter passes (FETCH_SIZE x2.0, WRITE_SIZE x1.0 after calibration
 # against a 1 GiB copy; profiles/drt-500k-8views_hbm_counters.md).  Valid only
-# for the kernel source it was measured on (fingerprint below: the kernel and the
-# binning that builds the tile lists it walks); otherwise null.
+# for the kernel source it was measured on (fingerprint below: the kernel, the
+# projection and binning that build the records and tile lists it walks, and the
+# record layout); otherwise null.
 MEASURED_TRAFFIC = {"kernel": "render_bwd_tiles", "workload": "drt-batch-500k-8views",
                     "fingerprint": "bcb1c09c8efd434b", "bytes": 3031883827,
                     "settings": (16, 16, 0, 64)}  # tile_w, tile_h, variant, batch of the measured run
@@ -69,8 +70,10 @@ def kernel_fingerprint():
     import hashlib
     import re
     h = hashlib.sha256()
-    for f in ("gesr_render.hip", "gesr_device.h", "gesr_bin.hip"):
-        with open(os.path.join(ROOT, "paper_2411_09156_amd", "csrc", f)) as fh:
+    for f in ("paper_2411_09156_amd/csrc/gesr_render.hip", "paper_2411_09156_amd/csrc/gesr_device.h",
+              "paper_2411_09156_amd/csrc/gesr_bin.hip", "paper_2411_09156_amd/csrc/gesr_project.hip",
+              "paper_2411_09156_amd/csrc/gesr_kernels.h", "include/gesr.h"):
+        with open(os.path.join(ROOT, f)) as fh:
             t = re.sub(r"/\*.*?\*/", "", fh.read(), flags=re.S)
         t = re.sub(r"//[^\n]*", "", t)
         h.update("\n".join(line.rstrip() for line in t.split("\n") if line.strip()).encode())
@@ -102,6 +105,10 @@ def parse_args():
     p.add_argument("--channels", action="store_true",
                    help="extended rasterizer: depth and alpha maps in the forward and seeded synthetic upstream "
                         "gradients for them in the backward (16x16 one-wave renderer; implies --no-autotune)")
+    p.add_argument("--workloads", default="1,2,4,5",
+                   help="other configurations timed in the same run after the headline (comma list of 1..5; "
+                        "'' for none)")
+    p.add_argument("--workload-steps", type=int, default=10, help="timed steps of each other workload")
     p.add_argument("--calibrate-copy", type=int, default=0,
                    help="also run a plain device copy of this many MiB (hardware counter calibration)")
     return p.parse_args()
@@ -109,6 +116,219 @@ def parse_args():
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+def make_step_fn(scene):
+    """Step builder for the workload's loss: "l1" (mean |X - Y| over all
+    values), "l1+dssim" (Eq. 8 per view, lambda 0.2, the loss kernel) or
+    "l1+surface" (L1 plus the surface-alignment regulariser, weights 0.1,
+    whose gradient is added to the parameter gradients)."""
+    import numpy as np
+    import torch
+    normals = None
+    if scene.loss == "l1+surface":
+        normals = torch.as_tensor(np.ascontiguousarray(np.asarray(scene.normals, np.float32).T), device="cuda")
+    if scene.loss not in ("l1", "l1+dssim", "l1+surface"):
+        raise ValueError(f"unsupported loss {scene.loss!r}")
+
+    def make_step(rast, sp, target, m_cap, events=None, chan=None):
+        n = sp.n
+        scale = 1.0 / float(target.numel())
+        loss_ws = rast.alloc_loss_workspace() if scene.loss == "l1+dssim" else None
+
+        def rec(i):
+            if events is not None:
+                events[i].record()
+
+        def step():
+            rec(0)
+            proj = rast.project(sp)
+            rec(1)
+            bins = rast.bin(proj, n, m_cap=m_cap, sync=False)
+            rec(2)
+            f = rast.render_fwd(proj, bins, n, channels=chan is not None)
+            rec(3)
+            if scene.loss == "l1+dssim":
+                dL, _ = rast.loss_eq8(f["image"], target, 0.2, want_loss=False, workspace=loss_ws)
+            else:
+                dL = rast.l1_grad(f["image"], target, scale)
+            rec(4)
+            ws = rast.render_bwd_tiles(proj, bins, n, f["final_T"], f["n_contrib"], dL,
+                                       dL_ddepth=None if chan is None else chan[0],
+                                       dL_dalpha=None if chan is None else chan[1])
+            rec(5)
+            g = rast.project_bwd(sp, proj, bins, ws)
+            if normals is not None:
+                rast.surface_align(sp, normals, g, 0.1, 0.1, want_losses=False)
+            rec(6)
+            return f, g, bins
+        return step
+    return make_step
+
+
+def time_step(step, steps, warmup, graph=True):
+    """ms per step of `step` (captured in a HIP graph and replayed unless
+    graph=False), HIP events on the launch stream around `steps` replays after
+    `warmup`; returns (ms, wall seconds of the timed loop, the captured
+    outputs or None)."""
+    import torch
+    for _ in range(max(warmup, 1)):
+        step()
+    torch.cuda.synchronize()
+    res = None
+    run = step
+    if graph:
+        g = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            step()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g):
+            res = step()
+        run = g.replay
+    for _ in range(warmup):
+        run()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(steps):
+        run()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps, time.perf_counter() - t0, res
+
+
+def stage_times(make_step, rast, sp, target, m_cap, chan, steps, names):
+    """Per-stage milliseconds (eager, HIP events between the stages on the
+    launch stream) and their sum."""
+    import numpy as np
+    import torch
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(7)]
+    tstep = make_step(rast, sp, target, m_cap, evs, chan=chan)
+    tstep()
+    torch.cuda.synchronize()
+    acc = np.zeros(6)
+    for _ in range(steps):
+        tstep()
+        torch.cuda.synchronize()
+        acc += [evs[i].elapsed_time(evs[i + 1]) for i in range(6)]
+    return dict(zip(names, (acc / steps).round(4).tolist())), float(acc.sum() / steps)
+
+
+def per_view_times(scene, rs, sp, target, chan, make_step, steps, warmup, graph=True):
+    """The same pipeline view by view (V sequential one-view pipelines, the
+    parameter gradients summed), eager and captured in one graph."""
+    import torch
+    from paper_2411_09156_amd import Rasterizer
+    rasts, vsteps = [], []
+    off = offp = 0
+    P = scene.n_pixels
+    for cam in scene.cameras:
+        r = Rasterizer([cam], rs, store_tile_ids=False)
+        npx = 3 * cam.width * cam.height
+        tv = target[off:off + npx]
+        cv = None if chan is None else tuple(c[offp:offp + npx // 3] for c in chan)
+        off += npx
+        offp += npx // 3
+        fv = r.forward(sp, sync=True)
+        mv = int(fv["bins"]["M"])
+        del fv
+        rasts.append(r)
+        vsteps.append(make_step(r, sp, tv, mv, chan=cv))
+
+    def per_view_step():
+        total = None
+        for st_ in vsteps:
+            f, g, _ = st_()
+            if total is None:
+                total = {k2: v2.clone() for k2, v2 in g.items()}
+            else:
+                for k2 in total:
+                    total[k2].add_(g[k2])
+        return total
+    pv_ms, _, _ = time_step(per_view_step, steps, warmup, graph=False)
+    pv_graph_ms = time_step(per_view_step, steps, warmup, graph=True)[0] if graph else None
+    del rasts, vsteps
+    return {"eager_ms_per_step": round(pv_ms, 4), "eager_mpix_s": round(P / (pv_ms * 1e-3) / 1e6, 2),
+            "graph_ms_per_step": None if pv_graph_ms is None else round(pv_graph_ms, 4),
+            "graph_mpix_s": None if pv_graph_ms is None else round(P / (pv_graph_ms * 1e-3) / 1e6, 2)}
+
+
+def workload_leg(k, args, rs):
+    """Workload k (one of the other configurations) timed in this same run:
+    batched fwd+bwd in a graph vs the per-view pipelines, its own autotuned
+    settings (the headline's with --no-autotune), its own loss; the peak
+    device memory of its sizing run and batched step above what was allocated
+    before (torch's allocator: splats, targets, lists, workspaces, outputs)
+    and the sizes of the binning and backward buffers."""
+    import numpy as np
+    import torch
+
+    import gesr_inputs as gi
+    from paper_2411_09156_amd import Rasterizer, RasterSettings, Splats
+    log(f"[bench] workload {k}: building")
+    scene = gi.make_workload(k)
+    N, V, P = scene.n, scene.n_views, scene.n_pixels
+    rsk = RasterSettings(sh_degree=scene.sh_degree, tile_w=rs.tile_w, tile_h=rs.tile_h, batch=rs.batch,
+                         radix_bits=rs.radix_bits, variant=rs.variant)
+    sp = Splats.from_aos(scene.means, scene.scales, scene.quats, scene.opacities, scene.betas, scene.sh)
+    target = torch.as_tensor(np.concatenate([t.reshape(-1) for t in gi.target_images(scene, k)]), device="cuda")
+    rast = Rasterizer(scene.cameras, rsk, store_tile_ids=False)
+    tune = None
+    if not args.no_autotune:
+        tune = rast.autotune(sp, reps=2)
+        rsk = rast.settings
+        log(f"[bench] workload {k}: autotune chose tile {tune['tile']} variant {tune['variant']} batch "
+            f"{tune['batch']} radix {tune['radix_bits']}")
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    torch.cuda.reset_peak_memory_stats()
+    mem0 = torch.cuda.memory_allocated()
+    first = rast.forward(sp, sync=True, counts=True)
+    M = int(first["bins"]["M"])
+    listed_inst = int(first["bins"]["counters"][3].item())
+    n_listed = int(first["n_listed"].to(torch.int64).sum().item())
+    n_hit = int(first["n_hit"].to(torch.int64).sum().item())
+    del first
+    make_step = make_step_fn(scene)
+    step = make_step(rast, sp, target, M)
+    ms, _, res = time_step(step, args.workload_steps, args.warmup, graph=not args.no_graph)
+    if res is not None:
+        assert res[2]["counters"].cpu().numpy().view(np.uint32)[1] == 0, "instance capacity overflowed"
+    torch.cuda.synchronize()
+    peak = torch.cuda.max_memory_allocated() - mem0
+    sz = rast.sizes(N, M)
+    T = int(sz.total_tiles)
+    names = ["project", "bin", "render_fwd", "loss_grad", "render_bwd_tiles", "seg_reduce+project_bwd"]
+    stage_ms, _ = stage_times(make_step, rast, sp, target, M, None, max(args.workload_steps // 2, 2), names)
+    del res, step
+    pv = per_view_times(scene, rsk, sp, target, None, make_step, args.workload_steps, args.warmup,
+                        graph=not args.no_graph)
+    value = P / (ms * 1e-3) / 1e6
+    log(f"[bench] workload {k} ({scene.name}): {ms:.3f} ms per step, {value:.1f} Mpix/s; per view "
+        f"{pv['eager_ms_per_step']:.3f} ms eager, {pv['graph_ms_per_step']} ms graph")
+    out = {"workload": scene.name, "splats": N, "views": V, "pixels": P, "sh_degree": scene.sh_degree,
+           "loss": scene.loss, "value": round(value, 2), "unit": "Mpix/s", "ms_per_step": round(ms, 4),
+           "steps": args.workload_steps, "instances": M, "listed_instances": listed_inst,
+           "fragments": {"listed": n_listed, "hit": n_hit, "listed_per_s": round(n_listed / (ms * 1e-3), 1),
+                         "hit_per_s": round(n_hit / (ms * 1e-3), 1)},
+           "stages_ms": stage_ms, "per_view": pv,
+           "batched_speedup_vs_eager": round(pv["eager_ms_per_step"] / ms, 3),
+           "batched_speedup_vs_graph": None if pv["graph_ms_per_step"] is None
+           else round(pv["graph_ms_per_step"] / ms, 3),
+           "settings": {"tile": f"{rsk.tile_w}x{rsk.tile_h}", "variant": rsk.variant, "batch": rsk.batch or 64,
+                        "radix_bits": rsk.radix_bits, "autotuned": tune is not None},
+           "memory": {"peak_step_bytes": int(peak), "bin_scratch_bytes": int(sz.bin_scratch_bytes),
+                      "sorted_list_bytes": 4 * M, "ranges_worklist_bytes": 12 * T,
+                      "bwd_workspace_bytes": int(sz.bwd_workspace_bytes),
+                      "projection_bytes": V * N * (12 + 4) * 4}}
+    del rast, sp, target
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -145,32 +365,7 @@ def main():
             log("[bench] --channels: the extended channels run in the 16x16 one-wave renderer; autotuning is skipped")
             args.no_autotune = True
 
-    def make_step(rast, sp, target, m_cap, events=None, chan=None):
-        n = sp.n
-        scale = 1.0 / float(target.numel())
-
-        def rec(i):
-            if events is not None:
-                events[i].record()
-
-        def step():
-            rec(0)
-            proj = rast.project(sp)
-            rec(1)
-            bins = rast.bin(proj, n, m_cap=m_cap, sync=False)
-            rec(2)
-            f = rast.render_fwd(proj, bins, n, channels=chan is not None)
-            rec(3)
-            dL = rast.l1_grad(f["image"], target, scale)
-            rec(4)
-            ws = rast.render_bwd_tiles(proj, bins, n, f["final_T"], f["n_contrib"], dL,
-                                       dL_ddepth=None if chan is None else chan[0],
-                                       dL_dalpha=None if chan is None else chan[1])
-            rec(5)
-            g = rast.project_bwd(sp, proj, bins, ws)
-            rec(6)
-            return f, g, bins
-        return step
+    make_step = make_step_fn(scene)
 
     if args.calibrate_copy > 0:
         # plain device-to-device copy of known size, for scaling HBM byte counters
@@ -204,118 +399,26 @@ def main():
 
     # ---------------------------------------------------- batched, graph
     step = make_step(rast, sp, target, m_cap, chan=chan)
-    for _ in range(max(args.warmup, 1)):
-        step()
-    torch.cuda.synchronize()
-    if not args.no_graph:
-        graph = torch.cuda.CUDAGraph()
-        side = torch.cuda.Stream()
-        side.wait_stream(torch.cuda.current_stream())
-        with torch.cuda.stream(side):
-            step()
-        torch.cuda.current_stream().wait_stream(side)
-        torch.cuda.synchronize()
-        with torch.cuda.graph(graph):
-            res = step()
-        run = graph.replay
-    else:
-        res = None
-        run = step
-    for _ in range(args.warmup):
-        run()
-    torch.cuda.synchronize()
-    log(f"[bench] timing {args.steps} batched steps")
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    e0.record()
-    for _ in range(args.steps):
-        run()
-    e1.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms = e0.elapsed_time(e1) / args.steps
+    ms, wall, res = time_step(step, args.steps, args.warmup, graph=not args.no_graph)
     if res is not None:
         cnt = res[2]["counters"].cpu().numpy().view(np.uint32)
         assert cnt[1] == 0, "instance capacity overflowed inside the graph"
     value = P / (ms * 1e-3) / 1e6
+    log(f"[bench] batched: {ms:.4f} ms per step, {value:.1f} Mpix/s")
 
     # ------------------------------------- per-stage times (eager, events)
-    names = ["project", "bin", "render_fwd", "l1_grad", "render_bwd_tiles", "seg_reduce+project_bwd"]
-    evs = [torch.cuda.Event(enable_timing=True) for _ in range(7)]
-    tstep = make_step(rast, sp, target, m_cap, evs, chan=chan)
-    tstep()
-    torch.cuda.synchronize()
-    acc = np.zeros(6)
-    for _ in range(args.steps):
-        tstep()
-        torch.cuda.synchronize()
-        acc += [evs[i].elapsed_time(evs[i + 1]) for i in range(6)]
-    stage_ms = dict(zip(names, (acc / args.steps).round(4).tolist()))
-    eager_ms = float(acc.sum() / args.steps)
+    names = ["project", "bin", "render_fwd", "loss_grad", "render_bwd_tiles", "seg_reduce+project_bwd"]
+    stage_ms, eager_ms = stage_times(make_step, rast, sp, target, m_cap, chan, args.steps, names)
 
     # -------------------------------------------------- per-view baseline
     per_view = None
     if not args.no_per_view:
         log("[bench] per-view pipelines")
-        rasts, steps = [], []
-        off = offp = 0
-        for v, cam in enumerate(scene.cameras):
-            r = Rasterizer([cam], rs, store_tile_ids=False)
-            npx = 3 * cam.width * cam.height
-            tv = target[off:off + npx]
-            cv = None if chan is None else tuple(c[offp:offp + npx // 3] for c in chan)
-            off += npx
-            offp += npx // 3
-            fv = r.forward(sp, sync=True)
-            mv = int(fv["bins"]["M"])
-            del fv
-            rasts.append(r)
-            steps.append(make_step(r, sp, tv, mv, chan=cv))
-
-        def per_view_step():
-            total = None
-            for s in steps:
-                f, g, _ = s()
-                if total is None:
-                    total = {k2: v2.clone() for k2, v2 in g.items()}
-                else:
-                    for k2 in total:
-                        total[k2].add_(g[k2])
-            return total
-        for _ in range(args.warmup):
-            per_view_step()
-        torch.cuda.synchronize()
-        e0.record()
-        for _ in range(args.steps):
-            per_view_step()
-        e1.record()
-        torch.cuda.synchronize()
-        pv_ms = e0.elapsed_time(e1) / args.steps
-        pv_graph_ms = None
-        if not args.no_graph:
-            g2 = torch.cuda.CUDAGraph()
-            side = torch.cuda.Stream()
-            side.wait_stream(torch.cuda.current_stream())
-            with torch.cuda.stream(side):
-                per_view_step()
-            torch.cuda.current_stream().wait_stream(side)
-            torch.cuda.synchronize()
-            with torch.cuda.graph(g2):
-                per_view_step()
-            for _ in range(args.warmup):
-                g2.replay()
-            torch.cuda.synchronize()
-            e0.record()
-            for _ in range(args.steps):
-                g2.replay()
-            e1.record()
-            torch.cuda.synchronize()
-            pv_graph_ms = e0.elapsed_time(e1) / args.steps
-        per_view = {"eager_ms_per_step": round(pv_ms, 4), "eager_mpix_s": round(P / (pv_ms * 1e-3) / 1e6, 2),
-                    "graph_ms_per_step": None if pv_graph_ms is None else round(pv_graph_ms, 4),
-                    "graph_mpix_s": None if pv_graph_ms is None else round(P / (pv_graph_ms * 1e-3) / 1e6, 2),
-                    "batched_speedup_vs_eager": round(pv_ms / ms, 3),
-                    "batched_speedup_vs_graph": None if pv_graph_ms is None else round(pv_graph_ms / ms, 3)}
+        per_view = per_view_times(scene, rs, sp, target, chan, make_step, args.steps, args.warmup,
+                                  graph=not args.no_graph)
+        per_view["batched_speedup_vs_eager"] = round(per_view["eager_ms_per_step"] / ms, 3)
+        if per_view["graph_ms_per_step"] is not None:
+            per_view["batched_speedup_vs_graph"] = round(per_view["graph_ms_per_step"] / ms, 3)
 
     # ------------------------------------------------------------ roofline
     fwd_hit, bwd_hit = (FWD_HIT_CHANNELS, BWD_HIT_CHANNELS) if args.channels else (FWD_HIT, BWD_HIT)
@@ -357,6 +460,7 @@ def main():
             tile = tbase[vv] + (loc // widths[vv]) // rs.tile_h * tx_n[vv] + (loc % widths[vv]) // rs.tile_w
             pick = pick[np.argsort(tile, kind="stable")]
             pix_t = torch.as_tensor(pick.astype(np.int32), device="cuda")
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             run_s = lambda: rast.surface_points(sp, fx["proj"], fx["bins"], fx["depth"], fx["alpha"], pix_t,  # noqa
                                                 n_samples=K_S)
             sres = run_s()
@@ -397,6 +501,18 @@ def main():
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(scene, k, [int(x) for x in args.cpu_sample_views.split(",")], rs, args.channels)
 
+    # --------------------------------------- the other workloads, same run
+    others = {}
+    wl = [int(x) for x in args.workloads.split(",") if x.strip()]
+    if wl:
+        del rast, sp, target, res, step
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        for kk in wl:
+            if kk == k:
+                continue
+            others[f"cfg{kk}"] = workload_leg(kk, args, rs)
+
     out = {
         "metric": METRIC, "value": round(value, 2), "unit": "Mpix/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
@@ -419,6 +535,8 @@ def main():
         out["train"] = train
     if gsr_out is not None:
         out["gsr"] = gsr_out
+    if others:
+        out["workloads"] = others
     print(json.dumps(out), flush=True)
 
 
@@ -553,37 +671,71 @@ def gsr_leg(args, scene, sp, rs):
                          "traffic": None, "algorithmic_bytes_per_launch": per_splat * n}}
 
 
+def cpu_info():
+    """Host CPU model (as lscpu reports it, from /proc/cpuinfo), logical CPUs and
+    the threads this process may run on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"cpu_model": model, "logical_cpus": os.cpu_count(), "usable_threads": usable}
+
+
 def cpu_baseline(scene, k, views, rs, channels=False):
     """The FP64 oracle (as it stands) on the same workload restricted to a
     subset of its views: project, bin, render, L1 gradient, backward (with the
     depth and alpha channels and seeded upstream gradients for them when
-    `channels`)."""
+    `channels`); and the same on the first of those views with one thread."""
     import copy
 
     import numpy as np
 
     import gesr_inputs as gi
     import oracle
-    sub = copy.copy(scene)
-    sub.cameras = [scene.cameras[v] for v in views]
     st = oracle.Settings(sh_degree=scene.sh_degree, tile_w=rs.tile_w, tile_h=rs.tile_h)
     targets = gi.target_images(scene, k)
-    tgt = oracle.flat_images([targets[v] for v in views])
-    log(f"[bench] cpu baseline: oracle on views {views} ({sub.n_pixels} px) with {oracle.num_threads()} threads")
-    t0 = time.perf_counter()
-    fo = oracle.forward(sub, st, channels=channels)
-    dL = np.sign(fo["image"] - tgt) / tgt.size
-    if channels:
-        rng = np.random.default_rng([k, 78])
-        oracle.backward(sub, st, fo, dL, dL_ddepth=rng.standard_normal(sub.n_pixels) / (3 * sub.n_pixels),
-                        dL_dalpha=rng.standard_normal(sub.n_pixels) / (3 * sub.n_pixels))
-    else:
-        oracle.backward(sub, st, fo, dL)
-    dt = time.perf_counter() - t0
-    return {"value": round(sub.n_pixels / dt / 1e6, 4), "unit": "Mpix/s", "cores": oracle.num_threads(),
-            "kind": "oracle", "seconds": round(dt, 2),
-            "sample": f"views {views} of the workload ({sub.n_pixels} px, all {scene.n} splats), FP64 fwd+bwd"
-                      + (" with the depth and alpha channels" if channels else "")}
+
+    def run(vs):
+        sub = copy.copy(scene)
+        sub.cameras = [scene.cameras[v] for v in vs]
+        tgt = oracle.flat_images([targets[v] for v in vs])
+        t0 = time.perf_counter()
+        fo = oracle.forward(sub, st, channels=channels)
+        dL = np.sign(fo["image"] - tgt) / tgt.size
+        if channels:
+            rng = np.random.default_rng([k, 78])
+            oracle.backward(sub, st, fo, dL, dL_ddepth=rng.standard_normal(sub.n_pixels) / (3 * sub.n_pixels),
+                            dL_dalpha=rng.standard_normal(sub.n_pixels) / (3 * sub.n_pixels))
+        else:
+            oracle.backward(sub, st, fo, dL)
+        return sub.n_pixels, time.perf_counter() - t0
+
+    threads = oracle.num_threads()
+    log(f"[bench] cpu baseline: oracle on views {views} with {threads} threads")
+    px, dt = run(views)
+    oracle.set_threads(1)
+    try:
+        log(f"[bench] cpu baseline: oracle on view {views[0]} with one thread")
+        px1, dt1 = run(views[:1])
+    finally:
+        oracle.set_threads(threads)
+    suffix = " with the depth and alpha channels" if channels else ""
+    out = {"value": round(px / dt / 1e6, 4), "unit": "Mpix/s", "cores": threads, "kind": "oracle",
+           "seconds": round(dt, 2),
+           "sample": f"views {views} of the workload ({px} px, all {scene.n} splats), FP64 fwd+bwd" + suffix,
+           "single_thread": {"value": round(px1 / dt1 / 1e6, 5), "unit": "Mpix/s", "seconds": round(dt1, 2),
+                             "sample": f"view {views[0]} ({px1} px, all {scene.n} splats), FP64 fwd+bwd" + suffix}}
+    out.update(cpu_info())
+    return out
 
 
 if __name__ == "__main__":

@@ -406,6 +406,59 @@ gesr_status gesr_surface_points(gesr_ctx* ctx, const gesr_splats* splats, const 
 gesr_status gesr_l1_grad(gesr_ctx* ctx, const float* image, const float* target, uint64_t count, float scale,
                          float* grad, void* stream);
 
+/* Photometric loss of Eq. 8 (Sec. 3.2): per view v,
+ *   L_v = (1 - lambda) mean|X - Y| + lambda (1 - mean SSIM(X, Y))
+ * over the view's 3 H W values (X the rendered image, Y the target), with the
+ * SSIM of an 11 x 11 Gaussian window (GESR_LOSS_RADIUS = 5) of standard
+ * deviation `sigma`, zero padding outside the image, the map
+ *   S = (2 mu_x mu_y + c1)(2 s_xy + c2) / ((mu_x^2 + mu_y^2 + c1)(s_x^2 + s_y^2 + c2))
+ * per channel and pixel (mu, s^2, s_xy the window means, variances and
+ * covariance).  gesr_default_loss_settings(): lambda 0.2 (the paper's value),
+ * c1 = 0.01^2, c2 = 0.03^2, sigma = 1.5 (not given in the paper; the usual
+ * SSIM constants for images in [0, 1]). */
+#define GESR_LOSS_RADIUS 5
+typedef struct {
+    float lambda_dssim;
+    float c1, c2;
+    float sigma;
+} gesr_loss_settings;
+
+void gesr_default_loss_settings(gesr_loss_settings* s);
+
+/* Workspace bytes of gesr_loss_eq8 for the views.  Host-only; 0 for invalid views. */
+size_t gesr_loss_workspace_size(const gesr_camera* cams, int V);
+
+/* Gradient of sum_v L_v with respect to the image into grad (DEVICE [3P], the
+ * image layout; overwritten): (1 - lambda) sign(X - Y) / n_v (sign(0) = 0)
+ * minus lambda / n_v times the SSIM map's gradient, n_v = 3 H W.  loss
+ * (DEVICE float [V], nullable) receives L_v.  image, target, grad: DEVICE,
+ * 16-byte aligned, grad may not alias image or target.  Fixed-order sums:
+ * results are bitwise reproducible.  workspace: DEVICE, at least
+ * gesr_loss_workspace_size bytes.  GESR_ERR_INVALID for bad views, NULL or
+ * misaligned arrays, a small workspace, lambda outside [0, 1] or non-positive
+ * c1, c2, sigma; nothing is enqueued then. */
+gesr_status gesr_loss_eq8(gesr_ctx* ctx, const gesr_camera* cams, int V, const gesr_loss_settings* ls,
+                          const float* image, const float* target, float* grad, float* loss, void* workspace,
+                          size_t workspace_bytes, void* stream);
+
+/* Surface-alignment regulariser of the flattened-splat workload (the paper
+ * drives its splats flat onto the surface, Sec. 3.3; this loss is the reading
+ * used for that workload): with k* the axis of the smallest scale of splat i
+ * (lowest index on ties), n_i = R(q_i) e_k* and m_i its true surface normal
+ * (normals DEVICE [3][n], unit length, sign-free),
+ *   L = w_scale / n sum_i s_ik* + w_normal / n sum_i (1 - <n_i, m_i>^2).
+ * Its gradient with respect to the scales and the raw quaternions (through the
+ * normalisation) is ADDED to grads->scale and grads->quat (other gradient
+ * arrays untouched; k* held fixed).  losses (DEVICE float [2], nullable): the
+ * two terms, summed in a fixed order; they need a workspace of
+ * gesr_align_workspace_size(n) bytes (else workspace may be NULL).  DEVICE
+ * arrays 16-byte aligned.  GESR_ERR_INVALID for NULL or misaligned arrays,
+ * non-finite weights or a small workspace. */
+size_t gesr_align_workspace_size(int n);
+gesr_status gesr_surface_align(gesr_ctx* ctx, const gesr_splats* splats, const float* normals, float w_scale,
+                               float w_normal, const gesr_grads* grads, float* losses, void* workspace,
+                               size_t workspace_bytes, void* stream);
+
 /* Optimised (raw) splat parameters, DEVICE float32, structure-of-arrays with
  * the layouts of gesr_splats: mean[3][n], log_scale[3][n] (scale =
  * exp(log_scale)), quat[4][n], opacity_logit[n] (opacity = sigmoid(logit)),

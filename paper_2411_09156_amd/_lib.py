@@ -29,7 +29,8 @@ EXPORTS = (
     "gesr_render_fwd_ext", "gesr_render_bwd_ext", "gesr_render_bwd_tiles_ext", "gesr_surface_points",
     "gesr_project_bwd", "gesr_l1_grad", "gesr_autotune", "gesr_autotune_candidate", "gesr_default_adam_settings",
     "gesr_adam_step", "gesr_prune_workspace_size", "gesr_prune", "gesr_shape_reset", "gesr_knn_workspace_size",
-    "gesr_knn", "gesr_gsr_workspace_size", "gesr_gsr",
+    "gesr_knn", "gesr_gsr_workspace_size", "gesr_gsr", "gesr_default_loss_settings", "gesr_loss_workspace_size",
+    "gesr_loss_eq8", "gesr_align_workspace_size", "gesr_surface_align",
 )
 KNN_MAX = 16
 
@@ -184,6 +185,18 @@ def load():
     lib.gesr_surface_points.restype = st
     lib.gesr_l1_grad.argtypes = [vp, vp, vp, ctypes.c_uint64, ctypes.c_float, vp, vp]
     lib.gesr_l1_grad.restype = st
+    lib.gesr_default_loss_settings.argtypes = [P(LossSettings)]
+    lib.gesr_default_loss_settings.restype = None
+    lib.gesr_loss_workspace_size.argtypes = [P(Camera), ctypes.c_int]
+    lib.gesr_loss_workspace_size.restype = ctypes.c_size_t
+    lib.gesr_loss_eq8.argtypes = [vp, P(Camera), ctypes.c_int, P(LossSettings), vp, vp, vp, vp, vp, ctypes.c_size_t,
+                                  vp]
+    lib.gesr_loss_eq8.restype = st
+    lib.gesr_align_workspace_size.argtypes = [ctypes.c_int]
+    lib.gesr_align_workspace_size.restype = ctypes.c_size_t
+    lib.gesr_surface_align.argtypes = [vp, P(Splats), vp, ctypes.c_float, ctypes.c_float, P(Grads), vp, vp,
+                                       ctypes.c_size_t, vp]
+    lib.gesr_surface_align.restype = st
     lib.gesr_autotune.argtypes = [vp, P(Splats), P(Camera), ctypes.c_int, P(Settings), ctypes.c_int, c_float_p,
                                   ctypes.c_int, P(ctypes.c_int), vp]
     lib.gesr_autotune.restype = st
@@ -211,6 +224,11 @@ def load():
     lib.gesr_gsr.restype = st
     _lib = lib
     return lib
+
+
+class LossSettings(ctypes.Structure):
+    _fields_ = [("lambda_dssim", ctypes.c_float), ("c1", ctypes.c_float), ("c2", ctypes.c_float),
+                ("sigma", ctypes.c_float)]
 
 
 class GesrError(RuntimeError):

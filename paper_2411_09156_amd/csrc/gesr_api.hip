@@ -811,6 +811,150 @@ gesr_status gesr_surface_points(gesr_ctx* ctx, const gesr_splats* splats, const 
     return GESR_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Views and workspace layout of gesr_loss_eq8: 16 x 16 tiles per view; the
+// three adjoint maps [3P] and the per-tile partial sums [T][2], 256-byte aligned.
+struct LossLayout {
+    bool ok;
+    uint64_t pixels, tiles;
+    size_t o_b, o_c, o_partial, bytes;
+};
+
+LossLayout loss_layout(const gesr_camera* cams, int V, gesr::LossArgs* a) {
+    LossLayout L{false, 0, 0, 0, 0, 0, 0};
+    if (!cams || V < 1 || V > GESR_MAX_VIEWS) return L;
+    for (int v = 0; v < V; ++v) {
+        const int W = cams[v].width, H = cams[v].height;
+        if (W < 1 || H < 1 || W > 65535 || H > 65535) return L;
+        if (a) {
+            a->v[v].W = W;
+            a->v[v].H = H;
+            a->v[v].pix_base = (uint32_t)L.pixels;
+            a->v[v].tile_base = (uint32_t)L.tiles;
+            a->v[v].inv_n = (float)(1.0 / (3.0 * (double)W * (double)H));
+        }
+        L.pixels += (uint64_t)W * H;
+        L.tiles += (uint64_t)((W + 15) / 16) * ((H + 15) / 16);
+    }
+    if (3 * L.pixels >= (1ull << 32)) return L;
+    auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+    const size_t map = al(3 * L.pixels * sizeof(float));
+    L.o_b = map;
+    L.o_c = 2 * map;
+    L.o_partial = 3 * map;
+    L.bytes = 3 * map + al(2 * L.tiles * sizeof(float));
+    L.ok = true;
+    return L;
+}
+
+}  // namespace
+
+extern "C" {
+
+void gesr_default_loss_settings(gesr_loss_settings* s) {
+    if (!s) return;
+    s->lambda_dssim = 0.2f;
+    s->c1 = 0.01f * 0.01f;
+    s->c2 = 0.03f * 0.03f;
+    s->sigma = 1.5f;
+}
+
+size_t gesr_loss_workspace_size(const gesr_camera* cams, int V) {
+    const LossLayout L = loss_layout(cams, V, nullptr);
+    return L.ok ? L.bytes : 0;
+}
+
+gesr_status gesr_loss_eq8(gesr_ctx* ctx, const gesr_camera* cams, int V, const gesr_loss_settings* ls,
+                          const float* image, const float* target, float* grad, float* loss, void* workspace,
+                          size_t workspace_bytes, void* stream) {
+    if (!ctx) return GESR_ERR_INVALID;
+    if (!ls) return fail(ctx, GESR_ERR_INVALID, "loss settings are NULL");
+    if (!(ls->lambda_dssim >= 0.0f && ls->lambda_dssim <= 1.0f))
+        return fail(ctx, GESR_ERR_INVALID, "lambda_dssim must be in [0, 1]");
+    if (!(ls->c1 > 0.0f) || !(ls->c2 > 0.0f) || !isfinite(ls->c1) || !isfinite(ls->c2))
+        return fail(ctx, GESR_ERR_INVALID, "c1 and c2 must be positive and finite");
+    if (!(ls->sigma > 0.0f) || !isfinite(ls->sigma)) return fail(ctx, GESR_ERR_INVALID, "sigma must be positive");
+    gesr::LossArgs a;
+    memset(&a, 0, sizeof a);
+    const LossLayout L = loss_layout(cams, V, &a);
+    if (!L.ok) return fail(ctx, GESR_ERR_INVALID, "views: V in 1..%d, sizes 1..65535, 3 P < 2^32", GESR_MAX_VIEWS);
+    const void* ptrs[4] = {image, target, grad, workspace};
+    const char* names[4] = {"image", "target", "grad", "workspace"};
+    for (int k = 0; k < 4; ++k) {
+        if (!ptrs[k]) return fail(ctx, GESR_ERR_INVALID, "%s is NULL", names[k]);
+        if (!aligned16(ptrs[k])) return fail(ctx, GESR_ERR_INVALID, "%s is not 16-byte aligned", names[k]);
+    }
+    if (grad == image || grad == target) return fail(ctx, GESR_ERR_INVALID, "grad aliases image or target");
+    if (workspace_bytes < L.bytes)
+        return fail(ctx, GESR_ERR_INVALID, "workspace_bytes %zu < required %zu", workspace_bytes, L.bytes);
+    a.V = V;
+    double wsum = 0.0, wd[2 * GESR_LOSS_RADIUS + 1];
+    for (int k = -GESR_LOSS_RADIUS; k <= GESR_LOSS_RADIUS; ++k) {
+        wd[k + GESR_LOSS_RADIUS] = exp(-(double)(k * k) / (2.0 * (double)ls->sigma * ls->sigma));
+        wsum += wd[k + GESR_LOSS_RADIUS];
+    }
+    for (int k = 0; k <= 2 * GESR_LOSS_RADIUS; ++k) a.w[k] = (float)(wd[k] / wsum);
+    a.lam = ls->lambda_dssim;
+    a.c1 = ls->c1;
+    a.c2 = ls->c2;
+    a.image = image;
+    a.target = target;
+    char* ws = (char*)workspace;
+    a.amap = (float*)ws;
+    a.bmap = (float*)(ws + L.o_b);
+    a.cmap = (float*)(ws + L.o_c);
+    a.partial = (float*)(ws + L.o_partial);
+    a.grad = grad;
+    a.loss = loss;
+    GESR_TRY(hip_check(ctx, hipSetDevice(ctx->device), "hipSetDevice"));
+    GESR_TRY(hip_check(ctx, gesr::launch_ssim_loss(a, (uint32_t)L.tiles, loss != nullptr, (hipStream_t)stream),
+                       "loss launch"));
+    ctx->err.clear();
+    return GESR_OK;
+}
+
+size_t gesr_align_workspace_size(int n) { return n > 0 ? (size_t)((n + 255) / 256) * 2 * sizeof(float) + 256 : 0; }
+
+gesr_status gesr_surface_align(gesr_ctx* ctx, const gesr_splats* splats, const float* normals, float w_scale,
+                               float w_normal, const gesr_grads* grads, float* losses, void* workspace,
+                               size_t workspace_bytes, void* stream) {
+    if (!ctx) return GESR_ERR_INVALID;
+    if (!splats || splats->n < 0) return fail(ctx, GESR_ERR_INVALID, "splats is NULL or n is negative");
+    if (!isfinite(w_scale) || !isfinite(w_normal)) return fail(ctx, GESR_ERR_INVALID, "weights must be finite");
+    const int n = splats->n;
+    if (n == 0) {
+        ctx->err.clear();
+        return GESR_OK;
+    }
+    if (!grads) return fail(ctx, GESR_ERR_INVALID, "grads is NULL");
+    const void* ptrs[5] = {splats->scale, splats->quat, normals, grads->scale, grads->quat};
+    const char* names[5] = {"splats->scale", "splats->quat", "normals", "grads->scale", "grads->quat"};
+    for (int k = 0; k < 5; ++k) {
+        if (!ptrs[k]) return fail(ctx, GESR_ERR_INVALID, "%s is NULL", names[k]);
+        if (!aligned16(ptrs[k])) return fail(ctx, GESR_ERR_INVALID, "%s is not 16-byte aligned", names[k]);
+    }
+    if (losses && (!workspace || workspace_bytes < gesr_align_workspace_size(n)))
+        return fail(ctx, GESR_ERR_INVALID, "losses need a workspace of %zu bytes", gesr_align_workspace_size(n));
+    gesr::AlignArgs a;
+    a.n = n;
+    a.scale = splats->scale;
+    a.quat = splats->quat;
+    a.normal = normals;
+    a.w_scale_n = w_scale / (float)n;
+    a.w_normal_n = w_normal / (float)n;
+    a.g_scale = grads->scale;
+    a.g_quat = grads->quat;
+    a.partial = losses ? (float*)workspace : nullptr;
+    a.losses = losses;
+    GESR_TRY(hip_check(ctx, hipSetDevice(ctx->device), "hipSetDevice"));
+    GESR_TRY(hip_check(ctx, gesr::launch_surface_align(a, (hipStream_t)stream), "align launch"));
+    ctx->err.clear();
+    return GESR_OK;
+}
+
 gesr_status gesr_l1_grad(gesr_ctx* ctx, const float* image, const float* target, uint64_t count, float scale,
                          float* grad, void* stream) {
     if (!ctx) return GESR_ERR_INVALID;

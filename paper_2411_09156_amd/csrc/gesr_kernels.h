@@ -177,6 +177,42 @@ hipError_t launch_ranges_from_counts(const uint32_t* counts, const uint32_t* sta
 hipError_t launch_set_counters(uint32_t* counters, uint64_t m_cap, hipStream_t stream);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, uint64_t count, hipStream_t stream);
 hipError_t launch_worklist_keys(const uint32_t* ranges, uint64_t total_tiles, uint32_t* keys, hipStream_t stream);
+// Photometric loss of Eq. 8 (gesr_loss.hip).
+struct LossView {
+    int W, H;
+    uint32_t pix_base;   // first pixel of the view
+    uint32_t tile_base;  // first 16 x 16 loss tile of the view
+    float inv_n;         // 1 / (3 W H)
+};
+struct LossArgs {
+    int V;
+    LossView v[GESR_MAX_VIEWS];
+    float w[2 * GESR_LOSS_RADIUS + 1];  // normalised Gaussian weights, offsets -r..r
+    float lam, c1, c2;
+    const float* image;
+    const float* target;
+    float* amap;     // [3P] dS/dmu_x per value (CHW per view, as the image)
+    float* bmap;     // [3P] dS/dm2x
+    float* cmap;     // [3P] dS/dmxy
+    float* partial;  // [tiles][2]: per-tile sums of S and |X - Y|
+    float* grad;     // [3P]
+    float* loss;     // [V]
+};
+hipError_t launch_ssim_loss(const LossArgs& a, uint32_t n_tiles, bool want_loss, hipStream_t stream);
+
+// Surface-alignment regulariser (gesr_loss.hip).
+struct AlignArgs {
+    int n;
+    const float* scale;   // [3][n]
+    const float* quat;    // [4][n]
+    const float* normal;  // [3][n] true surface normals
+    float w_scale_n, w_normal_n;  // weights / n
+    float* g_scale;       // [3][n], added to
+    float* g_quat;        // [4][n], added to
+    float* partial;       // [blocks][2] (nullable when losses is)
+    float* losses;        // [2] (nullable)
+};
+hipError_t launch_surface_align(const AlignArgs& a, hipStream_t stream);
 hipError_t launch_l1_grad(const float* image, const float* target, uint64_t count, float scale, float* grad,
                           hipStream_t stream);
 

@@ -281,6 +281,26 @@ class Rasterizer:
             g["grad2d"] = grad2d
         return g
 
+    def surface_align(self, sp: Splats, normals, grads: dict, w_scale: float = 0.1, w_normal: float = 0.1,
+                      want_losses: bool = True, workspace=None):
+        """Surface-alignment regulariser (min-scale + normal terms): its gradient
+        is ADDED to grads["scale"] and grads["quat"]; returns the two loss terms
+        [2] (or None).  normals: [3][n] float32 device tensor (SoA)."""
+        nrm = normals.contiguous()
+        gc = _lib.Grads(*(grads[k].data_ptr() if k in grads else None
+                          for k in ("mean", "scale", "quat", "opacity", "beta", "sh")))
+        losses = torch.empty(2, dtype=torch.float32, device=self.device) if want_losses else None
+        if want_losses and workspace is None:
+            workspace = torch.empty(int(self.lib.gesr_align_workspace_size(sp.n)), dtype=torch.uint8,
+                                    device=self.device)
+        self._check(self.lib.gesr_surface_align(self.ctx, ctypes.byref(sp.to_c()), nrm.data_ptr(), float(w_scale),
+                                                float(w_normal), ctypes.byref(gc),
+                                                losses.data_ptr() if losses is not None else None,
+                                                workspace.data_ptr() if workspace is not None else None,
+                                                workspace.numel() if workspace is not None else 0, _stream()),
+                    self.ctx)
+        return losses
+
     def surface_points(self, sp: Splats, proj: dict, bins: dict, depth, alpha, pixels, n_samples: int = 32,
                        level: float = 0.3, span: float = 3.0, min_alpha: float = 0.5) -> dict:
         """Level-set surface points along the rays of `pixels` (int tensor of
@@ -309,6 +329,28 @@ class Rasterizer:
         self._check(self.lib.gesr_l1_grad(self.ctx, image.data_ptr(), target.data_ptr(), image.numel(),
                                           float(scale), grad.data_ptr(), _stream()), self.ctx)
         return grad
+
+    def loss_eq8(self, image, target, lambda_dssim: float = 0.2, want_loss: bool = True, workspace=None):
+        """Eq. 8 per view, (1 - lambda) mean|X - Y| + lambda (1 - mean SSIM):
+        returns (dL/dimage for the sum over views, per-view losses [V] or None).
+        `workspace` (uint8 tensor of gesr_loss_workspace_size bytes) may be
+        passed to keep the call allocation-free (e.g. under graph capture)."""
+        ls = _lib.LossSettings()
+        self.lib.gesr_default_loss_settings(ctypes.byref(ls))
+        ls.lambda_dssim = float(lambda_dssim)
+        if workspace is None:
+            workspace = self.alloc_loss_workspace()
+        grad = torch.empty_like(image)
+        loss = torch.empty(self.V, dtype=torch.float32, device=self.device) if want_loss else None
+        self._check(self.lib.gesr_loss_eq8(self.ctx, self.cams_c, self.V, ctypes.byref(ls), image.data_ptr(),
+                                           target.data_ptr(), grad.data_ptr(),
+                                           loss.data_ptr() if loss is not None else None, workspace.data_ptr(),
+                                           workspace.numel(), _stream()), self.ctx)
+        return grad, loss
+
+    def alloc_loss_workspace(self):
+        return torch.empty(int(self.lib.gesr_loss_workspace_size(self.cams_c, self.V)), dtype=torch.uint8,
+                           device=self.device)
 
     def forward(self, sp: Splats, sync: bool = True, m_cap: Optional[int] = None, counts: bool = False,
                 channels: bool = False):

@@ -19,12 +19,14 @@ def test_more_than_one_gpu_is_refused():
 
 
 def test_fingerprint_ignores_comments_not_code(tmp_path, monkeypatch):
-    src = os.path.join(ROOT, "paper_2411_09156_amd", "csrc")
     csrc = tmp_path / "paper_2411_09156_amd" / "csrc"
     csrc.mkdir(parents=True)
-    for f in ("gesr_render.hip", "gesr_device.h", "gesr_bin.hip"):
-        with open(os.path.join(src, f)) as fh:
-            (csrc / f).write_text(fh.read())
+    (tmp_path / "include").mkdir()
+    for f in ("paper_2411_09156_amd/csrc/gesr_render.hip", "paper_2411_09156_amd/csrc/gesr_device.h",
+              "paper_2411_09156_amd/csrc/gesr_bin.hip", "paper_2411_09156_amd/csrc/gesr_project.hip",
+              "paper_2411_09156_amd/csrc/gesr_kernels.h", "include/gesr.h"):
+        with open(os.path.join(ROOT, f)) as fh:
+            (tmp_path / f).write_text(fh.read())
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     base = bench.kernel_fingerprint()
     p = csrc / "gesr_bin.hip"
@@ -32,4 +34,8 @@ def test_fingerprint_ignores_comments_not_code(tmp_path, monkeypatch):
     p.write_text("// a new comment line\n" + text.replace("\n", "\n\n", 3) + "\n/* trailing\n   block */\n")
     assert bench.kernel_fingerprint() == base
     p.write_text(text.replace("IS_IPL = 2", "IS_IPL = 4", 1))
+    assert bench.kernel_fingerprint() != base
+    p.write_text(text)
+    h = tmp_path / "include" / "gesr.h"
+    h.write_text(h.read_text().replace("#define GESR_REC_FLOATS 12", "#define GESR_REC_FLOATS 16", 1))
     assert bench.kernel_fingerprint() != base

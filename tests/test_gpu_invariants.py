@@ -611,3 +611,128 @@ def test_autotuner_picks_a_candidate_that_renders_identically():
     assert res["radix_bits"] == min(widths)[2]
     assert (rast.settings.tile_w, rast.settings.tile_h) == tuple(int(x) for x in res["tile"].split("x"))
     np.testing.assert_array_equal(f32(rast.forward(sp)["image"]), ref)
+
+
+@pytest.mark.timeout(1200)
+def test_full_size_flattened_workload_finite_differences():
+    """The flattened workload at full size (1M splats, 4 views at 1957x1091,
+    SH degree 3) with its loss: L = sum(g . image) + L_reg, g seeded N(0,1)
+    over the tiles that 64 sampled splats' footprints cover (zero elsewhere
+    and at pixels with a decision inside its float32 band), L_reg the
+    surface-alignment regulariser (weights 0.1).  The GPU gradient (render
+    adjoint, projection adjoint, regulariser) of 64 sampled parameters equals
+    central differences of the FP64 oracle: |g - g_FD| <= 1e-3 max(|g_FD|,
+    1e-3 ||g||_inf), ||g||_inf over the parameter's tensor.  Each difference
+    re-renders the splat's pixel window from the splats whose footprints meet
+    it (the only pixels it changes); steps that change a decision are halved,
+    then skipped."""
+    torch = _torch()
+    scene = gi.make_workload(4)
+    st = oracle.Settings(sh_degree=3)
+    N, V = scene.n, scene.n_views
+    cams = scene.cameras
+    grid, T = oracle.tile_grid(cams, st.tile_w, st.tile_h)
+    pr = oracle.project(scene, st)
+    rng = gi.sample_rng(41)
+    # 64 (splat, parameter) samples among splats with modest footprints in some view
+    area = np.zeros(N)
+    for v in range(V):
+        r = pr["pix_rect"][v * N:(v + 1) * N].astype(np.int64)
+        a = np.where(pr["tiles_touched"][v * N:(v + 1) * N] > 0, (r[:, 2] - r[:, 0] + 1) * (r[:, 3] - r[:, 1] + 1), 0)
+        area = np.maximum(area, a)
+    pool = np.nonzero((area >= 9) & (area <= 2500))[0]
+    splats = rng.choice(pool, 64, replace=False)
+    groups = ("means", "scales", "quats", "opacities", "betas", "sh")
+    sizes = dict(means=3, scales=3, quats=4, opacities=1, betas=1, sh=48)
+    samples = [(int(i), groups[int(rng.integers(0, 6))]) for i in splats]
+    samples = [(i, gname, int(rng.integers(0, sizes[gname]))) for i, gname in samples]
+    # per sample and view: its pixel window (footprint rectangle + 2 px)
+    wins = {}
+    sel = np.zeros(T, bool)
+    for i, _, _ in samples:
+        w = np.full((V, 4), [0, 0, -1, -1], np.int32)
+        for v, c in enumerate(cams):
+            o = v * N + i
+            if pr["tiles_touched"][o] == 0:
+                continue
+            x0, y0, x1, y1 = (int(t) for t in pr["pix_rect"][o])
+            w[v] = [max(x0 - 2, 0), max(y0 - 2, 0), min(x1 + 2, c.width - 1), min(y1 + 2, c.height - 1)]
+            tx_n, _, base = grid[v]
+            for ty in range(w[v, 1] // st.tile_h, w[v, 3] // st.tile_h + 1):
+                sel[base + ty * tx_n + w[v, 0] // st.tile_w: base + ty * tx_n + w[v, 2] // st.tile_w + 1] = True
+        wins[i] = w
+    # upstream gradient on those tiles, zero at pixels with an in-band decision
+    _, vals, ranges = oracle.bin_instances(N, cams, pr["tile_rect"], pr["tiles_touched"], pr["zbits"], st, pr["rec"])
+    perr = oracle.record_err_bound(scene, st)
+    fo = oracle.render_fwd(N, cams, pr["rec"], vals, np.where(sel[:, None], ranges, 0).astype(np.uint32), st,
+                           perr=perr)
+    del vals, ranges
+    pix = ambiguous_tiles_to_pixels(cams, st, sel)
+    keep = pix & (fo["n_branch"] == 0) & ((fo["ambig"] & 2) == 0)
+    g_img = oracle.flat_images(gi.upstream_grads(scene, 43)).astype(np.float32).astype(np.float64)
+    g_img = mask_upstream(g_img, ~keep, cams)
+    log(f"[gpu] flattened FD: {int(sel.sum())} tiles, {int(pix.sum())} px ({int((pix & ~keep).sum())} in a band)")
+    # GPU: the benchmark pipeline, then the regulariser
+    rast = _rast(scene, st)
+    sp = splats_of(scene)
+    f = rast.forward(sp, sync=True)
+    gpu = rast.render_bwd(sp, f["proj"], f["bins"], f["final_T"], f["n_contrib"],
+                          torch.as_tensor(g_img.astype(np.float32), device="cuda"))
+    nrm = torch.as_tensor(np.ascontiguousarray(np.asarray(scene.normals, np.float32).T), device="cuda")
+    rast.surface_align(sp, nrm, gpu, 0.1, 0.1, want_losses=False)
+    torch.cuda.synchronize()
+    got = _gpu_grads(scene, st, dict(gpu, grad2d=torch.zeros(V * N * 12, device="cuda")))
+    del f, gpu
+    gmax = {gname: float(np.abs(got[gname]).max()) for gname in groups}
+    w_reg = float(np.float32(0.1))
+
+    def local_loss(i, gname, comp, val, cand):
+        sub = copy.copy(scene)
+        for fld in ("means", "log_scales", "scales", "quats", "opacity_logits", "opacities", "betas", "sh",
+                    "normals"):
+            setattr(sub, fld, np.asarray(getattr(scene, fld))[cand].astype(np.float64))
+        j = int(np.nonzero(cand == i)[0][0])
+        arr = getattr(sub, gname)
+        arr.reshape(len(cand), -1)[j, comp] = val
+        ps = oracle.project(sub, st)
+        loss, _, dec = oracle.window_fwdbwd(len(cand), cams, ps["rec"], ps["zbits"], ps["cull"], ps["pix_rect"],
+                                            wins[i], g_img, [], st)
+        Ls, Ln, _ = oracle.surface_alignment(sub.scales[j:j + 1], sub.quats[j:j + 1], sub.normals[j:j + 1],
+                                             w_reg, w_reg)
+        return loss + (Ls + Ln) / N, dec
+
+    checked = skipped = 0
+    worst = 0.0
+    for i, gname, comp in samples:
+        w = wins[i]
+        cand = []
+        for v in range(V):
+            if w[v, 2] < w[v, 0]:
+                continue
+            r = pr["pix_rect"][v * N:(v + 1) * N]
+            hit = (pr["tiles_touched"][v * N:(v + 1) * N] > 0) & (r[:, 2] >= w[v, 0]) & (r[:, 0] <= w[v, 2]) & \
+                  (r[:, 3] >= w[v, 1]) & (r[:, 1] <= w[v, 3])
+            cand.append(np.nonzero(hit)[0])
+        cand = np.unique(np.concatenate(cand + [[i]])).astype(np.int64)
+        base = float(np.asarray(getattr(scene, gname), np.float64).reshape(N, -1)[i, comp])
+        _, dec0 = local_loss(i, gname, comp, base, cand)
+        h = 1e-6 * max(abs(base), 1.0)
+        ok = False
+        for _ in range(4):
+            lp, dp = local_loss(i, gname, comp, base + h, cand)
+            lm, dm = local_loss(i, gname, comp, base - h, cand)
+            if dp == dec0 and dm == dec0:
+                ok = True
+                break
+            h *= 0.5
+        if not ok:
+            skipped += 1
+            continue
+        fd = (lp - lm) / (2 * h)
+        an = float(got[gname].reshape(N, -1)[i, comp])
+        bound = 1e-3 * max(abs(fd), 1e-3 * gmax[gname])
+        worst = max(worst, abs(an - fd) / bound)
+        assert abs(an - fd) <= bound, (i, gname, comp, an, fd)
+        checked += 1
+    assert checked >= 60 and skipped <= 4, (checked, skipped)
+    log(f"[gpu] flattened FD: {checked} of 64 parameters checked, {skipped} skipped; worst error / bar {worst:.2f}")
