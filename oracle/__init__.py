@@ -29,7 +29,8 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "gesr_oracle.cpp")
-_LIB = os.path.join(_HERE, "liboracle.so")
+# GESR_ORACLE_LIB selects another build of the same source (the sanitizer test's)
+_LIB = os.environ.get("GESR_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 
@@ -47,7 +48,8 @@ def build(force: bool = True) -> str:
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        stale = not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC)
+        if stale and "GESR_ORACLE_LIB" not in os.environ:
             build(force=True)
         _lib = ctypes.CDLL(_LIB)
         _lib.orc_bin_count.restype = ctypes.c_uint64

@@ -736,3 +736,48 @@ def test_full_size_flattened_workload_finite_differences():
         checked += 1
     assert checked >= 60 and skipped <= 4, (checked, skipped)
     log(f"[gpu] flattened FD: {checked} of 64 parameters checked, {skipped} skipped; worst error / bar {worst:.2f}")
+
+
+def test_non_finite_splats_are_culled():
+    """Splats with a NaN or infinite parameter (mean, scale, quaternion,
+    opacity, beta or an SH coefficient) are culled in every view, as the oracle
+    culls them; the image, final T and n_contrib equal those of the scene
+    without them bit for bit, their gradients are exactly zero and every other
+    splat's gradient equals the reduced scene's bit for bit."""
+    scene = gi.tiny_scene(9, n=40, deg=2, n_views=2, width=48, height=40)
+    st = oracle.Settings(sh_degree=2, bg=(0.1, 0.2, 0.3))
+    bad = [(3, "means", (0, 1), np.nan), (7, "means", (0, 2), np.inf), (11, "scales", (0, 0), np.inf),
+           (13, "scales", (0, 1), np.nan), (17, "quats", (0, 3), np.nan), (19, "opacities", (), np.nan),
+           (23, "betas", (), np.inf), (29, "betas", (), np.nan), (31, "sh", (0, 4, 1), np.nan),
+           (37, "sh", (0, 0, 2), -np.inf)]
+    mod = copy.copy(scene)
+    for f in ("means", "scales", "quats", "opacities", "betas", "sh"):
+        setattr(mod, f, np.array(getattr(scene, f), np.float32, copy=True))
+    for i, f, idx, val in bad:
+        arr = getattr(mod, f)
+        if arr.ndim == 1:
+            arr[i] = val
+        else:
+            arr[(i,) + idx[1:]] = val
+    bad_idx = np.array(sorted(i for i, _, _, _ in bad))
+    pr = oracle.project(mod, st)
+    for v in range(mod.n_views):
+        assert (pr["cull"][v * mod.n + bad_idx] != 0).all()
+    log("[gpu] non-finite splats: full scene")
+    g = run_gpu(mod, st, counts=False)
+    keep = np.setdiff1d(np.arange(scene.n), bad_idx)
+    red = copy.copy(scene)
+    for f in ("means", "log_scales", "scales", "quats", "opacity_logits", "opacities", "betas", "sh"):
+        setattr(red, f, np.asarray(getattr(scene, f))[keep])
+    log("[gpu] non-finite splats: reduced scene")
+    gr = run_gpu(red, st, counts=False)
+    for v in range(mod.n_views):
+        assert (g["tiles_touched"][v * mod.n + bad_idx] == 0).all()
+    for k in ("image", "final_T", "n_contrib"):
+        np.testing.assert_array_equal(g[k], gr[k], err_msg=k)
+    dL = oracle.flat_images(gi.upstream_grads(scene, 17))
+    gb = run_gpu_bwd(mod, st, g, dL)
+    gbr = run_gpu_bwd(red, st, gr, dL)
+    for k in PARAMS:
+        assert not gb[k][bad_idx].any(), k
+        np.testing.assert_array_equal(gb[k][keep], gbr[k], err_msg=k)
