@@ -288,7 +288,9 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs a) {
             float acc = 0.f;
 #pragma unroll
             for (int k = 0; k < K; ++k) acc = fmaf(Y[k], sh[3 * k + c], acc);
-            rgb[c] = fmaxf(acc + 0.5f, 0.0f);
+            // clamp at 0; a NaN stays NaN (fmaxf would return 0) so the pair is culled below
+            const float col = acc + 0.5f;
+            rgb[c] = col < 0.0f ? 0.0f : col;
         }
         bool keep = vp.ok && op >= st.alpha_min;
         float rx = sqrtf(qmax * vp.a), ry = sqrtf(qmax * vp.c);
@@ -300,7 +302,8 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs a) {
         fy1 = fminf(fy1, (float)(w.H - 1));
         keep = keep && fx0 <= fx1 && fy0 <= fy1;
         // non-finite parameters or results cull the pair
-        float chk = vp.u + vp.v + vp.L00 + vp.L10 + vp.L11 + op + beta + rgb[0] + rgb[1] + rgb[2] + qmax;
+        float chk = vp.u + vp.v + vp.L00 + vp.L10 + vp.L11 + op + beta + rgb[0] + rgb[1] + rgb[2] + qmax + vp.a +
+                    vp.c + vp.det;
         keep = keep && isfinite(chk);
         float4* rec = reinterpret_cast<float4*>(a.rec + vi * GESR_REC_FLOATS);
         if (keep) {

@@ -749,7 +749,7 @@ def test_non_finite_splats_are_culled():
     bad = [(3, "means", (0, 1), np.nan), (7, "means", (0, 2), np.inf), (11, "scales", (0, 0), np.inf),
            (13, "scales", (0, 1), np.nan), (17, "quats", (0, 3), np.nan), (19, "opacities", (), np.nan),
            (23, "betas", (), np.inf), (29, "betas", (), np.nan), (31, "sh", (0, 4, 1), np.nan),
-           (37, "sh", (0, 0, 2), -np.inf)]
+           (37, "sh", (0, 0, 2), np.inf)]
     mod = copy.copy(scene)
     for f in ("means", "scales", "quats", "opacities", "betas", "sh"):
         setattr(mod, f, np.array(getattr(scene, f), np.float32, copy=True))
