@@ -136,7 +136,8 @@ typedef struct {
  *  ranges[T][2]: [first, end) of each global tile in the sorted list, (0, 0)
  *      when empty.  Global tile ids number the tiles of view 0 row-major,
  *      then view 1, and so on.
- *  worklist[T]: global tile ids ordered by decreasing list length (ties by id).
+ *  worklist[T]: global tile ids ordered by decreasing list length (ties by
+ *      id), or by decreasing tile_work with GESR_BIN_WORK_ORDER.
  *  inst_base[V*n]: exclusive scan of tiles_touched in (view, splat) order: the
  *      instance slots of pair vi are inst_base[vi] + (row-major position of the
  *      tile in the pair's rectangle); the backward's per-instance partials use
@@ -144,7 +145,16 @@ typedef struct {
  *  counters[4]: [0] = M (instance slots: the tiles of every pair's
  *      rectangle), [1] = 1 if M > m_cap, [2] = min(M, m_cap), [3] = the
  *      instances in the tile lists (<= M: each rectangle row keeps only the
- *      columns its ellipse reaches).  Written on the device. */
+ *      columns its ellipse reaches).  Written on the device.
+ *  tile_work[T] (nullable, kept by the caller across calls): gesr_render_fwd
+ *      writes, per global tile, the list positions its renderer evaluated
+ *      before every pixel of the tile had terminated (at most the list
+ *      length); gesr_bin with GESR_BIN_WORK_ORDER orders the worklist by
+ *      decreasing tile_work (ties by id) instead of list length.  Most tiles
+ *      stop long before their lists end, so a previous forward's figures over
+ *      the same views and tile shape (consecutive training iterations, repeated
+ *      renders) start the longest-running tiles first.  The order schedules
+ *      tiles only: every output is the same whatever tile_work holds. */
 typedef struct {
     uint64_t m_cap;
     uint32_t* tile_sorted;
@@ -155,6 +165,7 @@ typedef struct {
     uint32_t* counters;
     void* scratch;
     size_t scratch_bytes;
+    uint32_t* tile_work;
 } gesr_bins;
 
 /* Gradient outputs, DEVICE, same layouts as gesr_splats; overwritten. */
@@ -190,7 +201,8 @@ gesr_status gesr_query_sizes(gesr_ctx* ctx, const gesr_camera* cams, int V, int 
 gesr_status gesr_project(gesr_ctx* ctx, const gesr_splats* splats, const gesr_camera* cams, int V,
                          const gesr_settings* st, const gesr_proj* out, void* stream);
 
-#define GESR_BIN_SYNC 1 /* read M back and fail with GESR_ERR_CAPACITY if M > m_cap */
+#define GESR_BIN_SYNC 1       /* read M back and fail with GESR_ERR_CAPACITY if M > m_cap */
+#define GESR_BIN_WORK_ORDER 2 /* worklist by decreasing bins->tile_work (non-NULL) */
 
 /* Tile binning: one instance per (view, splat, covered tile), sorted by the
  * (tile | depth) key (see gesr_bins).  A pair covers the tiles of its
@@ -265,7 +277,9 @@ typedef struct {
  * alpha < alpha_min are skipped; compositing stops before a fragment that
  * would take T below t_min.  Outputs (DEVICE, P = total pixels):
  * image[3P] (CHW per view), final_T[P], n_contrib[P] (1-based list position
- * of the last composited fragment, 0 if none).  counts may be NULL. */
+ * of the last composited fragment, 0 if none).  counts may be NULL.  Tiles are
+ * rendered in bins->worklist order; bins->tile_work, when non-NULL, receives
+ * each tile's evaluated list positions (see gesr_bins). */
 gesr_status gesr_render_fwd(gesr_ctx* ctx, const gesr_proj* proj, const gesr_bins* bins, const gesr_camera* cams,
                             int V, int n, const gesr_settings* st, float* image, float* final_T,
                             uint32_t* n_contrib, const gesr_fwd_counts* counts, void* stream);
@@ -339,7 +353,9 @@ gesr_status gesr_project_bwd(gesr_ctx* ctx, const gesr_splats* splats, const ges
 /* Autotuner (set-up call; it allocates, synchronises and is not capturable).
  * Times the whole forward + backward pipeline (gesr_project, gesr_bin with
  * capacity exactly M, gesr_render_fwd, gesr_render_bwd) on the caller's splats
- * and cameras, `reps` timed repetitions after one warm-up, for each candidate
+ * and cameras, `reps` timed repetitions after one warm-up (whose forward
+ * measures the tiles' work: the timed binnings order their worklists by it,
+ * GESR_BIN_WORK_ORDER), for each candidate
  * (tile shape, 16x16 renderer variant, LDS batch), then for the best of those
  * each depth-sort digit width 5..8, and writes the fastest into *inout (the
  * numeric settings are kept).  The upstream gradient is a constant.  Device

@@ -17,6 +17,7 @@ GESR_ERR_CAPACITY = 2
 GESR_ERR_HIP = 3
 GESR_ERR_UNSUPPORTED = 4
 GESR_BIN_SYNC = 1
+GESR_BIN_WORK_ORDER = 2
 BIN_STATIC_SCRATCH_BYTES = 64 << 20
 MAX_VIEWS = 32
 REC_FLOATS = 12
@@ -67,7 +68,8 @@ class Proj(ctypes.Structure):
 class Bins(ctypes.Structure):
     _fields_ = [("m_cap", ctypes.c_uint64), ("tile_sorted", ctypes.c_void_p), ("val_sorted", ctypes.c_void_p),
                 ("ranges", ctypes.c_void_p), ("worklist", ctypes.c_void_p), ("inst_base", ctypes.c_void_p),
-                ("counters", ctypes.c_void_p), ("scratch", ctypes.c_void_p), ("scratch_bytes", ctypes.c_size_t)]
+                ("counters", ctypes.c_void_p), ("scratch", ctypes.c_void_p), ("scratch_bytes", ctypes.c_size_t),
+                ("tile_work", ctypes.c_void_p)]
 
 
 class Grads(ctypes.Structure):

@@ -296,6 +296,8 @@ gesr_status check_bins(gesr_ctx* ctx, const gesr_bins* b, bool need_scratch) {
         return fail(ctx, GESR_ERR_INVALID, "bins->tile_sorted is not 16-byte aligned");
     if (need_scratch && (!b->scratch || !aligned16(b->scratch)))
         return fail(ctx, GESR_ERR_INVALID, "bins->scratch is NULL or not 16-byte aligned");
+    if (((uintptr_t)b->tile_work & 3u) != 0)
+        return fail(ctx, GESR_ERR_INVALID, "bins->tile_work is not 4-byte aligned");
     return GESR_OK;
 }
 
@@ -401,6 +403,8 @@ namespace {
 gesr_status bin_impl(gesr_ctx* ctx, const gesr_proj* proj, const gesr_camera* cams, int V, int n,
                      const gesr_settings* st, const gesr_bins* bins, const Geometry& g, void* scratch,
                      size_t scratch_bytes, int flags, uint64_t* m_out, void* stream) {
+    if ((flags & GESR_BIN_WORK_ORDER) && !bins->tile_work)
+        return fail(ctx, GESR_ERR_INVALID, "GESR_BIN_WORK_ORDER needs bins->tile_work");
     const DevCams dc = dev_cams(cams, V, st);
     BinScratch s = carve(scratch, g, dc, n, bins->m_cap);
     if (scratch_bytes < s.bytes)
@@ -492,8 +496,10 @@ gesr_status bin_impl(gesr_ctx* ctx, const gesr_proj* proj, const gesr_camera* ca
     GESR_TRY(hip_check(ctx, launch_ranges_from_counts(s.tile_count, s.tile_start, T, bins->counters + 2,
                                                       bins->ranges, strm),
                        "ranges"));
-    // 5. worklist: tiles by decreasing list length
-    GESR_TRY(hip_check(ctx, launch_worklist_keys(bins->ranges, T, s.w_keys_b, strm), "worklist keys"));
+    // 5. worklist: tiles by decreasing list length, or by decreasing work of a
+    //    previous forward (the positions each tile evaluated before terminating)
+    const uint32_t* work = (flags & GESR_BIN_WORK_ORDER) ? bins->tile_work : nullptr;
+    GESR_TRY(hip_check(ctx, launch_worklist_keys(bins->ranges, work, T, s.w_keys_b, strm), "worklist keys"));
     SortBuffers wb{s.w_keys_a, s.w_vals_a, s.w_keys_b, bins->worklist, s.block_hist, s.scan_partials};
     GESR_TRY(hip_check(ctx, radix_sort(s.w_keys_b, nullptr, T, nullptr, 16, 8, wb, &in_b, strm), "worklist sort"));
     ctx->err.clear();
@@ -606,6 +612,7 @@ gesr_status gesr_render_fwd_ext(gesr_ctx* ctx, const gesr_proj* proj, const gesr
     a.inst_base = bins->inst_base;
     a.n_items = (uint32_t)g.total_tiles;
     a.batch = st->batch > 0 ? st->batch : 64;
+    a.tile_work = bins->tile_work;
     a.image = image;
     a.final_T = final_T;
     a.n_contrib = n_contrib;
@@ -1327,7 +1334,7 @@ float autotune_trial(gesr_ctx* ctx, const gesr_splats* sp, const gesr_camera* ca
         if (gesr_query_sizes(ctx, cams, V, n, &st, m_cap, &sz) != GESR_OK) return false;
         const size_t o_rng = align256(m_cap * 4), o_wl = o_rng + align256(T * 8), o_ib = o_wl + align256(T * 4),
                      o_cnt = o_ib + align256((vn > 0 ? vn : 1) * 4), o_scr = o_cnt + 256,
-                     bytes = o_scr + align256(sz.bin_scratch_bytes);
+                     o_tw = o_scr + align256(sz.bin_scratch_bytes), bytes = o_tw + align256(T * 4);
         if (!binbuf.alloc(bytes)) return false;
         char* b = binbuf.as<char>();
         bins.m_cap = m_cap;
@@ -1339,6 +1346,7 @@ float autotune_trial(gesr_ctx* ctx, const gesr_splats* sp, const gesr_camera* ca
         bins.counters = reinterpret_cast<uint32_t*>(b + o_cnt);
         bins.scratch = b + o_scr;
         bins.scratch_bytes = sz.bin_scratch_bytes;
+        bins.tile_work = reinterpret_cast<uint32_t*>(b + o_tw);
         return true;
     };
     uint64_t m_cap = std::max<uint64_t>(4 * vn, 1024), M = 0;
@@ -1387,15 +1395,17 @@ float autotune_trial(gesr_ctx* ctx, const gesr_splats* sp, const gesr_camera* ca
     grads.beta = reinterpret_cast<float*>(gb + goff[4]);
     grads.sh = reinterpret_cast<float*>(gb + goff[5]);
 
-    auto pipeline = [&]() -> bool {
+    // the warm-up's forward measures each tile's work; the timed passes order
+    // their worklists by it, as a steady-state caller would
+    auto pipeline = [&](int bin_flags) -> bool {
         return gesr_project(ctx, sp, cams, V, &st, &proj, strm) == GESR_OK &&
-               gesr_bin(ctx, &proj, cams, V, n, &st, &bins, 0, nullptr, strm) == GESR_OK &&
+               gesr_bin(ctx, &proj, cams, V, n, &st, &bins, bin_flags, nullptr, strm) == GESR_OK &&
                gesr_render_fwd(ctx, &proj, &bins, cams, V, n, &st, image, final_T, n_contrib, nullptr, strm) ==
                    GESR_OK &&
                gesr_render_bwd(ctx, sp, &proj, &bins, cams, V, &st, final_T, n_contrib, dL, wsbuf.p, nullptr,
                                &grads, strm) == GESR_OK;
     };
-    if (!pipeline()) return -1.f;  // warm-up
+    if (!pipeline(0)) return -1.f;  // warm-up
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return -1.f;
     if (hipEventCreate(&e1) != hipSuccess) {
@@ -1404,7 +1414,7 @@ float autotune_trial(gesr_ctx* ctx, const gesr_splats* sp, const gesr_camera* ca
     }
     float ms = -1.f;
     bool ok = hipEventRecord(e0, strm) == hipSuccess;
-    for (int r = 0; ok && r < reps; ++r) ok = pipeline();
+    for (int r = 0; ok && r < reps; ++r) ok = pipeline(GESR_BIN_WORK_ORDER);
     ok = ok && hipEventRecord(e1, strm) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
          hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
     (void)hipEventDestroy(e0);

@@ -797,11 +797,13 @@ __global__ __launch_bounds__(256) void k_fill_u32(uint32_t* p, uint32_t value, u
     if (k < count) p[k] = value;
 }
 
-// Worklist key: longer lists first (descending length, ties by tile id).
-__global__ __launch_bounds__(256) void k_worklist_keys(const uint32_t* ranges, uint64_t total_tiles, uint32_t* keys) {
+// Worklist key: more work first (descending, ties by tile id); the work is the
+// list length, or a previous forward's evaluated positions when given.
+__global__ __launch_bounds__(256) void k_worklist_keys(const uint32_t* ranges, const uint32_t* work,
+                                                       uint64_t total_tiles, uint32_t* keys) {
     const uint64_t t = (uint64_t)blockIdx.x * 256 + threadIdx.x;
     if (t >= total_tiles) return;
-    const uint32_t len = ranges[2 * t + 1] - ranges[2 * t];  // list length as listed
+    const uint32_t len = work ? work[t] : ranges[2 * t + 1] - ranges[2 * t];
     keys[t] = 0xFFFFu - (len < 0xFFFFu ? len : 0xFFFFu);
 }
 
@@ -954,9 +956,10 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t value, uint64_t count, hipStrea
     return hipGetLastError();
 }
 
-hipError_t launch_worklist_keys(const uint32_t* ranges, uint64_t total_tiles, uint32_t* keys, hipStream_t stream) {
+hipError_t launch_worklist_keys(const uint32_t* ranges, const uint32_t* work, uint64_t total_tiles, uint32_t* keys,
+                                hipStream_t stream) {
     if (total_tiles == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_worklist_keys, grid_for(total_tiles), dim3(256), 0, stream, ranges, total_tiles, keys);
+    hipLaunchKernelGGL(k_worklist_keys, grid_for(total_tiles), dim3(256), 0, stream, ranges, work, total_tiles, keys);
     return hipGetLastError();
 }
 

@@ -51,6 +51,7 @@ struct RenderArgs {
     const uint32_t* inst_base;
     uint32_t n_items;  // number of work items (tiles) in the worklist
     int batch;         // records staged in LDS per round (one-wave renderers: 32 or 64)
+    uint32_t* tile_work;  // forward: list positions each tile evaluated (nullable)
     // forward outputs / backward inputs
     float* image;
     float* final_T;
@@ -176,7 +177,8 @@ hipError_t launch_ranges_from_counts(const uint32_t* counts, const uint32_t* sta
                                      const uint32_t* listed, uint32_t* ranges, hipStream_t stream);
 hipError_t launch_set_counters(uint32_t* counters, uint64_t m_cap, hipStream_t stream);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, uint64_t count, hipStream_t stream);
-hipError_t launch_worklist_keys(const uint32_t* ranges, uint64_t total_tiles, uint32_t* keys, hipStream_t stream);
+hipError_t launch_worklist_keys(const uint32_t* ranges, const uint32_t* work, uint64_t total_tiles, uint32_t* keys,
+                                hipStream_t stream);
 // Photometric loss of Eq. 8 (gesr_loss.hip).
 struct LossView {
     int W, H;

@@ -3,7 +3,8 @@
 // Forward: front-to-back alpha blending (Eq. 5 evaluated discretely) of the
 // generalized-exponential falloff exp(-kappa q^(beta/2)) (Eq. 3 in screen
 // space).  One workgroup per (view, tile) work item, taken in worklist order
-// (longest lists first, so the hardware dispatcher schedules greedily by
+// (most work first: the list length, or the positions a previous forward
+// evaluated per tile, so the hardware dispatcher schedules greedily by
 // load); each wave covers an 8x8 pixel block so lanes of a wave see similar
 // footprints.  Splat records are staged through LDS in batches and every lane
 // reads them by broadcast.
@@ -152,8 +153,12 @@ __global__ __launch_bounds__(TW * TH) void k_render_fwd(RenderArgs a) {
     float T = 1.0f, cr = 0.f, cg = 0.f, cb = 0.f;
     uint32_t contrib = 0, listed = 0, hit = 0;
     bool done = !ti.inside;
+    uint32_t stop = ti.r1;  // first list position not evaluated
     for (uint32_t base = ti.r0; base < ti.r1; base += NT) {
-        if (__syncthreads_count(done) == NT) break;
+        if (__syncthreads_count(done) == NT) {
+            stop = base;
+            break;
+        }
         const uint32_t pos = base + threadIdx.x;
         if (pos < ti.r1) stage_record(a.rec, a.val_sorted[pos], st.kappa, sA[threadIdx.x], sB[threadIdx.x], sC[threadIdx.x]);
         __syncthreads();
@@ -184,6 +189,7 @@ __global__ __launch_bounds__(TW * TH) void k_render_fwd(RenderArgs a) {
             }
         }
     }
+    if (a.tile_work && threadIdx.x == 0) a.tile_work[t] = stop - ti.r0;
     if (ti.inside) {
         a.image[ti.img] = fmaf(T, st.bg[0], cr);
         a.image[ti.img + ti.ch] = fmaf(T, st.bg[1], cg);
@@ -352,9 +358,13 @@ __global__ __launch_bounds__(64) void k_render_fwd_wave16(RenderArgs a) {
         }
     };
     fetch(r0);
+    uint32_t stop = r1;  // first list position not evaluated
     for (uint32_t base = r0; base < r1; base += B) {
         const bool all_done = done[0] && done[1] && done[2] && done[3];
-        if (__ballot(!all_done) == 0ull) break;
+        if (__ballot(!all_done) == 0ull) {
+            stop = base;
+            break;
+        }
         if ((int)lane < B && base + lane < r1) {
             sA[lane] = na;
             sB[lane] = make_float4(nb.x, nb.y, 0.5f * nb.z, nb.w);
@@ -393,6 +403,7 @@ __global__ __launch_bounds__(64) void k_render_fwd_wave16(RenderArgs a) {
         }
         __syncthreads();
     }
+    if (a.tile_work && lane == 0) a.tile_work[t] = stop - r0;
     const uint32_t ch = (uint32_t)w.W * (uint32_t)w.H;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {

@@ -113,9 +113,14 @@ class Rasterizer:
     """One rasterizer per (camera set, settings).  Calls enqueue on torch's
     current stream; outputs are freshly allocated device tensors."""
 
-    def __init__(self, cameras, settings: RasterSettings, device: int = 0, store_tile_ids: bool = True):
+    def __init__(self, cameras, settings: RasterSettings, device: int = 0, store_tile_ids: bool = True,
+                 work_order: bool = True):
         """store_tile_ids=False leaves bins["tile_sorted"] out (the renderers
-        read only the ranges and the sorted pair ids)."""
+        read only the ranges and the sorted pair ids).  work_order: the
+        rasterizer keeps a per-tile work buffer that every forward fills (the
+        list positions each tile evaluated) and, once filled, bins with
+        GESR_BIN_WORK_ORDER so the next call starts the longest-running tiles
+        first; results are the same either way."""
         self.lib = _lib.load()
         self.store_tile_ids = store_tile_ids
         self.cameras = list(cameras)
@@ -130,6 +135,9 @@ class Rasterizer:
         self.m_cap_hint = 0
         self.views = [(int(c.width), int(c.height)) for c in self.cameras]
         self.n_pixels = sum(w * h for w, h in self.views)
+        self.work_order = work_order
+        self._tile_work = None  # (tile shape, [T] int32 tensor, filled by a forward)
+        self._work_filled = False
 
     def __del__(self):
         lib = getattr(self, "lib", None)
@@ -169,6 +177,15 @@ class Rasterizer:
         c.rect, c.depth_key = p["rect"].data_ptr(), p["depth_key"].data_ptr()
         return c
 
+    def _work_buffer(self, T: int):
+        """The per-tile work buffer for the current tile shape (a new shape
+        starts an unfilled, zeroed buffer)."""
+        shape = (self.settings.tile_w, self.settings.tile_h, T)
+        if self._tile_work is None or self._tile_work[0] != shape:
+            self._tile_work = (shape, torch.zeros(max(T, 1), dtype=torch.int32, device=self.device))
+            self._work_filled = False
+        return self._tile_work[1]
+
     def alloc_bins(self, n: int, m_cap: int, scratch: bool = True) -> dict:
         sz = self.sizes(n, m_cap)
         T = int(sz.total_tiles)
@@ -177,7 +194,8 @@ class Rasterizer:
                     worklist=self._empty(T, torch.int32), inst_base=self._empty(self.V * n, torch.int32),
                     counters=self._empty(4, torch.int32),
                     scratch=torch.empty(int(sz.bin_scratch_bytes), dtype=torch.uint8, device=self.device)
-                    if scratch else None, scratch_bytes=int(sz.bin_scratch_bytes), total_tiles=T)
+                    if scratch else None, scratch_bytes=int(sz.bin_scratch_bytes), total_tiles=T,
+                    tile_work=self._work_buffer(T) if self.work_order else None)
 
     @staticmethod
     def _bins_c(b) -> _lib.Bins:
@@ -186,6 +204,8 @@ class Rasterizer:
         for k in ("tile_sorted", "val_sorted", "ranges", "worklist", "inst_base", "counters", "scratch"):
             setattr(c, k, b[k].data_ptr() if b[k] is not None else 0)
         c.scratch_bytes = b["scratch"].numel() if b["scratch"] is not None else 0
+        tw = b.get("tile_work")
+        c.tile_work = tw.data_ptr() if tw is not None else 0
         return c
 
     def bin(self, proj: dict, n: int, m_cap: Optional[int] = None, sync: bool = True,
@@ -200,9 +220,12 @@ class Rasterizer:
         fn = self.lib.gesr_bin_static if static_scratch else self.lib.gesr_bin
         while True:
             b = self.alloc_bins(n, m_cap, scratch=not static_scratch)
+            flags = _lib.GESR_BIN_SYNC if sync else 0
+            if b["tile_work"] is not None and self._work_filled:
+                flags |= _lib.GESR_BIN_WORK_ORDER
             m = ctypes.c_uint64(0)
             st = fn(self.ctx, ctypes.byref(self._proj_c(proj)), self.cams_c, self.V, n, ctypes.byref(self.st_c),
-                    ctypes.byref(self._bins_c(b)), _lib.GESR_BIN_SYNC if sync else 0, ctypes.byref(m), _stream())
+                    ctypes.byref(self._bins_c(b)), flags, ctypes.byref(m), _stream())
             if st == _lib.GESR_ERR_CAPACITY and sync and m.value > m_cap:
                 m_cap = int(m.value * 1.05) + 1024
                 continue
@@ -233,6 +256,8 @@ class Rasterizer:
                                                  out["final_T"].data_ptr(), out["n_contrib"].data_ptr(),
                                                  ctypes.byref(cnt) if cnt is not None else None,
                                                  ctypes.byref(chn) if chn is not None else None, _stream()), self.ctx)
+        if bins.get("tile_work") is not None and self._tile_work is not None and bins["tile_work"] is self._tile_work[1]:
+            self._work_filled = True  # later binnings on this stream see the figures
         return out
 
     def alloc_workspace(self, n: int, m_cap: int) -> torch.Tensor:

@@ -39,8 +39,8 @@ def test_struct_layouts_match_header(tmp_path):
 int main(void) {
   printf("%zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(gesr_camera), sizeof(gesr_settings), sizeof(gesr_splats),
          sizeof(gesr_proj), sizeof(gesr_bins), sizeof(gesr_grads), sizeof(gesr_sizes), sizeof(gesr_fwd_counts));
-  printf("%zu %zu %zu\\n", offsetof(gesr_settings, bg), offsetof(gesr_bins, scratch_bytes),
-         offsetof(gesr_camera, campos));
+  printf("%zu %zu %zu %zu\\n", offsetof(gesr_settings, bg), offsetof(gesr_bins, scratch_bytes),
+         offsetof(gesr_camera, campos), offsetof(gesr_bins, tile_work));
   return 0;
 }
 """)
@@ -52,7 +52,8 @@ int main(void) {
     mine = [ctypes.sizeof(t) for t in (_lib.Camera, _lib.Settings, _lib.Splats, _lib.Proj, _lib.Bins, _lib.Grads,
                                        _lib.Sizes, _lib.FwdCounts)]
     assert sizes == mine
-    assert offs == [_lib.Settings.bg.offset, _lib.Bins.scratch_bytes.offset, _lib.Camera.campos.offset]
+    assert offs == [_lib.Settings.bg.offset, _lib.Bins.scratch_bytes.offset, _lib.Camera.campos.offset,
+                    _lib.Bins.tile_work.offset]
 
 
 def _ctx(lib):

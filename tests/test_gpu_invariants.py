@@ -154,6 +154,59 @@ def test_deterministic_bitwise():
         np.testing.assert_array_equal(ga[k], gb[k])
 
 
+@pytest.mark.parametrize("variant,batch,B", [(0, 64, 64), (0, 32, 32), (1, 64, 256)])
+def test_work_order_schedules_only(variant, batch, B):
+    """The forward's per-tile work figure is the list positions its renderer
+    evaluated: the batch (B records) in which the tile's last pixel
+    terminated, read from the per-pixel counts, capped at the list length.  A
+    binning with GESR_BIN_WORK_ORDER orders the worklist by it (decreasing,
+    ties by tile id), and the forward and backward outputs are bit-identical
+    to those of the list-length order."""
+    torch = _torch()
+    scene, st = gi.make_workload(3, n_override=50_000), oracle.Settings()
+    dL = oracle.flat_images(gi.upstream_grads(scene, 7))
+    rast = _rast(scene, st, variant=variant, batch=batch)
+    sp = splats_of(scene)
+    dl = torch.as_tensor(np.asarray(dL, np.float32), device="cuda")
+    outs = []
+    for rep in range(2):
+        f = rast.forward(sp, counts=True)
+        g = rast.render_bwd(sp, f["proj"], f["bins"], f["final_T"], f["n_contrib"], dl, want_grad2d=True)
+        torch.cuda.synchronize()
+        b = f["bins"]
+        T = b["total_tiles"]
+        o = {k: f[k].cpu().numpy().copy() for k in ("image", "final_T", "n_contrib", "n_listed", "n_hit")}
+        o.update({"g_" + k: v.cpu().numpy().copy() for k, v in g.items()})
+        outs.append((o, u32(b["worklist"])[:T].copy(), u32(b["tile_work"])[:T].copy(),
+                     u32(b["ranges"])[:2 * T].reshape(T, 2).copy()))
+    (o0, wl0, work0, rng0), (o1, wl1, work1, rng1) = outs
+    lens = rng0[:, 1].astype(np.int64) - rng0[:, 0]
+    np.testing.assert_array_equal(wl0, np.lexsort((np.arange(T), -np.minimum(lens, 0xFFFF))))
+    # per-tile work from the per-pixel counts (tile-major pixel grid per view)
+    grid, T2 = oracle.tile_grid(scene.cameras, st.tile_w, st.tile_h)
+    assert T2 == T
+    maxl = np.zeros(T, np.int64)
+    base_px, t0 = 0, 0
+    for cam in scene.cameras:
+        W, H = int(cam.width), int(cam.height)
+        tx, ty = -(-W // st.tile_w), -(-H // st.tile_h)
+        nl = np.zeros((ty * st.tile_h, tx * st.tile_w), np.int64)
+        nl[:H, :W] = o0["n_listed"].view(np.uint32)[base_px:base_px + W * H].reshape(H, W)
+        maxl[t0:t0 + tx * ty] = nl.reshape(ty, st.tile_h, tx, st.tile_w).max(axis=(1, 3)).reshape(-1)
+        base_px += W * H
+        t0 += tx * ty
+    expect = np.minimum(lens, B * (-(-maxl // B)))
+    np.testing.assert_array_equal(work0.astype(np.int64), expect)
+    np.testing.assert_array_equal(work1, work0)
+    np.testing.assert_array_equal(wl1, np.lexsort((np.arange(T), -np.minimum(work0.astype(np.int64), 0xFFFF))))
+    assert not np.array_equal(wl1, wl0)
+    np.testing.assert_array_equal(rng1, rng0)
+    for k in o0:
+        np.testing.assert_array_equal(o1[k], o0[k], err_msg=k)
+    log(f"[gpu] work order (variant {variant}, batch {B}): {int((lens > work0).sum())} of {T} tiles stop before "
+        f"their list ends; evaluated {int(work0.sum())} of {int(lens.sum())} listed positions")
+
+
 def test_batched_equals_per_view_bitwise():
     """Tile lists, visit order and the per-pair reduction order of a view do not
     depend on the other views in the batch."""
@@ -395,7 +448,8 @@ def _full_size_run(k):
              tile_rect=np.stack([r[:, 0] & 0xFFFF, r[:, 0] >> 16, r[:, 1] & 0xFFFF, r[:, 1] >> 16], 1).astype(np.int32),
              depth_key=u32(proj["depth_key"])[:VN], M=M, listed=L, tile_sorted=u32(bins["tile_sorted"])[:L],
              val_sorted=u32(bins["val_sorted"])[:L], ranges=u32(bins["ranges"])[:2 * T].reshape(T, 2),
-             worklist=u32(bins["worklist"])[:T], inst_base=u32(bins["inst_base"])[:VN],
+             worklist=u32(bins["worklist"])[:T], tile_work=u32(bins["tile_work"])[:T].copy(),
+             inst_base=u32(bins["inst_base"])[:VN],
              image=f32(f["image"])[:3 * P], final_T=f32(f["final_T"])[:P], n_contrib=u32(f["n_contrib"])[:P],
              n_listed=u32(f["n_listed"])[:P], n_hit=u32(f["n_hit"])[:P])
     return scene, st, g, (rast, sp, proj, bins, f)
@@ -434,9 +488,11 @@ def test_full_size_workload(k):
     band = oracle.bin_band(N, scene.cameras, g["tile_rect"], g["tiles_touched"], rec, st)
     cmp = compare_lists(g["val_sorted"], g["tile_sorted"], g["ranges"], keys, vals, ranges, band)
     del keys
-    lens = g["ranges"][:, 1].astype(np.int64) - g["ranges"][:, 0]
-    T = len(lens)
-    np.testing.assert_array_equal(g["worklist"], np.lexsort((np.arange(T), -np.minimum(lens, 0xFFFF))))
+    T = len(g["ranges"])
+    # the run's rasterizer has measured each tile's work in an earlier forward:
+    # the worklist is ordered by it (the forward wrote the same figures again)
+    np.testing.assert_array_equal(g["worklist"],
+                                  np.lexsort((np.arange(T), -np.minimum(g["tile_work"].astype(np.int64), 0xFFFF))))
     base = np.concatenate([[0], np.cumsum(g["tiles_touched"].astype(np.int64))[:-1]])
     np.testing.assert_array_equal(g["inst_base"], base)
     assert int(g["tiles_touched"].astype(np.int64).sum()) == g["M"] >= g["listed"]
