@@ -505,74 +505,107 @@ __global__ __launch_bounds__(256) void k_project_bwd(ProjectBwdArgs a) {
     for (int k = 0; k < K * 3; ++k) a.g_sh[(size_t)k * n + i] = gsh[k];
 }
 
-// kSegLanes lanes (an aligned DPP group) per (view, splat).  The pair's
-// instance slots are contiguous (inst_base[vi] + j); lane l of the group takes
-// the blocks of 32 instances m = l, l + kSegLanes, ... and, in ascending
-// order, adds the partials of the block's visited instances (set bits); a
-// fixed DPP tree then adds the group.  The order depends only on the pair's
-// own instances, so a batch of views and views rendered one at a time give
-// identical sums.  Eight lanes: pairs of wide splats (hundreds of instances)
-// set the pace, and fewer lanes serialise their blocks.
+// Segmented sum of the visited partials per (view, splat).  The pair's
+// instance slots are contiguous (inst_base[vi] + j) and are taken in blocks of
+// 32 (one word of visited bits); within a block the set bits' partials are
+// added in ascending slot order.  A pair of at most kSegSmall instances is
+// summed by one lane (a sum per block, the two added at the end); a larger
+// pair by an aligned group of kSegLanes lanes, lane l taking the blocks l,
+// l + kSegLanes, ... in ascending order, then a fixed DPP tree over the group.
+// Both orders give the same float result for the small pairs (the tree adds
+// the other lanes' +0) and depend only on the pair's own instances, so a
+// batch of views and views rendered one at a time give identical sums.  One
+// thread per pair: the small pairs (most of them) keep every lane busy, then
+// each wave hands its large pairs to its eight groups, eight at a time.
 constexpr uint32_t kSegLanes = 8;
+constexpr uint32_t kSegSmall = 64;
+
+// Adds block j0 .. j0 + 31 of the pair (first slot `base`, cnt slots) to acc.
+template <int NP>
+__device__ __forceinline__ void seg_block(const SegReduceArgs& a, uint64_t base, uint32_t cnt, uint32_t j0,
+                                          uint64_t nwords, float (&acc)[NP]) {
+    // visited bits of instances j0 .. j0 + 31 of this pair
+    const uint64_t s0 = base + j0;
+    const uint64_t wi = s0 >> 5;
+    const uint32_t sh = (uint32_t)(s0 & 31u);
+    const uint32_t w0 = wi < nwords ? a.visited[wi] : 0u;
+    const uint32_t w1 = (sh != 0u && wi + 1 < nwords) ? a.visited[wi + 1] : 0u;
+    uint32_t bits = sh != 0u ? (w0 >> sh) | (w1 << (32u - sh)) : w0;
+    if (cnt - j0 < 32u) bits &= (1u << (cnt - j0)) - 1u;
+    // up to four visited partials in flight, then added in ascending order
+    while (bits != 0u) {
+        float4 v[4][3];
+        bool have[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            have[u] = bits != 0u;
+            const uint32_t b = have[u] ? (uint32_t)__builtin_ctz(bits) : 0u;
+            bits &= bits - 1u;
+            const float4* src = reinterpret_cast<const float4*>(a.partials + (s0 + b) * kPartialStride);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) v[u][k] = have[u] ? src[k] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (have[u]) {
+                const float t[12] = {v[u][0].x, v[u][0].y, v[u][0].z, v[u][0].w, v[u][1].x, v[u][1].y,
+                                     v[u][1].z, v[u][1].w, v[u][2].x, v[u][2].y, v[u][2].z, v[u][2].w};
+#pragma unroll
+                for (int k = 0; k < NP; ++k) acc[k] += t[k];
+            }
+    }
+}
+
+template <int NP>
+__device__ __forceinline__ void seg_write(const SegReduceArgs& a, uint64_t vi, const float (&acc)[NP]) {
+    float4* out = reinterpret_cast<float4*>(a.grad2d + (size_t)vi * GESR_GRAD2D_FLOATS);
+    out[0] = make_float4(acc[0], acc[1], acc[2], acc[3]);
+    out[1] = make_float4(acc[4], acc[5], acc[6], acc[7]);
+    out[2] = make_float4(acc[8], acc[9], acc[10], 0.0f);
+}
 
 __global__ __launch_bounds__(256) void k_seg_reduce(SegReduceArgs a) {
     constexpr int NP = GESR_PARTIAL_FLOATS + 1;  // the ten terms and dz
     constexpr uint32_t L = kSegLanes;
-    const uint64_t vi = ((uint64_t)blockIdx.x * 256u + threadIdx.x) / L;
-    const uint32_t lane = __lane_id() & (L - 1);
+    const uint64_t vi = (uint64_t)blockIdx.x * 256u + threadIdx.x;
+    const uint32_t lane = __lane_id();
     const bool valid = vi < a.vn;
-    float acc[NP];
-#pragma unroll
-    for (int k = 0; k < NP; ++k) acc[k] = 0.f;
-    bool any = false;
     const uint32_t cnt = valid ? a.tiles_touched[vi] : 0u;
-    if (cnt > 0) {
-        const uint64_t base = a.inst_base[vi];
-        const uint64_t nwords = (a.m_cap + 31) / 32;
-        for (uint32_t j0 = lane * 32u; j0 < cnt; j0 += L * 32u) {
-            // visited bits of instances j0 .. j0 + 31 of this pair
-            const uint64_t s0 = base + j0;
-            const uint64_t wi = s0 >> 5;
-            const uint32_t sh = (uint32_t)(s0 & 31u);
-            const uint32_t w0 = wi < nwords ? a.visited[wi] : 0u;
-            const uint32_t w1 = (sh != 0u && wi + 1 < nwords) ? a.visited[wi + 1] : 0u;
-            uint32_t bits = sh != 0u ? (w0 >> sh) | (w1 << (32u - sh)) : w0;
-            if (cnt - j0 < 32u) bits &= (1u << (cnt - j0)) - 1u;
-            // up to four visited partials in flight, then added in ascending order
-            while (bits != 0u) {
-                float4 v[4][3];
-                bool have[4];
+    const uint64_t base = valid ? a.inst_base[vi] : 0u;
+    const uint64_t nwords = (a.m_cap + 31) / 32;
+    const bool small = cnt <= kSegSmall;
+    if (valid && small) {
+        float acc0[NP], acc1[NP];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    have[u] = bits != 0u;
-                    const uint32_t b = have[u] ? (uint32_t)__builtin_ctz(bits) : 0u;
-                    bits &= bits - 1u;
-                    const float4* src = reinterpret_cast<const float4*>(a.partials + (s0 + b) * kPartialStride);
+        for (int k = 0; k < NP; ++k) acc0[k] = acc1[k] = 0.f;
+        if (cnt > 0) seg_block<NP>(a, base, cnt, 0u, nwords, acc0);
+        if (cnt > 32) seg_block<NP>(a, base, cnt, 32u, nwords, acc1);
 #pragma unroll
-                    for (int k = 0; k < 3; ++k) v[u][k] = have[u] ? src[k] : make_float4(0.f, 0.f, 0.f, 0.f);
-                }
-#pragma unroll
-                for (int u = 0; u < 4; ++u)
-                    if (have[u]) {
-                        const float t[12] = {v[u][0].x, v[u][0].y, v[u][0].z, v[u][0].w, v[u][1].x, v[u][1].y,
-                                             v[u][1].z, v[u][1].w, v[u][2].x, v[u][2].y, v[u][2].z, v[u][2].w};
-#pragma unroll
-                        for (int k = 0; k < NP; ++k) acc[k] += t[k];
-                    }
-                any = true;
-            }
-        }
+        for (int k = 0; k < NP; ++k) acc0[k] += acc1[k];
+        seg_write<NP>(a, vi, acc0);
     }
-    if (__ballot(any) != 0ull) {
+    // large pairs of this wave, eight at a time (group g = lane / L takes the
+    // g-th remaining one)
+    uint64_t large = __ballot(valid && !small);
+    const uint64_t wave0 = vi - lane;
+    const uint32_t g = lane / L, l = lane % L;
+    while (large != 0ull) {
+        uint64_t m = large;
+        for (uint32_t k = 0; k < g; ++k) m &= m - 1u;
+        const bool mine = m != 0ull;
+        const uint32_t pick = mine ? (uint32_t)__builtin_ctzll(m) : 0u;
+        const uint32_t c = (uint32_t)__shfl((int)cnt, (int)pick, 64);
+        const uint64_t b0 = (uint64_t)(uint32_t)__shfl((int)(uint32_t)base, (int)pick, 64);
+        float acc[NP];
+#pragma unroll
+        for (int k = 0; k < NP; ++k) acc[k] = 0.f;
+        if (mine)
+            for (uint32_t j0 = l * 32u; j0 < c; j0 += L * 32u) seg_block<NP>(a, b0, c, j0, nwords, acc);
 #pragma unroll
         for (int k = 0; k < NP; ++k) acc[k] = group_sum<L>(acc[k]);
-    }
-    // groups without visited instances hold zeros; the last lane of each group writes
-    if (valid && lane == L - 1) {
-        float4* out = reinterpret_cast<float4*>(a.grad2d + (size_t)vi * GESR_GRAD2D_FLOATS);
-        out[0] = make_float4(acc[0], acc[1], acc[2], acc[3]);
-        out[1] = make_float4(acc[4], acc[5], acc[6], acc[7]);
-        out[2] = make_float4(acc[8], acc[9], acc[10], 0.0f);
+        if (mine && l == L - 1) seg_write<NP>(a, wave0 + pick, acc);
+#pragma unroll
+        for (uint32_t k = 0; k < 64u / L; ++k) large &= large - 1u;
     }
 }
 
@@ -592,8 +625,7 @@ hipError_t launch_project(const ProjectArgs& a, int sh_degree, hipStream_t strea
 
 hipError_t launch_seg_reduce(const SegReduceArgs& a, hipStream_t stream) {
     if (a.vn == 0) return hipSuccess;
-    const uint64_t threads = (uint64_t)a.vn * kSegLanes;
-    hipLaunchKernelGGL(k_seg_reduce, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, stream, a);
+    hipLaunchKernelGGL(k_seg_reduce, dim3((unsigned)(((uint64_t)a.vn + 255) / 256)), dim3(256), 0, stream, a);
     return hipGetLastError();
 }
 

@@ -383,22 +383,26 @@ __global__ __launch_bounds__(64) void k_render_fwd_wave16(RenderArgs a) {
                 const float qq = ges_q(ra, rb.x, px[q], py[q], f);
                 if (COUNT) ++listed[q];
                 if (qq > rb.w) continue;  // beyond the alpha_min footprint
+                // Inside the footprint alpha almost never falls below alpha_min
+                // and a pixel terminates once: both decisions are selects, the
+                // state changing only where the fragment composites (a zero
+                // weight leaves the sums as they are: colours and depths of
+                // kept records are finite and non-negative).
                 ges_alpha(qq, rb.z, rb.y, st, amax, f);
-                if (f.alpha < st.alpha_min) continue;
-                if (COUNT) ++hit[q];
+                const bool ok = !(f.alpha < st.alpha_min);
+                if (COUNT) hit[q] += ok ? 1u : 0u;
                 const float Tn = T[q] * (1.0f - f.alpha);
-                if (Tn < st.t_min) {
-                    done[q] = true;
-                    continue;
-                }
+                const bool stop = ok && Tn < st.t_min;
+                const bool acc = ok && !stop;
+                done[q] = stop;
                 const float4 rc = sC[j];
-                const float wgt = f.alpha * T[q];
+                const float wgt = acc ? f.alpha * T[q] : 0.0f;
                 cr[q] = fmaf(rc.x, wgt, cr[q]);
                 cg[q] = fmaf(rc.y, wgt, cg[q]);
                 cb[q] = fmaf(rc.z, wgt, cb[q]);
                 if (EXT) cd[q] = fmaf(rc.w, wgt, cd[q]);  // rc.w: the splat's depth
-                T[q] = Tn;
-                contrib[q] = base + (uint32_t)j + 1u - r0;
+                T[q] = acc ? Tn : T[q];
+                contrib[q] = acc ? base + (uint32_t)j + 1u - r0 : contrib[q];
             }
         }
         __syncthreads();
@@ -522,30 +526,49 @@ __global__ __launch_bounds__(64) void k_render_bwd_wave16(RenderArgs a) {
             bool act = false;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                if (prel >= nc[q]) continue;
                 Fragment f;
                 const float qq = ges_q(ra, rb.x, pxb + (float)((q & 1) * 8), pyb + (float)((q >> 1) * 8), f);
-                if (qq > rb.w) continue;
+                if (prel >= nc[q] || qq > rb.w) continue;  // behind the pixel's last or beyond the footprint
+                // Inside the footprint alpha almost never falls below alpha_min,
+                // the alpha cap and a centred pixel are rarer still: those
+                // decisions are selects (a zeroed term leaves the sums as they
+                // are), so the wave takes one branch per quadrant.
                 ges_alpha(qq, rb.z, rb.y, st, amax, f);
-                if (f.alpha < st.alpha_min) continue;
-                act = true;
+                const bool ok = !(f.alpha < st.alpha_min);
+                act = act || ok;
                 const float Tk = T[q] * hw_rcp(1.0f - f.alpha);
-                const float aT = f.alpha * Tk;
+                const float aT = ok ? f.alpha * Tk : 0.0f;
                 gr[7] += aT * g0[q];
                 gr[8] += aT * g1[q];
                 gr[9] += aT * g2[q];
                 float dLda = Tk * ((rc.x - Br[q]) * g0[q] + (rc.y - Bg[q]) * g1[q] + (rc.z - Bb[q]) * g2[q]);
-                Br[q] = fmaf(f.alpha, rc.x - Br[q], Br[q]);
-                Bg[q] = fmaf(f.alpha, rc.y - Bg[q], Bg[q]);
-                Bb[q] = fmaf(f.alpha, rc.z - Bb[q], Bb[q]);
+                const float al = ok ? f.alpha : 0.0f;  // a skipped fragment leaves the colour behind as it is
+                Br[q] = fmaf(al, rc.x - Br[q], Br[q]);
+                Bg[q] = fmaf(al, rc.y - Bg[q], Bg[q]);
+                Bb[q] = fmaf(al, rc.z - Bb[q], Bb[q]);
                 if (EXT) {
                     dLda += Tk * ((z - BD[q]) * gD[q] + (1.0f - BA[q]) * gA[q]);
                     gz += aT * gD[q];
-                    BD[q] = fmaf(f.alpha, z - BD[q], BD[q]);
-                    BA[q] = fmaf(f.alpha, 1.0f - BA[q], BA[q]);
+                    BD[q] = fmaf(al, z - BD[q], BD[q]);
+                    BA[q] = fmaf(al, 1.0f - BA[q], BA[q]);
                 }
-                T[q] = Tk;
-                add_fragment_grad(f, ra, rb, rc.w, dLda, st.alpha_max, c2, gr);
+                T[q] = ok ? Tk : T[q];
+                // add_fragment_grad with its two early exits as selects
+                const bool live = ok && !(f.oG > st.alpha_max);
+                const float dl = live ? dLda : 0.0f;
+                gr[5] = fmaf(dl, f.G, gr[5]);
+                const bool geo = live && f.q > 1e-30f;
+                const float X = geo ? dl * f.oG * f.P : 0.0f;
+                const float lq = geo ? f.l2q : 0.0f;
+                gr[6] = fmaf(X * lq, c2, gr[6]);
+                const float d2 = X * rc.w * hw_rcp(geo ? f.q : 1.0f);
+                const float tq = d2 * f.t, wq = d2 * f.w;
+                gr[0] = fmaf(-tq, ra.z, gr[0]);
+                gr[1] = fmaf(-tq, ra.w, gr[1]);
+                gr[1] = fmaf(-wq, rb.x, gr[1]);
+                gr[2] = fmaf(tq, f.dx, gr[2]);
+                gr[3] = fmaf(tq, f.dy, gr[3]);
+                gr[4] = fmaf(wq, f.dy, gr[4]);
             }
             if (__ballot(act) != 0ull) {
                 const float tot = wave_sum10(gr, lane);
