@@ -12,8 +12,10 @@ Printed: one JSON line with Mpix/s (pixels of all views per second of
 fwd+bwd), the per-view comparison, per-stage times from HIP events on the
 launch stream, the roofline of the dominant kernel, the FP64 oracle timed
 on the host cores over a bounded sample, a training-step leg (the same
-graph followed by the fused Adam step, with the Adam kernel's HBM roofline)
-and a surface-regulariser leg (neighbour lists, losses and gradients).
+graph followed by the fused Adam step, with the Adam kernel's HBM roofline),
+a surface-points leg on the sphere-shell workload (level-set points along
+depth-map rays) and a surface-regulariser leg (neighbour lists, losses and
+gradients); then every other workload's batched step in the same run.
 """
 from __future__ import annotations
 
@@ -94,8 +96,10 @@ def parse_args():
     p.add_argument("--no-autotune", action="store_true",
                    help="keep --tile/--batch instead of the autotuner's choice")
     p.add_argument("--cpu-sample-views", default="0,1,2,3,4,5")
-    p.add_argument("--surface", type=int, default=0,
-                   help="also time level-set surface points for this many covered pixels (32 samples per ray)")
+    p.add_argument("--surface", type=int, default=65536,
+                   help="time level-set surface points for this many covered pixels (32 samples per ray; 0: skip)")
+    p.add_argument("--surface-workload", type=int, default=2,
+                   help="workload of the surface-points leg (default: the sphere shells)")
     p.add_argument("--no-train", action="store_true",
                    help="skip the training-step leg (fwd+bwd graph followed by the fused Adam step)")
     p.add_argument("--no-gsr", action="store_true",
@@ -438,53 +442,7 @@ def main():
                 "algorithmic_slots_per_launch": int(kern[dom])}
 
     # ------------------------------------------------------ surface points
-    surface = None
-    if args.surface > 0:
-        if (rs.tile_w, rs.tile_h, rs.variant) != (16, 16, 0):
-            log("[bench] --surface needs the 16x16 one-wave renderer; skipped")
-        else:
-            K_S = 32
-            fx = rast.forward(sp, sync=True, channels=True)
-            alpha_h = fx["alpha"].cpu().numpy()
-            cov = np.nonzero(alpha_h >= 0.5)[0]
-            pick = np.random.default_rng([k, 79]).choice(cov, min(args.surface, cov.size), replace=False)
-            # grouped by tile, so the rays a wave serves share their tile's list
-            cams = scene.cameras
-            widths = np.array([c.width for c in cams])
-            pbase = np.cumsum([0] + [c.width * c.height for c in cams])
-            tx_n = (widths + rs.tile_w - 1) // rs.tile_w
-            tbase = np.cumsum([0] + [int(tx_n[j]) * ((c.height + rs.tile_h - 1) // rs.tile_h)
-                                     for j, c in enumerate(cams)])
-            vv = np.searchsorted(pbase, pick, side="right") - 1
-            loc = pick - pbase[vv]
-            tile = tbase[vv] + (loc // widths[vv]) // rs.tile_h * tx_n[vv] + (loc % widths[vv]) // rs.tile_w
-            pick = pick[np.argsort(tile, kind="stable")]
-            pix_t = torch.as_tensor(pick.astype(np.int32), device="cuda")
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            run_s = lambda: rast.surface_points(sp, fx["proj"], fx["bins"], fx["depth"], fx["alpha"], pix_t,  # noqa
-                                                n_samples=K_S)
-            sres = run_s()
-            for _ in range(args.warmup):
-                run_s()
-            torch.cuda.synchronize()
-            e0.record()
-            for _ in range(args.steps):
-                run_s()
-            e1.record()
-            torch.cuda.synchronize()
-            s_ms = e0.elapsed_time(e1) / args.steps
-            cand = int(sres["n_candidates"].to(torch.int64).sum().item())
-            valid = float(sres["points"][:, 3].mean().item())
-            s_ach = cand * K_S * SURFACE_SLOTS_PER_SAMPLE / (s_ms * 1e-3) / 1e12
-            surface = {"rays": int(pick.size), "samples_per_ray": K_S, "ms": round(s_ms, 4),
-                       "rays_per_s": round(pick.size / (s_ms * 1e-3), 1), "valid_fraction": round(valid, 4),
-                       "candidates_per_ray": round(cand / max(pick.size, 1), 1),
-                       "roofline": {"bound": "alu", "kernel": "surface_points", "achieved": round(s_ach, 3),
-                                    "peak": round(VALU_SLOTS_PER_S / 1e12, 3), "unit": "Tslot/s",
-                                    "frac": round(s_ach / (VALU_SLOTS_PER_S / 1e12), 4),
-                                    "algorithmic_slots_per_launch": cand * K_S * SURFACE_SLOTS_PER_SAMPLE}}
-            log(f"[bench] surface points: {pick.size} rays in {s_ms:.3f} ms, valid {valid:.3f}")
-            del fx
+    surface = surface_leg(args) if args.surface > 0 else None
 
     # ------------------------------------------- training step with Adam
     train = None
@@ -669,6 +627,66 @@ def gsr_leg(args, scene, sp, rs):
             "roofline": {"bound": "hbm", "kernel": "gsr (frames + loss + gather + sum)", "achieved": round(ach / 1e9, 1),
                          "peak": HBM_BYTES_PER_S / 1e9, "unit": "GB/s", "frac": round(ach / HBM_BYTES_PER_S, 4),
                          "traffic": None, "algorithmic_bytes_per_launch": per_splat * n}}
+
+
+def surface_leg(args):
+    """Level-set surface points (the mesh-extraction sampling step) on the
+    workload --surface-workload (default: the sphere shells, where the density
+    of the opaque shells crosses the 0.3 level at most covered pixels): the
+    extended forward gives the depth and alpha maps, then --surface rays at
+    pixels with alpha >= 0.5, grouped by tile, K = 32 samples each."""
+    import numpy as np
+    import torch
+
+    import gesr_inputs as gi
+    from paper_2411_09156_amd import Rasterizer, RasterSettings, Splats
+    k = args.surface_workload
+    scene = gi.make_workload(k)
+    log(f"[bench] surface points on workload {k} ({scene.name})")
+    rs = RasterSettings(sh_degree=scene.sh_degree, tile_w=16, tile_h=16, variant=0)
+    sp = Splats.from_aos(scene.means, scene.scales, scene.quats, scene.opacities, scene.betas, scene.sh)
+    rast = Rasterizer(scene.cameras, rs, store_tile_ids=False)
+    K_S = 32
+    fx = rast.forward(sp, sync=True, channels=True)
+    alpha_h = fx["alpha"].cpu().numpy()
+    cov = np.nonzero(alpha_h >= 0.5)[0]
+    pick = np.random.default_rng([k, 79]).choice(cov, min(args.surface, cov.size), replace=False)
+    # grouped by tile, so the rays a wave serves share their tile's list
+    cams = scene.cameras
+    widths = np.array([c.width for c in cams])
+    pbase = np.cumsum([0] + [c.width * c.height for c in cams])
+    tx_n = (widths + rs.tile_w - 1) // rs.tile_w
+    tbase = np.cumsum([0] + [int(tx_n[j]) * ((c.height + rs.tile_h - 1) // rs.tile_h) for j, c in enumerate(cams)])
+    vv = np.searchsorted(pbase, pick, side="right") - 1
+    loc = pick - pbase[vv]
+    tile = tbase[vv] + (loc // widths[vv]) // rs.tile_h * tx_n[vv] + (loc % widths[vv]) // rs.tile_w
+    pick = pick[np.argsort(tile, kind="stable")]
+    pix_t = torch.as_tensor(pick.astype(np.int32), device="cuda")
+
+    def run_s():
+        return rast.surface_points(sp, fx["proj"], fx["bins"], fx["depth"], fx["alpha"], pix_t, n_samples=K_S)
+    sres = run_s()
+    for _ in range(args.warmup):
+        run_s()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        run_s()
+    e1.record()
+    torch.cuda.synchronize()
+    s_ms = e0.elapsed_time(e1) / args.steps
+    cand = int(sres["n_candidates"].to(torch.int64).sum().item())
+    valid = float(sres["points"][:, 3].mean().item())
+    s_ach = cand * K_S * SURFACE_SLOTS_PER_SAMPLE / (s_ms * 1e-3) / 1e12
+    log(f"[bench] surface points: {pick.size} rays in {s_ms:.3f} ms, valid {valid:.3f}")
+    return {"workload": scene.name, "rays": int(pick.size), "covered_pixels": int(cov.size),
+            "samples_per_ray": K_S, "ms": round(s_ms, 4), "rays_per_s": round(pick.size / (s_ms * 1e-3), 1),
+            "valid_fraction": round(valid, 4), "candidates_per_ray": round(cand / max(pick.size, 1), 1),
+            "roofline": {"bound": "alu", "kernel": "surface_points", "achieved": round(s_ach, 3),
+                         "peak": round(VALU_SLOTS_PER_S / 1e12, 3), "unit": "Tslot/s",
+                         "frac": round(s_ach / (VALU_SLOTS_PER_S / 1e12), 4),
+                         "algorithmic_slots_per_launch": cand * K_S * SURFACE_SLOTS_PER_SAMPLE}}
 
 
 def cpu_info():
