@@ -479,6 +479,12 @@ __device__ __forceinline__ void load_item(const IsArgs& a, uint32_t idx, uint32_
     }
 }
 
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t x) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) x += (uint32_t)__shfl_xor((int)x, d, 64);
+    return x;
+}
+
 __device__ __forceinline__ int wave_min_i(int x) {
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) x = min(x, __shfl_xor(x, d, 64));
@@ -532,6 +538,10 @@ __device__ __forceinline__ void wave_prefix_row(int* row) {
 // LDS grouped by bucket (at most IS_STAGE at a time, bucket windows) and
 // writes each bucket's run contiguously.
 constexpr int IS_STAGE = 16384;
+// VALU instructions, roughly, of one staging step: a (bucket, word) ballot, and
+// a pass over 64 expanded entries (owner search, seven-bit match, rank)
+constexpr int IS_BALLOT_COST = 8;
+constexpr int IS_MATCH_COST = 128;
 
 template <int LEVEL, int MODE>
 __global__ __launch_bounds__(IS_THREADS) __attribute__((amdgpu_waves_per_eu(8))) void k_is_chunks(IsArgs a) {
@@ -652,7 +662,66 @@ __global__ __launch_bounds__(IS_THREADS) __attribute__((amdgpu_waves_per_eu(8)))
                 const int b1 = l;
                 const uint32_t off0 = s_ls[b0];
                 const int bs = max(lo_w, b0), be = min(hi_w, b1 - 1);
-                if (bs <= be) {
+                // Two ways to stage the wave's entries of buckets [bs, be], giving the
+                // same positions: a ballot per (bucket, word) over the span (cheap when
+                // items cover much of it), or one pass per 64 entries of the expanded
+                // (item, bucket) list with ranks among equal buckets from a 7-bit match
+                // (cheap when items cover little of a wide span).  The cheaper by
+                // instruction count is taken, wave by wave.
+                // entries of each word in [bs, be]: item u covers [max(lo, bs), min(hi, be)]
+                auto entries = [&](int u, int& first) {
+                    first = max(lo[u], bs);
+                    const int h = min(hi[u], be);
+                    return any[u] && first <= h ? (uint32_t)(h - first + 1) : 0u;
+                };
+                // the chunk's mean entries per item against the wave's span: a pass
+                // over 64 entries costs about IS_MATCH_COST, a bucket of the ballot
+                // loop IS_IPL * IS_BALLOT_COST for the wave's 64 * IS_IPL items
+                const uint32_t chunk_entries = s_ls[g.width];
+                const bool by_match =
+                    bs <= be && (uint64_t)chunk_entries * IS_MATCH_COST <
+                                    (uint64_t)IS_CHUNK * 64u * IS_BALLOT_COST * (uint32_t)(be - bs + 1) / 64u;
+                if (by_match) {
+#pragma unroll
+                    for (int u = 0; u < IS_IPL; ++u) {
+                        int st0;
+                        const uint32_t nn = entries(u, st0);
+                        const uint32_t inc = wave_inclusive_scan(nn);
+                        const uint32_t ex = inc - nn;
+                        const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)inc, 63);
+                        const uint32_t val = LEVEL == 1 ? item0 + 64u * (uint32_t)u : p[u];
+                        for (uint32_t e0 = 0; e0 < tot; e0 += 64) {
+                            const uint32_t e = e0 + lane;
+                            const bool valid = e < tot;
+                            // owner: the last lane whose first entry is at or before e
+                            int own = 0;
+#pragma unroll
+                            for (int step = 32; step >= 1; step >>= 1) {
+                                const uint32_t exc = (uint32_t)__shfl((int)ex, own + step, 64);
+                                own = exc <= e ? own + step : own;
+                            }
+                            const uint32_t ex_o = (uint32_t)__shfl((int)ex, own, 64);
+                            const int b = __shfl(st0, own, 64) + (int)(e - ex_o);
+                            const uint32_t v = (uint32_t)__shfl((int)val, own, 64);
+                            // lanes of this pass in the same bucket, by its seven bits
+                            const uint32_t rel = valid ? (uint32_t)(b - b0) : 0u;
+                            uint64_t peers = __builtin_amdgcn_ballot_w64(valid);
+#pragma unroll
+                            for (int k = 0; k < 7; ++k) {
+                                const bool bit = (rel >> k) & 1u;
+                                const uint64_t m = __builtin_amdgcn_ballot_w64(valid && bit);
+                                peers &= bit ? m : ~m;
+                            }
+                            const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
+                                (uint32_t)(peers >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)peers, 0u));
+                            if (valid) {
+                                const uint32_t run = (uint32_t)s_cnt[wave][b];
+                                s_stage[s_ls[b] - off0 + run + rank] = v;
+                                if (rank == 0) s_cnt[wave][b] = (int)(run + (uint32_t)__popcll(peers));
+                            }
+                        }
+                    }
+                } else if (bs <= be) {
                     // stage offsets of buckets bs.., two per lane, read back with readlane;
                     // branch-free: every lane writes, those off the bucket to their own
                     // spare slot
