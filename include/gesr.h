@@ -118,7 +118,8 @@ typedef struct {
  *        q = (L00 dx + L10 dy)^2 + (L11 dy)^2; qmax = largest q with
  *        alpha >= alpha_min, padded by 2^-10; rgb after the clamp at 0)
  *  tiles_touched[V*n]: tiles covered (0 = culled)
- *  rect[V*n][2]: inclusive tile rectangle (tx0 | ty0 << 16, tx1 | ty1 << 16)
+ *  rect[V*n][2]: inclusive tile rectangle (tx0 | ty0 << 16, tx1 | ty1 << 16);
+ *      (0xFFFFFFFF, 0) for a culled pair
  *  depth_key[V*n]: bit pattern of the float32 camera depth. */
 typedef struct {
     float* rec;

@@ -449,7 +449,7 @@ gesr_status bin_impl(gesr_ctx* ctx, const gesr_proj* proj, const gesr_camera* ca
     // 4. row lists: every pair in the rows its rectangle covers (level 1), each
     //    entry with the columns its ellipse reaches in that row
     GESR_TRY(hip_check(ctx,
-                       launch_gather_rects(order_vd, proj->tiles_touched, proj->rect, proj->rec, g.vn, s.srect,
+                       launch_gather_rects(order_vd, proj->rect, proj->rec, g.vn, s.srect,
                                            s.sell, strm),
                        "rectangles"));
     IsArgs ia;

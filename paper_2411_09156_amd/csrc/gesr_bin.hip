@@ -353,14 +353,16 @@ __device__ __forceinline__ uint32_t row_columns(const float4& e0, const float4& 
     return (uint32_t)c0 | ((uint32_t)c1 << 16);
 }
 
-__global__ __launch_bounds__(256) void k_gather_rects(const uint32_t* order, const uint32_t* tiles_touched,
-                                                      const uint32_t* rect, const float* rec, uint64_t count,
-                                                      uint2* out, float4* ell) {
+// Culled pairs carry the rectangle (0xFFFFFFFF, 0), which no rectangle has
+// (its corners are tile indices below 2^16).
+__global__ __launch_bounds__(256) void k_gather_rects(const uint32_t* order, const uint32_t* rect, const float* rec,
+                                                      uint64_t count, uint2* out, float4* ell) {
     const uint64_t k = (uint64_t)blockIdx.x * 256 + threadIdx.x;
     if (k >= count) return;
     const uint32_t p = order[k];
-    const bool touched = tiles_touched[p] != 0;
-    out[k] = touched ? reinterpret_cast<const uint2*>(rect)[p] : make_uint2(0xFFFFFFFFu, 0u);
+    const uint2 r = reinterpret_cast<const uint2*>(rect)[p];
+    const bool touched = r.x != 0xFFFFFFFFu;
+    out[k] = r;
     if (ell != nullptr) {
         float4 e0 = make_float4(0.f, 0.f, 0.f, 0.f), e1 = e0;
         if (touched) row_ellipse(rec, p, e0, e1);
@@ -940,11 +942,10 @@ hipError_t radix_sort(const uint32_t* keys_in, const uint32_t* vals_in, uint64_t
     return hipSuccess;
 }
 
-hipError_t launch_gather_rects(const uint32_t* order, const uint32_t* tiles_touched, const uint32_t* rect,
-                               const float* rec, uint64_t count, uint2* out, float4* ell, hipStream_t stream) {
+hipError_t launch_gather_rects(const uint32_t* order, const uint32_t* rect, const float* rec, uint64_t count,
+                               uint2* out, float4* ell, hipStream_t stream) {
     if (count == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_gather_rects, grid_for(count), dim3(256), 0, stream, order, tiles_touched, rect, rec, count,
-                       out, ell);
+    hipLaunchKernelGGL(k_gather_rects, grid_for(count), dim3(256), 0, stream, order, rect, rec, count, out, ell);
     return hipGetLastError();
 }
 

@@ -322,7 +322,7 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs a) {
             rec[1] = zero;
             rec[2] = zero;
             a.tiles_touched[vi] = 0u;
-            reinterpret_cast<uint2*>(a.rect)[vi] = make_uint2(0u, 0u);
+            reinterpret_cast<uint2*>(a.rect)[vi] = make_uint2(0xFFFFFFFFu, 0u);  // culled: no rectangle
             a.depth_key[vi] = 0xFFFFFFFFu;
         }
     }
