@@ -440,7 +440,7 @@ __global__ __launch_bounds__(128) void k_gsr_loss(GsrArgs a) {
         if (with_part)
             for (int s = 0; s < K; ++s) {
                 if (nb_at(s) >= (uint32_t)a.n) continue;  // padding slots have no record
-                for (int c = 0; c < GSR_PARTIAL_FLOATS / 4; ++c)
+                for (int c = 0; c < GSR_PARTIAL_STRIDE / 4; ++c)
                     reinterpret_cast<float4*>(rec_at(s))[c] = make_float4(0.f, 0.f, 0.f, 0.f);
             }
         a.sample_out[(size_t)j * 4 + 0] = 0.f;
@@ -621,6 +621,9 @@ __global__ __launch_bounds__(128) void k_gsr_loss(GsrArgs a) {
         o4[0] = make_float4(g_mu[0], g_mu[1], g_mu[2], f.phi * g_sig[0]);
         o4[1] = make_float4(f.phi * g_sig[1], f.phi * g_sig[2], g_q[0], g_q[1]);
         o4[2] = make_float4(g_q[2], g_q[3], g_o, g_beta);
+        // the whole 64-byte record, so that the cache takes the write without
+        // reading the line first
+        o4[3] = make_float4(0.f, 0.f, 0.f, 0.f);
     }
 }
 #undef nb_at
