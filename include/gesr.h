@@ -46,7 +46,7 @@ typedef enum {
 } gesr_status;
 
 #define GESR_MAX_VIEWS 32
-#define GESR_REC_FLOATS 12    /* floats per projected record */
+#define GESR_REC_FLOATS 16    /* floats per projected record (one 64-byte line) */
 #define GESR_PARTIAL_FLOATS 10 /* colour and footprint terms of a gradient partial (du .. db) */
 #define GESR_GRAD2D_FLOATS 12  /* floats per grad2d row and per instance partial: the ten
                                   terms, dz (depth channel, 0 without it) and a zero pad */
@@ -112,11 +112,14 @@ typedef struct {
 } gesr_splats;
 
 /* Projection outputs, DEVICE, caller-allocated ([V * n] entries each):
- *  rec[V*n][12]: u, v, L00, L10, L11, opacity, beta, qmax, r, g, b, depth
+ *  rec[V*n][16]: u, v, L00, L10, L11, opacity, beta, qmax, r, g, b, depth,
+ *       then the two words of rect[] (bit patterns) and two zero words
  *       (the conic Sigma'^-1 = [[A, B], [B, C]] in Cholesky form:
  *        A = L00^2, B = L00 L10, C = L10^2 + L11^2, so that
  *        q = (L00 dx + L10 dy)^2 + (L11 dy)^2; qmax = largest q with
- *        alpha >= alpha_min, padded by 2^-10; rgb after the clamp at 0)
+ *        alpha >= alpha_min, padded by 2^-10; rgb after the clamp at 0;
+ *        one 64-byte line per record, so a renderer's gather of a listed
+ *        splat touches one line)
  *  tiles_touched[V*n]: tiles covered (0 = culled)
  *  rect[V*n][2]: inclusive tile rectangle (tx0 | ty0 << 16, tx1 | ty1 << 16);
  *      (0xFFFFFFFF, 0) for a culled pair

@@ -20,7 +20,7 @@ GESR_BIN_SYNC = 1
 GESR_BIN_WORK_ORDER = 2
 BIN_STATIC_SCRATCH_BYTES = 64 << 20
 MAX_VIEWS = 32
-REC_FLOATS = 12
+REC_FLOATS = 16
 PARTIAL_FLOATS = 10
 GRAD2D_FLOATS = 12  # du dv dL00 dL10 dL11 dop dbeta dr dg db dz + zero pad
 

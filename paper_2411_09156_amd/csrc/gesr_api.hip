@@ -608,7 +608,6 @@ gesr_status gesr_render_fwd_ext(gesr_ctx* ctx, const gesr_proj* proj, const gesr
     a.val_sorted = bins->val_sorted;
     a.ranges = bins->ranges;
     a.worklist = bins->worklist;
-    a.rect = proj->rect;
     a.inst_base = bins->inst_base;
     a.n_items = (uint32_t)g.total_tiles;
     a.batch = st->batch > 0 ? st->batch : 64;
@@ -660,7 +659,6 @@ gesr_status gesr_render_bwd_tiles_ext(gesr_ctx* ctx, const gesr_proj* proj, cons
     a.val_sorted = bins->val_sorted;
     a.ranges = bins->ranges;
     a.worklist = bins->worklist;
-    a.rect = proj->rect;
     a.inst_base = bins->inst_base;
     a.n_items = (uint32_t)g.total_tiles;
     a.batch = st->batch > 0 ? st->batch : 64;

@@ -47,7 +47,6 @@ struct RenderArgs {
     const uint32_t* val_sorted;
     const uint32_t* ranges;
     const uint32_t* worklist;
-    const uint32_t* rect;
     const uint32_t* inst_base;
     uint32_t n_items;  // number of work items (tiles) in the worklist
     int batch;         // records staged in LDS per round (one-wave renderers: 32 or 64)

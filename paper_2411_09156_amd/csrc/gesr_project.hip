@@ -309,18 +309,20 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs a) {
         if (keep) {
             int x0 = (int)fx0, x1 = (int)fx1, y0 = (int)fy0, y1 = (int)fy1;
             int tx0 = x0 / st.tile_w, tx1 = x1 / st.tile_w, ty0 = y0 / st.tile_h, ty1 = y1 / st.tile_h;
+            const uint2 rc = make_uint2((uint32_t)tx0 | ((uint32_t)ty0 << 16), (uint32_t)tx1 | ((uint32_t)ty1 << 16));
             rec[0] = make_float4(vp.u, vp.v, vp.L00, vp.L10);
             rec[1] = make_float4(vp.L11, op, beta, qmax);
             rec[2] = make_float4(rgb[0], rgb[1], rgb[2], vp.p[2]);
+            rec[3] = make_float4(__uint_as_float(rc.x), __uint_as_float(rc.y), 0.f, 0.f);
             a.tiles_touched[vi] = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
-            reinterpret_cast<uint2*>(a.rect)[vi] =
-                make_uint2((uint32_t)tx0 | ((uint32_t)ty0 << 16), (uint32_t)tx1 | ((uint32_t)ty1 << 16));
+            reinterpret_cast<uint2*>(a.rect)[vi] = rc;
             a.depth_key[vi] = __float_as_uint(vp.p[2]);
         } else {
             float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
             rec[0] = zero;
             rec[1] = zero;
             rec[2] = zero;
+            rec[3] = make_float4(__uint_as_float(0xFFFFFFFFu), 0.f, 0.f, 0.f);
             a.tiles_touched[vi] = 0u;
             reinterpret_cast<uint2*>(a.rect)[vi] = make_uint2(0xFFFFFFFFu, 0u);  // culled: no rectangle
             a.depth_key[vi] = 0xFFFFFFFFu;

@@ -254,7 +254,8 @@ __global__ __launch_bounds__(TW * TH) void k_render_bwd(RenderArgs a) {
             const uint32_t pos = hi - 1u - threadIdx.x;
             const uint32_t vi = a.val_sorted[pos];
             stage_record(a.rec, vi, st.kappa, sA[threadIdx.x], sB[threadIdx.x], sC[threadIdx.x]);
-            const uint2 r = reinterpret_cast<const uint2*>(a.rect)[vi];
+            const float4 r3 = reinterpret_cast<const float4*>(a.rec + (size_t)vi * GESR_REC_FLOATS)[3];
+            const uint2 r = make_uint2(__float_as_uint(r3.x), __float_as_uint(r3.y));  // the pair's rectangle
             sInst[threadIdx.x] = instance_index(a, r, vi, ti.tx, ti.ty);
         }
         __syncthreads();
@@ -509,7 +510,8 @@ __global__ __launch_bounds__(64) void k_render_bwd_wave16(RenderArgs a) {
             const uint32_t vi = a.val_sorted[pos];
             stage_record(a.rec, vi, st.kappa, sA[lane], sB[lane], sC[lane]);
             if (EXT) sZ[lane] = a.rec[(size_t)vi * GESR_REC_FLOATS + 11];
-            const uint2 r = reinterpret_cast<const uint2*>(a.rect)[vi];
+            const float4 r3 = reinterpret_cast<const float4*>(a.rec + (size_t)vi * GESR_REC_FLOATS)[3];
+            const uint2 r = make_uint2(__float_as_uint(r3.x), __float_as_uint(r3.y));  // the pair's rectangle
             sInst[lane] = instance_index(a, r, vi, tx, ty);
         }
         __syncthreads();

@@ -22,6 +22,8 @@ import numpy as np
 
 import oracle
 
+REC = 16  # floats per projected record of the HIP library (the first 12 carry the values)
+
 
 def log(msg: str) -> None:
     print(msg, flush=True)
@@ -63,7 +65,7 @@ def run_gpu(scene, st: oracle.Settings, counts=True, rast=None, **kw) -> dict:
     N, V = scene.n, scene.n_views
     VN = N * V
     p, b = out["proj"], out["bins"]
-    res["rec"] = f32(p["rec"])[:VN * 12].reshape(VN, 12)
+    res["rec"] = f32(p["rec"])[:VN * REC].reshape(VN, REC)[:, :12]
     res["tiles_touched"] = u32(p["tiles_touched"])[:VN]
     r = u32(p["rect"])[:2 * VN].reshape(VN, 2)
     res["tile_rect"] = np.stack([r[:, 0] & 0xFFFF, r[:, 0] >> 16, r[:, 1] & 0xFFFF, r[:, 1] >> 16], 1).astype(np.int32)

@@ -37,5 +37,5 @@ def test_fingerprint_ignores_comments_not_code(tmp_path, monkeypatch):
     assert bench.kernel_fingerprint() != base
     p.write_text(text)
     h = tmp_path / "include" / "gesr.h"
-    h.write_text(h.read_text().replace("#define GESR_REC_FLOATS 12", "#define GESR_REC_FLOATS 16", 1))
+    h.write_text(h.read_text().replace("#define GESR_REC_FLOATS 16", "#define GESR_REC_FLOATS 12", 1))
     assert bench.kernel_fingerprint() != base

@@ -27,7 +27,7 @@ import pytest
 
 import gesr_inputs as gi
 import oracle
-from tests.gpu_util import (MASKED_MAX, ambiguous_tiles_to_pixels, check_projection, compare_lists,
+from tests.gpu_util import (REC, MASKED_MAX, ambiguous_tiles_to_pixels, check_projection, compare_lists,
                             conic_grads_to_factor, end_to_end_reference, f32, factor_grads_to_conic,
                             last_composited, log, mask_upstream, norm_errors, oracle_rec, raster_settings, run_gpu,
                             run_gpu_bwd, same_input_reference, splats_of, u32)
@@ -444,7 +444,8 @@ def _full_size_run(k):
     grid, T = oracle.tile_grid(scene.cameras, st.tile_w, st.tile_h)
     L = int(cnt[3])
     P = scene.n_pixels
-    g = dict(rec=f32(proj["rec"])[:VN * 12].reshape(VN, 12), tiles_touched=u32(proj["tiles_touched"])[:VN],
+    g = dict(rec=f32(proj["rec"])[:VN * REC].reshape(VN, REC)[:, :12],
+             tiles_touched=u32(proj["tiles_touched"])[:VN],
              tile_rect=np.stack([r[:, 0] & 0xFFFF, r[:, 0] >> 16, r[:, 1] & 0xFFFF, r[:, 1] >> 16], 1).astype(np.int32),
              depth_key=u32(proj["depth_key"])[:VN], M=M, listed=L, tile_sorted=u32(bins["tile_sorted"])[:L],
              val_sorted=u32(bins["val_sorted"])[:L], ranges=u32(bins["ranges"])[:2 * T].reshape(T, 2),
