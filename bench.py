@@ -62,7 +62,7 @@ SURFACE_SLOTS_PER_SAMPLE = 16
 # projection and binning that build the records and tile lists it walks, and the
 # record layout); otherwise null.
 MEASURED_TRAFFIC = {"kernel": "render_bwd_tiles", "workload": "drt-batch-500k-8views",
-                    "fingerprint": "aab104532dc27d8c", "bytes": 2872796160,
+                    "fingerprint": "ff0e32ab3678259b", "bytes": 2078803968,
                     "settings": (16, 16, 0, 64)}  # tile_w, tile_h, variant, batch of the measured run
 
 
@@ -273,6 +273,7 @@ def workload_leg(k, args, rs):
 
     import gesr_inputs as gi
     from paper_2411_09156_amd import Rasterizer, RasterSettings, Splats
+    from paper_2411_09156_amd._lib import REC_FLOATS
     log(f"[bench] workload {k}: building")
     scene = gi.make_workload(k)
     N, V, P = scene.n, scene.n_views, scene.n_pixels
@@ -329,7 +330,7 @@ def workload_leg(k, args, rs):
                       "sort_buffer_bytes": 16 * V * N,  # depth/view sort ping-pong keys and values, in the scratch
                       "sorted_list_bytes": 4 * M, "ranges_worklist_bytes": 12 * T,
                       "bwd_workspace_bytes": int(sz.bwd_workspace_bytes),
-                      "projection_bytes": V * N * (12 + 4) * 4}}
+                      "projection_bytes": V * N * (REC_FLOATS * 4 + 16)}}  # record, count, rectangle, depth key
     del rast, sp, target
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
