@@ -448,10 +448,7 @@ gesr_status bin_impl(gesr_ctx* ctx, const gesr_proj* proj, const gesr_camera* ca
     }
     // 4. row lists: every pair in the rows its rectangle covers (level 1), each
     //    entry with the columns its ellipse reaches in that row
-    GESR_TRY(hip_check(ctx,
-                       launch_gather_rects(order_vd, proj->rect, proj->rec, g.vn, s.srect,
-                                           s.sell, strm),
-                       "rectangles"));
+    GESR_TRY(hip_check(ctx, launch_gather_rects(order_vd, proj->rec, g.vn, s.srect, s.sell, strm), "rectangles"));
     IsArgs ia;
     memset(&ia, 0, sizeof ia);
     ia.n = n;

@@ -353,14 +353,17 @@ __device__ __forceinline__ uint32_t row_columns(const float4& e0, const float4& 
     return (uint32_t)c0 | ((uint32_t)c1 << 16);
 }
 
+// The rectangle is read from the pair's record (its fourth 16-byte word), so a
+// pair costs one gathered line: the ellipse terms sit in the same 64 bytes.
 // Culled pairs carry the rectangle (0xFFFFFFFF, 0), which no rectangle has
 // (its corners are tile indices below 2^16).
-__global__ __launch_bounds__(256) void k_gather_rects(const uint32_t* order, const uint32_t* rect, const float* rec,
-                                                      uint64_t count, uint2* out, float4* ell) {
+__global__ __launch_bounds__(256) void k_gather_rects(const uint32_t* order, const float* rec, uint64_t count,
+                                                      uint2* out, float4* ell) {
     const uint64_t k = (uint64_t)blockIdx.x * 256 + threadIdx.x;
     if (k >= count) return;
     const uint32_t p = order[k];
-    const uint2 r = reinterpret_cast<const uint2*>(rect)[p];
+    const float4 r3 = reinterpret_cast<const float4*>(rec + (size_t)p * GESR_REC_FLOATS)[3];
+    const uint2 r = make_uint2(__float_as_uint(r3.x), __float_as_uint(r3.y));
     const bool touched = r.x != 0xFFFFFFFFu;
     out[k] = r;
     if (ell != nullptr) {
@@ -391,13 +394,12 @@ __global__ __launch_bounds__(256) void k_view_keys(const uint32_t* vals, uint64_
 // most IS_W consecutive buckets (level 1: a view's rows 128k..128k+127; level
 // 2: a row's tiles 128k..128k+127).  A segment's items are cut into chunks of
 // IS_CHUNK (two items per lane of 16 waves; wave w holds items 128 w .. 128 w +
-// 127, the second 64 in its second word).  In a wave, the items covering
-// bucket b are one ballot, and an item's rank among them is the popcount of
-// the lanes below it, so the order of equal buckets is the item order.
-// Per-(chunk, bucket) counts are scanned over a segment's chunks, bucket
-// totals over all buckets, and the scatter writes each item at bucket start
-// + chunk prefix + earlier waves + rank.  The bucketing arithmetic is integer
-// and the result is unique, independent of scheduling.
+// 127, the second 64 in its second word).  Per-(chunk, bucket) counts are
+// scanned over a segment's chunks, bucket totals over all buckets, and the
+// scatter writes a chunk's entries of bucket b from b's start + the chunk
+// prefix in chunk-item order, read off a (bucket, item) membership bitmap, so
+// the order of equal buckets is the item order.  The bucketing arithmetic is
+// integer and the result is unique, independent of scheduling.
 constexpr int IS_W = 128;
 constexpr int IS_IPL = 2;                            // items per lane
 constexpr int IS_THREADS = 1024;
@@ -534,28 +536,35 @@ __device__ __forceinline__ void wave_prefix_row(int* row) {
 }
 
 // Count pass (MODE 0) and scatter pass (MODE 1) over the chunks; persistent
-// blocks stride over the device-side chunk count.  Per-wave bucket counts come
-// from difference arrays (+1 at lo, -1 at hi + 1; integer LDS atomics, order
-// free).  The scatter ranks items by ballots, stages the chunk's entries in
-// LDS grouped by bucket (at most IS_STAGE at a time, bucket windows) and
-// writes each bucket's run contiguously.
-constexpr int IS_STAGE = 16384;
-// VALU instructions, roughly, of one staging step: a (bucket, word) ballot, and
-// a pass over 64 expanded entries (owner search, seven-bit match, rank)
-constexpr int IS_BALLOT_COST = 8;
-constexpr int IS_MATCH_COST = 128;
+// blocks stride over the device-side chunk count.  The count pass takes
+// per-wave bucket counts from difference arrays (+1 at lo, -1 at hi + 1;
+// integer LDS atomics, order free).  The scatter marks membership in bitmaps,
+// one bit per (bucket, chunk item): setting bits is order free (LDS OR
+// atomics), and reading a bucket's bits in index order yields its entries in
+// item order, so no ranks are computed.  Level 2 writes each bucket's entries
+// straight from its bits; level 1, whose entries also get their row's columns
+// (about 130 instructions each), first unpacks the bits into an LDS stage
+// grouped by bucket (at most IS_STAGE entries at a time, bucket windows) and
+// computes the columns over each bucket's run, 64 entries per step.
+constexpr int IS_STAGE = 4096;
+// Bitmap rows are padded to 65 words, so lanes setting bits of one item word in
+// different buckets mostly fall in different banks.
+constexpr int IS_BM_STRIDE = IS_CHUNK / 32 + 1;
+// VALU instructions, roughly, of one bit-setting step: a lane-serial step over
+// the wave's longest interval, and a pass over 64 expanded entries (owner search)
+constexpr int IS_SERIAL_COST = 5;
+constexpr int IS_PASS_COST = 40;
 
 template <int LEVEL, int MODE>
 __global__ __launch_bounds__(IS_THREADS) __attribute__((amdgpu_waves_per_eu(8))) void k_is_chunks(IsArgs a) {
-    __shared__ int s_cnt[IS_WAVES][IS_W + 1];
+    __shared__ int s_cnt[MODE == 0 ? IS_WAVES : 1][IS_W + 1];
     __shared__ uint32_t s_ls[IS_W + 1];  // chunk-local first entry of each bucket
     __shared__ uint32_t s_gb[IS_W];      // global position of that entry
-    constexpr int STAGE = MODE == 0 ? 1 : (LEVEL == 1 ? IS_STAGE / 2 : IS_STAGE);
-    // + 64 slots that absorb the writes of lanes not covering the current bucket
-    __shared__ uint32_t s_stage[STAGE + 64];
-    // level 1: the chunk's item values and rectangle columns; the stage holds
-    // chunk-local item indices
-    __shared__ uint32_t s_item_p[LEVEL == 1 && MODE == 1 ? IS_CHUNK : 1];
+    __shared__ uint32_t s_bm[MODE == 1 ? IS_W * IS_BM_STRIDE : 1];
+    // level 1: chunk-local item indices grouped by bucket
+    __shared__ uint32_t s_stage[LEVEL == 1 && MODE == 1 ? IS_STAGE : 1];
+    // the chunk's item values (level 1: and rectangle columns)
+    __shared__ uint32_t s_item_p[MODE == 1 ? IS_CHUNK : 1];
     __shared__ uint32_t s_item_c[LEVEL == 1 && MODE == 1 ? IS_CHUNK : 1];
     const uint32_t lane = __lane_id(), wave = threadIdx.x / 64;
     const uint32_t item0 = wave * (64 * IS_IPL) + lane;  // chunk-local index of this lane's first item
@@ -593,25 +602,18 @@ __global__ __launch_bounds__(IS_THREADS) __attribute__((amdgpu_waves_per_eu(8)))
 #pragma unroll
         for (int u = 0; u < IS_IPL; ++u)
             load_item<LEVEL>(a, idx_n + 64 * u, same ? g.end : 0u, p_n[u], a0_n[u], a1_n[u], cols_n[u]);
-        for (int j = threadIdx.x; j < IS_WAVES * (IS_W + 1); j += IS_THREADS) (&s_cnt[0][0])[j] = 0;
-        if (LEVEL == 1 && MODE == 1) {
+        if constexpr (MODE == 0) {
+            for (int j = threadIdx.x; j < IS_WAVES * (IS_W + 1); j += IS_THREADS) (&s_cnt[0][0])[j] = 0;
+            __syncthreads();
 #pragma unroll
-            for (int u = 0; u < IS_IPL; ++u) {
-                s_item_p[item0 + 64 * u] = p[u];
-                s_item_c[item0 + 64 * u] = cols[u];
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int u = 0; u < IS_IPL; ++u)
-            if (any[u]) {
-                atomicAdd(&s_cnt[wave][lo[u]], 1);
-                atomicAdd(&s_cnt[wave][hi[u] + 1], -1);
-            }
-        __syncthreads();
-        wave_prefix_row(s_cnt[wave]);  // s_cnt[w][b]: items of wave w covering bucket b
-        __syncthreads();
-        if (MODE == 0) {
+            for (int u = 0; u < IS_IPL; ++u)
+                if (any[u]) {
+                    atomicAdd(&s_cnt[wave][lo[u]], 1);
+                    atomicAdd(&s_cnt[wave][hi[u] + 1], -1);
+                }
+            __syncthreads();
+            wave_prefix_row(s_cnt[wave]);  // s_cnt[w][b]: items of wave w covering bucket b
+            __syncthreads();
             if (threadIdx.x < (uint32_t)g.width) {
                 int acc = 0;
 #pragma unroll
@@ -619,146 +621,105 @@ __global__ __launch_bounds__(IS_THREADS) __attribute__((amdgpu_waves_per_eu(8)))
                 a.mat[(uint64_t)cg * IS_W + threadIdx.x] = (uint32_t)acc;
             }
         } else {
-            // s_cnt[w][b] -> entries of earlier waves; s_ls: chunk-local bucket starts
-            if (threadIdx.x < IS_W) {
-                const uint32_t b = threadIdx.x;
-                int run = 0;
-#pragma unroll
-                for (int w = 0; w < IS_WAVES; ++w) {
-                    const int c = s_cnt[w][b];
-                    s_cnt[w][b] = run;
-                    run += c;
-                }
-                s_ls[b + 1] = (int)b < g.width ? (uint32_t)run : 0u;
-                if (b == 0) s_ls[0] = 0u;
-                s_gb[b] = gb;
-            }
-            __syncthreads();
-            if (wave == 0) wave_prefix_row(reinterpret_cast<int*>(s_ls + 1));
-            __syncthreads();
-            int lmin = IS_W, hmax = -1;
-#pragma unroll
-            for (int u = 0; u < IS_IPL; ++u)
-                if (any[u]) {
-                    lmin = min(lmin, lo[u]);
-                    hmax = max(hmax, hi[u]);
-                }
-            const int lo_w = __builtin_amdgcn_readfirstlane(wave_min_i(lmin));
-            const int hi_w = __builtin_amdgcn_readfirstlane(wave_max_i(hmax));
-            // b in [lo, hi] as one unsigned compare; empty items never match
-            uint32_t ulo[IS_IPL], uspan[IS_IPL];
+            for (int j = threadIdx.x; j < IS_W * IS_BM_STRIDE; j += IS_THREADS) s_bm[j] = 0u;
 #pragma unroll
             for (int u = 0; u < IS_IPL; ++u) {
-                ulo[u] = any[u] ? (uint32_t)lo[u] : 0x80000000u;
-                uspan[u] = any[u] ? (uint32_t)(hi[u] - lo[u]) : 0u;
+                s_item_p[item0 + 64 * u] = p[u];
+                if (LEVEL == 1) s_item_c[item0 + 64 * u] = cols[u];
             }
-            for (int b0 = 0; b0 < g.width;) {
-                // largest b1 with the window's entries fitting the stage (one bucket
-                // holds at most IS_CHUNK <= STAGE entries)
-                int l = b0 + 1, h = g.width;
-                while (l < h) {
-                    const int mid = (l + h + 1) >> 1;
-                    if (s_ls[mid] - s_ls[b0] <= (uint32_t)STAGE) l = mid;
-                    else h = mid - 1;
+            if (threadIdx.x < IS_W) s_gb[threadIdx.x] = gb;
+            __syncthreads();
+            // membership bits: the cheaper of a lane-serial walk over the
+            // intervals (as long as the wave's longest) and passes over 64
+            // expanded (item, bucket) entries, wave by wave
+#pragma unroll
+            for (int u = 0; u < IS_IPL; ++u) {
+                const uint32_t item = item0 + 64u * (uint32_t)u;
+                const uint32_t nn = any[u] ? (uint32_t)(hi[u] - lo[u] + 1) : 0u;
+                const uint32_t inc = wave_inclusive_scan(nn);
+                const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)inc, 63);
+                const uint32_t mx = __builtin_amdgcn_readfirstlane(wave_max_u32(nn));
+                if (mx * IS_SERIAL_COST <= (tot + 63u) / 64u * IS_PASS_COST) {
+                    uint32_t* row = s_bm + (item >> 5) + (uint32_t)lo[u] * IS_BM_STRIDE;
+                    const uint32_t bit = 1u << (item & 31u);
+                    for (uint32_t k = 0; k < mx; ++k)
+                        if (k < nn) atomicOr(row + k * IS_BM_STRIDE, bit);
+                } else {
+                    // the owner of entry e is the last lane whose first entry
+                    // is at or before e
+                    const uint32_t ex = inc - nn;
+                    for (uint32_t e0 = 0; e0 < tot; e0 += 64) {
+                        const uint32_t e = e0 + lane;
+                        int own = 0;
+#pragma unroll
+                        for (int step = 32; step >= 1; step >>= 1) {
+                            const uint32_t exc = (uint32_t)__shfl((int)ex, own + step, 64);
+                            own = exc <= e ? own + step : own;
+                        }
+                        const uint32_t ex_o = (uint32_t)__shfl((int)ex, own, 64);
+                        const uint32_t b = (uint32_t)__shfl(lo[u], own, 64) + (e - ex_o);
+                        const uint32_t it = item0 - lane + 64u * (uint32_t)u + (uint32_t)own;
+                        if (e < tot) atomicOr(s_bm + b * IS_BM_STRIDE + (it >> 5), 1u << (it & 31u));
+                    }
                 }
-                const int b1 = l;
-                const uint32_t off0 = s_ls[b0];
-                const int bs = max(lo_w, b0), be = min(hi_w, b1 - 1);
-                // Two ways to stage the wave's entries of buckets [bs, be], giving the
-                // same positions: a ballot per (bucket, word) over the span (cheap when
-                // items cover much of it), or one pass per 64 entries of the expanded
-                // (item, bucket) list with ranks among equal buckets from a 7-bit match
-                // (cheap when items cover little of a wide span).  The cheaper by
-                // instruction count is taken, wave by wave.
-                // entries of each word in [bs, be]: item u covers [max(lo, bs), min(hi, be)]
-                auto entries = [&](int u, int& first) {
-                    first = max(lo[u], bs);
-                    const int h = min(hi[u], be);
-                    return any[u] && first <= h ? (uint32_t)(h - first + 1) : 0u;
-                };
-                // the chunk's mean entries per item against the wave's span: a pass
-                // over 64 entries costs about IS_MATCH_COST, a bucket of the ballot
-                // loop IS_IPL * IS_BALLOT_COST for the wave's 64 * IS_IPL items
-                const uint32_t chunk_entries = s_ls[g.width];
-                const bool by_match =
-                    bs <= be && (uint64_t)chunk_entries * IS_MATCH_COST <
-                                    (uint64_t)IS_CHUNK * 64u * IS_BALLOT_COST * (uint32_t)(be - bs + 1) / 64u;
-                if (by_match) {
-#pragma unroll
-                    for (int u = 0; u < IS_IPL; ++u) {
-                        int st0;
-                        const uint32_t nn = entries(u, st0);
-                        const uint32_t inc = wave_inclusive_scan(nn);
-                        const uint32_t ex = inc - nn;
-                        const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)inc, 63);
-                        const uint32_t val = LEVEL == 1 ? item0 + 64u * (uint32_t)u : p[u];
-                        for (uint32_t e0 = 0; e0 < tot; e0 += 64) {
-                            const uint32_t e = e0 + lane;
-                            const bool valid = e < tot;
-                            // owner: the last lane whose first entry is at or before e
-                            int own = 0;
-#pragma unroll
-                            for (int step = 32; step >= 1; step >>= 1) {
-                                const uint32_t exc = (uint32_t)__shfl((int)ex, own + step, 64);
-                                own = exc <= e ? own + step : own;
-                            }
-                            const uint32_t ex_o = (uint32_t)__shfl((int)ex, own, 64);
-                            const int b = __shfl(st0, own, 64) + (int)(e - ex_o);
-                            const uint32_t v = (uint32_t)__shfl((int)val, own, 64);
-                            // lanes of this pass in the same bucket, by its seven bits
-                            const uint32_t rel = valid ? (uint32_t)(b - b0) : 0u;
-                            uint64_t peers = __builtin_amdgcn_ballot_w64(valid);
-#pragma unroll
-                            for (int k = 0; k < 7; ++k) {
-                                const bool bit = (rel >> k) & 1u;
-                                const uint64_t m = __builtin_amdgcn_ballot_w64(valid && bit);
-                                peers &= bit ? m : ~m;
-                            }
-                            const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
-                                (uint32_t)(peers >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)peers, 0u));
-                            if (valid) {
-                                const uint32_t run = (uint32_t)s_cnt[wave][b];
-                                s_stage[s_ls[b] - off0 + run + rank] = v;
-                                if (rank == 0) s_cnt[wave][b] = (int)(run + (uint32_t)__popcll(peers));
-                            }
+            }
+            __syncthreads();
+            if constexpr (LEVEL == 2) {
+                // a wave per bucket: lane l holds the bits of items 32 l .. 32 l + 31
+                for (int b = (int)wave; b < g.width; b += IS_WAVES) {
+                    uint32_t bits = s_bm[b * IS_BM_STRIDE + lane];
+                    const uint32_t c = (uint32_t)__popc(bits);
+                    uint32_t pos = s_gb[b] + wave_inclusive_scan(c) - c;
+                    const uint32_t key = g.bucket0 + (uint32_t)b;
+                    while (bits != 0u) {
+                        const uint32_t k = (uint32_t)__builtin_ctz(bits);
+                        bits &= bits - 1u;
+                        if (pos < a.out_cap) {
+                            a.out_vals[pos] = s_item_p[lane * 32u + k];
+                            if (a.out_keys) a.out_keys[pos] = key;
+                        }
+                        ++pos;
+                    }
+                }
+            } else {
+                // chunk-local bucket starts from the bitmap rows' populations
+                for (int b = (int)wave; b < IS_W; b += IS_WAVES) {
+                    const uint32_t c = b < g.width ? (uint32_t)__popc(s_bm[b * IS_BM_STRIDE + lane]) : 0u;
+                    const uint32_t t = wave_sum_u32(c);
+                    if (lane == 0) s_ls[b + 1] = t;
+                }
+                if (threadIdx.x == 0) s_ls[0] = 0u;
+                __syncthreads();
+                if (wave == 0) wave_prefix_row(reinterpret_cast<int*>(s_ls + 1));
+                __syncthreads();
+                for (int b0 = 0; b0 < g.width;) {
+                    // largest b1 with the window's entries fitting the stage (one
+                    // bucket holds at most IS_CHUNK <= IS_STAGE entries)
+                    int l = b0 + 1, h = g.width;
+                    while (l < h) {
+                        const int mid = (l + h + 1) >> 1;
+                        if (s_ls[mid] - s_ls[b0] <= (uint32_t)IS_STAGE) l = mid;
+                        else h = mid - 1;
+                    }
+                    const int b1 = l;
+                    const uint32_t off0 = s_ls[b0];
+                    for (int b = b0 + (int)wave; b < b1; b += IS_WAVES) {
+                        uint32_t bits = s_bm[b * IS_BM_STRIDE + lane];
+                        const uint32_t c = (uint32_t)__popc(bits);
+                        uint32_t q = s_ls[b] - off0 + wave_inclusive_scan(c) - c;
+                        while (bits != 0u) {
+                            const uint32_t k = (uint32_t)__builtin_ctz(bits);
+                            bits &= bits - 1u;
+                            s_stage[q++] = lane * 32u + k;
                         }
                     }
-                } else if (bs <= be) {
-                    // stage offsets of buckets bs.., two per lane, read back with readlane;
-                    // branch-free: every lane writes, those off the bucket to their own
-                    // spare slot
-                    const int k0 = bs + (int)lane, k1 = bs + 64 + (int)lane;
-                    const uint32_t o0 = k0 <= be ? s_ls[k0] - off0 + (uint32_t)s_cnt[wave][k0] : 0u;
-                    const uint32_t o1 = k1 <= be ? s_ls[k1] - off0 + (uint32_t)s_cnt[wave][k1] : 0u;
-                    const uint32_t spare = (uint32_t)STAGE + lane;
-                    const int nb = be - bs + 1;
-                    auto stage = [&](int b, uint32_t base) {
-                        // the wave's first word of items precedes its second
-#pragma unroll
-                        for (int u = 0; u < IS_IPL; ++u) {
-                            const bool hit = (uint32_t)b - ulo[u] <= uspan[u];
-                            const uint64_t m = __builtin_amdgcn_ballot_w64(hit);
-                            const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
-                                (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-                            const uint32_t sel = 0u - (uint32_t)hit;  // all ones on the bucket
-                            const uint32_t q = spare ^ (((base + rank) ^ spare) & sel);
-                            s_stage[q] = LEVEL == 1 ? item0 + 64u * (uint32_t)u : p[u];
-                            base += (uint32_t)__popcll(m);
-                        }
-                    };
-                    const int na = nb < 64 ? nb : 64;
-                    for (int k = 0; k < na; ++k) stage(bs + k, (uint32_t)__builtin_amdgcn_readlane((int)o0, k));
-                    for (int k = 64; k < nb; ++k)
-                        stage(bs + k, (uint32_t)__builtin_amdgcn_readlane((int)o1, k - 64));
-                }
-                __syncthreads();
-                for (int b = b0 + (int)wave; b < b1; b += IS_WAVES) {
-                    const uint32_t n_b = s_ls[b + 1] - s_ls[b];
-                    const uint32_t src = s_ls[b] - off0, dst = s_gb[b];
-                    for (uint32_t j = lane; j < n_b; j += 64) {
-                        const uint32_t pos = dst + j;
-                        if (pos < a.out_cap) {
-                            if (LEVEL == 1) {
+                    __syncthreads();
+                    for (int b = b0 + (int)wave; b < b1; b += IS_WAVES) {
+                        const uint32_t n_b = s_ls[b + 1] - s_ls[b];
+                        const uint32_t src = s_ls[b] - off0, dst = s_gb[b];
+                        for (uint32_t j = lane; j < n_b; j += 64) {
+                            const uint32_t pos = dst + j;
+                            if (pos < a.out_cap) {
                                 // the columns of the pair's rectangle that its ellipse
                                 // reaches in this entry's row (view row g.lo_off + b)
                                 const uint32_t li = s_stage[src + j];
@@ -770,15 +731,13 @@ __global__ __launch_bounds__(IS_THREADS) __attribute__((amdgpu_waves_per_eu(8)))
                                 }
                                 a.out_vals[pos] = s_item_p[li];
                                 a.out_cols[pos] = c;
-                            } else {
-                                a.out_vals[pos] = s_stage[src + j];
+                                if (a.out_keys) a.out_keys[pos] = g.bucket0 + (uint32_t)b;
                             }
-                            if (a.out_keys) a.out_keys[pos] = g.bucket0 + (uint32_t)b;
                         }
                     }
+                    __syncthreads();
+                    b0 = b1;
                 }
-                __syncthreads();
-                b0 = b1;
             }
         }
         __syncthreads();
@@ -942,10 +901,10 @@ hipError_t radix_sort(const uint32_t* keys_in, const uint32_t* vals_in, uint64_t
     return hipSuccess;
 }
 
-hipError_t launch_gather_rects(const uint32_t* order, const uint32_t* rect, const float* rec, uint64_t count,
-                               uint2* out, float4* ell, hipStream_t stream) {
+hipError_t launch_gather_rects(const uint32_t* order, const float* rec, uint64_t count, uint2* out, float4* ell,
+                               hipStream_t stream) {
     if (count == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_gather_rects, grid_for(count), dim3(256), 0, stream, order, rect, rec, count, out, ell);
+    hipLaunchKernelGGL(k_gather_rects, grid_for(count), dim3(256), 0, stream, order, rec, count, out, ell);
     return hipGetLastError();
 }
 

@@ -132,10 +132,10 @@ int radix_passes(int key_bits, int radix_bits);
 
 // Binning helper kernels.
 hipError_t launch_view_keys(const uint32_t* vals, uint64_t count, uint32_t n, uint32_t* keys, hipStream_t stream);
-// out[k] = rect[order[k]], or the empty rectangle (x = 0xFFFFFFFF) when the pair touches no tile;
+// out[k] = the rectangle in pair order[k]'s record (x = 0xFFFFFFFF when the pair touches no tile);
 // with ell (nullable, [2 count]) also the pair's footprint ellipse and its per-row constants.
-hipError_t launch_gather_rects(const uint32_t* order, const uint32_t* rect, const float* rec, uint64_t count,
-                               uint2* out, float4* ell, hipStream_t stream);
+hipError_t launch_gather_rects(const uint32_t* order, const float* rec, uint64_t count, uint2* out, float4* ell,
+                               hipStream_t stream);
 
 // Interval scatter (tile lists from rectangles, see gesr_bin.hip).  Level 1
 // writes each pair into the row lists of the rows its rectangle covers; level
