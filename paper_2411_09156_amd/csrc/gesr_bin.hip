@@ -483,22 +483,36 @@ __device__ __forceinline__ void load_item(const IsArgs& a, uint32_t idx, uint32_
     }
 }
 
-__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t x) {
+// Wave-wide integer reductions from one ballot per bit of x (x < 2^BITS):
+// scalar and lane-count arithmetic only, no cross-lane data movement.
+// Exclusive prefix of x over the lanes below this one; the wave total in *total.
+template <int BITS>
+__device__ __forceinline__ uint32_t wave_prefix_bits(uint32_t x, uint32_t* total) {
+    uint32_t pre = 0, tot = 0;
 #pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) x += (uint32_t)__shfl_xor((int)x, d, 64);
-    return x;
+    for (int k = 0; k < BITS; ++k) {
+        const uint64_t b = __ballot((x >> k) & 1u);
+        pre += __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u)) << k;
+        tot += (uint32_t)__popcll(b) << k;
+    }
+    *total = tot;
+    return pre;
 }
 
-__device__ __forceinline__ int wave_min_i(int x) {
+// Maximum of x over the wave (wave-uniform).
+template <int BITS>
+__device__ __forceinline__ uint32_t wave_max_bits(uint32_t x) {
+    uint64_t cand = __ballot(true);
+    uint32_t m = 0;
 #pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) x = min(x, __shfl_xor(x, d, 64));
-    return x;
-}
-
-__device__ __forceinline__ int wave_max_i(int x) {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) x = max(x, __shfl_xor(x, d, 64));
-    return x;
+    for (int k = BITS - 1; k >= 0; --k) {
+        const uint64_t b = __ballot((x >> k) & 1u) & cand;
+        if (b != 0ull) {
+            m |= 1u << k;
+            cand = b;
+        }
+    }
+    return m;
 }
 
 // Chunk id -> segment: the largest s with chunk_off[s] <= cg.
@@ -550,10 +564,6 @@ constexpr int IS_STAGE = 4096;
 // Bitmap rows are padded to 65 words, so lanes setting bits of one item word in
 // different buckets mostly fall in different banks.
 constexpr int IS_BM_STRIDE = IS_CHUNK / 32 + 1;
-// VALU instructions, roughly, of one bit-setting step: a lane-serial step over
-// the wave's longest interval, and a pass over 64 expanded entries (owner search)
-constexpr int IS_SERIAL_COST = 5;
-constexpr int IS_PASS_COST = 40;
 
 template <int LEVEL, int MODE>
 __global__ __launch_bounds__(IS_THREADS) __attribute__((amdgpu_waves_per_eu(8))) void k_is_chunks(IsArgs a) {
@@ -629,47 +639,25 @@ __global__ __launch_bounds__(IS_THREADS) __attribute__((amdgpu_waves_per_eu(8)))
             }
             if (threadIdx.x < IS_W) s_gb[threadIdx.x] = gb;
             __syncthreads();
-            // membership bits: the cheaper of a lane-serial walk over the
-            // intervals (as long as the wave's longest) and passes over 64
-            // expanded (item, bucket) entries, wave by wave
+            // membership bits, lane-serial over the intervals (as long as the
+            // wave's longest)
 #pragma unroll
             for (int u = 0; u < IS_IPL; ++u) {
                 const uint32_t item = item0 + 64u * (uint32_t)u;
-                const uint32_t nn = any[u] ? (uint32_t)(hi[u] - lo[u] + 1) : 0u;
-                const uint32_t inc = wave_inclusive_scan(nn);
-                const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)inc, 63);
-                const uint32_t mx = __builtin_amdgcn_readfirstlane(wave_max_u32(nn));
-                if (mx * IS_SERIAL_COST <= (tot + 63u) / 64u * IS_PASS_COST) {
-                    uint32_t* row = s_bm + (item >> 5) + (uint32_t)lo[u] * IS_BM_STRIDE;
-                    const uint32_t bit = 1u << (item & 31u);
-                    for (uint32_t k = 0; k < mx; ++k)
-                        if (k < nn) atomicOr(row + k * IS_BM_STRIDE, bit);
-                } else {
-                    // the owner of entry e is the last lane whose first entry
-                    // is at or before e
-                    const uint32_t ex = inc - nn;
-                    for (uint32_t e0 = 0; e0 < tot; e0 += 64) {
-                        const uint32_t e = e0 + lane;
-                        int own = 0;
-#pragma unroll
-                        for (int step = 32; step >= 1; step >>= 1) {
-                            const uint32_t exc = (uint32_t)__shfl((int)ex, own + step, 64);
-                            own = exc <= e ? own + step : own;
-                        }
-                        const uint32_t ex_o = (uint32_t)__shfl((int)ex, own, 64);
-                        const uint32_t b = (uint32_t)__shfl(lo[u], own, 64) + (e - ex_o);
-                        const uint32_t it = item0 - lane + 64u * (uint32_t)u + (uint32_t)own;
-                        if (e < tot) atomicOr(s_bm + b * IS_BM_STRIDE + (it >> 5), 1u << (it & 31u));
-                    }
-                }
+                const uint32_t nn = any[u] ? (uint32_t)(hi[u] - lo[u] + 1) : 0u;  // <= IS_W
+                const uint32_t mx = wave_max_bits<8>(nn);
+                uint32_t* row = s_bm + (item >> 5) + (uint32_t)lo[u] * IS_BM_STRIDE;
+                const uint32_t bit = 1u << (item & 31u);
+                for (uint32_t k = 0; k < mx; ++k)
+                    if (k < nn) atomicOr(row + k * IS_BM_STRIDE, bit);
             }
             __syncthreads();
             if constexpr (LEVEL == 2) {
                 // a wave per bucket: lane l holds the bits of items 32 l .. 32 l + 31
                 for (int b = (int)wave; b < g.width; b += IS_WAVES) {
                     uint32_t bits = s_bm[b * IS_BM_STRIDE + lane];
-                    const uint32_t c = (uint32_t)__popc(bits);
-                    uint32_t pos = s_gb[b] + wave_inclusive_scan(c) - c;
+                    uint32_t n_b;
+                    uint32_t pos = s_gb[b] + wave_prefix_bits<6>((uint32_t)__popc(bits), &n_b);
                     const uint32_t key = g.bucket0 + (uint32_t)b;
                     while (bits != 0u) {
                         const uint32_t k = (uint32_t)__builtin_ctz(bits);
@@ -685,7 +673,8 @@ __global__ __launch_bounds__(IS_THREADS) __attribute__((amdgpu_waves_per_eu(8)))
                 // chunk-local bucket starts from the bitmap rows' populations
                 for (int b = (int)wave; b < IS_W; b += IS_WAVES) {
                     const uint32_t c = b < g.width ? (uint32_t)__popc(s_bm[b * IS_BM_STRIDE + lane]) : 0u;
-                    const uint32_t t = wave_sum_u32(c);
+                    uint32_t t;
+                    wave_prefix_bits<6>(c, &t);
                     if (lane == 0) s_ls[b + 1] = t;
                 }
                 if (threadIdx.x == 0) s_ls[0] = 0u;
@@ -705,8 +694,8 @@ __global__ __launch_bounds__(IS_THREADS) __attribute__((amdgpu_waves_per_eu(8)))
                     const uint32_t off0 = s_ls[b0];
                     for (int b = b0 + (int)wave; b < b1; b += IS_WAVES) {
                         uint32_t bits = s_bm[b * IS_BM_STRIDE + lane];
-                        const uint32_t c = (uint32_t)__popc(bits);
-                        uint32_t q = s_ls[b] - off0 + wave_inclusive_scan(c) - c;
+                        uint32_t n_b;
+                        uint32_t q = s_ls[b] - off0 + wave_prefix_bits<6>((uint32_t)__popc(bits), &n_b);
                         while (bits != 0u) {
                             const uint32_t k = (uint32_t)__builtin_ctz(bits);
                             bits &= bits - 1u;

@@ -513,14 +513,18 @@ __global__ __launch_bounds__(256) void k_project_bwd(ProjectBwdArgs a) {
 // added in ascending slot order.  A pair of at most kSegSmall instances is
 // summed by one lane (a sum per block, the two added at the end); a larger
 // pair by an aligned group of kSegLanes lanes, lane l taking the blocks l,
-// l + kSegLanes, ... in ascending order, then a fixed DPP tree over the group.
-// Both orders give the same float result for the small pairs (the tree adds
-// the other lanes' +0) and depend only on the pair's own instances, so a
-// batch of views and views rendered one at a time give identical sums.  One
-// thread per pair: the small pairs (most of them) keep every lane busy, then
-// each wave hands its large pairs to its eight groups, eight at a time.
+// l + kSegLanes, ... in ascending order, then a fixed DPP tree over the group;
+// a pair of more than kSegHuge instances likewise by the whole wave (a DPP
+// tree per 16-lane row, then the four row totals in row order).  The order
+// depends only on the pair's own instance count, so a batch of views and
+// views rendered one at a time give identical sums.  One thread per pair: the
+// small pairs (most of them) keep every lane busy, then each wave sums its
+// huge pairs one at a time and hands the other large ones to its eight
+// groups, eight at a time (the longest pairs, thousands of instances, would
+// otherwise serialise hundreds of dependent loads on eight lanes).
 constexpr uint32_t kSegLanes = 8;
 constexpr uint32_t kSegSmall = 64;
+constexpr uint32_t kSegHuge = 512;
 
 // Adds block j0 .. j0 + 31 of the pair (first slot `base`, cnt slots) to acc.
 template <int NP>
@@ -586,10 +590,31 @@ __global__ __launch_bounds__(256) void k_seg_reduce(SegReduceArgs a) {
         for (int k = 0; k < NP; ++k) acc0[k] += acc1[k];
         seg_write<NP>(a, vi, acc0);
     }
-    // large pairs of this wave, eight at a time (group g = lane / L takes the
-    // g-th remaining one)
-    uint64_t large = __ballot(valid && !small);
     const uint64_t wave0 = vi - lane;
+    // huge pairs of this wave, one at a time over all its lanes
+    uint64_t huge = __ballot(valid && cnt > kSegHuge);
+    while (huge != 0ull) {
+        const uint32_t pick = (uint32_t)__builtin_ctzll(huge);
+        const uint32_t c = (uint32_t)__shfl((int)cnt, (int)pick, 64);
+        const uint64_t b0 = (uint64_t)(uint32_t)__shfl((int)(uint32_t)base, (int)pick, 64);
+        float acc[NP];
+#pragma unroll
+        for (int k = 0; k < NP; ++k) acc[k] = 0.f;
+        for (uint32_t j0 = lane * 32u; j0 < c; j0 += 64u * 32u) seg_block<NP>(a, b0, c, j0, nwords, acc);
+        float tot[NP];
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {
+            const int r = __float_as_int(group_sum<16>(acc[k]));
+            tot[k] = ((__int_as_float(__builtin_amdgcn_readlane(r, 0)) + __int_as_float(__builtin_amdgcn_readlane(r, 16))) +
+                      __int_as_float(__builtin_amdgcn_readlane(r, 32))) +
+                     __int_as_float(__builtin_amdgcn_readlane(r, 48));
+        }
+        if (lane == 0) seg_write<NP>(a, wave0 + pick, tot);
+        huge &= huge - 1u;
+    }
+    // the other large pairs, eight at a time (group g = lane / L takes the
+    // g-th remaining one)
+    uint64_t large = __ballot(valid && !small && cnt <= kSegHuge);
     const uint32_t g = lane / L, l = lane % L;
     while (large != 0ull) {
         uint64_t m = large;
