@@ -556,14 +556,21 @@ __device__ __forceinline__ void wave_prefix_row(int* row) {
 // one bit per (bucket, chunk item): setting bits is order free (LDS OR
 // atomics), and reading a bucket's bits in index order yields its entries in
 // item order, so no ranks are computed.  Level 2 writes each bucket's entries
-// straight from its bits; level 1, whose entries also get their row's columns
-// (about 130 instructions each), first unpacks the bits into an LDS stage
-// grouped by bucket (at most IS_STAGE entries at a time, bucket windows) and
-// computes the columns over each bucket's run, 64 entries per step.
+// from its bits (long runs through a per-wave stage); level 1, whose entries
+// also get their row's columns (about 130 instructions each), first unpacks
+// the bits into an LDS stage grouped by bucket (at most IS_STAGE entries at a
+// time, bucket windows) and computes the columns over each bucket's run, 64
+// entries per step.
 constexpr int IS_STAGE = 4096;
 // Bitmap rows are padded to 65 words, so lanes setting bits of one item word in
 // different buckets mostly fall in different banks.
 constexpr int IS_BM_STRIDE = IS_CHUNK / 32 + 1;
+// Level 2 writes a bucket's run straight from its bits when the run is short;
+// a longer one (up to IS_WSTAGE entries) is unpacked into a per-wave LDS stage
+// first and written coalesced (the direct writes scatter one value per lane
+// over the run, as many stores as the fullest bitmap word has bits).
+constexpr int IS_WSTAGE = 512;
+constexpr int IS_WSTAGE_MIN = 96;
 
 template <int LEVEL, int MODE>
 __global__ __launch_bounds__(IS_THREADS) __attribute__((amdgpu_waves_per_eu(8))) void k_is_chunks(IsArgs a) {
@@ -571,6 +578,8 @@ __global__ __launch_bounds__(IS_THREADS) __attribute__((amdgpu_waves_per_eu(8)))
     __shared__ uint32_t s_ls[IS_W + 1];  // chunk-local first entry of each bucket
     __shared__ uint32_t s_gb[IS_W];      // global position of that entry
     __shared__ uint32_t s_bm[MODE == 1 ? IS_W * IS_BM_STRIDE : 1];
+    // level 2: a stage per wave for one bucket's run
+    __shared__ uint32_t s_wst[LEVEL == 2 && MODE == 1 ? IS_WAVES * IS_WSTAGE : 1];
     // level 1: chunk-local item indices grouped by bucket
     __shared__ uint32_t s_stage[LEVEL == 1 && MODE == 1 ? IS_STAGE : 1];
     // the chunk's item values (level 1: and rectangle columns)
@@ -654,11 +663,36 @@ __global__ __launch_bounds__(IS_THREADS) __attribute__((amdgpu_waves_per_eu(8)))
             __syncthreads();
             if constexpr (LEVEL == 2) {
                 // a wave per bucket: lane l holds the bits of items 32 l .. 32 l + 31
+                uint32_t* wst = s_wst + wave * IS_WSTAGE;
                 for (int b = (int)wave; b < g.width; b += IS_WAVES) {
                     uint32_t bits = s_bm[b * IS_BM_STRIDE + lane];
                     uint32_t n_b;
-                    uint32_t pos = s_gb[b] + wave_prefix_bits<6>((uint32_t)__popc(bits), &n_b);
+                    const uint32_t pre = wave_prefix_bits<6>((uint32_t)__popc(bits), &n_b);
+                    uint32_t pos = s_gb[b] + pre;
                     const uint32_t key = g.bucket0 + (uint32_t)b;
+                    if (n_b > (uint32_t)IS_WSTAGE_MIN && n_b <= (uint32_t)IS_WSTAGE) {
+                        // unpack into the wave's stage, then write the run coalesced
+                        uint32_t q = pre;
+                        while (bits != 0u) {
+                            const uint32_t k = (uint32_t)__builtin_ctz(bits);
+                            bits &= bits - 1u;
+                            wst[q++] = s_item_p[lane * 32u + k];
+                        }
+                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                        __builtin_amdgcn_wave_barrier();
+                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                        const uint32_t dst = s_gb[b];
+                        for (uint32_t j = lane; j < n_b; j += 64) {
+                            if (dst + j < a.out_cap) {
+                                a.out_vals[dst + j] = wst[j];
+                                if (a.out_keys) a.out_keys[dst + j] = key;
+                            }
+                        }
+                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                        __builtin_amdgcn_wave_barrier();
+                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                        continue;
+                    }
                     while (bits != 0u) {
                         const uint32_t k = (uint32_t)__builtin_ctz(bits);
                         bits &= bits - 1u;
