@@ -88,7 +88,7 @@ typedef struct {
     int32_t batch;          /* splats staged per LDS round in the renderers: 0 (= 64), 32,
                                64 or 128 (128 only for the four-wave 16x16 and the 32x16
                                backward; other kernels clamp to what their tile holds) */
-    int32_t radix_bits;     /* digit width of the depth sort of the (view, splat) pairs, 4..8 */
+    int32_t radix_bits;     /* digit width of the (view, depth) sort of the (view, splat) pairs, 4..8 */
     int32_t variant;        /* 16x16 renderers: 0 = one wave per tile (4 px per lane),
                                1 = one workgroup of four waves per tile */
     int32_t reserved[3];

@@ -412,14 +412,17 @@ gesr_status bin_impl(gesr_ctx* ctx, const gesr_proj* proj, const gesr_camera* ca
     hipStream_t strm = (hipStream_t)stream;
     const uint64_t T = g.total_tiles;
 
-    // 1. depth order of the (view, splat) pairs: LSD passes over the 32 depth bits
+    // 1. (view, depth, pair) order of the (view, splat) pairs: LSD passes over
+    //    the 32 depth bits and then the view bits, which the last pass or two
+    //    take from the pair index (view = pair / n)
     SortBuffers db{s.d_keys_a, s.d_vals_a, s.d_keys_b, s.d_vals_b, s.block_hist, s.scan_partials};
     bool in_b = false;
-    GESR_TRY(hip_check(ctx, radix_sort(proj->depth_key, nullptr, g.vn, nullptr, 32, st->radix_bits, db, &in_b, strm),
-                       "depth sort"));
-    uint32_t* order = in_b ? s.d_vals_b : s.d_vals_a;
-    uint32_t* spare_keys = in_b ? s.d_keys_a : s.d_keys_b;
-    uint32_t* spare_vals = in_b ? s.d_vals_a : s.d_vals_b;
+    const int vbits = bits_for((uint64_t)V);
+    GESR_TRY(hip_check(ctx,
+                       radix_sort(proj->depth_key, nullptr, g.vn, nullptr, 32 + vbits, st->radix_bits, db, &in_b,
+                                  strm, vbits > 0 ? (uint32_t)n : 0u),
+                       "depth and view sort"));
+    const uint32_t* order_vd = in_b ? s.d_vals_b : s.d_vals_a;
     // 2. instance slots: exclusive scan of tiles_touched in pair order; M -> counters[0]
     GESR_TRY(hip_check(ctx, scan_exclusive(proj->tiles_touched, bins->inst_base, g.vn, s.scan_partials,
                                            bins->counters, strm),
@@ -434,19 +437,7 @@ gesr_status bin_impl(gesr_ctx* ctx, const gesr_proj* proj, const gesr_camera* ca
             return fail(ctx, GESR_ERR_CAPACITY, "M = %u instances exceed m_cap = %llu", m,
                         (unsigned long long)bins->m_cap);
     }
-    // 3. stable pass on the view: pairs in (view, depth, pair) order
-    const uint32_t* order_vd = order;
-    if (bits_for((uint64_t)V) > 0 && g.vn > 0) {
-        GESR_TRY(hip_check(ctx, launch_view_keys(order, g.vn, (uint32_t)n, spare_keys, strm), "view keys"));
-        SortBuffers vb{s.d_keys_a == spare_keys ? s.d_keys_b : s.d_keys_a, spare_vals, nullptr, nullptr,
-                       s.block_hist, s.scan_partials};
-        bool vb_in_b = false;
-        GESR_TRY(hip_check(ctx, radix_sort(spare_keys, order, g.vn, nullptr, bits_for((uint64_t)V), 8, vb, &vb_in_b,
-                                           strm),
-                           "view sort"));
-        order_vd = spare_vals;
-    }
-    // 4. row lists: every pair in the rows its rectangle covers (level 1), each
+    // 3. row lists: every pair in the rows its rectangle covers (level 1), each
     //    entry with the columns its ellipse reaches in that row
     GESR_TRY(hip_check(ctx, launch_gather_rects(order_vd, proj->rec, g.vn, s.srect, s.sell, strm), "rectangles"));
     IsArgs ia;
@@ -474,7 +465,7 @@ gesr_status bin_impl(gesr_ctx* ctx, const gesr_proj* proj, const gesr_camera* ca
                                                s.scan_partials, strm),
                        "row lists"));
     GESR_TRY(hip_check(ctx, launch_set_counters(s.counters, bins->m_cap, strm), "row counters"));
-    // 5. tile lists: every row-list entry in the tiles of its columns (level 2)
+    // 4. tile lists: every row-list entry in the tiles of its columns (level 2)
     IsArgs l2 = ia;
     l2.items = s.rowlist;
     l2.item_cols = s.rowcols;

@@ -171,13 +171,26 @@ __device__ __forceinline__ uint32_t count_of(const uint32_t* count_dev, uint64_t
     return count_dev ? *count_dev : (uint32_t)count_static;
 }
 
+// Digit of one key at bit `shift`.  With view_n != 0 the sorted key is the
+// 64-bit (val / view_n) << 32 | key (the view of a pair val = view * n + splat
+// above its 32-bit depth key), so a pass can take depth and view bits together.
+template <int BITS, bool VIEW>
+__device__ __forceinline__ uint32_t sort_digit(uint32_t key, uint32_t val, int shift, uint32_t view_n) {
+    if (VIEW) {
+        const uint64_t k64 = ((uint64_t)(val / view_n) << 32) | key;
+        return (uint32_t)(k64 >> shift) & ((1u << BITS) - 1u);
+    }
+    return (key >> shift) & ((1u << BITS) - 1u);
+}
+
 // Digit histogram of one block of SORT_TILE keys, stored digit-major:
 // block_hist[digit * nblocks + block].  Counting needs no ranking, so LDS
 // atomics (exact, order-independent) replace the ballot matching.
-template <int BITS>
-__global__ __launch_bounds__(SORT_THREADS) void k_radix_hist(const uint32_t* keys, uint64_t count_static,
-                                                             const uint32_t* count_dev, int shift,
-                                                             uint32_t* block_hist, uint32_t nblocks) {
+template <int BITS, bool VIEW>
+__global__ __launch_bounds__(SORT_THREADS) void k_radix_hist(const uint32_t* keys, const uint32_t* vals,
+                                                             uint64_t count_static, const uint32_t* count_dev,
+                                                             int shift, uint32_t view_n, uint32_t* block_hist,
+                                                             uint32_t nblocks) {
     constexpr int RADIX = 1 << BITS;
     __shared__ uint32_t hist[RADIX];
     for (int j = threadIdx.x; j < RADIX; j += SORT_THREADS) hist[j] = 0u;
@@ -185,16 +198,17 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_hist(const uint32_t* key
     const uint32_t n = count_of(count_dev, count_static);
     const uint64_t base = (uint64_t)blockIdx.x * SORT_TILE;
     if (base < n) {
-        uint32_t k[SORT_ITEMS];
+        uint32_t k[SORT_ITEMS], v[SORT_ITEMS];
 #pragma unroll
         for (int r = 0; r < SORT_ITEMS; ++r) {
             const uint64_t idx = base + (uint64_t)r * SORT_THREADS + threadIdx.x;
             k[r] = idx < n ? keys[idx] : 0u;
+            v[r] = VIEW && idx < n ? (vals ? vals[idx] : (uint32_t)idx) : 0u;
         }
 #pragma unroll
         for (int r = 0; r < SORT_ITEMS; ++r) {
             const uint64_t idx = base + (uint64_t)r * SORT_THREADS + threadIdx.x;
-            if (idx < n) atomicAdd(&hist[(k[r] >> shift) & (RADIX - 1)], 1u);
+            if (idx < n) atomicAdd(&hist[sort_digit<BITS, VIEW>(k[r], v[r], shift, view_n)], 1u);
         }
     }
     __syncthreads();
@@ -204,12 +218,12 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_hist(const uint32_t* key
 // Stable scatter of one block: ranks keys per digit in position order (wave
 // ballots + per-wave running counts), stages the block in LDS in sorted
 // order, then writes each digit run contiguously.
-template <int BITS>
+template <int BITS, bool VIEW>
 __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(const uint32_t* keys_in, const uint32_t* vals_in,
                                                                 uint32_t* keys_out, uint32_t* vals_out,
                                                                 uint64_t count_static, const uint32_t* count_dev,
-                                                                int shift, const uint32_t* block_off,
-                                                                uint32_t nblocks) {
+                                                                int shift, uint32_t view_n,
+                                                                const uint32_t* block_off, uint32_t nblocks) {
     constexpr int RADIX = 1 << BITS;
     __shared__ uint32_t hist[WAVES][RADIX];
     __shared__ uint32_t digit_start[RADIX + 1];
@@ -240,7 +254,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(const uint32_t* 
     for (int r = 0; r < SORT_ITEMS; ++r) {
         const uint64_t idx = base + r * 64 + lane;
         const bool valid = idx < n;
-        const uint32_t digit = (k[r] >> shift) & (RADIX - 1);
+        const uint32_t digit = sort_digit<BITS, VIEW>(k[r], v[r], shift, view_n);
         const uint64_t vmask = __ballot(valid);
         const uint64_t peers = match_digit<BITS>(digit, vmask);
         const uint32_t old = valid ? hist[wave][digit] : 0u;
@@ -269,7 +283,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(const uint32_t* 
     for (int r = 0; r < SORT_ITEMS; ++r) {
         const uint64_t idx = base + r * 64 + lane;
         if (idx < n) {
-            const uint32_t digit = (k[r] >> shift) & (RADIX - 1);
+            const uint32_t digit = sort_digit<BITS, VIEW>(k[r], v[r], shift, view_n);
             const uint32_t lp = digit_start[digit] + hist[wave][digit] + rank[r];
             s_keys[lp] = k[r];
             s_vals[lp] = v[r];
@@ -278,25 +292,34 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(const uint32_t* 
     __syncthreads();
     const uint32_t in_block = (uint32_t)min<uint64_t>(SORT_TILE, n - block_start);
     for (uint32_t j = threadIdx.x; j < in_block; j += SORT_THREADS) {
-        const uint32_t key = s_keys[j];
-        const uint32_t digit = (key >> shift) & (RADIX - 1);
+        const uint32_t key = s_keys[j], val = s_vals[j];
+        const uint32_t digit = sort_digit<BITS, VIEW>(key, val, shift, view_n);
         const uint32_t pos = g_off[digit] + (j - digit_start[digit]);
         keys_out[pos] = key;
-        vals_out[pos] = s_vals[j];
+        vals_out[pos] = val;
     }
 }
 
 template <int BITS>
 hipError_t sort_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout, uint64_t count_static,
-                     const uint32_t* count_dev, int shift, const SortBuffers& b, hipStream_t stream) {
+                     const uint32_t* count_dev, int shift, uint32_t view_n, const SortBuffers& b,
+                     hipStream_t stream) {
     const uint32_t nblocks = (uint32_t)((count_static + SORT_TILE - 1) / SORT_TILE);
-    hipLaunchKernelGGL(k_radix_hist<BITS>, dim3(nblocks), dim3(SORT_THREADS), 0, stream, kin, count_static,
-                       count_dev, shift, b.block_hist, nblocks);
+    if (view_n != 0u)
+        hipLaunchKernelGGL((k_radix_hist<BITS, true>), dim3(nblocks), dim3(SORT_THREADS), 0, stream, kin, vin,
+                           count_static, count_dev, shift, view_n, b.block_hist, nblocks);
+    else
+        hipLaunchKernelGGL((k_radix_hist<BITS, false>), dim3(nblocks), dim3(SORT_THREADS), 0, stream, kin, vin,
+                           count_static, count_dev, shift, view_n, b.block_hist, nblocks);
     hipError_t e = scan_exclusive(b.block_hist, b.block_hist, (uint64_t)nblocks << BITS, b.scan_partials, nullptr,
                                   stream);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_radix_scatter<BITS>, dim3(nblocks), dim3(SORT_THREADS), 0, stream, kin, vin, kout, vout,
-                       count_static, count_dev, shift, b.block_hist, nblocks);
+    if (view_n != 0u)
+        hipLaunchKernelGGL((k_radix_scatter<BITS, true>), dim3(nblocks), dim3(SORT_THREADS), 0, stream, kin, vin,
+                           kout, vout, count_static, count_dev, shift, view_n, b.block_hist, nblocks);
+    else
+        hipLaunchKernelGGL((k_radix_scatter<BITS, false>), dim3(nblocks), dim3(SORT_THREADS), 0, stream, kin, vin,
+                           kout, vout, count_static, count_dev, shift, view_n, b.block_hist, nblocks);
     return hipGetLastError();
 }
 
@@ -372,12 +395,6 @@ __global__ __launch_bounds__(256) void k_gather_rects(const uint32_t* order, con
         ell[2 * k] = e0;
         ell[2 * k + 1] = e1;
     }
-}
-
-// keys[k] = view of the pair vals[k] (pairs are numbered view * n + splat).
-__global__ __launch_bounds__(256) void k_view_keys(const uint32_t* vals, uint64_t count, uint32_t n, uint32_t* keys) {
-    const uint64_t k = (uint64_t)blockIdx.x * 256 + threadIdx.x;
-    if (k < count) keys[k] = vals[k] / n;
 }
 
 // ------------------------------------------------- interval scatter (lists)
@@ -894,7 +911,7 @@ int radix_passes(int key_bits, int radix_bits) { return key_bits <= 0 ? 0 : (key
 
 hipError_t radix_sort(const uint32_t* keys_in, const uint32_t* vals_in, uint64_t count_static,
                       const uint32_t* count_dev, int key_bits, int radix_bits, const SortBuffers& b,
-                      bool* result_in_b, hipStream_t stream) {
+                      bool* result_in_b, hipStream_t stream, uint32_t view_n) {
     const int passes = radix_passes(key_bits, radix_bits);
     const uint32_t* kin = keys_in;
     const uint32_t* vin = vals_in;
@@ -908,12 +925,15 @@ hipError_t radix_sort(const uint32_t* keys_in, const uint32_t* vals_in, uint64_t
         uint32_t* kout = (p & 1) ? b.keys_b : b.keys_a;
         uint32_t* vout = (p & 1) ? b.vals_b : b.vals_a;
         hipError_t e;
+        const int sh = p * radix_bits;
+        // the view enters the digits of the passes reaching past the 32 key bits
+        const uint32_t vn = sh + radix_bits > 32 ? view_n : 0u;
         switch (radix_bits) {
-            case 4: e = sort_pass<4>(kin, vin, kout, vout, count_static, count_dev, p * 4, b, stream); break;
-            case 5: e = sort_pass<5>(kin, vin, kout, vout, count_static, count_dev, p * 5, b, stream); break;
-            case 6: e = sort_pass<6>(kin, vin, kout, vout, count_static, count_dev, p * 6, b, stream); break;
-            case 7: e = sort_pass<7>(kin, vin, kout, vout, count_static, count_dev, p * 7, b, stream); break;
-            default: e = sort_pass<8>(kin, vin, kout, vout, count_static, count_dev, p * 8, b, stream); break;
+            case 4: e = sort_pass<4>(kin, vin, kout, vout, count_static, count_dev, sh, vn, b, stream); break;
+            case 5: e = sort_pass<5>(kin, vin, kout, vout, count_static, count_dev, sh, vn, b, stream); break;
+            case 6: e = sort_pass<6>(kin, vin, kout, vout, count_static, count_dev, sh, vn, b, stream); break;
+            case 7: e = sort_pass<7>(kin, vin, kout, vout, count_static, count_dev, sh, vn, b, stream); break;
+            default: e = sort_pass<8>(kin, vin, kout, vout, count_static, count_dev, sh, vn, b, stream); break;
         }
         if (e != hipSuccess) return e;
         kin = kout;
@@ -928,12 +948,6 @@ hipError_t launch_gather_rects(const uint32_t* order, const float* rec, uint64_t
                                hipStream_t stream) {
     if (count == 0) return hipSuccess;
     hipLaunchKernelGGL(k_gather_rects, grid_for(count), dim3(256), 0, stream, order, rec, count, out, ell);
-    return hipGetLastError();
-}
-
-hipError_t launch_view_keys(const uint32_t* vals, uint64_t count, uint32_t n, uint32_t* keys, hipStream_t stream) {
-    if (count == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_view_keys, grid_for(count), dim3(256), 0, stream, vals, count, n, keys);
     return hipGetLastError();
 }
 

@@ -117,6 +117,9 @@ hipError_t scan_exclusive(const uint32_t* in, uint32_t* out, uint64_t count, uin
 // Stable LSD radix sort of `count_static` (or *count_dev when non-null, which
 // must not exceed count_static) 32-bit keys over bits [0, key_bits) carrying
 // 32-bit values.  vals_in == nullptr means values are the positions 0..n-1.
+// With view_n != 0 the key is 64 bits, (value / view_n) << 32 | key, sorted
+// over bits [0, key_bits) (key_bits > 32: the view bits of (view, splat) pair
+// values), so no separate pass over a view key is needed.
 // Ping-pongs between (keys_a, vals_a) and (keys_b, vals_b); the first pass
 // reads keys_in / vals_in.  Returns (via *result_in_b) whether the result
 // ends in the b buffers.
@@ -127,11 +130,10 @@ struct SortBuffers {
 };
 hipError_t radix_sort(const uint32_t* keys_in, const uint32_t* vals_in, uint64_t count_static,
                       const uint32_t* count_dev, int key_bits, int radix_bits, const SortBuffers& b,
-                      bool* result_in_b, hipStream_t stream);
+                      bool* result_in_b, hipStream_t stream, uint32_t view_n = 0);
 int radix_passes(int key_bits, int radix_bits);
 
 // Binning helper kernels.
-hipError_t launch_view_keys(const uint32_t* vals, uint64_t count, uint32_t n, uint32_t* keys, hipStream_t stream);
 // out[k] = the rectangle in pair order[k]'s record (x = 0xFFFFFFFF when the pair touches no tile);
 // with ell (nullable, [2 count]) also the pair's footprint ellipse and its per-row constants.
 hipError_t launch_gather_rects(const uint32_t* order, const float* rec, uint64_t count, uint2* out, float4* ell,
