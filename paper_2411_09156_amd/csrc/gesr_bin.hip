@@ -576,8 +576,8 @@ __device__ __forceinline__ void wave_prefix_row(int* row) {
 // from its bits (long runs through a per-wave stage); level 1, whose entries
 // also get their row's columns (about 130 instructions each), first unpacks
 // the bits into an LDS stage grouped by bucket (at most IS_STAGE entries at a
-// time, bucket windows) and computes the columns over each bucket's run, 64
-// entries per step.
+// time, bucket windows) and computes the columns over the window's entries
+// with all threads of the block.
 constexpr int IS_STAGE = 4096;
 // Bitmap rows are padded to 65 words, so lanes setting bits of one item word in
 // different buckets mostly fall in different banks.
@@ -597,7 +597,8 @@ __global__ __launch_bounds__(IS_THREADS) __attribute__((amdgpu_waves_per_eu(8)))
     __shared__ uint32_t s_bm[MODE == 1 ? IS_W * IS_BM_STRIDE : 1];
     // level 2: a stage per wave for one bucket's run
     __shared__ uint32_t s_wst[LEVEL == 2 && MODE == 1 ? IS_WAVES * IS_WSTAGE : 1];
-    // level 1: chunk-local item indices grouped by bucket
+    // level 1: chunk-local item index | bucket << 11, grouped by bucket
+    static_assert(IS_CHUNK <= 2048, "chunk-local item indices take 11 bits");
     __shared__ uint32_t s_stage[LEVEL == 1 && MODE == 1 ? IS_STAGE : 1];
     // the chunk's item values (level 1: and rectangle columns)
     __shared__ uint32_t s_item_p[MODE == 1 ? IS_CHUNK : 1];
@@ -633,11 +634,16 @@ __global__ __launch_bounds__(IS_THREADS) __attribute__((amdgpu_waves_per_eu(8)))
         }
         const bool same = cg + 1 < cend && cg + 1 < s_next;
         const uint32_t idx_n = idx + IS_CHUNK;
+        // the next chunk's items are loaded now, except by the level-1 scatter,
+        // whose gathers in the copy-out need the registers (it loads them last)
+        constexpr bool EARLY = !(LEVEL == 1 && MODE == 1);
         uint32_t p_n[IS_IPL], cols_n[IS_IPL];
         int a0_n[IS_IPL], a1_n[IS_IPL];
+        if (EARLY) {
 #pragma unroll
-        for (int u = 0; u < IS_IPL; ++u)
-            load_item<LEVEL>(a, idx_n + 64 * u, same ? g.end : 0u, p_n[u], a0_n[u], a1_n[u], cols_n[u]);
+            for (int u = 0; u < IS_IPL; ++u)
+                load_item<LEVEL>(a, idx_n + 64 * u, same ? g.end : 0u, p_n[u], a0_n[u], a1_n[u], cols_n[u]);
+        }
         if constexpr (MODE == 0) {
             for (int j = threadIdx.x; j < IS_WAVES * (IS_W + 1); j += IS_THREADS) (&s_cnt[0][0])[j] = 0;
             __syncthreads();
@@ -750,28 +756,47 @@ __global__ __launch_bounds__(IS_THREADS) __attribute__((amdgpu_waves_per_eu(8)))
                         while (bits != 0u) {
                             const uint32_t k = (uint32_t)__builtin_ctz(bits);
                             bits &= bits - 1u;
-                            s_stage[q++] = lane * 32u + k;
+                            s_stage[q++] = (lane * 32u + k) | ((uint32_t)b << 11);
                         }
                     }
                     __syncthreads();
-                    for (int b = b0 + (int)wave; b < b1; b += IS_WAVES) {
-                        const uint32_t n_b = s_ls[b + 1] - s_ls[b];
-                        const uint32_t src = s_ls[b] - off0, dst = s_gb[b];
-                        for (uint32_t j = lane; j < n_b; j += 64) {
-                            const uint32_t pos = dst + j;
+                    // the window's entries over all threads of the block, two per
+                    // thread at a time so their ellipse gathers are in flight
+                    // together; each gets the columns of its pair's rectangle that
+                    // the ellipse reaches in the entry's row (view row g.lo_off + b)
+                    const uint32_t wn = s_ls[b1] - off0;
+                    const float4* ell = a.item_ell + 2 * (size_t)(idx - item0);
+                    for (uint32_t i0 = threadIdx.x; i0 < wn; i0 += 2 * IS_THREADS) {
+                        uint32_t w[2];
+                        float4 e0[2], e1[2];
+#pragma unroll
+                        for (int r = 0; r < 2; ++r) {
+                            const uint32_t i = i0 + (uint32_t)r * IS_THREADS;
+                            w[r] = i < wn ? s_stage[i] : 0u;
+                        }
+#pragma unroll
+                        for (int r = 0; r < 2; ++r) {
+                            const uint32_t i = i0 + (uint32_t)r * IS_THREADS;
+                            const uint32_t li = w[r] & (uint32_t)(IS_CHUNK - 1);
+                            if (i < wn && a.item_ell != nullptr) {
+                                e0[r] = ell[2 * li];
+                                e1[r] = ell[2 * li + 1];
+                            }
+                        }
+#pragma unroll
+                        for (int r = 0; r < 2; ++r) {
+                            const uint32_t i = i0 + (uint32_t)r * IS_THREADS;
+                            if (i >= wn) continue;
+                            const uint32_t li = w[r] & (uint32_t)(IS_CHUNK - 1), b = w[r] >> 11;
+                            const uint32_t pos = s_gb[b] + (i + off0 - s_ls[b]);
                             if (pos < a.out_cap) {
-                                // the columns of the pair's rectangle that its ellipse
-                                // reaches in this entry's row (view row g.lo_off + b)
-                                const uint32_t li = s_stage[src + j];
                                 uint32_t c = s_item_c[li];
-                                if (a.item_ell != nullptr) {
-                                    const float4* e = a.item_ell + 2 * ((size_t)(idx - item0) + li);
-                                    c = row_columns(e[0], e[1], g.lo_off + b, a.tile_w, a.tile_h,
+                                if (a.item_ell != nullptr)
+                                    c = row_columns(e0[r], e1[r], g.lo_off + (int)b, a.tile_w, a.tile_h,
                                                     (int)(c & 0xFFFFu), (int)(c >> 16));
-                                }
                                 a.out_vals[pos] = s_item_p[li];
                                 a.out_cols[pos] = c;
-                                if (a.out_keys) a.out_keys[pos] = g.bucket0 + (uint32_t)b;
+                                if (a.out_keys) a.out_keys[pos] = g.bucket0 + b;
                             }
                         }
                     }
@@ -785,12 +810,17 @@ __global__ __launch_bounds__(IS_THREADS) __attribute__((amdgpu_waves_per_eu(8)))
         if (cg >= cend) break;
         if (same) {
             idx = idx_n;
+            if (EARLY) {
 #pragma unroll
-            for (int u = 0; u < IS_IPL; ++u) {
-                p[u] = p_n[u];
-                cols[u] = cols_n[u];
-                a0[u] = a0_n[u];
-                a1[u] = a1_n[u];
+                for (int u = 0; u < IS_IPL; ++u) {
+                    p[u] = p_n[u];
+                    cols[u] = cols_n[u];
+                    a0[u] = a0_n[u];
+                    a1[u] = a1_n[u];
+                }
+            } else {
+#pragma unroll
+                for (int u = 0; u < IS_IPL; ++u) load_item<LEVEL>(a, idx + 64 * u, g.end, p[u], a0[u], a1[u], cols[u]);
             }
         } else {
             while (cg >= s_next) {
