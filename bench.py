@@ -62,7 +62,7 @@ SURFACE_SLOTS_PER_SAMPLE = 16
 # projection and binning that build the records and tile lists it walks, and the
 # record layout); otherwise null.
 MEASURED_TRAFFIC = {"kernel": "render_bwd_tiles", "workload": "drt-batch-500k-8views",
-                    "fingerprint": "ff0e32ab3678259b", "bytes": 2078803968,
+                    "fingerprint": "6d41123fc3378a40", "bytes": 2078875535,
                     "settings": (16, 16, 0, 64)}  # tile_w, tile_h, variant, batch of the measured run
 
 
