@@ -154,6 +154,22 @@ def test_deterministic_bitwise():
         np.testing.assert_array_equal(ga[k], gb[k])
 
 
+@pytest.mark.parametrize("views", [5, 16, 17])
+def test_lists_do_not_depend_on_digit_width(views):
+    """The (view, depth) sort takes the view bits in the pass that reaches past
+    the 32 depth bits, or in passes of their own (17 views: five view bits, so
+    4-bit digits spend two passes on them): every digit width gives the same
+    lists, tile keys, instance bases, worklist and image."""
+    scene, st = gi.tiny_scene(30 + views, n=400, n_views=views, deg=0), oracle.Settings(sh_degree=0)
+    ref = run_gpu(scene, st, counts=False, radix_bits=8)
+    assert ref["listed"] > 0
+    for b in (4, 5, 6, 7):
+        g = run_gpu(scene, st, counts=False, radix_bits=b)
+        for k in ("val_sorted", "tile_sorted", "ranges", "inst_base", "worklist", "image"):
+            np.testing.assert_array_equal(g[k], ref[k], err_msg=f"{views} views, {b}-bit digits: {k}")
+    log(f"[gpu] {views} views: lists identical at 4..8-bit digits ({ref['listed']} instances)")
+
+
 @pytest.mark.parametrize("variant,batch,B", [(0, 64, 64), (0, 32, 32), (1, 64, 256)])
 def test_work_order_schedules_only(variant, batch, B):
     """The forward's per-tile work figure is the list positions its renderer
