@@ -167,7 +167,7 @@ DevCams dev_cams(const gesr_camera* cams, int V, const gesr_settings* st) {
 
 // Layout of gesr_bins.scratch (256-byte aligned sub-buffers).
 struct BinScratch {
-    uint32_t *d_keys_a, *d_vals_a, *d_keys_b, *d_vals_b;  // depth and view sort, [V*n]
+    uint32_t *d_keys_a, *d_vals_a, *d_keys_b, *d_vals_b;  // (view, depth) sort, [V*n]
     uint32_t *rowlist, *rowcols;                          // row lists and their columns, [m_cap]
     uint2* srect;                                         // rectangles in (view, depth) order, [V*n]
     float4* sell;                                         // footprint ellipses in that order, [2 V*n]
