@@ -377,6 +377,7 @@ __global__ __launch_bounds__(64) void k_render_fwd_wave16(RenderArgs a) {
         for (int j = 0; j < cnt; ++j) {
             const float4 ra = sA[j];
             const float4 rb = sB[j];
+            const float4 rc = sC[j];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 if (done[q]) continue;
@@ -396,7 +397,6 @@ __global__ __launch_bounds__(64) void k_render_fwd_wave16(RenderArgs a) {
                 const bool stop = ok && Tn < st.t_min;
                 const bool acc = ok && !stop;
                 done[q] = stop;
-                const float4 rc = sC[j];
                 const float wgt = acc ? f.alpha * T[q] : 0.0f;
                 cr[q] = fmaf(rc.x, wgt, cr[q]);
                 cg[q] = fmaf(rc.y, wgt, cg[q]);
