@@ -552,18 +552,18 @@ __global__ __launch_bounds__(256) void k_is_seg_chunks(IsArgs a, uint32_t* chunk
     chunks[s] = (g.end - g.begin + IS_CHUNK - 1) / IS_CHUNK;
 }
 
-// Inclusive prefix over the IS_W entries row[0..IS_W) by one wave (two per lane).
+// Inclusive prefix over the IS_W entries row[0..IS_W) by one wave (two per
+// lane), for entries in [-OFF, 2^BITS / 2 - OFF): the lane sums (offset to be
+// non-negative) are prefixed by one ballot per bit (no cross-lane shuffles).
+template <int BITS, int OFF>
 __device__ __forceinline__ void wave_prefix_row(int* row) {
     const uint32_t lane = __lane_id();
     const int x0 = row[2 * lane], x1 = row[2 * lane + 1];
-    int inc = x0 + x1;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const int y = __shfl_up(inc, d, 64);
-        if (lane >= (uint32_t)d) inc += y;
-    }
-    row[2 * lane] = inc - x1;
-    row[2 * lane + 1] = inc;
+    const uint32_t v = (uint32_t)(x0 + x1 + 2 * OFF);  // < 2^BITS
+    uint32_t tot;
+    const int ex = (int)(wave_prefix_bits<BITS>(v, &tot) - 2u * OFF * lane);
+    row[2 * lane] = ex + x0;
+    row[2 * lane + 1] = ex + x0 + x1;
 }
 
 // Count pass (MODE 0) and scatter pass (MODE 1) over the chunks; persistent
@@ -654,7 +654,7 @@ __global__ __launch_bounds__(IS_THREADS) __attribute__((amdgpu_waves_per_eu(8)))
                     atomicAdd(&s_cnt[wave][hi[u] + 1], -1);
                 }
             __syncthreads();
-            wave_prefix_row(s_cnt[wave]);  // s_cnt[w][b]: items of wave w covering bucket b
+            wave_prefix_row<10, 128>(s_cnt[wave]);  // s_cnt[w][b]: items of wave w covering bucket b
             __syncthreads();
             if (threadIdx.x < (uint32_t)g.width) {
                 int acc = 0;
@@ -736,7 +736,7 @@ __global__ __launch_bounds__(IS_THREADS) __attribute__((amdgpu_waves_per_eu(8)))
                 }
                 if (threadIdx.x == 0) s_ls[0] = 0u;
                 __syncthreads();
-                if (wave == 0) wave_prefix_row(reinterpret_cast<int*>(s_ls + 1));
+                if (wave == 0) wave_prefix_row<13, 0>(reinterpret_cast<int*>(s_ls + 1));
                 __syncthreads();
                 for (int b0 = 0; b0 < g.width;) {
                     // largest b1 with the window's entries fitting the stage (one
