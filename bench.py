@@ -62,7 +62,7 @@ SURFACE_SLOTS_PER_SAMPLE = 16
 # projection and binning that build the records and tile lists it walks, and the
 # record layout); otherwise null.
 MEASURED_TRAFFIC = {"kernel": "render_bwd_tiles", "workload": "drt-batch-500k-8views",
-                    "fingerprint": "4f2d13d0416966da", "bytes": 2078898486,
+                    "fingerprint": "ec146a98f541c0cd", "bytes": 2078690996,
                     "settings": (16, 16, 0, 64)}  # tile_w, tile_h, variant, batch of the measured run
 
 
