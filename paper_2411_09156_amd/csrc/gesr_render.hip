@@ -538,13 +538,15 @@ __global__ __launch_bounds__(64) void k_render_bwd_wave16(RenderArgs a) {
                 ges_alpha(qq, rb.z, rb.y, st, amax, f);
                 const bool ok = !(f.alpha < st.alpha_min);
                 act = act || ok;
-                const float Tk = T[q] * hw_rcp(1.0f - f.alpha);
-                const float aT = ok ? f.alpha * Tk : 0.0f;
+                // a skipped fragment has alpha 0 here: it leaves T (rcp(1) = 1), the
+                // colour behind and the sums as they are
+                const float al = ok ? f.alpha : 0.0f;
+                const float Tk = T[q] * hw_rcp(1.0f - al);
+                const float aT = al * Tk;
                 gr[7] += aT * g0[q];
                 gr[8] += aT * g1[q];
                 gr[9] += aT * g2[q];
                 float dLda = Tk * ((rc.x - Br[q]) * g0[q] + (rc.y - Bg[q]) * g1[q] + (rc.z - Bb[q]) * g2[q]);
-                const float al = ok ? f.alpha : 0.0f;  // a skipped fragment leaves the colour behind as it is
                 Br[q] = fmaf(al, rc.x - Br[q], Br[q]);
                 Bg[q] = fmaf(al, rc.y - Bg[q], Bg[q]);
                 Bb[q] = fmaf(al, rc.z - Bb[q], Bb[q]);
@@ -554,7 +556,7 @@ __global__ __launch_bounds__(64) void k_render_bwd_wave16(RenderArgs a) {
                     BD[q] = fmaf(al, z - BD[q], BD[q]);
                     BA[q] = fmaf(al, 1.0f - BA[q], BA[q]);
                 }
-                T[q] = ok ? Tk : T[q];
+                T[q] = Tk;
                 // add_fragment_grad with its two early exits as selects
                 const bool live = ok && !(f.oG > st.alpha_max);
                 const float dl = live ? dLda : 0.0f;
