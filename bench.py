@@ -62,7 +62,7 @@ SURFACE_SLOTS_PER_SAMPLE = 16
 # projection and binning that build the records and tile lists it walks, and the
 # record layout); otherwise null.
 MEASURED_TRAFFIC = {"kernel": "render_bwd_tiles", "workload": "drt-batch-500k-8views",
-                    "fingerprint": "ec146a98f541c0cd", "bytes": 2078690996,
+                    "fingerprint": "3a21a60edd1f05f5", "bytes": 2078642230,
                     "settings": (16, 16, 0, 64)}  # tile_w, tile_h, variant, batch of the measured run
 
 
