@@ -62,6 +62,9 @@ def _case(name):
     if name == "wide-2200x2100":  # > 16k tiles in one view: global counting-grid path
         return gi.tiny_scene(8, n=300, deg=1, width=2200, height=2100, log_scale=(-3.5, -2.5)), \
             oracle.Settings(sh_degree=1)
+    if name == "giant-640x480":  # splats of more than 512 tiles: the segmented sum's whole-wave pairs
+        return gi.tiny_scene(9, n=24, deg=1, width=640, height=480, log_scale=(-0.6, -0.1), spread=0.3), \
+            oracle.Settings(sh_degree=1)
     if name == "ragged-5v":  # 1x1, 1x37, 23x1, 17x33 and 129x65 views
         return gi.ragged_scene(0), oracle.Settings(sh_degree=2)
     if name == "ragged-5v-t8":
@@ -73,7 +76,7 @@ def _case(name):
 
 CASES = ["tiny-d1", "tiny-d3-2v-bg", "tiny-kappa1", "ragged-5v", "ragged-5v-t8", "plain-2k", "plain-2k-v1",
          "plain-2k-t8", "plain-2k-t32x16", "plain-2k-t32", "spheres-100k", "drt-50k-8v", "drt-50k-8v-v1",
-         "surfels-40k-2v", "blobs-100k-2v", "wide-2200x2100"]
+         "surfels-40k-2v", "blobs-100k-2v", "wide-2200x2100", "giant-640x480"]
 
 
 @functools.lru_cache(maxsize=1)
@@ -293,3 +296,12 @@ def test_needles_tight_lists(tile):
                    ~ambiguous_tiles_to_pixels(scene.cameras, st, cmp["tiles_differ"]), "needles", str(tile))
     log(f"[gpu] needles {tile}: listed {g['listed']} of {g['M']} rectangle tiles; {cmp['n_band']} decisions within "
         f"the band, {cmp['n_flip']} taken the other way")
+
+
+def test_giant_case_reaches_whole_wave_pairs():
+    """The giant-splat case holds pairs of more than 512 instance slots, which the
+    segmented sum hands to a whole wave (the parity tests above cover them)."""
+    scene, st, g = _run("giant-640x480")
+    big = int((g["tiles_touched"] > 512).sum())
+    log(f"[gpu] giant case: {big} pairs of more than 512 slots, largest {int(g['tiles_touched'].max())}")
+    assert big > 0
